@@ -1,0 +1,9 @@
+"""CPU oracle for the SuperDC rank-one conquer path.
+
+TEST INFRASTRUCTURE: only the tests, the smoke check and the CPU-baseline leg of the
+benchmark import this package.  The product library never does.
+"""
+from .oracle import (  # noqa: F401
+    build, load, secular, loewner, bnorm, cauchy_apply, backward, validate,
+    solve_batch, ST_UNSORTED, ST_ZERO, ST_NONFINITE, ST_RHO, ST_NOCONV,
+)
