@@ -1,0 +1,461 @@
+#!/usr/bin/env python3
+"""Benchmark of the conquering-stage hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload level|conquer|single]
+
+A step is one pass of the whole rank-one path over one batch already resident in HBM:
+validation and packing, the secular solve (midpoint pass plus middle-way iterations to
+convergence), the Loewner vector and normalisation, and the Cauchy-like eigenvector
+matrix applied to the batch's right-hand sides.  The batched form runs every phase as one
+persistent launch over the whole batch; the plain form runs the same kernels once per
+problem.  Both are timed; `value` is the batched form's whole-job throughput in roots/s.
+
+Prints one JSON line.  The roofline object describes the dominant kernel (the secular
+solve, FP64 VALU-bound); `achieved` is its algorithmic FP64 rate (7 flops per pole-root
+pair evaluation, with the actual per-root iteration counts) over its HIP-event duration.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "secular roots/s + Cauchy-apply FP64 GFLOP/s, batched vs plain, at <=1e-12 rel err"
+PEAK_FP64_VALU = 78.6    # TFLOP/s, MI355X FP64 vector (256 CU x 2.4 GHz x 128 flop/clk)
+PEAK_FP64_MFMA = 78.6    # TFLOP/s, MI355X FP64 matrix
+FLOPS_PER_PAIR = 7       # secular: 2 sub, 1 rcp, 1 mul, 1 add, 1 fma(2)
+FLOPS_LOEWNER = 5        # per pair: 2 sub, 1 add, 2 mul
+FLOPS_BNORM = 6          # per pair: 2 sub, 1 rcp, 1 mul, 1 fma(2)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="conquer", choices=["conquer", "level", "single"])
+    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-level", action="store_true",
+                    help="with --workload conquer, skip the batched-level side measurement")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def workload(name):
+    from paper_2108_04209_amd import gen
+    if name == "level":
+        batch, X = gen.cfg2()
+        cfg = {"workload": "batched level: 4096 rank-one problems, n log-uniform in [64, 8192], "
+                           "FP64, rho ~ U[0.1,2], 16 right-hand sides",
+               "nprob": batch.nprob, "total_n": batch.total_n, "m": int(X.shape[1])}
+    else:
+        pr, X = gen.cfg0()
+        batch = gen.concat([pr])
+        cfg = {"workload": "single rank-one problem n=1024, 16 right-hand sides",
+               "nprob": 1, "total_n": pr.n, "m": int(X.shape[1])}
+    return batch, X, cfg
+
+
+class Pipeline:
+    """Preallocated device buffers and the four C-ABI calls of one step."""
+
+    def __init__(self, batch, X, persistent):
+        import torch
+        from paper_2108_04209_amd import native
+        self.torch = torch
+        self.native = native
+        self.ctx = native.Context()
+        self.b = native.Batch(self.ctx, batch.off)
+        dev = torch.device("cuda:0")
+        f = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+        self.d, self.z, self.rho = f(batch.d), f(batch.z), f(batch.rho)
+        self.X = f(np.asarray(X).T)                      # (m, total): column-major batch
+        tot, P = batch.total_n, batch.nprob
+        self.out = dict(lam=torch.empty(tot, dtype=torch.float64, device=dev),
+                        eta=torch.empty(tot, dtype=torch.float64, device=dev),
+                        origin=torch.empty(tot, dtype=torch.int32, device=dev),
+                        iters=torch.empty(tot, dtype=torch.int32, device=dev),
+                        status=torch.empty(P, dtype=torch.int32, device=dev))
+        self.zb = (torch.empty(tot, dtype=torch.float64, device=dev),
+                   torch.empty(tot, dtype=torch.float64, device=dev))
+        self.Y = torch.empty_like(self.X)
+        self.opts = native.default_opts(persistent=persistent)
+
+    def solve(self):
+        self.native.secular_solve(self.ctx, self.b, self.d, self.z, self.rho, opts=self.opts,
+                                  out=self.out)
+
+    def vectors(self):
+        o = self.out
+        self.native.loewner(self.ctx, self.b, self.d, self.z, self.rho, o["eta"], o["origin"],
+                            o["status"], opts=self.opts, out=self.zb)
+
+    def apply(self):
+        o = self.out
+        self.native.cauchy_apply(self.ctx, self.b, self.d, self.zb[0], self.zb[1], o["eta"],
+                                 o["origin"], o["status"], self.X, trans=1, opts=self.opts,
+                                 Y=self.Y)
+
+    def step(self):
+        self.solve()
+        self.vectors()
+        self.apply()
+
+
+def time_steps(pipe, steps, warmup):
+    torch = pipe.torch
+    for _ in range(warmup):
+        pipe.step()
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for s in range(steps):
+        e = ev[s]
+        e[0].record()
+        pipe.solve()
+        e[1].record()
+        pipe.vectors()
+        e[2].record()
+        pipe.apply()
+        e[3].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ph = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(3)] for e in ev])  # ms
+    tot = np.array([e[0].elapsed_time(e[3]) for e in ev])
+    return wall / steps * 1e3, tot, ph
+
+
+def accuracy(pipe, batch, X, nsample=4):
+    """Max |lambda - lambda_oracle| / ||A||_2 over a seeded sample of problems (largest
+    included), and the apply error, against the CPU oracle."""
+    import oracle
+    o = {k: v.cpu().numpy() for k, v in pipe.out.items()}
+    zh, bn = pipe.zb[0].cpu().numpy(), pipe.zb[1].cpu().numpy()
+    Y = pipe.Y.cpu().numpy().T
+    sizes = batch.sizes()
+    rng = np.random.default_rng(1)
+    pick = sorted({int(np.argmax(sizes))} | set(rng.choice(batch.nprob, min(nsample, batch.nprob), replace=False).tolist()))
+    err, aerr = 0.0, 0.0
+    for p in pick:
+        a, e = int(batch.off[p]), int(batch.off[p + 1])
+        pr = batch.problem(p)
+        lam, eta, org, its, st = oracle.secular(pr.d, pr.z, pr.rho)
+        err = max(err, np.abs(o["lam"][a:e] - lam).max() / np.abs(lam).max())
+        z1 = oracle.loewner(pr.d, pr.z, pr.rho, eta, org)
+        b1 = oracle.bnorm(pr.d, z1, eta, org)
+        rows = np.arange(0, e - a, max(1, (e - a) // 64))
+        Yo = oracle.cauchy_apply(pr.d, z1, b1, eta, org, X[a:e], trans=1, rows=rows)
+        aerr = max(aerr, np.abs(Y[a:e][rows] - Yo).max() / np.abs(X[a:e]).max())
+    return float(err), float(aerr), int(np.all(o["status"] == 0)), pick
+
+
+def cpu_baseline(batch, X, seconds):
+    """The oracle (plain FP64 C, OpenMP) on whole problems of the same workload, taken in a
+    seeded order until `seconds` of wall time are spent; roots/s of the full path."""
+    import oracle
+    oracle.load()
+    rng = np.random.default_rng(7)
+    order = rng.permutation(batch.nprob)
+    roots, t_used, probs = 0, 0.0, 0
+    m = X.shape[1]
+    for p in order:
+        a, e = int(batch.off[p]), int(batch.off[p + 1])
+        pr = batch.problem(p)
+        t0 = time.perf_counter()
+        lam, eta, org, its, st = oracle.secular(pr.d, pr.z, pr.rho)
+        zh = oracle.loewner(pr.d, pr.z, pr.rho, eta, org)
+        b = oracle.bnorm(pr.d, zh, eta, org)
+        oracle.cauchy_apply(pr.d, zh, b, eta, org, X[a:e], trans=1)
+        t_used += time.perf_counter() - t0
+        roots += e - a
+        probs += 1
+        if t_used >= seconds:
+            break
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": roots / t_used, "unit": "roots/s", "cores": cores, "kind": "oracle",
+            "sample": f"{probs} whole problems ({roots} roots, seeded order) of the same "
+                      f"workload, full path incl. apply to {m} vectors, {t_used:.1f} s"}
+
+
+def bench_level(args, name):
+    import torch
+    batch, X, cfg = workload(name)
+    tot = batch.total_n
+    sizes = batch.sizes().astype(np.float64)
+    m = X.shape[1]
+
+    pipe = Pipeline(batch, X, persistent=1)
+    wall_ms, tot_ms, ph = time_steps(pipe, args.steps, args.warmup)
+    iters = pipe.out["iters"].cpu().numpy().astype(np.float64)
+    status_ok = bool(np.all(pipe.out["status"].cpu().numpy() == 0))
+    ms = float(np.mean(tot_ms))
+    solve_ms, vec_ms, apply_ms = (float(x) for x in ph.mean(axis=0))
+
+    # algorithmic work of one step
+    n_of_root = np.repeat(sizes, batch.sizes())
+    pairs = float(np.sum(n_of_root * (1.0 + iters)))
+    sec_flops = FLOPS_PER_PAIR * pairs
+    n2 = float(np.sum(sizes ** 2))
+    vec_flops = (FLOPS_LOEWNER + FLOPS_BNORM) * n2
+    apply_flops = (2 * m + 3) * n2 + 2 * tot * m
+
+    # graph replay of the same step
+    graph_ms = None
+    try:
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            pipe.step()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            pipe.step()
+        g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        graph_ms = e0.elapsed_time(e1) / args.steps
+    except Exception as exc:  # report, do not hide
+        graph_ms = f"capture failed: {exc!r}"
+
+    err, aerr, st_ok, pick = accuracy(pipe, batch, X)
+
+    plain_res = None
+    if args.plain_steps > 0:
+        plain = Pipeline(batch, X, persistent=0)
+        p_wall, p_tot, p_ph = time_steps(plain, args.plain_steps, 1)
+        p_ms = float(np.mean(p_tot))
+        plain_res = {"ms_per_step": p_ms, "value": tot / (p_ms * 1e-3),
+                     "phase_ms": dict(zip(["solve", "loewner_b", "apply"],
+                                          (float(x) for x in p_ph.mean(axis=0)))),
+                     "launches_per_phase": batch.nprob, "steps": args.plain_steps}
+
+    roofline = {"bound": "alu", "achieved": sec_flops / (solve_ms * 1e-3) / 1e12,
+                "peak": PEAK_FP64_VALU, "unit": "TFLOP/s",
+                "frac": sec_flops / (solve_ms * 1e-3) / 1e12 / PEAK_FP64_VALU, "traffic": None,
+                "kernel": "k_secular (+k_validate)",
+                "algorithmic_flops_per_launch": sec_flops}
+    res = {
+        "metric": METRIC, "value": tot / (ms * 1e-3), "unit": "roots/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded generators, no dataset)", "config": cfg,
+        "secular_roots_per_s": tot / (solve_ms * 1e-3),
+        "apply_gflops": apply_flops / (apply_ms * 1e-3) / 1e9,
+        "phase_ms": {"solve": solve_ms, "loewner_b": vec_ms, "apply": apply_ms},
+        "mean_iters_after_midpoint": float(iters.mean()), "max_iters": int(iters.max()),
+        "graph_ms_per_step": graph_ms, "wall_ms_per_step": wall_ms,
+        "plain": plain_res,
+        "speedup_batched_vs_plain": None if plain_res is None else plain_res["ms_per_step"] / ms,
+        "accuracy": {"max_eig_err_rel_normA": err, "apply_err_rel": aerr,
+                     "problems_checked": pick, "status_all_ok": status_ok},
+        "roofline": roofline,
+    }
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(batch, X, args.cpu_seconds)
+    return res
+
+
+
+
+# ---------------------------------------------------------------------------------------
+# HSS conquering pass (n = 65536, leaf 128, depth 9, r = 8)
+# ---------------------------------------------------------------------------------------
+def conquer_flops(tree, iters):
+    """Algorithmic FP64 work of one conquer from the per-root evaluation counts."""
+    D, r, n = tree.depth, tree.r, tree.n
+    sec = vec = app = 0.0
+    for lvl in range(D):
+        nl = tree.leaf << (D - lvl)
+        sec += FLOPS_PER_PAIR * nl * float(np.sum(1.0 + iters[lvl]))
+        vec += r * (FLOPS_LOEWNER + FLOPS_BNORM) * n * nl
+        ncol = 2 * r if lvl > 0 else r
+        for t in range(r):
+            m = ncol - t - 1
+            if m > 0:
+                app += (2 * m + 3) * n * nl + 2 * n * m
+    return sec, vec, app
+
+
+def conquer_cpu_baseline(seconds):
+    """The HSS oracle (dense assembly of every node + LAPACK eigenvalues) on the subtree
+    rooted at a level-l node of the same tree, the largest that fits the time budget; the
+    roots the GPU path solves for that subtree (depth_s * r * n_s) per second."""
+    import oracle.hss as ohss
+    from paper_2108_04209_amd import gen
+    best = None
+    for ds in range(2, 7):
+        sub = gen.hss_tree(n=128 << ds, leaf=128, r=8, cfg=3)
+        t0 = time.perf_counter()
+        ohss.level_eigenvalues(sub)
+        dt = time.perf_counter() - t0
+        best = (ds, sub.n, dt)
+        if dt * 8.5 > seconds:   # the next depth costs ~8x (dense O(n^3))
+            break
+    ds, ns, dt = best
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": ds * 8 * ns / dt, "unit": "roots/s", "cores": cores, "kind": "oracle",
+            "sample": f"HSS tree n={ns} (leaf 128, depth {ds}, r 8), same generator: dense "
+                      f"assembly of every node and LAPACK eigenvalues, {dt:.1f} s; counted as "
+                      f"the {ds * 8 * ns} roots the GPU path solves for that tree"}
+
+
+def bench_conquer(args):
+    import torch
+    import oracle.hss as ohss
+    from paper_2108_04209_amd import gen, native
+    tree = gen.hss_tree()
+    ctx = native.Context()
+    plan = native.HSSPlan(ctx, tree.leaf, tree.depth, tree.r)
+    dev = torch.device("cuda:0")
+    gens = {k: torch.as_tensor(v, dtype=torch.float64, device=dev)
+            for k, v in native.pack_hss(tree).items()}
+    opts1 = native.default_opts(persistent=1)
+    out = native.hss_conquer(ctx, plan, gens, opts=opts1)
+    native.hss_set_timing(plan, True)
+
+    def timed(opts, steps, warm):
+        for _ in range(warm):
+            native.hss_conquer(ctx, plan, gens, opts=opts, out=out)
+        torch.cuda.synchronize()
+        tot, phases = [], {k: 0.0 for k in native.HSS_PHASES}
+        counts = None
+        for _ in range(steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            native.hss_conquer(ctx, plan, gens, opts=opts, out=out)
+            e1.record()
+            torch.cuda.synchronize()
+            tot.append(e0.elapsed_time(e1))
+            ph, counts = native.hss_phase_times(plan)
+            for k in phases:
+                phases[k] += ph[k] / steps
+        return float(np.mean(tot)), phases, counts
+
+    ms, phases, counts = timed(opts1, args.steps, args.warmup)
+    status = int(out["status"].cpu().numpy()[0])
+    iters = native.hss_iterations(plan).cpu().numpy().astype(np.float64)
+    lam = out["lam"].cpu().numpy()
+    sec_f, vec_f, app_f = conquer_flops(tree, iters)
+    roots = tree.depth * tree.r * tree.n
+
+    # graph replay of the same step (timing events off while capturing)
+    graph_ms = None
+    native.hss_set_timing(plan, False)
+    try:
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            native.hss_conquer(ctx, plan, gens, opts=opts1, out=out)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            native.hss_conquer(ctx, plan, gens, opts=opts1, out=out)
+        g.replay()
+        torch.cuda.synchronize()
+        glam = out["lam"].cpu().numpy()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        graph_ms = {"ms_per_step": e0.elapsed_time(e1) / args.steps,
+                    "replay_equals_eager": bool(np.array_equal(glam, lam))}
+    except Exception as exc:  # report, do not hide
+        graph_ms = f"capture failed: {exc!r}"
+    native.hss_set_timing(plan, True)
+
+    # accuracy: trace identity and sampled eigenpair residuals with the oracle's product
+    nA = float(np.abs(lam).max())
+    tr_err = abs(lam.sum() - ohss.trace(tree)) / (tree.n * nA)
+    rng = np.random.default_rng(5)
+    ks = np.sort(np.r_[0, tree.n - 1, rng.choice(tree.n, 30, replace=False)])
+    E = np.zeros((len(ks), tree.n))
+    E[np.arange(len(ks)), ks] = 1.0
+    Qs = native.hss_apply(ctx, plan, torch.as_tensor(E, device=dev), trans=0).cpu().numpy().T
+    resid = float((np.linalg.norm(ohss.matvec(tree, Qs) - Qs * lam[ks], axis=0) / nA).max())
+    orth = float(np.abs(Qs.T @ Qs - np.eye(len(ks))).max())
+
+    plain_res = None
+    if args.plain_steps > 0:
+        p_ms, p_ph, _ = timed(native.default_opts(persistent=0), args.plain_steps, 1)
+        plain_res = {"ms_per_step": p_ms, "value": roots / (p_ms * 1e-3),
+                     "phase_ms": p_ph, "steps": args.plain_steps,
+                     "launches": "one per node per phase"}
+
+    sec_ms = phases["secular"]
+    nsec = counts["secular"]
+    roofline = {"bound": "alu", "achieved": sec_f / (sec_ms * 1e-3) / 1e12,
+                "peak": PEAK_FP64_VALU, "unit": "TFLOP/s",
+                "frac": sec_f / (sec_ms * 1e-3) / 1e12 / PEAK_FP64_VALU, "traffic": None,
+                "kernel": "k_secular (+k_validate)", "launches_per_step": nsec,
+                "avg_launch_ms": sec_ms / nsec,
+                "algorithmic_flops_per_launch": sec_f / nsec}
+    cfg = {"workload": "HSS conquering pass: n=65536, leaf 128, depth 9, rank 8 "
+                       "(8 sequential rank-one updates per node), FP64, all nodes of a level "
+                       "batched per call",
+           "n": tree.n, "leaf": tree.leaf, "depth": tree.depth, "r": tree.r,
+           "rank_one_roots_per_step": roots}
+    res = {
+        "metric": METRIC, "value": roots / (ms * 1e-3), "unit": "roots/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded generators, no dataset)", "config": cfg,
+        "secular_roots_per_s": roots / (sec_ms * 1e-3),
+        "apply_gflops": app_f / (phases["apply"] * 1e-3) / 1e9,
+        "phase_ms": phases, "phase_intervals": counts,
+        "mean_iters_after_midpoint": float(iters.mean()), "max_iters": int(iters.max()),
+        "graph": graph_ms,
+        "plain": plain_res,
+        "speedup_batched_vs_plain": None if plain_res is None else plain_res["ms_per_step"] / ms,
+        "accuracy": {"status": status, "trace_err_rel": tr_err,
+                     "max_resid_rel_normA_sampled": resid, "orth_err_sampled": orth,
+                     "eigvecs_checked": len(ks)},
+        "roofline": roofline,
+    }
+    if not args.no_cpu:
+        res["cpu_baseline"] = conquer_cpu_baseline(args.cpu_seconds)
+    return res
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); "
+              "the path has no multi-GPU mode", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    if args.workload == "conquer":
+        res = bench_conquer(args)
+        if not args.no_level:
+            lv = bench_level(argparse.Namespace(**{**vars(args), "no_cpu": True}), "level")
+            res["level"] = {k: lv[k] for k in ("config", "value", "ms_per_step",
+                                               "secular_roots_per_s", "apply_gflops",
+                                               "phase_ms", "graph_ms_per_step", "plain",
+                                               "speedup_batched_vs_plain", "accuracy",
+                                               "roofline")}
+    else:
+        res = bench_level(args, args.workload)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,226 @@
+/*
+ * superdc.h -- C ABI of the MI355X (gfx950) conquering-stage library for SuperDC
+ * (Ou & Xia, "SuperDC: Stable superfast divide-and-conquer eigenvalue decomposition").
+ *
+ * The library solves batches of diagonal-plus-rank-one symmetric eigenproblems
+ *
+ *     A_p = diag(d_p) + rho_p z_p z_p^T,     p = 0 .. nprob-1,                   (*)
+ *
+ * the building block of the conquering stage (Sec. 2.2, eqs. rankrupd and rank1upd, with
+ * the paper's v = sqrt(rho) z).  For each problem it
+ *   1. finds all n_p eigenvalues as roots of the secular equation (eq. seceq) by solving
+ *      the shifted equations (eq. shiftedeq) for gaps eta_k relative to a per-root origin
+ *      pole d_K ("local shifting", Sec. 4.2.2): lambda_k = d_{K_k} + eta_k (eq. evalnew);
+ *   2. recomputes the update vector zhat by Loewner's formula (eq. lowner) and the column
+ *      normalisation b (eq. b) of the Cauchy-like eigenvector matrix
+ *          Qhat_ij = zhat_i b_j / (d_i - lambda_j)                (eqs. eigvecs, qscale),
+ *      with every difference d_i - lambda_j formed as (d_i - d_{K_j}) - eta_j (eq. qk);
+ *   3. applies Qhat or Qhat^T to blocks of vectors (Alg. 3 Z-update, Alg. 4);
+ *   4. (not in the paper) back-propagates dL/dlambda and dL/d(Qhat^T u) to (d, z, rho).
+ * It also runs a whole HSS conquering pass (Alg. 3) on a perfect binary tree.
+ *
+ * Conventions shared by every entry point
+ *   - Every array argument is a DEVICE pointer owned by the caller unless stated; the
+ *     library never frees or keeps it past the call.
+ *   - Problems are stored back to back (CSR layout): problem p owns the entries
+ *     off[p] .. off[p+1]-1 of every per-entry array (d, z, lam, eta, origin, zhat, ...).
+ *     The offsets are given once, on the host, to superdc_batch_create.
+ *   - d must be strictly increasing within each problem, z_i != 0, rho_p > 0, all finite
+ *     (the paper assumes deflation has already removed the other cases, Sec. 4.1).
+ *   - origin[k] is a LOCAL index within its problem: origin[k] in {k, k+1} for k < n_p-1,
+ *     origin[n_p-1] = n_p-1.  eta is the gap to that pole, lam = d[origin] + eta rounded.
+ *   - Matrices of right-hand sides are column-major over the whole batch: column c of X
+ *     starts at X + c*ldx and problem p's rows are off[p] .. off[p+1]-1 (ldx >= total_n).
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the default stream).  Calls do
+ *     not synchronise with the host.  Host-detectable argument errors return a negative
+ *     code synchronously and enqueue nothing.  Data-dependent errors are reported per
+ *     problem in the device `status` array written by superdc_secular_solve (bits below);
+ *     the later calls skip problems whose status is not 0 or SUPERDC_ST_NOCONV.
+ *   - Workspace lives in the context and only grows.  The first call for a batch shape may
+ *     allocate; later calls with the same or a smaller shape allocate nothing and issue no
+ *     memset, so they may be captured into a hipGraph.
+ *   - One context per host thread; calls on one context must not overlap in time.
+ */
+#ifndef SUPERDC_H
+#define SUPERDC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define SUPERDC_OK 0
+#define SUPERDC_EINVAL -1   /* NULL pointer, bad size, bad option                     */
+#define SUPERDC_ENOMEM -2   /* device allocation failed                               */
+#define SUPERDC_EHIP -3     /* a HIP runtime call or kernel launch failed             */
+#define SUPERDC_ENODEV -4   /* no gfx950 device visible                               */
+
+/* per-problem status bits (device array written by superdc_secular_solve) */
+#define SUPERDC_ST_UNSORTED 1   /* d not strictly increasing                          */
+#define SUPERDC_ST_ZERO 2       /* some z_i == 0 (would need deflation, Remark 1)     */
+#define SUPERDC_ST_NONFINITE 4  /* NaN or Inf in d, z or rho                          */
+#define SUPERDC_ST_RHO 8        /* rho <= 0                                           */
+#define SUPERDC_ST_NOCONV 16    /* a root hit the iteration cap; it keeps its best     */
+                                /* bracketed iterate                                   */
+
+typedef struct superdc_ctx superdc_ctx;
+typedef struct superdc_batch superdc_batch;
+
+/* Secular-solver options.  superdc_opts_default fills the defaults shown. */
+typedef struct {
+    double stop_c;       /* c in the stopping test |f| < c n eps (1+|psi|+|phi|)
+                            (eq. stopcrit); default 1.0, must be > 0                      */
+    int32_t max_iter;    /* iteration cap per root after the midpoint pass; default 40,
+                            1..200                                                        */
+    int32_t method;      /* 0 auto (direct below the crossover, FMM above), 1 direct sums,
+                            2 triangular FMM (Sec. 4.1.2)                                 */
+    int32_t fmm_order;   /* Chebyshev order of the FMM expansions; default 16, 4..32      */
+    int32_t fmm_leaf;    /* FMM leaf size; default 256, a multiple of 64                  */
+    int32_t persistent;  /* 1: one persistent launch per phase for the whole batch;
+                            0: one launch per problem per phase (the "plain" baseline)    */
+    int32_t apply_kernel;/* Cauchy apply: 0 auto (MFMA for m >= 4), 1 VALU, 2 FP64 MFMA    */
+    int32_t reserved[3]; /* must be 0                                                     */
+} superdc_opts;
+
+void superdc_opts_default(superdc_opts *opts);
+
+/* Create / destroy a context on the current HIP device (must be gfx950). */
+int superdc_create(superdc_ctx **ctx);
+void superdc_destroy(superdc_ctx *ctx);
+const char *superdc_strerror(int code);
+/* hipError_t value behind the last SUPERDC_EHIP / SUPERDC_ENOMEM of this host thread */
+int superdc_last_hip_error(void);
+
+/*
+ * Describe a batch.  off_host[0..nprob] are HOST offsets with off_host[0] = 0 and
+ * off_host[p+1] - off_host[p] >= 1; they are copied (to the device as well), so the
+ * caller may free them afterwards.  nprob >= 1.  The batch also holds the work lists
+ * (root tiles ordered longest-first) that the kernels consume.
+ */
+int superdc_batch_create(superdc_ctx *ctx, int32_t nprob, const int64_t *off_host,
+                         superdc_batch **batch);
+void superdc_batch_destroy(superdc_batch *batch);
+int64_t superdc_batch_total(const superdc_batch *batch);
+
+/*
+ * Eigenvalues of every problem (*) (Alg. 2 with local shifting, Sec. 4.2).
+ *   in : d[total], z[total], rho[nprob]
+ *   out: lam[total], eta[total], origin[total] (int32, local), iters[total] (int32,
+ *        evaluations of the secular sums after the midpoint pass; may be NULL), status[nprob] (int32, bits
+ *        above; always written).
+ * opts may be NULL (defaults).
+ */
+int superdc_secular_solve(superdc_ctx *ctx, const superdc_batch *batch, const double *d,
+                          const double *z, const double *rho, double *lam, double *eta,
+                          int32_t *origin, int32_t *iters, int32_t *status,
+                          const superdc_opts *opts, void *stream);
+
+/*
+ * Loewner update vector and normalisation (eqs. lowner and b), from the solver's output:
+ *   in : d, z (only its signs are used), rho, eta, origin, status
+ *   out: zhat[total] with rho zhat_i^2 = prod_j (lambda_j - d_i) / prod_{j!=i} (d_j - d_i)
+ *        and sign(zhat_i) = sign(z_i); bnorm[total] with
+ *        bnorm_j = (sum_i zhat_i^2 / (d_i - lambda_j)^2)^(-1/2) > 0.
+ */
+int superdc_loewner(superdc_ctx *ctx, const superdc_batch *batch, const double *d,
+                    const double *z, const double *rho, const double *eta,
+                    const int32_t *origin, const int32_t *status, double *zhat,
+                    double *bnorm, const superdc_opts *opts, void *stream);
+
+/*
+ * Y = Qhat X (trans = 0) or Y = Qhat^T X (trans = 1) for every problem, with
+ * Qhat_ij = zhat_i bnorm_j / ((d_i - d_{K_j}) - eta_j) (eqs. eigvecs, qscale, qk).
+ * X and Y are total x m column-major with leading dimensions ldx, ldy >= total; they
+ * must not overlap.  m >= 1.
+ */
+int superdc_cauchy_apply(superdc_ctx *ctx, const superdc_batch *batch, const double *d,
+                         const double *zhat, const double *bnorm, const double *eta,
+                         const int32_t *origin, const int32_t *status, int trans, int32_t m,
+                         const double *X, int64_t ldx, double *Y, int64_t ldy,
+                         const superdc_opts *opts, void *stream);
+
+/*
+ * Adjoint of the rank-one eigensolver (not in the paper; implicit differentiation of
+ * f(lambda_k) = 0).  With r_ik = 1/((d_i - d_{K_k}) - eta_k), q_ik = b_k z_i r_ik,
+ * b_k = (sum_i z_i^2 r_ik^2)^(-1/2) and projections p_k = q_k^T u:
+ *   in : d, z, rho, eta, origin, status, g_lam[total] = dL/dlambda (may be NULL),
+ *        g_proj[total] = dL/dp (may be NULL), u[total] (NULL iff g_proj is NULL)
+ *   out: g_d[total] = dL/dd, g_z[total] = dL/dz, g_rho[nprob] = dL/drho.
+ */
+int superdc_secular_backward(superdc_ctx *ctx, const superdc_batch *batch, const double *d,
+                             const double *z, const double *rho, const double *eta,
+                             const int32_t *origin, const int32_t *status,
+                             const double *g_lam, const double *g_proj, const double *u,
+                             double *g_d, double *g_z, double *g_rho,
+                             const superdc_opts *opts, void *stream);
+
+/* ------------------------------------------------------------------------------------
+ * HSS conquering pass (Alg. 3) on a perfect binary tree.
+ *
+ * The symmetric HSS matrix is given by its generators (Sec. 2.1, eq. hss) with the leaf
+ * blocks already divided (Sec. 3): for a node p with children c1, c2
+ *     A_p = blkdiag(A_c1, A_c2) + Z_p Z_p^T,   Z_p = [U_c1 B_p / sqrt(beta_p) ; sqrt(beta_p) U_c2],
+ *     U_p = [U_c1 R_c1 ; U_c2 R_c2],  A_leaf = D_leaf      (eqs. du, divnew1; Alg. 1).
+ * The conquer computes every A_p's eigenvalues bottom-up: dense leaf eigendecompositions,
+ * then per node the merge of the children's spectra (permutation P_p) and r sequential
+ * rank-one updates (Sec. 2.2, eq. rankrupd), all nodes of one level in one batched call.
+ * The eigenvectors are kept in the structured form of Lemma 2 (eq. eigmat): per node the
+ * permutation and r Cauchy-like factors, per leaf a dense block.
+ * Levels are numbered as in the paper: root 0, leaves `depth`; node q of level l owns
+ * entries [q n_l, (q+1) n_l), n_l = leaf 2^(depth-l), n = leaf 2^depth.
+ * ---------------------------------------------------------------------------------- */
+typedef struct superdc_hss superdc_hss;
+
+/* Plan a tree: leaf in [2, 128] even, depth in [1, 20], r in [1, 8].  Allocates the
+ * level batches, the factor storage and work buffers (O(r n depth) doubles). */
+int superdc_hss_plan_create(superdc_ctx *ctx, int32_t leaf, int32_t depth, int32_t r,
+                            superdc_hss **plan);
+void superdc_hss_plan_destroy(superdc_hss *plan);
+
+/*
+ * Conquering pass.  Device inputs (row-major small matrices; heap index h = 2^l - 1 + q):
+ *   leaf_D [2^depth][leaf][leaf]  symmetric leaf blocks
+ *   leaf_U [2^depth][leaf][r]     leaf bases
+ *   R      [2^(depth+1) - 1][r][r] transfer matrices (the root's entry is unused)
+ *   B      [2^depth - 1][r][r]    coupling generator of each non-leaf node's children
+ *   beta   [2^depth - 1]          balancing scalars, > 0
+ * Outputs: lam[n] (eigenvalues of A_root, ascending); lam_levels[(depth+1) n] or NULL
+ * (row l: eigenvalues of every level-l node, ascending per node); status[1]: OR of the
+ * status bits of every rank-one problem solved.  The structured eigenmatrix stays in the
+ * plan for superdc_hss_apply until the next conquer on the same plan.
+ */
+int superdc_hss_conquer(superdc_ctx *ctx, superdc_hss *plan, const double *leaf_D,
+                        const double *leaf_U, const double *R, const double *B,
+                        const double *beta, double *lam, double *lam_levels, int32_t *status,
+                        const superdc_opts *opts, void *stream);
+
+/*
+ * Y = Q X (trans = 0) or Q^T X (trans = 1) with the eigenmatrix Q of A_root from the last
+ * conquer (Lemma 2, Alg. 4): n x m column-major, leading dimensions >= n, X and Y must not
+ * overlap.  Column k of Q is the eigenvector of lam[k].
+ */
+int superdc_hss_apply(superdc_ctx *ctx, superdc_hss *plan, int trans, int32_t m,
+                      const double *X, int64_t ldx, double *Y, int64_t ldy,
+                      const superdc_opts *opts, void *stream);
+
+/*
+ * Phase timing of superdc_hss_conquer (for measurement).  With timing enabled, each
+ * conquer records HIP events on its stream between phases.  superdc_hss_phase_times waits
+ * for the last conquer and returns, per phase, the summed milliseconds ms[6] and the
+ * number of timed intervals launches[6] (may be NULL): 0 leaf eigendecompositions,
+ * 1 merges and assemblies, 2 secular solves (validation + solver), 3 Loewner and b,
+ * 4 Cauchy applies, 5 final copies.  Returns SUPERDC_EINVAL if timing was off.
+ */
+int superdc_hss_set_timing(superdc_hss *plan, int enable);
+/* Copy the per-root solver evaluation counts of the last conquer to dst (device,
+ * int32[depth][r][n], level-major). */
+int superdc_hss_iterations(superdc_hss *plan, int32_t *dst, void *stream);
+int superdc_hss_phase_times(superdc_hss *plan, double *ms, int32_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SUPERDC_H */

@@ -1,0 +1,241 @@
+// apply.hip -- Y = Qhat X or Qhat^T X for the Cauchy-like eigenvector matrix on gfx950.
+//
+//   Qhat = diag(zhat) C diag(b),  C_ij = 1/((d_i - d_{K_j}) - eta_j)     (eqs. qscale, qk)
+//   Y = Qhat X   : Y_i = zhat_i sum_j C_ij (b_j X_j)       (Alg. 4, untransposed branch)
+//   Y = Qhat^T X : Y_j = b_j    sum_i C_ij (zhat_i X_i)    (Alg. 3 Z-update, Alg. 4)
+//
+// The product is a dense contraction whose left factor is generated, never stored.
+// MFMA kernel: a workgroup of 4 wavefronts owns 64 output rows (16 per wavefront) and
+// all right-hand sides in blocks of 64 columns.  The reduction runs over 64-entry chunks:
+// the scaled right-hand sides (b_s X_s or zhat_s X_s) and the per-entry pole data are
+// staged in LDS, then each wavefront generates its 16x4 slice of C with one reciprocal
+// per lane and feeds v_mfma_f64_16x16x4f64 against 4x16 slices of the staged block.
+// VALU kernel (few right-hand sides): one output row per lane, the same staging, and
+// plain FMAs.
+#include "common.h"
+
+namespace sdc {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int AP_ROWS = 64;   // output rows per workgroup
+constexpr int AP_K = 64;      // reduction chunk
+constexpr int AP_C = 64;      // right-hand sides per pass
+constexpr int AP_LD = AP_K + 1;
+
+// per-entry data of the reduction index s
+template <int TRANS>
+__device__ __forceinline__ void stage_entry(const ApplyArgs &a, int64_t base, int n, int s,
+                                            double2 &sd, double &scale) {
+    if (s < n) {
+        if (TRANS == 0) {  // s runs over roots: (d_{K_s}, eta_s), scale b_s
+            sd = make_double2(a.d[base + clamp_idx(a.origin[base + s], n)], a.eta[base + s]);
+            scale = a.bnorm[base + s];
+        } else {           // s runs over poles: (d_s, 0), scale zhat_s
+            sd = make_double2(a.d[base + s], 0.0);
+            scale = a.zhat[base + s];
+        }
+    } else {
+        sd = make_double2(0.0, 0.0);
+        scale = 0.0;
+    }
+}
+
+template <int TRANS>
+__device__ void apply_tile_mfma(const ApplyArgs &a, Tile t, double *Xs, double2 *Sd,
+                                double *Ssc) {
+    const int p = t.prob;
+    const int64_t base = a.off[p];
+    const int n = (int)(a.off[p + 1] - base);
+    const int lane = lane_id();
+    const int wv = threadIdx.x / WAVE;
+    const int o0 = t.row0;
+    if (a.status[p] & ~SUPERDC_ST_NOCONV) {
+        const double nan = __builtin_nan("");
+        for (int e = threadIdx.x; e < AP_ROWS * a.m; e += blockDim.x) {
+            const int r = o0 + (e % AP_ROWS), c = e / AP_ROWS;
+            if (r < n) a.Y[base + r + (int64_t)c * a.ldy] = nan;
+        }
+        return;
+    }
+    // row data for the entries of C this lane generates: row o = o0 + 16 wv + lane%16
+    const int orow = o0 + wv * 16 + (lane & 15);
+    const bool ovalid = orow < n;
+    const int oc = ovalid ? orow : n - 1;
+    double ra, rb = 0.0;
+    if (TRANS == 0) {
+        ra = a.d[base + oc];
+    } else {
+        ra = a.d[base + clamp_idx(a.origin[base + oc], n)];
+        rb = a.eta[base + oc];
+    }
+    for (int c0 = 0; c0 < a.m; c0 += AP_C) {
+        const int ncols = min(AP_C, a.m - c0);
+        const int nct = (ncols + 15) / 16;
+        v4d acc[4];
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) acc[ct] = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int s0 = 0; s0 < n; s0 += AP_K) {
+            __syncthreads();
+            if (threadIdx.x < AP_K) {
+                double2 sd;
+                double sc;
+                stage_entry<TRANS>(a, base, n, s0 + threadIdx.x, sd, sc);
+                Sd[threadIdx.x] = sd;
+                Ssc[threadIdx.x] = sc;
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < AP_K * nct * 16; e += blockDim.x) {
+                const int sl = e % AP_K, c = e / AP_K;
+                const int s = s0 + sl;
+                double v = 0.0;
+                if (s < n && c < ncols) v = Ssc[sl] * a.X[base + s + (int64_t)(c0 + c) * a.ldx];
+                Xs[c * AP_LD + sl] = v;
+            }
+            __syncthreads();
+#pragma unroll 4
+            for (int kk = 0; kk < AP_K; kk += 4) {
+                const int sl = kk + (lane >> 4);
+                const double2 sd = Sd[sl];
+                const double tt = TRANS ? (sd.x - ra) - rb : (ra - sd.x) - sd.y;
+                const double av = (ovalid && s0 + sl < n) ? rcp_nr(tt) : 0.0;
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct) {
+                    if (ct < nct) {
+                        const double bv = Xs[(ct * 16 + (lane & 15)) * AP_LD + sl];
+                        acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[ct], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        // v_mfma_f64_16x16x4f64 returns D[4 v + lane/16][lane % 16] in accumulator v
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = o0 + wv * 16 + 4 * v + (lane >> 4);
+            if (row < n) {
+                const double post = TRANS ? a.bnorm[base + row] : a.zhat[base + row];
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct) {
+                    const int col = ct * 16 + (lane & 15);
+                    if (ct < nct && col < ncols)
+                        a.Y[base + row + (int64_t)(c0 + col) * a.ldy] = post * acc[ct][v];
+                }
+            }
+        }
+    }
+}
+
+template <int TRANS>
+__global__ __launch_bounds__(256) void k_apply_mfma(ApplyArgs a, Queue *q) {
+    __shared__ double Xs[AP_C * AP_LD];
+    __shared__ double2 Sd[AP_K];
+    __shared__ double Ssc[AP_K];
+    __shared__ int slot;
+    if (q) {
+        for (;;) {
+            const int item = queue_pull(q, a.ntiles, &slot);
+            if (item < 0) break;
+            apply_tile_mfma<TRANS>(a, a.tiles[item], Xs, Sd, Ssc);
+        }
+        queue_leave(q);
+    } else if ((int)blockIdx.x < a.ntiles) {
+        apply_tile_mfma<TRANS>(a, a.tiles[blockIdx.x], Xs, Sd, Ssc);
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// VALU variant: one output row per lane, up to 8 right-hand sides per pass
+// ---------------------------------------------------------------------------------------
+constexpr int AV_C = 8;
+
+template <int TRANS>
+__device__ void apply_tile_valu(const ApplyArgs &a, Tile t, double *Xs, double2 *Sd) {
+    const int p = t.prob;
+    const int64_t base = a.off[p];
+    const int n = (int)(a.off[p + 1] - base);
+    const int lane = lane_id();
+    const int o = t.row0 + lane;
+    const bool ovalid = o < n;
+    if (a.status[p] & ~SUPERDC_ST_NOCONV) {
+        if (ovalid)
+            for (int c = 0; c < a.m; ++c) a.Y[base + o + (int64_t)c * a.ldy] = __builtin_nan("");
+        return;
+    }
+    const int oc = ovalid ? o : n - 1;
+    double ra, rb = 0.0;
+    if (TRANS == 0) {
+        ra = a.d[base + oc];
+    } else {
+        ra = a.d[base + clamp_idx(a.origin[base + oc], n)];
+        rb = a.eta[base + oc];
+    }
+    const double post = TRANS ? a.bnorm[base + oc] : a.zhat[base + oc];
+    for (int c0 = 0; c0 < a.m; c0 += AV_C) {
+        const int ncols = min(AV_C, a.m - c0);
+        double acc[AV_C];
+#pragma unroll
+        for (int c = 0; c < AV_C; ++c) acc[c] = 0.0;
+        for (int s0 = 0; s0 < n; s0 += WAVE) {
+            __syncthreads();
+            {
+                double2 sd;
+                double sc;
+                const int s = s0 + lane;
+                stage_entry<TRANS>(a, base, n, s, sd, sc);
+                Sd[lane] = sd;
+#pragma unroll
+                for (int c = 0; c < AV_C; ++c)
+                    Xs[lane * AV_C + c] =
+                        (s < n && c < ncols) ? sc * a.X[base + s + (int64_t)(c0 + c) * a.ldx] : 0.0;
+            }
+            __syncthreads();
+            const int cnt = min(WAVE, n - s0);
+            for (int sl = 0; sl < cnt; ++sl) {
+                const double2 sd = Sd[sl];
+                const double tt = TRANS ? (sd.x - ra) - rb : (ra - sd.x) - sd.y;
+                const double r = rcp_nr(tt);
+#pragma unroll
+                for (int c = 0; c < AV_C; ++c)
+                    if (c < ncols) acc[c] = __builtin_fma(r, Xs[sl * AV_C + c], acc[c]);
+            }
+        }
+        if (ovalid)
+            for (int c = 0; c < ncols; ++c) a.Y[base + o + (int64_t)(c0 + c) * a.ldy] = post * acc[c];
+    }
+}
+
+template <int TRANS>
+__global__ __launch_bounds__(64) void k_apply_valu(ApplyArgs a, Queue *q) {
+    __shared__ double Xs[WAVE * AV_C];
+    __shared__ double2 Sd[WAVE];
+    __shared__ int slot;
+    if (q) {
+        for (;;) {
+            const int item = queue_pull(q, a.ntiles, &slot);
+            if (item < 0) break;
+            apply_tile_valu<TRANS>(a, a.tiles[item], Xs, Sd);
+        }
+        queue_leave(q);
+    } else if ((int)blockIdx.x < a.ntiles) {
+        apply_tile_valu<TRANS>(a, a.tiles[blockIdx.x], Xs, Sd);
+    }
+}
+
+hipError_t launch_apply(const ApplyArgs &a, int use_mfma, Queue *q, int grid, hipStream_t s) {
+    if (a.ntiles <= 0) return hipSuccess;
+    const dim3 g(q ? grid : a.ntiles);
+    if (use_mfma) {
+        if (a.trans)
+            hipLaunchKernelGGL(k_apply_mfma<1>, g, dim3(256), 0, s, a, q);
+        else
+            hipLaunchKernelGGL(k_apply_mfma<0>, g, dim3(256), 0, s, a, q);
+    } else {
+        if (a.trans)
+            hipLaunchKernelGGL(k_apply_valu<1>, g, dim3(64), 0, s, a, q);
+        else
+            hipLaunchKernelGGL(k_apply_valu<0>, g, dim3(64), 0, s, a, q);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace sdc

@@ -1,0 +1,220 @@
+// common.h -- internal declarations shared by the gfx950 kernels and the C-ABI host code.
+//
+// Layout decisions (all FP64 unless stated):
+//   - Problems are stored back to back; work is cut into tiles of 64 consecutive entries
+//     (roots or poles) of one problem, one wavefront lane per entry.
+//   - Kernels read the per-pole data of a problem with wave-uniform indices, so the
+//     compiler serves them from the scalar data cache and every lane reuses them.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/superdc.h"
+
+namespace sdc {
+
+constexpr int WAVE = 64;       // CDNA wavefront width
+constexpr int TILE = 64;       // entries per work tile
+constexpr int SEC_CHUNK = 512; // roots per work item of the secular solver
+
+struct Tile {
+    int32_t prob;  // problem index
+    int32_t row0;  // first local row of the tile
+};
+
+// self-resetting work queue of a persistent launch (two counters, zero between launches)
+struct Queue {
+    unsigned int next;
+    unsigned int done;
+};
+
+// ----------------------------------------------------------------------------------
+// device helpers
+// ----------------------------------------------------------------------------------
+
+// 1/t from the hardware reciprocal estimate refined by two Newton steps
+// r <- r + r (1 - t r); each step squares the relative error.
+__device__ __forceinline__ double rcp_nr(double t) {
+    double r = __builtin_amdgcn_rcp(t);
+    double e = __builtin_fma(-t, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-t, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    return r;
+}
+
+// clamp a caller-supplied local index into [0, n) so a bad origin array cannot read
+// outside its problem
+__device__ __forceinline__ int clamp_idx(int K, int n) { return K < 0 ? 0 : (K >= n ? n - 1 : K); }
+
+// the same with a single Newton step (relative error <= ~11 ulp on gfx950)
+__device__ __forceinline__ double rcp_nr1(double t) {
+    const double r = __builtin_amdgcn_rcp(t);
+    return __builtin_fma(r, __builtin_fma(-t, r, 1.0), r);
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
+
+template <typename T>
+__device__ __forceinline__ T wave_uniform(T v) {
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+// Read-only data indexed by a wave-uniform index: going through the constant address
+// space lets the compiler fetch it with scalar loads into SGPRs (one fetch feeds all 64
+// lanes, and the vector memory path stays free).  Only for data no kernel of the same
+// launch writes.
+typedef const __attribute__((address_space(4))) double *const_double_ptr;
+
+__device__ __forceinline__ const_double_ptr as_const(const double *p) {
+    return (const_double_ptr)p;
+}
+// packed pairs / quads read component-wise (adjacent scalar loads merge into one fetch)
+struct cpair {
+    const_double_ptr p;
+    __device__ __forceinline__ double2 operator[](int j) const {
+        return make_double2(p[2 * j], p[2 * j + 1]);
+    }
+};
+struct cquad {
+    const_double_ptr p;
+    __device__ __forceinline__ double4 operator[](int j) const {
+        return make_double4(p[4 * j], p[4 * j + 1], p[4 * j + 2], p[4 * j + 3]);
+    }
+};
+__device__ __forceinline__ cpair as_const(const double2 *p) { return cpair{(const_double_ptr)p}; }
+__device__ __forceinline__ cquad as_const(const double4 *p) { return cquad{(const_double_ptr)p}; }
+typedef cpair const_double2_ptr;
+typedef cquad const_double4_ptr;
+
+// Pull the next work item from a persistent queue (called by whole wavefront-0 of a WG
+// and broadcast through LDS).  Returns -1 when the queue is drained.
+__device__ __forceinline__ int queue_pull(Queue *q, int nitems, int *slot) {
+    if (threadIdx.x == 0) *slot = (int)atomicAdd(&q->next, 1u);
+    __syncthreads();
+    int it = __builtin_amdgcn_readfirstlane(*slot);
+    __syncthreads();
+    return it < nitems ? it : -1;
+}
+
+// The last workgroup to leave resets the counters, so the next launch (or graph replay)
+// starts from zero without a memset.
+__device__ __forceinline__ void queue_leave(Queue *q) {
+    if (threadIdx.x == 0) {
+        __threadfence();
+        unsigned prev = atomicAdd(&q->done, 1u);
+        if (prev == gridDim.x - 1) {
+            atomicExch(&q->next, 0u);
+            atomicExch(&q->done, 0u);
+            __threadfence();
+        }
+    }
+}
+
+}  // namespace sdc
+
+// ----------------------------------------------------------------------------------
+// host-side objects
+// ----------------------------------------------------------------------------------
+#ifdef __cplusplus
+#include <vector>
+
+struct superdc_ctx {
+    int device = 0;
+    int num_cu = 256;
+    // grow-only workspace buffers
+    void *ws[8] = {nullptr};
+    size_t ws_cap[8] = {0};
+    sdc::Queue *queues = nullptr;  // kNumQueues counters, zeroed at creation
+};
+
+enum WsSlot { WS_DW = 0, WS_KE = 1, WS_DZ = 2, WS_Z2 = 3, WS_BK = 4, WS_BP = 5, WS_TMP = 6 };
+enum QueueSlot { Q_SECULAR = 0, Q_LOEWNER, Q_BNORM, Q_APPLY, Q_BWD1, Q_BWD2, Q_VALIDATE, kNumQueues };
+
+struct superdc_batch {
+    superdc_ctx *ctx = nullptr;
+    int32_t nprob = 0;
+    int64_t total = 0;
+    int32_t max_n = 0;
+    std::vector<int64_t> off_h;
+    int64_t *off_d = nullptr;
+    // tiles of 64 entries: longest problems first (batched) and in problem order (plain)
+    sdc::Tile *tiles_lpt = nullptr;
+    sdc::Tile *tiles_nat = nullptr;
+    int32_t ntiles = 0;
+    std::vector<int32_t> tile_begin;  // problem p owns tiles_nat[tile_begin[p] .. tile_begin[p+1])
+    // the same for the secular solver's chunks of SEC_CHUNK roots
+    sdc::Tile *chunks_lpt = nullptr;
+    sdc::Tile *chunks_nat = nullptr;
+    int32_t nchunks = 0;
+    std::vector<int32_t> chunk_begin;
+};
+
+namespace sdc {
+// grow a workspace slot to at least `bytes`; returns nullptr on allocation failure
+void *ws_get(superdc_ctx *ctx, int slot, size_t bytes);
+
+// kernel launchers (implemented next to their kernels); return hipError_t
+struct SolveArgs {
+    const int64_t *off;
+    const Tile *tiles;
+    int ntiles;
+    const double *d, *z, *rho;
+    double2 *dw;     // workspace (d_j, w_j)
+    double *z2;      // workspace sum_j w_j per problem
+    double2 *ke;     // workspace (d_{K_k}, eta_k) per root
+    double *lam, *eta;
+    int32_t *origin, *iters, *status;
+    double stop_c;
+    int max_iter;
+    int chunk;       // roots per work item (the tile list is cut at this length)
+};
+hipError_t launch_validate(const SolveArgs &a, int prob_first, int nprob, hipStream_t s);
+hipError_t launch_secular(const SolveArgs &a, Queue *q, int grid, hipStream_t s);
+
+struct VecArgs {
+    const int64_t *off;
+    const Tile *tiles;
+    int ntiles;
+    const double *d, *z, *rho, *eta;
+    const int32_t *origin, *status;
+    double2 *ke;   // workspace (d_K, eta) per root (rebuilt by loewner)
+    double2 *dz;   // workspace (d_i, zhat_i) per pole
+    double *zhat, *bnorm;
+};
+hipError_t launch_loewner(const VecArgs &a, Queue *q, int grid, hipStream_t s);
+hipError_t launch_bnorm(const VecArgs &a, Queue *q, int grid, hipStream_t s);
+
+struct ApplyArgs {
+    const int64_t *off;
+    const Tile *tiles;
+    int ntiles;
+    const double *d, *zhat, *bnorm, *eta;
+    const int32_t *origin, *status;
+    int trans;
+    int m;
+    const double *X;
+    int64_t ldx;
+    double *Y;
+    int64_t ldy;
+};
+hipError_t launch_apply(const ApplyArgs &a, int use_mfma, Queue *q, int grid, hipStream_t s);
+
+struct BwdArgs {
+    const int64_t *off;
+    const Tile *tiles;
+    int ntiles;
+    int nprob;
+    const double *d, *z, *rho, *eta;
+    const int32_t *origin, *status;
+    const double *g_lam, *g_proj, *u;
+    double *g_d, *g_z, *g_rho;
+    double4 *pz;    // workspace (d_i, z_i, u_i, 0) per pole
+    double4 *rk;    // workspace (d_K, eta, alpha, beta) per root
+    double *gk;     // workspace gamma per root
+};
+hipError_t launch_backward(const BwdArgs &a, int prob_first, int nprob, Queue *q1, Queue *q2,
+                           int grid, hipStream_t s);
+}  // namespace sdc
+#endif

@@ -1,0 +1,42 @@
+// hss.h -- internal declarations of the HSS conquering pass.
+#pragma once
+
+#include "common.h"
+
+namespace sdc {
+
+constexpr int LEAF_MAX = 128;      // largest leaf block (its matrix lives in LDS)
+constexpr int LEAF_RANK_MAX = 8;   // largest off-diagonal rank r
+
+struct LeafArgs {
+    int leaf, r, nleaf, max_sweeps;
+    const double *D;  // nleaf x leaf x leaf, row-major
+    const double *U;  // nleaf x leaf x r, row-major
+    double *Q;        // nleaf x leaf x leaf, eigenvector j contiguous, ascending order
+    double *lam;      // nleaf * leaf eigenvalues, ascending per leaf
+    double *W;        // Q^T U, column-major with leading dimension ldw
+    int64_t ldw;
+};
+
+struct AssembleArgs {
+    int64_t n;             // entries of the level
+    int nl, r, level;      // node size, rank, level of the parents
+    int with_basis;        // also form the basis columns (not at the root)
+    const int32_t *perm;   // merge permutation of the level
+    const double *Wprev;   // children's basis columns (n x r, ld n)
+    const double *B, *beta, *R;
+    double *M;             // output: n x 2r, ld n (Z in columns 0..r-1, V in r..2r-1)
+};
+
+hipError_t launch_leaf_jacobi(const LeafArgs &a, hipStream_t s);
+hipError_t launch_merge(const double *lam_children, double *d_out, int32_t *perm, int nc,
+                        int64_t n, hipStream_t s);
+hipError_t launch_assemble(const AssembleArgs &a, hipStream_t s);
+hipError_t launch_permute(const int32_t *perm, int nl, int64_t n, int m, const double *X,
+                          int64_t ldx, double *Y, int64_t ldy, int scatter, hipStream_t s);
+hipError_t launch_leaf_apply(const double *Q, int L, int64_t n, int m, const double *X,
+                             int64_t ldx, double *Y, int64_t ldy, int trans, hipStream_t s);
+hipError_t launch_status_or(const int32_t *st, int cnt, int32_t *out, hipStream_t s);
+hipError_t launch_fill(double *x, int64_t n, double v, hipStream_t s);
+
+}  // namespace sdc

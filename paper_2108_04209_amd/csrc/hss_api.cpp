@@ -1,0 +1,369 @@
+// hss_api.cpp -- host side of the HSS conquering pass (Alg. 3) and of the structured
+// eigenmatrix application (Lemma 2, Alg. 4).  Every level is one batch of 2^l equal
+// rank-one problems, so each phase of a level is one launch (or one launch per node with
+// opts->persistent = 0, the plain baseline).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "common.h"
+#include "hss.h"
+
+using namespace sdc;
+
+struct superdc_hss {
+    superdc_ctx *ctx = nullptr;
+    int leaf = 0, depth = 0, r = 0;
+    int64_t n = 0;
+    std::vector<superdc_batch *> batch;  // levels 0 .. depth-1
+    std::vector<void *> allocs;
+    double *leafQ = nullptr;   // 2^depth x leaf x leaf
+    double *leaf_lam = nullptr;
+    double *Wleaf = nullptr;   // n x r
+    double *M[2] = {nullptr, nullptr};  // n x 2r update / basis columns (ping-pong)
+    double *ones = nullptr;    // rho = 1 for every node
+    int32_t *iters = nullptr;
+    // per level l and step t
+    double *poles0 = nullptr;  // [depth][n] merged spectra (poles of step 0)
+    double *lam = nullptr;     // [depth][r][n] eigenvalues after step t (poles of step t+1)
+    double *eta = nullptr, *zhat = nullptr, *bn = nullptr;  // [depth][r][n]
+    int32_t *org = nullptr;    // [depth][r][n]
+    int32_t *perm = nullptr;   // [depth][n]
+    int32_t *status = nullptr; // [depth][r][2^(depth-1)]
+    double *T[2] = {nullptr, nullptr};  // apply work buffers
+    int64_t tcap = 0;
+    bool ready = false;
+    // optional phase timing: events recorded between phases of the last conquer
+    bool timing = false;
+    std::vector<hipEvent_t> ev;
+    std::vector<int> ev_phase;  // phase that ends at event i (0 leaf, 1 merge/assemble,
+                                // 2 secular, 3 loewner/b, 4 apply, 5 copies)
+    int nev = 0;
+
+    size_t idx(int l, int t) const { return ((size_t)l * r + t) * (size_t)n; }
+    int32_t *st(int l, int t) const {
+        return status + ((size_t)l * r + t) * ((size_t)1 << (depth - 1));
+    }
+    const double *poles(int l, int t) const { return t == 0 ? poles0 + (size_t)l * n : lam + idx(l, t - 1); }
+};
+
+namespace {
+template <typename T>
+hipError_t alloc(superdc_hss *h, T **p, size_t count) {
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, sizeof(T) * std::max<size_t>(count, 1));
+    if (e == hipSuccess) {
+        h->allocs.push_back(q);
+        *p = (T *)q;
+    }
+    return e;
+}
+
+int fail(hipError_t e) { return e == hipErrorOutOfMemory ? SUPERDC_ENOMEM : SUPERDC_EHIP; }
+
+// record the end of a phase (no-op unless timing is on)
+hipError_t mark(superdc_hss *h, int phase, hipStream_t s) {
+    if (!h->timing) return hipSuccess;
+    if (h->nev >= (int)h->ev.size()) {
+        hipEvent_t e;
+        hipError_t rc = hipEventCreate(&e);
+        if (rc != hipSuccess) return rc;
+        h->ev.push_back(e);
+        h->ev_phase.push_back(0);
+    }
+    h->ev_phase[h->nev] = phase;
+    return hipEventRecord(h->ev[h->nev++], s);
+}
+}  // namespace
+
+extern "C" {
+
+void superdc_hss_plan_destroy(superdc_hss *h) {
+    if (!h) return;
+    (void)hipDeviceSynchronize();
+    for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+    for (auto *b : h->batch) superdc_batch_destroy(b);
+    for (void *p : h->allocs) (void)hipFree(p);
+    delete h;
+}
+
+int superdc_hss_plan_create(superdc_ctx *ctx, int32_t leaf, int32_t depth, int32_t r,
+                            superdc_hss **out) {
+    if (!ctx || !out || leaf < 2 || leaf > LEAF_MAX || (leaf & 1) || depth < 1 || depth > 20 ||
+        r < 1 || r > LEAF_RANK_MAX)
+        return SUPERDC_EINVAL;
+    *out = nullptr;
+    superdc_hss *h = new (std::nothrow) superdc_hss();
+    if (!h) return SUPERDC_ENOMEM;
+    h->ctx = ctx;
+    h->leaf = leaf;
+    h->depth = depth;
+    h->r = r;
+    h->n = (int64_t)leaf << depth;
+    const int64_t n = h->n;
+    for (int l = 0; l < depth; ++l) {
+        const int64_t cnt = (int64_t)1 << l, nl = n / cnt;
+        std::vector<int64_t> off(cnt + 1);
+        for (int64_t q = 0; q <= cnt; ++q) off[q] = q * nl;
+        superdc_batch *b = nullptr;
+        int rc = superdc_batch_create(ctx, (int32_t)cnt, off.data(), &b);
+        if (rc) {
+            superdc_hss_plan_destroy(h);
+            return rc;
+        }
+        h->batch.push_back(b);
+    }
+    const size_t nleaf = (size_t)1 << depth;
+    hipError_t e = alloc(h, &h->leafQ, nleaf * leaf * leaf);
+    if (e == hipSuccess) e = alloc(h, &h->leaf_lam, n);
+    if (e == hipSuccess) e = alloc(h, &h->Wleaf, n * r);
+    if (e == hipSuccess) e = alloc(h, &h->M[0], n * 2 * r);
+    if (e == hipSuccess) e = alloc(h, &h->M[1], n * 2 * r);
+    if (e == hipSuccess) e = alloc(h, &h->ones, n);
+    if (e == hipSuccess) e = alloc(h, &h->iters, (size_t)depth * r * n);
+    if (e == hipSuccess) e = alloc(h, &h->poles0, (size_t)depth * n);
+    if (e == hipSuccess) e = alloc(h, &h->lam, (size_t)depth * r * n);
+    if (e == hipSuccess) e = alloc(h, &h->eta, (size_t)depth * r * n);
+    if (e == hipSuccess) e = alloc(h, &h->zhat, (size_t)depth * r * n);
+    if (e == hipSuccess) e = alloc(h, &h->bn, (size_t)depth * r * n);
+    if (e == hipSuccess) e = alloc(h, &h->org, (size_t)depth * r * n);
+    if (e == hipSuccess) e = alloc(h, &h->perm, (size_t)depth * n);
+    if (e == hipSuccess) e = alloc(h, &h->status, (size_t)depth * r * ((size_t)1 << (depth - 1)));
+    if (e == hipSuccess) e = launch_fill(h->ones, n, 1.0, nullptr);
+    // level l uses 2^l of the 2^(depth-1) status slots of each step; the rest stay 0
+    if (e == hipSuccess)
+        e = hipMemset(h->status, 0, sizeof(int32_t) * (size_t)depth * r * ((size_t)1 << (depth - 1)));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        superdc_hss_plan_destroy(h);
+        return fail(e);
+    }
+    *out = h;
+    return SUPERDC_OK;
+}
+
+int superdc_hss_conquer(superdc_ctx *ctx, superdc_hss *h, const double *leaf_D,
+                        const double *leaf_U, const double *R, const double *B,
+                        const double *beta, double *lam_out, double *lam_levels,
+                        int32_t *status_out, const superdc_opts *opts, void *stream) {
+    if (!ctx || !h || h->ctx != ctx || !leaf_D || !leaf_U || !R || !B || !beta || !lam_out ||
+        !status_out)
+        return SUPERDC_EINVAL;
+    superdc_opts o;
+    if (opts) o = *opts;
+    else superdc_opts_default(&o);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = h->n;
+    const int r = h->r, D = h->depth;
+    h->ready = false;
+    h->nev = 0;
+    hipError_t e;
+    if ((e = mark(h, -1, s)) != hipSuccess) return fail(e);
+
+    // leaves: dense eigendecompositions and W = Q^T U
+    LeafArgs la{};
+    la.leaf = h->leaf;
+    la.r = r;
+    la.nleaf = 1 << D;
+    la.max_sweeps = 30;
+    la.D = leaf_D;
+    la.U = leaf_U;
+    la.Q = h->leafQ;
+    la.lam = h->leaf_lam;
+    la.W = h->Wleaf;
+    la.ldw = n;
+    if ((e = launch_leaf_jacobi(la, s)) != hipSuccess) return fail(e);
+    if ((e = mark(h, 0, s)) != hipSuccess) return fail(e);
+
+    const double *child_lam = h->leaf_lam;
+    const double *Wprev = h->Wleaf;
+    int mbuf = 0;  // buffer the next assembly writes
+    for (int l = D - 1; l >= 0; --l) {
+        const int nl = (int)(n >> l);
+        superdc_batch *b = h->batch[l];
+        double *d0 = h->poles0 + (size_t)l * n;
+        int32_t *perm = h->perm + (size_t)l * n;
+        if ((e = launch_merge(child_lam, d0, perm, nl / 2, n, s)) != hipSuccess) return fail(e);
+        AssembleArgs aa{};
+        aa.n = n;
+        aa.nl = nl;
+        aa.r = r;
+        aa.level = l;
+        aa.with_basis = l > 0;
+        aa.perm = perm;
+        aa.Wprev = Wprev;
+        aa.B = B;
+        aa.beta = beta;
+        aa.R = R;
+        aa.M = h->M[mbuf];
+        if ((e = launch_assemble(aa, s)) != hipSuccess) return fail(e);
+        if ((e = mark(h, 1, s)) != hipSuccess) return fail(e);
+        const int ncol = l > 0 ? 2 * r : r;
+        int cur = mbuf;
+        for (int t = 0; t < r; ++t) {
+            const double *poles = h->poles(l, t);
+            const double *zc = h->M[cur] + (size_t)t * n;
+            double *lam_t = h->lam + h->idx(l, t);
+            double *eta_t = h->eta + h->idx(l, t);
+            int32_t *org_t = h->org + h->idx(l, t);
+            int32_t *st_t = h->st(l, t);
+            int rc = superdc_secular_solve(ctx, b, poles, zc, h->ones, lam_t, eta_t, org_t,
+                                           h->iters + h->idx(l, t), st_t, &o, stream);
+            if (rc) return rc;
+            if ((e = mark(h, 2, s)) != hipSuccess) return fail(e);
+            rc = superdc_loewner(ctx, b, poles, zc, h->ones, eta_t, org_t, st_t,
+                                 h->zhat + h->idx(l, t), h->bn + h->idx(l, t), &o, stream);
+            if (rc) return rc;
+            if ((e = mark(h, 3, s)) != hipSuccess) return fail(e);
+            const int m = ncol - t - 1;
+            if (m > 0) {
+                rc = superdc_cauchy_apply(ctx, b, poles, h->zhat + h->idx(l, t),
+                                          h->bn + h->idx(l, t), eta_t, org_t, st_t, 1, m,
+                                          h->M[cur] + (size_t)(t + 1) * n, n,
+                                          h->M[1 - cur] + (size_t)(t + 1) * n, n, &o, stream);
+                if (rc) return rc;
+                if ((e = mark(h, 4, s)) != hipSuccess) return fail(e);
+            }
+            cur = 1 - cur;
+        }
+        child_lam = h->lam + h->idx(l, r - 1);
+        Wprev = h->M[cur] + (size_t)r * n;  // basis columns after the last step
+        mbuf = 1 - cur;
+    }
+    e = hipMemcpyAsync(lam_out, h->lam + h->idx(0, r - 1), sizeof(double) * n,
+                       hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return fail(e);
+    if (lam_levels) {
+        for (int l = 0; l < D; ++l) {
+            e = hipMemcpyAsync(lam_levels + (size_t)l * n, h->lam + h->idx(l, r - 1),
+                               sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) return fail(e);
+        }
+        e = hipMemcpyAsync(lam_levels + (size_t)D * n, h->leaf_lam, sizeof(double) * n,
+                           hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return fail(e);
+    }
+    if ((e = launch_status_or(h->status, D * r * (1 << (D - 1)), status_out, s)) != hipSuccess)
+        return fail(e);
+    if ((e = mark(h, 5, s)) != hipSuccess) return fail(e);
+    h->ready = true;
+    return SUPERDC_OK;
+}
+
+int superdc_hss_iterations(superdc_hss *h, int32_t *dst, void *stream) {
+    if (!h || !dst || !h->ready) return SUPERDC_EINVAL;
+    const size_t cnt = (size_t)h->depth * h->r * h->n;
+    hipError_t e = hipMemcpyAsync(dst, h->iters, sizeof(int32_t) * cnt, hipMemcpyDeviceToDevice,
+                                  (hipStream_t)stream);
+    return e == hipSuccess ? SUPERDC_OK : fail(e);
+}
+
+int superdc_hss_set_timing(superdc_hss *h, int enable) {
+    if (!h) return SUPERDC_EINVAL;
+    h->timing = enable != 0;
+    return SUPERDC_OK;
+}
+
+int superdc_hss_phase_times(superdc_hss *h, double *ms, int32_t *launches) {
+    if (!h || !ms) return SUPERDC_EINVAL;
+    for (int i = 0; i < 6; ++i) {
+        ms[i] = 0.0;
+        if (launches) launches[i] = 0;
+    }
+    if (!h->timing || h->nev < 2) return SUPERDC_EINVAL;
+    hipError_t e = hipEventSynchronize(h->ev[h->nev - 1]);
+    if (e != hipSuccess) return fail(e);
+    for (int i = 1; i < h->nev; ++i) {
+        float t = 0.f;
+        if ((e = hipEventElapsedTime(&t, h->ev[i - 1], h->ev[i])) != hipSuccess) return fail(e);
+        const int ph = h->ev_phase[i];
+        if (ph >= 0 && ph < 6) {
+            ms[ph] += t;
+            if (launches) launches[ph] += 1;
+        }
+    }
+    return SUPERDC_OK;
+}
+
+int superdc_hss_apply(superdc_ctx *ctx, superdc_hss *h, int trans, int32_t m, const double *X,
+                      int64_t ldx, double *Y, int64_t ldy, const superdc_opts *opts,
+                      void *stream) {
+    if (!ctx || !h || h->ctx != ctx || !X || !Y || m < 1 || (trans != 0 && trans != 1))
+        return SUPERDC_EINVAL;
+    if (!h->ready || ldx < h->n || ldy < h->n) return SUPERDC_EINVAL;
+    superdc_opts o;
+    if (opts) o = *opts;
+    else superdc_opts_default(&o);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = h->n;
+    const int r = h->r, D = h->depth;
+    hipError_t e;
+    if (h->tcap < n * m) {
+        for (int i = 0; i < 2; ++i) {
+            if (h->T[i]) {
+                (void)hipDeviceSynchronize();
+                (void)hipFree(h->T[i]);
+                h->allocs.erase(std::find(h->allocs.begin(), h->allocs.end(), (void *)h->T[i]));
+                h->T[i] = nullptr;
+            }
+            if ((e = alloc(h, &h->T[i], n * m)) != hipSuccess) return fail(e);
+        }
+        h->tcap = n * m;
+    }
+    double *T0 = h->T[0], *T1 = h->T[1];
+    if (trans == 1) {
+        // Q^T X: leaves, then per level P and Qhat_1^T .. Qhat_r^T (Alg. 4, transposed)
+        if ((e = launch_leaf_apply(h->leafQ, h->leaf, n, m, X, ldx, T0, n, 1, s)) != hipSuccess)
+            return fail(e);
+        for (int l = D - 1; l >= 0; --l) {
+            const int nl = (int)(n >> l);
+            if ((e = launch_permute(h->perm + (size_t)l * n, nl, n, m, T0, n, T1, n, 0, s)) !=
+                hipSuccess)
+                return fail(e);
+            std::swap(T0, T1);
+            for (int t = 0; t < r; ++t) {
+                int rc = superdc_cauchy_apply(ctx, h->batch[l], h->poles(l, t),
+                                              h->zhat + h->idx(l, t), h->bn + h->idx(l, t),
+                                              h->eta + h->idx(l, t), h->org + h->idx(l, t),
+                                              h->st(l, t), 1, m, T0, n, T1, n, &o, stream);
+                if (rc) return rc;
+                std::swap(T0, T1);
+            }
+        }
+        for (int c = 0; c < m; ++c) {
+            e = hipMemcpyAsync(Y + c * ldy, T0 + c * n, sizeof(double) * n,
+                               hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) return fail(e);
+        }
+    } else {
+        // Q X: per level Qhat_r .. Qhat_1 then P^T, from the root down; leaves last
+        for (int c = 0; c < m; ++c) {
+            e = hipMemcpyAsync(T0 + c * n, X + c * ldx, sizeof(double) * n,
+                               hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) return fail(e);
+        }
+        for (int l = 0; l < D; ++l) {
+            const int nl = (int)(n >> l);
+            for (int t = r - 1; t >= 0; --t) {
+                int rc = superdc_cauchy_apply(ctx, h->batch[l], h->poles(l, t),
+                                              h->zhat + h->idx(l, t), h->bn + h->idx(l, t),
+                                              h->eta + h->idx(l, t), h->org + h->idx(l, t),
+                                              h->st(l, t), 0, m, T0, n, T1, n, &o, stream);
+                if (rc) return rc;
+                std::swap(T0, T1);
+            }
+            if ((e = launch_permute(h->perm + (size_t)l * n, nl, n, m, T0, n, T1, n, 1, s)) !=
+                hipSuccess)
+                return fail(e);
+            std::swap(T0, T1);
+        }
+        if ((e = launch_leaf_apply(h->leafQ, h->leaf, n, m, T0, n, Y, ldy, 0, s)) != hipSuccess)
+            return fail(e);
+    }
+    return SUPERDC_OK;
+}
+
+}  // extern "C"

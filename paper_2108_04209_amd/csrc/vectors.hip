@@ -1,0 +1,169 @@
+// vectors.hip -- Loewner update vector and eigenvector normalisation for gfx950.
+//
+//   rho zhat_i^2 = prod_j (lambda_j - d_i) / prod_{j != i} (d_j - d_i)    (eq. lowner)
+//   b_j          = (sum_i zhat_i^2 / (d_i - lambda_j)^2)^(-1/2)             (eq. b)
+// Every lambda_j - d_i is formed from the solver's shifted representation as
+// (d_{K_j} - d_i) + eta_j (eq. qk), so nearby roots keep their relative accuracy.
+//
+// The paper evaluates the Loewner products as exponentials of log sums through an FMM
+// (eqs. lowner2, logv).  Here each lane keeps the numerator and denominator products of
+// one pole as separate running products and strips their binary exponents every 8
+// factors (frexp), accumulating the exponents in an integer; one division and one
+// ldexp finish the pole.  No logarithms, and the 8-factor blocks cannot over- or
+// underflow for factors between 2^-120 and 2^120.
+#include "common.h"
+
+namespace sdc {
+
+// ke_j = (d_{K_j}, eta_j) for every root (origin indices are local to the problem)
+__global__ __launch_bounds__(64) void k_pack_ke(VecArgs a) {
+    const Tile t = a.tiles[blockIdx.x];
+    const int64_t base = a.off[t.prob];
+    const int n = (int)(a.off[t.prob + 1] - base);
+    const int k = t.row0 + lane_id();
+    if (k < n) {
+        const int K = clamp_idx(a.origin[base + k], n);
+        a.ke[base + k] = make_double2(a.d[base + K], a.eta[base + k]);
+    }
+}
+
+__device__ __forceinline__ void renorm(double &num, double &den, int &E) {
+    E += __builtin_amdgcn_frexp_exp(num) - __builtin_amdgcn_frexp_exp(den);
+    num = __builtin_amdgcn_frexp_mant(num);
+    den = __builtin_amdgcn_frexp_mant(den);
+}
+
+// products over roots j in [j0, j1); SKIP drops the denominator factor j == i
+template <bool SKIP>
+__device__ __forceinline__ void loewner_range(const_double2_ptr ke, const_double_ptr dd,
+                                              int j0, int j1,
+                                              int i, double di, double &num, double &den,
+                                              int &E) {
+#define SDC_LW_BODY(JJ)                                   \
+    {                                                     \
+        const double2 kv = ke[(JJ)];                      \
+        num *= (kv.x - di) + kv.y;                        \
+        const double f = dd[(JJ)] - di;                   \
+        den *= (SKIP && (JJ) == i) ? 1.0 : f;             \
+    }
+    int j = j0;
+    for (; j + 8 <= j1; j += 8) {
+        SDC_LW_BODY(j)
+        SDC_LW_BODY(j + 1)
+        SDC_LW_BODY(j + 2)
+        SDC_LW_BODY(j + 3)
+        SDC_LW_BODY(j + 4)
+        SDC_LW_BODY(j + 5)
+        SDC_LW_BODY(j + 6)
+        SDC_LW_BODY(j + 7)
+        renorm(num, den, E);
+    }
+    for (; j < j1; ++j) SDC_LW_BODY(j)
+    renorm(num, den, E);
+#undef SDC_LW_BODY
+}
+
+__device__ void loewner_tile(const VecArgs &a, Tile t) {
+    const int p = t.prob;
+    const int64_t base = a.off[p];
+    const int n = (int)(a.off[p + 1] - base);
+    const int i = t.row0 + lane_id();
+    const bool active = i < n;
+    if (a.status[p] & ~SUPERDC_ST_NOCONV) {
+        if (active) {
+            const double nan = __builtin_nan("");
+            a.zhat[base + i] = nan;
+            a.dz[base + i] = make_double2(a.d[base + i], nan);
+        }
+        return;
+    }
+    const int ii = active ? i : n - 1;
+    const_double2_ptr ke = as_const(a.ke + base);  // written by k_pack_ke
+    const_double_ptr dd = as_const(a.d + base);
+    const double di = a.d[base + ii];
+    double num = 1.0, den = 1.0;
+    int E = 0;
+    const int t1 = wave_uniform(min(t.row0 + TILE, n));
+    loewner_range<false>(ke, dd, 0, t.row0, ii, di, num, den, E);
+    loewner_range<true>(ke, dd, t.row0, t1, ii, di, num, den, E);
+    loewner_range<false>(ke, dd, t1, n, ii, di, num, den, E);
+    const double R = ldexp(num / den, E);
+    if (active) {
+        const double zi = a.z[base + i];
+        const double zh = copysign(sqrt(R / a.rho[p]), zi);
+        a.zhat[base + i] = zh;
+        a.dz[base + i] = make_double2(di, zh);
+    }
+}
+
+__device__ void bnorm_tile(const VecArgs &a, Tile t) {
+    const int p = t.prob;
+    const int64_t base = a.off[p];
+    const int n = (int)(a.off[p + 1] - base);
+    const int j = t.row0 + lane_id();
+    const bool active = j < n;
+    if (a.status[p] & ~SUPERDC_ST_NOCONV) {
+        if (active) a.bnorm[base + j] = __builtin_nan("");
+        return;
+    }
+    const_double2_ptr dz = as_const(a.dz + base);  // written by k_loewner
+    const double2 kv = a.ke[base + (active ? j : n - 1)];
+    double s0 = 0.0, s1 = 0.0;
+    int i = 0;
+    for (; i + 2 <= n; i += 2) {
+        const double2 p0 = dz[i], p1 = dz[i + 1];
+        const double q0 = p0.y * rcp_nr((p0.x - kv.x) - kv.y);
+        const double q1 = p1.y * rcp_nr((p1.x - kv.x) - kv.y);
+        s0 = __builtin_fma(q0, q0, s0);
+        s1 = __builtin_fma(q1, q1, s1);
+    }
+    if (i < n) {
+        const double2 p0 = dz[i];
+        const double q0 = p0.y * rcp_nr((p0.x - kv.x) - kv.y);
+        s0 = __builtin_fma(q0, q0, s0);
+    }
+    if (active) a.bnorm[base + j] = 1.0 / sqrt(s0 + s1);
+}
+
+__global__ __launch_bounds__(64) void k_loewner(VecArgs a, Queue *q) {
+    __shared__ int slot;
+    if (q) {
+        for (;;) {
+            const int item = queue_pull(q, a.ntiles, &slot);
+            if (item < 0) break;
+            loewner_tile(a, a.tiles[item]);
+        }
+        queue_leave(q);
+    } else if ((int)blockIdx.x < a.ntiles) {
+        loewner_tile(a, a.tiles[blockIdx.x]);
+    }
+}
+
+__global__ __launch_bounds__(64) void k_bnorm(VecArgs a, Queue *q) {
+    __shared__ int slot;
+    if (q) {
+        for (;;) {
+            const int item = queue_pull(q, a.ntiles, &slot);
+            if (item < 0) break;
+            bnorm_tile(a, a.tiles[item]);
+        }
+        queue_leave(q);
+    } else if ((int)blockIdx.x < a.ntiles) {
+        bnorm_tile(a, a.tiles[blockIdx.x]);
+    }
+}
+
+hipError_t launch_loewner(const VecArgs &a, Queue *q, int grid, hipStream_t s) {
+    if (a.ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack_ke, dim3(a.ntiles), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_loewner, dim3(q ? grid : a.ntiles), dim3(64), 0, s, a, q);
+    return hipGetLastError();
+}
+
+hipError_t launch_bnorm(const VecArgs &a, Queue *q, int grid, hipStream_t s) {
+    if (a.ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bnorm, dim3(q ? grid : a.ntiles), dim3(64), 0, s, a, q);
+    return hipGetLastError();
+}
+
+}  // namespace sdc
