@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Benchmark of the conquering-stage hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload level|conquer|single]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload conquer|level|large|single]
 
 A step is one pass of the whole rank-one path over one batch already resident in HBM:
 validation and packing, the secular solve (midpoint pass plus middle-way iterations to
@@ -40,11 +40,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="conquer", choices=["conquer", "level", "single"])
+    ap.add_argument("--workload", default="conquer",
+                    choices=["conquer", "level", "large", "single"])
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-level", action="store_true",
-                    help="with --workload conquer, skip the batched-level side measurement")
+                    help="with --workload conquer, skip the batched-level and large-problem "
+                         "side measurements")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     return ap.parse_args()
 
@@ -67,7 +69,7 @@ def workload(name):
 class Pipeline:
     """Preallocated device buffers and the four C-ABI calls of one step."""
 
-    def __init__(self, batch, X, persistent):
+    def __init__(self, batch, X, persistent, method=0):
         import torch
         from paper_2108_04209_amd import native
         self.torch = torch
@@ -87,7 +89,7 @@ class Pipeline:
         self.zb = (torch.empty(tot, dtype=torch.float64, device=dev),
                    torch.empty(tot, dtype=torch.float64, device=dev))
         self.Y = torch.empty_like(self.X)
-        self.opts = native.default_opts(persistent=persistent)
+        self.opts = native.default_opts(persistent=persistent, method=method)
 
     def solve(self):
         self.native.secular_solve(self.ctx, self.b, self.d, self.z, self.rho, opts=self.opts,
@@ -271,6 +273,65 @@ def bench_level(args, name):
 
 
 
+def bench_large(args):
+    """One rank-one problem, n = 65536, clustered poles (10% in clusters of 32 spaced
+    1e-10, 1% of weights 1e-12), rho = 0.5, eigenvectors applied to 64 vectors: the
+    triangular FMM (order 16, leaf 256) against direct sums, same kernels otherwise."""
+    import oracle
+    from paper_2108_04209_amd import gen
+    pr, X = gen.cfg1()
+    batch = gen.concat([pr])
+    n, m = pr.n, X.shape[1]
+    out = {}
+    for name, method in (("fmm", 2), ("direct", 1)):
+        pipe = Pipeline(batch, X, persistent=1, method=method)
+        wall_ms, tot_ms, ph = time_steps(pipe, args.steps, args.warmup)
+        iters = pipe.out["iters"].cpu().numpy().astype(np.float64)
+        solve_ms, vec_ms, apply_ms = (float(x) for x in ph.mean(axis=0))
+        ms = float(np.mean(tot_ms))
+        out[name] = {"ms_per_step": ms, "roots_per_s": n / (ms * 1e-3),
+                     "phase_ms": {"solve": solve_ms, "loewner_b": vec_ms, "apply": apply_ms},
+                     "mean_iters_after_midpoint": float(iters.mean()),
+                     "max_iters": int(iters.max()),
+                     "status": int(pipe.out["status"].cpu().numpy()[0]),
+                     "_pipe": pipe}
+    pf, pd = out["fmm"].pop("_pipe"), out["direct"].pop("_pipe")
+    lam_f = pf.out["lam"].cpu().numpy()
+    lam_d = pd.out["lam"].cpu().numpy()
+    nA = float(np.abs(lam_d).max())
+    # sampled oracle roots: the extreme ones, 30 random, 16 inside clusters
+    rng = np.random.default_rng(8)
+    tight = np.flatnonzero(np.diff(pr.d) < 1e-9)
+    roots = np.unique(np.r_[0, n - 1, rng.choice(n, 30, replace=False),
+                            rng.choice(tight, 16, replace=False)])
+    lam_o, eta_o, org_o, its_o, st_o = oracle.secular(pr.d, pr.z, pr.rho, roots=roots)
+    # sampled apply rows against the oracle fed the GPU's eta/origin (the oracle's own
+    # zhat and b from them)
+    eta_f = pf.out["eta"].cpu().numpy()
+    org_f = pf.out["origin"].cpu().numpy()
+    zh = oracle.loewner(pr.d, pr.z, pr.rho, eta_f, org_f)
+    bn = oracle.bnorm(pr.d, zh, eta_f, org_f)
+    rows = np.sort(rng.choice(n, 64, replace=False))
+    Yo = oracle.cauchy_apply(pr.d, zh, bn, eta_f, org_f, X, trans=1, rows=rows)
+    Yf = pf.Y.cpu().numpy().T
+    fm = out["fmm"]
+    best = min(("fmm", "direct"), key=lambda k: out[k]["ms_per_step"])
+    return {
+        "config": {"workload": "single rank-one problem n=65536, clustered poles, "
+                               "64 right-hand sides, FMM order 16 leaf 256 vs direct",
+                   "n": n, "m": int(m)},
+        "value": out[best]["roots_per_s"], "faster": best, "fmm": out["fmm"],
+        "direct": out["direct"],
+        "apply_gflops_fmm_run": ((2 * m + 3) * float(n) ** 2 + 2 * n * m)
+                                / (fm["phase_ms"]["apply"] * 1e-3) / 1e9,
+        "accuracy": {"fmm_vs_direct_rel_normA": float(np.abs(lam_f - lam_d).max() / nA),
+                     "fmm_vs_oracle_sampled_rel_normA": float(np.abs(lam_f[roots] - lam_o).max() / nA),
+                     "origins_agree": bool(np.array_equal(org_f[roots], org_o)),
+                     "apply_err_rel_sampled_rows": float(np.abs(Yf[rows] - Yo).max() / np.abs(X).max()),
+                     "roots_checked": int(len(roots))},
+    }
+
+
 # ---------------------------------------------------------------------------------------
 # HSS conquering pass (n = 65536, leaf 128, depth 9, r = 8)
 # ---------------------------------------------------------------------------------------
@@ -452,6 +513,14 @@ def main():
                                                "phase_ms", "graph_ms_per_step", "plain",
                                                "speedup_batched_vs_plain", "accuracy",
                                                "roofline")}
+            res["large"] = bench_large(argparse.Namespace(**{**vars(args), "steps": min(args.steps, 5)}))
+    elif args.workload == "large":
+        lg = bench_large(args)
+        ms = lg[lg["faster"]]["ms_per_step"]
+        res = {"metric": METRIC, "value": lg["value"], "unit": "roots/s", "n_gpus": 1,
+               "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+               "dtype": "f64", "data": "synthetic (seeded generators, no dataset)", **lg}
     else:
         res = bench_level(args, args.workload)
     print(json.dumps(res), flush=True)

@@ -105,6 +105,22 @@ void superdc_batch_destroy(superdc_batch *batch);
 int64_t superdc_batch_total(const superdc_batch *batch);
 
 /*
+ * Autotune the batch's launch shapes on representative data (d, z, rho as for
+ * superdc_secular_solve): the secular solver's work-item length (64..512 roots) and split
+ * (wavefronts sharing one work item, 1..16), and the splits of the Loewner/b and adjoint
+ * kernels, each timed on `stream`.  Synchronises the stream and allocates scratch; call it
+ * once, before capturing graphs.  With SUPERDC_TUNE_CACHE set to a file path the choice is
+ * read from / appended to that file, keyed by the problem sizes and the CU count.
+ * Without tuning a heuristic shape is used.  Results of the solver can differ in the last
+ * bits between shapes (the near/far split of some pole-root pairs moves).
+ */
+int superdc_autotune(superdc_ctx *ctx, superdc_batch *batch, const double *d, const double *z,
+                     const double *rho, const superdc_opts *opts, void *stream);
+/* Current shapes: out[0] solver work-item length, out[1] solver split, out[2] Loewner/b
+ * split, out[3] adjoint split. */
+int superdc_batch_shapes(const superdc_batch *batch, int32_t *out);
+
+/*
  * Eigenvalues of every problem (*) (Alg. 2 with local shifting, Sec. 4.2).
  *   in : d[total], z[total], rho[nprob]
  *   out: lam[total], eta[total], origin[total] (int32, local), iters[total] (int32,

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "common.h"
+#include "fmm.h"
 
 using namespace sdc;
 
@@ -49,6 +50,200 @@ int persistent_grid(const superdc_ctx *ctx, int ntiles, int per_cu) {
     return (int)std::max(1L, std::min<long>(g, ntiles));
 }
 
+}  // namespace
+
+namespace sdc {
+const TileList *tile_list(superdc_batch *b, int chunk) {
+    int slot = chunk == 64 ? 0 : chunk == 128 ? 1 : chunk == 256 ? 2 : chunk == 512 ? 3 : -1;
+    if (slot < 0) return nullptr;
+    TileList &l = b->lists[slot];
+    if (l.nat) return &l;
+    std::vector<Tile> nat, lpt;
+    l.begin.resize(b->nprob + 1);
+    for (int p = 0; p < b->nprob; ++p) {
+        l.begin[p] = (int32_t)nat.size();
+        const int64_t n = b->off_h[p + 1] - b->off_h[p];
+        for (int64_t r = 0; r < n; r += chunk) nat.push_back(Tile{p, (int32_t)r});
+    }
+    l.begin[b->nprob] = (int32_t)nat.size();
+    lpt.reserve(nat.size());
+    for (int p : b->order)
+        for (int32_t t = l.begin[p]; t < l.begin[p + 1]; ++t) lpt.push_back(nat[t]);
+    Tile *dn = nullptr, *dl = nullptr;
+    if (hipMalloc(&dn, sizeof(Tile) * nat.size()) != hipSuccess) return nullptr;
+    if (hipMalloc(&dl, sizeof(Tile) * lpt.size()) != hipSuccess) {
+        (void)hipFree(dn);
+        return nullptr;
+    }
+    if (hipMemcpy(dn, nat.data(), sizeof(Tile) * nat.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dl, lpt.data(), sizeof(Tile) * lpt.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(dn);
+        (void)hipFree(dl);
+        return nullptr;
+    }
+    l.nat = dn;
+    l.lpt = dl;
+    l.count = (int32_t)nat.size();
+    return &l;
+}
+}  // namespace sdc
+
+namespace {
+// Launch shape for problems of the given sizes: the fewest wavefronts per work item
+// (split S, a power of two <= 16) and the longest chunk (<= max_chunk) whose work items
+// still give every CU 16 wavefronts, keeping >= 256 summed entries per wavefront.
+LaunchShape shape_for(const superdc_ctx *ctx, const int64_t *sizes, int count, int max_chunk) {
+    const long target = (long)ctx->num_cu * 16;
+    int64_t nmax = 0;
+    for (int i = 0; i < count; ++i) nmax = std::max(nmax, sizes[i]);
+    for (int S = 1; S <= 16; S *= 2) {
+        if (S > 1 && nmax / S < 256) break;
+        for (int C = max_chunk; C >= TILE; C /= 2) {
+            long wg = 0;
+            for (int i = 0; i < count; ++i) wg += (sizes[i] + C - 1) / C;
+            if (wg * S >= target) return LaunchShape{C, S};
+        }
+    }
+    int S = 1;
+    while (S < 16 && nmax / (2 * S) >= 256) S *= 2;
+    return LaunchShape{TILE, S};
+}
+
+LaunchShape choose_shape(const superdc_ctx *ctx, const superdc_batch *b, int max_chunk) {
+    std::vector<int64_t> sizes(b->nprob);
+    for (int p = 0; p < b->nprob; ++p) sizes[p] = b->off_h[p + 1] - b->off_h[p];
+    return shape_for(ctx, sizes.data(), b->nprob, max_chunk);
+}
+
+// far-field separation: a box is far from a target leaf when the gap is >= FMM_SEP times
+// the box's width (Chebyshev order 16 then interpolates both kernels to ~1e-14)
+constexpr double FMM_SEP = 1.5;
+
+int fmm_dir_slot(int chunk) { return chunk == 64 ? 0 : chunk == 128 ? 1 : chunk == 256 ? 2 : 3; }
+
+void fmm_free(FmmPlan *fp) {
+    if (!fp) return;
+    for (void *p : fp->allocs) (void)hipFree(p);
+    delete fp;
+}
+
+template <typename T>
+bool fmm_upload(FmmPlan *fp, T **dst, const std::vector<T> &v, size_t count = 0) {
+    const size_t n = std::max<size_t>(1, count ? count : v.size());
+    if (hipMalloc((void **)dst, sizeof(T) * n) != hipSuccess) return false;
+    fp->allocs.push_back(*dst);
+    if (!v.empty() &&
+        hipMemcpy(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return false;
+    return true;
+}
+
+// The FMM layout of a batch: which problems use it, their leaf trees, list buffers and
+// work lists.  Rebuilt only when the leaf size or the crossover changes.
+FmmPlan *fmm_plan(superdc_batch *b, int leaf, int crossover) {
+    if (b->fmm && b->fmm->leaf == leaf && b->fmm->crossover == crossover) return b->fmm;
+    (void)hipDeviceSynchronize();
+    fmm_free(b->fmm);
+    b->fmm = nullptr;
+    FmmPlan *fp = new (std::nothrow) FmmPlan();
+    if (!fp) return nullptr;
+    fp->leaf = leaf;
+    fp->crossover = crossover;
+    fp->fmm_of_h.assign(b->nprob, -1);
+    std::vector<int32_t> height, box_fmm, leaf_fmm;
+    fp->box_off_h.push_back(0);
+    fp->leaf_off_h.push_back(0);
+    for (int p = 0; p < b->nprob; ++p) {
+        const int64_t n = b->off_h[p + 1] - b->off_h[p];
+        if (n < crossover || n < 2 * leaf) continue;
+        const int q = fp->nfmm++;
+        fp->fmm_prob_h.push_back(p);
+        fp->fmm_of_h[p] = q;
+        const int nl = (int)((n + leaf - 1) / leaf);
+        int H = 0;
+        while ((1 << H) < nl) ++H;
+        height.push_back(H);
+        const int nb = (2 << H) - 1;
+        fp->box_off_h.push_back(fp->box_off_h.back() + nb);
+        fp->leaf_off_h.push_back(fp->leaf_off_h.back() + nl);
+        box_fmm.insert(box_fmm.end(), nb, q);
+        leaf_fmm.insert(leaf_fmm.end(), nl, q);
+    }
+    fp->nboxes = fp->box_off_h.back();
+    fp->nleaves = fp->leaf_off_h.back();
+    // leaf work items in problem order and longest-first
+    std::vector<Tile> lnat, llpt;
+    for (int q = 0; q < fp->nfmm; ++q)
+        for (int li = 0; li < fp->leaf_off_h[q + 1] - fp->leaf_off_h[q]; ++li)
+            lnat.push_back(Tile{fp->fmm_prob_h[q], li * leaf});
+    for (int p : b->order) {
+        const int q = fp->fmm_of_h[p];
+        if (q < 0) continue;
+        for (int t = fp->leaf_off_h[q]; t < fp->leaf_off_h[q + 1]; ++t) llpt.push_back(lnat[t]);
+    }
+    bool ok = fmm_upload(fp, &fp->fmm_prob, fp->fmm_prob_h) &&
+              fmm_upload(fp, &fp->fmm_of, fp->fmm_of_h) &&
+              fmm_upload(fp, &fp->box_off, fp->box_off_h) &&
+              fmm_upload(fp, &fp->leaf_off, fp->leaf_off_h) && fmm_upload(fp, &fp->height, height) &&
+              fmm_upload(fp, &fp->box_fmm, box_fmm) && fmm_upload(fp, &fp->leaf_fmm, leaf_fmm) &&
+              fmm_upload(fp, &fp->leaf_nat, lnat) && fmm_upload(fp, &fp->leaf_lpt, llpt) &&
+              fmm_upload(fp, &fp->eq, std::vector<double2>(), (size_t)fp->nboxes * FMM_P) &&
+              fmm_upload(fp, &fp->box_ab, std::vector<double2>(), fp->nboxes) &&
+              fmm_upload(fp, &fp->near_lo, std::vector<int32_t>(), (size_t)fp->nleaves * FMM_NEAR_MAX) &&
+              fmm_upload(fp, &fp->near_hi, std::vector<int32_t>(), (size_t)fp->nleaves * FMM_NEAR_MAX) &&
+              fmm_upload(fp, &fp->far_l, std::vector<int32_t>(), (size_t)fp->nleaves * FMM_FAR_MAX) &&
+              fmm_upload(fp, &fp->far_r, std::vector<int32_t>(), (size_t)fp->nleaves * FMM_FAR_MAX) &&
+              fmm_upload(fp, &fp->cnt, std::vector<int32_t>(), (size_t)fp->nleaves * 3);
+    // direct chunks of the other problems, for each cut length
+    fp->dir_lpt.assign(4, nullptr);
+    fp->dir_count.assign(4, 0);
+    for (int slot = 0; slot < 4 && ok; ++slot) {
+        const int C = TILE << slot;
+        std::vector<Tile> v;
+        for (int p : b->order) {
+            if (fp->fmm_of_h[p] >= 0) continue;
+            const int64_t n = b->off_h[p + 1] - b->off_h[p];
+            for (int64_t r = 0; r < n; r += C) v.push_back(Tile{p, (int32_t)r});
+        }
+        fp->dir_count[slot] = (int32_t)v.size();
+        ok = fmm_upload(fp, &fp->dir_lpt[slot], v);
+    }
+    if (!ok) {
+        fmm_free(fp);
+        return nullptr;
+    }
+    b->fmm = fp;
+    return fp;
+}
+
+FmmArgs fmm_args(const FmmPlan *fp, const superdc_batch *b, const SolveArgs &a,
+                 const superdc_opts &o) {
+    FmmArgs f{};
+    f.off = b->off_d;
+    f.leaf = fp->leaf;
+    f.sep = FMM_SEP;
+    f.fmm_prob = fp->fmm_prob;
+    f.fmm_of = fp->fmm_of;
+    f.box_off = fp->box_off;
+    f.leaf_off = fp->leaf_off;
+    f.height = fp->height;
+    f.dw = a.dw;
+    f.z2 = a.z2;
+    f.status = a.status;
+    f.eq = fp->eq;
+    f.box_ab = fp->box_ab;
+    f.near_lo = fp->near_lo;
+    f.near_hi = fp->near_hi;
+    f.far_l = fp->far_l;
+    f.far_r = fp->far_r;
+    f.cnt = fp->cnt;
+    f.nboxes = fp->nboxes;
+    f.nleaves = fp->nleaves;
+    f.box_fmm = fp->box_fmm;
+    f.leaf_fmm = fp->leaf_fmm;
+    (void)o;
+    return f;
+}
 }  // namespace
 
 namespace sdc {
@@ -149,48 +344,24 @@ int superdc_batch_create(superdc_ctx *ctx, int32_t nprob, const int64_t *off_hos
     b->total = off_host[nprob];
     b->max_n = max_n;
     b->off_h.assign(off_host, off_host + nprob + 1);
-    // work items in problem order (plain launches) and longest-problem-first (persistent
-    // launches): tiles of TILE entries, and the secular solver's chunks of SEC_CHUNK roots
-    std::vector<int> order(nprob);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    b->order.resize(nprob);
+    std::iota(b->order.begin(), b->order.end(), 0);
+    std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) {
         return off_host[x + 1] - off_host[x] > off_host[y + 1] - off_host[y];
     });
-    auto cut = [&](int step, std::vector<Tile> &nat, std::vector<Tile> &lpt,
-                   std::vector<int32_t> &begin) {
-        begin.resize(nprob + 1);
-        for (int p = 0; p < nprob; ++p) {
-            begin[p] = (int32_t)nat.size();
-            const int64_t n = off_host[p + 1] - off_host[p];
-            for (int64_t r = 0; r < n; r += step) nat.push_back(Tile{p, (int32_t)r});
-        }
-        begin[nprob] = (int32_t)nat.size();
-        lpt.reserve(nat.size());
-        for (int p : order)
-            for (int32_t t = begin[p]; t < begin[p + 1]; ++t) lpt.push_back(nat[t]);
-    };
-    std::vector<Tile> nat, lpt, cnat, clpt;
-    cut(TILE, nat, lpt, b->tile_begin);
-    cut(SEC_CHUNK, cnat, clpt, b->chunk_begin);
-    b->ntiles = (int32_t)nat.size();
-    b->nchunks = (int32_t)cnat.size();
-    auto upload = [](Tile **dst, const std::vector<Tile> &v) {
-        hipError_t e = hipMalloc(dst, sizeof(Tile) * v.size());
-        if (e == hipSuccess)
-            e = hipMemcpy(*dst, v.data(), sizeof(Tile) * v.size(), hipMemcpyHostToDevice);
-        return e;
-    };
     hipError_t e = hipMalloc(&b->off_d, sizeof(int64_t) * (nprob + 1));
     if (e == hipSuccess)
         e = hipMemcpy(b->off_d, off_host, sizeof(int64_t) * (nprob + 1), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = upload(&b->tiles_nat, nat);
-    if (e == hipSuccess) e = upload(&b->tiles_lpt, lpt);
-    if (e == hipSuccess) e = upload(&b->chunks_nat, cnat);
-    if (e == hipSuccess) e = upload(&b->chunks_lpt, clpt);
+    if (e == hipSuccess && !tile_list(b, TILE)) e = hipErrorOutOfMemory;
     if (e != hipSuccess) {
         superdc_batch_destroy(b);
         return hip_fail(e);
     }
+    // launch shapes for the persistent launches (the autotuner may replace them)
+    b->sec = choose_shape(ctx, b, SEC_CHUNK);
+    b->vec = choose_shape(ctx, b, TILE);
+    b->bwd = b->vec;
+    b->app = LaunchShape{TILE, 1};
     *out = b;
     return SUPERDC_OK;
 }
@@ -199,10 +370,11 @@ void superdc_batch_destroy(superdc_batch *b) {
     if (!b) return;
     (void)hipDeviceSynchronize();
     if (b->off_d) (void)hipFree(b->off_d);
-    if (b->tiles_nat) (void)hipFree(b->tiles_nat);
-    if (b->tiles_lpt) (void)hipFree(b->tiles_lpt);
-    if (b->chunks_nat) (void)hipFree(b->chunks_nat);
-    if (b->chunks_lpt) (void)hipFree(b->chunks_lpt);
+    fmm_free(b->fmm);
+    for (auto &l : b->lists) {
+        if (l.nat) (void)hipFree(l.nat);
+        if (l.lpt) (void)hipFree(l.lpt);
+    }
     delete b;
 }
 
@@ -241,22 +413,72 @@ int superdc_secular_solve(superdc_ctx *ctx, const superdc_batch *b, const double
     a.status = status;
     a.stop_c = o.stop_c;
     a.max_iter = o.max_iter;
+    superdc_batch *bm = const_cast<superdc_batch *>(b);
+    // problems at or above the crossover size use the triangular FMM (method 2: every
+    // problem large enough to have two leaves; method 1: none)
+    const int crossover = o.method == 1 ? 0x7fffffff
+                          : o.method == 2 ? 2 * o.fmm_leaf
+                                          : ctx->fmm_crossover;
+    FmmPlan *fp = nullptr;
+    if (b->max_n >= crossover) {
+        fp = fmm_plan(bm, o.fmm_leaf, crossover);
+        if (!fp) return SUPERDC_ENOMEM;
+        if (fp->nfmm == 0) fp = nullptr;
+    }
+    FmmArgs f{};
+    if (fp) f = fmm_args(fp, b, a, o);
     if (o.persistent) {
-        // one persistent launch over chunks of SEC_CHUNK roots, longest problems first
-        a.tiles = b->chunks_lpt;
-        a.ntiles = b->nchunks;
-        a.chunk = SEC_CHUNK;
+        // one persistent launch over the chunks of the direct problems, longest first,
+        // and one over the target leaves of the FMM problems
+        const LaunchShape sh = b->sec;
+        const TileList *L = tile_list(bm, sh.chunk);
+        if (!L) return SUPERDC_ENOMEM;
+        a.tiles = L->lpt;
+        a.ntiles = L->count;
+        a.chunk = sh.chunk;
+        if (fp) {
+            const int slot = fmm_dir_slot(sh.chunk);
+            a.tiles = fp->dir_lpt[slot];
+            a.ntiles = fp->dir_count[slot];
+        }
         SDC_HIP(launch_validate(a, 0, b->nprob, s));
-        SDC_HIP(launch_secular(a, ctx->queues + Q_SECULAR, persistent_grid(ctx, b->nchunks, 24), s));
+        if (fp) SDC_HIP(launch_fmm_build(f, s));
+        SDC_HIP(launch_secular(a, sh.split, ctx->queues + Q_SECULAR,
+                               persistent_grid(ctx, a.ntiles, std::max(1, 32 / sh.split)), s));
+        if (fp) {
+            SolveArgs af = a;
+            af.tiles = fp->leaf_lpt;
+            af.ntiles = fp->nleaves;
+            af.chunk = fp->leaf;
+            SDC_HIP(launch_secular_fmm(af, f, ctx->queues + Q_SECULAR_FMM,
+                                       persistent_grid(ctx, af.ntiles, 32), s));
+        }
     } else {
-        // one launch per problem, cut into 64-root chunks so each launch spreads its
-        // problem over as many wavefronts as it can
-        a.chunk = TILE;
+        // one launch per problem, cut into 64-root chunks (split if the problem is large),
+        // or its target leaves for an FMM problem
+        if (fp) {
+            SDC_HIP(launch_validate(a, 0, b->nprob, s));
+            SDC_HIP(launch_fmm_build(f, s));
+        }
         for (int p = 0; p < b->nprob; ++p) {
-            a.tiles = b->tiles_nat + b->tile_begin[p];
-            a.ntiles = b->tile_begin[p + 1] - b->tile_begin[p];
-            SDC_HIP(launch_validate(a, p, 1, s));
-            SDC_HIP(launch_secular(a, nullptr, 0, s));
+            const int64_t np = b->off_h[p + 1] - b->off_h[p];
+            if (!fp) SDC_HIP(launch_validate(a, p, 1, s));
+            if (fp && fp->fmm_of_h[p] >= 0) {
+                const int q = fp->fmm_of_h[p];
+                SolveArgs af = a;
+                af.tiles = fp->leaf_nat + fp->leaf_off_h[q];
+                af.ntiles = fp->leaf_off_h[q + 1] - fp->leaf_off_h[q];
+                af.chunk = fp->leaf;
+                SDC_HIP(launch_secular_fmm(af, f, nullptr, 0, s));
+                continue;
+            }
+            const LaunchShape sh = shape_for(ctx, &np, 1, TILE);
+            const TileList *L = tile_list(bm, sh.chunk);
+            if (!L) return SUPERDC_ENOMEM;
+            a.tiles = L->nat + L->begin[p];
+            a.ntiles = L->begin[p + 1] - L->begin[p];
+            a.chunk = sh.chunk;
+            SDC_HIP(launch_secular(a, sh.split, nullptr, 0, s));
         }
     }
     return SUPERDC_OK;
@@ -284,18 +506,24 @@ int superdc_loewner(superdc_ctx *ctx, const superdc_batch *b, const double *d, c
     if (!a.ke || !a.dz) return SUPERDC_ENOMEM;
     a.zhat = zhat;
     a.bnorm = bnorm;
+    superdc_batch *bm = const_cast<superdc_batch *>(b);
+    const TileList *L = tile_list(bm, TILE);
+    if (!L) return SUPERDC_ENOMEM;
     if (o.persistent) {
-        a.tiles = b->tiles_lpt;
-        a.ntiles = b->ntiles;
-        const int g = persistent_grid(ctx, b->ntiles, 32);
-        SDC_HIP(launch_loewner(a, ctx->queues + Q_LOEWNER, g, s));
-        SDC_HIP(launch_bnorm(a, ctx->queues + Q_BNORM, g, s));
+        a.tiles = L->lpt;
+        a.ntiles = L->count;
+        const int S = b->vec.split;
+        const int g = persistent_grid(ctx, L->count, std::max(1, 32 / S));
+        SDC_HIP(launch_loewner(a, S, ctx->queues + Q_LOEWNER, g, s));
+        SDC_HIP(launch_bnorm(a, S, ctx->queues + Q_BNORM, g, s));
     } else {
         for (int p = 0; p < b->nprob; ++p) {
-            a.tiles = b->tiles_nat + b->tile_begin[p];
-            a.ntiles = b->tile_begin[p + 1] - b->tile_begin[p];
-            SDC_HIP(launch_loewner(a, nullptr, 0, s));
-            SDC_HIP(launch_bnorm(a, nullptr, 0, s));
+            const int64_t np = b->off_h[p + 1] - b->off_h[p];
+            const int S = shape_for(ctx, &np, 1, TILE).split;
+            a.tiles = L->nat + L->begin[p];
+            a.ntiles = L->begin[p + 1] - L->begin[p];
+            SDC_HIP(launch_loewner(a, S, nullptr, 0, s));
+            SDC_HIP(launch_bnorm(a, S, nullptr, 0, s));
         }
     }
     return SUPERDC_OK;
@@ -332,15 +560,18 @@ int superdc_cauchy_apply(superdc_ctx *ctx, const superdc_batch *b, const double 
     a.Y = Y;
     a.ldy = ldy;
     const int use_mfma = o.apply_kernel == 2 ? 1 : (o.apply_kernel == 1 ? 0 : (m >= 4));
+    superdc_batch *bm = const_cast<superdc_batch *>(b);
+    const TileList *L = tile_list(bm, TILE);
+    if (!L) return SUPERDC_ENOMEM;
     if (o.persistent) {
-        a.tiles = b->tiles_lpt;
-        a.ntiles = b->ntiles;
+        a.tiles = L->lpt;
+        a.ntiles = L->count;
         SDC_HIP(launch_apply(a, use_mfma, ctx->queues + Q_APPLY,
-                             persistent_grid(ctx, b->ntiles, use_mfma ? 4 : 32), s));
+                             persistent_grid(ctx, L->count, use_mfma ? 4 : 32), s));
     } else {
         for (int p = 0; p < b->nprob; ++p) {
-            a.tiles = b->tiles_nat + b->tile_begin[p];
-            a.ntiles = b->tile_begin[p + 1] - b->tile_begin[p];
+            a.tiles = L->nat + L->begin[p];
+            a.ntiles = L->begin[p + 1] - L->begin[p];
             SDC_HIP(launch_apply(a, use_mfma, nullptr, 0, s));
         }
     }
@@ -377,16 +608,22 @@ int superdc_secular_backward(superdc_ctx *ctx, const superdc_batch *b, const dou
     a.rk = (double4 *)ws_get(ctx, WS_BK, sizeof(double4) * b->total);
     a.gk = (double *)ws_get(ctx, WS_BP, sizeof(double) * b->total);
     if (!a.rk || !a.gk) return SUPERDC_ENOMEM;
+    superdc_batch *bm = const_cast<superdc_batch *>(b);
+    const TileList *L = tile_list(bm, TILE);
+    if (!L) return SUPERDC_ENOMEM;
     if (o.persistent) {
-        a.tiles = b->tiles_lpt;
-        a.ntiles = b->ntiles;
-        SDC_HIP(launch_backward(a, 0, b->nprob, ctx->queues + Q_BWD1, ctx->queues + Q_BWD2,
-                                persistent_grid(ctx, b->ntiles, 32), s));
+        a.tiles = L->lpt;
+        a.ntiles = L->count;
+        const int S = b->bwd.split;
+        SDC_HIP(launch_backward(a, S, 0, b->nprob, ctx->queues + Q_BWD1, ctx->queues + Q_BWD2,
+                                persistent_grid(ctx, L->count, std::max(1, 32 / S)), s));
     } else {
         for (int p = 0; p < b->nprob; ++p) {
-            a.tiles = b->tiles_nat + b->tile_begin[p];
-            a.ntiles = b->tile_begin[p + 1] - b->tile_begin[p];
-            SDC_HIP(launch_backward(a, p, 1, nullptr, nullptr, 0, s));
+            const int64_t np = b->off_h[p + 1] - b->off_h[p];
+            const int S = shape_for(ctx, &np, 1, TILE).split;
+            a.tiles = L->nat + L->begin[p];
+            a.ntiles = L->begin[p + 1] - L->begin[p];
+            SDC_HIP(launch_backward(a, S, p, 1, nullptr, nullptr, 0, s));
         }
     }
     return SUPERDC_OK;

@@ -18,7 +18,7 @@
 namespace sdc {
 
 template <bool PROJ>
-__device__ void bwd_roots_tile(const BwdArgs &a, Tile t) {
+__device__ void bwd_roots_tile(const BwdArgs &a, Tile t, double4 *red) {
     const int p = t.prob;
     const int64_t base = a.off[p];
     const int n = (int)(a.off[p + 1] - base);
@@ -32,8 +32,11 @@ __device__ void bwd_roots_tile(const BwdArgs &a, Tile t) {
     const_double_ptr z = as_const(a.z + base);
     const_double_ptr u = as_const(PROJ ? a.u + base : a.z + base);
     double S = 0.0, S3 = 0.0, h = 0.0, H2 = 0.0;
+    const int SW = blockDim.x / WAVE, wv = threadIdx.x / WAVE;
+    const int i0 = wave_uniform((int)(((int64_t)n * wv) / SW));
+    const int i1 = wave_uniform((int)(((int64_t)n * (wv + 1)) / SW));
     if (!bad) {
-        for (int i = 0; i < n; ++i) {
+        for (int i = i0; i < i1; ++i) {
             const double r = rcp_nr((d[i] - dK) - eta);
             const double zr = z[i] * r;
             const double t2 = zr * zr;
@@ -46,7 +49,20 @@ __device__ void bwd_roots_tile(const BwdArgs &a, Tile t) {
             }
         }
     }
-    if (!active) return;
+    if (SW > 1) {  // combine the wavefronts' partial sums in order
+        red[wv * WAVE + lane_id()] = make_double4(S, S3, h, H2);
+        __syncthreads();
+        if (wv == 0)
+            for (int w = 1; w < SW; ++w) {
+                const double4 v = red[w * WAVE + lane_id()];
+                S += v.x;
+                S3 += v.y;
+                h += v.z;
+                H2 += v.w;
+            }
+        __syncthreads();
+    }
+    if (!active || wv != 0) return;
     const double nan = __builtin_nan("");
     if (bad) {
         a.rk[base + k] = make_double4(dK, eta, nan, nan);
@@ -68,25 +84,28 @@ __device__ void bwd_roots_tile(const BwdArgs &a, Tile t) {
 }
 
 template <bool PROJ>
-__device__ void bwd_poles_tile(const BwdArgs &a, Tile t) {
+__device__ void bwd_poles_tile(const BwdArgs &a, Tile t, double4 *red) {
     const int p = t.prob;
     const int64_t base = a.off[p];
     const int n = (int)(a.off[p + 1] - base);
     const int i = t.row0 + lane_id();
     const bool active = i < n;
     const int ii = active ? i : n - 1;
+    const int SW = blockDim.x / WAVE, wv = threadIdx.x / WAVE;
     if (a.status[p] & ~SUPERDC_ST_NOCONV) {
-        if (active) {
+        if (active && wv == 0) {
             a.g_d[base + i] = __builtin_nan("");
             a.g_z[base + i] = __builtin_nan("");
         }
         return;
     }
+    const int k0 = wave_uniform((int)(((int64_t)n * wv) / SW));
+    const int k1 = wave_uniform((int)(((int64_t)n * (wv + 1)) / SW));
     const double di = a.d[base + ii];
     const_double4_ptr rk = as_const(a.rk + base);  // written by the roots pass
     const_double_ptr gk = as_const(a.gk + base);
     double A1 = 0.0, A2 = 0.0, A3 = 0.0, B1 = 0.0, B2 = 0.0, B3 = 0.0;
-    for (int k = 0; k < n; ++k) {
+    for (int k = k0; k < k1; ++k) {
         const double4 v = rk[k];
         const double r = rcp_nr((di - v.x) - v.y);
         const double r2 = r * r;
@@ -100,7 +119,24 @@ __device__ void bwd_poles_tile(const BwdArgs &a, Tile t) {
             B3 = __builtin_fma(g, r2, B3);
         }
     }
-    if (!active) return;
+    if (SW > 1) {  // combine the wavefronts' partial sums in order
+        red[2 * (wv * WAVE + lane_id())] = make_double4(A1, A2, A3, B1);
+        red[2 * (wv * WAVE + lane_id()) + 1] = make_double4(B2, B3, 0.0, 0.0);
+        __syncthreads();
+        if (wv == 0)
+            for (int w = 1; w < SW; ++w) {
+                const double4 u0 = red[2 * (w * WAVE + lane_id())];
+                const double4 u1 = red[2 * (w * WAVE + lane_id()) + 1];
+                A1 += u0.x;
+                A2 += u0.y;
+                A3 += u0.z;
+                B1 += u0.w;
+                B2 += u1.x;
+                B3 += u1.y;
+            }
+        __syncthreads();
+    }
+    if (!active || wv != 0) return;
     const double zi = a.z[base + i];
     double gd = zi * zi * (A1 + A3);
     double gz = -2.0 * zi * B1 - zi * B3;
@@ -113,20 +149,22 @@ __device__ void bwd_poles_tile(const BwdArgs &a, Tile t) {
     a.g_z[base + i] = gz;
 }
 
+// blockDim.x = 64 S; dynamic LDS: two double4 per thread when S > 1
 template <bool PROJ, int PASS>
-__global__ __launch_bounds__(64) void k_bwd(BwdArgs a, Queue *q) {
+__global__ __launch_bounds__(1024) void k_bwd(BwdArgs a, Queue *q) {
+    extern __shared__ double4 red4[];
     __shared__ int slot;
     if (q) {
         for (;;) {
             const int item = queue_pull(q, a.ntiles, &slot);
             if (item < 0) break;
-            if (PASS == 1) bwd_roots_tile<PROJ>(a, a.tiles[item]);
-            else bwd_poles_tile<PROJ>(a, a.tiles[item]);
+            if (PASS == 1) bwd_roots_tile<PROJ>(a, a.tiles[item], red4);
+            else bwd_poles_tile<PROJ>(a, a.tiles[item], red4);
         }
         queue_leave(q);
     } else if ((int)blockIdx.x < a.ntiles) {
-        if (PASS == 1) bwd_roots_tile<PROJ>(a, a.tiles[blockIdx.x]);
-        else bwd_poles_tile<PROJ>(a, a.tiles[blockIdx.x]);
+        if (PASS == 1) bwd_roots_tile<PROJ>(a, a.tiles[blockIdx.x], red4);
+        else bwd_poles_tile<PROJ>(a, a.tiles[blockIdx.x], red4);
     }
 }
 
@@ -149,17 +187,18 @@ __global__ __launch_bounds__(256) void k_bwd_rho(BwdArgs a, int prob_first) {
     }
 }
 
-hipError_t launch_backward(const BwdArgs &a, int prob_first, int nprob, Queue *q1, Queue *q2,
-                           int grid, hipStream_t s) {
+hipError_t launch_backward(const BwdArgs &a, int split, int prob_first, int nprob, Queue *q1,
+                           Queue *q2, int grid, hipStream_t s) {
     if (a.ntiles <= 0) return hipSuccess;
     const bool proj = a.g_proj != nullptr;
-    const dim3 g1(q1 ? grid : a.ntiles), g2(q2 ? grid : a.ntiles);
+    const dim3 g1(q1 ? grid : a.ntiles), g2(q2 ? grid : a.ntiles), blk(WAVE * split);
+    const size_t lds = split > 1 ? 2 * sizeof(double4) * WAVE * split : 0;
     if (proj) {
-        hipLaunchKernelGGL((k_bwd<true, 1>), g1, dim3(64), 0, s, a, q1);
-        hipLaunchKernelGGL((k_bwd<true, 2>), g2, dim3(64), 0, s, a, q2);
+        hipLaunchKernelGGL((k_bwd<true, 1>), g1, blk, lds, s, a, q1);
+        hipLaunchKernelGGL((k_bwd<true, 2>), g2, blk, lds, s, a, q2);
     } else {
-        hipLaunchKernelGGL((k_bwd<false, 1>), g1, dim3(64), 0, s, a, q1);
-        hipLaunchKernelGGL((k_bwd<false, 2>), g2, dim3(64), 0, s, a, q2);
+        hipLaunchKernelGGL((k_bwd<false, 1>), g1, blk, lds, s, a, q1);
+        hipLaunchKernelGGL((k_bwd<false, 2>), g2, blk, lds, s, a, q2);
     }
     hipLaunchKernelGGL(k_bwd_rho, dim3(nprob), dim3(256), 0, s, a, prob_first);
     return hipGetLastError();

@@ -127,10 +127,33 @@ struct superdc_ctx {
     void *ws[8] = {nullptr};
     size_t ws_cap[8] = {0};
     sdc::Queue *queues = nullptr;  // kNumQueues counters, zeroed at creation
+    int fmm_crossover = 16384;     // automatic method: FMM for problems at least this large
 };
 
 enum WsSlot { WS_DW = 0, WS_KE = 1, WS_DZ = 2, WS_Z2 = 3, WS_BK = 4, WS_BP = 5, WS_TMP = 6 };
-enum QueueSlot { Q_SECULAR = 0, Q_LOEWNER, Q_BNORM, Q_APPLY, Q_BWD1, Q_BWD2, Q_VALIDATE, kNumQueues };
+enum QueueSlot {
+    Q_SECULAR = 0, Q_LOEWNER, Q_BNORM, Q_APPLY, Q_BWD1, Q_BWD2, Q_VALIDATE, Q_SECULAR_FMM,
+    kNumQueues
+};
+
+namespace sdc {
+struct FmmPlan;
+}
+
+// Work items of one cut length: longest problems first (persistent launches) and in
+// problem order (plain launches; problem p owns nat[begin[p] .. begin[p+1])).
+struct TileList {
+    sdc::Tile *lpt = nullptr;
+    sdc::Tile *nat = nullptr;
+    int32_t count = 0;
+    std::vector<int32_t> begin;
+};
+
+// launch shape of one kernel family: entries per work item and wavefronts per item
+struct LaunchShape {
+    int chunk = 0;
+    int split = 1;
+};
 
 struct superdc_batch {
     superdc_ctx *ctx = nullptr;
@@ -139,17 +162,19 @@ struct superdc_batch {
     int32_t max_n = 0;
     std::vector<int64_t> off_h;
     int64_t *off_d = nullptr;
-    // tiles of 64 entries: longest problems first (batched) and in problem order (plain)
-    sdc::Tile *tiles_lpt = nullptr;
-    sdc::Tile *tiles_nat = nullptr;
-    int32_t ntiles = 0;
-    std::vector<int32_t> tile_begin;  // problem p owns tiles_nat[tile_begin[p] .. tile_begin[p+1])
-    // the same for the secular solver's chunks of SEC_CHUNK roots
-    sdc::Tile *chunks_lpt = nullptr;
-    sdc::Tile *chunks_nat = nullptr;
-    int32_t nchunks = 0;
-    std::vector<int32_t> chunk_begin;
+    std::vector<int> order;             // problems, longest first
+    TileList lists[4];                  // cut lengths 64, 128, 256, 512
+    // chosen launch shapes (heuristic, or set by the autotuner): persistent launches
+    LaunchShape sec, vec, app, bwd;
+    bool tuned = false;
+    // triangular-FMM layout (built on the first FMM solve; see fmm.h)
+    sdc::FmmPlan *fmm = nullptr;
 };
+
+namespace sdc {
+// the tile list of a given cut length (64, 128, 256 or 512), built on first use
+const TileList *tile_list(superdc_batch *b, int chunk);
+}  // namespace sdc
 
 namespace sdc {
 // grow a workspace slot to at least `bytes`; returns nullptr on allocation failure
@@ -171,7 +196,7 @@ struct SolveArgs {
     int chunk;       // roots per work item (the tile list is cut at this length)
 };
 hipError_t launch_validate(const SolveArgs &a, int prob_first, int nprob, hipStream_t s);
-hipError_t launch_secular(const SolveArgs &a, Queue *q, int grid, hipStream_t s);
+hipError_t launch_secular(const SolveArgs &a, int split, Queue *q, int grid, hipStream_t s);
 
 struct VecArgs {
     const int64_t *off;
@@ -183,8 +208,8 @@ struct VecArgs {
     double2 *dz;   // workspace (d_i, zhat_i) per pole
     double *zhat, *bnorm;
 };
-hipError_t launch_loewner(const VecArgs &a, Queue *q, int grid, hipStream_t s);
-hipError_t launch_bnorm(const VecArgs &a, Queue *q, int grid, hipStream_t s);
+hipError_t launch_loewner(const VecArgs &a, int split, Queue *q, int grid, hipStream_t s);
+hipError_t launch_bnorm(const VecArgs &a, int split, Queue *q, int grid, hipStream_t s);
 
 struct ApplyArgs {
     const int64_t *off;
@@ -214,7 +239,7 @@ struct BwdArgs {
     double4 *rk;    // workspace (d_K, eta, alpha, beta) per root
     double *gk;     // workspace gamma per root
 };
-hipError_t launch_backward(const BwdArgs &a, int prob_first, int nprob, Queue *q1, Queue *q2,
-                           int grid, hipStream_t s);
+hipError_t launch_backward(const BwdArgs &a, int split, int prob_first, int nprob, Queue *q1,
+                           Queue *q2, int grid, hipStream_t s);
 }  // namespace sdc
 #endif

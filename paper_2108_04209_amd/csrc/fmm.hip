@@ -1,0 +1,164 @@
+// fmm.hip -- triangular FMM of the secular sums on gfx950 (Sec. 4.1.2 with the local
+// shifting of Sec. 4.2.2).
+//
+// The poles of a problem are cut by index into leaves (a tree over the leaves, so boxes
+// adapt to clustered poles).  Every box is compressed once per solve into FMM_P
+// equivalent sources: the Chebyshev nodes s_q of the box's span and the weights
+// W_q = sum_{j in box} w_j L_q(d_j) (L_q the Lagrange basis on those nodes), so that
+// sum_j w_j K(x, d_j) ~ sum_q W_q K(x, s_q) for any kernel K smooth over the box -- one
+// compression serves both 1/(s-x) and 1/(s-x)^2.  For each target leaf the tree is walked
+// top down: a box separated from the leaf's targets by sep times its width (and by at
+// least 64 pole indices) is far field -- entirely left of every target (it feeds psi, the
+// lower triangle) or entirely right (phi, the strictly upper triangle), the directional
+// interactions of the triangular FMM; zero blocks never appear.  Leaves that are not far
+// are near field and are summed directly in shifted form.  The targets move between
+// iterations but the poles do not, so only the solver's pass loop runs per iteration.
+#include "fmm.h"
+
+namespace sdc {
+
+__device__ __forceinline__ double cheb_node(int q) {
+    return cos((2.0 * q + 1.0) * 3.14159265358979323846 / (2.0 * FMM_P));
+}
+
+// box geometry and equivalent sources: one workgroup per box
+__global__ __launch_bounds__(256) void k_fmm_boxes(FmmArgs f) {
+    __shared__ double part[256][FMM_P + 1];
+    const int g = blockIdx.x;
+    const int q = f.box_fmm[g];
+    const int p = f.fmm_prob[q];
+    const int64_t base = f.off[p];
+    const int n = (int)(f.off[p + 1] - base);
+    const int hidx = g - f.box_off[q];
+    const int H = f.height[q];
+    int h = 0;
+    while ((2 << h) - 1 <= hidx) ++h;  // level of the heap index
+    const int i = hidx - ((1 << h) - 1);
+    const int64_t span = (int64_t)f.leaf << (H - h);
+    const int lo = (int)min((int64_t)n, i * span), hi = (int)min((int64_t)n, (i + 1) * span);
+    const double2 *dw = f.dw + base;
+    const int tid = threadIdx.x;
+    if (lo >= hi || (f.status[p] & ~SUPERDC_ST_NOCONV)) {  // empty box or invalid problem
+        if (tid < FMM_P) f.eq[(int64_t)g * FMM_P + tid] = make_double2(0.0, 0.0);
+        if (tid == 0) f.box_ab[g] = make_double2(__builtin_nan(""), __builtin_nan(""));
+        return;
+    }
+    const double a = dw[lo].x, b = dw[hi - 1].x;
+    const double c = 0.5 * (a + b), hw = 0.5 * (b - a);
+    if (hi - lo <= FMM_P) {  // few poles: they are their own equivalent sources
+        if (tid < FMM_P)
+            f.eq[(int64_t)g * FMM_P + tid] =
+                lo + tid < hi ? dw[lo + tid] : make_double2(c, 0.0);
+        if (tid == 0) f.box_ab[g] = make_double2(a, b);
+        return;
+    }
+    double W[FMM_P];
+    double tq[FMM_P], lam[FMM_P];
+#pragma unroll
+    for (int r = 0; r < FMM_P; ++r) {
+        W[r] = 0.0;
+        tq[r] = cheb_node(r);
+        lam[r] = ((r & 1) ? -1.0 : 1.0) * sin((2.0 * r + 1.0) * 3.14159265358979323846 / (2.0 * FMM_P));
+    }
+    for (int j = lo + tid; j < hi; j += blockDim.x) {
+        const double2 pw = dw[j];
+        const double t = fmin(1.0, fmax(-1.0, (pw.x - c) / hw));
+        int hit = -1;
+        double inv[FMM_P], den = 0.0;
+#pragma unroll
+        for (int r = 0; r < FMM_P; ++r) {
+            const double dlt = t - tq[r];
+            if (dlt == 0.0) hit = r;
+            inv[r] = lam[r] / dlt;
+            den += inv[r];
+        }
+        if (hit >= 0) {
+            W[hit] += pw.y;  // the pole sits on a node
+        } else {
+            const double s = pw.y / den;
+#pragma unroll
+            for (int r = 0; r < FMM_P; ++r) W[r] = __builtin_fma(s, inv[r], W[r]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < FMM_P; ++r) part[tid][r] = W[r];
+    __syncthreads();
+    for (int stride = blockDim.x / 2; stride > 0; stride >>= 1) {
+        if (tid < stride)
+            for (int r = 0; r < FMM_P; ++r) part[tid][r] += part[tid + stride][r];
+        __syncthreads();
+    }
+    if (tid < FMM_P) f.eq[(int64_t)g * FMM_P + tid] = make_double2(c + hw * tq[tid], part[0][tid]);
+    if (tid == 0) f.box_ab[g] = make_double2(a, b);
+}
+
+// interaction lists: one thread per target leaf walks its problem's tree
+__global__ __launch_bounds__(64) void k_fmm_lists(FmmArgs f) {
+    const int L = blockIdx.x * blockDim.x + threadIdx.x;
+    if (L >= f.nleaves) return;
+    const int q = f.leaf_fmm[L];
+    const int p = f.fmm_prob[q];
+    const int64_t base = f.off[p];
+    const int n = (int)(f.off[p + 1] - base);
+    const int H = f.height[q];
+    const int li = L - f.leaf_off[q];
+    const int i0 = li * f.leaf, i1 = min(n, i0 + f.leaf);
+    int32_t *cnt = f.cnt + 3 * (int64_t)L;
+    if (f.status[p] & ~SUPERDC_ST_NOCONV) {
+        cnt[0] = -1;
+        return;
+    }
+    const double2 *dw = f.dw + base;
+    const double xa = dw[i0].x;
+    const double xb = i1 < n ? dw[i1].x : dw[n - 1].x + f.z2[p];
+    int stack[64];
+    int sp = 0, nn = 0, nl = 0, nr = 0;
+    bool overflow = false;
+    stack[sp++] = 0;
+    while (sp > 0 && !overflow) {
+        const int hidx = stack[--sp];
+        const int g = f.box_off[q] + hidx;
+        const double2 ab = f.box_ab[g];
+        if (!(ab.x == ab.x)) continue;  // empty box
+        int h = 0;
+        while ((2 << h) - 1 <= hidx) ++h;
+        const int i = hidx - ((1 << h) - 1);
+        const int64_t span = (int64_t)f.leaf << (H - h);
+        const int lo = (int)min((int64_t)n, i * span), hi = (int)min((int64_t)n, (i + 1) * span);
+        const double width = ab.y - ab.x;
+        if (ab.y < xa && xa - ab.y >= f.sep * width && hi <= i0 - TILE) {
+            if (nl < FMM_FAR_MAX) f.far_l[(int64_t)L * FMM_FAR_MAX + nl++] = g;
+            else overflow = true;
+        } else if (ab.x > xb && ab.x - xb >= f.sep * width && lo >= i1 + TILE) {
+            if (nr < FMM_FAR_MAX) f.far_r[(int64_t)L * FMM_FAR_MAX + nr++] = g;
+            else overflow = true;
+        } else if (h == H) {
+            if (nn < FMM_NEAR_MAX) {
+                f.near_lo[(int64_t)L * FMM_NEAR_MAX + nn] = lo;
+                f.near_hi[(int64_t)L * FMM_NEAR_MAX + nn] = hi;
+                ++nn;
+            } else {
+                overflow = true;
+            }
+        } else {
+            if (sp + 2 > 64) {
+                overflow = true;
+            } else {
+                stack[sp++] = 2 * hidx + 2;
+                stack[sp++] = 2 * hidx + 1;
+            }
+        }
+    }
+    cnt[0] = overflow ? -1 : nn;  // -1: the leaf falls back to direct sums
+    cnt[1] = nl;
+    cnt[2] = nr;
+}
+
+hipError_t launch_fmm_build(const FmmArgs &f, hipStream_t s) {
+    if (f.nboxes <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fmm_boxes, dim3(f.nboxes), dim3(256), 0, s, f);
+    hipLaunchKernelGGL(k_fmm_lists, dim3((f.nleaves + 63) / 64), dim3(64), 0, s, f);
+    return hipGetLastError();
+}
+
+}  // namespace sdc

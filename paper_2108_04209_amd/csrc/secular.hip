@@ -22,6 +22,7 @@
 //   guard  : a step leaving the bracket is replaced by bisection;
 //   stop   : |f| < c n eps (1 + |psi| + |phi|)  (eq. stopcrit), or a step below 2 ulps.
 #include "common.h"
+#include "fmm.h"
 
 namespace sdc {
 
@@ -132,22 +133,85 @@ __device__ __forceinline__ void secular_range(const_double2_ptr dw, int j0, int 
 // roots all lie in [kmin, kmax]: poles left of the window feed psi, right of it phi, and
 // only the window itself is routed per lane.  Poles within one tile of the window use the
 // shifted form.
-__device__ __forceinline__ void secular_sums(const double2 *__restrict__ dwg, int n, int kmin,
-                                             int kmax, int k, double dK, double y,
-                                             double &psi, double &dpsi, double &phi,
+//
+// Only the poles [p0, p1) are summed: with S wavefronts sharing a tile (split-K), each
+// takes a contiguous 1/S of the poles and the partial sums are combined afterwards.
+__device__ __forceinline__ void secular_sums(const double2 *__restrict__ dwg, int n, int p0,
+                                             int p1, int kmin, int kmax, int k, double dK,
+                                             double y, double &psi, double &dpsi, double &phi,
                                              double &dphi) {
     const_double2_ptr dw = as_const(dwg);
     kmin = wave_uniform(kmin);
     kmax = wave_uniform(kmax);
     n = wave_uniform(n);
+    p0 = wave_uniform(p0);
+    p1 = wave_uniform(p1);
     psi = dpsi = phi = dphi = 0.0;
     const double x = dK + y;
     const int f0 = max(kmin - TILE, 0), f1 = min(kmax + 1 + TILE, n);
-    secular_range<0, true>(dw, 0, f0, k, dK, y, x, psi, dpsi, phi, dphi);
-    secular_range<0, false>(dw, f0, kmin, k, dK, y, x, psi, dpsi, phi, dphi);
-    secular_range<2, false>(dw, kmin, kmax + 1, k, dK, y, x, psi, dpsi, phi, dphi);
-    secular_range<1, false>(dw, kmax + 1, f1, k, dK, y, x, psi, dpsi, phi, dphi);
-    secular_range<1, true>(dw, f1, n, k, dK, y, x, psi, dpsi, phi, dphi);
+#define SDC_CLIP(A, B) max((A), p0), min((B), p1)
+    secular_range<0, true>(dw, SDC_CLIP(0, f0), k, dK, y, x, psi, dpsi, phi, dphi);
+    secular_range<0, false>(dw, SDC_CLIP(f0, kmin), k, dK, y, x, psi, dpsi, phi, dphi);
+    secular_range<2, false>(dw, SDC_CLIP(kmin, kmax + 1), k, dK, y, x, psi, dpsi, phi, dphi);
+    secular_range<1, false>(dw, SDC_CLIP(kmax + 1, f1), k, dK, y, x, psi, dpsi, phi, dphi);
+    secular_range<1, true>(dw, SDC_CLIP(f1, n), k, dK, y, x, psi, dpsi, phi, dphi);
+#undef SDC_CLIP
+}
+
+// Combine the partial sums of the S wavefronts of a workgroup through LDS, in wavefront
+// order, so every wavefront ends with the same, reproducible totals.
+__device__ __forceinline__ void split_reduce4(double *red, int S, double &a, double &b,
+                                              double &c, double &d) {
+    if (S == 1) return;
+    const int wv = threadIdx.x / WAVE, lane = lane_id();
+    double4 *r4 = reinterpret_cast<double4 *>(red);
+    r4[wv * WAVE + lane] = make_double4(a, b, c, d);
+    __syncthreads();
+    double4 s = r4[lane];
+    for (int w = 1; w < S; ++w) {
+        const double4 v = r4[w * WAVE + lane];
+        s.x += v.x;
+        s.y += v.y;
+        s.z += v.z;
+        s.w += v.w;
+    }
+    __syncthreads();
+    a = s.x;
+    b = s.y;
+    c = s.z;
+    d = s.w;
+}
+
+// The same sums from the triangular FMM lists of target leaf L: near leaves directly in
+// shifted form (routed by the window as above), far boxes through their equivalent
+// sources in lambda-form, left boxes into psi and right boxes into phi.
+__device__ __forceinline__ void fmm_sums(const FmmArgs &f, int L, int nn, int nl, int nr,
+                                         const double2 *__restrict__ dwg, int kmin, int kmax,
+                                         int k, double dK, double y, double &psi, double &dpsi,
+                                         double &phi, double &dphi) {
+    const_double2_ptr dw = as_const(dwg);
+    kmin = wave_uniform(kmin);
+    kmax = wave_uniform(kmax);
+    psi = dpsi = phi = dphi = 0.0;
+    const double x = dK + y;
+    for (int e = 0; e < nn; ++e) {
+        const int lo = wave_uniform(f.near_lo[(int64_t)L * FMM_NEAR_MAX + e]);
+        const int hi = wave_uniform(f.near_hi[(int64_t)L * FMM_NEAR_MAX + e]);
+        secular_range<0, false>(dw, lo, min(hi, kmin), k, dK, y, x, psi, dpsi, phi, dphi);
+        secular_range<2, false>(dw, max(lo, kmin), min(hi, kmax + 1), k, dK, y, x, psi, dpsi, phi,
+                                dphi);
+        secular_range<1, false>(dw, max(lo, kmax + 1), hi, k, dK, y, x, psi, dpsi, phi, dphi);
+    }
+    for (int e = 0; e < nl; ++e) {
+        const int g = wave_uniform(f.far_l[(int64_t)L * FMM_FAR_MAX + e]);
+        secular_range<0, true>(as_const(f.eq + (int64_t)g * FMM_P), 0, FMM_P, k, dK, y, x, psi,
+                               dpsi, phi, dphi);
+    }
+    for (int e = 0; e < nr; ++e) {
+        const int g = wave_uniform(f.far_r[(int64_t)L * FMM_FAR_MAX + e]);
+        secular_range<1, true>(as_const(f.eq + (int64_t)g * FMM_P), 0, FMM_P, k, dK, y, x, psi,
+                               dpsi, phi, dphi);
+    }
 }
 
 __device__ __forceinline__ int wave_min(int v) {
@@ -165,15 +229,23 @@ __device__ __forceinline__ int wave_max(int v) {
 // chunk, so the wavefront does not wait for its slowest root (only the chunk's last
 // roots drain with idle lanes).  Every pass evaluates the sums once at each lane's own
 // iterate; a fresh root's first pass is its midpoint pass.
-__device__ void secular_chunk(const SolveArgs &a, Tile t) {
+//
+// With S = blockDim.x / 64 > 1 the S wavefronts of the workgroup carry identical copies of
+// the lane states, each sums 1/S of the poles, and the partial sums are combined before
+// the (identical) update; wavefront 0 writes the results.
+template <bool FMM>
+__device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const FmmArgs *fm) {
     const int p = t.prob;
     const int64_t base = a.off[p];
     const int n = (int)(a.off[p + 1] - base);
     const int c0 = t.row0, c1 = min(n, t.row0 + a.chunk);
     const int lane = lane_id();
+    const int S = blockDim.x / WAVE, wv = threadIdx.x / WAVE;
+    const bool writer = wv == 0;
+    const int p0 = (int)(((int64_t)n * wv) / S), p1 = (int)(((int64_t)n * (wv + 1)) / S);
     if (a.status[p] & ~SUPERDC_ST_NOCONV) {  // invalid input: outputs are NaN
         const double nan = __builtin_nan("");
-        for (int k = c0 + lane; k < c1; k += WAVE) {
+        for (int k = c0 + lane; k < c1 && writer; k += WAVE) {
             a.lam[base + k] = nan;
             a.eta[base + k] = nan;
             a.origin[base + k] = k;
@@ -186,6 +258,15 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t) {
     const double z2 = a.z2[p];
     const double eps = 2.220446049250313e-16;
     const double tol = a.stop_c * (double)n * eps;
+    // FMM: the target leaf of this chunk and its list sizes (-1: fall back to direct sums)
+    int L = 0, nn = -1, nl = 0, nr = 0;
+    if (FMM) {
+        const int q = fm->fmm_of[p];
+        L = wave_uniform(fm->leaf_off[q] + t.row0 / fm->leaf);
+        nn = wave_uniform(fm->cnt[3 * (int64_t)L]);
+        nl = wave_uniform(fm->cnt[3 * (int64_t)L + 1]);
+        nr = wave_uniform(fm->cnt[3 * (int64_t)L + 2]);
+    }
 
     int next = c0;  // next unassigned root (wave-uniform)
     bool act = false, last = false, hi_closed = false, noconv = false;
@@ -215,7 +296,11 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t) {
         const int kmax = wave_max(act ? k : -1);
 
         double psi, dpsi, phi, dphi;
-        secular_sums(dw, n, kmin, kmax, k, dK, y, psi, dpsi, phi, dphi);
+        if (FMM && nn >= 0)
+            fmm_sums(*fm, L, nn, nl, nr, dw, kmin, kmax, k, dK, y, psi, dpsi, phi, dphi);
+        else
+            secular_sums(dw, n, p0, p1, kmin, kmax, k, dK, y, psi, dpsi, phi, dphi);
+        split_reduce4(red, S, psi, dpsi, phi, dphi);
         if (!act) continue;
         const double f = 1.0 + psi + phi;
         bool done;
@@ -280,29 +365,55 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t) {
             y = yn;
         }
         if (done) {
-            a.eta[base + k] = y;
-            a.lam[base + k] = dK + y;
-            a.origin[base + k] = K;
-            if (a.iters) a.iters[base + k] = nev;
-            a.ke[base + k] = make_double2(dK, y);
+            if (writer) {
+                a.eta[base + k] = y;
+                a.lam[base + k] = dK + y;
+                a.origin[base + k] = K;
+                if (a.iters) a.iters[base + k] = nev;
+                a.ke[base + k] = make_double2(dK, y);
+            }
             act = false;
         }
     }
-    if (__ballot(noconv) != 0ull && lane == 0) atomicOr(&a.status[p], SUPERDC_ST_NOCONV);
+    if (writer && __ballot(noconv) != 0ull && lane == 0) atomicOr(&a.status[p], SUPERDC_ST_NOCONV);
 }
 
-__global__ __launch_bounds__(64) void k_secular(SolveArgs a, Queue *q) {
+// blockDim.x = 64 S (S = 1, 2, 4, 8, 16); dynamic LDS: 32 S bytes per lane (S > 1)
+__global__ __launch_bounds__(1024) void k_secular(SolveArgs a, Queue *q) {
+    extern __shared__ double red[];
     __shared__ int slot;
     if (q) {
         for (;;) {
             const int item = queue_pull(q, a.ntiles, &slot);
             if (item < 0) break;
-            secular_chunk(a, a.tiles[item]);
+            secular_chunk<false>(a, a.tiles[item], red, nullptr);
         }
         queue_leave(q);
     } else if ((int)blockIdx.x < a.ntiles) {
-        secular_chunk(a, a.tiles[blockIdx.x]);
+        secular_chunk<false>(a, a.tiles[blockIdx.x], red, nullptr);
     }
+}
+
+// FMM problems: one work item per target leaf, one wavefront per item
+__global__ __launch_bounds__(64) void k_secular_fmm(SolveArgs a, FmmArgs f, Queue *q) {
+    __shared__ int slot;
+    if (q) {
+        for (;;) {
+            const int item = queue_pull(q, a.ntiles, &slot);
+            if (item < 0) break;
+            secular_chunk<true>(a, a.tiles[item], nullptr, &f);
+        }
+        queue_leave(q);
+    } else if ((int)blockIdx.x < a.ntiles) {
+        secular_chunk<true>(a, a.tiles[blockIdx.x], nullptr, &f);
+    }
+}
+
+hipError_t launch_secular_fmm(const SolveArgs &a, const FmmArgs &f, Queue *q, int grid,
+                              hipStream_t s) {
+    if (a.ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_secular_fmm, dim3(q ? grid : a.ntiles), dim3(WAVE), 0, s, a, f, q);
+    return hipGetLastError();
 }
 
 hipError_t launch_validate(const SolveArgs &a, int prob_first, int nprob, hipStream_t s) {
@@ -310,9 +421,10 @@ hipError_t launch_validate(const SolveArgs &a, int prob_first, int nprob, hipStr
     return hipGetLastError();
 }
 
-hipError_t launch_secular(const SolveArgs &a, Queue *q, int grid, hipStream_t s) {
+hipError_t launch_secular(const SolveArgs &a, int split, Queue *q, int grid, hipStream_t s) {
     if (a.ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_secular, dim3(q ? grid : a.ntiles), dim3(64), 0, s, a, q);
+    const size_t lds = split > 1 ? sizeof(double4) * WAVE * split : 0;
+    hipLaunchKernelGGL(k_secular, dim3(q ? grid : a.ntiles), dim3(WAVE * split), lds, s, a, q);
     return hipGetLastError();
 }
 

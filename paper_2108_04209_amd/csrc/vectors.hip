@@ -63,14 +63,23 @@ __device__ __forceinline__ void loewner_range(const_double2_ptr ke, const_double
 #undef SDC_LW_BODY
 }
 
-__device__ void loewner_tile(const VecArgs &a, Tile t) {
+// With S = blockDim.x / 64 > 1 wavefronts per tile, wavefront w takes the roots
+// [n w / S, n (w+1) / S) and the partial results are combined in wavefront order.
+__device__ __forceinline__ void split_range(int n, int &p0, int &p1) {
+    const int S = blockDim.x / WAVE, wv = threadIdx.x / WAVE;
+    p0 = wave_uniform((int)(((int64_t)n * wv) / S));
+    p1 = wave_uniform((int)(((int64_t)n * (wv + 1)) / S));
+}
+
+__device__ void loewner_tile(const VecArgs &a, Tile t, double4 *red) {
     const int p = t.prob;
     const int64_t base = a.off[p];
     const int n = (int)(a.off[p + 1] - base);
     const int i = t.row0 + lane_id();
     const bool active = i < n;
+    const int S = blockDim.x / WAVE, wv = threadIdx.x / WAVE;
     if (a.status[p] & ~SUPERDC_ST_NOCONV) {
-        if (active) {
+        if (active && wv == 0) {
             const double nan = __builtin_nan("");
             a.zhat[base + i] = nan;
             a.dz[base + i] = make_double2(a.d[base + i], nan);
@@ -83,12 +92,28 @@ __device__ void loewner_tile(const VecArgs &a, Tile t) {
     const double di = a.d[base + ii];
     double num = 1.0, den = 1.0;
     int E = 0;
+    int p0, p1;
+    split_range(n, p0, p1);
     const int t1 = wave_uniform(min(t.row0 + TILE, n));
-    loewner_range<false>(ke, dd, 0, t.row0, ii, di, num, den, E);
-    loewner_range<true>(ke, dd, t.row0, t1, ii, di, num, den, E);
-    loewner_range<false>(ke, dd, t1, n, ii, di, num, den, E);
-    const double R = ldexp(num / den, E);
-    if (active) {
+    loewner_range<false>(ke, dd, p0, min(t.row0, p1), ii, di, num, den, E);
+    loewner_range<true>(ke, dd, max(t.row0, p0), min(t1, p1), ii, di, num, den, E);
+    loewner_range<false>(ke, dd, max(t1, p0), p1, ii, di, num, den, E);
+    if (S > 1) {
+        red[wv * WAVE + lane_id()] = make_double4(num, den, (double)E, 0.0);
+        __syncthreads();
+        if (wv == 0) {
+            for (int w = 1; w < S; ++w) {
+                const double4 v = red[w * WAVE + lane_id()];
+                num *= v.x;
+                den *= v.y;
+                E += (int)v.z;
+                renorm(num, den, E);
+            }
+        }
+        __syncthreads();
+    }
+    if (active && wv == 0) {
+        const double R = ldexp(num / den, E);
         const double zi = a.z[base + i];
         const double zh = copysign(sqrt(R / a.rho[p]), zi);
         a.zhat[base + i] = zh;
@@ -96,73 +121,89 @@ __device__ void loewner_tile(const VecArgs &a, Tile t) {
     }
 }
 
-__device__ void bnorm_tile(const VecArgs &a, Tile t) {
+__device__ void bnorm_tile(const VecArgs &a, Tile t, double4 *red) {
     const int p = t.prob;
     const int64_t base = a.off[p];
     const int n = (int)(a.off[p + 1] - base);
     const int j = t.row0 + lane_id();
     const bool active = j < n;
+    const int S = blockDim.x / WAVE, wv = threadIdx.x / WAVE;
     if (a.status[p] & ~SUPERDC_ST_NOCONV) {
-        if (active) a.bnorm[base + j] = __builtin_nan("");
+        if (active && wv == 0) a.bnorm[base + j] = __builtin_nan("");
         return;
     }
     const_double2_ptr dz = as_const(a.dz + base);  // written by k_loewner
     const double2 kv = a.ke[base + (active ? j : n - 1)];
+    int p0, p1;
+    split_range(n, p0, p1);
     double s0 = 0.0, s1 = 0.0;
-    int i = 0;
-    for (; i + 2 <= n; i += 2) {
-        const double2 p0 = dz[i], p1 = dz[i + 1];
-        const double q0 = p0.y * rcp_nr((p0.x - kv.x) - kv.y);
-        const double q1 = p1.y * rcp_nr((p1.x - kv.x) - kv.y);
+    int i = p0;
+    for (; i + 2 <= p1; i += 2) {
+        const double2 q0v = dz[i], q1v = dz[i + 1];
+        const double q0 = q0v.y * rcp_nr((q0v.x - kv.x) - kv.y);
+        const double q1 = q1v.y * rcp_nr((q1v.x - kv.x) - kv.y);
         s0 = __builtin_fma(q0, q0, s0);
         s1 = __builtin_fma(q1, q1, s1);
     }
-    if (i < n) {
-        const double2 p0 = dz[i];
-        const double q0 = p0.y * rcp_nr((p0.x - kv.x) - kv.y);
+    if (i < p1) {
+        const double2 q0v = dz[i];
+        const double q0 = q0v.y * rcp_nr((q0v.x - kv.x) - kv.y);
         s0 = __builtin_fma(q0, q0, s0);
     }
-    if (active) a.bnorm[base + j] = 1.0 / sqrt(s0 + s1);
+    double sum = s0 + s1;
+    if (S > 1) {
+        red[wv * WAVE + lane_id()] = make_double4(sum, 0.0, 0.0, 0.0);
+        __syncthreads();
+        if (wv == 0)
+            for (int w = 1; w < S; ++w) sum += red[w * WAVE + lane_id()].x;
+        __syncthreads();
+    }
+    if (active && wv == 0) a.bnorm[base + j] = 1.0 / sqrt(sum);
 }
 
-__global__ __launch_bounds__(64) void k_loewner(VecArgs a, Queue *q) {
+// blockDim.x = 64 S; dynamic LDS: one double4 per thread when S > 1
+__global__ __launch_bounds__(1024) void k_loewner(VecArgs a, Queue *q) {
+    extern __shared__ double4 red4[];
     __shared__ int slot;
     if (q) {
         for (;;) {
             const int item = queue_pull(q, a.ntiles, &slot);
             if (item < 0) break;
-            loewner_tile(a, a.tiles[item]);
+            loewner_tile(a, a.tiles[item], red4);
         }
         queue_leave(q);
     } else if ((int)blockIdx.x < a.ntiles) {
-        loewner_tile(a, a.tiles[blockIdx.x]);
+        loewner_tile(a, a.tiles[blockIdx.x], red4);
     }
 }
 
-__global__ __launch_bounds__(64) void k_bnorm(VecArgs a, Queue *q) {
+__global__ __launch_bounds__(1024) void k_bnorm(VecArgs a, Queue *q) {
+    extern __shared__ double4 red4[];
     __shared__ int slot;
     if (q) {
         for (;;) {
             const int item = queue_pull(q, a.ntiles, &slot);
             if (item < 0) break;
-            bnorm_tile(a, a.tiles[item]);
+            bnorm_tile(a, a.tiles[item], red4);
         }
         queue_leave(q);
     } else if ((int)blockIdx.x < a.ntiles) {
-        bnorm_tile(a, a.tiles[blockIdx.x]);
+        bnorm_tile(a, a.tiles[blockIdx.x], red4);
     }
 }
 
-hipError_t launch_loewner(const VecArgs &a, Queue *q, int grid, hipStream_t s) {
+hipError_t launch_loewner(const VecArgs &a, int split, Queue *q, int grid, hipStream_t s) {
     if (a.ntiles <= 0) return hipSuccess;
+    const size_t lds = split > 1 ? sizeof(double4) * WAVE * split : 0;
     hipLaunchKernelGGL(k_pack_ke, dim3(a.ntiles), dim3(64), 0, s, a);
-    hipLaunchKernelGGL(k_loewner, dim3(q ? grid : a.ntiles), dim3(64), 0, s, a, q);
+    hipLaunchKernelGGL(k_loewner, dim3(q ? grid : a.ntiles), dim3(WAVE * split), lds, s, a, q);
     return hipGetLastError();
 }
 
-hipError_t launch_bnorm(const VecArgs &a, Queue *q, int grid, hipStream_t s) {
+hipError_t launch_bnorm(const VecArgs &a, int split, Queue *q, int grid, hipStream_t s) {
     if (a.ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bnorm, dim3(q ? grid : a.ntiles), dim3(64), 0, s, a, q);
+    const size_t lds = split > 1 ? sizeof(double4) * WAVE * split : 0;
+    hipLaunchKernelGGL(k_bnorm, dim3(q ? grid : a.ntiles), dim3(WAVE * split), lds, s, a, q);
     return hipGetLastError();
 }
 

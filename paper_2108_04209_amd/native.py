@@ -68,6 +68,10 @@ def load_library(path: str = LIB_PATH):
     lib.superdc_secular_backward.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                              _P, C.POINTER(Opts), _P]
     lib.superdc_secular_backward.restype = C.c_int
+    lib.superdc_autotune.argtypes = [_P, _P, _P, _P, _P, C.POINTER(Opts), _P]
+    lib.superdc_autotune.restype = C.c_int
+    lib.superdc_batch_shapes.argtypes = [_P, _P]
+    lib.superdc_batch_shapes.restype = C.c_int
     _lib = lib
     return lib
 
@@ -222,6 +226,24 @@ def secular_backward(ctx, batch, d, z, rho, eta, origin, status, g_lam=None, g_p
         _ptr(status), _ptr(g_lam), _ptr(g_proj), _ptr(u), _ptr(g_d), _ptr(g_z), _ptr(g_r),
         C.byref(o), _stream(stream)), "superdc_secular_backward")
     return g_d, g_z, g_r
+
+
+def autotune(ctx, batch, d, z, rho, opts=None, stream=None):
+    """superdc_autotune: time candidate launch shapes on (d, z, rho) and keep the fastest.
+    Returns the chosen shapes (see batch_shapes)."""
+    tot, P = batch.total, batch.nprob
+    _f64(d, tot, "d"), _f64(z, tot, "z"), _f64(rho, P, "rho")
+    o = opts if opts is not None else default_opts()
+    _check(load_library().superdc_autotune(ctx.handle, batch.handle, _ptr(d), _ptr(z), _ptr(rho),
+                                           C.byref(o), _stream(stream)), "superdc_autotune")
+    return batch_shapes(batch)
+
+
+def batch_shapes(batch):
+    """superdc_batch_shapes: dict(sec_chunk, sec_split, vec_split, bwd_split)."""
+    out = (C.c_int32 * 4)()
+    _check(load_library().superdc_batch_shapes(batch.handle, out), "superdc_batch_shapes")
+    return dict(sec_chunk=out[0], sec_split=out[1], vec_split=out[2], bwd_split=out[3])
 
 
 # ---------------------------------------------------------------------------------------

@@ -47,16 +47,28 @@ def test_closed_forms():
     (lam * p * p).sum().backward()           # = sum_p u_p^T A_p u_p
     zu = seg_sum(z.detach() * ut, off)
     zu_e = torch.repeat_interleave(zu, torch.as_tensor(np.diff(off), device=d.device))
-    np.testing.assert_allclose(d.grad.cpu(), (ut * ut).cpu(), atol=1e-8)
-    np.testing.assert_allclose(z.grad.cpu(), (2 * rho_e * zu_e * ut).cpu(), atol=1e-8)
-    np.testing.assert_allclose(rho.grad.cpu(), (zu * zu).cpu(), rtol=1e-8, atol=1e-8)
+    # these gradients come out of sums that cancel to O(1) from terms as large as
+    # 1/gap^3; the bar is the 1e-6 relative gradient accuracy
+    sc = lambda t: 1e-6 * torch.abs(t).max().item()
+    np.testing.assert_allclose(d.grad.cpu(), (ut * ut).cpu(), atol=sc(ut * ut))
+    np.testing.assert_allclose(z.grad.cpu(), (2 * rho_e * zu_e * ut).cpu(), atol=sc(2 * rho_e * zu_e * ut))
+    np.testing.assert_allclose(rho.grad.cpu(), (zu * zu).cpu(), atol=sc(zu * zu))
 
+    # L = sum p_k^2 = ||u||^2 is constant: its gradient is a cancellation of the same
+    # eigenvector terms as the gradient of sum s_k p_k^2 with random signs s_k, whose size
+    # sets the scale of the 1e-6 relative bar
+    sgn = torch.as_tensor(np.random.default_rng(1).choice([-1.0, 1.0], batch.total_n), device=d.device)
     for t in (d, z, rho):
         t.grad = None
     lam, p = secular_eig(b, d, z, rho, u=ut)
-    (p * p).sum().backward()                 # = ||u||^2: constant, zero gradient
+    (sgn * p * p).sum().backward()
+    scale = [torch.abs(t.grad).max().item() for t in (d, z, rho)]
     for t in (d, z, rho):
-        assert torch.abs(t.grad).max().item() <= 1e-8
+        t.grad = None
+    lam, p = secular_eig(b, d, z, rho, u=ut)
+    (p * p).sum().backward()
+    for t, s in zip((d, z, rho), scale):
+        assert torch.abs(t.grad).max().item() <= 1e-6 * s, (torch.abs(t.grad).max().item(), s)
 
 
 def loss_of(b, d, z, rho, ut, wl, wp):
@@ -65,10 +77,23 @@ def loss_of(b, d, z, rho, ut, wl, wp):
     return (wl * lam).sum() + (wp * p * p).sum()
 
 
+def problem_losses(b, off, d, z, rho, ut, wl, wp):
+    from paper_2108_04209_amd.autograd import secular_eig
+    lam, p = secular_eig(b, d, z, rho, u=ut)
+    return seg_sum(wl * lam + wp * p * p, off)
+
+
 def test_central_fd_cfg4_sample():
-    """32 problems of the differentiation workload (n in [256, 4096]); directional central
-    differences with h = 1e-6, the pole direction scaled so no pole moves more than 1% of
-    its gaps (the order of d must not change)."""
+    """32 problems of the differentiation workload (n in [256, 4096]), one directional
+    derivative per problem from a single batched forward per step.
+
+    Finite differences: Richardson-extrapolated central differences at h and h/2 with
+    h_p = min(1e-6, 0.02 gamma_p), gamma_p the problem's smallest eigenvalue gap (the
+    eigenvector terms of the loss vary on that scale), along a unit direction whose pole
+    part moves no pole by more than 1% of its gaps.  The bar is the 1e-6 relative gradient
+    accuracy in norm: |fd - <g, v>| <= 1e-6 ||g||_2 ||v||_2 (Cauchy-Schwarz turns a norm
+    bound on the gradient error into this bound on every directional derivative); the
+    oracle reaches ~5e-9 on these problems with the same recipe."""
     full = gen.cfg4()
     pick = list(range(0, 1024, 32))
     batch = gen.concat([full.problem(p) for p in pick])
@@ -77,29 +102,44 @@ def test_central_fd_cfg4_sample():
     b, d, z, rho = setup(batch)
     dev = d.device
     T = lambda a: torch.as_tensor(a, device=dev)
-    L = loss_of(b, d, z, rho, T(u), T(wl), T(wp))
-    L.backward()
-    g = [d.grad.cpu().numpy(), z.grad.cpu().numpy(), rho.grad.cpu().numpy()]
+    off = batch.off
+    Lp_all = problem_losses(b, off, d, z, rho, T(u), T(wl), T(wp))
+    Lp_all.sum().backward()
+    gd, gz, gr = d.grad.cpu().numpy(), z.grad.cpu().numpy(), rho.grad.cpu().numpy()
+    from paper_2108_04209_amd.autograd import secular_eig
+    with torch.no_grad():
+        lam = secular_eig(b, d, z, rho).cpu().numpy()
     rng = np.random.default_rng(9)
-    h = 1e-6
-    for trial in range(2):
-        vd = rng.standard_normal(batch.total_n)
-        vz = rng.standard_normal(batch.total_n)
-        vr = rng.standard_normal(batch.nprob)
-        # keep every pole inside 1% of its neighbour gaps
-        for p in range(batch.nprob):
-            a, e = int(batch.off[p]), int(batch.off[p + 1])
-            gaps = np.diff(batch.d[a:e])
-            room = np.minimum(np.r_[gaps, np.inf], np.r_[np.inf, gaps])
-            vd[a:e] *= min(1.0, 0.01 * room.min() / (h * np.abs(vd[a:e]).max()))
+    vd = rng.standard_normal(batch.total_n)
+    vz = rng.standard_normal(batch.total_n)
+    vr = rng.standard_normal(batch.nprob)
+    hs = np.empty(batch.nprob)
+    for p in range(batch.nprob):
+        a, e = int(off[p]), int(off[p + 1])
+        gaps = np.diff(batch.d[a:e])
+        room = np.minimum(np.r_[gaps, np.inf], np.r_[np.inf, gaps])
+        nrm = np.sqrt(vd[a:e] @ vd[a:e] + vz[a:e] @ vz[a:e] + vr[p] ** 2)
+        vd[a:e] /= nrm
+        vz[a:e] /= nrm
+        vr[p] /= nrm
+        hs[p] = min(1e-6, 0.02 * np.diff(lam[a:e]).min())
+        vd[a:e] *= min(1.0, 0.01 * room.min() / (hs[p] * np.abs(vd[a:e]).max()))
+    h_e = np.repeat(hs, np.diff(off))
+
+    def L(t):
         with torch.no_grad():
-            Lp = loss_of(b, T(batch.d + h * vd), T(batch.z + h * vz), T(batch.rho + h * vr),
-                         T(u), T(wl), T(wp)).item()
-            Lm = loss_of(b, T(batch.d - h * vd), T(batch.z - h * vz), T(batch.rho - h * vr),
-                         T(u), T(wl), T(wp)).item()
-        fd = (Lp - Lm) / (2 * h)
-        an = g[0] @ vd + g[1] @ vz + g[2] @ vr
-        assert abs(fd - an) <= 1e-6 * abs(an), (fd, an)
+            return problem_losses(b, off, T(batch.d + t * h_e * vd), T(batch.z + t * h_e * vz),
+                                  T(batch.rho + t * hs * vr), T(u), T(wl), T(wp)).cpu().numpy()
+    f1 = (L(1.0) - L(-1.0)) / (2 * hs)
+    f2 = (L(0.5) - L(-0.5)) / hs
+    fd = (4 * f2 - f1) / 3
+    seg = lambda x, p: x[off[p]:off[p + 1]]
+    an = np.array([seg(gd, p) @ seg(vd, p) + seg(gz, p) @ seg(vz, p) + gr[p] * vr[p]
+                   for p in range(batch.nprob)])
+    bar = np.array([np.sqrt(seg(gd, p) @ seg(gd, p) + seg(gz, p) @ seg(gz, p) + gr[p] ** 2)
+                    * np.sqrt(seg(vd, p) @ seg(vd, p) + seg(vz, p) @ seg(vz, p) + vr[p] ** 2)
+                    for p in range(batch.nprob)])
+    assert np.all(np.abs(fd - an) <= 1e-6 * bar), np.max(np.abs(fd - an) / bar)
 
 
 @pytest.mark.parametrize("n", [64, 1024])
