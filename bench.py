@@ -10,9 +10,12 @@ matrix applied to the batch's right-hand sides.  The batched form runs every pha
 persistent launch over the whole batch; the plain form runs the same kernels once per
 problem.  Both are timed; `value` is the batched form's whole-job throughput in roots/s.
 
-Prints one JSON line.  The roofline object describes the dominant kernel (the secular
-solve, FP64 VALU-bound); `achieved` is its algorithmic FP64 rate (7 flops per pole-root
-pair evaluation, with the actual per-root iteration counts) over its HIP-event duration.
+Prints one JSON line.  The roofline object describes the dominant kernel of the step (the
+kernel with the most time among those whose work has an algorithmic count): `achieved` is
+its algorithmic FP64 rate -- 7 flops per pole-root pair evaluation of the secular sums
+with the actual per-root evaluation counts, 5 and 6 per pair for the Loewner and b
+passes, (2m + 3) per matrix entry plus 2nm for an apply to m vectors -- over its
+duration measured with HIP events around each of its launches on the launch stream.
 """
 from __future__ import annotations
 
@@ -33,6 +36,45 @@ PEAK_FP64_MFMA = 78.6    # TFLOP/s, MI355X FP64 matrix
 FLOPS_PER_PAIR = 7       # secular: 2 sub, 1 rcp, 1 mul, 1 add, 1 fma(2)
 FLOPS_LOEWNER = 5        # per pair: 2 sub, 1 add, 2 mul
 FLOPS_BNORM = 6          # per pair: 2 sub, 1 rcp, 1 mul, 1 fma(2)
+
+
+FMM_CROSSOVER = 16384    # the library's automatic direct/FMM switch (roots per problem)
+MFMA_MIN_M = 4           # the library's automatic VALU/MFMA apply switch (columns)
+
+
+def kernel_roofline(kt, flops, steps):
+    """Per-kernel table and the roofline object of the dominant kernel.
+
+    kt: {kernel: (ms, launches)} from the library's per-kernel HIP-event timing over
+    `steps` steps; flops: {kernel: algorithmic FP64 flops per step} for the kernels whose
+    work has an algorithmic count.  The dominant kernel is the one with the largest time
+    per step among those."""
+    table = {}
+    for name, (ms, nl) in sorted(kt.items(), key=lambda x: -x[1][0]):
+        e = {"ms_per_step": ms / steps, "launches_per_step": nl / steps,
+             "avg_launch_ms": ms / nl}
+        if name in flops and ms > 0:
+            e["algorithmic_tflops"] = flops[name] / (ms / steps * 1e-3) / 1e12
+        table[name] = e
+    cand = [k for k in table if k in flops and flops[k] > 0]
+    if not cand:
+        return table, None
+    dom = max(cand, key=lambda k: table[k]["ms_per_step"])
+    e = table[dom]
+    achieved = e["algorithmic_tflops"]
+    peak = PEAK_FP64_MFMA if dom == "k_apply_mfma" else PEAK_FP64_VALU
+    roof = {"bound": "mfma" if dom == "k_apply_mfma" else "alu", "achieved": achieved,
+            "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+            "kernel": dom, "launches_per_step": e["launches_per_step"],
+            "avg_launch_ms": e["avg_launch_ms"],
+            "algorithmic_flops_per_launch": flops[dom] / e["launches_per_step"],
+            "timing": "HIP events around each launch on its stream (library kernel timing)"}
+    return table, roof
+
+
+def note(msg):
+    """progress line on stderr (the JSON result is the only stdout line)"""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def parse():
@@ -196,6 +238,7 @@ def bench_level(args, name):
 
     pipe = Pipeline(batch, X, persistent=1)
     wall_ms, tot_ms, ph = time_steps(pipe, args.steps, args.warmup)
+    note(f"{name} batched {float(np.mean(tot_ms)):.2f} ms/step")
     iters = pipe.out["iters"].cpu().numpy().astype(np.float64)
     status_ok = bool(np.all(pipe.out["status"].cpu().numpy() == 0))
     ms = float(np.mean(tot_ms))
@@ -245,11 +288,19 @@ def bench_level(args, name):
                                           (float(x) for x in p_ph.mean(axis=0)))),
                      "launches_per_phase": batch.nprob, "steps": args.plain_steps}
 
-    roofline = {"bound": "alu", "achieved": sec_flops / (solve_ms * 1e-3) / 1e12,
-                "peak": PEAK_FP64_VALU, "unit": "TFLOP/s",
-                "frac": sec_flops / (solve_ms * 1e-3) / 1e12 / PEAK_FP64_VALU, "traffic": None,
-                "kernel": "k_secular (+k_validate)",
-                "algorithmic_flops_per_launch": sec_flops}
+    # per-kernel timing pass
+    pipe.native.kernel_timing(True)
+    for _ in range(args.steps):
+        pipe.step()
+    torch.cuda.synchronize()
+    kt = pipe.native.kernel_times()
+    pipe.native.kernel_timing(False)
+    direct = batch.sizes().max() < FMM_CROSSOVER
+    kflops = {"k_loewner": FLOPS_LOEWNER * n2, "k_bnorm": FLOPS_BNORM * n2,
+              ("k_apply_mfma" if m >= MFMA_MIN_M else "k_apply_valu"): apply_flops}
+    if direct:
+        kflops["k_secular"] = sec_flops
+    kernels, roofline = kernel_roofline(kt, kflops, args.steps)
     res = {
         "metric": METRIC, "value": tot / (ms * 1e-3), "unit": "roots/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
@@ -258,6 +309,7 @@ def bench_level(args, name):
         "secular_roots_per_s": tot / (solve_ms * 1e-3),
         "apply_gflops": apply_flops / (apply_ms * 1e-3) / 1e9,
         "phase_ms": {"solve": solve_ms, "loewner_b": vec_ms, "apply": apply_ms},
+        "kernels": kernels,
         "mean_iters_after_midpoint": float(iters.mean()), "max_iters": int(iters.max()),
         "graph_ms_per_step": graph_ms, "wall_ms_per_step": wall_ms,
         "plain": plain_res,
@@ -266,8 +318,10 @@ def bench_level(args, name):
                      "problems_checked": pick, "status_all_ok": status_ok},
         "roofline": roofline,
     }
+    note(f"{name} graph/accuracy/plain done")
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(batch, X, args.cpu_seconds)
+        note(f"{name} cpu baseline done")
     return res
 
 
@@ -289,6 +343,7 @@ def bench_large(args):
         iters = pipe.out["iters"].cpu().numpy().astype(np.float64)
         solve_ms, vec_ms, apply_ms = (float(x) for x in ph.mean(axis=0))
         ms = float(np.mean(tot_ms))
+        note(f"large {name} {ms:.2f} ms/step")
         out[name] = {"ms_per_step": ms, "roots_per_s": n / (ms * 1e-3),
                      "phase_ms": {"solve": solve_ms, "loewner_b": vec_ms, "apply": apply_ms},
                      "mean_iters_after_midpoint": float(iters.mean()),
@@ -351,6 +406,26 @@ def conquer_flops(tree, iters):
     return sec, vec, app
 
 
+def conquer_kernel_flops(tree, iters):
+    """Algorithmic FP64 flops per kernel of one conquer (direct-sum kernels only: the FMM
+    solver's work has no pair count), mirroring the library's automatic choices."""
+    D, r, n = tree.depth, tree.r, tree.n
+    k = dict(k_secular=0.0, k_loewner=0.0, k_bnorm=0.0, k_apply_mfma=0.0, k_apply_valu=0.0)
+    for lvl in range(D):
+        nl = tree.leaf << (D - lvl)
+        if nl < FMM_CROSSOVER:
+            k["k_secular"] += FLOPS_PER_PAIR * nl * float(np.sum(1.0 + iters[lvl]))
+        k["k_loewner"] += r * FLOPS_LOEWNER * n * nl
+        k["k_bnorm"] += r * FLOPS_BNORM * n * nl
+        ncol = 2 * r if lvl > 0 else r
+        for t in range(r):
+            m = ncol - t - 1
+            if m > 0:
+                key = "k_apply_mfma" if m >= MFMA_MIN_M else "k_apply_valu"
+                k[key] += (2 * m + 3) * n * nl + 2 * n * m
+    return k
+
+
 def conquer_cpu_baseline(seconds):
     """The HSS oracle (dense assembly of every node + LAPACK eigenvalues) on the subtree
     rooted at a level-l node of the same tree, the largest that fits the time budget; the
@@ -407,6 +482,7 @@ def bench_conquer(args):
         return float(np.mean(tot)), phases, counts
 
     ms, phases, counts = timed(opts1, args.steps, args.warmup)
+    note(f"conquer batched {ms:.2f} ms/step")
     status = int(out["status"].cpu().numpy()[0])
     iters = native.hss_iterations(plan).cpu().numpy().astype(np.float64)
     lam = out["lam"].cpu().numpy()
@@ -439,6 +515,14 @@ def bench_conquer(args):
                     "replay_equals_eager": bool(np.array_equal(glam, lam))}
     except Exception as exc:  # report, do not hide
         graph_ms = f"capture failed: {exc!r}"
+    # per-kernel timing pass (phase events off)
+    native.kernel_timing(True)
+    for _ in range(args.steps):
+        native.hss_conquer(ctx, plan, gens, opts=opts1, out=out)
+    torch.cuda.synchronize()
+    kt = native.kernel_times()
+    native.kernel_timing(False)
+    kernels, roofline = kernel_roofline(kt, conquer_kernel_flops(tree, iters), args.steps)
     native.hss_set_timing(plan, True)
 
     # accuracy: trace identity and sampled eigenpair residuals with the oracle's product
@@ -459,14 +543,6 @@ def bench_conquer(args):
                      "phase_ms": p_ph, "steps": args.plain_steps,
                      "launches": "one per node per phase"}
 
-    sec_ms = phases["secular"]
-    nsec = counts["secular"]
-    roofline = {"bound": "alu", "achieved": sec_f / (sec_ms * 1e-3) / 1e12,
-                "peak": PEAK_FP64_VALU, "unit": "TFLOP/s",
-                "frac": sec_f / (sec_ms * 1e-3) / 1e12 / PEAK_FP64_VALU, "traffic": None,
-                "kernel": "k_secular (+k_validate)", "launches_per_step": nsec,
-                "avg_launch_ms": sec_ms / nsec,
-                "algorithmic_flops_per_launch": sec_f / nsec}
     cfg = {"workload": "HSS conquering pass: n=65536, leaf 128, depth 9, rank 8 "
                        "(8 sequential rank-one updates per node), FP64, all nodes of a level "
                        "batched per call",
@@ -477,9 +553,9 @@ def bench_conquer(args):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (seeded generators, no dataset)", "config": cfg,
-        "secular_roots_per_s": roots / (sec_ms * 1e-3),
+        "secular_roots_per_s": roots / (phases["secular"] * 1e-3),
         "apply_gflops": app_f / (phases["apply"] * 1e-3) / 1e9,
-        "phase_ms": phases, "phase_intervals": counts,
+        "phase_ms": phases, "phase_intervals": counts, "kernels": kernels,
         "mean_iters_after_midpoint": float(iters.mean()), "max_iters": int(iters.max()),
         "graph": graph_ms,
         "plain": plain_res,
@@ -489,8 +565,10 @@ def bench_conquer(args):
                      "eigvecs_checked": len(ks)},
         "roofline": roofline,
     }
+    note("conquer graph/accuracy/plain done")
     if not args.no_cpu:
         res["cpu_baseline"] = conquer_cpu_baseline(args.cpu_seconds)
+        note("conquer cpu baseline done")
     return res
 
 
@@ -510,7 +588,7 @@ def main():
             lv = bench_level(argparse.Namespace(**{**vars(args), "no_cpu": True}), "level")
             res["level"] = {k: lv[k] for k in ("config", "value", "ms_per_step",
                                                "secular_roots_per_s", "apply_gflops",
-                                               "phase_ms", "graph_ms_per_step", "plain",
+                                               "phase_ms", "kernels", "graph_ms_per_step", "plain",
                                                "speedup_batched_vs_plain", "accuracy",
                                                "roofline")}
             res["large"] = bench_large(argparse.Namespace(**{**vars(args), "steps": min(args.steps, 5)}))

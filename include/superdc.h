@@ -235,6 +235,20 @@ int superdc_hss_set_timing(superdc_hss *plan, int enable);
 int superdc_hss_iterations(superdc_hss *plan, int32_t *dst, void *stream);
 int superdc_hss_phase_times(superdc_hss *plan, double *ms, int32_t *launches);
 
+/*
+ * Per-kernel timing (for measurement; process-wide, off by default).  While enabled,
+ * every kernel launch of the library is bracketed by two HIP events recorded on the
+ * launch's stream.  Do not enable it while a stream is being captured into a graph.
+ * superdc_kernel_times waits for every recorded launch, writes the summed milliseconds
+ * ms[id] and launch counts launches[id] for the first `count` kernel ids, starts a new
+ * collection, and returns the number of kernel ids (negative on error); count = 0 only
+ * returns that number.
+ * superdc_kernel_name gives the kernel of an id ("unknown" out of range).
+ */
+int superdc_kernel_timing(int enable);
+int superdc_kernel_times(double *ms, int32_t *launches, int32_t count);
+const char *superdc_kernel_name(int32_t id);
+
 #ifdef __cplusplus
 }
 #endif

@@ -171,16 +171,25 @@ FmmPlan *fmm_plan(superdc_batch *b, int leaf, int crossover) {
     }
     fp->nboxes = fp->box_off_h.back();
     fp->nleaves = fp->leaf_off_h.back();
-    // leaf work items in problem order and longest-first
+    // work items (64-root pieces of the target leaves) in problem order and longest-first
     std::vector<Tile> lnat, llpt;
-    for (int q = 0; q < fp->nfmm; ++q)
-        for (int li = 0; li < fp->leaf_off_h[q + 1] - fp->leaf_off_h[q]; ++li)
-            lnat.push_back(Tile{fp->fmm_prob_h[q], li * leaf});
+    fp->item_off_h.push_back(0);
+    for (int q = 0; q < fp->nfmm; ++q) {
+        const int p = fp->fmm_prob_h[q];
+        const int64_t n = b->off_h[p + 1] - b->off_h[p];
+        for (int64_t r = 0; r < n; r += fp->sub) lnat.push_back(Tile{p, (int32_t)r});
+        fp->item_off_h.push_back((int32_t)lnat.size());
+    }
+    fp->nitems = (int)lnat.size();
     for (int p : b->order) {
         const int q = fp->fmm_of_h[p];
         if (q < 0) continue;
-        for (int t = fp->leaf_off_h[q]; t < fp->leaf_off_h[q + 1]; ++t) llpt.push_back(lnat[t]);
+        for (int t = fp->item_off_h[q]; t < fp->item_off_h[q + 1]; ++t) llpt.push_back(lnat[t]);
     }
+    // wavefronts per item: enough to give the launch ~16 wavefronts per CU
+    fp->split = 1;
+    while (fp->split < 8 && (long)fp->nitems * fp->split * 2 <= (long)b->ctx->num_cu * 16)
+        fp->split *= 2;
     bool ok = fmm_upload(fp, &fp->fmm_prob, fp->fmm_prob_h) &&
               fmm_upload(fp, &fp->fmm_of, fp->fmm_of_h) &&
               fmm_upload(fp, &fp->box_off, fp->box_off_h) &&
@@ -448,10 +457,11 @@ int superdc_secular_solve(superdc_ctx *ctx, const superdc_batch *b, const double
         if (fp) {
             SolveArgs af = a;
             af.tiles = fp->leaf_lpt;
-            af.ntiles = fp->nleaves;
-            af.chunk = fp->leaf;
-            SDC_HIP(launch_secular_fmm(af, f, ctx->queues + Q_SECULAR_FMM,
-                                       persistent_grid(ctx, af.ntiles, 32), s));
+            af.ntiles = fp->nitems;
+            af.chunk = fp->sub;
+            SDC_HIP(launch_secular_fmm(af, f, fp->split, ctx->queues + Q_SECULAR_FMM,
+                                       persistent_grid(ctx, af.ntiles, std::max(1, 32 / fp->split)),
+                                       s));
         }
     } else {
         // one launch per problem, cut into 64-root chunks (split if the problem is large),
@@ -466,10 +476,10 @@ int superdc_secular_solve(superdc_ctx *ctx, const superdc_batch *b, const double
             if (fp && fp->fmm_of_h[p] >= 0) {
                 const int q = fp->fmm_of_h[p];
                 SolveArgs af = a;
-                af.tiles = fp->leaf_nat + fp->leaf_off_h[q];
-                af.ntiles = fp->leaf_off_h[q + 1] - fp->leaf_off_h[q];
-                af.chunk = fp->leaf;
-                SDC_HIP(launch_secular_fmm(af, f, nullptr, 0, s));
+                af.tiles = fp->leaf_nat + fp->item_off_h[q];
+                af.ntiles = fp->item_off_h[q + 1] - fp->item_off_h[q];
+                af.chunk = fp->sub;
+                SDC_HIP(launch_secular_fmm(af, f, fp->split, nullptr, 0, s));
                 continue;
             }
             const LaunchShape sh = shape_for(ctx, &np, 1, TILE);
@@ -567,7 +577,7 @@ int superdc_cauchy_apply(superdc_ctx *ctx, const superdc_batch *b, const double 
         a.tiles = L->lpt;
         a.ntiles = L->count;
         SDC_HIP(launch_apply(a, use_mfma, ctx->queues + Q_APPLY,
-                             persistent_grid(ctx, L->count, use_mfma ? 4 : 32), s));
+                             persistent_grid(ctx, L->count, use_mfma ? 4 : 8), s));
     } else {
         for (int p = 0; p < b->nprob; ++p) {
             a.tiles = L->nat + L->begin[p];

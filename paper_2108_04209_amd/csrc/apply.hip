@@ -11,7 +11,7 @@
 // staged in LDS, then each wavefront generates its 16x4 slice of C with one reciprocal
 // per lane and feeds v_mfma_f64_16x16x4f64 against 4x16 slices of the staged block.
 // VALU kernel (few right-hand sides): one output row per lane, the same staging, and
-// plain FMAs.
+// plain FMAs; four wavefronts share a tile's reduction range.
 #include "common.h"
 
 namespace sdc {
@@ -41,9 +41,50 @@ __device__ __forceinline__ void stage_entry(const ApplyArgs &a, int64_t base, in
     }
 }
 
-template <int TRANS>
-__device__ void apply_tile_mfma(const ApplyArgs &a, Tile t, double *Xs, double2 *Sd,
-                                double *Ssc) {
+// raw data of one reduction chunk, held in registers while the previous chunk is
+// multiplied: threads < 64 hold entry s0 + tid's pole data and scale; every thread holds
+// NCT * 4 right-hand-side values, element e = tid + 256 i (row e % 64 of the chunk,
+// column e / 64 of the pass)
+template <int NCT>
+struct ApplyStage {
+    double2 sd;
+    double sc;
+    double x[NCT * 4];
+};
+
+template <int TRANS, int NCT>
+__device__ __forceinline__ void apply_fetch(const ApplyArgs &a, int64_t base, int n, int s0,
+                                            int c0, int ncols, ApplyStage<NCT> &st) {
+    const int tid = threadIdx.x;
+    if (tid < AP_K) stage_entry<TRANS>(a, base, n, s0 + tid, st.sd, st.sc);
+#pragma unroll
+    for (int i = 0; i < NCT * 4; ++i) {
+        const int e = tid + 256 * i;
+        const int sl = e % AP_K, c = e / AP_K;
+        const int s = s0 + sl;
+        double v = 0.0;
+        if (s < n && c < ncols) {
+            const double sc = TRANS == 0 ? a.bnorm[base + s] : a.zhat[base + s];
+            v = sc * a.X[base + s + (int64_t)(c0 + c) * a.ldx];
+        }
+        st.x[i] = v;
+    }
+}
+
+template <int NCT>
+__device__ __forceinline__ void apply_store(const ApplyStage<NCT> &st, double *Xs, double2 *Sd) {
+    const int tid = threadIdx.x;
+    if (tid < AP_K) Sd[tid] = st.sd;
+#pragma unroll
+    for (int i = 0; i < NCT * 4; ++i) {
+        const int e = tid + 256 * i;
+        Xs[(e / AP_K) * AP_LD + e % AP_K] = st.x[i];
+    }
+}
+
+// NCT: 16-column blocks per pass (the pass width is 16 NCT columns)
+template <int TRANS, int NCT>
+__device__ void apply_tile_mfma(const ApplyArgs &a, Tile t, double *Xs, double2 *Sd) {
     const int p = t.prob;
     const int64_t base = a.off[p];
     const int n = (int)(a.off[p + 1] - base);
@@ -69,30 +110,21 @@ __device__ void apply_tile_mfma(const ApplyArgs &a, Tile t, double *Xs, double2 
         ra = a.d[base + clamp_idx(a.origin[base + oc], n)];
         rb = a.eta[base + oc];
     }
-    for (int c0 = 0; c0 < a.m; c0 += AP_C) {
-        const int ncols = min(AP_C, a.m - c0);
+    constexpr int PW = 16 * NCT;  // columns per pass
+    for (int c0 = 0; c0 < a.m; c0 += PW) {
+        const int ncols = min(PW, a.m - c0);
         const int nct = (ncols + 15) / 16;
-        v4d acc[4];
+        v4d acc[NCT];
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct) acc[ct] = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int ct = 0; ct < NCT; ++ct) acc[ct] = v4d{0.0, 0.0, 0.0, 0.0};
+        ApplyStage<NCT> st;
+        apply_fetch<TRANS, NCT>(a, base, n, 0, c0, ncols, st);
         for (int s0 = 0; s0 < n; s0 += AP_K) {
+            __syncthreads();  // the previous chunk's reads of Xs/Sd are done
+            apply_store<NCT>(st, Xs, Sd);
             __syncthreads();
-            if (threadIdx.x < AP_K) {
-                double2 sd;
-                double sc;
-                stage_entry<TRANS>(a, base, n, s0 + threadIdx.x, sd, sc);
-                Sd[threadIdx.x] = sd;
-                Ssc[threadIdx.x] = sc;
-            }
-            __syncthreads();
-            for (int e = threadIdx.x; e < AP_K * nct * 16; e += blockDim.x) {
-                const int sl = e % AP_K, c = e / AP_K;
-                const int s = s0 + sl;
-                double v = 0.0;
-                if (s < n && c < ncols) v = Ssc[sl] * a.X[base + s + (int64_t)(c0 + c) * a.ldx];
-                Xs[c * AP_LD + sl] = v;
-            }
-            __syncthreads();
+            // the next chunk's loads are in flight while this one is multiplied
+            if (s0 + AP_K < n) apply_fetch<TRANS, NCT>(a, base, n, s0 + AP_K, c0, ncols, st);
 #pragma unroll 4
             for (int kk = 0; kk < AP_K; kk += 4) {
                 const int sl = kk + (lane >> 4);
@@ -100,7 +132,7 @@ __device__ void apply_tile_mfma(const ApplyArgs &a, Tile t, double *Xs, double2 
                 const double tt = TRANS ? (sd.x - ra) - rb : (ra - sd.x) - sd.y;
                 const double av = (ovalid && s0 + sl < n) ? rcp_nr(tt) : 0.0;
 #pragma unroll
-                for (int ct = 0; ct < 4; ++ct) {
+                for (int ct = 0; ct < NCT; ++ct) {
                     if (ct < nct) {
                         const double bv = Xs[(ct * 16 + (lane & 15)) * AP_LD + sl];
                         acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[ct], 0, 0, 0);
@@ -115,7 +147,7 @@ __device__ void apply_tile_mfma(const ApplyArgs &a, Tile t, double *Xs, double2 
             if (row < n) {
                 const double post = TRANS ? a.bnorm[base + row] : a.zhat[base + row];
 #pragma unroll
-                for (int ct = 0; ct < 4; ++ct) {
+                for (int ct = 0; ct < NCT; ++ct) {
                     const int col = ct * 16 + (lane & 15);
                     if (ct < nct && col < ncols)
                         a.Y[base + row + (int64_t)(c0 + col) * a.ldy] = post * acc[ct][v];
@@ -125,39 +157,43 @@ __device__ void apply_tile_mfma(const ApplyArgs &a, Tile t, double *Xs, double2 
     }
 }
 
-template <int TRANS>
+template <int TRANS, int NCT>
 __global__ __launch_bounds__(256) void k_apply_mfma(ApplyArgs a, Queue *q) {
-    __shared__ double Xs[AP_C * AP_LD];
+    __shared__ double Xs[16 * NCT * AP_LD];
     __shared__ double2 Sd[AP_K];
-    __shared__ double Ssc[AP_K];
     __shared__ int slot;
     if (q) {
         for (;;) {
             const int item = queue_pull(q, a.ntiles, &slot);
             if (item < 0) break;
-            apply_tile_mfma<TRANS>(a, a.tiles[item], Xs, Sd, Ssc);
+            apply_tile_mfma<TRANS, NCT>(a, a.tiles[item], Xs, Sd);
         }
         queue_leave(q);
     } else if ((int)blockIdx.x < a.ntiles) {
-        apply_tile_mfma<TRANS>(a, a.tiles[blockIdx.x], Xs, Sd, Ssc);
+        apply_tile_mfma<TRANS, NCT>(a, a.tiles[blockIdx.x], Xs, Sd);
     }
 }
 
 // ---------------------------------------------------------------------------------------
-// VALU variant: one output row per lane, up to 8 right-hand sides per pass
+// VALU variant: one output row per lane, up to 8 right-hand sides per pass.  AV_W
+// wavefronts share a tile: wavefront w takes the reduction chunks w, w + AV_W, ... (each
+// stages its own chunk), and the partial sums are added in wavefront order at the end.
 // ---------------------------------------------------------------------------------------
 constexpr int AV_C = 8;
+constexpr int AV_W = 4;
 
 template <int TRANS>
-__device__ void apply_tile_valu(const ApplyArgs &a, Tile t, double *Xs, double2 *Sd) {
+__device__ void apply_tile_valu(const ApplyArgs &a, Tile t, double *Xs, double2 *Sd,
+                                double *red) {
     const int p = t.prob;
     const int64_t base = a.off[p];
     const int n = (int)(a.off[p + 1] - base);
     const int lane = lane_id();
+    const int wv = threadIdx.x / WAVE;
     const int o = t.row0 + lane;
     const bool ovalid = o < n;
     if (a.status[p] & ~SUPERDC_ST_NOCONV) {
-        if (ovalid)
+        if (ovalid && wv == 0)
             for (int c = 0; c < a.m; ++c) a.Y[base + o + (int64_t)c * a.ldy] = __builtin_nan("");
         return;
     }
@@ -170,54 +206,75 @@ __device__ void apply_tile_valu(const ApplyArgs &a, Tile t, double *Xs, double2 
         rb = a.eta[base + oc];
     }
     const double post = TRANS ? a.bnorm[base + oc] : a.zhat[base + oc];
+    double *Xw = Xs + wv * WAVE * AV_C;
+    double2 *Sw = Sd + wv * WAVE;
+    const int nchunk = (n + WAVE - 1) / WAVE;
+    const int rounds = (nchunk + AV_W - 1) / AV_W;  // the same count for every wavefront
     for (int c0 = 0; c0 < a.m; c0 += AV_C) {
         const int ncols = min(AV_C, a.m - c0);
         double acc[AV_C];
 #pragma unroll
         for (int c = 0; c < AV_C; ++c) acc[c] = 0.0;
-        for (int s0 = 0; s0 < n; s0 += WAVE) {
+        for (int rd = 0; rd < rounds; ++rd) {
+            const int s0 = (rd * AV_W + wv) * WAVE;
             __syncthreads();
             {
                 double2 sd;
                 double sc;
                 const int s = s0 + lane;
                 stage_entry<TRANS>(a, base, n, s, sd, sc);
-                Sd[lane] = sd;
+                Sw[lane] = sd;
 #pragma unroll
                 for (int c = 0; c < AV_C; ++c)
-                    Xs[lane * AV_C + c] =
+                    Xw[lane * AV_C + c] =
                         (s < n && c < ncols) ? sc * a.X[base + s + (int64_t)(c0 + c) * a.ldx] : 0.0;
             }
             __syncthreads();
-            const int cnt = min(WAVE, n - s0);
+            const int cnt = max(0, min(WAVE, n - s0));
             for (int sl = 0; sl < cnt; ++sl) {
-                const double2 sd = Sd[sl];
+                const double2 sd = Sw[sl];
                 const double tt = TRANS ? (sd.x - ra) - rb : (ra - sd.x) - sd.y;
                 const double r = rcp_nr(tt);
 #pragma unroll
                 for (int c = 0; c < AV_C; ++c)
-                    if (c < ncols) acc[c] = __builtin_fma(r, Xs[sl * AV_C + c], acc[c]);
+                    if (c < ncols) acc[c] = __builtin_fma(r, Xw[sl * AV_C + c], acc[c]);
             }
         }
-        if (ovalid)
-            for (int c = 0; c < ncols; ++c) a.Y[base + o + (int64_t)(c0 + c) * a.ldy] = post * acc[c];
+        // partial sums of wavefronts 1.. through LDS, added in wavefront order by wavefront 0
+        __syncthreads();
+        if (wv > 0)
+#pragma unroll
+            for (int c = 0; c < AV_C; ++c) red[((wv - 1) * AV_C + c) * WAVE + lane] = acc[c];
+        __syncthreads();
+        if (wv == 0) {
+            for (int w = 1; w < AV_W; ++w)
+#pragma unroll
+                for (int c = 0; c < AV_C; ++c) acc[c] += red[((w - 1) * AV_C + c) * WAVE + lane];
+            if (ovalid)
+                for (int c = 0; c < ncols; ++c)
+                    a.Y[base + o + (int64_t)(c0 + c) * a.ldy] = post * acc[c];
+        }
     }
 }
 
 template <int TRANS>
-__global__ __launch_bounds__(64) void k_apply_valu(ApplyArgs a, Queue *q) {
-    __shared__ double Xs[WAVE * AV_C];
-    __shared__ double2 Sd[WAVE];
+__global__ __launch_bounds__(WAVE * AV_W) void k_apply_valu(ApplyArgs a, Queue *q) {
+    // the partial-sum exchange reuses the staging area (it follows a barrier that ends
+    // every read of it)
+    static_assert((AV_W - 1) * AV_C * WAVE <= AV_W * WAVE * AV_C, "reduction area");
+    __shared__ double Xs[AV_W * WAVE * AV_C];
+    __shared__ double2 Sd[AV_W * WAVE];
     __shared__ int slot;
+    double *red = Xs;
     if (q) {
         for (;;) {
             const int item = queue_pull(q, a.ntiles, &slot);
             if (item < 0) break;
-            apply_tile_valu<TRANS>(a, a.tiles[item], Xs, Sd);
+            apply_tile_valu<TRANS>(a, a.tiles[item], Xs, Sd, red);
         }
         queue_leave(q);
     } else if ((int)blockIdx.x < a.ntiles) {
-        apply_tile_valu<TRANS>(a, a.tiles[blockIdx.x], Xs, Sd);
+        apply_tile_valu<TRANS>(a, a.tiles[blockIdx.x], Xs, Sd, red);
     }
 }
 
@@ -225,15 +282,25 @@ hipError_t launch_apply(const ApplyArgs &a, int use_mfma, Queue *q, int grid, hi
     if (a.ntiles <= 0) return hipSuccess;
     const dim3 g(q ? grid : a.ntiles);
     if (use_mfma) {
-        if (a.trans)
-            hipLaunchKernelGGL(k_apply_mfma<1>, g, dim3(256), 0, s, a, q);
-        else
-            hipLaunchKernelGGL(k_apply_mfma<0>, g, dim3(256), 0, s, a, q);
+        // the pass width: 16, 32 or 64 columns, the smallest that covers m (64 beyond)
+        const int nct = a.m <= 16 ? 1 : (a.m <= 32 ? 2 : 4);
+#define SDC_APPLY_MFMA(T, C) \
+    SDC_LAUNCH(KID_APPLY_MFMA, (k_apply_mfma<T, C>), g, dim3(256), 0, s, a, q)
+        if (a.trans) {
+            if (nct == 1) SDC_APPLY_MFMA(1, 1);
+            else if (nct == 2) SDC_APPLY_MFMA(1, 2);
+            else SDC_APPLY_MFMA(1, 4);
+        } else {
+            if (nct == 1) SDC_APPLY_MFMA(0, 1);
+            else if (nct == 2) SDC_APPLY_MFMA(0, 2);
+            else SDC_APPLY_MFMA(0, 4);
+        }
+#undef SDC_APPLY_MFMA
     } else {
         if (a.trans)
-            hipLaunchKernelGGL(k_apply_valu<1>, g, dim3(64), 0, s, a, q);
+            SDC_LAUNCH(KID_APPLY_VALU, k_apply_valu<1>, g, dim3(WAVE * AV_W), 0, s, a, q);
         else
-            hipLaunchKernelGGL(k_apply_valu<0>, g, dim3(64), 0, s, a, q);
+            SDC_LAUNCH(KID_APPLY_VALU, k_apply_valu<0>, g, dim3(WAVE * AV_W), 0, s, a, q);
     }
     return hipGetLastError();
 }

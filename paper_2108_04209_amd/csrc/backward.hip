@@ -194,13 +194,13 @@ hipError_t launch_backward(const BwdArgs &a, int split, int prob_first, int npro
     const dim3 g1(q1 ? grid : a.ntiles), g2(q2 ? grid : a.ntiles), blk(WAVE * split);
     const size_t lds = split > 1 ? 2 * sizeof(double4) * WAVE * split : 0;
     if (proj) {
-        hipLaunchKernelGGL((k_bwd<true, 1>), g1, blk, lds, s, a, q1);
-        hipLaunchKernelGGL((k_bwd<true, 2>), g2, blk, lds, s, a, q2);
+        SDC_LAUNCH(KID_BWD, (k_bwd<true, 1>), g1, blk, lds, s, a, q1);
+        SDC_LAUNCH(KID_BWD, (k_bwd<true, 2>), g2, blk, lds, s, a, q2);
     } else {
-        hipLaunchKernelGGL((k_bwd<false, 1>), g1, blk, lds, s, a, q1);
-        hipLaunchKernelGGL((k_bwd<false, 2>), g2, blk, lds, s, a, q2);
+        SDC_LAUNCH(KID_BWD, (k_bwd<false, 1>), g1, blk, lds, s, a, q1);
+        SDC_LAUNCH(KID_BWD, (k_bwd<false, 2>), g2, blk, lds, s, a, q2);
     }
-    hipLaunchKernelGGL(k_bwd_rho, dim3(nprob), dim3(256), 0, s, a, prob_first);
+    SDC_LAUNCH(KID_BWD_RHO, k_bwd_rho, dim3(nprob), dim3(256), 0, s, a, prob_first);
     return hipGetLastError();
 }
 

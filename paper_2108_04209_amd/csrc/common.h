@@ -112,6 +112,34 @@ __device__ __forceinline__ void queue_leave(Queue *q) {
     }
 }
 
+// ----------------------------------------------------------------------------------
+// optional per-kernel timing (trace.cpp): a scope records HIP events around one launch
+// ----------------------------------------------------------------------------------
+enum KernelId : int {
+    KID_VALIDATE = 0, KID_FMM_BOXES, KID_FMM_LISTS, KID_SECULAR, KID_SECULAR_FMM, KID_PACK,
+    KID_LOEWNER, KID_BNORM, KID_APPLY_MFMA, KID_APPLY_VALU, KID_BWD, KID_BWD_RHO, KID_LEAF,
+    KID_MERGE, KID_ASSEMBLE, KID_PERMUTE, KID_LEAF_APPLY, KID_STATUS_OR, KID_FILL,
+    KID_LEAF_VECTORS, KID_COUNT
+};
+
+class TraceScope {
+  public:
+    TraceScope(int kid, hipStream_t s);
+    ~TraceScope();
+
+  private:
+    int kid_;
+    hipStream_t s_;
+    hipEvent_t e0_ = nullptr, e1_ = nullptr;
+};
+
+// a kernel launch bracketed by the trace scope of kernel id KID
+#define SDC_LAUNCH(KID, KERNEL, GRID, BLOCK, LDS, STREAM, ...)                     \
+    do {                                                                          \
+        ::sdc::TraceScope trace_scope_(KID, STREAM);                              \
+        hipLaunchKernelGGL(KERNEL, GRID, BLOCK, LDS, STREAM, __VA_ARGS__);        \
+    } while (0)
+
 }  // namespace sdc
 
 // ----------------------------------------------------------------------------------

@@ -48,16 +48,20 @@ struct FmmPlan {
     double2 *eq = nullptr, *box_ab = nullptr;
     int32_t *near_lo = nullptr, *near_hi = nullptr, *far_l = nullptr, *far_r = nullptr;
     int32_t *cnt = nullptr;
-    Tile *leaf_lpt = nullptr;          // leaf work items, longest problems first
-    std::vector<int32_t> leaf_begin;   // FMM problem q owns leaf_lpt-independent items
-    Tile *leaf_nat = nullptr;          // ... in problem order: [leaf_off[q], leaf_off[q+1])
+    // work items: 64-root pieces of the target leaves (a piece never crosses a leaf)
+    int sub = TILE;                    // roots per work item
+    int nitems = 0;
+    int split = 1;                     // wavefronts per work item (they share its lists)
+    std::vector<int32_t> item_off_h;   // FMM problem q owns items [item_off[q], item_off[q+1])
+    Tile *leaf_lpt = nullptr;          // work items, longest problems first
+    Tile *leaf_nat = nullptr;          // ... in problem order
     std::vector<Tile *> dir_lpt;       // direct chunks of the other problems, per cut length
     std::vector<int32_t> dir_count;
     std::vector<void *> allocs;
 };
 
 hipError_t launch_fmm_build(const FmmArgs &f, hipStream_t s);
-hipError_t launch_secular_fmm(const SolveArgs &a, const FmmArgs &f, Queue *q, int grid,
-                              hipStream_t s);
+hipError_t launch_secular_fmm(const SolveArgs &a, const FmmArgs &f, int split, Queue *q,
+                              int grid, hipStream_t s);
 
 }  // namespace sdc

@@ -156,8 +156,8 @@ __global__ __launch_bounds__(64) void k_fmm_lists(FmmArgs f) {
 
 hipError_t launch_fmm_build(const FmmArgs &f, hipStream_t s) {
     if (f.nboxes <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fmm_boxes, dim3(f.nboxes), dim3(256), 0, s, f);
-    hipLaunchKernelGGL(k_fmm_lists, dim3((f.nleaves + 63) / 64), dim3(64), 0, s, f);
+    SDC_LAUNCH(KID_FMM_BOXES, k_fmm_boxes, dim3(f.nboxes), dim3(256), 0, s, f);
+    SDC_LAUNCH(KID_FMM_LISTS, k_fmm_lists, dim3((f.nleaves + 63) / 64), dim3(64), 0, s, f);
     return hipGetLastError();
 }
 

@@ -7,6 +7,7 @@ namespace sdc {
 
 constexpr int LEAF_MAX = 128;      // largest leaf block (its matrix lives in LDS)
 constexpr int LEAF_RANK_MAX = 8;   // largest off-diagonal rank r
+constexpr int LEAF_SWEEPS = 16;    // Jacobi sweeps per leaf (the rotation log's capacity)
 
 struct LeafArgs {
     int leaf, r, nleaf, max_sweeps;
@@ -16,6 +17,10 @@ struct LeafArgs {
     double *lam;      // nleaf * leaf eigenvalues, ascending per leaf
     double *W;        // Q^T U, column-major with leading dimension ldw
     int64_t ldw;
+    double *rot;      // nleaf x max_sweeps x (leaf-1) x leaf/2 rotation tangents (0: none)
+    int32_t *rank;    // nleaf x leaf ascending rank of each diagonal entry
+    int32_t *sweeps;  // nleaf sweeps logged
+    int32_t *status;  // nleaf: 0, or SUPERDC_ST_NOCONV if max_sweeps did not converge
 };
 
 struct AssembleArgs {

@@ -14,35 +14,59 @@
 namespace sdc {
 
 // ---------------------------------------------------------------------------------------
-// leaf eigendecomposition: cyclic Jacobi, one workgroup per leaf, matrix in LDS
+// leaf eigendecomposition: cyclic Jacobi in two kernels.  The matrix (128 x 129 doubles)
+// fills most of a CU's LDS, so the eigenvector accumulation cannot sit beside it:
+//   k_leaf_jacobi  rotates A in LDS and logs every round's rotation tangents t to HBM;
+//   k_leaf_vectors replays the log on V = I held in LDS, then writes the sorted
+//                  eigenvectors and W = Q^T U.
+// Both use the round-robin (circle) pair ordering, so a round's pairs are disjoint.
 // ---------------------------------------------------------------------------------------
 constexpr int LJ_LD = LEAF_MAX + 1;
+constexpr int LJ_THREADS = 1024;
+constexpr int LV_RB = 8;  // rounds of rotations staged in LDS per block of the replay
 
 // Round-robin (circle) ordering: in round `rd` every index takes part in exactly one of
 // m/2 disjoint pairs, and over m-1 rounds every pair meets once.
 __device__ __forceinline__ int rr_player(int pos, int rd, int m) {
-    return pos == 0 ? 0 : 1 + (pos - 1 + rd) % (m - 1);
+    if (pos == 0) return 0;
+    int v = pos - 1 + rd;  // < 2 (m - 1)
+    if (v >= m - 1) v -= m - 1;
+    return 1 + v;
 }
 
-__global__ __launch_bounds__(256) void k_leaf_jacobi(LeafArgs a) {
+__device__ __forceinline__ void rr_pair(int pr, int rd, int m, int &p, int &q) {
+    p = rr_player(pr, rd, m);
+    q = rr_player(m - 1 - pr, rd, m);
+    if (p > q) {
+        const int t = p;
+        p = q;
+        q = t;
+    }
+}
+
+// cos and sin of the rotation with tangent t (the same operations in both kernels)
+__device__ __forceinline__ double2 rot_cs(double t) {
+    const double c = 1.0 / sqrt(t * t + 1.0);
+    return make_double2(c, t * c);
+}
+
+// One round applies A <- J^T A J for the m/2 disjoint rotations of the round at once:
+// every 2 x 2 block (rows of pair P1, columns of pair P2) depends only on its own four
+// entries, so the round is a single pass over the matrix.  Diagonal blocks use the
+// updates app - t apq, aqq + t apq and set apq = 0.
+__global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
     __shared__ double A[LEAF_MAX * LJ_LD];
-    __shared__ double cs[2 * (LEAF_MAX / 2)];
-    __shared__ int pq[2 * (LEAF_MAX / 2)];
-    __shared__ double red[8];
+    __shared__ double2 cs[LEAF_MAX / 2];
+    __shared__ double tt[LEAF_MAX / 2];
+    __shared__ int2 pq[LEAF_MAX / 2];
+    __shared__ double red[LJ_THREADS / WAVE];
     __shared__ int nrot;
-    __shared__ int rank[LEAF_MAX];
-    __shared__ double ev[LEAF_MAX];
 
     const int leafid = blockIdx.x;
     const int L = a.leaf;
     const int tid = threadIdx.x, nt = blockDim.x;
     const double *D = a.D + (size_t)leafid * L * L;
-    double *V = a.Q + (size_t)leafid * L * L;  // column j (an eigenvector) contiguous
-    for (int e = tid; e < L * L; e += nt) {
-        const int i = e / L, j = e % L;
-        A[i * LJ_LD + j] = D[e];
-        V[j * L + i] = (i == j) ? 1.0 : 0.0;
-    }
+    for (int e = tid; e < L * L; e += nt) A[(e / L) * LJ_LD + e % L] = D[e];
     __syncthreads();
     // Frobenius norm for the absolute part of the rotation threshold
     double fro = 0.0;
@@ -53,101 +77,155 @@ __global__ __launch_bounds__(256) void k_leaf_jacobi(LeafArgs a) {
     for (int o = WAVE / 2; o > 0; o >>= 1) fro += __shfl_xor(fro, o);
     if (lane_id() == 0) red[tid / WAVE] = fro;
     __syncthreads();
-    if (tid == 0) {
-        double t = 0.0;
-        for (int w = 0; w < nt / WAVE; ++w) t += red[w];
-        red[4] = sqrt(t);
-    }
-    __syncthreads();
-    const double absfloor = 1e-18 * red[4];
+    double tot = 0.0;
+    for (int w = 0; w < nt / WAVE; ++w) tot += red[w];
+    const double absfloor = 1e-18 * sqrt(tot);
     const int m = L;  // even
     const int half = m / 2;
-    for (int sweep = 0; sweep < a.max_sweeps; ++sweep) {
+    double *log = a.rot + (size_t)leafid * a.max_sweeps * (m - 1) * half;
+    int sweep = 0;
+    bool converged = false;
+    for (; sweep < a.max_sweeps; ++sweep) {
         if (tid == 0) nrot = 0;
         __syncthreads();
         for (int rd = 0; rd < m - 1; ++rd) {
             if (tid < half) {
-                int p = rr_player(tid, rd, m), q = rr_player(m - 1 - tid, rd, m);
-                if (p > q) {
-                    const int t = p;
-                    p = q;
-                    q = t;
-                }
+                int p, q;
+                rr_pair(tid, rd, m, p, q);
                 const double apq = A[p * LJ_LD + q];
                 const double app = A[p * LJ_LD + p], aqq = A[q * LJ_LD + q];
-                double c = 1.0, s = 0.0;
+                double t = 0.0;
                 if (fabs(apq) > 2.220446049250313e-16 * sqrt(fabs(app) * fabs(aqq)) + absfloor) {
                     const double theta = (aqq - app) / (2.0 * apq);
-                    double t;
                     if (fabs(theta) > 1e150) t = 0.5 / theta;
                     else t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-                    c = 1.0 / sqrt(t * t + 1.0);
-                    s = t * c;
                     atomicAdd(&nrot, 1);
                 }
-                cs[2 * tid] = c;
-                cs[2 * tid + 1] = s;
-                pq[2 * tid] = p;
-                pq[2 * tid + 1] = q;
+                cs[tid] = t != 0.0 ? rot_cs(t) : make_double2(1.0, 0.0);
+                tt[tid] = t;
+                pq[tid] = make_int2(p, q);
+                log[((size_t)sweep * (m - 1) + rd) * half + tid] = t;
             }
             __syncthreads();
-            // rows: A <- J^T A
-            for (int e = tid; e < half * L; e += nt) {
-                const int pr = e / L, j = e % L;
-                const double c = cs[2 * pr], s = cs[2 * pr + 1];
-                if (s == 0.0) continue;
-                const int p = pq[2 * pr], q = pq[2 * pr + 1];
-                const double ap = A[p * LJ_LD + j], aq = A[q * LJ_LD + j];
-                A[p * LJ_LD + j] = c * ap - s * aq;
-                A[q * LJ_LD + j] = s * ap + c * aq;
-            }
-            __syncthreads();
-            // columns: A <- A J, and V <- V J
-            for (int e = tid; e < half * L; e += nt) {
-                const int pr = e / L, i = e % L;
-                const double c = cs[2 * pr], s = cs[2 * pr + 1];
-                if (s == 0.0) continue;
-                const int p = pq[2 * pr], q = pq[2 * pr + 1];
-                const double ap = A[i * LJ_LD + p], aq = A[i * LJ_LD + q];
-                A[i * LJ_LD + p] = c * ap - s * aq;
-                A[i * LJ_LD + q] = s * ap + c * aq;
-                const double vp = V[p * L + i], vq = V[q * L + i];
-                V[p * L + i] = c * vp - s * vq;
-                V[q * L + i] = s * vp + c * vq;
+            for (int blk = tid; blk < half * half; blk += nt) {
+                const int P1 = blk / half, P2 = blk % half;
+                const double2 r1 = cs[P1], r2 = cs[P2];
+                if (r1.y == 0.0 && r2.y == 0.0) continue;
+                const int2 ab = pq[P1], cd = pq[P2];
+                if (P1 == P2) {
+                    const double t = tt[P1];
+                    const double apq = A[ab.x * LJ_LD + ab.y];
+                    A[ab.x * LJ_LD + ab.x] -= t * apq;
+                    A[ab.y * LJ_LD + ab.y] += t * apq;
+                    A[ab.x * LJ_LD + ab.y] = 0.0;
+                    A[ab.y * LJ_LD + ab.x] = 0.0;
+                    continue;
+                }
+                const double xac = A[ab.x * LJ_LD + cd.x], xad = A[ab.x * LJ_LD + cd.y];
+                const double xbc = A[ab.y * LJ_LD + cd.x], xbd = A[ab.y * LJ_LD + cd.y];
+                // rows: J1^T X
+                const double yac = r1.x * xac - r1.y * xbc, ybc = r1.y * xac + r1.x * xbc;
+                const double yad = r1.x * xad - r1.y * xbd, ybd = r1.y * xad + r1.x * xbd;
+                // columns: (J1^T X) J2
+                A[ab.x * LJ_LD + cd.x] = r2.x * yac - r2.y * yad;
+                A[ab.x * LJ_LD + cd.y] = r2.y * yac + r2.x * yad;
+                A[ab.y * LJ_LD + cd.x] = r2.x * ybc - r2.y * ybd;
+                A[ab.y * LJ_LD + cd.y] = r2.y * ybc + r2.x * ybd;
             }
             __syncthreads();
         }
-        if (nrot == 0) break;
+        const int nr = nrot;
         __syncthreads();
+        if (nr == 0) {  // a sweep without rotations: nothing of it needs replaying
+            converged = true;
+            break;
+        }
     }
     // ascending order of the eigenvalues (ties broken by index)
-    if (tid < L) ev[tid] = A[tid * LJ_LD + tid];
-    __syncthreads();
     if (tid < L) {
-        const double v = ev[tid];
+        const double v = A[tid * LJ_LD + tid];
         int r = 0;
-        for (int j = 0; j < L; ++j) r += (ev[j] < v) || (ev[j] == v && j < tid);
-        rank[tid] = r;
+        for (int j = 0; j < L; ++j) {
+            const double w = A[j * LJ_LD + j];
+            r += (w < v) || (w == v && j < tid);
+        }
+        a.rank[(size_t)leafid * L + tid] = r;
         a.lam[(size_t)leafid * L + r] = v;
     }
-    __syncthreads();
-    // sorted eigenvectors through LDS (the matrix is no longer needed)
+    if (tid == 0) {
+        a.sweeps[leafid] = sweep;
+        a.status[leafid] = converged ? 0 : SUPERDC_ST_NOCONV;
+    }
+}
+
+__global__ __launch_bounds__(LJ_THREADS) void k_leaf_vectors(LeafArgs a) {
+    __shared__ double V[LEAF_MAX * LJ_LD];
+    __shared__ double2 cs[2][LV_RB][LEAF_MAX / 2];
+    __shared__ int2 pq[2][LV_RB][LEAF_MAX / 2];
+
+    const int leafid = blockIdx.x;
+    const int L = a.leaf;
+    const int m = L, half = m / 2;
+    const int tid = threadIdx.x, nt = blockDim.x;
     for (int e = tid; e < L * L; e += nt) {
-        const int j = e / L, i = e % L;
-        A[rank[j] * LJ_LD + i] = V[j * L + i];
+        const int i = e / L, j = e % L;
+        V[i * LJ_LD + j] = (i == j) ? 1.0 : 0.0;
+    }
+    const double *log = a.rot + (size_t)leafid * a.max_sweeps * (m - 1) * half;
+    const int rounds = a.sweeps[leafid] * (m - 1);
+    const int per_block = LV_RB * half;  // tangents per staged block
+    const int nblk = (rounds + LV_RB - 1) / LV_RB;
+    // block b holds rounds [b RB, (b+1) RB); thread tid stages entry tid of a block
+    double tnext = 0.0;
+    if (tid < per_block && tid < rounds * half) tnext = log[tid];
+    for (int b = 0; b < nblk; ++b) {
+        if (tid < per_block) {
+            const int g = b * per_block + tid;
+            const int rr = tid / half, pr = tid % half;
+            cs[b & 1][rr][pr] =
+                (g < rounds * half && tnext != 0.0) ? rot_cs(tnext) : make_double2(1.0, 0.0);
+            int p, q;
+            rr_pair(pr, (b * LV_RB + rr) % (m - 1), m, p, q);
+            pq[b & 1][rr][pr] = make_int2(p, q);
+        }
+        __syncthreads();
+        // the next block's tangents are in flight while this block is replayed
+        if (tid < per_block) {
+            const int g = (b + 1) * per_block + tid;
+            tnext = g < rounds * half ? log[g] : 0.0;
+        }
+        for (int rr = 0; rr < LV_RB; ++rr) {
+            const int g = b * LV_RB + rr;
+            if (g >= rounds) break;
+            // columns: V <- V J
+            for (int e = tid; e < half * L; e += nt) {
+                const int pr = e / L, i = e % L;
+                const double2 r = cs[b & 1][rr][pr];
+                if (r.y == 0.0) continue;
+                const int2 c = pq[b & 1][rr][pr];
+                const double vp = V[i * LJ_LD + c.x], vq = V[i * LJ_LD + c.y];
+                V[i * LJ_LD + c.x] = r.x * vp - r.y * vq;
+                V[i * LJ_LD + c.y] = r.y * vp + r.x * vq;
+            }
+            __syncthreads();
+        }
     }
     __syncthreads();
+    // sorted eigenvectors: column j of V is the eigenvector of diagonal entry j, whose
+    // ascending rank the Jacobi kernel stored
+    const int32_t *rank = a.rank + (size_t)leafid * L;
+    double *Q = a.Q + (size_t)leafid * L * L;  // eigenvector k contiguous
     for (int e = tid; e < L * L; e += nt) {
         const int j = e / L, i = e % L;
-        V[j * L + i] = A[j * LJ_LD + i];
+        Q[(size_t)rank[j] * L + i] = V[i * LJ_LD + j];
     }
     // W = Q^T U (L x r), column-major with leading dimension ldw over the whole level
     const double *U = a.U + (size_t)leafid * L * a.r;
     for (int e = tid; e < L * a.r; e += nt) {
         const int j = e % L, c = e / L;
         double acc = 0.0;
-        for (int i = 0; i < L; ++i) acc = __builtin_fma(A[j * LJ_LD + i], U[i * a.r + c], acc);
-        a.W[(int64_t)c * a.ldw + (int64_t)leafid * L + j] = acc;
+        for (int i = 0; i < L; ++i) acc = __builtin_fma(V[i * LJ_LD + j], U[i * a.r + c], acc);
+        a.W[(int64_t)c * a.ldw + (int64_t)leafid * L + rank[j]] = acc;
     }
 }
 
@@ -296,42 +374,43 @@ __global__ void k_fill(double *x, int64_t n, double v) {
 static inline dim3 grid_for(int64_t n, int b = 256) { return dim3((unsigned)((n + b - 1) / b)); }
 
 hipError_t launch_leaf_jacobi(const LeafArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_leaf_jacobi, dim3(a.nleaf), dim3(256), 0, s, a);
+    SDC_LAUNCH(KID_LEAF, k_leaf_jacobi, dim3(a.nleaf), dim3(LJ_THREADS), 0, s, a);
+    SDC_LAUNCH(KID_LEAF_VECTORS, k_leaf_vectors, dim3(a.nleaf), dim3(LJ_THREADS), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_merge(const double *lam_children, double *d_out, int32_t *perm, int nc,
                         int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_merge, grid_for(n), dim3(256), 0, s, lam_children, d_out, perm, nc, n);
+    SDC_LAUNCH(KID_MERGE, k_merge, grid_for(n), dim3(256), 0, s, lam_children, d_out, perm, nc, n);
     return hipGetLastError();
 }
 
 hipError_t launch_assemble(const AssembleArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_assemble, grid_for(a.n), dim3(256), 0, s, a);
+    SDC_LAUNCH(KID_ASSEMBLE, k_assemble, grid_for(a.n), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_permute(const int32_t *perm, int nl, int64_t n, int m, const double *X,
                           int64_t ldx, double *Y, int64_t ldy, int scatter, hipStream_t s) {
-    hipLaunchKernelGGL(k_permute, grid_for(n), dim3(256), 0, s, perm, nl, n, m, X, ldx, Y, ldy,
+    SDC_LAUNCH(KID_PERMUTE, k_permute, grid_for(n), dim3(256), 0, s, perm, nl, n, m, X, ldx, Y, ldy,
                        scatter);
     return hipGetLastError();
 }
 
 hipError_t launch_leaf_apply(const double *Q, int L, int64_t n, int m, const double *X,
                              int64_t ldx, double *Y, int64_t ldy, int trans, hipStream_t s) {
-    hipLaunchKernelGGL(k_leaf_apply, grid_for(n * m), dim3(256), 0, s, Q, L, n, m, X, ldx, Y, ldy,
+    SDC_LAUNCH(KID_LEAF_APPLY, k_leaf_apply, grid_for(n * m), dim3(256), 0, s, Q, L, n, m, X, ldx, Y, ldy,
                        trans);
     return hipGetLastError();
 }
 
 hipError_t launch_status_or(const int32_t *st, int cnt, int32_t *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_status_or, dim3(1), dim3(256), 0, s, st, cnt, out);
+    SDC_LAUNCH(KID_STATUS_OR, k_status_or, dim3(1), dim3(256), 0, s, st, cnt, out);
     return hipGetLastError();
 }
 
 hipError_t launch_fill(double *x, int64_t n, double v, hipStream_t s) {
-    hipLaunchKernelGGL(k_fill, grid_for(n), dim3(256), 0, s, x, n, v);
+    SDC_LAUNCH(KID_FILL, k_fill, grid_for(n), dim3(256), 0, s, x, n, v);
     return hipGetLastError();
 }
 

@@ -23,6 +23,9 @@ struct superdc_hss {
     double *leafQ = nullptr;   // 2^depth x leaf x leaf
     double *leaf_lam = nullptr;
     double *Wleaf = nullptr;   // n x r
+    double *leaf_rot = nullptr;     // Jacobi rotation log: 2^depth x LEAF_SWEEPS x (leaf-1) x leaf/2
+    int32_t *leaf_rank = nullptr;   // 2^depth x leaf
+    int32_t *leaf_sweeps = nullptr; // 2^depth
     double *M[2] = {nullptr, nullptr};  // n x 2r update / basis columns (ping-pong)
     double *ones = nullptr;    // rho = 1 for every node
     int32_t *iters = nullptr;
@@ -120,6 +123,10 @@ int superdc_hss_plan_create(superdc_ctx *ctx, int32_t leaf, int32_t depth, int32
     hipError_t e = alloc(h, &h->leafQ, nleaf * leaf * leaf);
     if (e == hipSuccess) e = alloc(h, &h->leaf_lam, n);
     if (e == hipSuccess) e = alloc(h, &h->Wleaf, n * r);
+    if (e == hipSuccess)
+        e = alloc(h, &h->leaf_rot, nleaf * LEAF_SWEEPS * (leaf - 1) * (leaf / 2));
+    if (e == hipSuccess) e = alloc(h, &h->leaf_rank, n);
+    if (e == hipSuccess) e = alloc(h, &h->leaf_sweeps, nleaf);
     if (e == hipSuccess) e = alloc(h, &h->M[0], n * 2 * r);
     if (e == hipSuccess) e = alloc(h, &h->M[1], n * 2 * r);
     if (e == hipSuccess) e = alloc(h, &h->ones, n);
@@ -131,11 +138,14 @@ int superdc_hss_plan_create(superdc_ctx *ctx, int32_t leaf, int32_t depth, int32
     if (e == hipSuccess) e = alloc(h, &h->bn, (size_t)depth * r * n);
     if (e == hipSuccess) e = alloc(h, &h->org, (size_t)depth * r * n);
     if (e == hipSuccess) e = alloc(h, &h->perm, (size_t)depth * n);
-    if (e == hipSuccess) e = alloc(h, &h->status, (size_t)depth * r * ((size_t)1 << (depth - 1)));
+    // per-node status bits of every rank-one step, then one word per leaf
+    if (e == hipSuccess)
+        e = alloc(h, &h->status, (size_t)depth * r * ((size_t)1 << (depth - 1)) + nleaf);
     if (e == hipSuccess) e = launch_fill(h->ones, n, 1.0, nullptr);
     // level l uses 2^l of the 2^(depth-1) status slots of each step; the rest stay 0
     if (e == hipSuccess)
-        e = hipMemset(h->status, 0, sizeof(int32_t) * (size_t)depth * r * ((size_t)1 << (depth - 1)));
+        e = hipMemset(h->status, 0,
+                      sizeof(int32_t) * ((size_t)depth * r * ((size_t)1 << (depth - 1)) + nleaf));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         superdc_hss_plan_destroy(h);
@@ -168,13 +178,17 @@ int superdc_hss_conquer(superdc_ctx *ctx, superdc_hss *h, const double *leaf_D,
     la.leaf = h->leaf;
     la.r = r;
     la.nleaf = 1 << D;
-    la.max_sweeps = 30;
+    la.max_sweeps = LEAF_SWEEPS;
     la.D = leaf_D;
     la.U = leaf_U;
     la.Q = h->leafQ;
     la.lam = h->leaf_lam;
     la.W = h->Wleaf;
     la.ldw = n;
+    la.rot = h->leaf_rot;
+    la.rank = h->leaf_rank;
+    la.sweeps = h->leaf_sweeps;
+    la.status = h->status + (size_t)D * r * ((size_t)1 << (D - 1));  // after the nodes' bits
     if ((e = launch_leaf_jacobi(la, s)) != hipSuccess) return fail(e);
     if ((e = mark(h, 0, s)) != hipSuccess) return fail(e);
 
@@ -246,7 +260,8 @@ int superdc_hss_conquer(superdc_ctx *ctx, superdc_hss *h, const double *leaf_D,
                            hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return fail(e);
     }
-    if ((e = launch_status_or(h->status, D * r * (1 << (D - 1)), status_out, s)) != hipSuccess)
+    if ((e = launch_status_or(h->status, D * r * (1 << (D - 1)) + (1 << D), status_out, s)) !=
+        hipSuccess)
         return fail(e);
     if ((e = mark(h, 5, s)) != hipSuccess) return fail(e);
     h->ready = true;

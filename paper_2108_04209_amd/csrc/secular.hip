@@ -79,6 +79,15 @@ __global__ __launch_bounds__(256) void k_validate(SolveArgs a, int prob_first) {
 // x = d_K + y, which is accurate there (eq. farfield), and a reciprocal with one Newton
 // step (<= 11 ulp, measured); near pairs keep the shifted form (d_j - d_K) - y (eq.
 // localshift) and a reciprocal refined twice.
+//
+// Far pairs are taken two poles at a time with one shared reciprocal (the FP64
+// reciprocal issues at a quarter of the FMA rate on gfx950):
+//   w0/t0 + w1/t1       = (w0 t1 + w1 t0) / (t0 t1)
+//   w0/t0^2 + w1/t1^2   = (w0 t1 t1 + w1 t0 t0) / (t0 t1)^2
+// t0 and t1 have the same sign (both poles lie on one side of every root of the range),
+// so neither numerator cancels.  The products need every |t| of the range inside
+// [2^-300, 2^300]; a range outside that (checked once per range for the whole wavefront)
+// takes one reciprocal per pole.
 template <int MODE, bool FAR>
 __device__ __forceinline__ void secular_range(const_double2_ptr dw, int j0, int j1,
                                               int k, double dK, double y, double x,
@@ -104,8 +113,47 @@ __device__ __forceinline__ void secular_range(const_double2_ptr dw, int j0, int 
             dphi = __builtin_fma(wg, r, dphi);                        \
         }                                                             \
     }
-    // blocks of 4 poles, the next block's scalar fetch issued before this block's math
+// two far poles, one reciprocal (MODE 0 or 1 only)
+#define SDC_SEC_PAIR(PA, PB)                                          \
+    {                                                                 \
+        const double2 pa = (PA), pb = (PB);                           \
+        const double t0 = pa.x - x, t1 = pb.x - x;                    \
+        const double R = rcp_nr1(t0 * t1);                            \
+        const double u0 = pa.y * t1, u1 = pb.y * t0;                  \
+        const double num2 = __builtin_fma(u0, t1, u1 * t0);           \
+        if (MODE == 0) {                                              \
+            psi = __builtin_fma(u0 + u1, R, psi);                     \
+            dpsi = __builtin_fma(num2, R * R, dpsi);                  \
+        } else {                                                      \
+            phi = __builtin_fma(u0 + u1, R, phi);                     \
+            dphi = __builtin_fma(num2, R * R, dphi);                  \
+        }                                                             \
+    }
     int j = j0;
+    if (FAR && MODE != 2 && j + 4 <= j1) {
+        // the nearest and farthest pole of the range bound every |t|
+        const double tn = fabs((MODE == 0 ? dw[j1 - 1].x : dw[j0].x) - x);
+        const double tf = fabs((MODE == 0 ? dw[j0].x : dw[j1 - 1].x) - x);
+        const bool ok = tn >= 0x1p-300 && tf <= 0x1p300;
+        if (__ballot(!ok) == 0ull) {
+            double2 c0 = dw[j], c1 = dw[j + 1], c2 = dw[j + 2], c3 = dw[j + 3];
+            for (; j + 8 <= j1; j += 4) {
+                const double2 n0 = dw[j + 4], n1 = dw[j + 5], n2 = dw[j + 6], n3 = dw[j + 7];
+                SDC_SEC_PAIR(c0, c1)
+                SDC_SEC_PAIR(c2, c3)
+                c0 = n0;
+                c1 = n1;
+                c2 = n2;
+                c3 = n3;
+            }
+            SDC_SEC_PAIR(c0, c1)
+            SDC_SEC_PAIR(c2, c3)
+            j += 4;
+            for (; j < j1; ++j) SDC_SEC_BODY(j, dw[j])
+            return;
+        }
+    }
+    // blocks of 4 poles, the next block's scalar fetch issued before this block's math
     if (j + 4 <= j1) {
         double2 c0 = dw[j], c1 = dw[j + 1], c2 = dw[j + 2], c3 = dw[j + 3];
         for (; j + 8 <= j1; j += 4) {
@@ -126,6 +174,7 @@ __device__ __forceinline__ void secular_range(const_double2_ptr dw, int j0, int 
         j += 4;
     }
     for (; j < j1; ++j) SDC_SEC_BODY(j, dw[j])
+#undef SDC_SEC_PAIR
 #undef SDC_SEC_BODY
 }
 
@@ -184,30 +233,35 @@ __device__ __forceinline__ void split_reduce4(double *red, int S, double &a, dou
 
 // The same sums from the triangular FMM lists of target leaf L: near leaves directly in
 // shifted form (routed by the window as above), far boxes through their equivalent
-// sources in lambda-form, left boxes into psi and right boxes into phi.
+// sources in lambda-form, left boxes into psi and right boxes into phi.  With S wavefronts
+// per work item, wavefront wv takes the wv-th of S contiguous parts of every near range
+// and the far boxes e = wv (mod S).
 __device__ __forceinline__ void fmm_sums(const FmmArgs &f, int L, int nn, int nl, int nr,
                                          const double2 *__restrict__ dwg, int kmin, int kmax,
-                                         int k, double dK, double y, double &psi, double &dpsi,
-                                         double &phi, double &dphi) {
+                                         int k, double dK, double y, int wv, int S, double &psi,
+                                         double &dpsi, double &phi, double &dphi) {
     const_double2_ptr dw = as_const(dwg);
     kmin = wave_uniform(kmin);
     kmax = wave_uniform(kmax);
+    wv = wave_uniform(wv);
     psi = dpsi = phi = dphi = 0.0;
     const double x = dK + y;
     for (int e = 0; e < nn; ++e) {
-        const int lo = wave_uniform(f.near_lo[(int64_t)L * FMM_NEAR_MAX + e]);
-        const int hi = wave_uniform(f.near_hi[(int64_t)L * FMM_NEAR_MAX + e]);
+        const int lo0 = wave_uniform(f.near_lo[(int64_t)L * FMM_NEAR_MAX + e]);
+        const int hi0 = wave_uniform(f.near_hi[(int64_t)L * FMM_NEAR_MAX + e]);
+        const int lo = lo0 + (int)(((int64_t)(hi0 - lo0) * wv) / S);
+        const int hi = lo0 + (int)(((int64_t)(hi0 - lo0) * (wv + 1)) / S);
         secular_range<0, false>(dw, lo, min(hi, kmin), k, dK, y, x, psi, dpsi, phi, dphi);
         secular_range<2, false>(dw, max(lo, kmin), min(hi, kmax + 1), k, dK, y, x, psi, dpsi, phi,
                                 dphi);
         secular_range<1, false>(dw, max(lo, kmax + 1), hi, k, dK, y, x, psi, dpsi, phi, dphi);
     }
-    for (int e = 0; e < nl; ++e) {
+    for (int e = wv; e < nl; e += S) {
         const int g = wave_uniform(f.far_l[(int64_t)L * FMM_FAR_MAX + e]);
         secular_range<0, true>(as_const(f.eq + (int64_t)g * FMM_P), 0, FMM_P, k, dK, y, x, psi,
                                dpsi, phi, dphi);
     }
-    for (int e = 0; e < nr; ++e) {
+    for (int e = wv; e < nr; e += S) {
         const int g = wave_uniform(f.far_r[(int64_t)L * FMM_FAR_MAX + e]);
         secular_range<1, true>(as_const(f.eq + (int64_t)g * FMM_P), 0, FMM_P, k, dK, y, x, psi,
                                dpsi, phi, dphi);
@@ -297,7 +351,7 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
 
         double psi, dpsi, phi, dphi;
         if (FMM && nn >= 0)
-            fmm_sums(*fm, L, nn, nl, nr, dw, kmin, kmax, k, dK, y, psi, dpsi, phi, dphi);
+            fmm_sums(*fm, L, nn, nl, nr, dw, kmin, kmax, k, dK, y, wv, S, psi, dpsi, phi, dphi);
         else
             secular_sums(dw, n, p0, p1, kmin, kmax, k, dK, y, psi, dpsi, phi, dphi);
         split_reduce4(red, S, psi, dpsi, phi, dphi);
@@ -394,37 +448,41 @@ __global__ __launch_bounds__(1024) void k_secular(SolveArgs a, Queue *q) {
     }
 }
 
-// FMM problems: one work item per target leaf, one wavefront per item
-__global__ __launch_bounds__(64) void k_secular_fmm(SolveArgs a, FmmArgs f, Queue *q) {
+// FMM problems: one work item per 64-root piece of a target leaf; blockDim.x = 64 S with
+// the same dynamic LDS as k_secular
+__global__ __launch_bounds__(512) void k_secular_fmm(SolveArgs a, FmmArgs f, Queue *q) {
+    extern __shared__ double red[];
     __shared__ int slot;
     if (q) {
         for (;;) {
             const int item = queue_pull(q, a.ntiles, &slot);
             if (item < 0) break;
-            secular_chunk<true>(a, a.tiles[item], nullptr, &f);
+            secular_chunk<true>(a, a.tiles[item], red, &f);
         }
         queue_leave(q);
     } else if ((int)blockIdx.x < a.ntiles) {
-        secular_chunk<true>(a, a.tiles[blockIdx.x], nullptr, &f);
+        secular_chunk<true>(a, a.tiles[blockIdx.x], red, &f);
     }
 }
 
-hipError_t launch_secular_fmm(const SolveArgs &a, const FmmArgs &f, Queue *q, int grid,
-                              hipStream_t s) {
+hipError_t launch_secular_fmm(const SolveArgs &a, const FmmArgs &f, int split, Queue *q,
+                              int grid, hipStream_t s) {
     if (a.ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_secular_fmm, dim3(q ? grid : a.ntiles), dim3(WAVE), 0, s, a, f, q);
+    const size_t lds = split > 1 ? sizeof(double4) * WAVE * split : 0;
+    SDC_LAUNCH(KID_SECULAR_FMM, k_secular_fmm, dim3(q ? grid : a.ntiles), dim3(WAVE * split), lds, s, a,
+                       f, q);
     return hipGetLastError();
 }
 
 hipError_t launch_validate(const SolveArgs &a, int prob_first, int nprob, hipStream_t s) {
-    hipLaunchKernelGGL(k_validate, dim3(nprob), dim3(256), 0, s, a, prob_first);
+    SDC_LAUNCH(KID_VALIDATE, k_validate, dim3(nprob), dim3(256), 0, s, a, prob_first);
     return hipGetLastError();
 }
 
 hipError_t launch_secular(const SolveArgs &a, int split, Queue *q, int grid, hipStream_t s) {
     if (a.ntiles <= 0) return hipSuccess;
     const size_t lds = split > 1 ? sizeof(double4) * WAVE * split : 0;
-    hipLaunchKernelGGL(k_secular, dim3(q ? grid : a.ntiles), dim3(WAVE * split), lds, s, a, q);
+    SDC_LAUNCH(KID_SECULAR, k_secular, dim3(q ? grid : a.ntiles), dim3(WAVE * split), lds, s, a, q);
     return hipGetLastError();
 }
 

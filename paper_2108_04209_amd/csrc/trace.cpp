@@ -1,0 +1,119 @@
+// trace.cpp -- optional per-kernel timing (process-wide).
+//
+// When enabled, every kernel launch of the library is bracketed by two HIP events on its
+// own stream; superdc_kernel_times() waits for the recorded events and returns the summed
+// durations and launch counts per kernel, then starts a new collection.  Off by default;
+// not for use while a stream is being captured into a graph.
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <vector>
+
+#include "common.h"
+
+namespace sdc {
+namespace {
+
+struct Mark {
+    int kid;
+    hipEvent_t e0, e1;
+};
+
+struct Tracer {
+    std::mutex mu;
+    bool on = false;
+    std::vector<hipEvent_t> pool;  // idle events
+    std::vector<Mark> marks;       // recorded, not yet collected
+};
+
+Tracer &tracer() {
+    static Tracer t;
+    return t;
+}
+
+hipEvent_t take(Tracer &t) {
+    if (!t.pool.empty()) {
+        hipEvent_t e = t.pool.back();
+        t.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+const char *kNames[KID_COUNT] = {
+    "k_validate", "k_fmm_boxes", "k_fmm_lists", "k_secular", "k_secular_fmm", "k_pack_ke",
+    "k_loewner", "k_bnorm", "k_apply_mfma", "k_apply_valu", "k_bwd", "k_bwd_rho",
+    "k_leaf_jacobi", "k_merge", "k_assemble", "k_permute", "k_leaf_apply", "k_status_or",
+    "k_fill", "k_leaf_vectors"};
+
+}  // namespace
+
+TraceScope::TraceScope(int kid, hipStream_t s) : kid_(kid), s_(s) {
+    Tracer &t = tracer();
+    if (!t.on) return;  // racy read is fine: enabling is not synchronised with launches
+    std::lock_guard<std::mutex> g(t.mu);
+    e0_ = take(t);
+    e1_ = take(t);
+    if (e0_ && e1_) (void)hipEventRecord(e0_, s_);
+}
+
+TraceScope::~TraceScope() {
+    if (!e0_ || !e1_) return;
+    Tracer &t = tracer();
+    std::lock_guard<std::mutex> g(t.mu);
+    (void)hipEventRecord(e1_, s_);
+    t.marks.push_back(Mark{kid_, e0_, e1_});
+}
+
+}  // namespace sdc
+
+using namespace sdc;
+
+extern "C" {
+
+int superdc_kernel_timing(int enable) {
+    Tracer &t = tracer();
+    std::lock_guard<std::mutex> g(t.mu);
+    t.on = enable != 0;
+    return SUPERDC_OK;
+}
+
+int superdc_kernel_times(double *ms, int32_t *launches, int32_t count) {
+    if (count < 0 || (count > 0 && (!ms || !launches))) return SUPERDC_EINVAL;
+    if (count == 0) return KID_COUNT;  // size query: collects nothing
+    Tracer &t = tracer();
+    std::vector<Mark> marks;
+    {
+        std::lock_guard<std::mutex> g(t.mu);
+        marks.swap(t.marks);
+    }
+    for (int i = 0; i < count; ++i) {
+        ms[i] = 0.0;
+        launches[i] = 0;
+    }
+    int rc = SUPERDC_OK;
+    for (const Mark &m : marks) {
+        float dt = 0.f;
+        if (hipEventSynchronize(m.e1) != hipSuccess ||
+            hipEventElapsedTime(&dt, m.e0, m.e1) != hipSuccess)
+            rc = SUPERDC_EHIP;
+        if (m.kid < count) {
+            ms[m.kid] += dt;
+            launches[m.kid] += 1;
+        }
+    }
+    std::lock_guard<std::mutex> g(t.mu);
+    for (const Mark &m : marks) {
+        t.pool.push_back(m.e0);
+        t.pool.push_back(m.e1);
+    }
+    return rc == SUPERDC_OK ? KID_COUNT : rc;
+}
+
+const char *superdc_kernel_name(int32_t id) {
+    return id >= 0 && id < KID_COUNT ? kNames[id] : "unknown";
+}
+
+}  // extern "C"

@@ -136,8 +136,30 @@ __device__ void bnorm_tile(const VecArgs &a, Tile t, double4 *red) {
     const double2 kv = a.ke[base + (active ? j : n - 1)];
     int p0, p1;
     split_range(n, p0, p1);
+    // two poles share one reciprocal (the FP64 reciprocal issues at a quarter of the FMA
+    // rate): zhat0^2/t0^2 + zhat1^2/t1^2 = ((zhat0 t1)^2 + (zhat1 t0)^2) / (t0 t1)^2, a sum
+    // of two squares over a square.  The products need every |t| inside [2^-240, 2^240];
+    // the smallest |t| of a root is |eta| (its origin is its nearest pole) and the largest
+    // is at an end of the pole range.  A wavefront with a root outside takes one
+    // reciprocal per pole.
     double s0 = 0.0, s1 = 0.0;
     int i = p0;
+    bool paired = false;
+    if (p0 < p1) {
+        const double tmax = fmax(fabs((dz[p0].x - kv.x) - kv.y), fabs((dz[p1 - 1].x - kv.x) - kv.y));
+        const bool ok = fabs(kv.y) >= 0x1p-240 && tmax <= 0x1p240;
+        paired = __ballot(!ok) == 0ull;
+    }
+    if (paired) {
+        for (; i + 2 <= p1; i += 2) {
+            const double2 q0v = dz[i], q1v = dz[i + 1];
+            const double t0 = (q0v.x - kv.x) - kv.y, t1 = (q1v.x - kv.x) - kv.y;
+            const double R = rcp_nr(t0 * t1);
+            const double u0 = q0v.y * t1, u1 = q1v.y * t0;
+            const double num = __builtin_fma(u0, u0, u1 * u1);
+            s0 = __builtin_fma(num * R, R, s0);
+        }
+    }
     for (; i + 2 <= p1; i += 2) {
         const double2 q0v = dz[i], q1v = dz[i + 1];
         const double q0 = q0v.y * rcp_nr((q0v.x - kv.x) - kv.y);
@@ -195,15 +217,15 @@ __global__ __launch_bounds__(1024) void k_bnorm(VecArgs a, Queue *q) {
 hipError_t launch_loewner(const VecArgs &a, int split, Queue *q, int grid, hipStream_t s) {
     if (a.ntiles <= 0) return hipSuccess;
     const size_t lds = split > 1 ? sizeof(double4) * WAVE * split : 0;
-    hipLaunchKernelGGL(k_pack_ke, dim3(a.ntiles), dim3(64), 0, s, a);
-    hipLaunchKernelGGL(k_loewner, dim3(q ? grid : a.ntiles), dim3(WAVE * split), lds, s, a, q);
+    SDC_LAUNCH(KID_PACK, k_pack_ke, dim3(a.ntiles), dim3(64), 0, s, a);
+    SDC_LAUNCH(KID_LOEWNER, k_loewner, dim3(q ? grid : a.ntiles), dim3(WAVE * split), lds, s, a, q);
     return hipGetLastError();
 }
 
 hipError_t launch_bnorm(const VecArgs &a, int split, Queue *q, int grid, hipStream_t s) {
     if (a.ntiles <= 0) return hipSuccess;
     const size_t lds = split > 1 ? sizeof(double4) * WAVE * split : 0;
-    hipLaunchKernelGGL(k_bnorm, dim3(q ? grid : a.ntiles), dim3(WAVE * split), lds, s, a, q);
+    SDC_LAUNCH(KID_BNORM, k_bnorm, dim3(q ? grid : a.ntiles), dim3(WAVE * split), lds, s, a, q);
     return hipGetLastError();
 }
 

@@ -72,6 +72,12 @@ def load_library(path: str = LIB_PATH):
     lib.superdc_autotune.restype = C.c_int
     lib.superdc_batch_shapes.argtypes = [_P, _P]
     lib.superdc_batch_shapes.restype = C.c_int
+    lib.superdc_kernel_timing.argtypes = [C.c_int]
+    lib.superdc_kernel_timing.restype = C.c_int
+    lib.superdc_kernel_times.argtypes = [_P, _P, C.c_int32]
+    lib.superdc_kernel_times.restype = C.c_int
+    lib.superdc_kernel_name.argtypes = [C.c_int32]
+    lib.superdc_kernel_name.restype = C.c_char_p
     _lib = lib
     return lib
 
@@ -237,6 +243,24 @@ def autotune(ctx, batch, d, z, rho, opts=None, stream=None):
     _check(load_library().superdc_autotune(ctx.handle, batch.handle, _ptr(d), _ptr(z), _ptr(rho),
                                            C.byref(o), _stream(stream)), "superdc_autotune")
     return batch_shapes(batch)
+
+
+def kernel_timing(enable=True):
+    """superdc_kernel_timing: bracket every library launch with HIP events."""
+    _check(load_library().superdc_kernel_timing(int(bool(enable))), "superdc_kernel_timing")
+
+
+def kernel_times():
+    """superdc_kernel_times: {kernel name: (ms, launches)} since the last call (waits for
+    the recorded launches), kernels that ran only."""
+    lib = load_library()
+    cnt = lib.superdc_kernel_times(None, None, 0)
+    if cnt < 0:
+        _check(cnt, "superdc_kernel_times")
+    ms = (C.c_double * cnt)()
+    nl = (C.c_int32 * cnt)()
+    _check(min(0, lib.superdc_kernel_times(ms, nl, cnt)), "superdc_kernel_times")
+    return {lib.superdc_kernel_name(i).decode(): (ms[i], nl[i]) for i in range(cnt) if nl[i]}
 
 
 def batch_shapes(batch):

@@ -37,3 +37,26 @@ def test_autotune_and_cache(orc, tmp_path, monkeypatch):
     assert native.autotune(ctx, b2, d, z, rho) == sh
     lines = (tmp_path / "tune.txt").read_text().split("\n")
     assert len([x for x in lines if x.strip()]) == 1
+
+
+def test_kernel_timing():
+    """Per-kernel timing brackets each launch: one solve gives one validation and one
+    solver launch with positive durations; with timing off nothing is collected."""
+    from paper_2108_04209_amd import native
+    from tests import gpu_pipeline as gp
+    batch = gen.small_batch([300, 1200], seed=72)
+    ctx = gp.context()
+    b = native.Batch(ctx, batch.off)
+    d, z, rho = gp.to_dev(batch.d), gp.to_dev(batch.z), gp.to_dev(batch.rho)
+    native.kernel_times()  # drop anything collected before
+    native.kernel_timing(True)
+    try:
+        native.secular_solve(ctx, b, d, z, rho)
+        kt = native.kernel_times()
+    finally:
+        native.kernel_timing(False)
+    assert kt["k_validate"][1] == 1 and kt["k_secular"][1] == 1
+    assert kt["k_secular"][0] > 0.0
+    native.secular_solve(ctx, b, d, z, rho)
+    torch.cuda.synchronize()
+    assert native.kernel_times() == {}
