@@ -42,7 +42,7 @@ FMM_CROSSOVER = 16384    # the library's automatic direct/FMM switch (roots per 
 MFMA_MIN_M = 4           # the library's automatic VALU/MFMA apply switch (columns)
 
 
-def kernel_roofline(kt, flops, steps):
+def kernel_roofline(kt, flops, steps, workload=None):
     """Per-kernel table and the roofline object of the dominant kernel.
 
     kt: {kernel: (ms, launches)} from the library's per-kernel HIP-event timing over
@@ -64,12 +64,44 @@ def kernel_roofline(kt, flops, steps):
     achieved = e["algorithmic_tflops"]
     peak = PEAK_FP64_MFMA if dom == "k_apply_mfma" else PEAK_FP64_VALU
     roof = {"bound": "mfma" if dom == "k_apply_mfma" else "alu", "achieved": achieved,
-            "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+            "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": kernel_traffic(dom, workload) if workload else None,
             "kernel": dom, "launches_per_step": e["launches_per_step"],
             "avg_launch_ms": e["avg_launch_ms"],
             "algorithmic_flops_per_launch": flops[dom] / e["launches_per_step"],
             "timing": "HIP events around each launch on its stream (library kernel timing)"}
     return table, roof
+
+
+CALIB_BYTES = 512 << 20  # the calibration copy: this many bytes read and written
+PROFILES = os.path.join(ROOT, "profiles")
+CSRC = os.path.join(ROOT, "paper_2108_04209_amd", "csrc")
+
+
+def kernel_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` in `workload` from the committed counter summary
+    profiles/<kernel>_<workload>_traffic.md (FETCH_SIZE + WRITE_SIZE, each scaled by the
+    same counter's reading for a copy of known size), or None if there is none or the
+    kernel's sources changed since it was taken (their SHA-256 is recorded in it)."""
+    import hashlib
+    path = os.path.join(PROFILES, f"{kernel}_{workload}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    try:
+        srcs = fields["sources"].split(",")
+        h = hashlib.sha256()
+        for f in srcs:
+            h.update(open(os.path.join(CSRC, f.strip()), "rb").read())
+        if h.hexdigest() != fields["sources_sha256"]:
+            return None
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, OSError, ValueError):
+        return None
 
 
 def note(msg):
@@ -90,6 +122,9 @@ def parse():
                     help="with --workload conquer, skip the batched-level and large-problem "
                          "side measurements")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one 512 MiB device-to-device copy (the reference kernel "
+                         "that scales the profiler's FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
 
 
@@ -300,7 +335,7 @@ def bench_level(args, name):
               ("k_apply_mfma" if m >= MFMA_MIN_M else "k_apply_valu"): apply_flops}
     if direct:
         kflops["k_secular"] = sec_flops
-    kernels, roofline = kernel_roofline(kt, kflops, args.steps)
+    kernels, roofline = kernel_roofline(kt, kflops, args.steps, name)
     res = {
         "metric": METRIC, "value": tot / (ms * 1e-3), "unit": "roots/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
@@ -522,7 +557,8 @@ def bench_conquer(args):
     torch.cuda.synchronize()
     kt = native.kernel_times()
     native.kernel_timing(False)
-    kernels, roofline = kernel_roofline(kt, conquer_kernel_flops(tree, iters), args.steps)
+    kernels, roofline = kernel_roofline(kt, conquer_kernel_flops(tree, iters), args.steps,
+                                        "conquer")
     native.hss_set_timing(plan, True)
 
     # accuracy: trace identity and sampled eigenpair residuals with the oracle's product
@@ -582,6 +618,13 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.calibrate_copy:
+        x = torch.ones(CALIB_BYTES // 8, dtype=torch.float64, device="cuda:0")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        note(f"calibration copy of {CALIB_BYTES} bytes done")
+        del x, y
     if args.workload == "conquer":
         res = bench_conquer(args)
         if not args.no_level:
