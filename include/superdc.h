@@ -76,12 +76,14 @@ typedef struct {
                             1..200                                                        */
     int32_t method;      /* 0 auto (direct below the crossover, FMM above), 1 direct sums,
                             2 triangular FMM (Sec. 4.1.2)                                 */
-    int32_t fmm_order;   /* Chebyshev order of the FMM expansions; default 16, 4..32      */
+    int32_t fmm_order;   /* Chebyshev nodes per FMM box; 16 (the only supported order)      */
     int32_t fmm_leaf;    /* FMM leaf size; default 256, a multiple of 64                  */
     int32_t persistent;  /* 1: one persistent launch per phase for the whole batch;
                             0: one launch per problem per phase (the "plain" baseline)    */
     int32_t apply_kernel;/* Cauchy apply: 0 auto (MFMA for m >= 4), 1 VALU, 2 FP64 MFMA    */
-    int32_t reserved[3]; /* must be 0                                                     */
+    int32_t fmm_crossover;/* method 0: problems with at least this many roots use the FMM
+                            (solver, b, Qhat^T X); 0 = the context's default (16384)      */
+    int32_t reserved[2]; /* must be 0                                                     */
 } superdc_opts;
 
 void superdc_opts_default(superdc_opts *opts);
@@ -139,6 +141,10 @@ int superdc_secular_solve(superdc_ctx *ctx, const superdc_batch *batch, const do
  *   out: zhat[total] with rho zhat_i^2 = prod_j (lambda_j - d_i) / prod_{j!=i} (d_j - d_i)
  *        and sign(zhat_i) = sign(z_i); bnorm[total] with
  *        bnorm_j = (sum_i zhat_i^2 / (d_i - lambda_j)^2)^(-1/2) > 0.
+ * Problems that use the FMM (opts.method / opts.fmm_crossover, as for the solver) get b
+ * through the eigenvector-side triangular FMM (Sec. 4.3: near poles in the shifted form,
+ * far boxes through Chebyshev equivalent sources), the others by direct sums; zhat is
+ * always formed by direct products.
  */
 int superdc_loewner(superdc_ctx *ctx, const superdc_batch *batch, const double *d,
                     const double *z, const double *rho, const double *eta,
@@ -149,7 +155,10 @@ int superdc_loewner(superdc_ctx *ctx, const superdc_batch *batch, const double *
  * Y = Qhat X (trans = 0) or Y = Qhat^T X (trans = 1) for every problem, with
  * Qhat_ij = zhat_i bnorm_j / ((d_i - d_{K_j}) - eta_j) (eqs. eigvecs, qscale, qk).
  * X and Y are total x m column-major with leading dimensions ldx, ldy >= total; they
- * must not overlap.  m >= 1.
+ * must not overlap.  m >= 1.  With trans = 1, problems that use the FMM (as for the
+ * solver) are applied through the eigenvector-side triangular FMM (Sec. 4.3, Alg. 3
+ * Z-update) in passes of 16 columns; the others, and every trans = 0 product, use the
+ * FP64 MFMA kernel (m >= 4) or the VALU kernel.
  */
 int superdc_cauchy_apply(superdc_ctx *ctx, const superdc_batch *batch, const double *d,
                          const double *zhat, const double *bnorm, const double *eta,

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libsuperdc.so")
 
-SOURCES = ["secular.hip", "vectors.hip", "apply.hip", "backward.hip", "fmm.hip", "hss.hip",
+SOURCES = ["secular.hip", "vectors.hip", "apply.hip", "backward.hip", "fmm.hip", "fmm_vec.hip", "hss.hip",
            "api.cpp", "hss_api.cpp", "tune.cpp", "trace.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

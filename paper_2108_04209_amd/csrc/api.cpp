@@ -35,11 +35,12 @@ int hip_fail(hipError_t e) {
 int opts_check(const superdc_opts *o) {
     if (!(o->stop_c > 0.0) || o->max_iter < 1 || o->max_iter > 200) return SUPERDC_EINVAL;
     if (o->method < 0 || o->method > 2) return SUPERDC_EINVAL;
-    if (o->fmm_order < 4 || o->fmm_order > 32) return SUPERDC_EINVAL;
+    if (o->fmm_order != FMM_P) return SUPERDC_EINVAL;
     if (o->fmm_leaf < 64 || o->fmm_leaf % 64) return SUPERDC_EINVAL;
     if (o->persistent != 0 && o->persistent != 1) return SUPERDC_EINVAL;
     if (o->apply_kernel < 0 || o->apply_kernel > 2) return SUPERDC_EINVAL;
-    for (int i = 0; i < 3; ++i)
+    if (o->fmm_crossover < 0) return SUPERDC_EINVAL;
+    for (int i = 0; i < 2; ++i)
         if (o->reserved[i] != 0) return SUPERDC_EINVAL;
     return SUPERDC_OK;
 }
@@ -202,7 +203,12 @@ FmmPlan *fmm_plan(superdc_batch *b, int leaf, int crossover) {
               fmm_upload(fp, &fp->near_hi, std::vector<int32_t>(), (size_t)fp->nleaves * FMM_NEAR_MAX) &&
               fmm_upload(fp, &fp->far_l, std::vector<int32_t>(), (size_t)fp->nleaves * FMM_FAR_MAX) &&
               fmm_upload(fp, &fp->far_r, std::vector<int32_t>(), (size_t)fp->nleaves * FMM_FAR_MAX) &&
-              fmm_upload(fp, &fp->cnt, std::vector<int32_t>(), (size_t)fp->nleaves * 3);
+              fmm_upload(fp, &fp->cnt, std::vector<int32_t>(), (size_t)fp->nleaves * 3) &&
+              fmm_upload(fp, &fp->used, std::vector<int32_t>(), fp->nboxes) &&
+              fmm_upload(fp, &fp->vnode, std::vector<double>(), (size_t)fp->nboxes * FMM_P) &&
+              fmm_upload(fp, &fp->vw, std::vector<double>(),
+                         (size_t)fp->nboxes * FMM_P * FMMV_MAX_M) &&
+              fmm_upload(fp, &fp->tail, std::vector<double>(), b->nprob);
     // direct chunks of the other problems, for each cut length
     fp->dir_lpt.assign(4, nullptr);
     fp->dir_count.assign(4, 0);
@@ -237,8 +243,9 @@ FmmArgs fmm_args(const FmmPlan *fp, const superdc_batch *b, const SolveArgs &a,
     f.leaf_off = fp->leaf_off;
     f.height = fp->height;
     f.dw = a.dw;
-    f.z2 = a.z2;
+    f.tail = a.z2;  // the last root lies below d_{n-1} + sum_j w_j
     f.status = a.status;
+    f.used = fp->used;
     f.eq = fp->eq;
     f.box_ab = fp->box_ab;
     f.near_lo = fp->near_lo;
@@ -252,6 +259,63 @@ FmmArgs fmm_args(const FmmPlan *fp, const superdc_batch *b, const SolveArgs &a,
     f.leaf_fmm = fp->leaf_fmm;
     (void)o;
     return f;
+}
+// The eigenvector-side FMM of one call: the list geometry comes from `pairs` (written by
+// the pack kernel from this call's d) and the last roots' offsets.
+FmmArgs fmm_vec_args(const FmmPlan *fp, const superdc_batch *b, const double2 *pairs,
+                     const int32_t *status) {
+    SolveArgs a{};
+    a.dw = const_cast<double2 *>(pairs);
+    a.status = const_cast<int32_t *>(status);
+    superdc_opts o;
+    superdc_opts_default(&o);
+    FmmArgs f = fmm_args(fp, b, a, o);
+    f.tail = fp->tail;
+    return f;
+}
+
+// the FMM plan that applies to this call, or nullptr (rc = ENOMEM on allocation failure)
+FmmPlan *fmm_for(superdc_ctx *ctx, superdc_batch *b, const superdc_opts &o, int &rc) {
+    rc = SUPERDC_OK;
+    const int crossover = o.method == 1 ? 0x7fffffff
+                          : o.method == 2 ? 2 * o.fmm_leaf
+                          : o.fmm_crossover > 0 ? o.fmm_crossover
+                                              : ctx->fmm_crossover;
+    if (b->max_n < crossover) return nullptr;
+    FmmPlan *fp = fmm_plan(b, o.fmm_leaf, crossover);
+    if (!fp) {
+        rc = SUPERDC_ENOMEM;
+        return nullptr;
+    }
+    return fp->nfmm > 0 ? fp : nullptr;
+}
+
+// Run the eigenvector-side FMM over every FMM problem of the batch for columns
+// [pk.c0, pk.c0 + v.m): pack the sources, build the lists (first pass only), compress the
+// used boxes, evaluate at the roots (one persistent launch, or one launch per problem).
+hipError_t fmmv_run(superdc_ctx *ctx, const superdc_batch *b, const FmmPlan *fp,
+                    const FmmArgs &f, FmmvPackArgs pk, const FmmVec &v, bool lists,
+                    bool persistent, hipStream_t s) {
+    pk.tiles = fp->leaf_nat;
+    pk.ntiles = fp->nitems;
+    hipError_t e = launch_fmmv_pack(pk, v, s);
+    if (e == hipSuccess && lists) e = launch_fmm_lists(f, s);
+    if (e == hipSuccess) e = launch_fmmv_sources(f, v, s);
+    if (e != hipSuccess) return e;
+    SolveArgs it{};
+    it.off = b->off_d;
+    if (persistent) {
+        it.tiles = fp->leaf_lpt;
+        it.ntiles = fp->nitems;
+        return launch_fmmv_eval(it, f, v, fp->split, ctx->queues + Q_FMMV,
+                                persistent_grid(ctx, fp->nitems, std::max(1, 32 / fp->split)), s);
+    }
+    for (int q = 0; q < fp->nfmm && e == hipSuccess; ++q) {
+        it.tiles = fp->leaf_nat + fp->item_off_h[q];
+        it.ntiles = fp->item_off_h[q + 1] - fp->item_off_h[q];
+        e = launch_fmmv_eval(it, f, v, fp->split, nullptr, 0, s);
+    }
+    return e;
 }
 }  // namespace
 
@@ -272,6 +336,189 @@ void *ws_get(superdc_ctx *ctx, int slot, size_t bytes) {
     ctx->ws_cap[slot] = cap;
     return p;
 }
+}  // namespace sdc
+
+#define SDC_OPTS(o, opts)                       \
+    superdc_opts o;                             \
+    if (opts) o = *(opts);                      \
+    else superdc_opts_default(&o);              \
+    {                                           \
+        int rc_ = opts_check(&o);               \
+        if (rc_) return rc_;                    \
+    }
+
+namespace sdc {
+// Loewner/b and the Cauchy apply.  reuse_lists: the batch's FMM interaction lists were
+// built by a solve on the same poles d and stay valid (internal callers only).
+int loewner_run(superdc_ctx *ctx, const superdc_batch *b, const double *d, const double *z,
+                const double *rho, const double *eta, const int32_t *origin,
+                const int32_t *status, double *zhat, double *bnorm, const superdc_opts *opts,
+                void *stream, bool reuse_lists) {
+    if (!ctx || !b || b->ctx != ctx || !d || !z || !rho || !eta || !origin || !status || !zhat ||
+        !bnorm)
+        return SUPERDC_EINVAL;
+    SDC_OPTS(o, opts);
+    hipStream_t s = (hipStream_t)stream;
+    VecArgs a{};
+    a.off = b->off_d;
+    a.d = d;
+    a.z = z;
+    a.rho = rho;
+    a.eta = eta;
+    a.origin = origin;
+    a.status = status;
+    a.ke = (double2 *)ws_get(ctx, WS_KE, sizeof(double2) * b->total);
+    a.dz = (double2 *)ws_get(ctx, WS_DZ, sizeof(double2) * b->total);
+    if (!a.ke || !a.dz) return SUPERDC_ENOMEM;
+    a.zhat = zhat;
+    a.bnorm = bnorm;
+    superdc_batch *bm = const_cast<superdc_batch *>(b);
+    const TileList *L = tile_list(bm, TILE);
+    if (!L) return SUPERDC_ENOMEM;
+    // large problems: b by the eigenvector-side FMM, the others by direct sums
+    int rc;
+    FmmPlan *fp = fmm_for(ctx, bm, o, rc);
+    if (rc) return rc;
+    FmmvPackArgs pk{};
+    FmmVec v{};
+    FmmArgs f{};
+    if (fp) {
+        double2 *pairs = (double2 *)ws_get(ctx, WS_VPAIR, sizeof(double2) * b->total);
+        double *src = (double *)ws_get(ctx, WS_VSRC, sizeof(double) * b->total);
+        if (!pairs || !src) return SUPERDC_ENOMEM;
+        pk.off = b->off_d;
+        pk.d = d;
+        pk.zhat = zhat;
+        pk.eta = eta;
+        pk.origin = origin;
+        pk.pairs = pairs;
+        pk.tail = fp->tail;
+        v.m = 1;
+        v.kern = 2;
+        v.src = src;
+        v.vnode = fp->vnode;
+        v.vw = fp->vw;
+        v.d = d;
+        v.origin = origin;
+        v.eta = eta;
+        v.bout = bnorm;
+        f = fmm_vec_args(fp, b, pairs, status);
+    }
+    if (o.persistent) {
+        a.tiles = L->lpt;
+        a.ntiles = L->count;
+        const int S = b->vec.split;
+        const int g = persistent_grid(ctx, L->count, std::max(1, 32 / S));
+        SDC_HIP(launch_loewner(a, S, ctx->queues + Q_LOEWNER, g, s));
+        if (fp) {
+            a.tiles = fp->dir_lpt[0];
+            a.ntiles = fp->dir_count[0];
+        }
+        SDC_HIP(launch_bnorm(a, S, ctx->queues + Q_BNORM,
+                             persistent_grid(ctx, a.ntiles, std::max(1, 32 / S)), s));
+        if (fp) SDC_HIP(fmmv_run(ctx, b, fp, f, pk, v, !reuse_lists, true, s));
+    } else {
+        for (int p = 0; p < b->nprob; ++p) {
+            const int64_t np = b->off_h[p + 1] - b->off_h[p];
+            const int S = shape_for(ctx, &np, 1, TILE).split;
+            a.tiles = L->nat + L->begin[p];
+            a.ntiles = L->begin[p + 1] - L->begin[p];
+            SDC_HIP(launch_loewner(a, S, nullptr, 0, s));
+            if (!fp || fp->fmm_of_h[p] < 0) SDC_HIP(launch_bnorm(a, S, nullptr, 0, s));
+        }
+        if (fp) SDC_HIP(fmmv_run(ctx, b, fp, f, pk, v, !reuse_lists, false, s));
+    }
+    return SUPERDC_OK;
+}
+
+int apply_run(superdc_ctx *ctx, const superdc_batch *b, const double *d, const double *zhat,
+              const double *bnorm, const double *eta, const int32_t *origin,
+              const int32_t *status, int trans, int32_t m, const double *X, int64_t ldx,
+              double *Y, int64_t ldy, const superdc_opts *opts, void *stream, bool reuse_lists) {
+    if (!ctx || !b || b->ctx != ctx || !d || !zhat || !bnorm || !eta || !origin || !status ||
+        !X || !Y)
+        return SUPERDC_EINVAL;
+    if ((trans != 0 && trans != 1) || m < 1 || ldx < b->total || ldy < b->total)
+        return SUPERDC_EINVAL;
+    SDC_OPTS(o, opts);
+    // X and Y must not overlap
+    const char *x0 = (const char *)X, *x1 = (const char *)(X + (ldx * (m - 1) + b->total));
+    const char *y0 = (const char *)Y, *y1 = (const char *)(Y + (ldy * (m - 1) + b->total));
+    if (x0 < y1 && y0 < x1) return SUPERDC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    ApplyArgs a{};
+    a.off = b->off_d;
+    a.d = d;
+    a.zhat = zhat;
+    a.bnorm = bnorm;
+    a.eta = eta;
+    a.origin = origin;
+    a.status = status;
+    a.trans = trans;
+    a.m = m;
+    a.X = X;
+    a.ldx = ldx;
+    a.Y = Y;
+    a.ldy = ldy;
+    const int use_mfma = o.apply_kernel == 2 ? 1 : (o.apply_kernel == 1 ? 0 : (m >= 4));
+    superdc_batch *bm = const_cast<superdc_batch *>(b);
+    const TileList *L = tile_list(bm, TILE);
+    if (!L) return SUPERDC_ENOMEM;
+    // Y = Qhat^T X of the large problems by the eigenvector-side FMM (the sums run over the
+    // poles for every root, the layout of the solver's lists); the others, and every
+    // Qhat X, by the direct kernels
+    int rc;
+    FmmPlan *fp = trans == 1 ? fmm_for(ctx, bm, o, rc) : nullptr;
+    if (trans == 1 && rc) return rc;
+    if (o.persistent) {
+        a.tiles = fp ? fp->dir_lpt[0] : L->lpt;
+        a.ntiles = fp ? fp->dir_count[0] : L->count;
+        SDC_HIP(launch_apply(a, use_mfma, ctx->queues + Q_APPLY,
+                             persistent_grid(ctx, a.ntiles, use_mfma ? 4 : 8), s));
+    } else {
+        for (int p = 0; p < b->nprob; ++p) {
+            if (fp && fp->fmm_of_h[p] >= 0) continue;
+            a.tiles = L->nat + L->begin[p];
+            a.ntiles = L->begin[p + 1] - L->begin[p];
+            SDC_HIP(launch_apply(a, use_mfma, nullptr, 0, s));
+        }
+    }
+    if (fp) {
+        const int mc = std::min(m, FMMV_MAX_M);
+        double2 *pairs = (double2 *)ws_get(ctx, WS_VPAIR, sizeof(double2) * b->total);
+        double *src = (double *)ws_get(ctx, WS_VSRC, sizeof(double) * b->total * mc);
+        if (!pairs || !src) return SUPERDC_ENOMEM;
+        FmmvPackArgs pk{};
+        pk.off = b->off_d;
+        pk.d = d;
+        pk.zhat = zhat;
+        pk.eta = eta;
+        pk.origin = origin;
+        pk.X = X;
+        pk.ldx = ldx;
+        pk.pairs = pairs;
+        pk.tail = fp->tail;
+        FmmVec v{};
+        v.kern = 1;
+        v.src = src;
+        v.vnode = fp->vnode;
+        v.vw = fp->vw;
+        v.d = d;
+        v.origin = origin;
+        v.eta = eta;
+        v.post = bnorm;
+        v.ldy = ldy;
+        const FmmArgs f = fmm_vec_args(fp, b, pairs, status);
+        for (int c0 = 0; c0 < m; c0 += FMMV_MAX_M) {
+            pk.c0 = c0;
+            v.m = std::min(FMMV_MAX_M, m - c0);
+            v.Y = Y + (int64_t)c0 * ldy;
+            SDC_HIP(fmmv_run(ctx, b, fp, f, pk, v, c0 == 0 && !reuse_lists, o.persistent != 0, s));
+        }
+    }
+    return SUPERDC_OK;
+}
+
 }  // namespace sdc
 
 extern "C" {
@@ -329,7 +576,7 @@ int superdc_create(superdc_ctx **out) {
 void superdc_destroy(superdc_ctx *ctx) {
     if (!ctx) return;
     (void)hipDeviceSynchronize();
-    for (int i = 0; i < 8; ++i)
+    for (int i = 0; i < kNumWs; ++i)
         if (ctx->ws[i]) (void)hipFree(ctx->ws[i]);
     if (ctx->queues) (void)hipFree(ctx->queues);
     delete ctx;
@@ -389,15 +636,6 @@ void superdc_batch_destroy(superdc_batch *b) {
 
 int64_t superdc_batch_total(const superdc_batch *b) { return b ? b->total : -1; }
 
-#define SDC_OPTS(o, opts)                       \
-    superdc_opts o;                             \
-    if (opts) o = *(opts);                      \
-    else superdc_opts_default(&o);              \
-    {                                           \
-        int rc_ = opts_check(&o);               \
-        if (rc_) return rc_;                    \
-    }
-
 int superdc_secular_solve(superdc_ctx *ctx, const superdc_batch *b, const double *d,
                           const double *z, const double *rho, double *lam, double *eta,
                           int32_t *origin, int32_t *iters, int32_t *status,
@@ -427,7 +665,8 @@ int superdc_secular_solve(superdc_ctx *ctx, const superdc_batch *b, const double
     // problem large enough to have two leaves; method 1: none)
     const int crossover = o.method == 1 ? 0x7fffffff
                           : o.method == 2 ? 2 * o.fmm_leaf
-                                          : ctx->fmm_crossover;
+                          : o.fmm_crossover > 0 ? o.fmm_crossover
+                                              : ctx->fmm_crossover;
     FmmPlan *fp = nullptr;
     if (b->max_n >= crossover) {
         fp = fmm_plan(bm, o.fmm_leaf, crossover);
@@ -498,45 +737,7 @@ int superdc_loewner(superdc_ctx *ctx, const superdc_batch *b, const double *d, c
                     const double *rho, const double *eta, const int32_t *origin,
                     const int32_t *status, double *zhat, double *bnorm,
                     const superdc_opts *opts, void *stream) {
-    if (!ctx || !b || b->ctx != ctx || !d || !z || !rho || !eta || !origin || !status || !zhat ||
-        !bnorm)
-        return SUPERDC_EINVAL;
-    SDC_OPTS(o, opts);
-    hipStream_t s = (hipStream_t)stream;
-    VecArgs a{};
-    a.off = b->off_d;
-    a.d = d;
-    a.z = z;
-    a.rho = rho;
-    a.eta = eta;
-    a.origin = origin;
-    a.status = status;
-    a.ke = (double2 *)ws_get(ctx, WS_KE, sizeof(double2) * b->total);
-    a.dz = (double2 *)ws_get(ctx, WS_DZ, sizeof(double2) * b->total);
-    if (!a.ke || !a.dz) return SUPERDC_ENOMEM;
-    a.zhat = zhat;
-    a.bnorm = bnorm;
-    superdc_batch *bm = const_cast<superdc_batch *>(b);
-    const TileList *L = tile_list(bm, TILE);
-    if (!L) return SUPERDC_ENOMEM;
-    if (o.persistent) {
-        a.tiles = L->lpt;
-        a.ntiles = L->count;
-        const int S = b->vec.split;
-        const int g = persistent_grid(ctx, L->count, std::max(1, 32 / S));
-        SDC_HIP(launch_loewner(a, S, ctx->queues + Q_LOEWNER, g, s));
-        SDC_HIP(launch_bnorm(a, S, ctx->queues + Q_BNORM, g, s));
-    } else {
-        for (int p = 0; p < b->nprob; ++p) {
-            const int64_t np = b->off_h[p + 1] - b->off_h[p];
-            const int S = shape_for(ctx, &np, 1, TILE).split;
-            a.tiles = L->nat + L->begin[p];
-            a.ntiles = L->begin[p + 1] - L->begin[p];
-            SDC_HIP(launch_loewner(a, S, nullptr, 0, s));
-            SDC_HIP(launch_bnorm(a, S, nullptr, 0, s));
-        }
-    }
-    return SUPERDC_OK;
+    return loewner_run(ctx, b, d, z, rho, eta, origin, status, zhat, bnorm, opts, stream, false);
 }
 
 int superdc_cauchy_apply(superdc_ctx *ctx, const superdc_batch *b, const double *d,
@@ -544,48 +745,8 @@ int superdc_cauchy_apply(superdc_ctx *ctx, const superdc_batch *b, const double 
                          const int32_t *origin, const int32_t *status, int trans, int32_t m,
                          const double *X, int64_t ldx, double *Y, int64_t ldy,
                          const superdc_opts *opts, void *stream) {
-    if (!ctx || !b || b->ctx != ctx || !d || !zhat || !bnorm || !eta || !origin || !status ||
-        !X || !Y)
-        return SUPERDC_EINVAL;
-    if ((trans != 0 && trans != 1) || m < 1 || ldx < b->total || ldy < b->total)
-        return SUPERDC_EINVAL;
-    SDC_OPTS(o, opts);
-    // X and Y must not overlap
-    const char *x0 = (const char *)X, *x1 = (const char *)(X + (ldx * (m - 1) + b->total));
-    const char *y0 = (const char *)Y, *y1 = (const char *)(Y + (ldy * (m - 1) + b->total));
-    if (x0 < y1 && y0 < x1) return SUPERDC_EINVAL;
-    hipStream_t s = (hipStream_t)stream;
-    ApplyArgs a{};
-    a.off = b->off_d;
-    a.d = d;
-    a.zhat = zhat;
-    a.bnorm = bnorm;
-    a.eta = eta;
-    a.origin = origin;
-    a.status = status;
-    a.trans = trans;
-    a.m = m;
-    a.X = X;
-    a.ldx = ldx;
-    a.Y = Y;
-    a.ldy = ldy;
-    const int use_mfma = o.apply_kernel == 2 ? 1 : (o.apply_kernel == 1 ? 0 : (m >= 4));
-    superdc_batch *bm = const_cast<superdc_batch *>(b);
-    const TileList *L = tile_list(bm, TILE);
-    if (!L) return SUPERDC_ENOMEM;
-    if (o.persistent) {
-        a.tiles = L->lpt;
-        a.ntiles = L->count;
-        SDC_HIP(launch_apply(a, use_mfma, ctx->queues + Q_APPLY,
-                             persistent_grid(ctx, L->count, use_mfma ? 4 : 8), s));
-    } else {
-        for (int p = 0; p < b->nprob; ++p) {
-            a.tiles = L->nat + L->begin[p];
-            a.ntiles = L->begin[p + 1] - L->begin[p];
-            SDC_HIP(launch_apply(a, use_mfma, nullptr, 0, s));
-        }
-    }
-    return SUPERDC_OK;
+    return apply_run(ctx, b, d, zhat, bnorm, eta, origin, status, trans, m, X, ldx, Y, ldy, opts,
+                     stream, false);
 }
 
 int superdc_secular_backward(superdc_ctx *ctx, const superdc_batch *b, const double *d,

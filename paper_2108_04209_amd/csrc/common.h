@@ -119,7 +119,7 @@ enum KernelId : int {
     KID_VALIDATE = 0, KID_FMM_BOXES, KID_FMM_LISTS, KID_SECULAR, KID_SECULAR_FMM, KID_PACK,
     KID_LOEWNER, KID_BNORM, KID_APPLY_MFMA, KID_APPLY_VALU, KID_BWD, KID_BWD_RHO, KID_LEAF,
     KID_MERGE, KID_ASSEMBLE, KID_PERMUTE, KID_LEAF_APPLY, KID_STATUS_OR, KID_FILL,
-    KID_LEAF_VECTORS, KID_COUNT
+    KID_LEAF_VECTORS, KID_FMM_GEOM, KID_FMMV_PACK, KID_FMMV_SOURCES, KID_FMMV_EVAL, KID_COUNT
 };
 
 class TraceScope {
@@ -152,16 +152,19 @@ struct superdc_ctx {
     int device = 0;
     int num_cu = 256;
     // grow-only workspace buffers
-    void *ws[8] = {nullptr};
-    size_t ws_cap[8] = {0};
+    void *ws[10] = {nullptr};
+    size_t ws_cap[10] = {0};
     sdc::Queue *queues = nullptr;  // kNumQueues counters, zeroed at creation
     int fmm_crossover = 16384;     // automatic method: FMM for problems at least this large
 };
 
-enum WsSlot { WS_DW = 0, WS_KE = 1, WS_DZ = 2, WS_Z2 = 3, WS_BK = 4, WS_BP = 5, WS_TMP = 6 };
+enum WsSlot {
+    WS_DW = 0, WS_KE = 1, WS_DZ = 2, WS_Z2 = 3, WS_BK = 4, WS_BP = 5, WS_TMP = 6, WS_VPAIR = 7,
+    WS_VSRC = 8, kNumWs
+};
 enum QueueSlot {
     Q_SECULAR = 0, Q_LOEWNER, Q_BNORM, Q_APPLY, Q_BWD1, Q_BWD2, Q_VALIDATE, Q_SECULAR_FMM,
-    kNumQueues
+    Q_FMMV, kNumQueues
 };
 
 namespace sdc {
@@ -205,6 +208,18 @@ const TileList *tile_list(superdc_batch *b, int chunk);
 }  // namespace sdc
 
 namespace sdc {
+// Loewner/b and the Cauchy apply behind superdc_loewner / superdc_cauchy_apply.
+// reuse_lists: the batch's FMM interaction lists were built by a solve on the same poles
+// d (internal callers that know it).
+int loewner_run(superdc_ctx *ctx, const superdc_batch *b, const double *d, const double *z,
+                const double *rho, const double *eta, const int32_t *origin,
+                const int32_t *status, double *zhat, double *bnorm, const superdc_opts *opts,
+                void *stream, bool reuse_lists);
+int apply_run(superdc_ctx *ctx, const superdc_batch *b, const double *d, const double *zhat,
+              const double *bnorm, const double *eta, const int32_t *origin,
+              const int32_t *status, int trans, int32_t m, const double *X, int64_t ldx,
+              double *Y, int64_t ldy, const superdc_opts *opts, void *stream, bool reuse_lists);
+
 // grow a workspace slot to at least `bytes`; returns nullptr on allocation failure
 void *ws_get(superdc_ctx *ctx, int slot, size_t bytes);
 

@@ -24,9 +24,10 @@ struct FmmArgs {
     const int32_t *box_off;   // [nfmm + 1]
     const int32_t *leaf_off;  // [nfmm + 1]
     const int32_t *height;    // [nfmm] tree height H (levels 0..H)
-    const double2 *dw;        // (d_j, w_j) of the batch (from validation)
-    const double *z2;         // sum of w per problem
+    const double2 *dw;        // (d_j, w_j) of the batch (from validation); .x alone for geometry
+    const double *tail;       // [nprob] bound of the last root above d_{n-1}
     const int32_t *status;
+    int32_t *used;            // [nboxes] 1 if some target leaf lists the box as far field
     double2 *eq;              // [boxes][FMM_P] equivalent sources (node, weight)
     double2 *box_ab;          // [boxes] (first pole, last pole) of the box
     int32_t *near_lo, *near_hi;   // [leaves][FMM_NEAR_MAX] pole ranges of near leaves
@@ -57,10 +58,52 @@ struct FmmPlan {
     Tile *leaf_nat = nullptr;          // ... in problem order
     std::vector<Tile *> dir_lpt;       // direct chunks of the other problems, per cut length
     std::vector<int32_t> dir_count;
+    int32_t *used = nullptr;           // [nboxes]
+    double *vnode = nullptr, *vw = nullptr;  // eigenvector-side equivalent sources
+    double *tail = nullptr;            // [nprob] per-call bound of the last root
     std::vector<void *> allocs;
 };
 
+// Eigenvector-side FMM (Sec. 4.3-4.4 with local shifting): sums over the poles i of a
+// problem for every root j, sum_i src_i,c K(d_i - lambda_j), with K = 1/t (the apply
+// Y = Qhat^T X: src = zhat_i X_i,c, scaled by b_j) or K = 1/t^2 (b: src = zhat_i^2).
+struct FmmVec {
+    int m;                    // columns of src (<= FMMV_MAX_M)
+    int kern;                 // 1: 1/t, 2: 1/t^2
+    double *src;              // [total][m] pole-major source weights
+    double *vnode;            // [boxes][FMM_P] equivalent source nodes
+    double *vw;               // [boxes][FMM_P][m] equivalent source weights
+    const double *d;          // poles
+    const int32_t *origin;    // roots' origins (local indices)
+    const double *eta;        // roots' offsets
+    const double *post;       // kern 1: per-root scale (b); unused for kern 2
+    double *Y;                // kern 1: output columns, ld ldy
+    int64_t ldy;
+    double *bout;             // kern 2: b_j = (sum)^(-1/2)
+};
+constexpr int FMMV_MAX_M = 16;
+
+// packing of the source weights of the FMM problems (and the list geometry)
+struct FmmvPackArgs {
+    const int64_t *off;
+    const Tile *tiles;   // 64-entry tiles of the FMM problems
+    int ntiles;
+    const double *d, *zhat, *eta;
+    const int32_t *origin;
+    const double *X;     // kern 1: right-hand sides (column-major, ld ldx), columns c0..c0+m-1
+    int64_t ldx;
+    int c0;
+    double2 *pairs;      // (d_i, zhat_i) for the list geometry
+    double *tail;        // [nprob] lambda_{n-1} - d_{n-1}
+};
+hipError_t launch_fmmv_pack(const FmmvPackArgs &a, const FmmVec &v, hipStream_t s);
+
 hipError_t launch_fmm_build(const FmmArgs &f, hipStream_t s);
+// geometry and interaction lists only (no secular equivalent sources)
+hipError_t launch_fmm_lists(const FmmArgs &f, hipStream_t s);
+hipError_t launch_fmmv_sources(const FmmArgs &f, const FmmVec &v, hipStream_t s);
+hipError_t launch_fmmv_eval(const SolveArgs &items, const FmmArgs &f, const FmmVec &v, int split,
+                            Queue *q, int grid, hipStream_t s);
 hipError_t launch_secular_fmm(const SolveArgs &a, const FmmArgs &f, int split, Queue *q,
                               int grid, hipStream_t s);
 

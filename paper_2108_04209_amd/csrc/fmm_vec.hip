@@ -1,0 +1,301 @@
+// fmm_vec.hip -- eigenvector-side triangular FMM on gfx950 (Sec. 4.3, "Structured
+// eigenvectors via FMM with local shifting", and the Z-update of Alg. 3).
+//
+// For the roots j of a large problem the sums over its poles i
+//     apply:  Y_j,c = b_j sum_i r_ij (zhat_i X_i,c)        (Y = Qhat^T X, eqs. eigvecs, qk)
+//     b:      b_j   = (sum_i zhat_i^2 r_ij^2)^(-1/2)      (eq. b)
+// with r_ij = 1/(d_i - lambda_j) are evaluated on the same pole tree and interaction
+// lists as the secular sums: near leaves directly in the shifted form
+// (d_i - d_{K_j}) - eta_j, far boxes through equivalent sources in lambda-form.  The
+// equivalent sources of a box are its Chebyshev nodes and the weights
+// W_q,c = sum_{i in box} src_i,c L_q(d_i), one column per right-hand side.  Plain sums
+// need no psi/phi split, but the lists are the directional ones of the solver and the
+// near field keeps the local shifting, as the paper prescribes for these products.
+#include "fmm.h"
+
+namespace sdc {
+
+namespace {
+
+__device__ __forceinline__ double cheb_node_v(int q) {
+    return cos((2.0 * q + 1.0) * 3.14159265358979323846 / (2.0 * FMM_P));
+}
+
+__device__ __forceinline__ double cheb_bary_v(int q) {
+    return ((q & 1) ? -1.0 : 1.0) * sin((2.0 * q + 1.0) * 3.14159265358979323846 / (2.0 * FMM_P));
+}
+
+}  // namespace
+
+// src_i,c = zhat_i X_i,c0+c (kern 1) or zhat_i^2 (kern 2); one lane per pole
+__global__ __launch_bounds__(64) void k_fmmv_pack(FmmvPackArgs a, FmmVec v) {
+    const Tile t = a.tiles[blockIdx.x];
+    const int64_t base = a.off[t.prob];
+    const int n = (int)(a.off[t.prob + 1] - base);
+    const int i = t.row0 + lane_id();
+    if (i >= n) return;
+    const double zh = a.zhat[base + i];
+    const double di = a.d[base + i];
+    a.pairs[base + i] = make_double2(di, zh);
+    double *src = v.src + (base + i) * v.m;
+    if (v.kern == 1) {
+        for (int c = 0; c < v.m; ++c) src[c] = zh * a.X[base + i + (int64_t)(a.c0 + c) * a.ldx];
+    } else {
+        src[0] = zh * zh;
+    }
+    if (i == n - 1) {
+        const int K = clamp_idx(a.origin[base + i], n);
+        a.tail[t.prob] = (a.d[base + K] + a.eta[base + i]) - di;
+    }
+}
+
+// Equivalent sources, one workgroup (256 threads) per box, in two launches: LEAVES = true
+// compresses every leaf box from its poles; LEAVES = false compresses every used box above
+// the leaves from the equivalent sources of its leaves (16 per leaf instead of up to
+// n/4 poles: the far field of a leaf's sources equals that of its poles to the
+// interpolation accuracy, and the box's nodes interpolate it again).  Points are taken
+// 256 at a time: each thread forms the 16 Lagrange values of one point in LDS, then thread
+// (q, c) accumulates sum_k L_q(x_k) w_k,c over the chunk.
+template <bool LEAVES>
+__global__ __launch_bounds__(256) void k_fmmv_sources(FmmArgs f, FmmVec v) {
+    __shared__ double Lq[256][FMM_P + 1];
+    __shared__ double Ss[256][FMMV_MAX_M + 1];
+    const int g = blockIdx.x;
+    const int qf = f.box_fmm[g];
+    const int p = f.fmm_prob[qf];
+    const int64_t base = f.off[p];
+    const int n = (int)(f.off[p + 1] - base);
+    const int hidx = g - f.box_off[qf];
+    const int H = f.height[qf];
+    int h = 0;
+    while ((2 << h) - 1 <= hidx) ++h;
+    // uniform for the workgroup: leaves in the first launch, used upper boxes in the second
+    if (LEAVES ? (h != H) : (h == H || !f.used[g])) return;
+    if (f.status[p] & ~SUPERDC_ST_NOCONV) return;
+    const int bi = hidx - ((1 << h) - 1);
+    const int64_t span = (int64_t)f.leaf << (H - h);
+    const int lo = (int)min((int64_t)n, bi * span), hi = (int)min((int64_t)n, (bi + 1) * span);
+    if (lo >= hi) return;  // empty box (never listed)
+    const int tid = threadIdx.x;
+    const int m = v.m;
+    const double *d = v.d + base;
+    const double *src = v.src + base * m;
+    const double a = d[lo], b = d[hi - 1];
+    const double cc = 0.5 * (a + b), hw = 0.5 * (b - a);
+    double *node = v.vnode + (int64_t)g * FMM_P;
+    double *w = v.vw + (int64_t)g * FMM_P * m;
+    if (LEAVES && hi - lo <= FMM_P) {  // few poles: they are their own equivalent sources
+        if (tid < FMM_P) {
+            const bool in = lo + tid < hi;
+            node[tid] = in ? d[lo + tid] : cc;
+            for (int c = 0; c < m; ++c) w[tid * m + c] = in ? src[(int64_t)(lo + tid) * m + c] : 0.0;
+        }
+        return;
+    }
+    // the points: poles of a leaf, or the sources of the box's leaves
+    const int leaf0 = (1 << H) - 1 + bi * (1 << (H - h));      // heap index of the first leaf
+    const int nleaf = (int)((hi - lo + f.leaf - 1) / f.leaf);  // leaves with poles
+    const int npts = LEAVES ? hi - lo : nleaf * FMM_P;
+    const int q = tid / FMMV_MAX_M, c = tid % FMMV_MAX_M;  // accumulator of this thread
+    double tq[FMM_P], lam[FMM_P];
+#pragma unroll
+    for (int r = 0; r < FMM_P; ++r) {
+        tq[r] = cheb_node_v(r);
+        lam[r] = cheb_bary_v(r);
+    }
+    const double ihw = 1.0 / hw;
+    double acc = 0.0;
+    for (int k0 = 0; k0 < npts; k0 += 256) {
+        const int k = k0 + tid;
+        if (k < npts) {
+            double x;
+            const double *wk;
+            if (LEAVES) {
+                x = d[lo + k];
+                wk = src + (int64_t)(lo + k) * m;
+            } else {
+                const int gl = f.box_off[qf] + leaf0 + k / FMM_P;
+                x = v.vnode[(int64_t)gl * FMM_P + k % FMM_P];
+                wk = v.vw + ((int64_t)gl * FMM_P + k % FMM_P) * m;
+            }
+            const double t = fmin(1.0, fmax(-1.0, (x - cc) * ihw));
+            int hit = -1;
+            double inv[FMM_P], den = 0.0;
+#pragma unroll
+            for (int r = 0; r < FMM_P; ++r) {
+                const double dlt = t - tq[r];
+                if (dlt == 0.0) hit = r;
+                inv[r] = lam[r] * rcp_nr(dlt);
+                den += inv[r];
+            }
+            const double iden = 1.0 / den;
+#pragma unroll
+            for (int r = 0; r < FMM_P; ++r)
+                Lq[tid][r] = hit >= 0 ? (r == hit ? 1.0 : 0.0) : inv[r] * iden;
+            for (int cc2 = 0; cc2 < m; ++cc2) Ss[tid][cc2] = wk[cc2];
+        } else {
+#pragma unroll
+            for (int r = 0; r < FMM_P; ++r) Lq[tid][r] = 0.0;
+            for (int cc2 = 0; cc2 < m; ++cc2) Ss[tid][cc2] = 0.0;
+        }
+        __syncthreads();
+        if (c < m) {
+            const int cnt = min(256, npts - k0);
+            for (int kk = 0; kk < cnt; ++kk) acc = __builtin_fma(Lq[kk][q], Ss[kk][c], acc);
+        }
+        __syncthreads();
+    }
+    if (tid < FMM_P) node[tid] = cc + hw * tq[tid];
+    if (c < m) w[q * m + c] = acc;
+}
+
+// Evaluation at the roots: work items are 64-root pieces of the target leaves; S
+// wavefronts per item split the near ranges and the far boxes, and their partial sums are
+// added in wavefront order.  NC >= m accumulators per lane.
+template <int KERN, int NC>
+__device__ void fmmv_item(const SolveArgs &it, const FmmArgs &f, const FmmVec &v, Tile t,
+                          double *red) {
+    const int p = t.prob;
+    const int64_t base = it.off[p];
+    const int n = (int)(it.off[p + 1] - base);
+    const int lane = lane_id();
+    const int S = blockDim.x / WAVE, wv = wave_uniform((int)(threadIdx.x / WAVE));
+    const int j = t.row0 + lane;
+    const bool active = j < n;
+    const int m = v.m;
+    if (f.status[p] & ~SUPERDC_ST_NOCONV) {
+        if (active && wv == 0) {
+            const double nan = __builtin_nan("");
+            if (KERN == 1)
+                for (int c = 0; c < m; ++c) v.Y[base + j + (int64_t)c * v.ldy] = nan;
+            else
+                v.bout[base + j] = nan;
+        }
+        return;
+    }
+    const int jj = active ? j : n - 1;
+    const double dK = v.d[base + clamp_idx(v.origin[base + jj], n)];
+    const double eta = v.eta[base + jj];
+    const double x = dK + eta;
+    const int qf = f.fmm_of[p];
+    const int L = wave_uniform(f.leaf_off[qf] + t.row0 / f.leaf);
+    int nn = wave_uniform(f.cnt[3 * (int64_t)L]);
+    const int nl = wave_uniform(f.cnt[3 * (int64_t)L + 1]);
+    const int nr = wave_uniform(f.cnt[3 * (int64_t)L + 2]);
+    const const_double_ptr dd = as_const(v.d + base);
+    const const_double_ptr src = as_const(v.src + base * m);
+    double acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+    // one near range [lo, hi) of poles, shifted form, two Newton steps
+    auto near = [&](int lo, int hi) {
+        for (int i = lo; i < hi; ++i) {
+            const double r = rcp_nr((dd[i] - dK) - eta);
+            if (KERN == 1) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    if (c < m) acc[c] = __builtin_fma(r, src[(int64_t)i * m + c], acc[c]);
+            } else {
+                acc[0] = __builtin_fma(r * r, src[i], acc[0]);
+            }
+        }
+    };
+    if (nn < 0) {  // lists overflowed: every pole directly, split over the wavefronts
+        near(wave_uniform((int)(((int64_t)n * wv) / S)), wave_uniform((int)(((int64_t)n * (wv + 1)) / S)));
+    } else {
+        for (int e = 0; e < nn; ++e) {
+            const int lo0 = wave_uniform(f.near_lo[(int64_t)L * FMM_NEAR_MAX + e]);
+            const int hi0 = wave_uniform(f.near_hi[(int64_t)L * FMM_NEAR_MAX + e]);
+            near(lo0 + (int)(((int64_t)(hi0 - lo0) * wv) / S),
+                 lo0 + (int)(((int64_t)(hi0 - lo0) * (wv + 1)) / S));
+        }
+        // far boxes of both sides, lambda-form, one Newton step
+        for (int e = wv; e < nl + nr; e += S) {
+            const int g = wave_uniform(e < nl ? f.far_l[(int64_t)L * FMM_FAR_MAX + e]
+                                              : f.far_r[(int64_t)L * FMM_FAR_MAX + e - nl]);
+            const const_double_ptr nd = as_const(v.vnode + (int64_t)g * FMM_P);
+            const const_double_ptr ww = as_const(v.vw + (int64_t)g * FMM_P * m);
+#pragma unroll 4
+            for (int q = 0; q < FMM_P; ++q) {
+                const double r = rcp_nr1(nd[q] - x);
+                if (KERN == 1) {
+#pragma unroll
+                    for (int c = 0; c < NC; ++c)
+                        if (c < m) acc[c] = __builtin_fma(r, ww[q * m + c], acc[c]);
+                } else {
+                    acc[0] = __builtin_fma(r * r, ww[q], acc[0]);
+                }
+            }
+        }
+    }
+    if (S > 1) {
+        if (wv > 0)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) red[((wv - 1) * NC + c) * WAVE + lane] = acc[c];
+        __syncthreads();
+        if (wv == 0)
+            for (int w = 1; w < S; ++w)
+#pragma unroll
+                for (int c = 0; c < NC; ++c) acc[c] += red[((w - 1) * NC + c) * WAVE + lane];
+        __syncthreads();
+    }
+    if (active && wv == 0) {
+        if (KERN == 1) {
+            const double post = v.post[base + j];
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                if (c < m) v.Y[base + j + (int64_t)c * v.ldy] = post * acc[c];
+        } else {
+            v.bout[base + j] = 1.0 / sqrt(acc[0]);
+        }
+    }
+}
+
+// blockDim.x = 64 S; dynamic LDS: (S - 1) NC doubles per lane
+template <int KERN, int NC>
+__global__ __launch_bounds__(512) void k_fmmv_eval(SolveArgs it, FmmArgs f, FmmVec v, Queue *q) {
+    extern __shared__ double red[];
+    __shared__ int slot;
+    if (q) {
+        for (;;) {
+            const int item = queue_pull(q, it.ntiles, &slot);
+            if (item < 0) break;
+            fmmv_item<KERN, NC>(it, f, v, it.tiles[item], red);
+        }
+        queue_leave(q);
+    } else if ((int)blockIdx.x < it.ntiles) {
+        fmmv_item<KERN, NC>(it, f, v, it.tiles[blockIdx.x], red);
+    }
+}
+
+hipError_t launch_fmmv_pack(const FmmvPackArgs &a, const FmmVec &v, hipStream_t s) {
+    if (a.ntiles <= 0) return hipSuccess;
+    SDC_LAUNCH(KID_FMMV_PACK, k_fmmv_pack, dim3(a.ntiles), dim3(64), 0, s, a, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fmmv_sources(const FmmArgs &f, const FmmVec &v, hipStream_t s) {
+    if (f.nboxes <= 0) return hipSuccess;
+    SDC_LAUNCH(KID_FMMV_SOURCES, k_fmmv_sources<true>, dim3(f.nboxes), dim3(256), 0, s, f, v);
+    SDC_LAUNCH(KID_FMMV_SOURCES, k_fmmv_sources<false>, dim3(f.nboxes), dim3(256), 0, s, f, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fmmv_eval(const SolveArgs &it, const FmmArgs &f, const FmmVec &v, int split,
+                            Queue *q, int grid, hipStream_t s) {
+    if (it.ntiles <= 0) return hipSuccess;
+    const dim3 g(q ? grid : it.ntiles), blk(WAVE * split);
+    if (v.kern == 2) {
+        const size_t lds = sizeof(double) * WAVE * (split - 1) * 1;
+        SDC_LAUNCH(KID_FMMV_EVAL, (k_fmmv_eval<2, 1>), g, blk, lds, s, it, f, v, q);
+    } else if (v.m <= 8) {
+        const size_t lds = sizeof(double) * WAVE * (split - 1) * 8;
+        SDC_LAUNCH(KID_FMMV_EVAL, (k_fmmv_eval<1, 8>), g, blk, lds, s, it, f, v, q);
+    } else {
+        const size_t lds = sizeof(double) * WAVE * (split - 1) * 16;
+        SDC_LAUNCH(KID_FMMV_EVAL, (k_fmmv_eval<1, 16>), g, blk, lds, s, it, f, v, q);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace sdc

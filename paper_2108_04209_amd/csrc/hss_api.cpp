@@ -228,16 +228,16 @@ int superdc_hss_conquer(superdc_ctx *ctx, superdc_hss *h, const double *leaf_D,
                                            h->iters + h->idx(l, t), st_t, &o, stream);
             if (rc) return rc;
             if ((e = mark(h, 2, s)) != hipSuccess) return fail(e);
-            rc = superdc_loewner(ctx, b, poles, zc, h->ones, eta_t, org_t, st_t,
-                                 h->zhat + h->idx(l, t), h->bn + h->idx(l, t), &o, stream);
+            // the solve just built the FMM lists of these poles: Loewner/b and the apply reuse them
+            rc = loewner_run(ctx, b, poles, zc, h->ones, eta_t, org_t, st_t,
+                             h->zhat + h->idx(l, t), h->bn + h->idx(l, t), &o, stream, true);
             if (rc) return rc;
             if ((e = mark(h, 3, s)) != hipSuccess) return fail(e);
             const int m = ncol - t - 1;
             if (m > 0) {
-                rc = superdc_cauchy_apply(ctx, b, poles, h->zhat + h->idx(l, t),
-                                          h->bn + h->idx(l, t), eta_t, org_t, st_t, 1, m,
-                                          h->M[cur] + (size_t)(t + 1) * n, n,
-                                          h->M[1 - cur] + (size_t)(t + 1) * n, n, &o, stream);
+                rc = apply_run(ctx, b, poles, h->zhat + h->idx(l, t), h->bn + h->idx(l, t), eta_t,
+                               org_t, st_t, 1, m, h->M[cur] + (size_t)(t + 1) * n, n,
+                               h->M[1 - cur] + (size_t)(t + 1) * n, n, &o, stream, true);
                 if (rc) return rc;
                 if ((e = mark(h, 4, s)) != hipSuccess) return fail(e);
             }

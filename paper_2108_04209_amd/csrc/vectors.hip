@@ -7,10 +7,10 @@
 //
 // The paper evaluates the Loewner products as exponentials of log sums through an FMM
 // (eqs. lowner2, logv).  Here each lane keeps the numerator and denominator products of
-// one pole as separate running products and strips their binary exponents every 8
-// factors (frexp), accumulating the exponents in an integer; one division and one
-// ldexp finish the pole.  No logarithms, and the 8-factor blocks cannot over- or
-// underflow for factors between 2^-120 and 2^120.
+// one pole as separate running products (two interleaved chains each) and strips their
+// binary exponents every 8 factors per chain (frexp), accumulating the exponents in an
+// integer; one division and one ldexp finish the pole.  No logarithms, and the 8-factor
+// blocks cannot over- or underflow for factors between 2^-120 and 2^120.
 #include "common.h"
 
 namespace sdc {
@@ -33,34 +33,49 @@ __device__ __forceinline__ void renorm(double &num, double &den, int &E) {
     den = __builtin_amdgcn_frexp_mant(den);
 }
 
-// products over roots j in [j0, j1); SKIP drops the denominator factor j == i
+// products over roots j in [j0, j1); SKIP drops the denominator factor j == i.
+// Two independent product chains (even and odd roots) keep the multiplies from waiting
+// on each other; roots are read in pointer-stepped blocks of 4 (one scalar address add per
+// block); each chain strips its exponents after every 8 factors.  The latency of the
+// scalar loads is covered by the other wavefronts of the SIMD.
 template <bool SKIP>
 __device__ __forceinline__ void loewner_range(const_double2_ptr ke, const_double_ptr dd,
                                               int j0, int j1,
                                               int i, double di, double &num, double &den,
                                               int &E) {
-#define SDC_LW_BODY(JJ)                                   \
-    {                                                     \
-        const double2 kv = ke[(JJ)];                      \
-        num *= (kv.x - di) + kv.y;                        \
-        const double f = dd[(JJ)] - di;                   \
-        den *= (SKIP && (JJ) == i) ? 1.0 : f;             \
-    }
+    double na = 1.0, da = 1.0, nb = 1.0, db = 1.0;
     int j = j0;
-    for (; j + 8 <= j1; j += 8) {
-        SDC_LW_BODY(j)
-        SDC_LW_BODY(j + 1)
-        SDC_LW_BODY(j + 2)
-        SDC_LW_BODY(j + 3)
-        SDC_LW_BODY(j + 4)
-        SDC_LW_BODY(j + 5)
-        SDC_LW_BODY(j + 6)
-        SDC_LW_BODY(j + 7)
-        renorm(num, den, E);
+    if (j + 4 <= j1) {
+        const_double_ptr kp = ke.p + 2 * (int64_t)j;  // (d_K, eta) pairs
+        const_double_ptr dp = dd + j;
+        int blk = 0;
+        for (; j + 4 <= j1; j += 4, kp += 8, dp += 4) {
+            na *= (kp[0] - di) + kp[1];
+            nb *= (kp[2] - di) + kp[3];
+            na *= (kp[4] - di) + kp[5];
+            nb *= (kp[6] - di) + kp[7];
+            const double f0 = dp[0] - di, f1 = dp[1] - di, f2 = dp[2] - di, f3 = dp[3] - di;
+            da *= (SKIP && j == i) ? 1.0 : f0;
+            db *= (SKIP && j + 1 == i) ? 1.0 : f1;
+            da *= (SKIP && j + 2 == i) ? 1.0 : f2;
+            db *= (SKIP && j + 3 == i) ? 1.0 : f3;
+            if (++blk == 4) {  // 8 factors per chain
+                renorm(na, da, E);
+                renorm(nb, db, E);
+                blk = 0;
+            }
+        }
     }
-    for (; j < j1; ++j) SDC_LW_BODY(j)
+    renorm(na, da, E);  // at most 8 factors per chain since the last strip
+    renorm(nb, db, E);
+    for (; j < j1; ++j) {  // at most 3 more factors per chain after the strip above
+        const double2 kv = ke[j];
+        na *= (kv.x - di) + kv.y;
+        da *= (SKIP && j == i) ? 1.0 : dd[j] - di;
+    }
+    num *= na * nb;  // mantissas in [0.5, 1) times at most 3 factors: no over- or underflow
+    den *= da * db;
     renorm(num, den, E);
-#undef SDC_LW_BODY
 }
 
 // With S = blockDim.x / 64 > 1 wavefronts per tile, wavefront w takes the roots

@@ -86,3 +86,57 @@ def test_large_clustered_fmm_vs_direct(orc):
                             gp.to_dev(rf["status"], torch.int32), gp.to_dev(E.T), trans=0)
     Q = Q.cpu().numpy().T
     assert np.abs(Q.T @ Q - np.eye(len(cols))).max() <= 1e-12
+
+
+# ------------------------------------------------------ eigenvector-side FMM (b, Qhat^T X)
+def _opts(method, persistent=1):
+    from paper_2108_04209_amd import native
+    return native.default_opts(method=method, persistent=persistent)
+
+
+@pytest.mark.parametrize("kind,n,m", [("clustered", 4096, 5), ("uniform", 3000, 16),
+                                      ("clustered", 16384, 20)])
+def test_fmm_vectors_vs_oracle(orc, kind, n, m):
+    """b and Y = Qhat^T X through the FMM (method 2), fed the oracle's (eta, origin), against
+    the oracle: b to 1e-12 relative per entry, sampled rows of Y to 1e-12 sum_i |Qhat_ij X_i|
+    (the FMM's far-field interpolation error is ~5e-15 of that sum), and against the direct
+    MFMA apply to 1e-12 ||X_c||_2 (Qhat is orthogonal).  m = 20 takes two column passes."""
+    from tests import gpu_pipeline as gp
+    batch, X = gen.small_batch([n], seed=63, kind=kind, m=m)
+    pr = batch.problem(0)
+    lam, eta, org, its, st = orc.secular(pr.d, pr.z, pr.rho)
+    zo = orc.loewner(pr.d, pr.z, pr.rho, eta, org)
+    bo = orc.bnorm(pr.d, zo, eta, org)
+    zf, bf = gp.loewner_from(batch, eta, org, opts=_opts(2))
+    assert np.all(np.abs(zf - zo) <= 1e-12 * np.abs(zo))
+    assert np.all(np.abs(bf - bo) <= 1e-12 * np.abs(bo)), np.max(np.abs(bf - bo) / np.abs(bo))
+    Yf = gp.apply_from(batch, zo, bo, eta, org, X, 1, opts=_opts(2))
+    Yd = gp.apply_from(batch, zo, bo, eta, org, X, 1, opts=_opts(1))
+    rng = np.random.default_rng(3)
+    rows = np.unique(np.r_[0, n - 1, rng.choice(n, 62, replace=False)])
+    Yo = orc.cauchy_apply(pr.d, zo, bo, eta, org, X, trans=1, rows=rows)
+    C = 1.0 / ((pr.d[:, None] - pr.d[org[rows]][None, :]) - eta[rows][None, :])
+    Qabs = np.abs(zo[:, None] * C * bo[rows][None, :])
+    tol = 1e-12 * (Qabs.T @ np.abs(X))
+    assert np.all(np.abs(Yf[rows] - Yo) <= tol), np.max(np.abs(Yf[rows] - Yo) / tol)
+    assert np.abs(Yf - Yd).max() <= 1e-12 * np.linalg.norm(X, axis=0).max()
+
+
+@pytest.mark.parametrize("persistent", [1, 0])
+def test_fmm_vectors_mixed_batch(orc, persistent):
+    """FMM problems (n >= 512 under method 2) and direct ones in one call, fed the oracle's
+    (eta, origin): b and Qhat^T X agree with the all-direct path."""
+    from tests import gpu_pipeline as gp
+    batch, X = gen.small_batch([100, 1500, 5000, 64, 2048, 700], seed=64, kind="clustered", m=7)
+    ref = orc.solve_batch(batch, with_vectors=False)
+    eta, org = ref["eta"], ref["origin"]
+    zf, bf = gp.loewner_from(batch, eta, org, opts=_opts(2, persistent))
+    zd, bd = gp.loewner_from(batch, eta, org, opts=_opts(1, persistent))
+    assert np.array_equal(zf, zd)
+    assert np.all(np.abs(bf - bd) <= 1e-12 * np.abs(bd)), np.max(np.abs(bf - bd) / np.abs(bd))
+    Yf = gp.apply_from(batch, zd, bd, eta, org, X, 1, opts=_opts(2, persistent))
+    Yd = gp.apply_from(batch, zd, bd, eta, org, X, 1, opts=_opts(1, persistent))
+    for p in range(batch.nprob):
+        a, e = int(batch.off[p]), int(batch.off[p + 1])
+        nx = np.linalg.norm(X[a:e], axis=0).max()
+        assert np.abs(Yf[a:e] - Yd[a:e]).max() <= 1e-12 * nx, p
