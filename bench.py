@@ -38,7 +38,7 @@ FLOPS_LOEWNER = 5        # per pair: 2 sub, 1 add, 2 mul
 FLOPS_BNORM = 6          # per pair: 2 sub, 1 rcp, 1 mul, 1 fma(2)
 
 
-FMM_CROSSOVER = 16384    # the library's automatic direct/FMM switch (roots per problem)
+FMM_CROSSOVER = 4096     # the library's default direct/FMM switch (roots per problem)
 MFMA_MIN_M = 4           # the library's automatic VALU/MFMA apply switch (columns)
 
 
@@ -122,6 +122,9 @@ def parse():
                     help="with --workload conquer, skip the batched-level and large-problem "
                          "side measurements")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--fmm-crossover", type=int, default=0,
+                    help="problems with at least this many roots use the FMM (0: the "
+                         "library default, %d)" % FMM_CROSSOVER)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 512 MiB device-to-device copy (the reference kernel "
                          "that scales the profiler's FETCH_SIZE / WRITE_SIZE counters)")
@@ -146,7 +149,7 @@ def workload(name):
 class Pipeline:
     """Preallocated device buffers and the four C-ABI calls of one step."""
 
-    def __init__(self, batch, X, persistent, method=0):
+    def __init__(self, batch, X, persistent, method=0, crossover=0):
         import torch
         from paper_2108_04209_amd import native
         self.torch = torch
@@ -166,7 +169,8 @@ class Pipeline:
         self.zb = (torch.empty(tot, dtype=torch.float64, device=dev),
                    torch.empty(tot, dtype=torch.float64, device=dev))
         self.Y = torch.empty_like(self.X)
-        self.opts = native.default_opts(persistent=persistent, method=method)
+        self.opts = native.default_opts(persistent=persistent, method=method,
+                                        fmm_crossover=crossover)
 
     def solve(self):
         self.native.secular_solve(self.ctx, self.b, self.d, self.z, self.rho, opts=self.opts,
@@ -271,7 +275,7 @@ def bench_level(args, name):
     sizes = batch.sizes().astype(np.float64)
     m = X.shape[1]
 
-    pipe = Pipeline(batch, X, persistent=1)
+    pipe = Pipeline(batch, X, persistent=1, crossover=args.fmm_crossover)
     wall_ms, tot_ms, ph = time_steps(pipe, args.steps, args.warmup)
     note(f"{name} batched {float(np.mean(tot_ms)):.2f} ms/step")
     iters = pipe.out["iters"].cpu().numpy().astype(np.float64)
@@ -315,7 +319,7 @@ def bench_level(args, name):
 
     plain_res = None
     if args.plain_steps > 0:
-        plain = Pipeline(batch, X, persistent=0)
+        plain = Pipeline(batch, X, persistent=0, crossover=args.fmm_crossover)
         p_wall, p_tot, p_ph = time_steps(plain, args.plain_steps, 1)
         p_ms = float(np.mean(p_tot))
         plain_res = {"ms_per_step": p_ms, "value": tot / (p_ms * 1e-3),
@@ -330,7 +334,7 @@ def bench_level(args, name):
     torch.cuda.synchronize()
     kt = pipe.native.kernel_times()
     pipe.native.kernel_timing(False)
-    direct = batch.sizes().max() < FMM_CROSSOVER
+    direct = batch.sizes().max() < (args.fmm_crossover or FMM_CROSSOVER)
     kflops = {"k_loewner": FLOPS_LOEWNER * n2, "k_bnorm": FLOPS_BNORM * n2,
               ("k_apply_mfma" if m >= MFMA_MIN_M else "k_apply_valu"): apply_flops}
     if direct:
@@ -441,16 +445,16 @@ def conquer_flops(tree, iters):
     return sec, vec, app
 
 
-def conquer_kernel_flops(tree, iters):
+def conquer_kernel_flops(tree, iters, crossover=FMM_CROSSOVER):
     """Algorithmic FP64 flops per kernel of one conquer (direct-sum kernels only: the FMM
     kernels' work has no pair count), mirroring the library's automatic choices: levels
-    with nodes of at least FMM_CROSSOVER roots solve, normalise and apply Q^T by the FMM."""
+    with nodes of at least `crossover` roots solve, normalise and apply Q^T by the FMM."""
     D, r, n = tree.depth, tree.r, tree.n
     k = dict(k_secular=0.0, k_loewner=0.0, k_bnorm=0.0, k_apply_mfma=0.0, k_apply_valu=0.0)
     for lvl in range(D):
         nl = tree.leaf << (D - lvl)
         k["k_loewner"] += r * FLOPS_LOEWNER * n * nl
-        if nl >= FMM_CROSSOVER:
+        if nl >= crossover:
             continue  # solve, b and the Q^T applies of this level run through the FMM kernels
         k["k_secular"] += FLOPS_PER_PAIR * nl * float(np.sum(1.0 + iters[lvl]))
         k["k_bnorm"] += r * FLOPS_BNORM * n * nl
@@ -496,7 +500,7 @@ def bench_conquer(args):
     dev = torch.device("cuda:0")
     gens = {k: torch.as_tensor(v, dtype=torch.float64, device=dev)
             for k, v in native.pack_hss(tree).items()}
-    opts1 = native.default_opts(persistent=1)
+    opts1 = native.default_opts(persistent=1, fmm_crossover=args.fmm_crossover)
     out = native.hss_conquer(ctx, plan, gens, opts=opts1)
     native.hss_set_timing(plan, True)
 
@@ -559,7 +563,9 @@ def bench_conquer(args):
     torch.cuda.synchronize()
     kt = native.kernel_times()
     native.kernel_timing(False)
-    kernels, roofline = kernel_roofline(kt, conquer_kernel_flops(tree, iters), args.steps,
+    kernels, roofline = kernel_roofline(kt, conquer_kernel_flops(tree, iters,
+                                                                 args.fmm_crossover or FMM_CROSSOVER),
+                                        args.steps,
                                         "conquer")
     native.hss_set_timing(plan, True)
 
@@ -576,7 +582,8 @@ def bench_conquer(args):
 
     plain_res = None
     if args.plain_steps > 0:
-        p_ms, p_ph, _ = timed(native.default_opts(persistent=0), args.plain_steps, 1)
+        p_ms, p_ph, _ = timed(native.default_opts(persistent=0, fmm_crossover=args.fmm_crossover),
+                              args.plain_steps, 1)
         plain_res = {"ms_per_step": p_ms, "value": roots / (p_ms * 1e-3),
                      "phase_ms": p_ph, "steps": args.plain_steps,
                      "launches": "one per node per phase"}

@@ -36,7 +36,7 @@ int opts_check(const superdc_opts *o) {
     if (!(o->stop_c > 0.0) || o->max_iter < 1 || o->max_iter > 200) return SUPERDC_EINVAL;
     if (o->method < 0 || o->method > 2) return SUPERDC_EINVAL;
     if (o->fmm_order != FMM_P) return SUPERDC_EINVAL;
-    if (o->fmm_leaf < 64 || o->fmm_leaf % 64) return SUPERDC_EINVAL;
+    if (o->fmm_leaf < 64 || o->fmm_leaf > 1024 || o->fmm_leaf % 64) return SUPERDC_EINVAL;
     if (o->persistent != 0 && o->persistent != 1) return SUPERDC_EINVAL;
     if (o->apply_kernel < 0 || o->apply_kernel > 2) return SUPERDC_EINVAL;
     if (o->fmm_crossover < 0) return SUPERDC_EINVAL;
@@ -307,13 +307,12 @@ hipError_t fmmv_run(superdc_ctx *ctx, const superdc_batch *b, const FmmPlan *fp,
     if (persistent) {
         it.tiles = fp->leaf_lpt;
         it.ntiles = fp->nitems;
-        return launch_fmmv_eval(it, f, v, fp->split, ctx->queues + Q_FMMV,
-                                persistent_grid(ctx, fp->nitems, std::max(1, 32 / fp->split)), s);
+        return launch_fmmv_eval(it, f, v, fp->split, ctx->queues + Q_FMMV, ctx->num_cu, s);
     }
     for (int q = 0; q < fp->nfmm && e == hipSuccess; ++q) {
         it.tiles = fp->leaf_nat + fp->item_off_h[q];
         it.ntiles = fp->item_off_h[q + 1] - fp->item_off_h[q];
-        e = launch_fmmv_eval(it, f, v, fp->split, nullptr, 0, s);
+        e = launch_fmmv_eval(it, f, v, fp->split, nullptr, ctx->num_cu, s);
     }
     return e;
 }

@@ -119,7 +119,8 @@ enum KernelId : int {
     KID_VALIDATE = 0, KID_FMM_BOXES, KID_FMM_LISTS, KID_SECULAR, KID_SECULAR_FMM, KID_PACK,
     KID_LOEWNER, KID_BNORM, KID_APPLY_MFMA, KID_APPLY_VALU, KID_BWD, KID_BWD_RHO, KID_LEAF,
     KID_MERGE, KID_ASSEMBLE, KID_PERMUTE, KID_LEAF_APPLY, KID_STATUS_OR, KID_FILL,
-    KID_LEAF_VECTORS, KID_FMM_GEOM, KID_FMMV_PACK, KID_FMMV_SOURCES, KID_FMMV_EVAL, KID_COUNT
+    KID_LEAF_VECTORS, KID_FMM_GEOM, KID_FMMV_PACK, KID_FMMV_SOURCES, KID_FMMV_EVAL,
+    KID_FMMV_EVAL_MFMA, KID_COUNT
 };
 
 class TraceScope {
@@ -155,7 +156,7 @@ struct superdc_ctx {
     void *ws[10] = {nullptr};
     size_t ws_cap[10] = {0};
     sdc::Queue *queues = nullptr;  // kNumQueues counters, zeroed at creation
-    int fmm_crossover = 16384;     // automatic method: FMM for problems at least this large
+    int fmm_crossover = 4096;      // automatic method: FMM for problems at least this large (measured)
 };
 
 enum WsSlot {

@@ -102,8 +102,9 @@ hipError_t launch_fmm_build(const FmmArgs &f, hipStream_t s);
 // geometry and interaction lists only (no secular equivalent sources)
 hipError_t launch_fmm_lists(const FmmArgs &f, hipStream_t s);
 hipError_t launch_fmmv_sources(const FmmArgs &f, const FmmVec &v, hipStream_t s);
+// grid: persistent (q != nullptr) launches size themselves from num_cu
 hipError_t launch_fmmv_eval(const SolveArgs &items, const FmmArgs &f, const FmmVec &v, int split,
-                            Queue *q, int grid, hipStream_t s);
+                            Queue *q, int num_cu, hipStream_t s);
 hipError_t launch_secular_fmm(const SolveArgs &a, const FmmArgs &f, int split, Queue *q,
                               int grid, hipStream_t s);
 

@@ -268,6 +268,169 @@ __global__ __launch_bounds__(512) void k_fmmv_eval(SolveArgs it, FmmArgs f, FmmV
     }
 }
 
+// ---------------------------------------------------------------------------------------
+// Y = Qhat^T X through the FMM on MFMA: for a 64-root work item the near poles and the far
+// boxes' equivalent sources form one gathered reduction dimension, and the product
+//     Y_j,c = b_j sum_k 1/((s_k - d_{K_j}) - eta_j) W_k,c
+// (s_k a pole or a Chebyshev node, W_k,c its weight) is the dense contraction of the
+// direct apply: 64-source chunks are staged through LDS (the next chunk's data in
+// registers while the current one is multiplied), each wavefront generates its 16 x 4
+// slices of the Cauchy block and feeds v_mfma_f64_16x16x4f64.  Every source uses the
+// shifted difference, never less accurate than the lambda-form.
+// ---------------------------------------------------------------------------------------
+typedef double v4d_f __attribute__((ext_vector_type(4)));
+constexpr int FV_K = 64;            // sources per chunk
+constexpr int FV_LD = FV_K + 1;
+
+// The chunks of an item (built once per item in LDS): near ranges in 64-pole chunks, then
+// the far boxes 4 at a time (64 equivalent sources).  kind 0: poles [a, a + cnt); kind 1:
+// far boxes fbox[a .. a + cnt).
+// (near ranges are leaves of at most 1024 poles, the largest leaf the options allow)
+constexpr int FV_MAXCH = FMM_NEAR_MAX * (1024 / FV_K) + (2 * FMM_FAR_MAX + 3) / 4;
+
+struct FvStage {
+    double sd;     // source position (threads < 64)
+    double w[4];   // weights: element e = tid + 256 i -> source e % 64, column e / 64
+};
+
+__device__ __forceinline__ void fv_fetch(const FmmVec &v, int64_t base, const int *fbox, int4 ch,
+                                         FvStage &st) {
+    const int tid = threadIdx.x;
+    const int m = v.m;
+    if (ch.x == 0) {
+        if (tid < FV_K) st.sd = tid < ch.z ? v.d[base + ch.y + tid] : 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = tid + 256 * i, sl = e % FV_K, c = e / FV_K;
+            st.w[i] = (sl < ch.z && c < m) ? v.src[(base + ch.y + sl) * m + c] : 0.0;
+        }
+    } else {
+        if (tid < FV_K) {
+            const int bx = tid / FMM_P, qn = tid % FMM_P;
+            st.sd = bx < ch.z ? v.vnode[(int64_t)fbox[ch.y + bx] * FMM_P + qn] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = tid + 256 * i, sl = e % FV_K, c = e / FV_K;
+            const int bx = sl / FMM_P, qn = sl % FMM_P;
+            st.w[i] = (bx < ch.z && c < m)
+                          ? v.vw[((int64_t)fbox[ch.y + bx] * FMM_P + qn) * m + c]
+                          : 0.0;
+        }
+    }
+}
+
+struct FvShared {
+    double Xs[16 * FV_LD];
+    double Sd[FV_K];
+    int4 ctab[FV_MAXCH];
+    int fbox[2 * FMM_FAR_MAX];
+    int nch;
+};
+
+__device__ void fmmv_item_mfma(const SolveArgs &it, const FmmArgs &f, const FmmVec &v, Tile t,
+                               FvShared &sh) {
+    const int p = t.prob;
+    const int64_t base = it.off[p];
+    const int n = (int)(it.off[p + 1] - base);
+    const int lane = lane_id();
+    const int wv = threadIdx.x / WAVE;
+    const int o0 = t.row0;
+    const int m = v.m;
+    if (f.status[p] & ~SUPERDC_ST_NOCONV) {
+        const double nan = __builtin_nan("");
+        for (int e = threadIdx.x; e < FV_K * m; e += blockDim.x) {
+            const int r = o0 + (e % FV_K), c = e / FV_K;
+            if (r < n) v.Y[base + r + (int64_t)c * v.ldy] = nan;
+        }
+        return;
+    }
+    const int qf = f.fmm_of[p];
+    const int L = wave_uniform(f.leaf_off[qf] + t.row0 / f.leaf);
+    const int nn = wave_uniform(f.cnt[3 * (int64_t)L]);
+    const bool direct = nn < 0;  // overflowed lists: every pole, 64 at a time
+    __syncthreads();  // the previous item's reads of the tables are done
+    if (!direct) {
+        const int nl = f.cnt[3 * (int64_t)L + 1], nr = f.cnt[3 * (int64_t)L + 2];
+        for (int e = threadIdx.x; e < nl + nr; e += blockDim.x)
+            sh.fbox[e] = e < nl ? f.far_l[(int64_t)L * FMM_FAR_MAX + e]
+                                : f.far_r[(int64_t)L * FMM_FAR_MAX + e - nl];
+        if (threadIdx.x == 0) {
+            int c = 0;
+            for (int e = 0; e < nn; ++e) {
+                const int lo = f.near_lo[(int64_t)L * FMM_NEAR_MAX + e];
+                const int hi = f.near_hi[(int64_t)L * FMM_NEAR_MAX + e];
+                for (int a = lo; a < hi; a += FV_K) sh.ctab[c++] = make_int4(0, a, min(FV_K, hi - a), 0);
+            }
+            for (int a = 0; a < nl + nr; a += 4) sh.ctab[c++] = make_int4(1, a, min(4, nl + nr - a), 0);
+            sh.nch = c;
+        }
+    } else if (threadIdx.x == 0) {
+        sh.nch = (n + FV_K - 1) / FV_K;
+    }
+    __syncthreads();
+    const int nch = wave_uniform(sh.nch);
+    auto chunk = [&](int ci) -> int4 {
+        return direct ? make_int4(0, ci * FV_K, min(FV_K, n - ci * FV_K), 0) : sh.ctab[ci];
+    };
+    // the root of the Cauchy rows this lane generates: row o0 + 16 wv + lane%16
+    const int orow = o0 + wv * 16 + (lane & 15);
+    const bool ovalid = orow < n;
+    const int oc = ovalid ? orow : n - 1;
+    const double ra = v.d[base + clamp_idx(v.origin[base + oc], n)];
+    const double rb = v.eta[base + oc];
+    v4d_f acc = v4d_f{0.0, 0.0, 0.0, 0.0};
+    FvStage st;
+    int4 cur = chunk(0);
+    fv_fetch(v, base, sh.fbox, cur, st);
+    for (int ci = 0; ci < nch; ++ci) {
+        __syncthreads();  // the previous chunk's reads of Xs/Sd are done
+        if (threadIdx.x < FV_K) sh.Sd[threadIdx.x] = st.sd;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = threadIdx.x + 256 * i;
+            sh.Xs[(e / FV_K) * FV_LD + e % FV_K] = st.w[i];
+        }
+        __syncthreads();
+        const int nvalid = wave_uniform(cur.x == 0 ? cur.z : cur.z * FMM_P);
+        if (ci + 1 < nch) {
+            cur = chunk(ci + 1);
+            fv_fetch(v, base, sh.fbox, cur, st);  // in flight during the multiply below
+        }
+#pragma unroll 4
+        for (int kk = 0; kk < FV_K; kk += 4) {
+            const int sl = kk + (lane >> 4);
+            const double tt = (sh.Sd[sl] - ra) - rb;
+            const double av = (ovalid && sl < nvalid) ? rcp_nr(tt) : 0.0;
+            const double bv = sh.Xs[(lane & 15) * FV_LD + sl];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+    }
+    // v_mfma_f64_16x16x4f64 returns D[4 r + lane/16][lane % 16] in accumulator r
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = o0 + wv * 16 + 4 * r + (lane >> 4);
+        const int col = lane & 15;
+        if (row < n && col < m) v.Y[base + row + (int64_t)col * v.ldy] = v.post[base + row] * acc[r];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fmmv_eval_mfma(SolveArgs it, FmmArgs f, FmmVec v,
+                                                        Queue *q) {
+    __shared__ FvShared sh;
+    __shared__ int slot;
+    if (q) {
+        for (;;) {
+            const int item = queue_pull(q, it.ntiles, &slot);
+            if (item < 0) break;
+            fmmv_item_mfma(it, f, v, it.tiles[item], sh);
+        }
+        queue_leave(q);
+    } else if ((int)blockIdx.x < it.ntiles) {
+        fmmv_item_mfma(it, f, v, it.tiles[blockIdx.x], sh);
+    }
+}
+
 hipError_t launch_fmmv_pack(const FmmvPackArgs &a, const FmmVec &v, hipStream_t s) {
     if (a.ntiles <= 0) return hipSuccess;
     SDC_LAUNCH(KID_FMMV_PACK, k_fmmv_pack, dim3(a.ntiles), dim3(64), 0, s, a, v);
@@ -282,18 +445,20 @@ hipError_t launch_fmmv_sources(const FmmArgs &f, const FmmVec &v, hipStream_t s)
 }
 
 hipError_t launch_fmmv_eval(const SolveArgs &it, const FmmArgs &f, const FmmVec &v, int split,
-                            Queue *q, int grid, hipStream_t s) {
+                            Queue *q, int num_cu, hipStream_t s) {
     if (it.ntiles <= 0) return hipSuccess;
-    const dim3 g(q ? grid : it.ntiles), blk(WAVE * split);
+    if (v.kern == 1 && v.m >= 4) {  // a dense enough block of columns for the MFMA
+        const dim3 g(q ? min(it.ntiles, num_cu * 4) : it.ntiles);
+        SDC_LAUNCH(KID_FMMV_EVAL_MFMA, k_fmmv_eval_mfma, g, dim3(256), 0, s, it, f, v, q);
+        return hipGetLastError();
+    }
+    const dim3 g(q ? min(it.ntiles, num_cu * max(1, 32 / split)) : it.ntiles), blk(WAVE * split);
     if (v.kern == 2) {
         const size_t lds = sizeof(double) * WAVE * (split - 1) * 1;
         SDC_LAUNCH(KID_FMMV_EVAL, (k_fmmv_eval<2, 1>), g, blk, lds, s, it, f, v, q);
-    } else if (v.m <= 8) {
+    } else {
         const size_t lds = sizeof(double) * WAVE * (split - 1) * 8;
         SDC_LAUNCH(KID_FMMV_EVAL, (k_fmmv_eval<1, 8>), g, blk, lds, s, it, f, v, q);
-    } else {
-        const size_t lds = sizeof(double) * WAVE * (split - 1) * 16;
-        SDC_LAUNCH(KID_FMMV_EVAL, (k_fmmv_eval<1, 16>), g, blk, lds, s, it, f, v, q);
     }
     return hipGetLastError();
 }

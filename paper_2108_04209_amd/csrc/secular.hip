@@ -231,8 +231,8 @@ __device__ __forceinline__ void split_reduce4(double *red, int S, double &a, dou
     d = s.w;
 }
 
-// The same sums from the triangular FMM lists of target leaf L: near leaves directly in
-// shifted form (routed by the window as above), far boxes through their equivalent
+// The same sums from the triangular FMM lists of target leaf L: near leaves directly
+// (routed by the window as above), far boxes through their equivalent
 // sources in lambda-form, left boxes into psi and right boxes into phi.  With S wavefronts
 // per work item, wavefront wv takes the wv-th of S contiguous parts of every near range
 // and the far boxes e = wv (mod S).
@@ -246,15 +246,21 @@ __device__ __forceinline__ void fmm_sums(const FmmArgs &f, int L, int nn, int nl
     wv = wave_uniform(wv);
     psi = dpsi = phi = dphi = 0.0;
     const double x = dK + y;
+    // near leaves: the same window split as the direct sums, so only poles within one tile
+    // of the live roots take the shifted form
+    const int f0 = kmin - TILE, f1 = kmax + 1 + TILE;
     for (int e = 0; e < nn; ++e) {
         const int lo0 = wave_uniform(f.near_lo[(int64_t)L * FMM_NEAR_MAX + e]);
         const int hi0 = wave_uniform(f.near_hi[(int64_t)L * FMM_NEAR_MAX + e]);
         const int lo = lo0 + (int)(((int64_t)(hi0 - lo0) * wv) / S);
         const int hi = lo0 + (int)(((int64_t)(hi0 - lo0) * (wv + 1)) / S);
-        secular_range<0, false>(dw, lo, min(hi, kmin), k, dK, y, x, psi, dpsi, phi, dphi);
+        secular_range<0, true>(dw, lo, min(hi, f0), k, dK, y, x, psi, dpsi, phi, dphi);
+        secular_range<0, false>(dw, max(lo, f0), min(hi, kmin), k, dK, y, x, psi, dpsi, phi, dphi);
         secular_range<2, false>(dw, max(lo, kmin), min(hi, kmax + 1), k, dK, y, x, psi, dpsi, phi,
                                 dphi);
-        secular_range<1, false>(dw, max(lo, kmax + 1), hi, k, dK, y, x, psi, dpsi, phi, dphi);
+        secular_range<1, false>(dw, max(lo, kmax + 1), min(hi, f1), k, dK, y, x, psi, dpsi, phi,
+                                dphi);
+        secular_range<1, true>(dw, max(lo, f1), hi, k, dK, y, x, psi, dpsi, phi, dphi);
     }
     for (int e = wv; e < nl; e += S) {
         const int g = wave_uniform(f.far_l[(int64_t)L * FMM_FAR_MAX + e]);

@@ -46,7 +46,8 @@ const char *kNames[KID_COUNT] = {
     "k_validate", "k_fmm_boxes", "k_fmm_lists", "k_secular", "k_secular_fmm", "k_pack_ke",
     "k_loewner", "k_bnorm", "k_apply_mfma", "k_apply_valu", "k_bwd", "k_bwd_rho",
     "k_leaf_jacobi", "k_merge", "k_assemble", "k_permute", "k_leaf_apply", "k_status_or",
-    "k_fill", "k_leaf_vectors", "k_fmm_geom", "k_fmmv_pack", "k_fmmv_sources", "k_fmmv_eval"};
+    "k_fill", "k_leaf_vectors", "k_fmm_geom", "k_fmmv_pack", "k_fmmv_sources", "k_fmmv_eval",
+    "k_fmmv_eval_mfma"};
 
 }  // namespace
 
