@@ -208,7 +208,9 @@ FmmPlan *fmm_plan(superdc_batch *b, int leaf, int crossover) {
               fmm_upload(fp, &fp->vnode, std::vector<double>(), (size_t)fp->nboxes * FMM_P) &&
               fmm_upload(fp, &fp->vw, std::vector<double>(),
                          (size_t)fp->nboxes * FMM_P * FMMV_MAX_M) &&
-              fmm_upload(fp, &fp->tail, std::vector<double>(), b->nprob);
+              fmm_upload(fp, &fp->tail, std::vector<double>(), b->nprob) &&
+              fmm_upload(fp, &fp->lgeo, std::vector<double2>(), fp->nboxes) &&
+              fmm_upload(fp, &fp->lmom, std::vector<double>(), (size_t)fp->nboxes * FMML_K);
     // direct chunks of the other problems, for each cut length
     fp->dir_lpt.assign(4, nullptr);
     fp->dir_count.assign(4, 0);
@@ -374,18 +376,22 @@ int loewner_run(superdc_ctx *ctx, const superdc_batch *b, const double *d, const
     superdc_batch *bm = const_cast<superdc_batch *>(b);
     const TileList *L = tile_list(bm, TILE);
     if (!L) return SUPERDC_ENOMEM;
-    // large problems: b by the eigenvector-side FMM, the others by direct sums
+    // large problems: zhat and b through the FMM (far boxes by moment expansions of the
+    // Loewner log-sums and by equivalent sources for b), the others by direct products/sums
     int rc;
     FmmPlan *fp = fmm_for(ctx, bm, o, rc);
     if (rc) return rc;
     FmmvPackArgs pk{};
     FmmVec v{};
     FmmArgs f{};
+    FmmlArgs lf{};
     if (fp) {
         double2 *pairs = (double2 *)ws_get(ctx, WS_VPAIR, sizeof(double2) * b->total);
         double *src = (double *)ws_get(ctx, WS_VSRC, sizeof(double) * b->total);
         if (!pairs || !src) return SUPERDC_ENOMEM;
         pk.off = b->off_d;
+        pk.tiles = fp->leaf_nat;
+        pk.ntiles = fp->nitems;
         pk.d = d;
         pk.zhat = zhat;
         pk.eta = eta;
@@ -402,30 +408,55 @@ int loewner_run(superdc_ctx *ctx, const superdc_batch *b, const double *d, const
         v.eta = eta;
         v.bout = bnorm;
         f = fmm_vec_args(fp, b, pairs, status);
+        lf.pd = pairs;
+        lf.geo = fp->lgeo;
+        lf.mom = fp->lmom;
+        // (d_j, delta_j) pairs, the lists of these poles (unless the solve left them), the
+        // Loewner moments of every leaf and used box
+        SDC_HIP(launch_fmml_pack(pk, s));
+        if (!reuse_lists) SDC_HIP(launch_fmm_lists(f, s));
+        SDC_HIP(launch_fmml_moments(f, lf, s));
     }
+    a.tiles = L->lpt;
+    a.ntiles = L->count;
+    SDC_HIP(launch_pack_ke(a, s));
     if (o.persistent) {
-        a.tiles = L->lpt;
-        a.ntiles = L->count;
         const int S = b->vec.split;
-        const int g = persistent_grid(ctx, L->count, std::max(1, 32 / S));
-        SDC_HIP(launch_loewner(a, S, ctx->queues + Q_LOEWNER, g, s));
         if (fp) {
             a.tiles = fp->dir_lpt[0];
             a.ntiles = fp->dir_count[0];
         }
+        SDC_HIP(launch_loewner(a, S, ctx->queues + Q_LOEWNER,
+                               persistent_grid(ctx, a.ntiles, std::max(1, 32 / S)), s, false));
+        if (fp) {
+            VecArgs af = a;
+            af.tiles = fp->leaf_lpt;
+            af.ntiles = fp->nitems;
+            SDC_HIP(launch_loewner_fmm(af, f, lf, fp->split, ctx->queues + Q_LOEWNER,
+                                       persistent_grid(ctx, af.ntiles, std::max(1, 32 / fp->split)),
+                                       s));
+        }
         SDC_HIP(launch_bnorm(a, S, ctx->queues + Q_BNORM,
                              persistent_grid(ctx, a.ntiles, std::max(1, 32 / S)), s));
-        if (fp) SDC_HIP(fmmv_run(ctx, b, fp, f, pk, v, !reuse_lists, true, s));
+        if (fp) SDC_HIP(fmmv_run(ctx, b, fp, f, pk, v, false, true, s));
     } else {
         for (int p = 0; p < b->nprob; ++p) {
             const int64_t np = b->off_h[p + 1] - b->off_h[p];
             const int S = shape_for(ctx, &np, 1, TILE).split;
+            if (fp && fp->fmm_of_h[p] >= 0) {
+                const int q = fp->fmm_of_h[p];
+                VecArgs af = a;
+                af.tiles = fp->leaf_nat + fp->item_off_h[q];
+                af.ntiles = fp->item_off_h[q + 1] - fp->item_off_h[q];
+                SDC_HIP(launch_loewner_fmm(af, f, lf, fp->split, nullptr, 0, s));
+                continue;
+            }
             a.tiles = L->nat + L->begin[p];
             a.ntiles = L->begin[p + 1] - L->begin[p];
-            SDC_HIP(launch_loewner(a, S, nullptr, 0, s));
-            if (!fp || fp->fmm_of_h[p] < 0) SDC_HIP(launch_bnorm(a, S, nullptr, 0, s));
+            SDC_HIP(launch_loewner(a, S, nullptr, 0, s, false));
+            SDC_HIP(launch_bnorm(a, S, nullptr, 0, s));
         }
-        if (fp) SDC_HIP(fmmv_run(ctx, b, fp, f, pk, v, !reuse_lists, false, s));
+        if (fp) SDC_HIP(fmmv_run(ctx, b, fp, f, pk, v, false, false, s));
     }
     return SUPERDC_OK;
 }

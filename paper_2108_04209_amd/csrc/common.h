@@ -120,7 +120,7 @@ enum KernelId : int {
     KID_LOEWNER, KID_BNORM, KID_APPLY_MFMA, KID_APPLY_VALU, KID_BWD, KID_BWD_RHO, KID_LEAF,
     KID_MERGE, KID_ASSEMBLE, KID_PERMUTE, KID_LEAF_APPLY, KID_STATUS_OR, KID_FILL,
     KID_LEAF_VECTORS, KID_FMM_GEOM, KID_FMMV_PACK, KID_FMMV_SOURCES, KID_FMMV_EVAL,
-    KID_FMMV_EVAL_MFMA, KID_COUNT
+    KID_FMMV_EVAL_MFMA, KID_FMML_PACK, KID_FMML_MOMENTS, KID_LOEWNER_FMM, KID_COUNT
 };
 
 class TraceScope {
@@ -252,7 +252,10 @@ struct VecArgs {
     double2 *dz;   // workspace (d_i, zhat_i) per pole
     double *zhat, *bnorm;
 };
-hipError_t launch_loewner(const VecArgs &a, int split, Queue *q, int grid, hipStream_t s);
+// pack = false: the (d_K, eta) pairs were packed already (launch_pack_ke)
+hipError_t launch_loewner(const VecArgs &a, int split, Queue *q, int grid, hipStream_t s,
+                          bool pack = true);
+hipError_t launch_pack_ke(const VecArgs &a, hipStream_t s);
 hipError_t launch_bnorm(const VecArgs &a, int split, Queue *q, int grid, hipStream_t s);
 
 struct ApplyArgs {

@@ -61,6 +61,8 @@ struct FmmPlan {
     int32_t *used = nullptr;           // [nboxes]
     double *vnode = nullptr, *vw = nullptr;  // eigenvector-side equivalent sources
     double *tail = nullptr;            // [nprob] per-call bound of the last root
+    double2 *lgeo = nullptr;           // Loewner far field: box geometry and moments
+    double *lmom = nullptr;
     std::vector<void *> allocs;
 };
 
@@ -83,6 +85,23 @@ struct FmmVec {
 };
 constexpr int FMMV_MAX_M = 16;
 
+// Loewner far field (Sec. 4.3, eqs. lowner2 and logv with local shifting): for a far box B
+// and a pole x outside it,
+//     G_B(x) = sum_{j in B} log((lambda_j - x) / (d_j - x))
+//            = sum_{k >= 1} (-1)^(k+1) M_k r^k / k,   r = hw / (c - x),
+// with the box's centre c and half-width hw (its span covers its poles and roots) and the
+// moments M_k = sum_j ((t_j + D_j)^k - t_j^k), t_j = (d_j - c) / hw, D_j = delta_j / hw,
+// delta_j = lambda_j - d_j.  Every moment is a sum of terms proportional to delta_j, so no
+// cancellation: P_1 = D, P_{k+1} = (t + D) P_k + D t^k.
+constexpr int FMML_K = 28;  // moments per box (|r| <= 1/4 at separation 1.5: 0.25^28 ~ 1e-17)
+
+struct FmmlArgs {
+    const double2 *pd;        // (d_j, delta_j) per entry (pole and its root's offset)
+    double2 *geo;             // [boxes] (c, hw)
+    double *mom;              // [boxes][FMML_K] moments M_1 .. M_K
+};
+hipError_t launch_fmml_moments(const FmmArgs &f, const FmmlArgs &l, hipStream_t s);
+
 // packing of the source weights of the FMM problems (and the list geometry)
 struct FmmvPackArgs {
     const int64_t *off;
@@ -97,6 +116,11 @@ struct FmmvPackArgs {
     double *tail;        // [nprob] lambda_{n-1} - d_{n-1}
 };
 hipError_t launch_fmmv_pack(const FmmvPackArgs &a, const FmmVec &v, hipStream_t s);
+// Loewner far field: (d_j, delta_j) pairs and the last roots' offsets, then the products
+hipError_t launch_fmml_pack(const FmmvPackArgs &a, hipStream_t s);
+hipError_t launch_loewner_fmm(const VecArgs &a, const FmmArgs &f, const FmmlArgs &l, int split,
+                              Queue *q, int grid, hipStream_t s);
+
 
 hipError_t launch_fmm_build(const FmmArgs &f, hipStream_t s);
 // geometry and interaction lists only (no secular equivalent sources)

@@ -431,6 +431,114 @@ __global__ __launch_bounds__(256) void k_fmmv_eval_mfma(SolveArgs it, FmmArgs f,
     }
 }
 
+// ---------------------------------------------------------------------------------------
+// Loewner far field: box moments.  LEAVES = true: every leaf from its poles and roots;
+// LEAVES = false: every used box above the leaves from its leaves' moments, translated to
+// the box's centre and half-width (t_box = alpha + beta t_leaf):
+//     M_k = sum_m C(k, m) alpha^(k-m) beta^m M_m(leaf),  T_k(m) = alpha T_{k-1}(m) + beta T_{k-1}(m-1)
+// (M_0 = 0: each pole-root pair carries opposite unit charges).  One workgroup per box; the
+// per-thread partial moments are added by a fixed-order tree in LDS.
+// ---------------------------------------------------------------------------------------
+template <bool LEAVES>
+__global__ __launch_bounds__(256) void k_fmml_moments(FmmArgs f, FmmlArgs l) {
+    __shared__ double part[256][FMML_K + 1];
+    const int g = blockIdx.x;
+    const int qf = f.box_fmm[g];
+    const int p = f.fmm_prob[qf];
+    const int64_t base = f.off[p];
+    const int n = (int)(f.off[p + 1] - base);
+    const int hidx = g - f.box_off[qf];
+    const int H = f.height[qf];
+    int h = 0;
+    while ((2 << h) - 1 <= hidx) ++h;
+    if (LEAVES ? (h != H) : (h == H || !f.used[g])) return;  // uniform for the workgroup
+    if (f.status[p] & ~SUPERDC_ST_NOCONV) return;
+    const int bi = hidx - ((1 << h) - 1);
+    const int64_t span = (int64_t)f.leaf << (H - h);
+    const int lo = (int)min((int64_t)n, bi * span), hi = (int)min((int64_t)n, (bi + 1) * span);
+    if (lo >= hi) return;
+    const double2 *pd = l.pd + base;
+    const double a = pd[lo].x, b = pd[hi - 1].x + pd[hi - 1].y;  // poles and roots of the box
+    const double c = 0.5 * (a + b), hw = 0.5 * (b - a), ihw = 1.0 / hw;
+    const int tid = threadIdx.x;
+    double M[FMML_K];
+#pragma unroll
+    for (int k = 0; k < FMML_K; ++k) M[k] = 0.0;
+    if (LEAVES) {
+        for (int j = lo + tid; j < hi; j += blockDim.x) {
+            const double t = (pd[j].x - c) * ihw, D = pd[j].y * ihw, tD = t + D;
+            double P = D, tk = 1.0;
+#pragma unroll
+            for (int k = 0; k < FMML_K; ++k) {
+                M[k] += P;  // P = (t + D)^(k+1) - t^(k+1)
+                tk *= t;
+                P = __builtin_fma(tD, P, D * tk);
+            }
+        }
+    } else {
+        const int leaf0 = (1 << H) - 1 + bi * (1 << (H - h));
+        const int nleaf = (int)((hi - lo + f.leaf - 1) / f.leaf);
+        for (int e = tid; e < nleaf; e += blockDim.x) {
+            const int gl = f.box_off[qf] + leaf0 + e;
+            const double2 gc = l.geo[gl];
+            const double al = (gc.x - c) * ihw, be = gc.y * ihw;
+            const double *Ml = l.mom + (int64_t)gl * FMML_K;
+            double T[FMML_K + 1];  // T[m] = C(k, m) alpha^(k-m) beta^m for the current k
+            T[0] = 1.0;
+#pragma unroll
+            for (int m = 1; m <= FMML_K; ++m) T[m] = 0.0;
+#pragma unroll
+            for (int k = 1; k <= FMML_K; ++k) {
+#pragma unroll
+                for (int m = FMML_K; m >= 1; --m)
+                    if (m <= k) T[m] = __builtin_fma(al, T[m], be * T[m - 1]);
+                T[0] *= al;
+                double s2 = 0.0;
+#pragma unroll
+                for (int m = 1; m <= FMML_K; ++m)
+                    if (m <= k) s2 = __builtin_fma(T[m], Ml[m - 1], s2);
+                M[k - 1] += s2;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < FMML_K; ++k) part[tid][k] = M[k];
+    __syncthreads();
+    for (int stride = blockDim.x / 2; stride > 0; stride >>= 1) {
+        if (tid < stride)
+            for (int k = 0; k < FMML_K; ++k) part[tid][k] += part[tid + stride][k];
+        __syncthreads();
+    }
+    if (tid < FMML_K) l.mom[(int64_t)g * FMML_K + tid] = part[0][tid];
+    if (tid == 0) l.geo[g] = make_double2(c, hw);
+}
+
+hipError_t launch_fmml_moments(const FmmArgs &f, const FmmlArgs &l, hipStream_t s) {
+    if (f.nboxes <= 0) return hipSuccess;
+    SDC_LAUNCH(KID_FMML_MOMENTS, k_fmml_moments<true>, dim3(f.nboxes), dim3(256), 0, s, f, l);
+    SDC_LAUNCH(KID_FMML_MOMENTS, k_fmml_moments<false>, dim3(f.nboxes), dim3(256), 0, s, f, l);
+    return hipGetLastError();
+}
+
+// (d_j, delta_j) with delta_j = lambda_j - d_j = (d_{K_j} - d_j) + eta_j; one lane per entry
+__global__ __launch_bounds__(64) void k_fmml_pack(FmmvPackArgs a) {
+    const Tile t = a.tiles[blockIdx.x];
+    const int64_t base = a.off[t.prob];
+    const int n = (int)(a.off[t.prob + 1] - base);
+    const int j = t.row0 + lane_id();
+    if (j >= n) return;
+    const double dj = a.d[base + j];
+    const double delta = (a.d[base + clamp_idx(a.origin[base + j], n)] - dj) + a.eta[base + j];
+    a.pairs[base + j] = make_double2(dj, delta);
+    if (j == n - 1) a.tail[t.prob] = delta;
+}
+
+hipError_t launch_fmml_pack(const FmmvPackArgs &a, hipStream_t s) {
+    if (a.ntiles <= 0) return hipSuccess;
+    SDC_LAUNCH(KID_FMML_PACK, k_fmml_pack, dim3(a.ntiles), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_fmmv_pack(const FmmvPackArgs &a, const FmmVec &v, hipStream_t s) {
     if (a.ntiles <= 0) return hipSuccess;
     SDC_LAUNCH(KID_FMMV_PACK, k_fmmv_pack, dim3(a.ntiles), dim3(64), 0, s, a, v);

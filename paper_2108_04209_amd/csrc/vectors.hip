@@ -12,6 +12,7 @@
 // integer; one division and one ldexp finish the pole.  No logarithms, and the 8-factor
 // blocks cannot over- or underflow for factors between 2^-120 and 2^120.
 #include "common.h"
+#include "fmm.h"
 
 namespace sdc {
 
@@ -136,6 +137,119 @@ __device__ void loewner_tile(const VecArgs &a, Tile t, double4 *red) {
     }
 }
 
+// ---------------------------------------------------------------------------------------
+// Loewner products of the FMM problems: the near leaves of the lists exactly (the same
+// renormalised products), the far boxes through their moment expansions
+//     sum_{j in B} log((lambda_j - d_i) / (d_j - d_i)) = sum_k (-1)^(k+1) M_k r^k / k,
+//     r = hw / (c - d_i),
+// with a direct product over the box for the rare pole where |r| > 0.35.  Work items are
+// 64-pole pieces of the target leaves; S wavefronts split the lists.
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ double lw_series(const double *M, double r) {
+    // Horner from the top: sum_{k=1}^{K} (-1)^(k+1) M_k r^k / k
+    double acc = 0.0;
+#pragma unroll
+    for (int k = FMML_K; k >= 1; --k) {
+        const double ck = ((k & 1) ? 1.0 : -1.0) / (double)k;
+        acc = __builtin_fma(acc, r, ck * M[k - 1]);
+    }
+    return acc * r;
+}
+
+__device__ void loewner_fmm_tile(const VecArgs &a, const FmmArgs &f, const FmmlArgs &l, Tile t,
+                                 double4 *red) {
+    const int p = t.prob;
+    const int64_t base = a.off[p];
+    const int n = (int)(a.off[p + 1] - base);
+    const int i = t.row0 + lane_id();
+    const bool active = i < n;
+    const int S = blockDim.x / WAVE, wv = wave_uniform((int)(threadIdx.x / WAVE));
+    if (a.status[p] & ~SUPERDC_ST_NOCONV) {
+        if (active && wv == 0) {
+            const double nan = __builtin_nan("");
+            a.zhat[base + i] = nan;
+            a.dz[base + i] = make_double2(a.d[base + i], nan);
+        }
+        return;
+    }
+    const int ii = active ? i : n - 1;
+    const_double2_ptr ke = as_const(a.ke + base);  // written by k_pack_ke
+    const_double_ptr dd = as_const(a.d + base);
+    const double di = a.d[base + ii];
+    double num = 1.0, den = 1.0, far = 0.0;
+    int E = 0;
+    const int qf = f.fmm_of[p];
+    const int L = wave_uniform(f.leaf_off[qf] + t.row0 / f.leaf);
+    const int nn = wave_uniform(f.cnt[3 * (int64_t)L]);
+    const int t0 = t.row0, t1 = wave_uniform(min(t.row0 + TILE, n));
+    // exact products over [lo, hi), the poles of this item dropping their own factor
+    auto exact = [&](int lo, int hi) {
+        loewner_range<false>(ke, dd, lo, min(hi, t0), ii, di, num, den, E);
+        loewner_range<true>(ke, dd, max(lo, t0), min(hi, t1), ii, di, num, den, E);
+        loewner_range<false>(ke, dd, max(lo, t1), hi, ii, di, num, den, E);
+    };
+    if (nn < 0) {
+        exact(wave_uniform((int)(((int64_t)n * wv) / S)),
+              wave_uniform((int)(((int64_t)n * (wv + 1)) / S)));
+    } else {
+        for (int e = 0; e < nn; ++e) {
+            const int lo0 = wave_uniform(f.near_lo[(int64_t)L * FMM_NEAR_MAX + e]);
+            const int hi0 = wave_uniform(f.near_hi[(int64_t)L * FMM_NEAR_MAX + e]);
+            exact(lo0 + (int)(((int64_t)(hi0 - lo0) * wv) / S),
+                  lo0 + (int)(((int64_t)(hi0 - lo0) * (wv + 1)) / S));
+        }
+        const int nl = wave_uniform(f.cnt[3 * (int64_t)L + 1]);
+        const int nr = wave_uniform(f.cnt[3 * (int64_t)L + 2]);
+        for (int e = wv; e < nl + nr; e += S) {
+            const int g = wave_uniform(e < nl ? f.far_l[(int64_t)L * FMM_FAR_MAX + e]
+                                              : f.far_r[(int64_t)L * FMM_FAR_MAX + e - nl]);
+            const double2 gc = l.geo[g];
+            const double r = gc.y / (gc.x - di);
+            if (fabs(r) <= 0.35) {
+                far += lw_series(l.mom + (int64_t)g * FMML_K, r);
+            } else {  // too close for the expansion: the box's exact products for this lane
+                const int hidx = g - f.box_off[qf];
+                const int H = f.height[qf];
+                int h = 0;
+                while ((2 << h) - 1 <= hidx) ++h;
+                const int bi = hidx - ((1 << h) - 1);
+                const int64_t span = (int64_t)f.leaf << (H - h);
+                const int lo = (int)min((int64_t)n, bi * span);
+                const int hi = (int)min((int64_t)n, (bi + 1) * span);
+                for (int j = lo; j < hi; ++j) {  // j != i: a far box never holds pole i
+                    const double2 kv = ke[j];
+                    num *= (kv.x - di) + kv.y;
+                    den *= dd[j] - di;
+                    if ((j & 7) == 7) renorm(num, den, E);
+                }
+                renorm(num, den, E);
+            }
+        }
+    }
+    if (S > 1) {
+        red[wv * WAVE + lane_id()] = make_double4(num, den, (double)E, far);
+        __syncthreads();
+        if (wv == 0) {
+            for (int w = 1; w < S; ++w) {
+                const double4 v = red[w * WAVE + lane_id()];
+                num *= v.x;
+                den *= v.y;
+                E += (int)v.z;
+                far += v.w;
+                renorm(num, den, E);
+            }
+        }
+        __syncthreads();
+    }
+    if (active && wv == 0) {
+        const double R = ldexp((num / den) * exp(far), E);
+        const double zi = a.z[base + i];
+        const double zh = copysign(sqrt(R / a.rho[p]), zi);
+        a.zhat[base + i] = zh;
+        a.dz[base + i] = make_double2(di, zh);
+    }
+}
+
 __device__ void bnorm_tile(const VecArgs &a, Tile t, double4 *red) {
     const int p = t.prob;
     const int64_t base = a.off[p];
@@ -229,10 +343,41 @@ __global__ __launch_bounds__(1024) void k_bnorm(VecArgs a, Queue *q) {
     }
 }
 
-hipError_t launch_loewner(const VecArgs &a, int split, Queue *q, int grid, hipStream_t s) {
+__global__ __launch_bounds__(1024) void k_loewner_fmm(VecArgs a, FmmArgs f, FmmlArgs l, Queue *q) {
+    extern __shared__ double4 red4[];
+    __shared__ int slot;
+    if (q) {
+        for (;;) {
+            const int item = queue_pull(q, a.ntiles, &slot);
+            if (item < 0) break;
+            loewner_fmm_tile(a, f, l, a.tiles[item], red4);
+        }
+        queue_leave(q);
+    } else if ((int)blockIdx.x < a.ntiles) {
+        loewner_fmm_tile(a, f, l, a.tiles[blockIdx.x], red4);
+    }
+}
+
+hipError_t launch_pack_ke(const VecArgs &a, hipStream_t s) {
+    if (a.ntiles <= 0) return hipSuccess;
+    SDC_LAUNCH(KID_PACK, k_pack_ke, dim3(a.ntiles), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_loewner_fmm(const VecArgs &a, const FmmArgs &f, const FmmlArgs &l, int split,
+                              Queue *q, int grid, hipStream_t s) {
     if (a.ntiles <= 0) return hipSuccess;
     const size_t lds = split > 1 ? sizeof(double4) * WAVE * split : 0;
-    SDC_LAUNCH(KID_PACK, k_pack_ke, dim3(a.ntiles), dim3(64), 0, s, a);
+    SDC_LAUNCH(KID_LOEWNER_FMM, k_loewner_fmm, dim3(q ? grid : a.ntiles), dim3(WAVE * split), lds,
+               s, a, f, l, q);
+    return hipGetLastError();
+}
+
+hipError_t launch_loewner(const VecArgs &a, int split, Queue *q, int grid, hipStream_t s,
+                          bool pack) {
+    if (a.ntiles <= 0) return hipSuccess;
+    const size_t lds = split > 1 ? sizeof(double4) * WAVE * split : 0;
+    if (pack) SDC_LAUNCH(KID_PACK, k_pack_ke, dim3(a.ntiles), dim3(64), 0, s, a);
     SDC_LAUNCH(KID_LOEWNER, k_loewner, dim3(q ? grid : a.ntiles), dim3(WAVE * split), lds, s, a, q);
     return hipGetLastError();
 }
