@@ -333,12 +333,17 @@ def bench_level(args, name):
         pipe.step()
     torch.cuda.synchronize()
     kt = pipe.native.kernel_times()
+    kw = pipe.native.kernel_work()
     pipe.native.kernel_timing(False)
-    direct = batch.sizes().max() < (args.fmm_crossover or FMM_CROSSOVER)
-    kflops = {"k_loewner": FLOPS_LOEWNER * n2, "k_bnorm": FLOPS_BNORM * n2,
-              ("k_apply_mfma" if m >= MFMA_MIN_M else "k_apply_valu"): apply_flops}
-    if direct:
-        kflops["k_secular"] = sec_flops
+    # direct kernels serve the problems below the FMM crossover only
+    small = sizes[sizes < (args.fmm_crossover or FMM_CROSSOVER)]
+    n2d = float(np.sum(small ** 2))
+    kflops = {"k_loewner": FLOPS_LOEWNER * n2d, "k_bnorm": FLOPS_BNORM * n2d,
+              ("k_apply_mfma" if m >= MFMA_MIN_M else "k_apply_valu"):
+                  (2 * m + 3) * n2d + 2 * float(np.sum(small)) * m}
+    for k in ("k_secular", "k_secular_fmm"):  # the solvers count their pair evaluations
+        if k in kw:
+            kflops[k] = FLOPS_PER_PAIR * kw[k] / args.steps
     kernels, roofline = kernel_roofline(kt, kflops, args.steps, name)
     res = {
         "metric": METRIC, "value": tot / (ms * 1e-3), "unit": "roots/s", "n_gpus": 1,
@@ -446,16 +451,16 @@ def conquer_flops(tree, iters):
 
 
 def conquer_kernel_flops(tree, iters, crossover=FMM_CROSSOVER):
-    """Algorithmic FP64 flops per kernel of one conquer (direct-sum kernels only: the FMM
-    kernels' work has no pair count), mirroring the library's automatic choices: levels
-    with nodes of at least `crossover` roots solve, normalise and apply Q^T by the FMM."""
+    """Algorithmic FP64 flops per kernel of one conquer for the direct kernels, mirroring the
+    library's automatic choices: levels with nodes of at least `crossover` roots run
+    through the FMM kernels (the solvers' pair evaluations are counted by the library)."""
     D, r, n = tree.depth, tree.r, tree.n
     k = dict(k_secular=0.0, k_loewner=0.0, k_bnorm=0.0, k_apply_mfma=0.0, k_apply_valu=0.0)
     for lvl in range(D):
         nl = tree.leaf << (D - lvl)
-        k["k_loewner"] += r * FLOPS_LOEWNER * n * nl
         if nl >= crossover:
-            continue  # solve, b and the Q^T applies of this level run through the FMM kernels
+            continue  # this level's solves, zhat, b and Q^T applies run through the FMM kernels
+        k["k_loewner"] += r * FLOPS_LOEWNER * n * nl
         k["k_secular"] += FLOPS_PER_PAIR * nl * float(np.sum(1.0 + iters[lvl]))
         k["k_bnorm"] += r * FLOPS_BNORM * n * nl
         ncol = 2 * r if lvl > 0 else r
@@ -562,11 +567,13 @@ def bench_conquer(args):
         native.hss_conquer(ctx, plan, gens, opts=opts1, out=out)
     torch.cuda.synchronize()
     kt = native.kernel_times()
+    kw = native.kernel_work()
     native.kernel_timing(False)
-    kernels, roofline = kernel_roofline(kt, conquer_kernel_flops(tree, iters,
-                                                                 args.fmm_crossover or FMM_CROSSOVER),
-                                        args.steps,
-                                        "conquer")
+    kflops = conquer_kernel_flops(tree, iters, args.fmm_crossover or FMM_CROSSOVER)
+    for k in ("k_secular", "k_secular_fmm"):  # the solvers count their pair evaluations
+        if k in kw:
+            kflops[k] = FLOPS_PER_PAIR * kw[k] / args.steps
+    kernels, roofline = kernel_roofline(kt, kflops, args.steps, "conquer")
     native.hss_set_timing(plan, True)
 
     # accuracy: trace identity and sampled eigenpair residuals with the oracle's product

@@ -256,6 +256,13 @@ int superdc_hss_phase_times(superdc_hss *plan, double *ms, int32_t *launches);
  */
 int superdc_kernel_timing(int enable);
 int superdc_kernel_times(double *ms, int32_t *launches, int32_t count);
+/*
+ * Pole-root pair evaluations counted while kernel timing was on, per kernel id (the
+ * secular solvers count each pass of each live root times the poles or equivalent sources
+ * it sums; kernels without a counter report 0).  Waits for the device, then clears the
+ * counters.  Returns the number of kernel ids (negative on error).
+ */
+int superdc_kernel_work(double *pairs, int32_t count);
 const char *superdc_kernel_name(int32_t id);
 
 #ifdef __cplusplus

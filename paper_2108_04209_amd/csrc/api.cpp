@@ -191,12 +191,32 @@ FmmPlan *fmm_plan(superdc_batch *b, int leaf, int crossover) {
     fp->split = 1;
     while (fp->split < 8 && (long)fp->nitems * fp->split * 2 <= (long)b->ctx->num_cu * 16)
         fp->split *= 2;
+    // the solver's items (pieces of ssub roots that never cross a leaf)
+    std::vector<Tile> snat, slpt;
+    fp->ssub = leaf % (2 * TILE) == 0 ? 2 * TILE : TILE;  // divides the leaf
+    fp->sitem_off_h.push_back(0);
+    for (int q = 0; q < fp->nfmm; ++q) {
+        const int p = fp->fmm_prob_h[q];
+        const int64_t n = b->off_h[p + 1] - b->off_h[p];
+        for (int64_t r = 0; r < n; r += fp->ssub) snat.push_back(Tile{p, (int32_t)r});
+        fp->sitem_off_h.push_back((int32_t)snat.size());
+    }
+    fp->snitems = (int)snat.size();
+    for (int p : b->order) {
+        const int q = fp->fmm_of_h[p];
+        if (q < 0) continue;
+        for (int t = fp->sitem_off_h[q]; t < fp->sitem_off_h[q + 1]; ++t) slpt.push_back(snat[t]);
+    }
+    fp->ssplit = 1;
+    while (fp->ssplit < 8 && (long)fp->snitems * fp->ssplit * 2 <= (long)b->ctx->num_cu * 16)
+        fp->ssplit *= 2;
     bool ok = fmm_upload(fp, &fp->fmm_prob, fp->fmm_prob_h) &&
               fmm_upload(fp, &fp->fmm_of, fp->fmm_of_h) &&
               fmm_upload(fp, &fp->box_off, fp->box_off_h) &&
               fmm_upload(fp, &fp->leaf_off, fp->leaf_off_h) && fmm_upload(fp, &fp->height, height) &&
               fmm_upload(fp, &fp->box_fmm, box_fmm) && fmm_upload(fp, &fp->leaf_fmm, leaf_fmm) &&
               fmm_upload(fp, &fp->leaf_nat, lnat) && fmm_upload(fp, &fp->leaf_lpt, llpt) &&
+              fmm_upload(fp, &fp->sitem_nat, snat) && fmm_upload(fp, &fp->sitem_lpt, slpt) &&
               fmm_upload(fp, &fp->eq, std::vector<double2>(), (size_t)fp->nboxes * FMM_P) &&
               fmm_upload(fp, &fp->box_ab, std::vector<double2>(), fp->nboxes) &&
               fmm_upload(fp, &fp->near_lo, std::vector<int32_t>(), (size_t)fp->nleaves * FMM_NEAR_MAX) &&
@@ -721,15 +741,17 @@ int superdc_secular_solve(superdc_ctx *ctx, const superdc_batch *b, const double
         }
         SDC_HIP(launch_validate(a, 0, b->nprob, s));
         if (fp) SDC_HIP(launch_fmm_build(f, s));
+        a.work = trace_work(KID_SECULAR);
         SDC_HIP(launch_secular(a, sh.split, ctx->queues + Q_SECULAR,
                                persistent_grid(ctx, a.ntiles, std::max(1, 32 / sh.split)), s));
         if (fp) {
             SolveArgs af = a;
-            af.tiles = fp->leaf_lpt;
-            af.ntiles = fp->nitems;
-            af.chunk = fp->sub;
-            SDC_HIP(launch_secular_fmm(af, f, fp->split, ctx->queues + Q_SECULAR_FMM,
-                                       persistent_grid(ctx, af.ntiles, std::max(1, 32 / fp->split)),
+            af.tiles = fp->sitem_lpt;
+            af.ntiles = fp->snitems;
+            af.chunk = fp->ssub;
+            af.work = trace_work(KID_SECULAR_FMM);
+            SDC_HIP(launch_secular_fmm(af, f, fp->ssplit, ctx->queues + Q_SECULAR_FMM,
+                                       persistent_grid(ctx, af.ntiles, std::max(1, 32 / fp->ssplit)),
                                        s));
         }
     } else {
@@ -745,10 +767,11 @@ int superdc_secular_solve(superdc_ctx *ctx, const superdc_batch *b, const double
             if (fp && fp->fmm_of_h[p] >= 0) {
                 const int q = fp->fmm_of_h[p];
                 SolveArgs af = a;
-                af.tiles = fp->leaf_nat + fp->item_off_h[q];
-                af.ntiles = fp->item_off_h[q + 1] - fp->item_off_h[q];
-                af.chunk = fp->sub;
-                SDC_HIP(launch_secular_fmm(af, f, fp->split, nullptr, 0, s));
+                af.tiles = fp->sitem_nat + fp->sitem_off_h[q];
+                af.ntiles = fp->sitem_off_h[q + 1] - fp->sitem_off_h[q];
+                af.chunk = fp->ssub;
+                af.work = trace_work(KID_SECULAR_FMM);
+                SDC_HIP(launch_secular_fmm(af, f, fp->ssplit, nullptr, 0, s));
                 continue;
             }
             const LaunchShape sh = shape_for(ctx, &np, 1, TILE);
@@ -757,6 +780,7 @@ int superdc_secular_solve(superdc_ctx *ctx, const superdc_batch *b, const double
             a.tiles = L->nat + L->begin[p];
             a.ntiles = L->begin[p + 1] - L->begin[p];
             a.chunk = sh.chunk;
+            a.work = trace_work(KID_SECULAR);
             SDC_HIP(launch_secular(a, sh.split, nullptr, 0, s));
         }
     }

@@ -123,6 +123,10 @@ enum KernelId : int {
     KID_FMMV_EVAL_MFMA, KID_FMML_PACK, KID_FMML_MOMENTS, KID_LOEWNER_FMM, KID_COUNT
 };
 
+// device counter of the pair evaluations of kernel `kid` while kernel timing is on (the
+// current device), else nullptr
+unsigned long long *trace_work(int kid);
+
 class TraceScope {
   public:
     TraceScope(int kid, hipStream_t s);
@@ -238,6 +242,7 @@ struct SolveArgs {
     double stop_c;
     int max_iter;
     int chunk;       // roots per work item (the tile list is cut at this length)
+    unsigned long long *work;  // when kernel timing is on: pole-root pair evaluations
 };
 hipError_t launch_validate(const SolveArgs &a, int prob_first, int nprob, hipStream_t s);
 hipError_t launch_secular(const SolveArgs &a, int split, Queue *q, int grid, hipStream_t s);

@@ -56,6 +56,14 @@ struct FmmPlan {
     std::vector<int32_t> item_off_h;   // FMM problem q owns items [item_off[q], item_off[q+1])
     Tile *leaf_lpt = nullptr;          // work items, longest problems first
     Tile *leaf_nat = nullptr;          // ... in problem order
+    // the solver's work items: longer pieces (ssub roots), so a wavefront refills lanes whose
+    // roots converged instead of idling until its slowest root is done
+    int ssub = 2 * TILE;
+    int snitems = 0;
+    int ssplit = 1;
+    std::vector<int32_t> sitem_off_h;
+    Tile *sitem_lpt = nullptr;
+    Tile *sitem_nat = nullptr;
     std::vector<Tile *> dir_lpt;       // direct chunks of the other problems, per cut length
     std::vector<int32_t> dir_count;
     int32_t *used = nullptr;           // [nboxes]

@@ -327,6 +327,20 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
         nl = wave_uniform(fm->cnt[3 * (int64_t)L + 1]);
         nr = wave_uniform(fm->cnt[3 * (int64_t)L + 2]);
     }
+    // pair evaluations of this wavefront per pass and live root (kernel timing only)
+    int64_t pairs_per_pass = p1 - p0;
+    if (a.work && FMM && nn >= 0) {
+        pairs_per_pass = 0;
+        for (int e = 0; e < nn; ++e) {
+            const int lo0 = fm->near_lo[(int64_t)L * FMM_NEAR_MAX + e];
+            const int hi0 = fm->near_hi[(int64_t)L * FMM_NEAR_MAX + e];
+            pairs_per_pass += (int)(((int64_t)(hi0 - lo0) * (wv + 1)) / S) -
+                              (int)(((int64_t)(hi0 - lo0) * wv) / S);
+        }
+        const int nfar = (nl > wv ? (nl - wv + S - 1) / S : 0) + (nr > wv ? (nr - wv + S - 1) / S : 0);
+        pairs_per_pass += (int64_t)FMM_P * nfar;
+    }
+    unsigned long long work = 0;
 
     int next = c0;  // next unassigned root (wave-uniform)
     bool act = false, last = false, hi_closed = false, noconv = false;
@@ -361,6 +375,7 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
         else
             secular_sums(dw, n, p0, p1, kmin, kmax, k, dK, y, psi, dpsi, phi, dphi);
         split_reduce4(red, S, psi, dpsi, phi, dphi);
+        if (a.work) work += (unsigned long long)pairs_per_pass * (unsigned long long)__popcll(__ballot(act));
         if (!act) continue;
         const double f = 1.0 + psi + phi;
         bool done;
@@ -436,6 +451,7 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
         }
     }
     if (writer && __ballot(noconv) != 0ull && lane == 0) atomicOr(&a.status[p], SUPERDC_ST_NOCONV);
+    if (a.work && lane == 0) atomicAdd(a.work, work);
 }
 
 // blockDim.x = 64 S (S = 1, 2, 4, 8, 16); dynamic LDS: 32 S bytes per lane (S > 1)

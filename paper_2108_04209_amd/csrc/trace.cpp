@@ -22,6 +22,8 @@ struct Mark {
 struct Tracer {
     std::mutex mu;
     bool on = false;
+    unsigned long long *work = nullptr;  // [KID_COUNT] device counters (device `work_dev`)
+    int work_dev = -1;
     std::vector<hipEvent_t> pool;  // idle events
     std::vector<Mark> marks;       // recorded, not yet collected
 };
@@ -51,6 +53,14 @@ const char *kNames[KID_COUNT] = {
 
 }  // namespace
 
+unsigned long long *trace_work(int kid) {
+    Tracer &t = tracer();
+    if (!t.on) return nullptr;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev != t.work_dev || !t.work) return nullptr;
+    return t.work + kid;
+}
+
 TraceScope::TraceScope(int kid, hipStream_t s) : kid_(kid), s_(s) {
     Tracer &t = tracer();
     if (!t.on) return;  // racy read is fine: enabling is not synchronised with launches
@@ -77,8 +87,41 @@ extern "C" {
 int superdc_kernel_timing(int enable) {
     Tracer &t = tracer();
     std::lock_guard<std::mutex> g(t.mu);
+    if (enable) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return SUPERDC_EHIP;
+        if (t.work && t.work_dev != dev) {
+            (void)hipFree(t.work);
+            t.work = nullptr;
+        }
+        if (!t.work) {
+            if (hipMalloc(&t.work, sizeof(unsigned long long) * KID_COUNT) != hipSuccess) {
+                t.work = nullptr;
+                return SUPERDC_ENOMEM;
+            }
+            t.work_dev = dev;
+        }
+        if (hipMemset(t.work, 0, sizeof(unsigned long long) * KID_COUNT) != hipSuccess ||
+            hipDeviceSynchronize() != hipSuccess)
+            return SUPERDC_EHIP;
+    }
     t.on = enable != 0;
     return SUPERDC_OK;
+}
+
+int superdc_kernel_work(double *pairs, int32_t count) {
+    if (count < 0 || (count > 0 && !pairs)) return SUPERDC_EINVAL;
+    Tracer &t = tracer();
+    std::lock_guard<std::mutex> g(t.mu);
+    unsigned long long h[KID_COUNT] = {0};
+    if (t.work) {
+        if (hipDeviceSynchronize() != hipSuccess ||
+            hipMemcpy(h, t.work, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemset(t.work, 0, sizeof(h)) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+            return SUPERDC_EHIP;
+    }
+    for (int i = 0; i < count; ++i) pairs[i] = i < KID_COUNT ? (double)h[i] : 0.0;
+    return KID_COUNT;
 }
 
 int superdc_kernel_times(double *ms, int32_t *launches, int32_t count) {

@@ -77,6 +77,8 @@ def load_library(path: str = LIB_PATH):
     lib.superdc_kernel_timing.restype = C.c_int
     lib.superdc_kernel_times.argtypes = [_P, _P, C.c_int32]
     lib.superdc_kernel_times.restype = C.c_int
+    lib.superdc_kernel_work.argtypes = [_P, C.c_int32]
+    lib.superdc_kernel_work.restype = C.c_int
     lib.superdc_kernel_name.argtypes = [C.c_int32]
     lib.superdc_kernel_name.restype = C.c_char_p
     _lib = lib
@@ -262,6 +264,16 @@ def kernel_times():
     nl = (C.c_int32 * cnt)()
     _check(min(0, lib.superdc_kernel_times(ms, nl, cnt)), "superdc_kernel_times")
     return {lib.superdc_kernel_name(i).decode(): (ms[i], nl[i]) for i in range(cnt) if nl[i]}
+
+
+def kernel_work():
+    """superdc_kernel_work: {kernel name: pole-root pair evaluations} counted while kernel
+    timing was on (kernels with a counter only); waits for the device and clears them."""
+    lib = load_library()
+    cnt = lib.superdc_kernel_times(None, None, 0)
+    w = (C.c_double * cnt)()
+    _check(min(0, lib.superdc_kernel_work(w, cnt)), "superdc_kernel_work")
+    return {lib.superdc_kernel_name(i).decode(): w[i] for i in range(cnt) if w[i] > 0}
 
 
 def batch_shapes(batch):

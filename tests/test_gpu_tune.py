@@ -51,12 +51,19 @@ def test_kernel_timing():
     native.kernel_times()  # drop anything collected before
     native.kernel_timing(True)
     try:
-        native.secular_solve(ctx, b, d, z, rho)
+        res = native.secular_solve(ctx, b, d, z, rho)
         kt = native.kernel_times()
+        kw = native.kernel_work()
     finally:
         native.kernel_timing(False)
     assert kt["k_validate"][1] == 1 and kt["k_secular"][1] == 1
     assert kt["k_secular"][0] > 0.0
+    # the solver's pair count: every pass (the midpoint pass and each iteration) of every
+    # root sums over all n_p poles
+    its = res["iters"].cpu().numpy().astype(np.int64)
+    want = sum(int(batch.off[p + 1] - batch.off[p]) * int(np.sum(1 + its[batch.off[p]:batch.off[p + 1]]))
+               for p in range(batch.nprob))
+    assert kw["k_secular"] == want
     native.secular_solve(ctx, b, d, z, rho)
     torch.cuda.synchronize()
     assert native.kernel_times() == {}
