@@ -8,7 +8,7 @@
 namespace sdc {
 
 constexpr int FMM_P = 16;          // Chebyshev nodes per box (equivalent sources)
-constexpr int FMM_NEAR_MAX = 24;   // near leaves per target leaf
+constexpr int FMM_NEAR_MAX = 24;   // near leaves (and so near ranges) per target leaf
 constexpr int FMM_FAR_MAX = 64;    // far boxes per side per target leaf
 
 // Per batch: the problems that use the FMM, their trees, and per-leaf interaction lists.
@@ -30,7 +30,7 @@ struct FmmArgs {
     int32_t *used;            // [nboxes] 1 if some target leaf lists the box as far field
     double2 *eq;              // [boxes][FMM_P] equivalent sources (node, weight)
     double2 *box_ab;          // [boxes] (first pole, last pole) of the box
-    int32_t *near_lo, *near_hi;   // [leaves][FMM_NEAR_MAX] pole ranges of near leaves
+    int32_t *near_lo, *near_hi;   // [leaves][FMM_NEAR_MAX] pole ranges: runs of adjacent near leaves
     int32_t *far_l, *far_r;       // [leaves][FMM_FAR_MAX] far box ids (global)
     int32_t *cnt;             // [leaves][3] counts (near, far left, far right); -1 = direct
     int nboxes, nleaves;

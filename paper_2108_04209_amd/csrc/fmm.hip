@@ -138,7 +138,7 @@ __global__ __launch_bounds__(64) void k_fmm_lists(FmmArgs f) {
     const double xa = dw[i0].x;
     const double xb = i1 < n ? dw[i1].x : dw[n - 1].x + fmax(f.tail[p], 0.0);
     int stack[64];
-    int sp = 0, nn = 0, nl = 0, nr = 0;
+    int sp = 0, nn = 0, nl = 0, nr = 0, nleaf = 0;
     bool overflow = false;
     stack[sp++] = 0;
     while (sp > 0 && !overflow) {
@@ -167,7 +167,14 @@ __global__ __launch_bounds__(64) void k_fmm_lists(FmmArgs f) {
                 overflow = true;
             }
         } else if (h == H) {
-            if (nn < FMM_NEAR_MAX) {
+            // leaves are visited left to right: a leaf adjacent to the previous near range
+            // extends it, so the near field is a few long contiguous ranges (still at most
+            // FMM_NEAR_MAX leaves in all)
+            if (++nleaf > FMM_NEAR_MAX) {
+                overflow = true;
+            } else if (nn > 0 && f.near_hi[(int64_t)L * FMM_NEAR_MAX + nn - 1] == lo) {
+                f.near_hi[(int64_t)L * FMM_NEAR_MAX + nn - 1] = hi;
+            } else if (nn < FMM_NEAR_MAX) {
                 f.near_lo[(int64_t)L * FMM_NEAR_MAX + nn] = lo;
                 f.near_hi[(int64_t)L * FMM_NEAR_MAX + nn] = hi;
                 ++nn;

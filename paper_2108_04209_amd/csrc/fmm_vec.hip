@@ -285,7 +285,9 @@ constexpr int FV_LD = FV_K + 1;
 // The chunks of an item (built once per item in LDS): near ranges in 64-pole chunks, then
 // the far boxes 4 at a time (64 equivalent sources).  kind 0: poles [a, a + cnt); kind 1:
 // far boxes fbox[a .. a + cnt).
-// (near ranges are leaves of at most 1024 poles, the largest leaf the options allow)
+// (at most FMM_NEAR_MAX near leaves of at most 1024 poles, the largest leaf the options
+// allow; a run of adjacent leaves has no more chunks than its leaves, since every leaf but
+// a problem's last holds a multiple of 64 poles)
 constexpr int FV_MAXCH = FMM_NEAR_MAX * (1024 / FV_K) + (2 * FMM_FAR_MAX + 3) / 4;
 
 struct FvStage {

@@ -129,51 +129,94 @@ __device__ __forceinline__ void secular_range(const_double2_ptr dw, int j0, int 
             dphi = __builtin_fma(num2, R * R, dphi);                  \
         }                                                             \
     }
+    // Poles come in blocks of 4 (one 64-byte scalar fetch).  Two register sets A and B
+    // alternate, so the next block's fetch is in flight during this block's arithmetic
+    // and no register copies are needed between blocks.
+#define SDC_SET4(S, Q)                                                  \
+    S##0 = make_double2((Q)[0], (Q)[1]);                                \
+    S##1 = make_double2((Q)[2], (Q)[3]);                                \
+    S##2 = make_double2((Q)[4], (Q)[5]);                                \
+    S##3 = make_double2((Q)[6], (Q)[7]);
     int j = j0;
+    const_double_ptr q = dw.p + 2 * (int64_t)j0;
     if (FAR && MODE != 2 && j + 4 <= j1) {
         // the nearest and farthest pole of the range bound every |t|
         const double tn = fabs((MODE == 0 ? dw[j1 - 1].x : dw[j0].x) - x);
         const double tf = fabs((MODE == 0 ? dw[j0].x : dw[j1 - 1].x) - x);
         const bool ok = tn >= 0x1p-300 && tf <= 0x1p300;
         if (__ballot(!ok) == 0ull) {
-            double2 c0 = dw[j], c1 = dw[j + 1], c2 = dw[j + 2], c3 = dw[j + 3];
-            for (; j + 8 <= j1; j += 4) {
-                const double2 n0 = dw[j + 4], n1 = dw[j + 5], n2 = dw[j + 6], n3 = dw[j + 7];
-                SDC_SEC_PAIR(c0, c1)
-                SDC_SEC_PAIR(c2, c3)
-                c0 = n0;
-                c1 = n1;
-                c2 = n2;
-                c3 = n3;
+            double2 a0, a1, a2, a3, b0, b1, b2, b3;
+            SDC_SET4(a, q)
+            for (;;) {
+                if (j + 8 > j1) {
+                    SDC_SEC_PAIR(a0, a1)
+                    SDC_SEC_PAIR(a2, a3)
+                    j += 4;
+                    q += 8;
+                    break;
+                }
+                SDC_SET4(b, q + 8)
+                SDC_SEC_PAIR(a0, a1)
+                SDC_SEC_PAIR(a2, a3)
+                j += 4;
+                q += 8;
+                if (j + 8 > j1) {
+                    SDC_SEC_PAIR(b0, b1)
+                    SDC_SEC_PAIR(b2, b3)
+                    j += 4;
+                    q += 8;
+                    break;
+                }
+                SDC_SET4(a, q + 8)
+                SDC_SEC_PAIR(b0, b1)
+                SDC_SEC_PAIR(b2, b3)
+                j += 4;
+                q += 8;
             }
-            SDC_SEC_PAIR(c0, c1)
-            SDC_SEC_PAIR(c2, c3)
-            j += 4;
-            for (; j < j1; ++j) SDC_SEC_BODY(j, dw[j])
+            for (; j < j1; ++j, q += 2) SDC_SEC_BODY(j, make_double2(q[0], q[1]))
             return;
         }
     }
-    // blocks of 4 poles, the next block's scalar fetch issued before this block's math
     if (j + 4 <= j1) {
-        double2 c0 = dw[j], c1 = dw[j + 1], c2 = dw[j + 2], c3 = dw[j + 3];
-        for (; j + 8 <= j1; j += 4) {
-            const double2 n0 = dw[j + 4], n1 = dw[j + 5], n2 = dw[j + 6], n3 = dw[j + 7];
-            SDC_SEC_BODY(j, c0)
-            SDC_SEC_BODY(j + 1, c1)
-            SDC_SEC_BODY(j + 2, c2)
-            SDC_SEC_BODY(j + 3, c3)
-            c0 = n0;
-            c1 = n1;
-            c2 = n2;
-            c3 = n3;
+        double2 a0, a1, a2, a3, b0, b1, b2, b3;
+        SDC_SET4(a, q)
+        for (;;) {
+            if (j + 8 > j1) {
+                SDC_SEC_BODY(j, a0)
+                SDC_SEC_BODY(j + 1, a1)
+                SDC_SEC_BODY(j + 2, a2)
+                SDC_SEC_BODY(j + 3, a3)
+                j += 4;
+                q += 8;
+                break;
+            }
+            SDC_SET4(b, q + 8)
+            SDC_SEC_BODY(j, a0)
+            SDC_SEC_BODY(j + 1, a1)
+            SDC_SEC_BODY(j + 2, a2)
+            SDC_SEC_BODY(j + 3, a3)
+            j += 4;
+            q += 8;
+            if (j + 8 > j1) {
+                SDC_SEC_BODY(j, b0)
+                SDC_SEC_BODY(j + 1, b1)
+                SDC_SEC_BODY(j + 2, b2)
+                SDC_SEC_BODY(j + 3, b3)
+                j += 4;
+                q += 8;
+                break;
+            }
+            SDC_SET4(a, q + 8)
+            SDC_SEC_BODY(j, b0)
+            SDC_SEC_BODY(j + 1, b1)
+            SDC_SEC_BODY(j + 2, b2)
+            SDC_SEC_BODY(j + 3, b3)
+            j += 4;
+            q += 8;
         }
-        SDC_SEC_BODY(j, c0)
-        SDC_SEC_BODY(j + 1, c1)
-        SDC_SEC_BODY(j + 2, c2)
-        SDC_SEC_BODY(j + 3, c3)
-        j += 4;
     }
-    for (; j < j1; ++j) SDC_SEC_BODY(j, dw[j])
+    for (; j < j1; ++j, q += 2) SDC_SEC_BODY(j, make_double2(q[0], q[1]))
+#undef SDC_SET4
 #undef SDC_SEC_PAIR
 #undef SDC_SEC_BODY
 }
