@@ -739,7 +739,7 @@ int superdc_secular_solve(superdc_ctx *ctx, const superdc_batch *b, const double
             a.tiles = fp->dir_lpt[slot];
             a.ntiles = fp->dir_count[slot];
         }
-        SDC_HIP(launch_validate(a, 0, b->nprob, s));
+        SDC_HIP(launch_validate(a, 0, b->nprob, b->max_n, s));
         if (fp) SDC_HIP(launch_fmm_build(f, s));
         a.work = trace_work(KID_SECULAR);
         SDC_HIP(launch_secular(a, sh.split, ctx->queues + Q_SECULAR,
@@ -758,12 +758,12 @@ int superdc_secular_solve(superdc_ctx *ctx, const superdc_batch *b, const double
         // one launch per problem, cut into 64-root chunks (split if the problem is large),
         // or its target leaves for an FMM problem
         if (fp) {
-            SDC_HIP(launch_validate(a, 0, b->nprob, s));
+            SDC_HIP(launch_validate(a, 0, b->nprob, b->max_n, s));
             SDC_HIP(launch_fmm_build(f, s));
         }
         for (int p = 0; p < b->nprob; ++p) {
             const int64_t np = b->off_h[p + 1] - b->off_h[p];
-            if (!fp) SDC_HIP(launch_validate(a, p, 1, s));
+            if (!fp) SDC_HIP(launch_validate(a, p, 1, (int)np, s));
             if (fp && fp->fmm_of_h[p] >= 0) {
                 const int q = fp->fmm_of_h[p];
                 SolveArgs af = a;

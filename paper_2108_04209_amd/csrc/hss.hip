@@ -52,8 +52,9 @@ __device__ __forceinline__ double2 rot_cs(double t) {
 
 // One round applies A <- J^T A J for the m/2 disjoint rotations of the round at once:
 // every 2 x 2 block (rows of pair P1, columns of pair P2) depends only on its own four
-// entries, so the round is a single pass over the matrix.  Diagonal blocks use the
-// updates app - t apq, aqq + t apq and set apq = 0.
+// entries, so the round is a single pass over the matrix, and by symmetry a pass over the
+// blocks P1 <= P2.  Diagonal blocks use the updates app - t apq, aqq + t apq and set
+// apq = 0.
 __global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
     __shared__ double A[LEAF_MAX * LJ_LD];
     __shared__ double2 cs[LEAF_MAX / 2];
@@ -82,6 +83,8 @@ __global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
     const double absfloor = 1e-18 * sqrt(tot);
     const int m = L;  // even
     const int half = m / 2;
+    const int hh = (half + 1) & ~1;          // half rounded up to even, for the folding
+    const int nfold = (hh / 2) * (hh + 1);  // blocks of the folded triangle
     double *log = a.rot + (size_t)leafid * a.max_sweeps * (m - 1) * half;
     int sweep = 0;
     bool converged = false;
@@ -107,8 +110,20 @@ __global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
                 log[((size_t)sweep * (m - 1) + rd) * half + tid] = t;
             }
             __syncthreads();
-            for (int blk = tid; blk < half * half; blk += nt) {
-                const int P1 = blk / half, P2 = blk % half;
+            // A is symmetric: only blocks P1 <= P2 (the upper triangle) are updated, and
+            // entries are read and written at (min(i,j), max(i,j)).  The blocks are dealt out
+            // by folding row r of the block triangle with row hh-1-r (hh+1 blocks together).
+            for (int blk = tid; blk < nfold; blk += nt) {
+                const int r = blk / (hh + 1), e = blk - r * (hh + 1);
+                int P1, P2;
+                if (e < hh - r) {
+                    P1 = r;
+                    P2 = r + e;
+                } else {
+                    P1 = hh - 1 - r;
+                    P2 = e - 1;
+                }
+                if (P2 >= half) continue;  // padding of an odd half
                 const double2 r1 = cs[P1], r2 = cs[P2];
                 if (r1.y == 0.0 && r2.y == 0.0) continue;
                 const int2 ab = pq[P1], cd = pq[P2];
@@ -118,19 +133,21 @@ __global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
                     A[ab.x * LJ_LD + ab.x] -= t * apq;
                     A[ab.y * LJ_LD + ab.y] += t * apq;
                     A[ab.x * LJ_LD + ab.y] = 0.0;
-                    A[ab.y * LJ_LD + ab.x] = 0.0;
                     continue;
                 }
-                const double xac = A[ab.x * LJ_LD + cd.x], xad = A[ab.x * LJ_LD + cd.y];
-                const double xbc = A[ab.y * LJ_LD + cd.x], xbd = A[ab.y * LJ_LD + cd.y];
+                const int iac = min(ab.x, cd.x) * LJ_LD + max(ab.x, cd.x);
+                const int iad = min(ab.x, cd.y) * LJ_LD + max(ab.x, cd.y);
+                const int ibc = min(ab.y, cd.x) * LJ_LD + max(ab.y, cd.x);
+                const int ibd = min(ab.y, cd.y) * LJ_LD + max(ab.y, cd.y);
+                const double xac = A[iac], xad = A[iad], xbc = A[ibc], xbd = A[ibd];
                 // rows: J1^T X
                 const double yac = r1.x * xac - r1.y * xbc, ybc = r1.y * xac + r1.x * xbc;
                 const double yad = r1.x * xad - r1.y * xbd, ybd = r1.y * xad + r1.x * xbd;
                 // columns: (J1^T X) J2
-                A[ab.x * LJ_LD + cd.x] = r2.x * yac - r2.y * yad;
-                A[ab.x * LJ_LD + cd.y] = r2.y * yac + r2.x * yad;
-                A[ab.y * LJ_LD + cd.x] = r2.x * ybc - r2.y * ybd;
-                A[ab.y * LJ_LD + cd.y] = r2.y * ybc + r2.x * ybd;
+                A[iac] = r2.x * yac - r2.y * yad;
+                A[iad] = r2.y * yac + r2.x * yad;
+                A[ibc] = r2.x * ybc - r2.y * ybd;
+                A[ibd] = r2.y * ybc + r2.x * ybd;
             }
             __syncthreads();
         }

@@ -29,18 +29,41 @@ namespace sdc {
 // ---------------------------------------------------------------------------------------
 // validation and packing: dw_j = (d_j, rho z_j^2), z2 = sum_j w_j, status bits
 // ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_validate(SolveArgs a, int prob_first) {
+__global__ __launch_bounds__(1024) void k_validate(SolveArgs a, int prob_first) {
     const int p = prob_first + blockIdx.x;
     const int64_t base = a.off[p];
     const int n = (int)(a.off[p + 1] - base);
     const double rho = a.rho[p];
     int st = 0;
     double ws = 0.0;
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
-        const double dj = a.d[base + j], zj = a.z[base + j];
+    const double *d = a.d + base, *z = a.z + base;
+    const int nt = blockDim.x;
+    // four entries per thread per step, all loads issued before any use
+    int j = threadIdx.x;
+    for (; j + 3 * nt < n; j += 4 * nt) {
+        double dj[4], dn[4], zj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = j + u * nt;
+            dj[u] = d[i];
+            zj[u] = z[i];
+            dn[u] = i + 1 < n ? d[i + 1] : __builtin_inf();
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (!isfinite(dj[u]) || !isfinite(zj[u])) st |= SUPERDC_ST_NONFINITE;
+            if (zj[u] == 0.0) st |= SUPERDC_ST_ZERO;
+            if (!(dj[u] < dn[u])) st |= SUPERDC_ST_UNSORTED;
+            const double w = rho * zj[u] * zj[u];
+            a.dw[base + j + u * nt] = make_double2(dj[u], w);
+            ws += w;
+        }
+    }
+    for (; j < n; j += nt) {
+        const double dj = d[j], zj = z[j];
         if (!isfinite(dj) || !isfinite(zj)) st |= SUPERDC_ST_NONFINITE;
         if (zj == 0.0) st |= SUPERDC_ST_ZERO;
-        if (j + 1 < n && !(dj < a.d[base + j + 1])) st |= SUPERDC_ST_UNSORTED;
+        if (j + 1 < n && !(dj < d[j + 1])) st |= SUPERDC_ST_UNSORTED;
         const double w = rho * zj * zj;
         a.dw[base + j] = make_double2(dj, w);
         ws += w;
@@ -49,8 +72,8 @@ __global__ __launch_bounds__(256) void k_validate(SolveArgs a, int prob_first) {
         ws += __shfl_xor(ws, o);
         st |= __shfl_xor(st, o);
     }
-    __shared__ double sw[4];
-    __shared__ int ss[4];
+    __shared__ double sw[1024 / WAVE];
+    __shared__ int ss[1024 / WAVE];
     const int wv = threadIdx.x / WAVE;
     if (lane_id() == 0) {
         sw[wv] = ws;
@@ -539,8 +562,10 @@ hipError_t launch_secular_fmm(const SolveArgs &a, const FmmArgs &f, int split, Q
     return hipGetLastError();
 }
 
-hipError_t launch_validate(const SolveArgs &a, int prob_first, int nprob, hipStream_t s) {
-    SDC_LAUNCH(KID_VALIDATE, k_validate, dim3(nprob), dim3(256), 0, s, a, prob_first);
+hipError_t launch_validate(const SolveArgs &a, int prob_first, int nprob, int max_n, hipStream_t s) {
+    // one workgroup per problem, sized to the batch's largest problem
+    const int bs = max_n >= 8192 ? 1024 : (max_n >= 2048 ? 512 : 256);
+    SDC_LAUNCH(KID_VALIDATE, k_validate, dim3(nprob), dim3(bs), 0, s, a, prob_first);
     return hipGetLastError();
 }
 
