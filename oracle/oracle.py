@@ -54,6 +54,8 @@ def load():
         lib.oracle_cauchy_apply.restype = None
         lib.oracle_backward.argtypes = [i64, _P, _P, dbl, _P, _P, _P, _P, _P, _P, _P, _P]
         lib.oracle_backward.restype = None
+        lib.oracle_deflate.argtypes = [i64, _P, _P, dbl, dbl, _P, _P, _P, _P, _P, _P, _P]
+        lib.oracle_deflate.restype = i64
         _lib = lib
     return _lib
 
@@ -175,3 +177,77 @@ def solve_batch(batch, with_vectors=True):
             out["zhat"][a:e] = zh
             out["b"][a:e] = bnorm(pr.d, zh, eta, org)
     return out
+
+
+def deflate(d, z, rho, tau):
+    """Deflation of diag(d) + rho z z^T with tolerance tau (Remark 1).  Returns a dict with
+    kept, d, z (reduced problem first, then the deflated eigenvalues with z = 0), perm (pole
+    index of each output position), rright, rleft, c, s (the rotations, by pole index)."""
+    d, z = _f64(d), _f64(z)
+    n = d.size
+    out = {"d": np.empty(n), "z": np.empty(n), "perm": np.empty(n, dtype=np.int32),
+           "rright": np.empty(n, dtype=np.int32), "rleft": np.empty(n, dtype=np.int32),
+           "c": np.empty(n), "s": np.empty(n)}
+    out["kept"] = int(load().oracle_deflate(n, _ptr(d), _ptr(z), float(rho), float(tau),
+                                            _ptr(out["d"]), _ptr(out["z"]), _ptr(out["perm"]),
+                                            _ptr(out["rright"]), _ptr(out["rleft"]),
+                                            _ptr(out["c"]), _ptr(out["s"])))
+    return out
+
+
+def deflate_expand(df, U, trans=0):
+    """The orthogonal factor of the deflation applied to a block.
+
+    With G the product of the rotations (the first made acting first) and P the
+    placement of output position j at pole perm[j], the full eigenvector matrix is
+    Q = G^T P (Qhat (+) I).  trans 0: returns G^T P U for U whose rows are output positions;
+    trans 1: returns P^T G X for X whose rows are pole indices."""
+    U = np.array(np.asarray(U, dtype=np.float64).reshape(df["d"].size, -1), copy=True)
+    n = U.shape[0]
+    rot = [a for a in range(n) if df["rright"][a] >= 0]  # creation order: increasing a
+    if trans == 0:
+        Y = np.empty_like(U)
+        Y[df["perm"]] = U
+        for a in reversed(rot):  # G^T = G_1^T ... G_R^T: the last rotation first
+            b, c, s = df["rright"][a], df["c"][a], df["s"][a]
+            ya, yb = Y[a].copy(), Y[b].copy()
+            Y[a] = c * ya + s * yb
+            Y[b] = -s * ya + c * yb
+        return Y
+    Y = U
+    for a in rot:  # G = G_R ... G_1: the first rotation first
+        b, c, s = df["rright"][a], df["c"][a], df["s"][a]
+        ya, yb = Y[a].copy(), Y[b].copy()
+        Y[a] = c * ya - s * yb
+        Y[b] = s * ya + c * yb
+    return Y[df["perm"]]
+
+
+def deflated_eig(d, z, rho, tau, vectors=True):
+    """Eigenvalues (and, for small n, the dense eigenvector matrix) of diag(d) + rho z z^T
+    through deflation: the reduced problem by the secular oracle, the deflated eigenvalues
+    as they come.  Eigenvalue j belongs to output position j of deflate()."""
+    df = deflate(d, z, rho, tau)
+    k = df["kept"]
+    n = df["d"].size
+    lam = df["d"].copy()
+    res = {"deflate": df, "status": 0}
+    if k > 0:
+        dr, zr = df["d"][:k], df["z"][:k]
+        lr, eta, org, its, st = secular(dr, zr, rho)
+        res["status"] = st
+        lam[:k] = lr
+        res["eta"], res["origin"] = eta, org
+        if vectors:
+            zh = loewner(dr, zr, rho, eta, org)
+            b = bnorm(dr, zh, eta, org)
+            res["zhat"], res["b"] = zh, b
+            Qh = cauchy_apply(dr, zh, b, eta, org, np.eye(k), 0)
+            U = np.zeros((n, n))
+            U[:k, :k] = Qh
+            U[k:, k:] = np.eye(n - k)
+            res["Q"] = deflate_expand(df, U, 0)
+    elif vectors:
+        res["Q"] = deflate_expand(df, np.eye(n), 0)
+    res["lam"] = lam
+    return res

@@ -23,6 +23,9 @@
  *     eq. qscale), every d_i - lambda_j formed as (d_i - d_{K_j}) - eta_j (eq. qk).
  *   - the adjoint of lambda and of projections p_k = q_k^T u with respect to (d, z, rho),
  *     from implicit differentiation of f(lambda_k) = 0 (not in the paper).
+ *   - deflation with a user tolerance tau (Remark 1): the two rules taken in the paper's
+ *     order, the second as a left-to-right scan in which a pole that survives a rotation
+ *     carries its rotated values on to the next comparison.
  *
  * Status bits returned by the validating entry points:
  *   1 d not strictly increasing, 2 some z_i == 0, 4 non-finite input, 8 rho <= 0,
@@ -342,4 +345,109 @@ void oracle_backward(int64_t n, const double *d, const double *z, double rho,
     free(Sk);
     free(hk);
     free(bk);
+}
+
+/* ---------------------------------------------------------------------------------- */
+/* deflation (Remark 1)                                                               */
+/* ---------------------------------------------------------------------------------- */
+/*
+ * A = diag(d) + v v^T with v = sqrt(rho) z, d non-decreasing, tau >= 0.
+ *   rule 1: pole k is deflated if |v_k| < tau; its eigenpair is (d_k, e_k).
+ *   rule 2: over the remaining poles in increasing order, the current pole a and the next
+ *           remaining pole b are rotated together if |(d_a - d_b) v_a v_b| < (v_a^2 + v_b^2)
+ *           tau (both sides scale by rho, so z takes the place of v).  With r =
+ *           sqrt(z_a^2 + z_b^2), c = z_b / r, s = z_a / r the rotation G = [c -s; s c] on
+ *           (a, b) maps (z_a, z_b) to (0, r) and diag(d_a, d_b) to
+ *           [c^2 d_a + s^2 d_b, cs (d_a - d_b); cs (d_a - d_b), s^2 d_a + c^2 d_b]; the
+ *           off-diagonal entry is below tau and is dropped.  Pole a is deflated with the
+ *           eigenvalue c^2 d_a + s^2 d_b; pole b continues with d_b' = s^2 d_a + c^2 d_b
+ *           (held inside [d_a, d_b]) and z_b' = r and is compared with the next pole.
+ *           Otherwise pole a is kept.
+ * Every expression is evaluated exactly as written (this file is built without FP
+ * contraction), so another implementation that evaluates the same expressions in the
+ * same order reaches the same decisions.
+ *
+ * Outputs (all of length n):
+ *   dout/zout[0 .. kept)  the reduced problem, strictly increasing poles;
+ *   dout[kept .. n)       the deflated eigenvalues in order of their pole's index, zout = 0;
+ *   perm[j]               the pole index of output position j;
+ *   rright[i]             for a pole deflated by rule 2, the pole it was rotated with
+ *                         (-1 otherwise); rleft[b] = a whenever rright[a] = b (-1 otherwise);
+ *   rc[i], rs[i]          that rotation's c and s (1 and 0 where there is none).
+ * Returns kept.
+ */
+int64_t oracle_deflate(int64_t n, const double *d, const double *z, double rho, double tau,
+                       double *dout, double *zout, int32_t *perm, int32_t *rright,
+                       int32_t *rleft, double *rc, double *rs)
+{
+    const double sv = sqrt(rho);
+    /* per pole: its final value and whether it is kept */
+    double *dv = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *zv = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    char *keep = (char *)malloc((size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        rright[i] = -1;
+        rleft[i] = -1;
+        rc[i] = 1.0;
+        rs[i] = 0.0;
+        dv[i] = d[i];
+        zv[i] = 0.0;
+        keep[i] = 0;
+    }
+    int64_t a = -1;     /* the current pole of the scan */
+    double da = 0.0, za = 0.0;
+    for (int64_t b = 0; b < n; ++b) {
+        if (fabs(sv * z[b]) < tau) continue; /* rule 1 */
+        if (a < 0) {
+            a = b;
+            da = d[b];
+            za = z[b];
+            continue;
+        }
+        const double db = d[b], zb = z[b];
+        const double r2 = za * za + zb * zb;
+        const double lhs = fabs(((da - db) * za) * zb);
+        if (lhs < r2 * tau) { /* rule 2: rotate a into b */
+            const double r = sqrt(r2);
+            const double c = zb / r, s = za / r;
+            const double cc = c * c, ss = s * s;
+            const double dl = cc * da + ss * db;
+            double dr = ss * da + cc * db;
+            if (dr < da) dr = da;
+            if (dr > db) dr = db;
+            dv[a] = dl;
+            rright[a] = (int32_t)b;
+            rleft[b] = (int32_t)a;
+            rc[a] = c;
+            rs[a] = s;
+            a = b;
+            da = dr;
+            za = r;
+        } else { /* a is kept with its current values */
+            keep[a] = 1;
+            dv[a] = da;
+            zv[a] = za;
+            a = b;
+            da = db;
+            za = zb;
+        }
+    }
+    if (a >= 0) {
+        keep[a] = 1;
+        dv[a] = da;
+        zv[a] = za;
+    }
+    int64_t kept = 0;
+    for (int64_t i = 0; i < n; ++i) kept += keep[i];
+    int64_t pk = 0, pd = kept;
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t j = keep[i] ? pk++ : pd++;
+        dout[j] = dv[i];
+        zout[j] = keep[i] ? zv[i] : 0.0;
+        perm[j] = (int32_t)i;
+    }
+    free(dv);
+    free(zv);
+    free(keep);
+    return kept;
 }

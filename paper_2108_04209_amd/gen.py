@@ -217,6 +217,47 @@ def small_batch(sizes, seed: int = 0, kind: str = "uniform", m: int = 0):
     return b
 
 
+def deflation_problem(n: int, g: np.random.Generator, rho: float = 1.0, dup_frac: float = 0.05,
+                      near_frac: float = 0.10, tiny_frac: float = 0.05,
+                      zero_frac: float = 0.01) -> RankOne:
+    """Poles that call for deflation: sorted U[0,1) where a share of the poles repeats its
+    left neighbour exactly (duplicates, also in runs) and a share sits a tiny distance
+    10^U[-15,-9] above it; z ~ N(0,1) normalised, with a share of entries replaced by
+    tiny values +-10^U[-14,-9] and a share by exact zeros.  d is non-decreasing, not
+    strictly increasing."""
+    u = np.sort(g.random(n))
+    kind = g.random(n)
+    gaps = 10.0 ** g.uniform(-15, -9, n)
+    d = u.copy()
+    for i in range(1, n):
+        if kind[i] < dup_frac:
+            d[i] = d[i - 1]
+        elif kind[i] < dup_frac + near_frac:
+            d[i] = d[i - 1] + gaps[i]
+        else:
+            d[i] = max(u[i], d[i - 1] + 1e-6)
+    z = g.standard_normal(n)
+    z /= np.linalg.norm(z)
+    zk = g.random(n)
+    tiny = zk < tiny_frac
+    z[tiny] = np.sign(z[tiny]) * 10.0 ** g.uniform(-14, -9, int(tiny.sum()))
+    z[(zk >= tiny_frac) & (zk < tiny_frac + zero_frac)] = 0.0
+    return RankOne(d=d, z=z, rho=float(rho))
+
+
+def deflation_batch(sizes, seed: int = 0, m: int = 0):
+    """Batches of deflation_problem draws with rho ~ U[0.1, 2]."""
+    probs = []
+    for p, n in enumerate(sizes):
+        g = rng_for(300 + seed, p)
+        probs.append(deflation_problem(int(n), g, rho=g.uniform(0.1, 2.0)))
+    b = concat(probs)
+    if m:
+        gx = rng_for(300 + seed, 1 << 31)
+        return b, np.asfortranarray(gx.standard_normal((b.total_n, m)))
+    return b
+
+
 # ----------------------------------------------------------------------------------------
 # HSS generators for a conquer pass (perfect binary tree, Sec. 2.1 eq. hss)
 # ----------------------------------------------------------------------------------------
