@@ -182,6 +182,77 @@ int superdc_secular_backward(superdc_ctx *ctx, const superdc_batch *batch, const
                              const superdc_opts *opts, void *stream);
 
 /* ------------------------------------------------------------------------------------
+ * Deflation (Remark 1) with a user tolerance tau >= 0.
+ *
+ * For A = diag(d) + v v^T, v = sqrt(rho) z, d non-decreasing (equal poles allowed):
+ *   rule 1: pole k deflates if |v_k| < tau; its eigenpair is (d_k, e_k);
+ *   rule 2: scanning the remaining poles in increasing order, the current pole a and the
+ *           next remaining pole b are rotated together if
+ *           |(d_a - d_b) v_a v_b| < (v_a^2 + v_b^2) tau.  With r = |(z_a, z_b)|,
+ *           c = z_b / r, s = z_a / r, the rotation G = [c -s; s c] on (a, b) takes
+ *           (z_a, z_b) to (0, r); the off-diagonal entry cs (d_a - d_b) it creates is below
+ *           tau and is dropped.  Pole a deflates with eigenvalue c^2 d_a + s^2 d_b; pole b
+ *           continues into the next test with d_b' = s^2 d_a + c^2 d_b (held in
+ *           [d_a, d_b]) and z_b' = r.
+ * Decisions are taken in FP64 with the expressions above evaluated as written (no fused
+ * multiply-adds), so a plain sequential implementation reaches the same ones.
+ * The eigenvector matrix of the deflated problem is Q = G^T P (Qhat (+) I): G the product
+ * of the rotations (the first made acting first), P the placement below, Qhat that of the
+ * reduced problem.
+ *
+ *   in : d, z [total] (device), rho [nprob] (device), tau (host scalar, finite, >= 0)
+ *   out: per problem p, at its offset, with k = kept[p]:
+ *        d_out/z_out[0 .. k)  the reduced problem (strictly increasing poles; solve it with
+ *                             the same rho after gathering it into a batch of sizes
+ *                             kept[p], superdc_batch_copy_rows);
+ *        d_out[k .. n_p)      the deflated eigenvalues in pole order, z_out = 0 there;
+ *        perm[j]              the pole (local index) of output position j;
+ *        rot_right[i]         for a pole deflated by rule 2, the pole it was rotated into
+ *                             (local index), else -1; rot_left[b] = a when rot_right[a] = b,
+ *                             else -1;
+ *        rot_c[i], rot_s[i]   that rotation's c and s (1 and 0 where there is none);
+ *        kept[p] (device int32), status[p] (device int32: SUPERDC_ST_NONFINITE for a
+ *        non-finite d, z or rho, SUPERDC_ST_UNSORTED for a decrease in d,
+ *        SUPERDC_ST_RHO for rho <= 0; such a problem gets kept = 0 and no other output).
+ * tau = 0 deflates nothing (the output is the input and perm the identity).  All
+ * arrays are caller-owned device memory; returns SUPERDC_EINVAL for NULL pointers or a
+ * bad tau.
+ */
+int superdc_deflate(superdc_ctx *ctx, const superdc_batch *batch, const double *d,
+                    const double *z, const double *rho, double tau, double *d_out,
+                    double *z_out, int32_t *perm, int32_t *rot_right, int32_t *rot_left,
+                    double *rot_c, double *rot_s, int32_t *kept, int32_t *status, void *stream);
+
+/*
+ * The orthogonal factor of a deflation, on total x m column-major blocks (leading
+ * dimensions ldx, ldy >= total; every problem on its own rows, as for
+ * superdc_cauchy_apply):
+ *   trans 0: Y = G^T P X, rows of X indexed by output position (rows [0, k) holding the
+ *            reduced problem's Qhat applied to a block, rows [k, n_p) the block's deflated
+ *            rows unchanged), so that Y = Q (block);
+ *   trans 1: Y = P^T G X, rows of X indexed by pole, so that rows [0, k) of Y are the input
+ *            to Qhat^T and rows [k, n_p) are already rows of Q^T X.
+ * perm, rot_* as written by superdc_deflate for the same batch.  X and Y must not overlap.
+ */
+int superdc_deflate_expand(superdc_ctx *ctx, const superdc_batch *batch, const int32_t *perm,
+                           const int32_t *rot_right, const int32_t *rot_left,
+                           const double *rot_c, const double *rot_s, int trans, int32_t m,
+                           const double *X, int64_t ldx, double *Y, int64_t ldy, void *stream);
+
+/*
+ * Row copy between two batches with the same number of problems (a batch and its reduced
+ * problems), on total x m column-major blocks (leading dimensions lds >= src total,
+ * ldd >= dst total): for every problem p, rows [0, k_p) of p's rows in src go to the first
+ * k_p rows of p's rows in dst, k_p = min(n_src_p, n_dst_p, rows[p]) (rows: device
+ * int32[nprob], or NULL for no third bound).  With fill non-NULL (host pointer) the other
+ * rows of dst are set to *fill, else they are left as they are.  src and dst must differ.
+ */
+int superdc_batch_copy_rows(superdc_ctx *ctx, const superdc_batch *src_batch,
+                            const superdc_batch *dst_batch, const int32_t *rows, int32_t m,
+                            const double *src, int64_t lds, double *dst, int64_t ldd,
+                            const double *fill, void *stream);
+
+/* ------------------------------------------------------------------------------------
  * HSS conquering pass (Alg. 3) on a perfect binary tree.
  *
  * The symmetric HSS matrix is given by its generators (Sec. 2.1, eq. hss) with the leaf

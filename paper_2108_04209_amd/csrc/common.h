@@ -120,7 +120,8 @@ enum KernelId : int {
     KID_LOEWNER, KID_BNORM, KID_APPLY_MFMA, KID_APPLY_VALU, KID_BWD, KID_BWD_RHO, KID_LEAF,
     KID_MERGE, KID_ASSEMBLE, KID_PERMUTE, KID_LEAF_APPLY, KID_STATUS_OR, KID_FILL,
     KID_LEAF_VECTORS, KID_FMM_GEOM, KID_FMMV_PACK, KID_FMMV_SOURCES, KID_FMMV_EVAL,
-    KID_FMMV_EVAL_MFMA, KID_FMML_PACK, KID_FMML_MOMENTS, KID_LOEWNER_FMM, KID_COUNT
+    KID_FMMV_EVAL_MFMA, KID_FMML_PACK, KID_FMML_MOMENTS, KID_LOEWNER_FMM, KID_DEFLATE,
+    KID_DEFL_PLACE, KID_DEFL_ROTATE, KID_COPY_ROWS, KID_COUNT
 };
 
 // device counter of the pair evaluations of kernel `kid` while kernel timing is on (the
@@ -153,20 +154,21 @@ class TraceScope {
 #ifdef __cplusplus
 #include <vector>
 
+enum WsSlot {
+    WS_DW = 0, WS_KE = 1, WS_DZ = 2, WS_Z2 = 3, WS_BK = 4, WS_BP = 5, WS_TMP = 6, WS_VPAIR = 7,
+    WS_VSRC = 8, WS_DEFL_VAL = 9, WS_DEFL_FLAG = 10, WS_DEFL_T = 11, kNumWs
+};
+
 struct superdc_ctx {
     int device = 0;
     int num_cu = 256;
     // grow-only workspace buffers
-    void *ws[10] = {nullptr};
-    size_t ws_cap[10] = {0};
+    void *ws[kNumWs] = {nullptr};
+    size_t ws_cap[kNumWs] = {0};
     sdc::Queue *queues = nullptr;  // kNumQueues counters, zeroed at creation
     int fmm_crossover = 4096;      // automatic method: FMM for problems at least this large (measured)
 };
 
-enum WsSlot {
-    WS_DW = 0, WS_KE = 1, WS_DZ = 2, WS_Z2 = 3, WS_BK = 4, WS_BP = 5, WS_TMP = 6, WS_VPAIR = 7,
-    WS_VSRC = 8, kNumWs
-};
 enum QueueSlot {
     Q_SECULAR = 0, Q_LOEWNER, Q_BNORM, Q_APPLY, Q_BWD1, Q_BWD2, Q_VALIDATE, Q_SECULAR_FMM,
     Q_FMMV, kNumQueues
@@ -293,5 +295,21 @@ struct BwdArgs {
 };
 hipError_t launch_backward(const BwdArgs &a, int split, int prob_first, int nprob, Queue *q1,
                            Queue *q2, int grid, hipStream_t s);
+
+// deflation (deflate.hip)
+hipError_t launch_deflate(const int64_t *off, int nprob, const double *d, const double *z,
+                          const double *rho, double tau, double *dout, double *zout,
+                          int32_t *perm, int32_t *rright, int32_t *rleft, double *rc, double *rs,
+                          int32_t *kept, int32_t *status, double2 *val, int8_t *flag,
+                          hipStream_t s);
+hipError_t launch_deflate_expand(const int64_t *off, int nprob, int64_t total, int m,
+                                 const int32_t *perm, const int32_t *rright,
+                                 const int32_t *rleft, const double *rc, const double *rs,
+                                 int trans, const double *X, int64_t ldx, double *Y,
+                                 int64_t ldy, double *T, hipStream_t s);
+hipError_t launch_copy_rows(const int64_t *soff, const int64_t *doff, int nprob,
+                            int64_t dtotal, int m, const int32_t *rows, const double *src,
+                            int64_t lds, double *dst, int64_t ldd, const double *fill,
+                            hipStream_t s);
 }  // namespace sdc
 #endif

@@ -220,22 +220,20 @@ def small_batch(sizes, seed: int = 0, kind: str = "uniform", m: int = 0):
 def deflation_problem(n: int, g: np.random.Generator, rho: float = 1.0, dup_frac: float = 0.05,
                       near_frac: float = 0.10, tiny_frac: float = 0.05,
                       zero_frac: float = 0.01) -> RankOne:
-    """Poles that call for deflation: sorted U[0,1) where a share of the poles repeats its
-    left neighbour exactly (duplicates, also in runs) and a share sits a tiny distance
-    10^U[-15,-9] above it; z ~ N(0,1) normalised, with a share of entries replaced by
-    tiny values +-10^U[-14,-9] and a share by exact zeros.  d is non-decreasing, not
-    strictly increasing."""
-    u = np.sort(g.random(n))
+    """Poles that call for deflation: sorted U[0,1) points at least 1e-6 apart, where a share
+    of the poles repeats its left neighbour exactly (duplicates, also in runs) and a share
+    sits a tiny distance 10^U[-15,-9] above it; z ~ N(0,1) normalised, with a share of
+    entries replaced by tiny values +-10^U[-14,-9] and a share by exact zeros.  d is
+    non-decreasing, not strictly increasing."""
+    base = gapped_uniform(g, n, 0.0, 1.0, 1e-6) if n > 1 else g.random(n)
     kind = g.random(n)
-    gaps = 10.0 ** g.uniform(-15, -9, n)
-    d = u.copy()
-    for i in range(1, n):
-        if kind[i] < dup_frac:
-            d[i] = d[i - 1]
-        elif kind[i] < dup_frac + near_frac:
-            d[i] = d[i - 1] + gaps[i]
-        else:
-            d[i] = max(u[i], d[i - 1] + 1e-6)
+    kind[0] = 1.0
+    step = np.where(kind < dup_frac, 0.0, 10.0 ** g.uniform(-15, -9, n))
+    follow = kind < dup_frac + near_frac          # placed relative to its left neighbour
+    head = np.maximum.accumulate(np.where(follow, 0, np.arange(n)))
+    # offsets inside each run of followers: cumulative steps since the run's head
+    cs = np.cumsum(np.where(follow, step, 0.0))
+    d = base[head] + (cs - cs[head])
     z = g.standard_normal(n)
     z /= np.linalg.norm(z)
     zk = g.random(n)

@@ -81,6 +81,14 @@ def load_library(path: str = LIB_PATH):
     lib.superdc_kernel_work.restype = C.c_int
     lib.superdc_kernel_name.argtypes = [C.c_int32]
     lib.superdc_kernel_name.restype = C.c_char_p
+    lib.superdc_deflate.argtypes = [_P, _P, _P, _P, _P, C.c_double, _P, _P, _P, _P, _P, _P, _P,
+                                    _P, _P, _P]
+    lib.superdc_deflate.restype = C.c_int
+    lib.superdc_deflate_expand.argtypes = [_P, _P, _P, _P, _P, _P, _P, C.c_int, i32, _P, i64,
+                                           _P, i64, _P]
+    lib.superdc_deflate_expand.restype = C.c_int
+    lib.superdc_batch_copy_rows.argtypes = [_P, _P, _P, _P, i32, _P, i64, _P, i64, _P, _P]
+    lib.superdc_batch_copy_rows.restype = C.c_int
     _lib = lib
     return lib
 
@@ -219,6 +227,63 @@ def cauchy_apply(ctx, batch, d, zhat, bnorm, eta, origin, status, X, trans=0, op
         _ptr(status), int(trans), int(m), _ptr(X), int(ldx), _ptr(Y), int(Y.shape[1]),
         C.byref(o), _stream(stream)), "superdc_cauchy_apply")
     return Y
+
+
+def deflate(ctx, batch, d, z, rho, tau, stream=None, out=None):
+    """superdc_deflate.  Returns dict(d, z, perm, rot_right, rot_left, rot_c, rot_s, kept,
+    status) of device tensors (kept and status per problem)."""
+    import torch
+    tot, P = batch.total, batch.nprob
+    _f64(d, tot, "d"), _f64(z, tot, "z"), _f64(rho, P, "rho")
+    dev = d.device
+    if out is None:
+        f64 = dict(dtype=torch.float64, device=dev)
+        i32 = dict(dtype=torch.int32, device=dev)
+        out = dict(d=torch.empty(tot, **f64), z=torch.empty(tot, **f64),
+                   perm=torch.empty(tot, **i32), rot_right=torch.empty(tot, **i32),
+                   rot_left=torch.empty(tot, **i32), rot_c=torch.empty(tot, **f64),
+                   rot_s=torch.empty(tot, **f64), kept=torch.empty(P, **i32),
+                   status=torch.empty(P, **i32))
+    _check(load_library().superdc_deflate(
+        ctx.handle, batch.handle, _ptr(d), _ptr(z), _ptr(rho), float(tau), _ptr(out["d"]),
+        _ptr(out["z"]), _ptr(out["perm"]), _ptr(out["rot_right"]), _ptr(out["rot_left"]),
+        _ptr(out["rot_c"]), _ptr(out["rot_s"]), _ptr(out["kept"]), _ptr(out["status"]),
+        _stream(stream)), "superdc_deflate")
+    return out
+
+
+def deflate_expand(ctx, batch, df, X, trans=0, stream=None, Y=None):
+    """superdc_deflate_expand on an (m, ldx) row-major tensor (= column-major total x m)."""
+    import torch
+    if X.dim() == 1:
+        X = X.view(1, -1)
+    m, ldx = X.shape
+    if not X.is_contiguous() or X.dtype != torch.float64 or not X.is_cuda:
+        raise SuperdcError("X must be a contiguous CUDA float64 (m, ldx) tensor")
+    if Y is None:
+        Y = torch.empty((m, batch.total), dtype=torch.float64, device=X.device)
+    _check(load_library().superdc_deflate_expand(
+        ctx.handle, batch.handle, _ptr(df["perm"]), _ptr(df["rot_right"]), _ptr(df["rot_left"]),
+        _ptr(df["rot_c"]), _ptr(df["rot_s"]), int(trans), int(m), _ptr(X), int(ldx), _ptr(Y),
+        int(Y.shape[1]), _stream(stream)), "superdc_deflate_expand")
+    return Y
+
+
+def batch_copy_rows(ctx, src_batch, dst_batch, src, rows=None, fill=None, stream=None, dst=None):
+    """superdc_batch_copy_rows on (m, ld) row-major tensors (= column-major total x m)."""
+    import torch
+    if src.dim() == 1:
+        src = src.view(1, -1)
+    m, lds = src.shape
+    if not src.is_contiguous() or src.dtype != torch.float64 or not src.is_cuda:
+        raise SuperdcError("src must be a contiguous CUDA float64 (m, ld) tensor")
+    if dst is None:
+        dst = torch.empty((m, dst_batch.total), dtype=torch.float64, device=src.device)
+    fv = None if fill is None else C.byref(C.c_double(float(fill)))
+    _check(load_library().superdc_batch_copy_rows(
+        ctx.handle, src_batch.handle, dst_batch.handle, _ptr(rows), int(m), _ptr(src), int(lds),
+        _ptr(dst), int(dst.shape[-1]), fv, _stream(stream)), "superdc_batch_copy_rows")
+    return dst
 
 
 def secular_backward(ctx, batch, d, z, rho, eta, origin, status, g_lam=None, g_proj=None,

@@ -88,3 +88,53 @@ def backward_from(batch, eta, origin, g_lam=None, g_proj=None, u=None, opts=None
                                          g_proj=f(g_proj), u=f(u), opts=opts)
     torch.cuda.synchronize()
     return gd.cpu().numpy(), gz.cpu().numpy(), gr.cpu().numpy()
+
+
+def deflated_run(batch, tau, X=None, opts=None):
+    """Deflate every problem of a gen.Batch on the GPU, solve the reduced problems, and
+    (with X: host (total, m)) apply the full eigenvector matrix Q = G^T P (Qhat (+) I) and its
+    transpose.  Eigenvalue j of problem p belongs to output position j."""
+    ctx = context()
+    b = native.Batch(ctx, batch.off)
+    d, z, rho = to_dev(batch.d), to_dev(batch.z), to_dev(batch.rho)
+    df = native.deflate(ctx, b, d, z, rho, tau)
+    kept = df["kept"].cpu().numpy()
+    # the reduced batch: problems of kept[p] poles (one dummy pole where nothing is kept)
+    roff = np.concatenate([[0], np.cumsum(np.maximum(kept, 1))]).astype(np.int64)
+    rb = native.Batch(ctx, roff)
+    dr = native.batch_copy_rows(ctx, b, rb, df["d"], rows=df["kept"], fill=0.0).view(-1)
+    zr = native.batch_copy_rows(ctx, b, rb, df["z"], rows=df["kept"], fill=1.0).view(-1)
+    o = opts if opts is not None else native.default_opts()
+    s = native.secular_solve(ctx, rb, dr, zr, rho, opts=o)
+    lam = df["d"].clone()
+    native.batch_copy_rows(ctx, rb, b, s["lam"], rows=df["kept"], dst=lam.view(1, -1))
+    out = {"lam": lam, "kept": df["kept"], "dstatus": df["status"], "rstatus": s["status"],
+           "dfl": df}
+    if X is not None:
+        zh, bn = native.loewner(ctx, rb, dr, zr, rho, s["eta"], s["origin"], s["status"], opts=o)
+        Xt = to_dev(np.asarray(X).T)
+        # Q X: Qhat on the leading rows, the deflated rows as they are, then G^T P
+        Xr = native.batch_copy_rows(ctx, b, rb, Xt, rows=df["kept"], fill=0.0)
+        Yr = native.cauchy_apply(ctx, rb, dr, zh, bn, s["eta"], s["origin"], s["status"], Xr,
+                                 trans=0, opts=o)
+        U = Xt.clone()
+        native.batch_copy_rows(ctx, rb, b, Yr, rows=df["kept"], dst=U)
+        out["Y0"] = native.deflate_expand(ctx, b, df, U, trans=0)
+        # Q^T X: P^T G, then Qhat^T on the leading rows
+        V = native.deflate_expand(ctx, b, df, Xt, trans=1)
+        Vr = native.batch_copy_rows(ctx, b, rb, V, rows=df["kept"], fill=0.0)
+        Wr = native.cauchy_apply(ctx, rb, dr, zh, bn, s["eta"], s["origin"], s["status"], Vr,
+                                 trans=1, opts=o)
+        native.batch_copy_rows(ctx, rb, b, Wr, rows=df["kept"], dst=V)
+        out["Y1"] = V
+    torch.cuda.synchronize()
+    res = {}
+    for k, v in out.items():
+        if k == "dfl":
+            res[k] = {kk: vv.cpu().numpy() for kk, vv in v.items()}
+        else:
+            res[k] = v.cpu().numpy()
+    for t in (0, 1):
+        if f"Y{t}" in res:
+            res[f"Y{t}"] = res[f"Y{t}"].T
+    return res

@@ -42,6 +42,12 @@ def test_no_device_or_bad_args_fail_cleanly():
     assert lib.superdc_batch_create(None, 1, None, None) == -1
     assert lib.superdc_secular_solve(None, None, None, None, None, None, None, None, None, None,
                                      None, None) == -1
+    assert lib.superdc_deflate(None, None, None, None, None, 1e-10, None, None, None, None,
+                               None, None, None, None, None, None) == -1
+    assert lib.superdc_deflate_expand(None, None, None, None, None, None, None, 0, 1, None, 1,
+                                      None, 1, None) == -1
+    assert lib.superdc_batch_copy_rows(None, None, None, None, 1, None, 1, None, 1, None,
+                                       None) == -1
     o = native.default_opts()
     assert o.stop_c == 1.0 and o.max_iter == 40 and o.persistent == 1
     assert lib.superdc_strerror(-4) == b"no gfx950 device"
