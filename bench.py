@@ -39,7 +39,7 @@ FLOPS_LOEWNER = 5        # per pair: 2 sub, 1 add, 2 mul
 FLOPS_BNORM = 6          # per pair: 2 sub, 1 rcp, 1 mul, 1 fma(2)
 
 
-FMM_CROSSOVER = 4096     # the library's default direct/FMM switch (roots per problem)
+FMM_CROSSOVER = 1024     # the library's default direct/FMM switch (roots per problem)
 MFMA_MIN_M = 4           # the library's automatic VALU/MFMA apply switch (columns)
 
 
@@ -126,6 +126,9 @@ def parse():
     ap.add_argument("--fmm-crossover", type=int, default=0,
                     help="problems with at least this many roots use the FMM (0: the "
                          "library default, %d)" % FMM_CROSSOVER)
+    ap.add_argument("--fmm-leaf", type=int, default=64,
+                    help="poles per FMM leaf (multiple of 64, at most 1024; the library "
+                         "default is 64)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 512 MiB device-to-device copy (the reference kernel "
                          "that scales the profiler's FETCH_SIZE / WRITE_SIZE counters)")
@@ -150,7 +153,7 @@ def workload(name):
 class Pipeline:
     """Preallocated device buffers and the four C-ABI calls of one step."""
 
-    def __init__(self, batch, X, persistent, method=0, crossover=0):
+    def __init__(self, batch, X, persistent, method=0, crossover=0, leaf=256):
         import torch
         from paper_2108_04209_amd import native
         self.torch = torch
@@ -171,7 +174,7 @@ class Pipeline:
                    torch.empty(tot, dtype=torch.float64, device=dev))
         self.Y = torch.empty_like(self.X)
         self.opts = native.default_opts(persistent=persistent, method=method,
-                                        fmm_crossover=crossover)
+                                        fmm_crossover=crossover, fmm_leaf=leaf)
 
     def solve(self):
         self.native.secular_solve(self.ctx, self.b, self.d, self.z, self.rho, opts=self.opts,
@@ -276,7 +279,7 @@ def bench_level(args, name):
     sizes = batch.sizes().astype(np.float64)
     m = X.shape[1]
 
-    pipe = Pipeline(batch, X, persistent=1, crossover=args.fmm_crossover)
+    pipe = Pipeline(batch, X, persistent=1, crossover=args.fmm_crossover, leaf=args.fmm_leaf)
     wall_ms, tot_ms, ph = time_steps(pipe, args.steps, args.warmup)
     note(f"{name} batched {float(np.mean(tot_ms)):.2f} ms/step")
     iters = pipe.out["iters"].cpu().numpy().astype(np.float64)
@@ -320,7 +323,7 @@ def bench_level(args, name):
 
     plain_res = None
     if args.plain_steps > 0:
-        plain = Pipeline(batch, X, persistent=0, crossover=args.fmm_crossover)
+        plain = Pipeline(batch, X, persistent=0, crossover=args.fmm_crossover, leaf=args.fmm_leaf)
         p_wall, p_tot, p_ph = time_steps(plain, args.plain_steps, 1)
         p_ms = float(np.mean(p_tot))
         plain_res = {"ms_per_step": p_ms, "value": tot / (p_ms * 1e-3),
@@ -383,7 +386,7 @@ def bench_large(args):
     n, m = pr.n, X.shape[1]
     out = {}
     for name, method in (("fmm", 2), ("direct", 1)):
-        pipe = Pipeline(batch, X, persistent=1, method=method)
+        pipe = Pipeline(batch, X, persistent=1, method=method, leaf=256)  # as specified
         wall_ms, tot_ms, ph = time_steps(pipe, args.steps, args.warmup)
         iters = pipe.out["iters"].cpu().numpy().astype(np.float64)
         solve_ms, vec_ms, apply_ms = (float(x) for x in ph.mean(axis=0))
@@ -610,7 +613,8 @@ def bench_conquer(args):
     dev = torch.device("cuda:0")
     gens = {k: torch.as_tensor(v, dtype=torch.float64, device=dev)
             for k, v in native.pack_hss(tree).items()}
-    opts1 = native.default_opts(persistent=1, fmm_crossover=args.fmm_crossover)
+    opts1 = native.default_opts(persistent=1, fmm_crossover=args.fmm_crossover,
+                                fmm_leaf=args.fmm_leaf)
     out = native.hss_conquer(ctx, plan, gens, opts=opts1)
     native.hss_set_timing(plan, True)
 
@@ -694,7 +698,8 @@ def bench_conquer(args):
 
     plain_res = None
     if args.plain_steps > 0:
-        p_ms, p_ph, _ = timed(native.default_opts(persistent=0, fmm_crossover=args.fmm_crossover),
+        p_ms, p_ph, _ = timed(native.default_opts(persistent=0, fmm_crossover=args.fmm_crossover,
+                                                  fmm_leaf=args.fmm_leaf),
                               args.plain_steps, 1)
         plain_res = {"ms_per_step": p_ms, "value": roots / (p_ms * 1e-3),
                      "phase_ms": p_ph, "steps": args.plain_steps,

@@ -77,12 +77,12 @@ typedef struct {
     int32_t method;      /* 0 auto (direct below the crossover, FMM above), 1 direct sums,
                             2 triangular FMM (Sec. 4.1.2)                                 */
     int32_t fmm_order;   /* Chebyshev nodes per FMM box; 16 (the only supported order)      */
-    int32_t fmm_leaf;    /* FMM leaf size; default 256, a multiple of 64, at most 1024    */
+    int32_t fmm_leaf;    /* FMM leaf size; default 64, a multiple of 64, at most 1024     */
     int32_t persistent;  /* 1: one persistent launch per phase for the whole batch;
                             0: one launch per problem per phase (the "plain" baseline)    */
     int32_t apply_kernel;/* Cauchy apply: 0 auto (MFMA for m >= 4), 1 VALU, 2 FP64 MFMA    */
     int32_t fmm_crossover;/* method 0: problems with at least this many roots use the FMM
-                            (solver, b, Qhat^T X); 0 = the context's default (4096)       */
+                            (solver, b, Qhat^T X); 0 = the context's default (1024)       */
     int32_t reserved[2]; /* must be 0                                                     */
 } superdc_opts;
 

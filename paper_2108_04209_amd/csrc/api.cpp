@@ -580,7 +580,7 @@ void superdc_opts_default(superdc_opts *o) {
     o->max_iter = 40;
     o->method = 0;
     o->fmm_order = 16;
-    o->fmm_leaf = 256;
+    o->fmm_leaf = 64;
     o->persistent = 1;
     o->apply_kernel = 0;
 }

@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) void k_fmm_geom(FmmArgs f) {
 
 // secular equivalent sources of the boxes some target lists as far: one workgroup per box
 __global__ __launch_bounds__(256) void k_fmm_boxes(FmmArgs f) {
-    __shared__ double part[256][FMM_P + 1];
+    __shared__ double part[(256 / WAVE) * FMM_P];
     const int g = blockIdx.x;
     if (!f.used[g]) return;  // uniform: the whole workgroup leaves
     const BoxRange rg = box_range(f, g);
@@ -86,42 +86,45 @@ __global__ __launch_bounds__(256) void k_fmm_boxes(FmmArgs f) {
         tq[r] = cheb_node(r);
         lam[r] = cheb_bary(r);
     }
+    const double ihw = 1.0 / hw;
     for (int j = lo + tid; j < hi; j += blockDim.x) {
         const double2 pw = dw[j];
-        const double t = fmin(1.0, fmax(-1.0, (pw.x - c) / hw));
+        const double t = fmin(1.0, fmax(-1.0, (pw.x - c) * ihw));
         int hit = -1;
         double inv[FMM_P], den = 0.0;
 #pragma unroll
         for (int r = 0; r < FMM_P; ++r) {
             const double dlt = t - tq[r];
             if (dlt == 0.0) hit = r;
-            inv[r] = lam[r] / dlt;
+            inv[r] = lam[r] * rcp_nr(dlt);
             den += inv[r];
         }
         if (hit >= 0) {
             W[hit] += pw.y;  // the pole sits on a node
         } else {
-            const double s = pw.y / den;
+            const double s = pw.y * rcp_nr(den);
 #pragma unroll
             for (int r = 0; r < FMM_P; ++r) W[r] = __builtin_fma(s, inv[r], W[r]);
         }
     }
+    block_sum<FMM_P>(W, part);
+    if (tid < FMM_P) {
+        double wq = 0.0;
 #pragma unroll
-    for (int r = 0; r < FMM_P; ++r) part[tid][r] = W[r];
-    __syncthreads();
-    for (int stride = blockDim.x / 2; stride > 0; stride >>= 1) {
-        if (tid < stride)
-            for (int r = 0; r < FMM_P; ++r) part[tid][r] += part[tid + stride][r];
-        __syncthreads();
+        for (int r = 0; r < FMM_P; ++r) wq = r == tid ? W[r] : wq;
+        f.eq[(int64_t)g * FMM_P + tid] = make_double2(c + hw * tq[tid], wq);
     }
-    if (tid < FMM_P) f.eq[(int64_t)g * FMM_P + tid] = make_double2(c + hw * tq[tid], part[0][tid]);
 }
 
-// interaction lists: one thread per target leaf walks its problem's tree; far boxes are
-// flagged as used
-__global__ __launch_bounds__(64) void k_fmm_lists(FmmArgs f) {
-    const int L = blockIdx.x * blockDim.x + threadIdx.x;
-    if (L >= f.nleaves) return;
+// interaction lists: one wavefront per target leaf walks its problem's tree level by level.
+// Lane i holds the i-th candidate box of the level (children of the previous level's open
+// boxes, left to right).  A candidate separated from the leaf is far (flagged as used), a
+// leaf that is not is near, any other box opens its two children for the next level.  More
+// than 64 candidates on a level, or full lists, make the leaf fall back to direct sums.
+__global__ __launch_bounds__(WAVE) void k_fmm_lists(FmmArgs f) {
+    __shared__ int slot[WAVE];
+    const int L = blockIdx.x;
+    const int lane = threadIdx.x;
     const int q = f.leaf_fmm[L];
     const int p = f.fmm_prob[q];
     const int64_t base = f.off[p];
@@ -131,74 +134,100 @@ __global__ __launch_bounds__(64) void k_fmm_lists(FmmArgs f) {
     const int i0 = li * f.leaf, i1 = min(n, i0 + f.leaf);
     int32_t *cnt = f.cnt + 3 * (int64_t)L;
     if (f.status[p] & ~SUPERDC_ST_NOCONV) {
-        cnt[0] = -1;
+        if (lane == 0) cnt[0] = -1;
         return;
     }
     const double2 *dw = f.dw + base;
     const double xa = dw[i0].x;
     const double xb = i1 < n ? dw[i1].x : dw[n - 1].x + fmax(f.tail[p], 0.0);
-    int stack[64];
-    int sp = 0, nn = 0, nl = 0, nr = 0, nleaf = 0;
+    int32_t *far_l = f.far_l + (int64_t)L * FMM_FAR_MAX;
+    int32_t *far_r = f.far_r + (int64_t)L * FMM_FAR_MAX;
+    int32_t *near_lo = f.near_lo + (int64_t)L * FMM_NEAR_MAX;
+    int32_t *near_hi = f.near_hi + (int64_t)L * FMM_NEAR_MAX;
+    int hidx = 0, ncand = 1;  // the root
+    int nn = 0, nl = 0, nr = 0;
     bool overflow = false;
-    stack[sp++] = 0;
-    while (sp > 0 && !overflow) {
-        const int hidx = stack[--sp];
+    for (int h = 0; h <= H && ncand > 0 && !overflow; ++h) {
+        const bool valid = lane < ncand;
         const int g = f.box_off[q] + hidx;
-        const double2 ab = f.box_ab[g];
-        if (!(ab.x == ab.x)) continue;  // empty box
-        int h = 0;
-        while ((2 << h) - 1 <= hidx) ++h;
+        const double2 ab = valid ? f.box_ab[g] : make_double2(0.0, 0.0);
+        const bool live = valid && ab.x == ab.x;  // empty boxes are dropped
         const int i = hidx - ((1 << h) - 1);
         const int64_t span = (int64_t)f.leaf << (H - h);
         const int lo = (int)min((int64_t)n, i * span), hi = (int)min((int64_t)n, (i + 1) * span);
         const double width = ab.y - ab.x;
-        if (ab.y < xa && xa - ab.y >= f.sep * width && hi <= i0 - TILE) {
-            if (nl < FMM_FAR_MAX) {
-                f.far_l[(int64_t)L * FMM_FAR_MAX + nl++] = g;
-                f.used[g] = 1;
-            } else {
-                overflow = true;
-            }
-        } else if (ab.x > xb && ab.x - xb >= f.sep * width && lo >= i1 + TILE) {
-            if (nr < FMM_FAR_MAX) {
-                f.far_r[(int64_t)L * FMM_FAR_MAX + nr++] = g;
-                f.used[g] = 1;
-            } else {
-                overflow = true;
-            }
-        } else if (h == H) {
-            // leaves are visited left to right: a leaf adjacent to the previous near range
-            // extends it, so the near field is a few long contiguous ranges (still at most
-            // FMM_NEAR_MAX leaves in all)
-            if (++nleaf > FMM_NEAR_MAX) {
-                overflow = true;
-            } else if (nn > 0 && f.near_hi[(int64_t)L * FMM_NEAR_MAX + nn - 1] == lo) {
-                f.near_hi[(int64_t)L * FMM_NEAR_MAX + nn - 1] = hi;
-            } else if (nn < FMM_NEAR_MAX) {
-                f.near_lo[(int64_t)L * FMM_NEAR_MAX + nn] = lo;
-                f.near_hi[(int64_t)L * FMM_NEAR_MAX + nn] = hi;
-                ++nn;
-            } else {
-                overflow = true;
-            }
-        } else {
-            if (sp + 2 > 64) {
-                overflow = true;
-            } else {
-                stack[sp++] = 2 * hidx + 2;
-                stack[sp++] = 2 * hidx + 1;
-            }
+        const bool fl = live && ab.y < xa && xa - ab.y >= f.sep * width && hi <= i0 - TILE;
+        const bool fr = live && !fl && ab.x > xb && ab.x - xb >= f.sep * width && lo >= i1 + TILE;
+        const bool nr_leaf = live && !fl && !fr && h == H;
+        const bool open = live && !fl && !fr && h < H;
+        // far boxes, appended in lane order
+        const unsigned long long ml = __ballot(fl), mr = __ballot(fr);
+        const int rl = __builtin_amdgcn_mbcnt_hi((unsigned)(ml >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)ml, 0u));
+        const int rr = __builtin_amdgcn_mbcnt_hi((unsigned)(mr >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mr, 0u));
+        if (nl + __popcll(ml) > FMM_FAR_MAX || nr + __popcll(mr) > FMM_FAR_MAX) {
+            overflow = true;
+            break;
         }
+        if (fl) {
+            far_l[nl + rl] = g;
+            f.used[g] = 1;
+        }
+        if (fr) {
+            far_r[nr + rr] = g;
+            f.used[g] = 1;
+        }
+        nl += __popcll(ml);
+        nr += __popcll(mr);
+        // near leaves (ascending), adjacent ones merged into one range
+        const unsigned long long mn = __ballot(nr_leaf);
+        if (mn) {
+            if (__popcll(mn) > FMM_NEAR_MAX) {
+                overflow = true;
+                break;
+            }
+            const unsigned long long below = lane ? (mn & ((1ull << lane) - 1)) : 0ull;
+            const int prev = below ? 63 - __builtin_clzll(below) : -1;
+            const int hprev = __shfl(hi, prev < 0 ? 0 : prev);
+            const bool start = nr_leaf && (prev < 0 || hprev != lo);
+            const unsigned long long ms = __ballot(start);
+            const int rs = __builtin_amdgcn_mbcnt_hi((unsigned)(ms >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)ms, 0u));
+            // the run of a start lane ends at the last near lane before the next start
+            const unsigned long long after = lane < 63 ? (ms & ~((2ull << lane) - 1)) : 0ull;
+            const int nxt = after ? __builtin_ctzll(after) : 64;
+            const unsigned long long upto = nxt < 64 ? (mn & ((1ull << nxt) - 1)) : mn;
+            const int last = upto ? 63 - __builtin_clzll(upto) : 0;
+            const int hend = __shfl(hi, last);
+            if (start) {
+                near_lo[nn + rs] = lo;
+                near_hi[nn + rs] = hend;
+            }
+            nn += __popcll(ms);
+        }
+        // the children of the open boxes, in order, are the next level's candidates
+        const unsigned long long mo = __ballot(open);
+        const int no = __popcll(mo);
+        if (2 * no > WAVE) {
+            overflow = true;
+            break;
+        }
+        const int ro = __builtin_amdgcn_mbcnt_hi((unsigned)(mo >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mo, 0u));
+        __syncthreads();
+        if (open) slot[ro] = hidx;
+        __syncthreads();
+        ncand = 2 * no;
+        hidx = lane < ncand ? 2 * slot[lane >> 1] + 1 + (lane & 1) : 0;
     }
-    cnt[0] = overflow ? -1 : nn;  // -1: the leaf falls back to direct sums
-    cnt[1] = nl;
-    cnt[2] = nr;
+    if (lane == 0) {
+        cnt[0] = overflow ? -1 : nn;  // -1: the leaf falls back to direct sums
+        cnt[1] = nl;
+        cnt[2] = nr;
+    }
 }
 
 hipError_t launch_fmm_lists(const FmmArgs &f, hipStream_t s) {
     if (f.nboxes <= 0) return hipSuccess;
     SDC_LAUNCH(KID_FMM_GEOM, k_fmm_geom, dim3((f.nboxes + 255) / 256), dim3(256), 0, s, f);
-    SDC_LAUNCH(KID_FMM_LISTS, k_fmm_lists, dim3((f.nleaves + 63) / 64), dim3(64), 0, s, f);
+    SDC_LAUNCH(KID_FMM_LISTS, k_fmm_lists, dim3(f.nleaves), dim3(WAVE), 0, s, f);
     return hipGetLastError();
 }
 

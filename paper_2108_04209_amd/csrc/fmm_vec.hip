@@ -53,13 +53,16 @@ __global__ __launch_bounds__(64) void k_fmmv_pack(FmmvPackArgs a, FmmVec v) {
 // compresses every leaf box from its poles; LEAVES = false compresses every used box above
 // the leaves from the equivalent sources of its leaves (16 per leaf instead of up to
 // n/4 poles: the far field of a leaf's sources equals that of its poles to the
-// interpolation accuracy, and the box's nodes interpolate it again).  Points are taken
-// 256 at a time: each thread forms the 16 Lagrange values of one point in LDS, then thread
-// (q, c) accumulates sum_k L_q(x_k) w_k,c over the chunk.
+// interpolation accuracy, and the box's nodes interpolate it again).  Points are taken a
+// chunk at a time: each of the chunk's threads forms the 16 Lagrange values of one point in
+// LDS, then thread (q, c) accumulates sum_k L_q(x_k) w_k,c over the chunk.
 template <bool LEAVES>
 __global__ __launch_bounds__(256) void k_fmmv_sources(FmmArgs f, FmmVec v) {
-    __shared__ double Lq[256][FMM_P + 1];
-    __shared__ double Ss[256][FMMV_MAX_M + 1];
+    // points per chunk: leaves (a few hundred poles at most) in chunks of 64 and a small
+    // LDS footprint, upper boxes (up to 16 sources per leaf below) 256 at a time
+    constexpr int FV_CHUNK = LEAVES ? 64 : 256;
+    __shared__ double Lq[FV_CHUNK][FMM_P + 1];
+    __shared__ double Ss[FV_CHUNK][FMMV_MAX_M + 1];
     const int g = blockIdx.x;
     const int qf = f.box_fmm[g];
     const int p = f.fmm_prob[qf];
@@ -105,9 +108,11 @@ __global__ __launch_bounds__(256) void k_fmmv_sources(FmmArgs f, FmmVec v) {
     }
     const double ihw = 1.0 / hw;
     double acc = 0.0;
-    for (int k0 = 0; k0 < npts; k0 += 256) {
+    for (int k0 = 0; k0 < npts; k0 += FV_CHUNK) {
         const int k = k0 + tid;
-        if (k < npts) {
+        if (tid >= FV_CHUNK) {
+            // the chunk's points have their threads
+        } else if (k < npts) {
             double x;
             const double *wk;
             if (LEAVES) {
@@ -140,7 +145,7 @@ __global__ __launch_bounds__(256) void k_fmmv_sources(FmmArgs f, FmmVec v) {
         }
         __syncthreads();
         if (c < m) {
-            const int cnt = min(256, npts - k0);
+            const int cnt = min(FV_CHUNK, npts - k0);
             for (int kk = 0; kk < cnt; ++kk) acc = __builtin_fma(Lq[kk][q], Ss[kk][c], acc);
         }
         __syncthreads();

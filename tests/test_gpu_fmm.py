@@ -16,18 +16,20 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def solve(batch, method, persistent=1, vectors=False, X=None):
+def solve(batch, method, persistent=1, vectors=False, X=None, leaf=64):
     from paper_2108_04209_amd import native
     from tests import gpu_pipeline as gp
     return gp.run(batch, X=X, trans=(0,) if X is not None else (),
-                  opts=native.default_opts(method=method, persistent=persistent),
+                  opts=native.default_opts(method=method, persistent=persistent, fmm_leaf=leaf),
                   vectors=vectors)
 
 
-@pytest.mark.parametrize("kind,n", [("clustered", 4096), ("uniform", 3000), ("clustered", 16384)])
-def test_fmm_vs_oracle(orc, kind, n):
+@pytest.mark.parametrize("kind,n,leaf", [("clustered", 4096, 64), ("clustered", 4096, 256),
+                                         ("uniform", 3000, 64), ("uniform", 3000, 128),
+                                         ("clustered", 16384, 64)])
+def test_fmm_vs_oracle(orc, kind, n, leaf):
     batch = gen.small_batch([n], seed=61, kind=kind)
-    res = solve(batch, method=2)
+    res = solve(batch, method=2, leaf=leaf)
     assert res["status"][0] == 0
     pr = batch.problem(0)
     lam, eta, org, its, st = orc.secular(pr.d, pr.z, pr.rho)
@@ -89,14 +91,15 @@ def test_large_clustered_fmm_vs_direct(orc):
 
 
 # ------------------------------------------------------ eigenvector-side FMM (b, Qhat^T X)
-def _opts(method, persistent=1):
+def _opts(method, persistent=1, leaf=64):
     from paper_2108_04209_amd import native
-    return native.default_opts(method=method, persistent=persistent)
+    return native.default_opts(method=method, persistent=persistent, fmm_leaf=leaf)
 
 
-@pytest.mark.parametrize("kind,n,m", [("clustered", 4096, 5), ("uniform", 3000, 16),
-                                      ("clustered", 16384, 20)])
-def test_fmm_vectors_vs_oracle(orc, kind, n, m):
+@pytest.mark.parametrize("kind,n,m,leaf", [("clustered", 4096, 5, 64), ("clustered", 4096, 5, 256),
+                                           ("uniform", 3000, 16, 64), ("clustered", 16384, 20, 64),
+                                           ("clustered", 16384, 20, 256)])
+def test_fmm_vectors_vs_oracle(orc, kind, n, m, leaf):
     """zhat, b and Y = Qhat^T X through the FMM (method 2), fed the oracle's (eta, origin),
     against the oracle: zhat and b to 1e-12 relative per entry, sampled rows of Y to 1e-12 sum_i |Qhat_ij X_i|
     (the FMM's far-field interpolation error is ~5e-15 of that sum), and against the direct
@@ -107,10 +110,10 @@ def test_fmm_vectors_vs_oracle(orc, kind, n, m):
     lam, eta, org, its, st = orc.secular(pr.d, pr.z, pr.rho)
     zo = orc.loewner(pr.d, pr.z, pr.rho, eta, org)
     bo = orc.bnorm(pr.d, zo, eta, org)
-    zf, bf = gp.loewner_from(batch, eta, org, opts=_opts(2))
+    zf, bf = gp.loewner_from(batch, eta, org, opts=_opts(2, leaf=leaf))
     assert np.all(np.abs(zf - zo) <= 1e-12 * np.abs(zo))
     assert np.all(np.abs(bf - bo) <= 1e-12 * np.abs(bo)), np.max(np.abs(bf - bo) / np.abs(bo))
-    Yf = gp.apply_from(batch, zo, bo, eta, org, X, 1, opts=_opts(2))
+    Yf = gp.apply_from(batch, zo, bo, eta, org, X, 1, opts=_opts(2, leaf=leaf))
     Yd = gp.apply_from(batch, zo, bo, eta, org, X, 1, opts=_opts(1))
     rng = np.random.default_rng(3)
     rows = np.unique(np.r_[0, n - 1, rng.choice(n, 62, replace=False)])
@@ -124,7 +127,7 @@ def test_fmm_vectors_vs_oracle(orc, kind, n, m):
 
 @pytest.mark.parametrize("persistent", [1, 0])
 def test_fmm_vectors_mixed_batch(orc, persistent):
-    """FMM problems (n >= 512 under method 2) and direct ones in one call, fed the oracle's
+    """FMM problems (n >= two leaves under method 2) and direct ones in one call, fed the oracle's
     (eta, origin): zhat, b and Qhat^T X agree with the all-direct path."""
     from tests import gpu_pipeline as gp
     batch, X = gen.small_batch([100, 1500, 5000, 64, 2048, 700], seed=64, kind="clustered", m=7)

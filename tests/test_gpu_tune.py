@@ -51,7 +51,7 @@ def test_kernel_timing():
     native.kernel_times()  # drop anything collected before
     native.kernel_timing(True)
     try:
-        res = native.secular_solve(ctx, b, d, z, rho)
+        res = native.secular_solve(ctx, b, d, z, rho, opts=native.default_opts(method=1))
         kt = native.kernel_times()
         kw = native.kernel_work()
     finally:
