@@ -644,6 +644,27 @@ def bench_conquer(args):
     sec_f, vec_f, app_f = conquer_flops(tree, iters)
     roots = tree.depth * tree.r * tree.n
 
+    # ablation of the local shifting (Sec. 4.2.2): the same conquer with the iterate kept as
+    # lambda itself; per level, the largest share over the r rank-one steps of roots that
+    # needed more than 5 iterations, and the eigenvalues against the shifted run
+    abl = None
+    if not args.no_level:
+        o_un = native.default_opts(persistent=1, fmm_crossover=args.fmm_crossover,
+                                   fmm_leaf=args.fmm_leaf, unshifted=1)
+        un = native.hss_conquer(ctx, plan, gens, opts=o_un)
+        torch.cuda.synchronize()
+        it_un = native.hss_iterations(plan).cpu().numpy()
+        lam_un = un["lam"].cpu().numpy()
+        mu = lambda it: [float(100.0 * np.max(np.mean(it[l] > 5, axis=1))) for l in range(it.shape[0])]
+        abl = {"levels_n": [int(tree.leaf << (tree.depth - l)) for l in range(tree.depth)],
+               "mu_percent_shifted": mu(iters), "mu_percent_unshifted": mu(it_un),
+               "status_unshifted": int(un["status"].cpu().numpy()[0]),
+               "nonfinite_unshifted": int(np.count_nonzero(~np.isfinite(lam_un)))}
+        fin = np.isfinite(lam_un)
+        abl["max_lam_diff_rel_normA_finite"] = (
+            float(np.abs(lam_un[fin] - lam[fin]).max() / np.abs(lam).max()) if fin.any() else None)
+        native.hss_conquer(ctx, plan, gens, opts=opts1, out=out)  # restore the shifted state
+        torch.cuda.synchronize()
     # graph replay of the same step (timing events off while capturing)
     graph_ms = None
     native.hss_set_timing(plan, False)
@@ -722,6 +743,7 @@ def bench_conquer(args):
         "phase_ms": phases, "phase_intervals": counts, "kernels": kernels,
         "mean_iters_after_midpoint": float(iters.mean()), "max_iters": int(iters.max()),
         "graph": graph_ms,
+        "ablation_unshifted": abl,
         "plain": plain_res,
         "speedup_batched_vs_plain": None if plain_res is None else plain_res["ms_per_step"] / ms,
         "accuracy": {"status": status, "trace_err_rel": tr_err,

@@ -83,7 +83,10 @@ typedef struct {
     int32_t apply_kernel;/* Cauchy apply: 0 auto (MFMA for m >= 4), 1 VALU, 2 FP64 MFMA    */
     int32_t fmm_crossover;/* method 0: problems with at least this many roots use the FMM
                             (solver, b, Qhat^T X); 0 = the context's default (1024)       */
-    int32_t reserved[2]; /* must be 0                                                     */
+    int32_t unshifted;   /* 1: ablation of the local shifting (Sec. 4.2.2): the iterate is
+                            kept as lambda itself and every pole difference is formed as
+                            d_j - lambda, the original secular equation; default 0     */
+    int32_t reserved;    /* must be 0                                                     */
 } superdc_opts;
 
 void superdc_opts_default(superdc_opts *opts);

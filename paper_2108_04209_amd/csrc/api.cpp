@@ -40,8 +40,8 @@ int opts_check(const superdc_opts *o) {
     if (o->persistent != 0 && o->persistent != 1) return SUPERDC_EINVAL;
     if (o->apply_kernel < 0 || o->apply_kernel > 2) return SUPERDC_EINVAL;
     if (o->fmm_crossover < 0) return SUPERDC_EINVAL;
-    for (int i = 0; i < 2; ++i)
-        if (o->reserved[i] != 0) return SUPERDC_EINVAL;
+    if (o->unshifted != 0 && o->unshifted != 1) return SUPERDC_EINVAL;
+    if (o->reserved != 0) return SUPERDC_EINVAL;
     return SUPERDC_OK;
 }
 
@@ -710,6 +710,7 @@ int superdc_secular_solve(superdc_ctx *ctx, const superdc_batch *b, const double
     a.status = status;
     a.stop_c = o.stop_c;
     a.max_iter = o.max_iter;
+    a.unshifted = o.unshifted;
     superdc_batch *bm = const_cast<superdc_batch *>(b);
     // problems at or above the crossover size use the triangular FMM (method 2: every
     // problem large enough to have two leaves; method 1: none)

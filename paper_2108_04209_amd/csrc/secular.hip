@@ -253,8 +253,8 @@ __device__ __forceinline__ void secular_range(const_double2_ptr dw, int j0, int 
 // takes a contiguous 1/S of the poles and the partial sums are combined afterwards.
 __device__ __forceinline__ void secular_sums(const double2 *__restrict__ dwg, int n, int p0,
                                              int p1, int kmin, int kmax, int k, double dK,
-                                             double y, double &psi, double &dpsi, double &phi,
-                                             double &dphi) {
+                                             double y, bool unsh, double &psi, double &dpsi,
+                                             double &phi, double &dphi) {
     const_double2_ptr dw = as_const(dwg);
     kmin = wave_uniform(kmin);
     kmax = wave_uniform(kmax);
@@ -263,11 +263,15 @@ __device__ __forceinline__ void secular_sums(const double2 *__restrict__ dwg, in
     p1 = wave_uniform(p1);
     psi = dpsi = phi = dphi = 0.0;
     const double x = dK + y;
-    const int f0 = max(kmin - TILE, 0), f1 = min(kmax + 1 + TILE, n);
+    // unshifted (ablation): every pole in lambda-form, none shifted
+    const int f0 = unsh ? kmin : max(kmin - TILE, 0), f1 = unsh ? kmax + 1 : min(kmax + 1 + TILE, n);
 #define SDC_CLIP(A, B) max((A), p0), min((B), p1)
     secular_range<0, true>(dw, SDC_CLIP(0, f0), k, dK, y, x, psi, dpsi, phi, dphi);
     secular_range<0, false>(dw, SDC_CLIP(f0, kmin), k, dK, y, x, psi, dpsi, phi, dphi);
-    secular_range<2, false>(dw, SDC_CLIP(kmin, kmax + 1), k, dK, y, x, psi, dpsi, phi, dphi);
+    if (unsh)
+        secular_range<2, true>(dw, SDC_CLIP(kmin, kmax + 1), k, dK, y, x, psi, dpsi, phi, dphi);
+    else
+        secular_range<2, false>(dw, SDC_CLIP(kmin, kmax + 1), k, dK, y, x, psi, dpsi, phi, dphi);
     secular_range<1, false>(dw, SDC_CLIP(kmax + 1, f1), k, dK, y, x, psi, dpsi, phi, dphi);
     secular_range<1, true>(dw, SDC_CLIP(f1, n), k, dK, y, x, psi, dpsi, phi, dphi);
 #undef SDC_CLIP
@@ -304,8 +308,8 @@ __device__ __forceinline__ void split_reduce4(double *red, int S, double &a, dou
 // and the far boxes e = wv (mod S).
 __device__ __forceinline__ void fmm_sums(const FmmArgs &f, int L, int nn, int nl, int nr,
                                          const double2 *__restrict__ dwg, int kmin, int kmax,
-                                         int k, double dK, double y, int wv, int S, double &psi,
-                                         double &dpsi, double &phi, double &dphi) {
+                                         int k, double dK, double y, int wv, int S, bool unsh,
+                                         double &psi, double &dpsi, double &phi, double &dphi) {
     const_double2_ptr dw = as_const(dwg);
     kmin = wave_uniform(kmin);
     kmax = wave_uniform(kmax);
@@ -314,7 +318,7 @@ __device__ __forceinline__ void fmm_sums(const FmmArgs &f, int L, int nn, int nl
     const double x = dK + y;
     // near leaves: the same window split as the direct sums, so only poles within one tile
     // of the live roots take the shifted form
-    const int f0 = kmin - TILE, f1 = kmax + 1 + TILE;
+    const int f0 = unsh ? kmin : kmin - TILE, f1 = unsh ? kmax + 1 : kmax + 1 + TILE;
     for (int e = 0; e < nn; ++e) {
         const int lo0 = wave_uniform(f.near_lo[(int64_t)L * FMM_NEAR_MAX + e]);
         const int hi0 = wave_uniform(f.near_hi[(int64_t)L * FMM_NEAR_MAX + e]);
@@ -322,8 +326,12 @@ __device__ __forceinline__ void fmm_sums(const FmmArgs &f, int L, int nn, int nl
         const int hi = lo0 + (int)(((int64_t)(hi0 - lo0) * (wv + 1)) / S);
         secular_range<0, true>(dw, lo, min(hi, f0), k, dK, y, x, psi, dpsi, phi, dphi);
         secular_range<0, false>(dw, max(lo, f0), min(hi, kmin), k, dK, y, x, psi, dpsi, phi, dphi);
-        secular_range<2, false>(dw, max(lo, kmin), min(hi, kmax + 1), k, dK, y, x, psi, dpsi, phi,
-                                dphi);
+        if (unsh)
+            secular_range<2, true>(dw, max(lo, kmin), min(hi, kmax + 1), k, dK, y, x, psi, dpsi,
+                                   phi, dphi);
+        else
+            secular_range<2, false>(dw, max(lo, kmin), min(hi, kmax + 1), k, dK, y, x, psi, dpsi,
+                                    phi, dphi);
         secular_range<1, false>(dw, max(lo, kmax + 1), min(hi, f1), k, dK, y, x, psi, dpsi, phi,
                                 dphi);
         secular_range<1, true>(dw, max(lo, f1), hi, k, dK, y, x, psi, dpsi, phi, dphi);
@@ -384,6 +392,7 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
     const double z2 = a.z2[p];
     const double eps = 2.220446049250313e-16;
     const double tol = a.stop_c * (double)n * eps;
+    const bool unsh = a.unshifted != 0;  // ablation: the iterate lives in lambda's precision
     // FMM: the target leaf of this chunk and its list sizes (-1: fall back to direct sums)
     int L = 0, nn = -1, nl = 0, nr = 0;
     if (FMM) {
@@ -426,6 +435,7 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
             dk1 = last ? dk : dw[k + 1].x;
             dK = dk;
             y = last ? 0.5 * z2 : 0.5 * (dk1 - dk);  // midpoint pass
+            if (unsh) y = (dK + y) - dK;
             phase = 0;
             nev = 0;
             hi_closed = false;
@@ -437,9 +447,10 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
 
         double psi, dpsi, phi, dphi;
         if (FMM && nn >= 0)
-            fmm_sums(*fm, L, nn, nl, nr, dw, kmin, kmax, k, dK, y, wv, S, psi, dpsi, phi, dphi);
+            fmm_sums(*fm, L, nn, nl, nr, dw, kmin, kmax, k, dK, y, wv, S, unsh, psi, dpsi, phi,
+                     dphi);
         else
-            secular_sums(dw, n, p0, p1, kmin, kmax, k, dK, y, psi, dpsi, phi, dphi);
+            secular_sums(dw, n, p0, p1, kmin, kmax, k, dK, y, unsh, psi, dpsi, phi, dphi);
         split_reduce4(red, S, psi, dpsi, phi, dphi);
         if (a.work) work += (unsigned long long)pairs_per_pass * (unsigned long long)__popcll(__ballot(act));
         if (!act) continue;
@@ -455,6 +466,7 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
                     K = k + 1;
                     dK = dk1;
                     y = -y;
+                    if (unsh) y = (dK + y) - dK;
                     lo = y;
                     hi = 0.0;
                 }
@@ -485,8 +497,9 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
             double yn;
             if (!last) {
                 // middle-way: psi ~ a1 + b1/(d_k - x), phi ~ a2 + b2/(d_{k+1} - x)
-                const double A = (dk - dK) - y;   // < 0
-                const double B = (dk1 - dK) - y;  // > 0
+                const double xl = dK + y;
+                const double A = unsh ? dk - xl : (dk - dK) - y;   // < 0
+                const double B = unsh ? dk1 - xl : (dk1 - dK) - y;  // > 0
                 const double C = f - dpsi * A - dphi * B;
                 const double qa = C * (A + B) + dpsi * A * A + dphi * B * B;
                 const double qb = A * B * f;
@@ -500,6 +513,7 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
             const bool inside = (yn > lo) && (yn < hi || (hi_closed && yn == hi));
             if (!inside || !isfinite(yn)) yn = 0.5 * (lo + hi);
             // a step below rounding, or a collapsed bracket: accept without re-evaluation
+            if (unsh) yn = (dK + yn) - dK;  // lambda = d_K + y rounded, as the iterate itself
             if (fabs(yn - y) <= 2.0 * eps * fabs(yn) ||
                 hi - lo <= 2.0 * eps * fmax(fabs(lo), fabs(hi)))
                 done = true;

@@ -1,0 +1,85 @@
+"""The ablation of local shifting (opts.unshifted = 1): the iterate is kept as lambda and
+every pole difference is formed as d_j - lambda, the original secular equation.
+
+What it must show (Sec. 4.2, and the comparison the paper makes with and without local
+shifting):
+  - eigenvalues themselves stay within 1e-12 ||A||_2 on well-separated poles: the error
+    of each d_j - lambda is eps |lambda|, absolute;
+  - the gaps eta = lambda - d_K lose their relative accuracy: with rho = 1e-20 lambda rounds
+    to d_K and the unshifted eta is off by O(1) relatively, while the shifted solver keeps
+    eta to 1e-12 relatively, and the Cauchy-like eigenvector matrix built from the
+    unshifted gaps is far from orthogonal, or NaN where a gap rounded to zero;
+  - inside clusters of poles the unshifted gaps are off by orders of magnitude more than
+    the shifted ones.
+"""
+import numpy as np
+import pytest
+
+from paper_2108_04209_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def run(batch, unshifted, vectors=False, method=0):
+    from paper_2108_04209_amd import native
+    from tests import gpu_pipeline as gp
+    return gp.run(batch, opts=native.default_opts(unshifted=unshifted, method=method),
+                  vectors=vectors)
+
+
+def test_unshifted_eigenvalues_on_separated_poles(orc):
+    batch = gen.small_batch([1024, 300, 4096], seed=81, kind="uniform")
+    res = run(batch, 1)
+    for p in range(batch.nprob):
+        a, e = int(batch.off[p]), int(batch.off[p + 1])
+        pr = batch.problem(p)
+        lam = orc.secular(pr.d, pr.z, pr.rho)[0]
+        assert np.abs(res["lam"][a:e] - lam).max() <= 1e-12 * np.abs(lam).max(), p
+
+
+def test_unshifted_loses_the_gaps(orc):
+    batch = gen.small_batch([512], seed=82, kind="tinyrho")
+    pr = batch.problem(0)
+    lam_o, eta_o, org_o, its_o, st_o = orc.secular(pr.d, pr.z, pr.rho)
+    sh = run(batch, 0, vectors=True)
+    un = run(batch, 1, vectors=True)
+    rel = lambda r: np.abs(r["eta"] - eta_o) / np.abs(eta_o)
+    assert rel(sh).max() <= 1e-12
+    assert np.median(rel(un)) >= 1e-3
+    # Qhat from each run's own (zhat, b, eta, origin): orthogonal only with shifting
+    from tests import gpu_pipeline as gp
+    n = pr.n
+    cols = np.arange(0, n, 16)
+    E = np.zeros((n, len(cols)))
+    E[cols, np.arange(len(cols))] = 1.0
+    orth = {}
+    for name, r in (("sh", sh), ("un", un)):
+        Q = gp.apply_from(batch, r["zhat"], r["b"], r["eta"], r["origin"], E, 0)
+        orth[name] = np.abs(Q.T @ Q - np.eye(len(cols))).max()
+    assert orth["sh"] <= 1e-12
+    # gaps that round to zero give infinite Cauchy entries: NaN, the failure the paper reports
+    # for the unshifted equation, or at best a matrix far from orthogonal
+    assert not orth["un"] <= 1e-6
+
+
+@pytest.mark.parametrize("method", [1, 2])
+def test_unshifted_inside_clusters(orc, method):
+    """Roots inside clusters of poles 1e-10 apart (direct sums and FMM): the shifted gaps
+    match the oracle's to 1e-10 relatively, the unshifted ones are off by ~eps |lambda| /
+    gap, orders of magnitude more."""
+    batch = gen.small_batch([4096], seed=83, kind="clustered")
+    pr = batch.problem(0)
+    sh = run(batch, 0, method=method)
+    un = run(batch, 1, method=method)
+    assert sh["status"][0] == 0
+    tight = np.flatnonzero(np.diff(pr.d) < 1e-9)
+    roots = tight[:: max(1, tight.size // 48)]
+    lam_o, eta_o, org_o, its_o, st_o = orc.secular(pr.d, pr.z, pr.rho, roots=roots)
+    assert np.array_equal(sh["origin"][roots], org_o)
+    err = lambda r: np.abs(r["eta"][roots] - eta_o) / np.abs(eta_o)
+    assert err(sh).max() <= 1e-10
+    med = np.median(err(un))  # NaN (a gap that rounded to zero) also fails the bars below
+    assert not med <= 1e-7
+    assert not med <= 100 * max(err(sh).max(), 1e-16)
