@@ -15,6 +15,8 @@
 
 namespace sdc {
 
+typedef double v4d_f __attribute__((ext_vector_type(4)));
+
 namespace {
 
 __device__ __forceinline__ double cheb_node_v(int q) {
@@ -55,7 +57,7 @@ __global__ __launch_bounds__(64) void k_fmmv_pack(FmmvPackArgs a, FmmVec v) {
 // n/4 poles: the far field of a leaf's sources equals that of its poles to the
 // interpolation accuracy, and the box's nodes interpolate it again).  Points are taken a
 // chunk at a time: each of the chunk's threads forms the 16 Lagrange values of one point in
-// LDS, then thread (q, c) accumulates sum_k L_q(x_k) w_k,c over the chunk.
+// LDS, then W_q,c += sum_k L_q(x_k) w_k,c over the chunk runs on the FP64 MFMA.
 template <bool LEAVES>
 __global__ __launch_bounds__(256) void k_fmmv_sources(FmmArgs f, FmmVec v) {
     // points per chunk: leaves (a few hundred poles at most) in chunks of 64 and a small
@@ -99,7 +101,7 @@ __global__ __launch_bounds__(256) void k_fmmv_sources(FmmArgs f, FmmVec v) {
     const int leaf0 = (1 << H) - 1 + bi * (1 << (H - h));      // heap index of the first leaf
     const int nleaf = (int)((hi - lo + f.leaf - 1) / f.leaf);  // leaves with poles
     const int npts = LEAVES ? hi - lo : nleaf * FMM_P;
-    const int q = tid / FMMV_MAX_M, c = tid % FMMV_MAX_M;  // accumulator of this thread
+    const int lane = tid & (WAVE - 1), wv = tid / WAVE;
     double tq[FMM_P], lam[FMM_P];
 #pragma unroll
     for (int r = 0; r < FMM_P; ++r) {
@@ -107,7 +109,7 @@ __global__ __launch_bounds__(256) void k_fmmv_sources(FmmArgs f, FmmVec v) {
         lam[r] = cheb_bary_v(r);
     }
     const double ihw = 1.0 / hw;
-    double acc = 0.0;
+    v4d_f acc = v4d_f{0.0, 0.0, 0.0, 0.0};
     for (int k0 = 0; k0 < npts; k0 += FV_CHUNK) {
         const int k = k0 + tid;
         if (tid >= FV_CHUNK) {
@@ -137,21 +139,42 @@ __global__ __launch_bounds__(256) void k_fmmv_sources(FmmArgs f, FmmVec v) {
 #pragma unroll
             for (int r = 0; r < FMM_P; ++r)
                 Lq[tid][r] = hit >= 0 ? (r == hit ? 1.0 : 0.0) : inv[r] * iden;
-            for (int cc2 = 0; cc2 < m; ++cc2) Ss[tid][cc2] = wk[cc2];
+            for (int cc2 = 0; cc2 < FMMV_MAX_M; ++cc2) Ss[tid][cc2] = cc2 < m ? wk[cc2] : 0.0;
         } else {
 #pragma unroll
             for (int r = 0; r < FMM_P; ++r) Lq[tid][r] = 0.0;
-            for (int cc2 = 0; cc2 < m; ++cc2) Ss[tid][cc2] = 0.0;
+            for (int cc2 = 0; cc2 < FMMV_MAX_M; ++cc2) Ss[tid][cc2] = 0.0;
         }
         __syncthreads();
-        if (c < m) {
-            const int cnt = min(FV_CHUNK, npts - k0);
-            for (int kk = 0; kk < cnt; ++kk) acc = __builtin_fma(Lq[kk][q], Ss[kk][c], acc);
+        // W (16 nodes x 16 columns) += L (16 x chunk) S (chunk x 16) on the FP64 MFMA: each
+        // wavefront takes a quarter of the chunk, 4 points per step
+        // (A lane l = L[l % 16][k + l / 16], B lane l = S[k + l / 16][l % 16])
+#pragma unroll
+        for (int st = 0; st < FV_CHUNK / 16; ++st) {
+            const int kk = wv * (FV_CHUNK / 4) + 4 * st + (lane >> 4);
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Lq[kk][lane & 15], Ss[kk][lane & 15], acc,
+                                                     0, 0, 0);
         }
         __syncthreads();
     }
+    // the four wavefronts' partial W added in wavefront order (through the staging LDS);
+    // accumulator r of lane l holds W[4 r + l / 16][l % 16]
+    double *red = &Lq[0][0];
+    if (wv > 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[((wv - 1) * 4 + r) * WAVE + lane] = acc[r];
+    }
+    __syncthreads();
+    if (wv == 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            double s2 = acc[r];
+            for (int u = 0; u < 3; ++u) s2 += red[(u * 4 + r) * WAVE + lane];
+            const int qn = 4 * r + (lane >> 4), cn = lane & 15;
+            if (cn < m) w[qn * m + cn] = s2;
+        }
+    }
     if (tid < FMM_P) node[tid] = cc + hw * tq[tid];
-    if (c < m) w[q * m + c] = acc;
 }
 
 // Evaluation at the roots: work items are 64-root pieces of the target leaves; S
@@ -283,7 +306,6 @@ __global__ __launch_bounds__(512) void k_fmmv_eval(SolveArgs it, FmmArgs f, FmmV
 // slices of the Cauchy block and feeds v_mfma_f64_16x16x4f64.  Every source uses the
 // shifted difference, never less accurate than the lambda-form.
 // ---------------------------------------------------------------------------------------
-typedef double v4d_f __attribute__((ext_vector_type(4)));
 constexpr int FV_K = 64;            // sources per chunk
 constexpr int FV_LD = FV_K + 1;
 
