@@ -59,10 +59,11 @@ __global__ __launch_bounds__(64) void k_fmmv_pack(FmmvPackArgs a, FmmVec v) {
 // chunk at a time: each of the chunk's threads forms the 16 Lagrange values of one point in
 // LDS, then W_q,c += sum_k L_q(x_k) w_k,c over the chunk runs on the FP64 MFMA.
 template <bool LEAVES>
-__global__ __launch_bounds__(256) void k_fmmv_sources(FmmArgs f, FmmVec v) {
-    // points per chunk: leaves (a few hundred poles at most) in chunks of 64 and a small
-    // LDS footprint, upper boxes (up to 16 sources per leaf below) 256 at a time
-    constexpr int FV_CHUNK = LEAVES ? 64 : 256;
+__global__ __launch_bounds__(LEAVES ? 64 : 256) void k_fmmv_sources(FmmArgs f, FmmVec v) {
+    // leaves: one wavefront, 64 points per chunk; upper boxes (up to 16 sources per leaf
+    // below): four wavefronts, 256 points per chunk
+    constexpr int NW = LEAVES ? 1 : 4;
+    constexpr int FV_CHUNK = 64 * NW;
     __shared__ double Lq[FV_CHUNK][FMM_P + 1];
     __shared__ double Ss[FV_CHUNK][FMMV_MAX_M + 1];
     const int g = blockIdx.x;
@@ -147,11 +148,11 @@ __global__ __launch_bounds__(256) void k_fmmv_sources(FmmArgs f, FmmVec v) {
         }
         __syncthreads();
         // W (16 nodes x 16 columns) += L (16 x chunk) S (chunk x 16) on the FP64 MFMA: each
-        // wavefront takes a quarter of the chunk, 4 points per step
+        // wavefront takes 64 points of the chunk, 4 per step
         // (A lane l = L[l % 16][k + l / 16], B lane l = S[k + l / 16][l % 16])
 #pragma unroll
-        for (int st = 0; st < FV_CHUNK / 16; ++st) {
-            const int kk = wv * (FV_CHUNK / 4) + 4 * st + (lane >> 4);
+        for (int st = 0; st < 16; ++st) {
+            const int kk = wv * 64 + 4 * st + (lane >> 4);
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Lq[kk][lane & 15], Ss[kk][lane & 15], acc,
                                                      0, 0, 0);
         }
@@ -160,16 +161,16 @@ __global__ __launch_bounds__(256) void k_fmmv_sources(FmmArgs f, FmmVec v) {
     // the four wavefronts' partial W added in wavefront order (through the staging LDS);
     // accumulator r of lane l holds W[4 r + l / 16][l % 16]
     double *red = &Lq[0][0];
-    if (wv > 0) {
+    if (NW > 1 && wv > 0) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) red[((wv - 1) * 4 + r) * WAVE + lane] = acc[r];
     }
-    __syncthreads();
+    if (NW > 1) __syncthreads();
     if (wv == 0) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             double s2 = acc[r];
-            for (int u = 0; u < 3; ++u) s2 += red[(u * 4 + r) * WAVE + lane];
+            for (int u = 0; u < NW - 1; ++u) s2 += red[(u * 4 + r) * WAVE + lane];
             const int qn = 4 * r + (lane >> 4), cn = lane & 15;
             if (cn < m) w[qn * m + cn] = s2;
         }
@@ -469,8 +470,8 @@ __global__ __launch_bounds__(256) void k_fmmv_eval_mfma(SolveArgs it, FmmArgs f,
 // per-thread partial moments are added by a fixed-order tree in LDS.
 // ---------------------------------------------------------------------------------------
 template <bool LEAVES>
-__global__ __launch_bounds__(256) void k_fmml_moments(FmmArgs f, FmmlArgs l) {
-    __shared__ double part[256][FMML_K + 1];
+__global__ __launch_bounds__(LEAVES ? 64 : 256) void k_fmml_moments(FmmArgs f, FmmlArgs l) {
+    __shared__ double part[LEAVES ? 64 : 256][FMML_K + 1];
     const int g = blockIdx.x;
     const int qf = f.box_fmm[g];
     const int p = f.fmm_prob[qf];
@@ -533,18 +534,26 @@ __global__ __launch_bounds__(256) void k_fmml_moments(FmmArgs f, FmmlArgs l) {
 #pragma unroll
     for (int k = 0; k < FMML_K; ++k) part[tid][k] = M[k];
     __syncthreads();
-    for (int stride = blockDim.x / 2; stride > 0; stride >>= 1) {
-        if (tid < stride)
-            for (int k = 0; k < FMML_K; ++k) part[tid][k] += part[tid + stride][k];
-        __syncthreads();
+    if (LEAVES) {  // one wavefront: lane k adds column k over the 64 lanes in order
+        if (tid < FMML_K) {
+            double sk = 0.0;
+            for (int u = 0; u < 64; ++u) sk += part[u][tid];
+            l.mom[(int64_t)g * FMML_K + tid] = sk;
+        }
+    } else {
+        for (int stride = blockDim.x / 2; stride > 0; stride >>= 1) {
+            if (tid < stride)
+                for (int k = 0; k < FMML_K; ++k) part[tid][k] += part[tid + stride][k];
+            __syncthreads();
+        }
+        if (tid < FMML_K) l.mom[(int64_t)g * FMML_K + tid] = part[0][tid];
     }
-    if (tid < FMML_K) l.mom[(int64_t)g * FMML_K + tid] = part[0][tid];
     if (tid == 0) l.geo[g] = make_double2(c, hw);
 }
 
 hipError_t launch_fmml_moments(const FmmArgs &f, const FmmlArgs &l, hipStream_t s) {
     if (f.nboxes <= 0) return hipSuccess;
-    SDC_LAUNCH(KID_FMML_MOMENTS, k_fmml_moments<true>, dim3(f.nboxes), dim3(256), 0, s, f, l);
+    SDC_LAUNCH(KID_FMML_MOMENTS, k_fmml_moments<true>, dim3(f.nboxes), dim3(64), 0, s, f, l);
     SDC_LAUNCH(KID_FMML_MOMENTS, k_fmml_moments<false>, dim3(f.nboxes), dim3(256), 0, s, f, l);
     return hipGetLastError();
 }
@@ -576,7 +585,7 @@ hipError_t launch_fmmv_pack(const FmmvPackArgs &a, const FmmVec &v, hipStream_t 
 
 hipError_t launch_fmmv_sources(const FmmArgs &f, const FmmVec &v, hipStream_t s) {
     if (f.nboxes <= 0) return hipSuccess;
-    SDC_LAUNCH(KID_FMMV_SOURCES, k_fmmv_sources<true>, dim3(f.nboxes), dim3(256), 0, s, f, v);
+    SDC_LAUNCH(KID_FMMV_SOURCES, k_fmmv_sources<true>, dim3(f.nboxes), dim3(64), 0, s, f, v);
     SDC_LAUNCH(KID_FMMV_SOURCES, k_fmmv_sources<false>, dim3(f.nboxes), dim3(256), 0, s, f, v);
     return hipGetLastError();
 }
