@@ -6,8 +6,9 @@
 // equivalent sources: the Chebyshev nodes s_q of the box's span and the weights
 // W_q = sum_{j in box} w_j L_q(d_j) (L_q the Lagrange basis on those nodes), so that
 // sum_j w_j K(x, d_j) ~ sum_q W_q K(x, s_q) for any kernel K smooth over the box -- one
-// compression serves both 1/(s-x) and 1/(s-x)^2.  Only boxes that some target lists as far
-// field are compressed.  For each target leaf the tree is walked top down: a box separated from the leaf's targets by sep times its width (and by at
+// compression serves both 1/(s-x) and 1/(s-x)^2.  Every leaf is compressed from its
+// poles; above the leaves only boxes that some target lists as far field are compressed,
+// from their leaves' sources.  For each target leaf the tree is walked top down: a box separated from the leaf's targets by sep times its width (and by at
 // least 64 pole indices) is far field -- entirely left of every target (it feeds psi, the
 // lower triangle) or entirely right (phi, the strictly upper triangle), the directional
 // interactions of the triangular FMM; zero blocks never appear.  Leaves that are not far
@@ -61,18 +62,30 @@ __global__ __launch_bounds__(256) void k_fmm_geom(FmmArgs f) {
         f.box_ab[g] = make_double2(f.dw[r.base + r.lo].x, f.dw[r.base + r.hi - 1].x);
 }
 
-// secular equivalent sources of the boxes some target lists as far: one workgroup per box
-__global__ __launch_bounds__(256) void k_fmm_boxes(FmmArgs f) {
-    __shared__ double part[(256 / WAVE) * FMM_P];
+// Secular equivalent sources, in two launches.  LEAVES: every leaf from its poles, one
+// wavefront per leaf.  Upper boxes: every box some target lists as far, four wavefronts,
+// from the equivalent sources of its leaves (16 per leaf instead of every pole below: the
+// far field of a leaf's sources equals that of its poles to the interpolation accuracy,
+// and the box's nodes interpolate it again).
+template <bool LEAVES>
+__global__ __launch_bounds__(LEAVES ? 64 : 256) void k_fmm_boxes(FmmArgs f) {
+    __shared__ double part[LEAVES ? 64 * (FMM_P + 1) : (256 / WAVE) * FMM_P];
     const int g = blockIdx.x;
-    if (!f.used[g]) return;  // uniform: the whole workgroup leaves
+    const int qf = f.box_fmm[g];
+    const int hidx = g - f.box_off[qf];
+    const int H = f.height[qf];
+    int h = 0;
+    while ((2 << h) - 1 <= hidx) ++h;
+    // uniform for the workgroup: every leaf in the first launch, used upper boxes after
+    if (LEAVES ? (h != H) : (h == H || !f.used[g])) return;
     const BoxRange rg = box_range(f, g);
     const int lo = rg.lo, hi = rg.hi;
+    if (lo >= hi || (f.status[rg.p] & ~SUPERDC_ST_NOCONV)) return;
     const double2 *dw = f.dw + rg.base;
     const int tid = threadIdx.x;
     const double a = dw[lo].x, b = dw[hi - 1].x;
     const double c = 0.5 * (a + b), hw = 0.5 * (b - a);
-    if (hi - lo <= FMM_P) {  // few poles: they are their own equivalent sources
+    if (LEAVES && hi - lo <= FMM_P) {  // few poles: they are their own equivalent sources
         if (tid < FMM_P)
             f.eq[(int64_t)g * FMM_P + tid] =
                 lo + tid < hi ? dw[lo + tid] : make_double2(c, 0.0);
@@ -87,8 +100,12 @@ __global__ __launch_bounds__(256) void k_fmm_boxes(FmmArgs f) {
         lam[r] = cheb_bary(r);
     }
     const double ihw = 1.0 / hw;
-    for (int j = lo + tid; j < hi; j += blockDim.x) {
-        const double2 pw = dw[j];
+    // the points: the leaf's poles, or the sources of the box's leaves
+    const int bi = hidx - ((1 << h) - 1);
+    const int leaf0 = f.box_off[qf] + (1 << H) - 1 + bi * (1 << (H - h));
+    const int npts = LEAVES ? hi - lo : ((hi - lo + f.leaf - 1) / f.leaf) * FMM_P;
+    for (int k = tid; k < npts; k += blockDim.x) {
+        const double2 pw = LEAVES ? dw[lo + k] : f.eq[(int64_t)leaf0 * FMM_P + k];
         const double t = fmin(1.0, fmax(-1.0, (pw.x - c) * ihw));
         int hit = -1;
         double inv[FMM_P], den = 0.0;
@@ -100,20 +117,26 @@ __global__ __launch_bounds__(256) void k_fmm_boxes(FmmArgs f) {
             den += inv[r];
         }
         if (hit >= 0) {
-            W[hit] += pw.y;  // the pole sits on a node
+            W[hit] += pw.y;  // the point sits on a node
         } else {
             const double s = pw.y * rcp_nr(den);
 #pragma unroll
             for (int r = 0; r < FMM_P; ++r) W[r] = __builtin_fma(s, inv[r], W[r]);
         }
     }
-    block_sum<FMM_P>(W, part);
-    if (tid < FMM_P) {
-        double wq = 0.0;
+    double wq = 0.0;
+    if (LEAVES) {  // one wavefront: lane q adds column q over the 64 lanes in order
+#pragma unroll
+        for (int r = 0; r < FMM_P; ++r) part[tid * (FMM_P + 1) + r] = W[r];
+        __syncthreads();
+        if (tid < FMM_P)
+            for (int u = 0; u < 64; ++u) wq += part[u * (FMM_P + 1) + tid];
+    } else {
+        block_sum<FMM_P>(W, part);
 #pragma unroll
         for (int r = 0; r < FMM_P; ++r) wq = r == tid ? W[r] : wq;
-        f.eq[(int64_t)g * FMM_P + tid] = make_double2(c + hw * tq[tid], wq);
     }
+    if (tid < FMM_P) f.eq[(int64_t)g * FMM_P + tid] = make_double2(c + hw * tq[tid], wq);
 }
 
 // interaction lists: one wavefront per target leaf walks its problem's tree level by level.
@@ -235,7 +258,8 @@ hipError_t launch_fmm_build(const FmmArgs &f, hipStream_t s) {
     if (f.nboxes <= 0) return hipSuccess;
     hipError_t e = launch_fmm_lists(f, s);
     if (e != hipSuccess) return e;
-    SDC_LAUNCH(KID_FMM_BOXES, k_fmm_boxes, dim3(f.nboxes), dim3(256), 0, s, f);
+    SDC_LAUNCH(KID_FMM_BOXES, k_fmm_boxes<true>, dim3(f.nboxes), dim3(64), 0, s, f);
+    SDC_LAUNCH(KID_FMM_BOXES, k_fmm_boxes<false>, dim3(f.nboxes), dim3(256), 0, s, f);
     return hipGetLastError();
 }
 
