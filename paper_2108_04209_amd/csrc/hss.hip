@@ -24,8 +24,8 @@ namespace sdc {
 constexpr int LJ_LD = LEAF_MAX + 1;
 constexpr int LJ_THREADS = 1024;
 constexpr int LV_RB = 8;  // rounds of rotations staged in LDS per block of the replay
-constexpr int LV_LANES = LJ_THREADS / LEAF_MAX;  // lanes per row in the replay (8)
-static_assert(WAVE % LV_LANES == 0, "a row's lanes must share a wavefront");
+constexpr int LV_ROWS = LEAF_MAX / (LJ_THREADS / WAVE);  // rows per wavefront in the replay (8)
+static_assert(LEAF_MAX / 2 <= WAVE, "a round's pairs must fit one wavefront");
 
 // Round-robin (circle) ordering: in round `rd` every index takes part in exactly one of
 // m/2 disjoint pairs, and over m-1 rounds every pair meets once.
@@ -186,7 +186,7 @@ __global__ __launch_bounds__(LJ_THREADS) void k_leaf_vectors(LeafArgs a) {
     const int L = a.leaf;
     const int m = L, half = m / 2;
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int row = tid / LV_LANES, sub = tid % LV_LANES;  // replay: row and its lane share
+    const int lane = tid % WAVE, row0 = (tid / WAVE) * LV_ROWS;  // replay: pair and rows
     for (int e = tid; e < L * L; e += nt) {
         const int i = e / L, j = e % L;
         V[i * LJ_LD + j] = (i == j) ? 1.0 : 0.0;
@@ -214,17 +214,22 @@ __global__ __launch_bounds__(LJ_THREADS) void k_leaf_vectors(LeafArgs a) {
             const int g = (b + 1) * per_block + tid;
             tnext = g < rounds * half ? log[g] : 0.0;
         }
-        // columns: V <- V J, round after round.  Rows are independent, and the 8 lanes
-        // that own a row (pairs sub, sub + 8, ...) sit in one wavefront, whose LDS
-        // accesses complete in program order: consecutive rounds need no barrier.
-        if (row < L) {
+        // columns: V <- V J, round after round.  Rows are independent: wavefront w owns
+        // rows [8w, 8w + 8) and lane pr the round's pair pr, so a round's rotation is read
+        // once per lane and applied to 8 rows, and every access to those rows comes from
+        // one wavefront, whose LDS accesses complete in program order -- consecutive rounds
+        // need no barrier.
+        if (lane < half) {
             const int rounds_here = min(LV_RB, rounds - b * LV_RB);
-            double *vr = V + row * LJ_LD;
             for (int rr = 0; rr < rounds_here; ++rr) {
-                for (int pr = sub; pr < half; pr += LV_LANES) {
-                    const double2 r = cs[b & 1][rr][pr];
-                    if (r.y == 0.0) continue;
-                    const int2 c = pq[b & 1][rr][pr];
+                const double2 r = cs[b & 1][rr][lane];
+                if (r.y == 0.0) continue;
+                const int2 c = pq[b & 1][rr][lane];
+#pragma unroll
+                for (int k = 0; k < LV_ROWS; ++k) {
+                    const int i = row0 + k;
+                    if (i >= L) break;
+                    double *vr = V + i * LJ_LD;
                     const double vp = vr[c.x], vq = vr[c.y];
                     vr[c.x] = r.x * vp - r.y * vq;
                     vr[c.y] = r.y * vp + r.x * vq;
