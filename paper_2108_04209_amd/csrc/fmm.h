@@ -10,6 +10,8 @@ namespace sdc {
 constexpr int FMM_P = 16;          // Chebyshev nodes per box (equivalent sources)
 constexpr int FMM_NEAR_MAX = 24;   // near leaves (and so near ranges) per target leaf
 constexpr int FMM_FAR_MAX = 64;    // far boxes per side per target leaf
+constexpr int FMM_LOC = 4 * FMM_P; // local expansion of a target leaf: psi, psi', phi, phi'
+                                   // far fields, FMM_P Chebyshev coefficients each
 
 // Per batch: the problems that use the FMM, their trees, and per-leaf interaction lists.
 // Problem q (in FMM numbering) owns boxes [box_off[q], box_off[q+1]) in heap order over its
@@ -33,6 +35,11 @@ struct FmmArgs {
     int32_t *near_lo, *near_hi;   // [leaves][FMM_NEAR_MAX] pole ranges: runs of adjacent near leaves
     int32_t *far_l, *far_r;       // [leaves][FMM_FAR_MAX] far box ids (global)
     int32_t *cnt;             // [leaves][3] counts (near, far left, far right); -1 = direct
+    // Far boxes also separated from the whole target interval (by sep times its width)
+    // enter the leaf's local expansion instead of being summed per root and iteration.
+    int8_t *far_l_loc, *far_r_loc;  // [leaves][FMM_FAR_MAX] 1: the box is in the expansion
+    double2 *loc_ab;          // [leaves] (centre, half-width) of the target interval
+    double *loc;              // [leaves][FMM_LOC] Chebyshev coefficients on that interval
     int nboxes, nleaves;
     const int32_t *box_fmm;   // [nboxes] owning FMM problem of each box
     const int32_t *leaf_fmm;  // [nleaves] owning FMM problem of each leaf
@@ -49,6 +56,9 @@ struct FmmPlan {
     double2 *eq = nullptr, *box_ab = nullptr;
     int32_t *near_lo = nullptr, *near_hi = nullptr, *far_l = nullptr, *far_r = nullptr;
     int32_t *cnt = nullptr;
+    int8_t *far_l_loc = nullptr, *far_r_loc = nullptr;
+    double2 *loc_ab = nullptr;
+    double *loc = nullptr;
     // work items: 64-root pieces of the target leaves (a piece never crosses a leaf)
     int sub = TILE;                    // roots per work item
     int nitems = 0;

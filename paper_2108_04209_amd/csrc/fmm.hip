@@ -181,6 +181,8 @@ __global__ __launch_bounds__(WAVE) void k_fmm_lists(FmmArgs f) {
         const double width = ab.y - ab.x;
         const bool fl = live && ab.y < xa && xa - ab.y >= f.sep * width && hi <= i0 - TILE;
         const bool fr = live && !fl && ab.x > xb && ab.x - xb >= f.sep * width && lo >= i1 + TILE;
+        // also separated from the whole target interval: into the leaf's local expansion
+        const bool loc = (fl && xa - ab.y >= f.sep * (xb - xa)) || (fr && ab.x - xb >= f.sep * (xb - xa));
         const bool nr_leaf = live && !fl && !fr && h == H;
         const bool open = live && !fl && !fr && h < H;
         // far boxes, appended in lane order
@@ -193,10 +195,12 @@ __global__ __launch_bounds__(WAVE) void k_fmm_lists(FmmArgs f) {
         }
         if (fl) {
             far_l[nl + rl] = g;
+            f.far_l_loc[(int64_t)L * FMM_FAR_MAX + nl + rl] = loc;
             f.used[g] = 1;
         }
         if (fr) {
             far_r[nr + rr] = g;
+            f.far_r_loc[(int64_t)L * FMM_FAR_MAX + nr + rr] = loc;
             f.used[g] = 1;
         }
         nl += __popcll(ml);
@@ -244,7 +248,79 @@ __global__ __launch_bounds__(WAVE) void k_fmm_lists(FmmArgs f) {
         cnt[0] = overflow ? -1 : nn;  // -1: the leaf falls back to direct sums
         cnt[1] = nl;
         cnt[2] = nr;
+        f.loc_ab[L] = make_double2(0.5 * (xa + xb), 0.5 * (xb - xa));
     }
+}
+
+// Local expansion of a target leaf (one workgroup of 64 threads per leaf): the far field of
+// the boxes flagged for it, psi_far(x) = sum W_q / (s_q - x) over the left boxes and
+// phi_far over the right ones, with their derivatives, sampled at the FMM_P Chebyshev nodes
+// of the target interval [xa, xb] (which holds every iterate of the leaf's roots) and turned
+// into Chebyshev coefficients, so that the solver evaluates four short series per root and
+// iteration instead of 16 equivalent sources per box.  Thread (node m, part u) sums the
+// boxes e = u (mod 4); the parts are added in order.
+__global__ __launch_bounds__(64) void k_fmm_local(FmmArgs f) {
+    __shared__ double part[4][4][FMM_P];  // [part][function][node]
+    __shared__ double val[4][FMM_P];      // [function][node]
+    const int L = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int q = f.leaf_fmm[L];
+    const int p = f.fmm_prob[q];
+    if (f.status[p] & ~SUPERDC_ST_NOCONV) return;
+    const int nn = f.cnt[3 * (int64_t)L];
+    if (nn < 0) return;  // the leaf sums every pole directly
+    const int nl = f.cnt[3 * (int64_t)L + 1], nr = f.cnt[3 * (int64_t)L + 2];
+    const double2 cw = f.loc_ab[L];
+    const int m = tid % FMM_P, u = tid / FMM_P;
+    const double tm = cheb_node(m);
+    const double x = cw.x + cw.y * tm;
+    double ps = 0.0, dps = 0.0, ph = 0.0, dph = 0.0;
+    for (int e = u; e < nl + nr; e += 4) {
+        const bool left = e < nl;
+        const int k = left ? e : e - nl;
+        if (!(left ? f.far_l_loc : f.far_r_loc)[(int64_t)L * FMM_FAR_MAX + k]) continue;
+        const int g = (left ? f.far_l : f.far_r)[(int64_t)L * FMM_FAR_MAX + k];
+        const double2 *eq = f.eq + (int64_t)g * FMM_P;
+        double s0 = 0.0, s1 = 0.0;
+        for (int r = 0; r < FMM_P; ++r) {
+            const double2 sw = eq[r];
+            const double rr = rcp_nr(sw.x - x);
+            const double wr = sw.y * rr;
+            s0 += wr;
+            s1 = __builtin_fma(wr, rr, s1);
+        }
+        if (left) {
+            ps += s0;
+            dps += s1;
+        } else {
+            ph += s0;
+            dph += s1;
+        }
+    }
+    part[u][0][m] = ps;
+    part[u][1][m] = dps;
+    part[u][2][m] = ph;
+    part[u][3][m] = dph;
+    __syncthreads();
+    {
+        const int fn = tid / FMM_P;  // thread (function fn, node m) adds the parts in order
+        val[fn][m] = ((part[0][fn][m] + part[1][fn][m]) + part[2][fn][m]) + part[3][fn][m];
+    }
+    __syncthreads();
+    // c_k = (2 - [k = 0]) / P * sum_m f(t_m) T_k(t_m), thread (function fn, degree k)
+    const int fn = tid / FMM_P, k = tid % FMM_P;
+    double ck = 0.0;
+    for (int mm = 0; mm < FMM_P; ++mm) {
+        const double t = cheb_node(mm);
+        double T0 = 1.0, T1 = t, Tk = k == 0 ? 1.0 : t;
+        for (int j = 2; j <= k; ++j) {
+            Tk = 2.0 * t * T1 - T0;
+            T0 = T1;
+            T1 = Tk;
+        }
+        ck = __builtin_fma(val[fn][mm], Tk, ck);
+    }
+    f.loc[(int64_t)L * FMM_LOC + fn * FMM_P + k] = ck * ((k == 0 ? 1.0 : 2.0) / FMM_P);
 }
 
 hipError_t launch_fmm_lists(const FmmArgs &f, hipStream_t s) {
@@ -260,6 +336,7 @@ hipError_t launch_fmm_build(const FmmArgs &f, hipStream_t s) {
     if (e != hipSuccess) return e;
     SDC_LAUNCH(KID_FMM_BOXES, k_fmm_boxes<true>, dim3(f.nboxes), dim3(64), 0, s, f);
     SDC_LAUNCH(KID_FMM_BOXES, k_fmm_boxes<false>, dim3(f.nboxes), dim3(256), 0, s, f);
+    SDC_LAUNCH(KID_FMM_LOCAL, k_fmm_local, dim3(f.nleaves), dim3(64), 0, s, f);
     return hipGetLastError();
 }
 

@@ -336,15 +336,43 @@ __device__ __forceinline__ void fmm_sums(const FmmArgs &f, int L, int nn, int nl
                                 dphi);
         secular_range<1, true>(dw, max(lo, f1), hi, k, dK, y, x, psi, dpsi, phi, dphi);
     }
+    // far boxes outside the leaf's local expansion, through their equivalent sources
+    const int8_t *locl = f.far_l_loc + (int64_t)L * FMM_FAR_MAX;
+    const int8_t *locr = f.far_r_loc + (int64_t)L * FMM_FAR_MAX;
     for (int e = wv; e < nl; e += S) {
+        if (wave_uniform((int)locl[e])) continue;
         const int g = wave_uniform(f.far_l[(int64_t)L * FMM_FAR_MAX + e]);
         secular_range<0, true>(as_const(f.eq + (int64_t)g * FMM_P), 0, FMM_P, k, dK, y, x, psi,
                                dpsi, phi, dphi);
     }
     for (int e = wv; e < nr; e += S) {
+        if (wave_uniform((int)locr[e])) continue;
         const int g = wave_uniform(f.far_r[(int64_t)L * FMM_FAR_MAX + e]);
         secular_range<1, true>(as_const(f.eq + (int64_t)g * FMM_P), 0, FMM_P, k, dK, y, x, psi,
                                dpsi, phi, dphi);
+    }
+    // the others through the leaf's local expansion: four Chebyshev series on the target
+    // interval (Clenshaw), added by the first wavefront only
+    if (wv == 0) {
+        const double2 cw = f.loc_ab[L];
+        const double t = cw.y > 0.0 ? fmin(1.0, fmax(-1.0, (x - cw.x) / cw.y)) : 0.0;
+        const const_double_ptr c = as_const(f.loc + (int64_t)L * FMM_LOC);
+        double r[4];
+#pragma unroll
+        for (int fn = 0; fn < 4; ++fn) {
+            double b1 = 0.0, b2 = 0.0;
+#pragma unroll
+            for (int j = FMM_P - 1; j >= 1; --j) {
+                const double b0 = __builtin_fma(2.0 * t, b1, c[fn * FMM_P + j] - b2);
+                b2 = b1;
+                b1 = b0;
+            }
+            r[fn] = __builtin_fma(t, b1, c[fn * FMM_P] - b2);
+        }
+        psi += r[0];
+        dpsi += r[1];
+        phi += r[2];
+        dphi += r[3];
     }
 }
 
@@ -412,8 +440,12 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
             pairs_per_pass += (int)(((int64_t)(hi0 - lo0) * (wv + 1)) / S) -
                               (int)(((int64_t)(hi0 - lo0) * wv) / S);
         }
-        const int nfar = (nl > wv ? (nl - wv + S - 1) / S : 0) + (nr > wv ? (nr - wv + S - 1) / S : 0);
+        int nfar = 0;
+        for (int e = wv; e < nl; e += S) nfar += fm->far_l_loc[(int64_t)L * FMM_FAR_MAX + e] ? 0 : 1;
+        for (int e = wv; e < nr; e += S) nfar += fm->far_r_loc[(int64_t)L * FMM_FAR_MAX + e] ? 0 : 1;
         pairs_per_pass += (int64_t)FMM_P * nfar;
+        // the local expansion (four 16-term Clenshaw series, 128 flops) counts as 18 pairs
+        if (wv == 0) pairs_per_pass += 18;
     }
     unsigned long long work = 0;
 
