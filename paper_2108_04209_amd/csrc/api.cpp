@@ -224,9 +224,10 @@ FmmPlan *fmm_plan(superdc_batch *b, int leaf, int crossover) {
               fmm_upload(fp, &fp->far_l, std::vector<int32_t>(), (size_t)fp->nleaves * FMM_FAR_MAX) &&
               fmm_upload(fp, &fp->far_r, std::vector<int32_t>(), (size_t)fp->nleaves * FMM_FAR_MAX) &&
               fmm_upload(fp, &fp->cnt, std::vector<int32_t>(), (size_t)fp->nleaves * 3) &&
-              fmm_upload(fp, &fp->far_l_loc, std::vector<int8_t>(), (size_t)fp->nleaves * FMM_FAR_MAX) &&
-              fmm_upload(fp, &fp->far_r_loc, std::vector<int8_t>(), (size_t)fp->nleaves * FMM_FAR_MAX) &&
               fmm_upload(fp, &fp->loc_ab, std::vector<double2>(), (size_t)fp->nleaves) &&
+              fmm_upload(fp, &fp->far_ld, std::vector<int32_t>(), (size_t)fp->nleaves * FMM_FAR_MAX) &&
+              fmm_upload(fp, &fp->far_rd, std::vector<int32_t>(), (size_t)fp->nleaves * FMM_FAR_MAX) &&
+              fmm_upload(fp, &fp->cntd, std::vector<int32_t>(), (size_t)fp->nleaves * 2) &&
               fmm_upload(fp, &fp->loc, std::vector<double>(), (size_t)fp->nleaves * FMM_LOC) &&
               fmm_upload(fp, &fp->used, std::vector<int32_t>(), fp->nboxes) &&
               fmm_upload(fp, &fp->vnode, std::vector<double>(), (size_t)fp->nboxes * FMM_P) &&
@@ -279,8 +280,9 @@ FmmArgs fmm_args(const FmmPlan *fp, const superdc_batch *b, const SolveArgs &a,
     f.far_l = fp->far_l;
     f.far_r = fp->far_r;
     f.cnt = fp->cnt;
-    f.far_l_loc = fp->far_l_loc;
-    f.far_r_loc = fp->far_r_loc;
+    f.far_ld = fp->far_ld;
+    f.far_rd = fp->far_rd;
+    f.cntd = fp->cntd;
     f.loc_ab = fp->loc_ab;
     f.loc = fp->loc;
     f.nboxes = fp->nboxes;

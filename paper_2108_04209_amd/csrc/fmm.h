@@ -37,7 +37,9 @@ struct FmmArgs {
     int32_t *cnt;             // [leaves][3] counts (near, far left, far right); -1 = direct
     // Far boxes also separated from the whole target interval (by sep times its width)
     // enter the leaf's local expansion instead of being summed per root and iteration.
-    int8_t *far_l_loc, *far_r_loc;  // [leaves][FMM_FAR_MAX] 1: the box is in the expansion
+    int32_t *far_ld, *far_rd;       // [leaves][FMM_FAR_MAX] the far boxes summed directly
+                                    // from the front, those in the expansion from the back
+    int32_t *cntd;                  // [leaves][2] counts of the direct ones (left, right)
     double2 *loc_ab;          // [leaves] (centre, half-width) of the target interval
     double *loc;              // [leaves][FMM_LOC] Chebyshev coefficients on that interval
     int nboxes, nleaves;
@@ -56,7 +58,7 @@ struct FmmPlan {
     double2 *eq = nullptr, *box_ab = nullptr;
     int32_t *near_lo = nullptr, *near_hi = nullptr, *far_l = nullptr, *far_r = nullptr;
     int32_t *cnt = nullptr;
-    int8_t *far_l_loc = nullptr, *far_r_loc = nullptr;
+    int32_t *far_ld = nullptr, *far_rd = nullptr, *cntd = nullptr;
     double2 *loc_ab = nullptr;
     double *loc = nullptr;
     // work items: 64-root pieces of the target leaves (a piece never crosses a leaf)

@@ -168,7 +168,7 @@ __global__ __launch_bounds__(WAVE) void k_fmm_lists(FmmArgs f) {
     int32_t *near_lo = f.near_lo + (int64_t)L * FMM_NEAR_MAX;
     int32_t *near_hi = f.near_hi + (int64_t)L * FMM_NEAR_MAX;
     int hidx = 0, ncand = 1;  // the root
-    int nn = 0, nl = 0, nr = 0;
+    int nn = 0, nl = 0, nr = 0, ndl = 0, ndr = 0, nel = 0, ner = 0;
     bool overflow = false;
     for (int h = 0; h <= H && ncand > 0 && !overflow; ++h) {
         const bool valid = lane < ncand;
@@ -195,16 +195,37 @@ __global__ __launch_bounds__(WAVE) void k_fmm_lists(FmmArgs f) {
         }
         if (fl) {
             far_l[nl + rl] = g;
-            f.far_l_loc[(int64_t)L * FMM_FAR_MAX + nl + rl] = loc;
             f.used[g] = 1;
         }
         if (fr) {
             far_r[nr + rr] = g;
-            f.far_r_loc[(int64_t)L * FMM_FAR_MAX + nr + rr] = loc;
             f.used[g] = 1;
         }
         nl += __popcll(ml);
         nr += __popcll(mr);
+        // split for the solver: the far boxes summed directly from the front of far_ld/far_rd,
+        // those in the expansion from the back (both together fit, as the lists did)
+        {
+            const unsigned long long mdl = __ballot(fl && !loc), mdr = __ballot(fr && !loc);
+            const unsigned long long mel = __ballot(fl && loc), mer = __ballot(fr && loc);
+            auto rank = [&](unsigned long long mk) {
+                return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mk >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((unsigned)mk, 0u));
+            };
+            int32_t *ld = f.far_ld + (int64_t)L * FMM_FAR_MAX, *rd = f.far_rd + (int64_t)L * FMM_FAR_MAX;
+            if (fl) {
+                if (loc) ld[FMM_FAR_MAX - 1 - (nel + rank(mel))] = g;
+                else ld[ndl + rank(mdl)] = g;
+            }
+            if (fr) {
+                if (loc) rd[FMM_FAR_MAX - 1 - (ner + rank(mer))] = g;
+                else rd[ndr + rank(mdr)] = g;
+            }
+            ndl += __popcll(mdl);
+            ndr += __popcll(mdr);
+            nel += __popcll(mel);
+            ner += __popcll(mer);
+        }
         // near leaves (ascending), adjacent ones merged into one range
         const unsigned long long mn = __ballot(nr_leaf);
         if (mn) {
@@ -248,19 +269,23 @@ __global__ __launch_bounds__(WAVE) void k_fmm_lists(FmmArgs f) {
         cnt[0] = overflow ? -1 : nn;  // -1: the leaf falls back to direct sums
         cnt[1] = nl;
         cnt[2] = nr;
+        f.cntd[2 * (int64_t)L] = ndl;
+        f.cntd[2 * (int64_t)L + 1] = ndr;
         f.loc_ab[L] = make_double2(0.5 * (xa + xb), 0.5 * (xb - xa));
     }
 }
 
-// Local expansion of a target leaf (one workgroup of 64 threads per leaf): the far field of
-// the boxes flagged for it, psi_far(x) = sum W_q / (s_q - x) over the left boxes and
+// Local expansion of a target leaf (one workgroup of 256 threads per leaf): the far field of
+// the boxes listed for it, psi_far(x) = sum W_q / (s_q - x) over the left boxes and
 // phi_far over the right ones, with their derivatives, sampled at the FMM_P Chebyshev nodes
 // of the target interval [xa, xb] (which holds every iterate of the leaf's roots) and turned
 // into Chebyshev coefficients, so that the solver evaluates four short series per root and
 // iteration instead of 16 equivalent sources per box.  Thread (node m, part u) sums the
-// boxes e = u (mod 4); the parts are added in order.
-__global__ __launch_bounds__(64) void k_fmm_local(FmmArgs f) {
-    __shared__ double part[4][4][FMM_P];  // [part][function][node]
+// boxes e = u (mod LOC_PARTS), two sources per reciprocal (all on one side of the node);
+// the parts are added in order.
+constexpr int LOC_PARTS = 16;
+__global__ __launch_bounds__(FMM_P * LOC_PARTS) void k_fmm_local(FmmArgs f) {
+    __shared__ double part[LOC_PARTS][4][FMM_P];  // [part][function][node]
     __shared__ double val[4][FMM_P];      // [function][node]
     const int L = blockIdx.x;
     const int tid = threadIdx.x;
@@ -269,25 +294,35 @@ __global__ __launch_bounds__(64) void k_fmm_local(FmmArgs f) {
     if (f.status[p] & ~SUPERDC_ST_NOCONV) return;
     const int nn = f.cnt[3 * (int64_t)L];
     if (nn < 0) return;  // the leaf sums every pole directly
-    const int nl = f.cnt[3 * (int64_t)L + 1], nr = f.cnt[3 * (int64_t)L + 2];
+    const int nel = f.cnt[3 * (int64_t)L + 1] - f.cntd[2 * (int64_t)L];
+    const int ner = f.cnt[3 * (int64_t)L + 2] - f.cntd[2 * (int64_t)L + 1];
     const double2 cw = f.loc_ab[L];
     const int m = tid % FMM_P, u = tid / FMM_P;
     const double tm = cheb_node(m);
     const double x = cw.x + cw.y * tm;
     double ps = 0.0, dps = 0.0, ph = 0.0, dph = 0.0;
-    for (int e = u; e < nl + nr; e += 4) {
-        const bool left = e < nl;
-        const int k = left ? e : e - nl;
-        if (!(left ? f.far_l_loc : f.far_r_loc)[(int64_t)L * FMM_FAR_MAX + k]) continue;
-        const int g = (left ? f.far_l : f.far_r)[(int64_t)L * FMM_FAR_MAX + k];
+    for (int e = u; e < nel + ner; e += LOC_PARTS) {
+        const bool left = e < nel;
+        const int k = left ? e : e - nel;
+        const int g = (left ? f.far_ld : f.far_rd)[(int64_t)L * FMM_FAR_MAX + FMM_FAR_MAX - 1 - k];
         const double2 *eq = f.eq + (int64_t)g * FMM_P;
         double s0 = 0.0, s1 = 0.0;
-        for (int r = 0; r < FMM_P; ++r) {
-            const double2 sw = eq[r];
-            const double rr = rcp_nr(sw.x - x);
-            const double wr = sw.y * rr;
-            s0 += wr;
-            s1 = __builtin_fma(wr, rr, s1);
+#pragma unroll 2
+        for (int r = 0; r < FMM_P; r += 2) {
+            // w0/t0 + w1/t1 = (w0 t1 + w1 t0)/(t0 t1), and the squares likewise
+            const double2 a = eq[r], b = eq[r + 1];
+            const double t0 = a.x - x, t1 = b.x - x;
+            const double pr = fabs(t0 * t1);
+            if (pr > 0x1p-900 && pr < 0x1p900) {
+                const double R = rcp_nr(t0 * t1);
+                const double u0 = a.y * t1, u1 = b.y * t0;
+                s0 = __builtin_fma(u0 + u1, R, s0);
+                s1 = __builtin_fma(__builtin_fma(u0, t1, u1 * t0), R * R, s1);
+            } else {  // the product would leave the exponent range: one source at a time
+                const double r0 = rcp_nr(t0), r1 = rcp_nr(t1);
+                s0 += a.y * r0 + b.y * r1;
+                s1 += a.y * r0 * r0 + b.y * r1 * r1;
+            }
         }
         if (left) {
             ps += s0;
@@ -302,11 +337,14 @@ __global__ __launch_bounds__(64) void k_fmm_local(FmmArgs f) {
     part[u][2][m] = ph;
     part[u][3][m] = dph;
     __syncthreads();
-    {
+    if (tid < 4 * FMM_P) {
         const int fn = tid / FMM_P;  // thread (function fn, node m) adds the parts in order
-        val[fn][m] = ((part[0][fn][m] + part[1][fn][m]) + part[2][fn][m]) + part[3][fn][m];
+        double sv = 0.0;
+        for (int w = 0; w < LOC_PARTS; ++w) sv += part[w][fn][m];
+        val[fn][m] = sv;
     }
     __syncthreads();
+    if (tid >= 4 * FMM_P) return;
     // c_k = (2 - [k = 0]) / P * sum_m f(t_m) T_k(t_m), thread (function fn, degree k)
     const int fn = tid / FMM_P, k = tid % FMM_P;
     double ck = 0.0;
@@ -336,7 +374,7 @@ hipError_t launch_fmm_build(const FmmArgs &f, hipStream_t s) {
     if (e != hipSuccess) return e;
     SDC_LAUNCH(KID_FMM_BOXES, k_fmm_boxes<true>, dim3(f.nboxes), dim3(64), 0, s, f);
     SDC_LAUNCH(KID_FMM_BOXES, k_fmm_boxes<false>, dim3(f.nboxes), dim3(256), 0, s, f);
-    SDC_LAUNCH(KID_FMM_LOCAL, k_fmm_local, dim3(f.nleaves), dim3(64), 0, s, f);
+    SDC_LAUNCH(KID_FMM_LOCAL, k_fmm_local, dim3(f.nleaves), dim3(FMM_P * LOC_PARTS), 0, s, f);
     return hipGetLastError();
 }
 

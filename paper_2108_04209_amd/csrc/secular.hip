@@ -337,17 +337,13 @@ __device__ __forceinline__ void fmm_sums(const FmmArgs &f, int L, int nn, int nl
         secular_range<1, true>(dw, max(lo, f1), hi, k, dK, y, x, psi, dpsi, phi, dphi);
     }
     // far boxes outside the leaf's local expansion, through their equivalent sources
-    const int8_t *locl = f.far_l_loc + (int64_t)L * FMM_FAR_MAX;
-    const int8_t *locr = f.far_r_loc + (int64_t)L * FMM_FAR_MAX;
     for (int e = wv; e < nl; e += S) {
-        if (wave_uniform((int)locl[e])) continue;
-        const int g = wave_uniform(f.far_l[(int64_t)L * FMM_FAR_MAX + e]);
+        const int g = wave_uniform(f.far_ld[(int64_t)L * FMM_FAR_MAX + e]);
         secular_range<0, true>(as_const(f.eq + (int64_t)g * FMM_P), 0, FMM_P, k, dK, y, x, psi,
                                dpsi, phi, dphi);
     }
     for (int e = wv; e < nr; e += S) {
-        if (wave_uniform((int)locr[e])) continue;
-        const int g = wave_uniform(f.far_r[(int64_t)L * FMM_FAR_MAX + e]);
+        const int g = wave_uniform(f.far_rd[(int64_t)L * FMM_FAR_MAX + e]);
         secular_range<1, true>(as_const(f.eq + (int64_t)g * FMM_P), 0, FMM_P, k, dK, y, x, psi,
                                dpsi, phi, dphi);
     }
@@ -427,8 +423,8 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
         const int q = fm->fmm_of[p];
         L = wave_uniform(fm->leaf_off[q] + t.row0 / fm->leaf);
         nn = wave_uniform(fm->cnt[3 * (int64_t)L]);
-        nl = wave_uniform(fm->cnt[3 * (int64_t)L + 1]);
-        nr = wave_uniform(fm->cnt[3 * (int64_t)L + 2]);
+        nl = wave_uniform(fm->cntd[2 * (int64_t)L]);      // far boxes outside the
+        nr = wave_uniform(fm->cntd[2 * (int64_t)L + 1]);  // local expansion
     }
     // pair evaluations of this wavefront per pass and live root (kernel timing only)
     int64_t pairs_per_pass = p1 - p0;
@@ -440,9 +436,7 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
             pairs_per_pass += (int)(((int64_t)(hi0 - lo0) * (wv + 1)) / S) -
                               (int)(((int64_t)(hi0 - lo0) * wv) / S);
         }
-        int nfar = 0;
-        for (int e = wv; e < nl; e += S) nfar += fm->far_l_loc[(int64_t)L * FMM_FAR_MAX + e] ? 0 : 1;
-        for (int e = wv; e < nr; e += S) nfar += fm->far_r_loc[(int64_t)L * FMM_FAR_MAX + e] ? 0 : 1;
+        const int nfar = (nl > wv ? (nl - wv + S - 1) / S : 0) + (nr > wv ? (nr - wv + S - 1) / S : 0);
         pairs_per_pass += (int64_t)FMM_P * nfar;
         // the local expansion (four 16-term Clenshaw series, 128 flops) counts as 18 pairs
         if (wv == 0) pairs_per_pass += 18;
