@@ -1,4 +1,4 @@
-"""Oracle for the HSS conquering pass (test infrastructure only).
+"""Oracle for the HSS dividing and conquering passes (test infrastructure only).
 
 The conquering stage (Alg. 3) computes the eigendecomposition of the symmetric HSS
 matrix defined by its generators (Sec. 2.1, eq. hss).  With the leaf blocks taken as
@@ -119,3 +119,55 @@ def matvec(tree, X):
         rows = slice(q * leaf, (q + 1) * leaf)
         Y[rows] = tree.leaf_D[q] @ X[rows] + tree.leaf_U[q] @ f[(D, q)]
     return Y
+
+
+# ------------------------------------------------------------------------ dividing stage
+def dense_original(tree):
+    """The HSS matrix of undivided generators, written out (eq. hss): D_p = [[D_c1,
+    U_c1 B_p U_c2^T], [U_c2 B_p^T U_c1^T, D_c2]] with the nested bases."""
+    U = bases(tree)
+    A = {(tree.depth, q): tree.leaf_D[q].copy() for q in range(1 << tree.depth)}
+    for lvl in range(tree.depth - 1, -1, -1):
+        for q in range(1 << lvl):
+            (l1, a), (_, b) = _children(lvl, q)
+            na = A[(l1, a)].shape[0]
+            M = np.zeros((2 * na, 2 * na))
+            M[:na, :na] = A[(l1, a)]
+            M[na:, na:] = A[(l1, b)]
+            C = U[(l1, a)] @ tree.B[lvl][q] @ U[(l1, b)].T
+            M[:na, na:] = C
+            M[na:, :na] = C.T
+            A[(lvl, q)] = M
+    return A[(0, 0)]
+
+
+def divide(tree, balanced=True):
+    """The balanced dividing stage (Alg. 1, top-down part) for square couplings.
+
+    Top down, every node p carries the pending update H_p of Lemma genupd (zero at the
+    root): its children's coupling becomes B_p - R_c1 H_p R_c2^T (eq. genupd), beta_p is
+    that coupling's 2-norm, and the children inherit R_c H_p R_c^T plus p's own division
+    (eq. divnew1): (1/beta_p) B B^T for the left child, beta_p I for the right.  A leaf ends
+    as D - U H U^T.  Returns a tree of the same shape with the divided leaf blocks, the
+    updated couplings and their norms, i.e. the input of the conquering pass.
+    balanced=False gives the earlier dividing (eq. divide: B B^T to the left child, I to the
+    right, beta = 1), whose generators can grow exponentially down the tree."""
+    import copy
+    D, r = tree.depth, tree.r
+    out = copy.deepcopy(tree)
+    H = {(0, 0): np.zeros((r, r))}
+    for lvl in range(D):
+        for q in range(1 << lvl):
+            (l1, a), (_, b) = _children(lvl, q)
+            R1, R2 = tree.R[l1][a], tree.R[l1][b]
+            Hp = H[(lvl, q)]
+            Bt = tree.B[lvl][q] - R1 @ Hp @ R2.T
+            beta = np.linalg.norm(Bt, 2) if balanced else 1.0
+            out.B[lvl][q] = Bt
+            out.beta[lvl][q] = beta
+            H[(l1, a)] = R1 @ Hp @ R1.T + (Bt @ Bt.T) / beta
+            H[(l1, b)] = R2 @ Hp @ R2.T + beta * np.eye(r)
+    for q in range(1 << D):
+        U = tree.leaf_U[q]
+        out.leaf_D[q] = tree.leaf_D[q] - U @ H[(D, q)] @ U.T
+    return out

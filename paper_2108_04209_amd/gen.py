@@ -319,3 +319,51 @@ def hss_tree(n: int = 65536, leaf: int = 128, r: int = 8, cfg: int = 3) -> HSSTr
         beta[lvl] = np.array([np.linalg.norm(Bl[i], 2) for i in range(cnt)])
     return HSSTree(n=n, leaf=leaf, depth=depth, r=r, leaf_D=leaf_D, leaf_U=leaf_U,
                    R=R, B=B, beta=beta)
+
+
+def hss_original(n: int = 65536, leaf: int = 128, r: int = 8, cfg: int = 5) -> HSSTree:
+    """Generators of an HSS matrix before the dividing stage (eq. hss): leaf blocks
+    N(0,1)/sqrt(leaf) symmetrised, orthonormal U and stacked R, couplings B ~ N(0,1)
+    (the coupling of node p's children is U_c1 B_p U_c2^T).  beta holds ||B||_2 of the
+    undivided couplings, for reference only."""
+    t = hss_tree(n, leaf, r, cfg)
+    return t
+
+
+def tridiag_hss(n: int, leaf: int, diag=3.0, off=-1.0) -> HSSTree:
+    """The symmetric tridiagonal matrix with the given diagonal and off-diagonal (scalars or
+    arrays of n and n-1 entries) as an HSS form of rank 2 (the paper's first example):
+    node bases [e_first, e_last] of the node's rows, R_c1 = [[1, 0], [0, 0]],
+    R_c2 = [[0, 0], [0, 1]], and the coupling of siblings c1, c2 is off[k] e_last(c1)
+    e_first(c2)^T, i.e. B = [[0, 0], [off[k], 0]] with k the last row of c1."""
+    nleaf = n // leaf
+    depth = int(round(np.log2(nleaf)))
+    if leaf * (1 << depth) != n or leaf < 2:
+        raise ValueError("n must be leaf * 2^depth with leaf >= 2")
+    dg = np.broadcast_to(np.asarray(diag, dtype=np.float64), (n,)).copy()
+    od = np.broadcast_to(np.asarray(off, dtype=np.float64), (n - 1,)).copy()
+    leaf_D = np.zeros((nleaf, leaf, leaf))
+    for q in range(nleaf):
+        a = q * leaf
+        leaf_D[q][np.arange(leaf), np.arange(leaf)] = dg[a:a + leaf]
+        leaf_D[q][np.arange(leaf - 1), np.arange(1, leaf)] = od[a:a + leaf - 1]
+        leaf_D[q][np.arange(1, leaf), np.arange(leaf - 1)] = od[a:a + leaf - 1]
+    leaf_U = np.zeros((nleaf, leaf, 2))
+    leaf_U[:, 0, 0] = 1.0
+    leaf_U[:, leaf - 1, 1] = 1.0
+    R, B, beta = {}, {}, {}
+    for lvl in range(1, depth + 1):
+        Rl = np.zeros((1 << lvl, 2, 2))
+        Rl[0::2, 0, 0] = 1.0
+        Rl[1::2, 1, 1] = 1.0
+        R[lvl] = Rl
+    for lvl in range(depth):
+        cnt = 1 << lvl
+        size = leaf << (depth - lvl)
+        Bl = np.zeros((cnt, 2, 2))
+        for q in range(cnt):
+            Bl[q, 1, 0] = od[q * size + size // 2 - 1]
+        B[lvl] = Bl
+        beta[lvl] = np.abs(Bl[:, 1, 0])
+    return HSSTree(n=n, leaf=leaf, depth=depth, r=2, leaf_D=leaf_D, leaf_U=leaf_U,
+                   R=R, B=B, beta=beta)
