@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Benchmark of the conquering-stage hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload conquer|level|large|single]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload conquer|level|large|single|deflate|ex1]
 
 A step is one pass of the whole rank-one path over one batch already resident in HBM:
 validation and packing, the secular solve (midpoint pass plus middle-way iterations to
@@ -116,7 +116,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="conquer",
-                    choices=["conquer", "level", "large", "single", "deflate"])
+                    choices=["conquer", "level", "large", "single", "deflate", "ex1"])
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-level", action="store_true",
@@ -539,6 +539,61 @@ def bench_deflate(args):
     }
 
 
+def bench_ex1(args):
+    """The paper's first example end to end: the symmetric tridiagonal matrix with 3 on the
+    diagonal and -1 beside it, n = 65536, written as an HSS form of rank 2 (leaf 128).  One
+    step: the dividing stage (balanced) and the conquering pass; the eigenvalues are checked
+    against the closed form 3 - 2 cos(k pi / (n + 1))."""
+    import torch
+    from paper_2108_04209_amd import gen, native
+    n, leaf = 65536, 128
+    tree = gen.tridiag_hss(n, leaf)
+    ctx = native.Context()
+    plan = native.HSSPlan(ctx, tree.leaf, tree.depth, tree.r)
+    dev = torch.device("cuda:0")
+    gens = {k: torch.as_tensor(v, dtype=torch.float64, device=dev)
+            for k, v in native.pack_hss(tree).items()}
+    o = native.default_opts(persistent=1, fmm_crossover=args.fmm_crossover, fmm_leaf=args.fmm_leaf)
+    dv = native.hss_divide(ctx, plan, gens)
+    out = native.hss_conquer(ctx, plan, dv, opts=o)
+
+    def step():
+        native.hss_divide(ctx, plan, gens, out=dv)
+        native.hss_conquer(ctx, plan, dv, opts=o, out=out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    native.kernel_times()
+    native.kernel_timing(True)
+    try:
+        for _ in range(args.steps):
+            native.hss_divide(ctx, plan, gens, out=dv)
+        torch.cuda.synchronize()
+        kt = native.kernel_times()
+    finally:
+        native.kernel_timing(False)
+    div = kt.get("k_divide", (0.0, 0))
+    lam = out["lam"].cpu().numpy()
+    exact = np.sort(3.0 - 2.0 * np.cos(np.arange(1, n + 1) * np.pi / (n + 1)))
+    note(f"ex1 {ms:.2f} ms/step")
+    return {"config": {"workload": "tridiagonal (3 on the diagonal, -1 beside it) as an HSS form "
+                                   "of rank 2: n=65536, leaf 128, depth 9; balanced dividing "
+                                   "stage + conquering pass", "n": n, "leaf": leaf,
+                       "depth": tree.depth, "r": 2},
+            "ms_per_step": ms, "divide_ms": div[0] / args.steps,
+            "divide_launches": div[1] // max(1, args.steps),
+            "accuracy": {"status": int(out["status"].cpu().numpy()[0]),
+                         "lam_err_rel_normA": float(np.abs(lam - exact).max() / 5.0)}}
+
+
 # ---------------------------------------------------------------------------------------
 # HSS conquering pass (n = 65536, leaf 128, depth 9, r = 8)
 # ---------------------------------------------------------------------------------------
@@ -786,12 +841,19 @@ def main():
                                                "roofline")}
             res["large"] = bench_large(argparse.Namespace(**{**vars(args), "steps": min(args.steps, 5)}))
             res["deflate"] = bench_deflate(argparse.Namespace(**{**vars(args), "steps": min(args.steps, 5)}))
+            res["ex1"] = bench_ex1(argparse.Namespace(**{**vars(args), "steps": min(args.steps, 5)}))
     elif args.workload == "deflate":
         dfl = bench_deflate(args)
         res = {"metric": METRIC, "value": dfl["roots_per_s"], "unit": "roots/s", "n_gpus": 1,
                "steps": args.steps, "warmup": args.warmup, "ms_per_step": dfl["ms_per_step"],
                "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
                "dtype": "f64", "data": "synthetic (seeded generators, no dataset)", **dfl}
+    elif args.workload == "ex1":
+        ex = bench_ex1(args)
+        res = {"metric": METRIC, "value": 2 * (ex["config"]["depth"]) * ex["config"]["n"] / (ex["ms_per_step"] * 1e-3),
+               "unit": "roots/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+               "ms_per_step": ex["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+               "vs_baseline": None, "dtype": "f64", "data": "synthetic (closed-form matrix)", **ex}
     elif args.workload == "large":
         lg = bench_large(args)
         ms = lg[lg["faster"]]["ms_per_step"]

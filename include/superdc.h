@@ -279,6 +279,24 @@ int superdc_hss_plan_create(superdc_ctx *ctx, int32_t leaf, int32_t depth, int32
 void superdc_hss_plan_destroy(superdc_hss *plan);
 
 /*
+ * Dividing stage (Alg. 1) for the original generators of an HSS matrix (eq. hss: the
+ * coupling of node p's children is U_c1 B_p U_c2^T, bases nested by eq. du), in the
+ * layout of superdc_hss_conquer.  Top down, each node's pending update H (Lemma genupd,
+ * zero at the root) turns its children's coupling into B_p - R_c1 H R_c2^T with
+ * beta_p = ||B_p - R_c1 H R_c2^T||_2, and the children inherit R_c H R_c^T plus the
+ * balanced division (eq. divnew1): (1/beta_p) B B^T for the left child, beta_p I for the
+ * right one; a leaf ends as D - U H U^T.  balanced = 0 uses the earlier division (eq.
+ * divide: B B^T and I, beta = 1).  A coupling that vanishes gets beta = 1.
+ *   out: leaf_D_out [2^depth][leaf][leaf], B_out [2^depth - 1][r][r], beta_out [2^depth - 1]
+ *        -- with leaf_U and R unchanged, exactly the input of superdc_hss_conquer, whose
+ *        eigenvalues are then those of the original matrix.
+ * Outputs must not alias the inputs.  Device pointers, caller-owned.
+ */
+int superdc_hss_divide(superdc_ctx *ctx, superdc_hss *plan, const double *leaf_D,
+                       const double *leaf_U, const double *R, const double *B, int balanced,
+                       double *leaf_D_out, double *B_out, double *beta_out, void *stream);
+
+/*
  * Conquering pass.  Device inputs (row-major small matrices; heap index h = 2^l - 1 + q):
  *   leaf_D [2^depth][leaf][leaf]  symmetric leaf blocks
  *   leaf_U [2^depth][leaf][r]     leaf bases

@@ -163,6 +163,8 @@ def divide(tree, balanced=True):
             Hp = H[(lvl, q)]
             Bt = tree.B[lvl][q] - R1 @ Hp @ R2.T
             beta = np.linalg.norm(Bt, 2) if balanced else 1.0
+            if not beta > 0.0:
+                beta = 1.0  # a vanished coupling: nothing to balance, Z_p = [0; U_c2]
             out.B[lvl][q] = Bt
             out.beta[lvl][q] = beta
             H[(l1, a)] = R1 @ Hp @ R1.T + (Bt @ Bt.T) / beta

@@ -33,6 +33,15 @@ struct AssembleArgs {
     double *M;             // output: n x 2r, ld n (Z in columns 0..r-1, V in r..2r-1)
 };
 
+// dividing stage (divide.hip)
+struct DivideArgs {
+    int leaf, r, depth, balanced;
+    const double *D, *U, *R, *B;  // original generators (layout of the conquering pass)
+    double *D_out, *B_out, *beta_out;
+    double *H;                    // [2^(depth+1) - 1][r][r] pending updates, heap order
+};
+hipError_t launch_divide(const DivideArgs &a, hipStream_t s);
+
 hipError_t launch_leaf_jacobi(const LeafArgs &a, hipStream_t s);
 hipError_t launch_merge(const double *lam_children, double *d_out, int32_t *perm, int nc,
                         int64_t n, hipStream_t s);

@@ -311,7 +311,10 @@ __global__ __launch_bounds__(256) void k_assemble(AssembleArgs a) {
     const int64_t node = e / nl;
     const int64_t base = node * nl;
     const int pos = (int)(e - base);
-    const int src = a.perm[e];
+    // the merge writes a permutation only when the children's spectra are sorted and free of
+    // NaN (a failed child solve returns NaN): clamp, so that such a node stays in bounds and
+    // only its status reports it
+    const int src = min(max(a.perm[e], 0), nl - 1);
     const int child = src < nc ? 0 : 1;
     const int64_t hp = ((int64_t)1 << a.level) - 1 + node;                 // parent heap index
     const int64_t hc = ((int64_t)1 << (a.level + 1)) - 1 + 2 * node + child;  // child heap index
@@ -351,7 +354,7 @@ __global__ __launch_bounds__(256) void k_permute(const int32_t *perm, int nl, in
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
     const int64_t base = (e / nl) * nl;
-    const int64_t src = base + perm[e];
+    const int64_t src = base + min(max(perm[e], 0), nl - 1);  // in bounds for any perm (k_assemble)
     for (int c = 0; c < m; ++c) {
         if (scatter) Y[src + c * ldy] = X[e + c * ldx];
         else Y[e + c * ldy] = X[src + c * ldx];

@@ -37,6 +37,7 @@ struct superdc_hss {
     int32_t *perm = nullptr;   // [depth][n]
     int32_t *status = nullptr; // [depth][r][2^(depth-1)]
     double *T[2] = {nullptr, nullptr};  // apply work buffers
+    double *Hdiv = nullptr;    // dividing stage: pending updates per node (on first use)
     int64_t tcap = 0;
     bool ready = false;
     // optional phase timing: events recorded between phases of the last conquer
@@ -142,6 +143,7 @@ int superdc_hss_plan_create(superdc_ctx *ctx, int32_t leaf, int32_t depth, int32
     if (e == hipSuccess)
         e = alloc(h, &h->status, (size_t)depth * r * ((size_t)1 << (depth - 1)) + nleaf);
     if (e == hipSuccess) e = launch_fill(h->ones, n, 1.0, nullptr);
+    if (e == hipSuccess) e = hipMemset(h->perm, 0, sizeof(int32_t) * (size_t)depth * n);
     // level l uses 2^l of the 2^(depth-1) status slots of each step; the rest stay 0
     if (e == hipSuccess)
         e = hipMemset(h->status, 0,
@@ -153,6 +155,34 @@ int superdc_hss_plan_create(superdc_ctx *ctx, int32_t leaf, int32_t depth, int32
     }
     *out = h;
     return SUPERDC_OK;
+}
+
+int superdc_hss_divide(superdc_ctx *ctx, superdc_hss *h, const double *leaf_D,
+                       const double *leaf_U, const double *R, const double *B, int balanced,
+                       double *leaf_D_out, double *B_out, double *beta_out, void *stream) {
+    if (!ctx || !h || h->ctx != ctx || !leaf_D || !leaf_U || !R || !B || !leaf_D_out || !B_out ||
+        !beta_out || (balanced != 0 && balanced != 1) || leaf_D_out == leaf_D || B_out == B)
+        return SUPERDC_EINVAL;
+    const size_t nodes = ((size_t)2 << h->depth) - 1;
+    if (!h->Hdiv) {
+        hipError_t e = alloc(h, &h->Hdiv, nodes * h->r * h->r);
+        if (e != hipSuccess) return fail(e);
+    }
+    DivideArgs a{};
+    a.leaf = h->leaf;
+    a.r = h->r;
+    a.depth = h->depth;
+    a.balanced = balanced;
+    a.D = leaf_D;
+    a.U = leaf_U;
+    a.R = R;
+    a.B = B;
+    a.D_out = leaf_D_out;
+    a.B_out = B_out;
+    a.beta_out = beta_out;
+    a.H = h->Hdiv;
+    hipError_t e = launch_divide(a, (hipStream_t)stream);
+    return e == hipSuccess ? SUPERDC_OK : fail(e);
 }
 
 int superdc_hss_conquer(superdc_ctx *ctx, superdc_hss *h, const double *leaf_D,

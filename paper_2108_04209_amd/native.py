@@ -427,6 +427,26 @@ def hss_conquer(ctx, plan, gens, opts=None, stream=None, levels=False, out=None)
     return out
 
 
+def hss_divide(ctx, plan, gens, balanced=True, stream=None, out=None):
+    """superdc_hss_divide on packed original generators (device tensors as from pack_hss);
+    returns the conquer's input: dict(leaf_D, leaf_U, R, B, beta) (`out`, if given, is
+    such a dict from an earlier call and is written in place)."""
+    import torch
+    lib = load_library()
+    lib.superdc_hss_divide.argtypes = [_P, _P, _P, _P, _P, _P, C.c_int, _P, _P, _P, _P]
+    lib.superdc_hss_divide.restype = C.c_int
+    if out is None:
+        out = dict(leaf_D=torch.empty_like(gens["leaf_D"]), leaf_U=gens["leaf_U"], R=gens["R"],
+                   B=torch.empty_like(gens["B"]),
+                   beta=torch.empty(gens["B"].shape[0], dtype=torch.float64,
+                                    device=gens["B"].device))
+    _check(lib.superdc_hss_divide(ctx.handle, plan.handle, _ptr(gens["leaf_D"]), _ptr(gens["leaf_U"]),
+                                  _ptr(gens["R"]), _ptr(gens["B"]), int(bool(balanced)),
+                                  _ptr(out["leaf_D"]), _ptr(out["B"]), _ptr(out["beta"]),
+                                  _stream(stream)), "superdc_hss_divide")
+    return out
+
+
 def hss_apply(ctx, plan, X, trans=0, opts=None, stream=None, Y=None):
     """superdc_hss_apply.  X: contiguous (m, n) tensor, each row one vector."""
     import torch

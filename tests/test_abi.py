@@ -48,6 +48,8 @@ def test_no_device_or_bad_args_fail_cleanly():
                                       None, 1, None) == -1
     assert lib.superdc_batch_copy_rows(None, None, None, None, 1, None, 1, None, 1, None,
                                        None) == -1
+    assert lib.superdc_hss_divide(None, None, None, None, None, None, 1, None, None, None,
+                                  None) == -1
     o = native.default_opts()
     assert o.stop_c == 1.0 and o.max_iter == 40 and o.persistent == 1
     assert lib.superdc_strerror(-4) == b"no gfx950 device"

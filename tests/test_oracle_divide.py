@@ -6,6 +6,9 @@ of eq. divnew1), against facts fixed by the mathematics:
   - the tridiagonal matrix of the paper's first example, written as an HSS form of rank 2,
     assembles to the tridiagonal matrix exactly, and tridiag(-1, 3, -1) has the closed-form
     spectrum 3 - 2 cos(k pi / (n + 1));
+  - with orthonormal nested bases, the assembled matrix has trace sum tr D_leaf and squared
+    Frobenius norm sum ||D_leaf||_F^2 + 2 sum_p ||B_p||_F^2 (each coupling block appears
+    twice, and orthonormal bases keep its norm);
   - Prop. prop:b: with the balanced update, ||B-tilde|| at level l is at most 2^l beta;
     the unbalanced update (eq. divide) lets it grow far beyond that on the same tree.
 """
@@ -65,3 +68,16 @@ def test_balanced_norm_bound_and_unbalanced_growth():
     for bl in (True, False):
         Ad = oh.dense_nodes(oh.divide(s, balanced=bl))[(0, 0)]
         assert np.abs(A - Ad).max() <= 1e-10 * np.abs(A).max() * (1 if bl else 1e6)
+
+
+def test_trace_and_frobenius_of_the_assembly():
+    from oracle import hss as oh
+    t = gen.hss_original(n=1024, leaf=32, r=4, cfg=12)
+    A = oh.dense_original(t)
+    assert np.abs(A - A.T).max() == 0.0
+    fro = float(np.sum(t.leaf_D ** 2)) + 2.0 * sum(float(np.sum(t.B[l] ** 2)) for l in t.B)
+    assert np.sum(A ** 2) == pytest.approx(fro, rel=1e-13)
+    assert np.trace(A) == pytest.approx(sum(np.trace(x) for x in t.leaf_D), rel=1e-13, abs=1e-13)
+    # the divided form has the same invariants of its spectrum
+    ev = np.linalg.eigvalsh(oh.dense_nodes(oh.divide(t))[(0, 0)])
+    assert np.sum(ev ** 2) == pytest.approx(fro, rel=1e-12)
