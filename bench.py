@@ -542,8 +542,9 @@ def bench_deflate(args):
 def bench_ex1(args):
     """The paper's first example end to end: the symmetric tridiagonal matrix with 3 on the
     diagonal and -1 beside it, n = 65536, written as an HSS form of rank 2 (leaf 128).  One
-    step: the dividing stage (balanced) and the conquering pass; the eigenvalues are checked
-    against the closed form 3 - 2 cos(k pi / (n + 1))."""
+    step: the dividing stage (balanced) and the conquering pass with deflation at the
+    paper's tau = 1e-10; the eigenvalues are checked against the closed form
+    3 - 2 cos(k pi / (n + 1)) and sampled eigenvectors against the matrix itself."""
     import torch
     from paper_2108_04209_amd import gen, native
     n, leaf = 65536, 128
@@ -553,7 +554,9 @@ def bench_ex1(args):
     dev = torch.device("cuda:0")
     gens = {k: torch.as_tensor(v, dtype=torch.float64, device=dev)
             for k, v in native.pack_hss(tree).items()}
-    o = native.default_opts(persistent=1, fmm_crossover=args.fmm_crossover, fmm_leaf=args.fmm_leaf)
+    tau = 1e-10
+    o = native.default_opts(persistent=1, fmm_crossover=args.fmm_crossover, fmm_leaf=args.fmm_leaf,
+                            hss_tau=tau)
     dv = native.hss_divide(ctx, plan, gens)
     out = native.hss_conquer(ctx, plan, dv, opts=o)
 
@@ -571,6 +574,10 @@ def bench_ex1(args):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
+    native.hss_set_timing(plan, True)
+    native.hss_conquer(ctx, plan, dv, opts=o, out=out)
+    phases, _ = native.hss_phase_times(plan)
+    native.hss_set_timing(plan, False)
     native.kernel_times()
     native.kernel_timing(True)
     try:
@@ -583,15 +590,29 @@ def bench_ex1(args):
     div = kt.get("k_divide", (0.0, 0))
     lam = out["lam"].cpu().numpy()
     exact = np.sort(3.0 - 2.0 * np.cos(np.arange(1, n + 1) * np.pi / (n + 1)))
+    rng = np.random.default_rng(5)
+    ks = np.sort(np.r_[0, n - 1, rng.choice(n, 30, replace=False)])
+    E = np.zeros((len(ks), n))
+    E[np.arange(len(ks)), ks] = 1.0
+    Qs = native.hss_apply(ctx, plan, torch.as_tensor(E, device=dev), trans=0).cpu().numpy().T
+    TQ = 3.0 * Qs
+    TQ[:-1] -= Qs[1:]
+    TQ[1:] -= Qs[:-1]
+    resid = float((np.linalg.norm(TQ - Qs * lam[ks], axis=0) / 5.0).max())
+    orth = float(np.abs(Qs.T @ Qs - np.eye(len(ks))).max())
     note(f"ex1 {ms:.2f} ms/step")
     return {"config": {"workload": "tridiagonal (3 on the diagonal, -1 beside it) as an HSS form "
                                    "of rank 2: n=65536, leaf 128, depth 9; balanced dividing "
-                                   "stage + conquering pass", "n": n, "leaf": leaf,
+                                   "stage + conquering pass with deflation, tau = 1e-10",
+                       "n": n, "leaf": leaf,
                        "depth": tree.depth, "r": 2},
-            "ms_per_step": ms, "divide_ms": div[0] / args.steps,
+            "ms_per_step": ms, "conquer_phase_ms": phases, "divide_ms": div[0] / args.steps,
             "divide_launches": div[1] // max(1, args.steps),
             "accuracy": {"status": int(out["status"].cpu().numpy()[0]),
-                         "lam_err_rel_normA": float(np.abs(lam - exact).max() / 5.0)}}
+                         "lam_err_rel_normA": float(np.abs(lam - exact).max() / 5.0),
+                         "max_resid_rel_normA_sampled": resid, "orth_err_sampled": orth,
+                         "eigvecs_checked": len(ks)},
+            "tau": tau}
 
 
 # ---------------------------------------------------------------------------------------

@@ -87,6 +87,8 @@ typedef struct {
                             kept as lambda itself and every pole difference is formed as
                             d_j - lambda, the original secular equation; default 0     */
     int32_t reserved;    /* must be 0                                                     */
+    double hss_tau;      /* superdc_hss_conquer only: deflation tolerance (Remark 1) for every
+                            rank-one problem of the pass, finite, >= 0; default 0 (none)  */
 } superdc_opts;
 
 void superdc_opts_default(superdc_opts *opts);

@@ -42,6 +42,7 @@ int opts_check(const superdc_opts *o) {
     if (o->fmm_crossover < 0) return SUPERDC_EINVAL;
     if (o->unshifted != 0 && o->unshifted != 1) return SUPERDC_EINVAL;
     if (o->reserved != 0) return SUPERDC_EINVAL;
+    if (!std::isfinite(o->hss_tau) || o->hss_tau < 0.0) return SUPERDC_EINVAL;
     return SUPERDC_OK;
 }
 

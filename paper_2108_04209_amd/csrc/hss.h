@@ -50,6 +50,10 @@ hipError_t launch_permute(const int32_t *perm, int nl, int64_t n, int m, const d
                           int64_t ldx, double *Y, int64_t ldy, int scatter, hipStream_t s);
 hipError_t launch_leaf_apply(const double *Q, int L, int64_t n, int m, const double *X,
                              int64_t ldx, double *Y, int64_t ldy, int trans, hipStream_t s);
+// ascending sort of every segment of nl keys (ties keep their order); vout[pos] = index
+// within the segment of the key placed at pos.  kbuf, vbuf: n-entry work buffers.
+hipError_t launch_seg_sort(const double *keys, int nl, int64_t n, double *kout, int32_t *vout,
+                           double *kbuf, int32_t *vbuf, hipStream_t s);
 hipError_t launch_status_or(const int32_t *st, int cnt, int32_t *out, hipStream_t s);
 hipError_t launch_fill(double *x, int64_t n, double v, hipStream_t s);
 

@@ -300,6 +300,29 @@ __global__ __launch_bounds__(256) void k_merge(const double *lam_children, doubl
     perm[base + pos] = loc;
 }
 
+// One pass of a bottom-up merge sort inside every segment of nl keys: runs of w (the last
+// one ragged) are merged pairwise.  An element's place is its index in its run plus the
+// number of keys of the partner run that go before it (strictly smaller for the left run,
+// smaller or equal for the right one), so equal keys keep their order and every place lies
+// inside the pair of runs whatever the keys hold.
+__global__ __launch_bounds__(256) void k_sort_pass(const double *kin, const int32_t *vin,
+                                                   double *kout, int32_t *vout, int nl, int w,
+                                                   int64_t total) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    const int64_t base = (e / nl) * nl;
+    const int i = (int)(e - base);
+    const int ps = (i / (2 * w)) * (2 * w);
+    const int mid = min(ps + w, nl), end = min(ps + 2 * w, nl);
+    const double v = kin[e];
+    const int32_t idx = vin ? vin[e] : i;
+    int pos;
+    if (i < mid) pos = (i - ps) + count_less(kin + base + mid, end - mid, v);
+    else pos = (i - mid) + count_leq(kin + base + ps, mid - ps, v);
+    kout[base + ps + pos] = v;
+    vout[base + ps + pos] = idx;
+}
+
 // ---------------------------------------------------------------------------------------
 // update columns Z = P [W_c1 B_p / sqrt(beta_p) ; sqrt(beta_p) W_c2] and basis columns
 // V = P [W_c1 R_c1 ; W_c2 R_c2] of every node of a level
@@ -412,6 +435,30 @@ hipError_t launch_leaf_jacobi(const LeafArgs &a, hipStream_t s) {
 hipError_t launch_merge(const double *lam_children, double *d_out, int32_t *perm, int nc,
                         int64_t n, hipStream_t s) {
     SDC_LAUNCH(KID_MERGE, k_merge, grid_for(n), dim3(256), 0, s, lam_children, d_out, perm, nc, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_seg_sort(const double *keys, int nl, int64_t n, double *kout, int32_t *vout,
+                           double *kbuf, int32_t *vbuf, hipStream_t s) {
+    int passes = 0;
+    while ((1 << passes) < nl) ++passes;
+    if (passes == 0) {  // segments of one key
+        SDC_LAUNCH(KID_SORT, k_sort_pass, grid_for(n), dim3(256), 0, s, keys, nullptr, kout, vout,
+                   1, 1, n);
+        return hipGetLastError();
+    }
+    const double *kin = keys;
+    const int32_t *vin = nullptr;
+    for (int q = 0; q < passes; ++q) {
+        // the last pass writes the outputs
+        const bool to_out = ((passes - 1 - q) & 1) == 0;
+        double *ko = to_out ? kout : kbuf;
+        int32_t *vo = to_out ? vout : vbuf;
+        SDC_LAUNCH(KID_SORT, k_sort_pass, grid_for(n), dim3(256), 0, s, kin, vin, ko, vo, nl,
+                   1 << q, n);
+        kin = ko;
+        vin = vo;
+    }
     return hipGetLastError();
 }
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -38,6 +39,26 @@ struct superdc_hss {
     int32_t *status = nullptr; // [depth][r][2^(depth-1)]
     double *T[2] = {nullptr, nullptr};  // apply work buffers
     double *Hdiv = nullptr;    // dividing stage: pending updates per node (on first use)
+    // deflation inside the pass (opts->hss_tau > 0), allocated on first use; per level l and
+    // step t ([depth][r][n] unless noted) the factor G^T P of Remark 1, the reduced problem
+    // and the sort S of its eigenvalues, so that the step's eigenvector matrix is
+    // G^T P (Qhat (+) I) S^T (S^T scatters by dS, S gathers)
+    bool defl = false;         // the last conquer deflated
+    bool defl_mem = false;
+    double *dr = nullptr;      // reduced poles (reduced layout, at most n)
+    int32_t *dperm = nullptr, *drr = nullptr, *drl = nullptr, *dS = nullptr;
+    double *dc = nullptr, *ds = nullptr;
+    int32_t *dkept = nullptr;  // [depth][r][2^(depth-1)]
+    std::vector<superdc_batch *> rb;  // [depth][r] reduced batches of the last deflated pass
+    // work buffers of the deflated pass
+    double *xd = nullptr, *xz = nullptr, *xzr = nullptr, *xlam = nullptr, *xE = nullptr,
+           *xk = nullptr;  // n
+    int32_t *xv = nullptr; // n
+    double2 *xval = nullptr;
+    int8_t *xflag = nullptr;
+    double *xY = nullptr, *xR0 = nullptr, *xR1 = nullptr, *xT = nullptr;  // n x 2r
+    double *xa[3] = {nullptr, nullptr, nullptr};  // apply work buffers of a deflated pass
+    int64_t xcap = 0;
     int64_t tcap = 0;
     bool ready = false;
     // optional phase timing: events recorded between phases of the last conquer
@@ -50,6 +71,12 @@ struct superdc_hss {
     size_t idx(int l, int t) const { return ((size_t)l * r + t) * (size_t)n; }
     int32_t *st(int l, int t) const {
         return status + ((size_t)l * r + t) * ((size_t)1 << (depth - 1));
+    }
+    // status words of the deflation pass, after the leaves' words
+    size_t nstat() const { return (size_t)depth * r * ((size_t)1 << (depth - 1)) + ((size_t)1 << depth); }
+    int32_t *dst(int l, int t) const { return st(l, t) + nstat(); }
+    int32_t *kept(int l, int t) const {
+        return dkept + ((size_t)l * r + t) * ((size_t)1 << (depth - 1));
     }
     const double *poles(int l, int t) const { return t == 0 ? poles0 + (size_t)l * n : lam + idx(l, t - 1); }
 };
@@ -81,6 +108,112 @@ hipError_t mark(superdc_hss *h, int phase, hipStream_t s) {
     h->ev_phase[h->nev] = phase;
     return hipEventRecord(h->ev[h->nev++], s);
 }
+
+hipError_t defl_alloc(superdc_hss *h) {
+    if (h->defl_mem) return hipSuccess;
+    const size_t n = h->n, r = h->r, steps = (size_t)h->depth * r;
+    hipError_t e = alloc(h, &h->dr, steps * n);
+    if (e == hipSuccess) e = alloc(h, &h->dperm, steps * n);
+    if (e == hipSuccess) e = alloc(h, &h->drr, steps * n);
+    if (e == hipSuccess) e = alloc(h, &h->drl, steps * n);
+    if (e == hipSuccess) e = alloc(h, &h->dS, steps * n);
+    if (e == hipSuccess) e = alloc(h, &h->dc, steps * n);
+    if (e == hipSuccess) e = alloc(h, &h->ds, steps * n);
+    if (e == hipSuccess) e = alloc(h, &h->dkept, steps * ((size_t)1 << (h->depth - 1)));
+    for (double **p : {&h->xd, &h->xz, &h->xzr, &h->xlam, &h->xE, &h->xk})
+        if (e == hipSuccess) e = alloc(h, p, n);
+    if (e == hipSuccess) e = alloc(h, &h->xv, n);
+    if (e == hipSuccess) e = alloc(h, &h->xval, n);
+    if (e == hipSuccess) e = alloc(h, &h->xflag, n);
+    for (double **p : {&h->xY, &h->xR0, &h->xR1, &h->xT})
+        if (e == hipSuccess) e = alloc(h, p, n * 2 * r);
+    if (e == hipSuccess) {
+        h->rb.assign(steps, nullptr);
+        h->defl_mem = true;
+    }
+    return e;
+}
+
+// One rank-one step of level l with deflation (Remark 1): deflate every node's problem,
+// gather the reduced problems into a batch of their sizes (read back from the device),
+// solve them, and sort each node's eigenvalues -- the reduced roots and the deflated
+// values -- into the poles of the next step.  The remaining update and basis columns
+// (cur's columns t+1 .. ncol-1) are taken to the new eigenbasis:
+// S ((Qhat^T (+) I) P^T G) X, into the other buffer.
+int defl_step(superdc_ctx *ctx, superdc_hss *h, int l, int t, int cur, int ncol,
+              const superdc_opts &o, void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    superdc_batch *b = h->batch[l];
+    const int nprob = b->nprob;
+    const int64_t n = h->n;
+    const int nl = (int)(n >> l);
+    const size_t k = h->idx(l, t);
+    const double *poles = h->poles(l, t);
+    const double *zc = h->M[cur] + (size_t)t * n;
+    int32_t *kept = h->kept(l, t);
+    hipError_t e = launch_deflate(b->off_d, nprob, poles, zc, h->ones, o.hss_tau, h->xd, h->xz,
+                                  h->dperm + k, h->drr + k, h->drl + k, h->dc + k, h->ds + k,
+                                  kept, h->dst(l, t), h->xval, h->xflag, s);
+    if (e != hipSuccess) return fail(e);
+    std::vector<int32_t> kh(nprob);
+    if ((e = hipMemcpyAsync(kh.data(), kept, sizeof(int32_t) * nprob, hipMemcpyDeviceToHost, s)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return fail(e);
+    // a node that deflated completely keeps a one-pole stand-in (d = 0, z = 1) whose
+    // results are never copied back
+    std::vector<int64_t> roff(nprob + 1, 0);
+    for (int p = 0; p < nprob; ++p) roff[p + 1] = roff[p] + std::max(kh[p], 1);
+    superdc_batch *&rb = h->rb[(size_t)l * h->r + t];
+    if (rb) superdc_batch_destroy(rb);
+    rb = nullptr;
+    int rc = superdc_batch_create(ctx, nprob, roff.data(), &rb);
+    if (rc) return rc;
+    const int64_t rt = roff[nprob];
+    const double zero = 0.0, one = 1.0;
+    double *dr = h->dr + k;
+    if ((e = launch_copy_rows(b->off_d, rb->off_d, nprob, rt, 1, kept, h->xd, n, dr, rt, &zero,
+                              s)) != hipSuccess ||
+        (e = launch_copy_rows(b->off_d, rb->off_d, nprob, rt, 1, kept, h->xz, n, h->xzr, rt, &one,
+                              s)) != hipSuccess ||
+        (e = mark(h, 1, s)) != hipSuccess)
+        return fail(e);
+    rc = superdc_secular_solve(ctx, rb, dr, h->xzr, h->ones, h->xlam, h->eta + k, h->org + k,
+                               h->iters + k, h->st(l, t), &o, stream);
+    if (rc) return rc;
+    if ((e = mark(h, 2, s)) != hipSuccess) return fail(e);
+    rc = loewner_run(ctx, rb, dr, h->xzr, h->ones, h->eta + k, h->org + k, h->st(l, t),
+                     h->zhat + k, h->bn + k, &o, stream, true);
+    if (rc) return rc;
+    if ((e = mark(h, 3, s)) != hipSuccess) return fail(e);
+    // the step's eigenvalues per node: reduced roots first, deflated values after, sorted
+    if ((e = hipMemcpyAsync(h->xE, h->xd, sizeof(double) * n, hipMemcpyDeviceToDevice, s)) !=
+            hipSuccess ||
+        (e = launch_copy_rows(rb->off_d, b->off_d, nprob, n, 1, kept, h->xlam, rt, h->xE, n,
+                              nullptr, s)) != hipSuccess ||
+        (e = launch_seg_sort(h->xE, nl, n, h->lam + k, h->dS + k, h->xk, h->xv, s)) != hipSuccess)
+        return fail(e);
+    const int m = ncol - t - 1;
+    if (m > 0) {
+        const double *X = h->M[cur] + (size_t)(t + 1) * n;
+        if ((e = launch_deflate_expand(b->off_d, nprob, n, m, h->dperm + k, h->drr + k, h->drl + k,
+                                       h->dc + k, h->ds + k, 1, X, n, h->xY, n, h->xT, s)) !=
+                hipSuccess ||
+            (e = launch_copy_rows(b->off_d, rb->off_d, nprob, rt, m, kept, h->xY, n, h->xR0, rt,
+                                  &zero, s)) != hipSuccess)
+            return fail(e);
+        rc = apply_run(ctx, rb, dr, h->zhat + k, h->bn + k, h->eta + k, h->org + k, h->st(l, t), 1,
+                       m, h->xR0, rt, h->xR1, rt, &o, stream, true);
+        if (rc) return rc;
+        if ((e = launch_copy_rows(rb->off_d, b->off_d, nprob, n, m, kept, h->xR1, rt, h->xY, n,
+                                  nullptr, s)) != hipSuccess ||
+            (e = launch_permute(h->dS + k, nl, n, m, h->xY, n, h->M[1 - cur] + (size_t)(t + 1) * n,
+                                n, 0, s)) != hipSuccess)
+            return fail(e);
+    }
+    if ((e = mark(h, 4, s)) != hipSuccess) return fail(e);
+    return SUPERDC_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -88,6 +221,7 @@ extern "C" {
 void superdc_hss_plan_destroy(superdc_hss *h) {
     if (!h) return;
     (void)hipDeviceSynchronize();
+    for (auto *b : h->rb) superdc_batch_destroy(b);
     for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
     for (auto *b : h->batch) superdc_batch_destroy(b);
     for (void *p : h->allocs) (void)hipFree(p);
@@ -140,14 +274,15 @@ int superdc_hss_plan_create(superdc_ctx *ctx, int32_t leaf, int32_t depth, int32
     if (e == hipSuccess) e = alloc(h, &h->org, (size_t)depth * r * n);
     if (e == hipSuccess) e = alloc(h, &h->perm, (size_t)depth * n);
     // per-node status bits of every rank-one step, then one word per leaf
+    // twice the nodes' words: the solves', the leaves', then the deflation pass's
     if (e == hipSuccess)
-        e = alloc(h, &h->status, (size_t)depth * r * ((size_t)1 << (depth - 1)) + nleaf);
+        e = alloc(h, &h->status, 2 * (size_t)depth * r * ((size_t)1 << (depth - 1)) + nleaf);
     if (e == hipSuccess) e = launch_fill(h->ones, n, 1.0, nullptr);
     if (e == hipSuccess) e = hipMemset(h->perm, 0, sizeof(int32_t) * (size_t)depth * n);
     // level l uses 2^l of the 2^(depth-1) status slots of each step; the rest stay 0
     if (e == hipSuccess)
         e = hipMemset(h->status, 0,
-                      sizeof(int32_t) * ((size_t)depth * r * ((size_t)1 << (depth - 1)) + nleaf));
+                      sizeof(int32_t) * (2 * (size_t)depth * r * ((size_t)1 << (depth - 1)) + nleaf));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         superdc_hss_plan_destroy(h);
@@ -195,10 +330,20 @@ int superdc_hss_conquer(superdc_ctx *ctx, superdc_hss *h, const double *leaf_D,
     superdc_opts o;
     if (opts) o = *opts;
     else superdc_opts_default(&o);
+    if (!std::isfinite(o.hss_tau) || o.hss_tau < 0.0) return SUPERDC_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = h->n;
     const int r = h->r, D = h->depth;
     h->ready = false;
+    const bool defl = o.hss_tau > 0.0;
+    h->defl = defl;
+    if (defl) {
+        hipError_t ea = defl_alloc(h);
+        if (ea != hipSuccess) return fail(ea);
+        // the deflation pass's status words start clear
+        ea = hipMemsetAsync(h->dst(0, 0), 0, sizeof(int32_t) * (size_t)D * r * ((size_t)1 << (D - 1)), s);
+        if (ea != hipSuccess) return fail(ea);
+    }
     h->nev = 0;
     hipError_t e;
     if ((e = mark(h, -1, s)) != hipSuccess) return fail(e);
@@ -248,6 +393,12 @@ int superdc_hss_conquer(superdc_ctx *ctx, superdc_hss *h, const double *leaf_D,
         const int ncol = l > 0 ? 2 * r : r;
         int cur = mbuf;
         for (int t = 0; t < r; ++t) {
+            if (defl) {
+                int rc = defl_step(ctx, h, l, t, cur, ncol, o, stream);
+                if (rc) return rc;
+                cur = 1 - cur;
+                continue;
+            }
             const double *poles = h->poles(l, t);
             const double *zc = h->M[cur] + (size_t)t * n;
             double *lam_t = h->lam + h->idx(l, t);
@@ -290,8 +441,8 @@ int superdc_hss_conquer(superdc_ctx *ctx, superdc_hss *h, const double *leaf_D,
                            hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return fail(e);
     }
-    if ((e = launch_status_or(h->status, D * r * (1 << (D - 1)) + (1 << D), status_out, s)) !=
-        hipSuccess)
+    if ((e = launch_status_or(h->status, (int)(h->nstat() + (defl ? (size_t)D * r * (1 << (D - 1)) : 0)),
+                              status_out, s)) != hipSuccess)
         return fail(e);
     if ((e = mark(h, 5, s)) != hipSuccess) return fail(e);
     h->ready = true;
@@ -359,6 +510,54 @@ int superdc_hss_apply(superdc_ctx *ctx, superdc_hss *h, int trans, int32_t m, co
         h->tcap = n * m;
     }
     double *T0 = h->T[0], *T1 = h->T[1];
+    if (h->defl) {
+        if (h->xcap < n * m) {
+            for (double **p : {&h->xa[0], &h->xa[1], &h->xa[2]}) {
+                if (*p) {
+                    (void)hipDeviceSynchronize();
+                    (void)hipFree(*p);
+                    h->allocs.erase(std::find(h->allocs.begin(), h->allocs.end(), (void *)*p));
+                    *p = nullptr;
+                }
+                if ((e = alloc(h, p, n * m)) != hipSuccess) return fail(e);
+            }
+            h->xcap = n * m;
+        }
+    }
+    // one step of a deflated pass (see defl_step): trans 1 applies S (Qhat^T (+) I) P^T G
+    // to T0, trans 0 G^T P (Qhat (+) I) S^T; the result is left in T0
+    auto defl_apply = [&](int l, int t, int tr) -> int {
+        superdc_batch *b = h->batch[l], *rb = h->rb[(size_t)l * r + t];
+        const int nprob = b->nprob, nl = (int)(n >> l);
+        const int64_t rt = rb->total;
+        const size_t k = h->idx(l, t);
+        const int32_t *kept = h->kept(l, t);
+        double *R0 = h->xa[0], *R1 = h->xa[1], *Tx = h->xa[2];
+        const double zero = 0.0;
+        hipError_t ee;
+        if (tr == 1) {
+            if ((ee = launch_deflate_expand(b->off_d, nprob, n, m, h->dperm + k, h->drr + k,
+                                            h->drl + k, h->dc + k, h->ds + k, 1, T0, n, T1, n, Tx,
+                                            s)) != hipSuccess)
+                return fail(ee);
+        } else if ((ee = launch_permute(h->dS + k, nl, n, m, T0, n, T1, n, 1, s)) != hipSuccess) {
+            return fail(ee);
+        }
+        if ((ee = launch_copy_rows(b->off_d, rb->off_d, nprob, rt, m, kept, T1, n, R0, rt, &zero,
+                                   s)) != hipSuccess)
+            return fail(ee);
+        int rc = superdc_cauchy_apply(ctx, rb, h->dr + k, h->zhat + k, h->bn + k, h->eta + k,
+                                      h->org + k, h->st(l, t), tr, m, R0, rt, R1, rt, &o, stream);
+        if (rc) return rc;
+        if ((ee = launch_copy_rows(rb->off_d, b->off_d, nprob, n, m, kept, R1, rt, T1, n, nullptr,
+                                   s)) != hipSuccess)
+            return fail(ee);
+        if (tr == 1) ee = launch_permute(h->dS + k, nl, n, m, T1, n, T0, n, 0, s);
+        else
+            ee = launch_deflate_expand(b->off_d, nprob, n, m, h->dperm + k, h->drr + k, h->drl + k,
+                                       h->dc + k, h->ds + k, 0, T1, n, T0, n, Tx, s);
+        return ee == hipSuccess ? SUPERDC_OK : fail(ee);
+    };
     if (trans == 1) {
         // Q^T X: leaves, then per level P and Qhat_1^T .. Qhat_r^T (Alg. 4, transposed)
         if ((e = launch_leaf_apply(h->leafQ, h->leaf, n, m, X, ldx, T0, n, 1, s)) != hipSuccess)
@@ -370,6 +569,11 @@ int superdc_hss_apply(superdc_ctx *ctx, superdc_hss *h, int trans, int32_t m, co
                 return fail(e);
             std::swap(T0, T1);
             for (int t = 0; t < r; ++t) {
+                if (h->defl) {
+                    int rc = defl_apply(l, t, 1);
+                    if (rc) return rc;
+                    continue;
+                }
                 int rc = superdc_cauchy_apply(ctx, h->batch[l], h->poles(l, t),
                                               h->zhat + h->idx(l, t), h->bn + h->idx(l, t),
                                               h->eta + h->idx(l, t), h->org + h->idx(l, t),
@@ -393,6 +597,11 @@ int superdc_hss_apply(superdc_ctx *ctx, superdc_hss *h, int trans, int32_t m, co
         for (int l = 0; l < D; ++l) {
             const int nl = (int)(n >> l);
             for (int t = r - 1; t >= 0; --t) {
+                if (h->defl) {
+                    int rc = defl_apply(l, t, 0);
+                    if (rc) return rc;
+                    continue;
+                }
                 int rc = superdc_cauchy_apply(ctx, h->batch[l], h->poles(l, t),
                                               h->zhat + h->idx(l, t), h->bn + h->idx(l, t),
                                               h->eta + h->idx(l, t), h->org + h->idx(l, t),

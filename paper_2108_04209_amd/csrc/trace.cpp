@@ -50,7 +50,7 @@ const char *kNames[KID_COUNT] = {
     "k_leaf_jacobi", "k_merge", "k_assemble", "k_permute", "k_leaf_apply", "k_status_or",
     "k_fill", "k_leaf_vectors", "k_fmm_geom", "k_fmmv_pack", "k_fmmv_sources", "k_fmmv_eval",
     "k_fmmv_eval_mfma", "k_fmml_pack", "k_fmml_moments", "k_loewner_fmm", "k_deflate",
-    "k_defl_place", "k_defl_rotate", "k_copy_rows", "k_fmm_local", "k_divide"};
+    "k_defl_place", "k_defl_rotate", "k_copy_rows", "k_fmm_local", "k_divide", "k_sort_pass"};
 
 }  // namespace
 
