@@ -15,6 +15,11 @@
 #include "common.h"
 #include "fmm.h"
 
+// waves per CU the FMM solver's split aims at (its items times the split)
+#ifndef SDC_FMM_WAVES_PER_CU
+#define SDC_FMM_WAVES_PER_CU 16
+#endif
+
 using namespace sdc;
 
 namespace {
@@ -209,7 +214,8 @@ FmmPlan *fmm_plan(superdc_batch *b, int leaf, int crossover) {
         for (int t = fp->sitem_off_h[q]; t < fp->sitem_off_h[q + 1]; ++t) slpt.push_back(snat[t]);
     }
     fp->ssplit = 1;
-    while (fp->ssplit < 8 && (long)fp->snitems * fp->ssplit * 2 <= (long)b->ctx->num_cu * 16)
+    while (fp->ssplit < 8 &&
+           (long)fp->snitems * fp->ssplit * 2 <= (long)b->ctx->num_cu * SDC_FMM_WAVES_PER_CU)
         fp->ssplit *= 2;
     bool ok = fmm_upload(fp, &fp->fmm_prob, fp->fmm_prob_h) &&
               fmm_upload(fp, &fp->fmm_of, fp->fmm_of_h) &&

@@ -164,11 +164,16 @@ int defl_step(superdc_ctx *ctx, superdc_hss *h, int l, int t, int cur, int ncol,
     // results are never copied back
     std::vector<int64_t> roff(nprob + 1, 0);
     for (int p = 0; p < nprob; ++p) roff[p + 1] = roff[p] + std::max(kh[p], 1);
+    // the batch of the same step in the previous pass is kept when the sizes agree (its
+    // tile lists and FMM plan depend on nothing else)
     superdc_batch *&rb = h->rb[(size_t)l * h->r + t];
-    if (rb) superdc_batch_destroy(rb);
-    rb = nullptr;
-    int rc = superdc_batch_create(ctx, nprob, roff.data(), &rb);
-    if (rc) return rc;
+    int rc = SUPERDC_OK;
+    if (!rb || rb->off_h != roff) {
+        if (rb) superdc_batch_destroy(rb);
+        rb = nullptr;
+        rc = superdc_batch_create(ctx, nprob, roff.data(), &rb);
+        if (rc) return rc;
+    }
     const int64_t rt = roff[nprob];
     const double zero = 0.0, one = 1.0;
     double *dr = h->dr + k;
