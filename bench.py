@@ -739,6 +739,24 @@ def bench_conquer(args):
         fin = np.isfinite(lam_un)
         abl["max_lam_diff_rel_normA_finite"] = (
             float(np.abs(lam_un[fin] - lam[fin]).max() / np.abs(lam).max()) if fin.any() else None)
+        # the hybrid interpolation of [li93] (middle way and fixed weight) in place of the
+        # middle way alone, with local shifting
+        o_hy = native.default_opts(persistent=1, fmm_crossover=args.fmm_crossover,
+                                   fmm_leaf=args.fmm_leaf, interp=1)
+        native.hss_conquer(ctx, plan, gens, opts=o_hy)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        hy = native.hss_conquer(ctx, plan, gens, opts=o_hy)
+        e1.record()
+        torch.cuda.synchronize()
+        it_hy = native.hss_iterations(plan).cpu().numpy()
+        abl["hybrid_li93"] = {"mu_percent": mu(it_hy), "mean_iters": float(it_hy.mean()),
+                              "mean_iters_middle_way": float(iters.mean()),
+                              "ms_per_step": e0.elapsed_time(e1),
+                              "status": int(hy["status"].cpu().numpy()[0]),
+                              "max_lam_diff_rel_normA": float(np.abs(hy["lam"].cpu().numpy() - lam).max()
+                                                              / np.abs(lam).max())}
         native.hss_conquer(ctx, plan, gens, opts=opts1, out=out)  # restore the shifted state
         torch.cuda.synchronize()
     # graph replay of the same step (timing events off while capturing)

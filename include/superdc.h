@@ -86,7 +86,11 @@ typedef struct {
     int32_t unshifted;   /* 1: ablation of the local shifting (Sec. 4.2.2): the iterate is
                             kept as lambda itself and every pole difference is formed as
                             d_j - lambda, the original secular equation; default 0     */
-    int32_t reserved;    /* must be 0                                                     */
+    int32_t interp;      /* rational interpolation of the iteration (Sec. 4.1.1): 0 the middle
+                            way (default); 1 the hybrid of [li93]: the middle way and the
+                            fixed-weight scheme (the nearer pole keeps its true weight, the
+                            other pole's matches f'), switching scheme after a step that
+                            leaves f's sign unchanged and reduces |f| by less than 10x      */
     double hss_tau;      /* superdc_hss_conquer only: deflation tolerance (Remark 1) for every
                             rank-one problem of the pass, finite, >= 0; default 0 (none)  */
 } superdc_opts;

@@ -46,7 +46,7 @@ int opts_check(const superdc_opts *o) {
     if (o->apply_kernel < 0 || o->apply_kernel > 2) return SUPERDC_EINVAL;
     if (o->fmm_crossover < 0) return SUPERDC_EINVAL;
     if (o->unshifted != 0 && o->unshifted != 1) return SUPERDC_EINVAL;
-    if (o->reserved != 0) return SUPERDC_EINVAL;
+    if (o->interp != 0 && o->interp != 1) return SUPERDC_EINVAL;
     if (!std::isfinite(o->hss_tau) || o->hss_tau < 0.0) return SUPERDC_EINVAL;
     return SUPERDC_OK;
 }
@@ -728,6 +728,7 @@ int superdc_secular_solve(superdc_ctx *ctx, const superdc_batch *b, const double
     a.stop_c = o.stop_c;
     a.max_iter = o.max_iter;
     a.unshifted = o.unshifted;
+    a.hybrid = o.interp;
     superdc_batch *bm = const_cast<superdc_batch *>(b);
     // problems at or above the crossover size use the triangular FMM (method 2: every
     // problem large enough to have two leaves; method 1: none)

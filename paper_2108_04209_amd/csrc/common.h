@@ -270,6 +270,7 @@ struct SolveArgs {
     int chunk;       // roots per work item (the tile list is cut at this length)
     unsigned long long *work;  // when kernel timing is on: pole-root pair evaluations
     int unshifted;   // ablation: iterate on lambda itself, every difference d_j - lambda
+    int hybrid;      // interpolation: 0 middle way, 1 the middle-way / fixed-weight hybrid
 };
 hipError_t launch_validate(const SolveArgs &a, int prob_first, int nprob, int max_n, hipStream_t s);
 hipError_t launch_secular(const SolveArgs &a, int split, Queue *q, int grid, hipStream_t s);

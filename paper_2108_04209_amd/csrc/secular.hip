@@ -445,6 +445,8 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
 
     int next = c0;  // next unassigned root (wave-uniform)
     bool act = false, last = false, hi_closed = false, noconv = false;
+    bool fw = false;     // hybrid: the fixed-weight scheme takes the next step
+    double fprev = 0.0;  // hybrid: f at the previous iterate
     int k = c0, K = c0, nev = 0, phase = 0;
     double dk = 0.0, dk1 = 0.0, dK = 0.0, y = 0.0, lo = 0.0, hi = 0.0;
     for (;;) {
@@ -465,6 +467,7 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
             phase = 0;
             nev = 0;
             hi_closed = false;
+            fw = false;
         }
         next = min(c1, next + (int)__popcll(freem));
         if (__ballot(act) == 0ull) break;
@@ -519,15 +522,39 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
             done = true;
             noconv = true;
         }
+        if (a.hybrid && phase == 1 && nev > 0) {
+            // hybrid [li93]: a step that kept f's sign and did not cut |f| tenfold hands the
+            // next step to the other scheme
+            if ((f < 0.0) == (fprev < 0.0) && fabs(f) > 0.1 * fabs(fprev)) fw = !fw;
+        }
+        fprev = f;
         if (!done) {
             double yn;
             if (!last) {
-                // middle-way: psi ~ a1 + b1/(d_k - x), phi ~ a2 + b2/(d_{k+1} - x)
+                // f ~ C + b1/(d_k - x) + b2/(d_{k+1} - x) through f and f' at the iterate,
+                // solved as a quadratic in the step s: the middle way takes b1 = psi' A^2,
+                // b2 = phi' B^2; the fixed-weight scheme gives the origin's pole its true
+                // weight w_K and the other pole the rest of f'
                 const double xl = dK + y;
                 const double A = unsh ? dk - xl : (dk - dK) - y;   // < 0
                 const double B = unsh ? dk1 - xl : (dk1 - dK) - y;  // > 0
-                const double C = f - dpsi * A - dphi * B;
-                const double qa = C * (A + B) + dpsi * A * A + dphi * B * B;
+                double C, qa;
+                if (!fw) {
+                    C = f - dpsi * A - dphi * B;
+                    qa = C * (A + B) + dpsi * A * A + dphi * B * B;
+                } else {
+                    const double wK = dw[K].y, df = dpsi + dphi;
+                    double b1, b2;
+                    if (K == k) {
+                        b1 = wK;
+                        b2 = fmax(df - wK / (A * A), 0.0) * B * B;
+                    } else {
+                        b2 = wK;
+                        b1 = fmax(df - wK / (B * B), 0.0) * A * A;
+                    }
+                    C = f - b1 / A - b2 / B;
+                    qa = C * (A + B) + b1 + b2;
+                }
                 const double qb = A * B * f;
                 const double disc = sqrt(fabs(qa * qa - 4.0 * qb * C));
                 const double s = qa > 0.0 ? (2.0 * qb) / (qa + disc) : (qa - disc) / (2.0 * C);

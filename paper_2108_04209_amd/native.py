@@ -26,7 +26,7 @@ class Opts(C.Structure):
     _fields_ = [("stop_c", C.c_double), ("max_iter", C.c_int32), ("method", C.c_int32),
                 ("fmm_order", C.c_int32), ("fmm_leaf", C.c_int32), ("persistent", C.c_int32),
                 ("apply_kernel", C.c_int32), ("fmm_crossover", C.c_int32),
-                ("unshifted", C.c_int32), ("reserved", C.c_int32),
+                ("unshifted", C.c_int32), ("interp", C.c_int32),
                 ("hss_tau", C.c_double)]
 
 

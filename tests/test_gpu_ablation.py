@@ -83,3 +83,38 @@ def test_unshifted_inside_clusters(orc, method):
     med = np.median(err(un))  # NaN (a gap that rounded to zero) also fails the bars below
     assert not med <= 1e-7
     assert not med <= 100 * max(err(sh).max(), 1e-16)
+
+
+@pytest.mark.parametrize("kind", ["uniform", "clustered", "tinyrho"])
+@pytest.mark.parametrize("method", [1, 2])
+def test_hybrid_interpolation(orc, kind, method):
+    """opts.interp = 1, the middle-way / fixed-weight hybrid of [li93]: the same
+    eigenvalues as the oracle (the interpolation decides only the path of the iteration)
+    and gaps within the stopping test's guarantee, every root converged, with the direct
+    sums and with the FMM."""
+    from paper_2108_04209_amd import native
+    from tests import gpu_pipeline as gp
+    batch = gen.small_batch([2048, 777, 4100], seed=84, kind=kind)
+    res = gp.run(batch, opts=native.default_opts(interp=1, method=method), vectors=False)
+    mw = gp.run(batch, opts=native.default_opts(method=method), vectors=False)
+    assert (res["status"] == 0).all()
+    for p in range(batch.nprob):
+        a, e = int(batch.off[p]), int(batch.off[p + 1])
+        pr = batch.problem(p)
+        lam, eta = orc.secular(pr.d, pr.z, pr.rho)[:2]
+        assert np.abs(res["lam"][a:e] - lam).max() <= 1e-12 * np.abs(lam).max(), p
+        # same origins; each gap within what the stopping test guarantees at the root:
+        # |f| <= c n eps (1 + |psi| + |phi|) moves it by at most that over f'
+        assert (res["origin"][a:e] == mw["origin"][a:e]).all()
+        K = res["origin"][a:e]
+        t = (pr.d[:, None] - pr.d[K][None, :]) - eta[None, :]
+        wv = (pr.rho * pr.z ** 2)[:, None]
+        below = np.arange(pr.n)[:, None] <= np.arange(pr.n)[None, :]
+        psi = np.where(below, wv / t, 0.0).sum(0)
+        phi = np.where(below, 0.0, wv / t).sum(0)
+        fp = (wv / t ** 2).sum(0)
+        eps = np.finfo(float).eps
+        bound = 2.0 * pr.n * eps * (1.0 + np.abs(psi) + np.abs(phi)) / fp + 4.0 * eps * np.abs(eta)
+        assert np.all(np.abs(res["eta"][a:e] - eta) <= bound), p
+    # the hybrid takes at most a few more steps on average than the middle way
+    assert res["iters"].mean() <= mw["iters"].mean() + 1.0
