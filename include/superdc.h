@@ -313,6 +313,12 @@ int superdc_hss_divide(superdc_ctx *ctx, superdc_hss *plan, const double *leaf_D
  * (row l: eigenvalues of every level-l node, ascending per node); status[1]: OR of the
  * status bits of every rank-one problem solved.  The structured eigenmatrix stays in the
  * plan for superdc_hss_apply until the next conquer on the same plan.
+ * opts->hss_tau > 0 deflates every rank-one problem of the pass (Remark 1, as in Alg. 3):
+ * per step the host reads the kept counts back (one stream synchronisation; such a pass
+ * cannot be captured in a graph), solves the reduced problems as a batch of their sizes and
+ * sorts each node's eigenvalues; superdc_hss_apply replays the rotations, placements and
+ * sorts.  Without deflation a problem with a vanishing weight or equal poles fails: its
+ * node returns NaN eigenvalues and its bits in status (SUPERDC_ST_ZERO, _UNSORTED).
  */
 int superdc_hss_conquer(superdc_ctx *ctx, superdc_hss *plan, const double *leaf_D,
                         const double *leaf_U, const double *R, const double *B,
