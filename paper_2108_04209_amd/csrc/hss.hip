@@ -14,18 +14,30 @@
 namespace sdc {
 
 // ---------------------------------------------------------------------------------------
-// leaf eigendecomposition: cyclic Jacobi in two kernels.  The matrix (128 x 129 doubles)
-// fills most of a CU's LDS, so the eigenvector accumulation cannot sit beside it:
-//   k_leaf_jacobi  rotates A in LDS and logs every round's rotation tangents t to HBM;
-//   k_leaf_vectors replays the log on V = I held in LDS, then writes the sorted
-//                  eigenvectors and W = Q^T U.
-// Both use the round-robin (circle) pair ordering, so a round's pairs are disjoint.
+// leaf eigendecomposition: cyclic Jacobi in three kernels, each sized so that two
+// workgroups share a CU (the rounds are short and end in barriers: a second leaf's waves
+// fill the first one's waits):
+//   k_leaf_jacobi  rotates A -- its upper triangle, packed by rows (66 KB for a leaf of
+//                  128) -- in LDS and logs every round's rotation tangents t to HBM;
+//   k_leaf_vectors replays the log on V = I, half of V's rows per workgroup (rows of V J
+//                  are independent), then writes those rows of the sorted eigenvectors;
+//   k_leaf_w       W = Q^T U from the stored eigenvectors.
+// All use the round-robin (circle) pair ordering, so a round's pairs are disjoint.
 // ---------------------------------------------------------------------------------------
 constexpr int LJ_LD = LEAF_MAX + 1;
 constexpr int LJ_THREADS = 1024;
-constexpr int LV_RB = 8;  // rounds of rotations staged in LDS per block of the replay
-constexpr int LV_ROWS = LEAF_MAX / (LJ_THREADS / WAVE);  // rows per wavefront in the replay (8)
+constexpr int LJ_PACKED = LEAF_MAX * (LEAF_MAX + 1) / 2;
+// blocks of the folded triangle per thread: (h/2)(h+1) blocks, h = LEAF_MAX/2 rounded up
+// to even, over LJ_THREADS threads
+constexpr int LJ_BLK = ((LEAF_MAX / 4) * (LEAF_MAX / 2 + 1) + LJ_THREADS - 1) / LJ_THREADS;
+constexpr int LV_THREADS = 512;
+constexpr int LV_RB = 4;  // rounds of rotations staged in LDS per block of the replay
+constexpr int LV_ROWS = (LEAF_MAX / 2) / (LV_THREADS / WAVE);  // rows per wavefront (8)
 static_assert(LEAF_MAX / 2 <= WAVE, "a round's pairs must fit one wavefront");
+static_assert(LV_RB * (LEAF_MAX / 2) <= LV_THREADS, "one tangent per staging thread");
+
+// entry (i, j), i <= j, of the upper triangle of an m x m matrix packed by rows
+__device__ __forceinline__ int ut(int i, int j, int m) { return ((i * (2 * m - i - 1)) >> 1) + j; }
 
 // Round-robin (circle) ordering: in round `rd` every index takes part in exactly one of
 // m/2 disjoint pairs, and over m-1 rounds every pair meets once.
@@ -58,7 +70,7 @@ __device__ __forceinline__ double2 rot_cs(double t) {
 // blocks P1 <= P2.  Diagonal blocks use the updates app - t apq, aqq + t apq and set
 // apq = 0.
 __global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
-    __shared__ double A[LEAF_MAX * LJ_LD];
+    __shared__ double A[LJ_PACKED];  // upper triangle, packed by rows
     __shared__ double2 cs[LEAF_MAX / 2];
     __shared__ double tt[LEAF_MAX / 2];
     __shared__ int2 pq[LEAF_MAX / 2];
@@ -69,12 +81,12 @@ __global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
     const int L = a.leaf;
     const int tid = threadIdx.x, nt = blockDim.x;
     const double *D = a.D + (size_t)leafid * L * L;
-    for (int e = tid; e < L * L; e += nt) A[(e / L) * LJ_LD + e % L] = D[e];
-    __syncthreads();
-    // Frobenius norm for the absolute part of the rotation threshold
+    // Frobenius norm (of the whole block) for the absolute part of the rotation threshold
     double fro = 0.0;
     for (int e = tid; e < L * L; e += nt) {
-        const double v = A[(e / L) * LJ_LD + e % L];
+        const int i = e / L, j = e - i * L;
+        const double v = D[e];
+        if (i <= j) A[ut(i, j, L)] = v;
         fro += v * v;
     }
     for (int o = WAVE / 2; o > 0; o >>= 1) fro += __shfl_xor(fro, o);
@@ -88,6 +100,27 @@ __global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
     const int hh = (half + 1) & ~1;          // half rounded up to even, for the folding
     const int nfold = (hh / 2) * (hh + 1);  // blocks of the folded triangle
     double *log = a.rot + (size_t)leafid * a.max_sweeps * (m - 1) * half;
+    // this thread's blocks, the same in every round
+    int bP1[LJ_BLK], bP2[LJ_BLK];  // bP1 < 0: no block
+#pragma unroll
+    for (int u = 0; u < LJ_BLK; ++u) {
+        bP1[u] = -1;
+        bP2[u] = 0;
+        const int blk = tid + u * nt;
+        if (blk >= nfold) continue;
+        const int r = blk / (hh + 1), e = blk - r * (hh + 1);
+        int P1, P2;
+        if (e < hh - r) {
+            P1 = r;
+            P2 = r + e;
+        } else {
+            P1 = hh - 1 - r;
+            P2 = e - 1;
+        }
+        if (P2 >= half) continue;  // padding of an odd half
+        bP1[u] = P1;
+        bP2[u] = P2;
+    }
     int sweep = 0;
     bool converged = false;
     for (; sweep < a.max_sweeps; ++sweep) {
@@ -97,8 +130,8 @@ __global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
             if (tid < half) {
                 int p, q;
                 rr_pair(tid, rd, m, p, q);
-                const double apq = A[p * LJ_LD + q];
-                const double app = A[p * LJ_LD + p], aqq = A[q * LJ_LD + q];
+                const double apq = A[ut(p, q, m)];
+                const double app = A[ut(p, p, m)], aqq = A[ut(q, q, m)];
                 double t = 0.0;
                 if (fabs(apq) > 2.220446049250313e-16 * sqrt(fabs(app) * fabs(aqq)) + absfloor) {
                     const double theta = (aqq - app) / (2.0 * apq);
@@ -115,32 +148,25 @@ __global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
             // A is symmetric: only blocks P1 <= P2 (the upper triangle) are updated, and
             // entries are read and written at (min(i,j), max(i,j)).  The blocks are dealt out
             // by folding row r of the block triangle with row hh-1-r (hh+1 blocks together).
-            for (int blk = tid; blk < nfold; blk += nt) {
-                const int r = blk / (hh + 1), e = blk - r * (hh + 1);
-                int P1, P2;
-                if (e < hh - r) {
-                    P1 = r;
-                    P2 = r + e;
-                } else {
-                    P1 = hh - 1 - r;
-                    P2 = e - 1;
-                }
-                if (P2 >= half) continue;  // padding of an odd half
+#pragma unroll
+            for (int u = 0; u < LJ_BLK; ++u) {
+                const int P1 = bP1[u], P2 = bP2[u];
+                if (P1 < 0) continue;
                 const double2 r1 = cs[P1], r2 = cs[P2];
                 if (r1.y == 0.0 && r2.y == 0.0) continue;
                 const int2 ab = pq[P1], cd = pq[P2];
                 if (P1 == P2) {
                     const double t = tt[P1];
-                    const double apq = A[ab.x * LJ_LD + ab.y];
-                    A[ab.x * LJ_LD + ab.x] -= t * apq;
-                    A[ab.y * LJ_LD + ab.y] += t * apq;
-                    A[ab.x * LJ_LD + ab.y] = 0.0;
+                    const double apq = A[ut(ab.x, ab.y, m)];
+                    A[ut(ab.x, ab.x, m)] -= t * apq;
+                    A[ut(ab.y, ab.y, m)] += t * apq;
+                    A[ut(ab.x, ab.y, m)] = 0.0;
                     continue;
                 }
-                const int iac = min(ab.x, cd.x) * LJ_LD + max(ab.x, cd.x);
-                const int iad = min(ab.x, cd.y) * LJ_LD + max(ab.x, cd.y);
-                const int ibc = min(ab.y, cd.x) * LJ_LD + max(ab.y, cd.x);
-                const int ibd = min(ab.y, cd.y) * LJ_LD + max(ab.y, cd.y);
+                const int iac = ut(min(ab.x, cd.x), max(ab.x, cd.x), m);
+                const int iad = ut(min(ab.x, cd.y), max(ab.x, cd.y), m);
+                const int ibc = ut(min(ab.y, cd.x), max(ab.y, cd.x), m);
+                const int ibd = ut(min(ab.y, cd.y), max(ab.y, cd.y), m);
                 const double xac = A[iac], xad = A[iad], xbc = A[ibc], xbd = A[ibd];
                 // rows: J1^T X
                 const double yac = r1.x * xac - r1.y * xbc, ybc = r1.y * xac + r1.x * xbc;
@@ -162,10 +188,10 @@ __global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
     }
     // ascending order of the eigenvalues (ties broken by index)
     if (tid < L) {
-        const double v = A[tid * LJ_LD + tid];
+        const double v = A[ut(tid, tid, L)];
         int r = 0;
         for (int j = 0; j < L; ++j) {
-            const double w = A[j * LJ_LD + j];
+            const double w = A[ut(j, j, L)];
             r += (w < v) || (w == v && j < tid);
         }
         a.rank[(size_t)leafid * L + tid] = r;
@@ -177,19 +203,21 @@ __global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
     }
 }
 
-__global__ __launch_bounds__(LJ_THREADS) void k_leaf_vectors(LeafArgs a) {
-    __shared__ double V[LEAF_MAX * LJ_LD];
+// blockIdx.x = 2 leaf + h: rows [h L/2, (h+1) L/2) of the leaf's V
+__global__ __launch_bounds__(LV_THREADS) void k_leaf_vectors(LeafArgs a) {
+    __shared__ double V[(LEAF_MAX / 2) * LJ_LD];
     __shared__ double2 cs[2][LV_RB][LEAF_MAX / 2];
-    __shared__ int2 pq[2][LV_RB][LEAF_MAX / 2];
+    __shared__ int pq[2][LV_RB][LEAF_MAX / 2];  // p | q << 16
 
-    const int leafid = blockIdx.x;
+    const int leafid = blockIdx.x >> 1;
     const int L = a.leaf;
     const int m = L, half = m / 2;
+    const int rows = L / 2, rbase = (blockIdx.x & 1) * rows;
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid % WAVE, row0 = (tid / WAVE) * LV_ROWS;  // replay: pair and rows
-    for (int e = tid; e < L * L; e += nt) {
+    for (int e = tid; e < rows * L; e += nt) {
         const int i = e / L, j = e % L;
-        V[i * LJ_LD + j] = (i == j) ? 1.0 : 0.0;
+        V[i * LJ_LD + j] = (rbase + i == j) ? 1.0 : 0.0;
     }
     const double *log = a.rot + (size_t)leafid * a.max_sweeps * (m - 1) * half;
     const int rounds = a.sweeps[leafid] * (m - 1);
@@ -206,7 +234,7 @@ __global__ __launch_bounds__(LJ_THREADS) void k_leaf_vectors(LeafArgs a) {
                 (g < rounds * half && tnext != 0.0) ? rot_cs(tnext) : make_double2(1.0, 0.0);
             int p, q;
             rr_pair(pr, (b * LV_RB + rr) % (m - 1), m, p, q);
-            pq[b & 1][rr][pr] = make_int2(p, q);
+            pq[b & 1][rr][pr] = p | (q << 16);
         }
         __syncthreads();
         // the next block's tangents are in flight while this block is replayed
@@ -219,40 +247,57 @@ __global__ __launch_bounds__(LJ_THREADS) void k_leaf_vectors(LeafArgs a) {
         // once per lane and applied to 8 rows, and every access to those rows comes from
         // one wavefront, whose LDS accesses complete in program order -- consecutive rounds
         // need no barrier.
-        if (lane < half) {
+        if (lane < half && row0 < rows) {
             const int rounds_here = min(LV_RB, rounds - b * LV_RB);
             for (int rr = 0; rr < rounds_here; ++rr) {
                 const double2 r = cs[b & 1][rr][lane];
                 if (r.y == 0.0) continue;
-                const int2 c = pq[b & 1][rr][lane];
+                const int c = pq[b & 1][rr][lane], cx = c & 0xffff, cy = c >> 16;
+                // all 16 loads of the round issued before the first store (the lanes' columns
+                // are disjoint, so nothing the stores write is read again this round)
+                double vp[LV_ROWS], vq[LV_ROWS];
+#pragma unroll
+                for (int k = 0; k < LV_ROWS; ++k) {
+                    const int i = min(row0 + k, rows - 1);
+                    vp[k] = V[i * LJ_LD + cx];
+                    vq[k] = V[i * LJ_LD + cy];
+                }
 #pragma unroll
                 for (int k = 0; k < LV_ROWS; ++k) {
                     const int i = row0 + k;
-                    if (i >= L) break;
-                    double *vr = V + i * LJ_LD;
-                    const double vp = vr[c.x], vq = vr[c.y];
-                    vr[c.x] = r.x * vp - r.y * vq;
-                    vr[c.y] = r.y * vp + r.x * vq;
+                    if (i >= rows) break;
+                    V[i * LJ_LD + cx] = r.x * vp[k] - r.y * vq[k];
+                    V[i * LJ_LD + cy] = r.y * vp[k] + r.x * vq[k];
                 }
             }
         }
     }
     __syncthreads();
-    // sorted eigenvectors: column j of V is the eigenvector of diagonal entry j, whose
-    // ascending rank the Jacobi kernel stored
+    // these rows of the sorted eigenvectors: column j of V is the eigenvector of diagonal
+    // entry j, whose ascending rank the Jacobi kernel stored
     const int32_t *rank = a.rank + (size_t)leafid * L;
     double *Q = a.Q + (size_t)leafid * L * L;  // eigenvector k contiguous
-    for (int e = tid; e < L * L; e += nt) {
-        const int j = e / L, i = e % L;
-        Q[(size_t)rank[j] * L + i] = V[i * LJ_LD + j];
+    for (int e = tid; e < rows * L; e += nt) {
+        const int j = e / rows, i = e % rows;
+        Q[(size_t)rank[j] * L + rbase + i] = V[i * LJ_LD + j];
     }
-    // W = Q^T U (L x r), column-major with leading dimension ldw over the whole level
-    const double *U = a.U + (size_t)leafid * L * a.r;
-    for (int e = tid; e < L * a.r; e += nt) {
-        const int j = e % L, c = e / L;
+}
+
+// W = Q^T U (L x r) per leaf, column-major with leading dimension ldw over the whole level
+__global__ __launch_bounds__(256) void k_leaf_w(LeafArgs a) {
+    __shared__ double Us[LEAF_MAX * LEAF_RANK_MAX];
+    const int leafid = blockIdx.x;
+    const int L = a.leaf, r = a.r, tid = threadIdx.x;
+    const double *U = a.U + (size_t)leafid * L * r;
+    for (int e = tid; e < L * r; e += blockDim.x) Us[e] = U[e];
+    __syncthreads();
+    const double *Q = a.Q + (size_t)leafid * L * L;
+    for (int e = tid; e < L * r; e += blockDim.x) {
+        const int k = e % L, c = e / L;
+        const double *q = Q + (size_t)k * L;
         double acc = 0.0;
-        for (int i = 0; i < L; ++i) acc = __builtin_fma(V[i * LJ_LD + j], U[i * a.r + c], acc);
-        a.W[(int64_t)c * a.ldw + (int64_t)leafid * L + rank[j]] = acc;
+        for (int i = 0; i < L; ++i) acc = __builtin_fma(q[i], Us[i * r + c], acc);
+        a.W[(int64_t)c * a.ldw + (int64_t)leafid * L + k] = acc;
     }
 }
 
@@ -428,7 +473,8 @@ static inline dim3 grid_for(int64_t n, int b = 256) { return dim3((unsigned)((n 
 
 hipError_t launch_leaf_jacobi(const LeafArgs &a, hipStream_t s) {
     SDC_LAUNCH(KID_LEAF, k_leaf_jacobi, dim3(a.nleaf), dim3(LJ_THREADS), 0, s, a);
-    SDC_LAUNCH(KID_LEAF_VECTORS, k_leaf_vectors, dim3(a.nleaf), dim3(LJ_THREADS), 0, s, a);
+    SDC_LAUNCH(KID_LEAF_VECTORS, k_leaf_vectors, dim3(2 * a.nleaf), dim3(LV_THREADS), 0, s, a);
+    SDC_LAUNCH(KID_LEAF_VECTORS, k_leaf_w, dim3(a.nleaf), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
