@@ -601,12 +601,37 @@ def bench_ex1(args):
     resid = float((np.linalg.norm(TQ - Qs * lam[ks], axis=0) / 5.0).max())
     orth = float(np.abs(Qs.T @ Qs - np.eye(len(ks))).max())
     note(f"ex1 {ms:.2f} ms/step")
+    # the paper's range of sizes (8192 .. 262144): time of divide + conquer and accuracy
+    sweep = []
+    for nn in (8192, 16384, 32768, 65536, 131072, 262144):
+        tr = gen.tridiag_hss(nn, leaf)
+        pl = native.HSSPlan(ctx, tr.leaf, tr.depth, tr.r)
+        gg = {k: torch.as_tensor(v, dtype=torch.float64, device=dev)
+              for k, v in native.pack_hss(tr).items()}
+        dd = native.hss_divide(ctx, pl, gg)
+        oo = native.hss_conquer(ctx, pl, dd, opts=o)  # warm-up: reduced batches, FMM plans
+        torch.cuda.synchronize()
+        reps = 3
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            native.hss_divide(ctx, pl, gg, out=dd)
+            native.hss_conquer(ctx, pl, dd, opts=o, out=oo)
+        e1.record()
+        torch.cuda.synchronize()
+        ex = np.sort(3.0 - 2.0 * np.cos(np.arange(1, nn + 1) * np.pi / (nn + 1)))
+        sweep.append({"n": nn, "ms": e0.elapsed_time(e1) / reps,
+                      "status": int(oo["status"].cpu().numpy()[0]),
+                      "lam_err_rel_normA": float(np.abs(oo["lam"].cpu().numpy() - ex).max() / 5.0)})
+        del pl, gg, dd, oo
+    note("ex1 size sweep done")
     return {"config": {"workload": "tridiagonal (3 on the diagonal, -1 beside it) as an HSS form "
                                    "of rank 2: n=65536, leaf 128, depth 9; balanced dividing "
                                    "stage + conquering pass with deflation, tau = 1e-10",
                        "n": n, "leaf": leaf,
                        "depth": tree.depth, "r": 2},
             "ms_per_step": ms, "conquer_phase_ms": phases, "divide_ms": div[0] / args.steps,
+            "size_sweep": sweep,
             "divide_launches": div[1] // max(1, args.steps),
             "accuracy": {"status": int(out["status"].cpu().numpy()[0]),
                          "lam_err_rel_normA": float(np.abs(lam - exact).max() / 5.0),
