@@ -107,3 +107,29 @@ def test_dense_generators_unchanged():
     _, lam1, st1 = run(tree, 1e-15)
     assert st0 == 0 and st1 == 0
     assert np.abs(lam1 - lam0).max() <= 1e-13 * np.abs(lam0).max()
+
+
+def test_vanished_couplings_and_fully_deflated_nodes():
+    """Couplings that vanish (B_p = 0: the dividing stage takes beta_p = 1 and the update
+    column of the left child is zero, so rule 1 takes all of its poles) and leaf bases that
+    are zero (every update column vanishes, every node deflates completely and its reduced
+    problem is a one-pole stand-in whose results are never used): the spectrum is still
+    LAPACK's of the assembled matrix, and the structured eigenmatrix stays orthogonal."""
+    import copy
+    from oracle import hss as ohss
+    from paper_2108_04209_amd import native
+    from tests import gpu_pipeline as gp
+    base = gen.hss_original(n=1024, leaf=32, r=4, cfg=45)
+    t1 = copy.deepcopy(base)
+    for l in (0, 2):
+        t1.B[l][:] = 0.0
+    t2 = copy.deepcopy(base)
+    t2.leaf_U[:] = 0.0
+    for t in (t1, t2):
+        plan, lam, st = run(t, 1e-13)
+        assert st == 0
+        ev = np.linalg.eigvalsh(ohss.dense_original(t))
+        assert np.abs(lam - ev).max() <= 1e-12 * np.abs(ev).max()
+        n = t.n
+        Q = native.hss_apply(gp.context(), plan, gp.to_dev(np.eye(n)), trans=0).cpu().numpy().T
+        assert np.abs(Q.T @ Q - np.eye(n)).max() <= 1e-12

@@ -81,3 +81,17 @@ def test_trace_and_frobenius_of_the_assembly():
     # the divided form has the same invariants of its spectrum
     ev = np.linalg.eigvalsh(oh.dense_nodes(oh.divide(t))[(0, 0)])
     assert np.sum(ev ** 2) == pytest.approx(fro, rel=1e-12)
+
+
+def test_vanished_coupling_takes_unit_beta():
+    """A coupling that vanishes has no norm to balance by: beta = 1, and the division is
+    still exact (the left child's update column is zero)."""
+    import copy
+    from oracle import hss as oh
+    t = copy.deepcopy(gen.hss_original(n=256, leaf=16, r=4, cfg=13))
+    t.B[0][:] = 0.0
+    d = oh.divide(t)
+    assert d.beta[0][0] == 1.0 and np.all(d.B[0][0] == 0.0)
+    A = oh.dense_original(t)
+    Ad = oh.dense_nodes(d)[(0, 0)]
+    assert np.abs(A - Ad).max() <= 1e-13 * np.abs(A).max()
