@@ -73,7 +73,7 @@ __global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
     __shared__ double A[LJ_PACKED];  // upper triangle, packed by rows
     __shared__ double2 cs[LEAF_MAX / 2];
     __shared__ double tt[LEAF_MAX / 2];
-    __shared__ int2 pq[LEAF_MAX / 2];
+    __shared__ int4 pq[LEAF_MAX / 2];  // p, q and where rows p, q start in the packed triangle
     __shared__ double red[LJ_THREADS / WAVE];
     __shared__ int nrot;
 
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
                 }
                 cs[tid] = t != 0.0 ? rot_cs(t) : make_double2(1.0, 0.0);
                 tt[tid] = t;
-                pq[tid] = make_int2(p, q);
+                pq[tid] = make_int4(p, q, ut(p, 0, m), ut(q, 0, m));
                 log[((size_t)sweep * (m - 1) + rd) * half + tid] = t;
             }
             __syncthreads();
@@ -154,19 +154,20 @@ __global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
                 if (P1 < 0) continue;
                 const double2 r1 = cs[P1], r2 = cs[P2];
                 if (r1.y == 0.0 && r2.y == 0.0) continue;
-                const int2 ab = pq[P1], cd = pq[P2];
+                const int4 ab = pq[P1], cd = pq[P2];  // (index, index, row start, row start)
                 if (P1 == P2) {
                     const double t = tt[P1];
-                    const double apq = A[ut(ab.x, ab.y, m)];
-                    A[ut(ab.x, ab.x, m)] -= t * apq;
-                    A[ut(ab.y, ab.y, m)] += t * apq;
-                    A[ut(ab.x, ab.y, m)] = 0.0;
+                    const double apq = A[ab.z + ab.y];
+                    A[ab.z + ab.x] -= t * apq;
+                    A[ab.w + ab.y] += t * apq;
+                    A[ab.z + ab.y] = 0.0;
                     continue;
                 }
-                const int iac = ut(min(ab.x, cd.x), max(ab.x, cd.x), m);
-                const int iad = ut(min(ab.x, cd.y), max(ab.x, cd.y), m);
-                const int ibc = ut(min(ab.y, cd.x), max(ab.y, cd.x), m);
-                const int ibd = ut(min(ab.y, cd.y), max(ab.y, cd.y), m);
+                // entry (i, j) of the upper triangle sits at rowstart(min) + max
+                const int iac = ab.x < cd.x ? ab.z + cd.x : cd.z + ab.x;
+                const int iad = ab.x < cd.y ? ab.z + cd.y : cd.w + ab.x;
+                const int ibc = ab.y < cd.x ? ab.w + cd.x : cd.z + ab.y;
+                const int ibd = ab.y < cd.y ? ab.w + cd.y : cd.w + ab.y;
                 const double xac = A[iac], xad = A[iad], xbc = A[ibc], xbd = A[ibd];
                 // rows: J1^T X
                 const double yac = r1.x * xac - r1.y * xbc, ybc = r1.y * xac + r1.x * xbc;
