@@ -391,7 +391,7 @@ namespace sdc {
 int loewner_run(superdc_ctx *ctx, const superdc_batch *b, const double *d, const double *z,
                 const double *rho, const double *eta, const int32_t *origin,
                 const int32_t *status, double *zhat, double *bnorm, const superdc_opts *opts,
-                void *stream, bool reuse_lists) {
+                void *stream, bool reuse_lists, bool fmm_b) {
     if (!ctx || !b || b->ctx != ctx || !d || !z || !rho || !eta || !origin || !status || !zhat ||
         !bnorm)
         return SUPERDC_EINVAL;
@@ -475,7 +475,7 @@ int loewner_run(superdc_ctx *ctx, const superdc_batch *b, const double *d, const
         }
         SDC_HIP(launch_bnorm(a, S, ctx->queues + Q_BNORM,
                              persistent_grid(ctx, a.ntiles, std::max(1, 32 / S)), s));
-        if (fp) SDC_HIP(fmmv_run(ctx, b, fp, f, pk, v, false, true, s));
+        if (fp && fmm_b) SDC_HIP(fmmv_run(ctx, b, fp, f, pk, v, false, true, s));
     } else {
         for (int p = 0; p < b->nprob; ++p) {
             const int64_t np = b->off_h[p + 1] - b->off_h[p];
@@ -493,7 +493,7 @@ int loewner_run(superdc_ctx *ctx, const superdc_batch *b, const double *d, const
             SDC_HIP(launch_loewner(a, S, nullptr, 0, s, false));
             SDC_HIP(launch_bnorm(a, S, nullptr, 0, s));
         }
-        if (fp) SDC_HIP(fmmv_run(ctx, b, fp, f, pk, v, false, false, s));
+        if (fp && fmm_b) SDC_HIP(fmmv_run(ctx, b, fp, f, pk, v, false, false, s));
     }
     return SUPERDC_OK;
 }
@@ -501,10 +501,12 @@ int loewner_run(superdc_ctx *ctx, const superdc_batch *b, const double *d, const
 int apply_run(superdc_ctx *ctx, const superdc_batch *b, const double *d, const double *zhat,
               const double *bnorm, const double *eta, const int32_t *origin,
               const int32_t *status, int trans, int32_t m, const double *X, int64_t ldx,
-              double *Y, int64_t ldy, const superdc_opts *opts, void *stream, bool reuse_lists) {
+              double *Y, int64_t ldy, const superdc_opts *opts, void *stream, bool reuse_lists,
+              bool fuse_b) {
     if (!ctx || !b || b->ctx != ctx || !d || !zhat || !bnorm || !eta || !origin || !status ||
         !X || !Y)
         return SUPERDC_EINVAL;
+    if (fuse_b && (trans != 1 || m + 1 > FMMV_MAX_M)) return SUPERDC_EINVAL;
     if ((trans != 0 && trans != 1) || m < 1 || ldx < b->total || ldy < b->total)
         return SUPERDC_EINVAL;
     SDC_OPTS(o, opts);
@@ -551,7 +553,7 @@ int apply_run(superdc_ctx *ctx, const superdc_batch *b, const double *d, const d
         }
     }
     if (fp) {
-        const int mc = std::min(m, FMMV_MAX_M);
+        const int mc = std::min(m + (fuse_b ? 1 : 0), FMMV_MAX_M);
         double2 *pairs = (double2 *)ws_get(ctx, WS_VPAIR, sizeof(double2) * b->total);
         double *src = (double *)ws_get(ctx, WS_VSRC, sizeof(double) * b->total * mc);
         if (!pairs || !src) return SUPERDC_ENOMEM;
@@ -575,10 +577,12 @@ int apply_run(superdc_ctx *ctx, const superdc_batch *b, const double *d, const d
         v.eta = eta;
         v.post = bnorm;
         v.ldy = ldy;
+        v.fuse_b = fuse_b ? 1 : 0;
+        v.bout = const_cast<double *>(bnorm);  // written only with fuse_b
         const FmmArgs f = fmm_vec_args(fp, b, pairs, status);
         for (int c0 = 0; c0 < m; c0 += FMMV_MAX_M) {
             pk.c0 = c0;
-            v.m = std::min(FMMV_MAX_M, m - c0);
+            v.m = std::min(FMMV_MAX_M, m - c0) + v.fuse_b;  // one chunk when fused
             v.Y = Y + (int64_t)c0 * ldy;
             SDC_HIP(fmmv_run(ctx, b, fp, f, pk, v, c0 == 0 && !reuse_lists, o.persistent != 0, s));
         }

@@ -241,15 +241,18 @@ const TileList *tile_list(superdc_batch *b, int chunk);
 namespace sdc {
 // Loewner/b and the Cauchy apply behind superdc_loewner / superdc_cauchy_apply.
 // reuse_lists: the batch's FMM interaction lists were built by a solve on the same poles
-// d (internal callers that know it).
+// d (internal callers that know it).  fmm_b = false leaves b of the FMM problems to the
+// next apply_run with fuse_b = true (Qhat^T X, 1 <= m < 16 columns), whose evaluation
+// forms b from the same equivalent sources and writes it to bnorm.
 int loewner_run(superdc_ctx *ctx, const superdc_batch *b, const double *d, const double *z,
                 const double *rho, const double *eta, const int32_t *origin,
                 const int32_t *status, double *zhat, double *bnorm, const superdc_opts *opts,
-                void *stream, bool reuse_lists);
+                void *stream, bool reuse_lists, bool fmm_b = true);
 int apply_run(superdc_ctx *ctx, const superdc_batch *b, const double *d, const double *zhat,
               const double *bnorm, const double *eta, const int32_t *origin,
               const int32_t *status, int trans, int32_t m, const double *X, int64_t ldx,
-              double *Y, int64_t ldy, const superdc_opts *opts, void *stream, bool reuse_lists);
+              double *Y, int64_t ldy, const superdc_opts *opts, void *stream, bool reuse_lists,
+              bool fuse_b = false);
 
 // grow a workspace slot to at least `bytes`; returns nullptr on allocation failure
 void *ws_get(superdc_ctx *ctx, int slot, size_t bytes);

@@ -102,6 +102,9 @@ struct FmmVec {
     double *Y;                // kern 1: output columns, ld ldy
     int64_t ldy;
     double *bout;             // kern 2: b_j = (sum)^(-1/2)
+    int fuse_b;               // kern 1 on the MFMA: the last of the m weight columns is zhat^2;
+                              // the evaluation forms b from it with the kernel 1/t^2, writes
+                              // it to bout and scales the other m - 1 columns by it
 };
 constexpr int FMMV_MAX_M = 16;
 

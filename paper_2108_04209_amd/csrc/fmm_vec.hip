@@ -41,7 +41,9 @@ __global__ __launch_bounds__(64) void k_fmmv_pack(FmmvPackArgs a, FmmVec v) {
     a.pairs[base + i] = make_double2(di, zh);
     double *src = v.src + (base + i) * v.m;
     if (v.kern == 1) {
-        for (int c = 0; c < v.m; ++c) src[c] = zh * a.X[base + i + (int64_t)(a.c0 + c) * a.ldx];
+        const int mx = v.m - v.fuse_b;
+        for (int c = 0; c < mx; ++c) src[c] = zh * a.X[base + i + (int64_t)(a.c0 + c) * a.ldx];
+        if (v.fuse_b) src[mx] = zh * zh;
     } else {
         src[0] = zh * zh;
     }
@@ -367,12 +369,15 @@ __device__ void fmmv_item_mfma(const SolveArgs &it, const FmmArgs &f, const FmmV
     const int wv = threadIdx.x / WAVE;
     const int o0 = t.row0;
     const int m = v.m;
+    const int mo = m - v.fuse_b;  // output columns
     if (f.status[p] & ~SUPERDC_ST_NOCONV) {
         const double nan = __builtin_nan("");
-        for (int e = threadIdx.x; e < FV_K * m; e += blockDim.x) {
+        for (int e = threadIdx.x; e < FV_K * mo; e += blockDim.x) {
             const int r = o0 + (e % FV_K), c = e / FV_K;
             if (r < n) v.Y[base + r + (int64_t)c * v.ldy] = nan;
         }
+        if (v.fuse_b && threadIdx.x < FV_K && o0 + (int)threadIdx.x < n)
+            v.bout[base + o0 + threadIdx.x] = nan;
         return;
     }
     const int qf = f.fmm_of[p];
@@ -410,6 +415,8 @@ __device__ void fmmv_item_mfma(const SolveArgs &it, const FmmArgs &f, const FmmV
     const double ra = v.d[base + clamp_idx(v.origin[base + oc], n)];
     const double rb = v.eta[base + oc];
     v4d_f acc = v4d_f{0.0, 0.0, 0.0, 0.0};
+    v4d_f accb = v4d_f{0.0, 0.0, 0.0, 0.0};  // fuse_b: the same sources through 1/t^2
+    const bool fb = v.fuse_b != 0;
     FvStage st;
     int4 cur = chunk(0);
     fv_fetch(v, base, sh.fbox, cur, st);
@@ -434,6 +441,7 @@ __device__ void fmmv_item_mfma(const SolveArgs &it, const FmmArgs &f, const FmmV
             const double av = (ovalid && sl < nvalid) ? rcp_nr(tt) : 0.0;
             const double bv = sh.Xs[(lane & 15) * FV_LD + sl];
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+            if (fb) accb = __builtin_amdgcn_mfma_f64_16x16x4f64(av * av, bv, accb, 0, 0, 0);
         }
     }
     // v_mfma_f64_16x16x4f64 returns D[4 r + lane/16][lane % 16] in accumulator r
@@ -441,7 +449,14 @@ __device__ void fmmv_item_mfma(const SolveArgs &it, const FmmArgs &f, const FmmV
     for (int r = 0; r < 4; ++r) {
         const int row = o0 + wv * 16 + 4 * r + (lane >> 4);
         const int col = lane & 15;
-        if (row < n && col < m) v.Y[base + row + (int64_t)col * v.ldy] = v.post[base + row] * acc[r];
+        double post;
+        if (fb) {  // b of this row sits in column m - 1 of the second product
+            post = 1.0 / sqrt(__shfl(accb[r], (lane & ~15) | (m - 1)));
+            if (row < n && col == 0) v.bout[base + row] = post;
+        } else {
+            post = row < n ? v.post[base + row] : 0.0;
+        }
+        if (row < n && col < mo) v.Y[base + row + (int64_t)col * v.ldy] = post * acc[r];
     }
 }
 
@@ -593,7 +608,7 @@ hipError_t launch_fmmv_sources(const FmmArgs &f, const FmmVec &v, hipStream_t s)
 hipError_t launch_fmmv_eval(const SolveArgs &it, const FmmArgs &f, const FmmVec &v, int split,
                             Queue *q, int num_cu, hipStream_t s) {
     if (it.ntiles <= 0) return hipSuccess;
-    if (v.kern == 1 && v.m >= 4) {  // a dense enough block of columns for the MFMA
+    if (v.kern == 1 && (v.m >= 4 || v.fuse_b)) {  // a dense enough block of columns for the MFMA
         const dim3 g(q ? min(it.ntiles, num_cu * 4) : it.ntiles);
         SDC_LAUNCH(KID_FMMV_EVAL_MFMA, k_fmmv_eval_mfma, g, dim3(256), 0, s, it, f, v, q);
         return hipGetLastError();

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "common.h"
+#include "fmm.h"
 #include "hss.h"
 
 using namespace sdc;
@@ -187,8 +188,11 @@ int defl_step(superdc_ctx *ctx, superdc_hss *h, int l, int t, int cur, int ncol,
                                h->iters + k, h->st(l, t), &o, stream);
     if (rc) return rc;
     if ((e = mark(h, 2, s)) != hipSuccess) return fail(e);
+    // b of the FMM problems comes with the apply of the remaining columns when there are any
+    const int m = ncol - t - 1;
+    const bool fuse = m >= 1 && m + 1 <= FMMV_MAX_M;
     rc = loewner_run(ctx, rb, dr, h->xzr, h->ones, h->eta + k, h->org + k, h->st(l, t),
-                     h->zhat + k, h->bn + k, &o, stream, true);
+                     h->zhat + k, h->bn + k, &o, stream, true, !fuse);
     if (rc) return rc;
     if ((e = mark(h, 3, s)) != hipSuccess) return fail(e);
     // the step's eigenvalues per node: reduced roots first, deflated values after, sorted
@@ -198,7 +202,6 @@ int defl_step(superdc_ctx *ctx, superdc_hss *h, int l, int t, int cur, int ncol,
                               nullptr, s)) != hipSuccess ||
         (e = launch_seg_sort(h->xE, nl, n, h->lam + k, h->dS + k, h->xk, h->xv, s)) != hipSuccess)
         return fail(e);
-    const int m = ncol - t - 1;
     if (m > 0) {
         const double *X = h->M[cur] + (size_t)(t + 1) * n;
         if ((e = launch_deflate_expand(b->off_d, nprob, n, m, h->dperm + k, h->drr + k, h->drl + k,
@@ -208,7 +211,7 @@ int defl_step(superdc_ctx *ctx, superdc_hss *h, int l, int t, int cur, int ncol,
                                   &zero, s)) != hipSuccess)
             return fail(e);
         rc = apply_run(ctx, rb, dr, h->zhat + k, h->bn + k, h->eta + k, h->org + k, h->st(l, t), 1,
-                       m, h->xR0, rt, h->xR1, rt, &o, stream, true);
+                       m, h->xR0, rt, h->xR1, rt, &o, stream, true, fuse);
         if (rc) return rc;
         if ((e = launch_copy_rows(rb->off_d, b->off_d, nprob, n, m, kept, h->xR1, rt, h->xY, n,
                                   nullptr, s)) != hipSuccess ||
@@ -414,16 +417,18 @@ int superdc_hss_conquer(superdc_ctx *ctx, superdc_hss *h, const double *leaf_D,
                                            h->iters + h->idx(l, t), st_t, &o, stream);
             if (rc) return rc;
             if ((e = mark(h, 2, s)) != hipSuccess) return fail(e);
-            // the solve just built the FMM lists of these poles: Loewner/b and the apply reuse them
+            // the solve just built the FMM lists of these poles: Loewner/b and the apply reuse
+            // them; b of the FMM problems comes with the apply when columns remain
+            const int m = ncol - t - 1;
+            const bool fuse = m >= 1 && m + 1 <= FMMV_MAX_M;
             rc = loewner_run(ctx, b, poles, zc, h->ones, eta_t, org_t, st_t,
-                             h->zhat + h->idx(l, t), h->bn + h->idx(l, t), &o, stream, true);
+                             h->zhat + h->idx(l, t), h->bn + h->idx(l, t), &o, stream, true, !fuse);
             if (rc) return rc;
             if ((e = mark(h, 3, s)) != hipSuccess) return fail(e);
-            const int m = ncol - t - 1;
             if (m > 0) {
                 rc = apply_run(ctx, b, poles, h->zhat + h->idx(l, t), h->bn + h->idx(l, t), eta_t,
                                org_t, st_t, 1, m, h->M[cur] + (size_t)(t + 1) * n, n,
-                               h->M[1 - cur] + (size_t)(t + 1) * n, n, &o, stream, true);
+                               h->M[1 - cur] + (size_t)(t + 1) * n, n, &o, stream, true, fuse);
                 if (rc) return rc;
                 if ((e = mark(h, 4, s)) != hipSuccess) return fail(e);
             }
