@@ -444,6 +444,7 @@ int loewner_run(superdc_ctx *ctx, const superdc_batch *b, const double *d, const
         v.origin = origin;
         v.eta = eta;
         v.bout = bnorm;
+        v.zh = zhat;
         f = fmm_vec_args(fp, b, pairs, status);
         lf.pd = pairs;
         lf.geo = fp->lgeo;
@@ -473,8 +474,9 @@ int loewner_run(superdc_ctx *ctx, const superdc_batch *b, const double *d, const
                                        persistent_grid(ctx, af.ntiles, std::max(1, 32 / fp->split)),
                                        s));
         }
-        SDC_HIP(launch_bnorm(a, S, ctx->queues + Q_BNORM,
-                             persistent_grid(ctx, a.ntiles, std::max(1, 32 / S)), s));
+        if (fmm_b)
+            SDC_HIP(launch_bnorm(a, S, ctx->queues + Q_BNORM,
+                                 persistent_grid(ctx, a.ntiles, std::max(1, 32 / S)), s));
         if (fp && fmm_b) SDC_HIP(fmmv_run(ctx, b, fp, f, pk, v, false, true, s));
     } else {
         for (int p = 0; p < b->nprob; ++p) {
@@ -491,7 +493,7 @@ int loewner_run(superdc_ctx *ctx, const superdc_batch *b, const double *d, const
             a.tiles = L->nat + L->begin[p];
             a.ntiles = L->begin[p + 1] - L->begin[p];
             SDC_HIP(launch_loewner(a, S, nullptr, 0, s, false));
-            SDC_HIP(launch_bnorm(a, S, nullptr, 0, s));
+            if (fmm_b) SDC_HIP(launch_bnorm(a, S, nullptr, 0, s));
         }
         if (fp && fmm_b) SDC_HIP(fmmv_run(ctx, b, fp, f, pk, v, false, false, s));
     }
@@ -529,7 +531,10 @@ int apply_run(superdc_ctx *ctx, const superdc_batch *b, const double *d, const d
     a.ldx = ldx;
     a.Y = Y;
     a.ldy = ldy;
-    const int use_mfma = o.apply_kernel == 2 ? 1 : (o.apply_kernel == 1 ? 0 : (m >= 4));
+    a.fuse_b = fuse_b ? 1 : 0;
+    a.bout = const_cast<double *>(bnorm);  // written only with fuse_b
+    const int use_mfma =
+        fuse_b ? 1 : (o.apply_kernel == 2 ? 1 : (o.apply_kernel == 1 ? 0 : (m >= 4)));
     superdc_batch *bm = const_cast<superdc_batch *>(b);
     const TileList *L = tile_list(bm, TILE);
     if (!L) return SUPERDC_ENOMEM;
@@ -578,6 +583,7 @@ int apply_run(superdc_ctx *ctx, const superdc_batch *b, const double *d, const d
         v.post = bnorm;
         v.ldy = ldy;
         v.fuse_b = fuse_b ? 1 : 0;
+        v.zh = zhat;
         v.bout = const_cast<double *>(bnorm);  // written only with fuse_b
         const FmmArgs f = fmm_vec_args(fp, b, pairs, status);
         for (int c0 = 0; c0 < m; c0 += FMMV_MAX_M) {

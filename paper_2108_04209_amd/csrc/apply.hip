@@ -31,8 +31,8 @@ __device__ __forceinline__ void stage_entry(const ApplyArgs &a, int64_t base, in
         if (TRANS == 0) {  // s runs over roots: (d_{K_s}, eta_s), scale b_s
             sd = make_double2(a.d[base + clamp_idx(a.origin[base + s], n)], a.eta[base + s]);
             scale = a.bnorm[base + s];
-        } else {           // s runs over poles: (d_s, 0), scale zhat_s
-            sd = make_double2(a.d[base + s], 0.0);
+        } else {           // s runs over poles: (d_s, zhat_s), scale zhat_s
+            sd = make_double2(a.d[base + s], a.zhat[base + s]);
             scale = a.zhat[base + s];
         }
     } else {
@@ -97,6 +97,8 @@ __device__ void apply_tile_mfma(const ApplyArgs &a, Tile t, double *Xs, double2 
             const int r = o0 + (e % AP_ROWS), c = e / AP_ROWS;
             if (r < n) a.Y[base + r + (int64_t)c * a.ldy] = nan;
         }
+        if (TRANS == 1 && a.fuse_b && threadIdx.x < AP_ROWS && o0 + (int)threadIdx.x < n)
+            a.bout[base + o0 + threadIdx.x] = nan;
         return;
     }
     // row data for the entries of C this lane generates: row o = o0 + 16 wv + lane%16
@@ -117,6 +119,12 @@ __device__ void apply_tile_mfma(const ApplyArgs &a, Tile t, double *Xs, double2 
         v4d acc[NCT];
 #pragma unroll
         for (int ct = 0; ct < NCT; ++ct) acc[ct] = v4d{0.0, 0.0, 0.0, 0.0};
+        // fuse_b (one pass of at most 15 columns): b = sum (zhat_s / t)^2, each term squared
+        // after the division as the b kernel does (zhat^2 and 1/t^2 apart can leave the
+        // exponent range); the second product's column ncols sums them
+        const bool fb = TRANS == 1 && NCT == 1 && a.fuse_b;
+        const double bone = (lane & 15) == ncols ? 1.0 : 0.0;
+        v4d accb = v4d{0.0, 0.0, 0.0, 0.0};
         ApplyStage<NCT> st;
         apply_fetch<TRANS, NCT>(a, base, n, 0, c0, ncols, st);
         for (int s0 = 0; s0 < n; s0 += AP_K) {
@@ -136,6 +144,10 @@ __device__ void apply_tile_mfma(const ApplyArgs &a, Tile t, double *Xs, double2 
                     if (ct < nct) {
                         const double bv = Xs[(ct * 16 + (lane & 15)) * AP_LD + sl];
                         acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[ct], 0, 0, 0);
+                        if (fb) {
+                            const double qv = av * sd.y;
+                            accb = __builtin_amdgcn_mfma_f64_16x16x4f64(qv * qv, bone, accb, 0, 0, 0);
+                        }
                     }
                 }
             }
@@ -144,8 +156,13 @@ __device__ void apply_tile_mfma(const ApplyArgs &a, Tile t, double *Xs, double2 
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int row = o0 + wv * 16 + 4 * v + (lane >> 4);
+            double postb = 0.0;
+            if (fb) {  // b of this row sits in column ncols of the second product
+                postb = 1.0 / sqrt(__shfl(accb[v], (lane & ~15) | ncols));
+                if (row < n && (lane & 15) == 0) a.bout[base + row] = postb;
+            }
             if (row < n) {
-                const double post = TRANS ? a.bnorm[base + row] : a.zhat[base + row];
+                const double post = fb ? postb : (TRANS ? a.bnorm[base + row] : a.zhat[base + row]);
 #pragma unroll
                 for (int ct = 0; ct < NCT; ++ct) {
                     const int col = ct * 16 + (lane & 15);

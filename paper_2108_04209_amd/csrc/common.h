@@ -241,9 +241,10 @@ const TileList *tile_list(superdc_batch *b, int chunk);
 namespace sdc {
 // Loewner/b and the Cauchy apply behind superdc_loewner / superdc_cauchy_apply.
 // reuse_lists: the batch's FMM interaction lists were built by a solve on the same poles
-// d (internal callers that know it).  fmm_b = false leaves b of the FMM problems to the
-// next apply_run with fuse_b = true (Qhat^T X, 1 <= m < 16 columns), whose evaluation
-// forms b from the same equivalent sources and writes it to bnorm.
+// d (internal callers that know it).  fmm_b = false leaves b to the next apply_run with
+// fuse_b = true (Qhat^T X, 1 <= m < 16 columns, on the MFMA kernels), whose products form
+// b beside the columns (from the same equivalent sources for the FMM problems) and write
+// it to bnorm.
 int loewner_run(superdc_ctx *ctx, const superdc_batch *b, const double *d, const double *z,
                 const double *rho, const double *eta, const int32_t *origin,
                 const int32_t *status, double *zhat, double *bnorm, const superdc_opts *opts,
@@ -306,6 +307,8 @@ struct ApplyArgs {
     int64_t ldx;
     double *Y;
     int64_t ldy;
+    int fuse_b;    // trans 1, MFMA, m < 16: form b with the kernel 1/t^2 on the weights
+    double *bout;  // zhat^2 beside the m columns, write it here and scale by it
 };
 hipError_t launch_apply(const ApplyArgs &a, int use_mfma, Queue *q, int grid, hipStream_t s);
 

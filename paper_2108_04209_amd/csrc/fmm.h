@@ -105,6 +105,7 @@ struct FmmVec {
     int fuse_b;               // kern 1 on the MFMA: the last of the m weight columns is zhat^2;
                               // the evaluation forms b from it with the kernel 1/t^2, writes
                               // it to bout and scales the other m - 1 columns by it
+    const double *zh;         // fuse_b: zhat, for b's near terms (zhat / t)^2
 };
 constexpr int FMMV_MAX_M = 16;
 

@@ -215,6 +215,7 @@ __device__ void fmmv_item(const SolveArgs &it, const FmmArgs &f, const FmmVec &v
     const int nr = wave_uniform(f.cnt[3 * (int64_t)L + 2]);
     const const_double_ptr dd = as_const(v.d + base);
     const const_double_ptr src = as_const(v.src + base * m);
+    const const_double_ptr zhv = as_const((KERN == 2 ? v.zh : v.d) + base);
     double acc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] = 0.0;
@@ -226,8 +227,9 @@ __device__ void fmmv_item(const SolveArgs &it, const FmmArgs &f, const FmmVec &v
 #pragma unroll
                 for (int c = 0; c < NC; ++c)
                     if (c < m) acc[c] = __builtin_fma(r, src[(int64_t)i * m + c], acc[c]);
-            } else {
-                acc[0] = __builtin_fma(r * r, src[i], acc[0]);
+            } else {  // (zhat / t)^2, squared after the division (r^2 zhat^2 can leave range)
+                const double qv = r * zhv[i];
+                acc[0] = __builtin_fma(qv, qv, acc[0]);
             }
         }
     };
@@ -321,7 +323,7 @@ constexpr int FV_LD = FV_K + 1;
 constexpr int FV_MAXCH = FMM_NEAR_MAX * (1024 / FV_K) + (2 * FMM_FAR_MAX + 3) / 4;
 
 struct FvStage {
-    double sd;     // source position (threads < 64)
+    double2 sd;    // source position and, for near poles with fuse_b, zhat (threads < 64)
     double w[4];   // weights: element e = tid + 256 i -> source e % 64, column e / 64
 };
 
@@ -330,7 +332,10 @@ __device__ __forceinline__ void fv_fetch(const FmmVec &v, int64_t base, const in
     const int tid = threadIdx.x;
     const int m = v.m;
     if (ch.x == 0) {
-        if (tid < FV_K) st.sd = tid < ch.z ? v.d[base + ch.y + tid] : 0.0;
+        if (tid < FV_K)
+            st.sd = tid < ch.z ? make_double2(v.d[base + ch.y + tid],
+                                              v.fuse_b ? v.zh[base + ch.y + tid] : 0.0)
+                               : make_double2(0.0, 0.0);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int e = tid + 256 * i, sl = e % FV_K, c = e / FV_K;
@@ -339,7 +344,8 @@ __device__ __forceinline__ void fv_fetch(const FmmVec &v, int64_t base, const in
     } else {
         if (tid < FV_K) {
             const int bx = tid / FMM_P, qn = tid % FMM_P;
-            st.sd = bx < ch.z ? v.vnode[(int64_t)fbox[ch.y + bx] * FMM_P + qn] : 0.0;
+            st.sd = make_double2(bx < ch.z ? v.vnode[(int64_t)fbox[ch.y + bx] * FMM_P + qn] : 0.0,
+                                 0.0);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -354,7 +360,7 @@ __device__ __forceinline__ void fv_fetch(const FmmVec &v, int64_t base, const in
 
 struct FvShared {
     double Xs[16 * FV_LD];
-    double Sd[FV_K];
+    double2 Sd[FV_K];
     int4 ctab[FV_MAXCH];
     int fbox[2 * FMM_FAR_MAX];
     int nch;
@@ -417,6 +423,7 @@ __device__ void fmmv_item_mfma(const SolveArgs &it, const FmmArgs &f, const FmmV
     v4d_f acc = v4d_f{0.0, 0.0, 0.0, 0.0};
     v4d_f accb = v4d_f{0.0, 0.0, 0.0, 0.0};  // fuse_b: the same sources through 1/t^2
     const bool fb = v.fuse_b != 0;
+    const double bone = (lane & 15) == m - 1 ? 1.0 : 0.0;
     FvStage st;
     int4 cur = chunk(0);
     fv_fetch(v, base, sh.fbox, cur, st);
@@ -430,6 +437,7 @@ __device__ void fmmv_item_mfma(const SolveArgs &it, const FmmArgs &f, const FmmV
         }
         __syncthreads();
         const int nvalid = wave_uniform(cur.x == 0 ? cur.z : cur.z * FMM_P);
+        const bool cur_near = cur.x == 0;
         if (ci + 1 < nch) {
             cur = chunk(ci + 1);
             fv_fetch(v, base, sh.fbox, cur, st);  // in flight during the multiply below
@@ -437,11 +445,19 @@ __device__ void fmmv_item_mfma(const SolveArgs &it, const FmmArgs &f, const FmmV
 #pragma unroll 4
         for (int kk = 0; kk < FV_K; kk += 4) {
             const int sl = kk + (lane >> 4);
-            const double tt = (sh.Sd[sl] - ra) - rb;
+            const double2 sdv = sh.Sd[sl];
+            const double tt = (sdv.x - ra) - rb;
             const double av = (ovalid && sl < nvalid) ? rcp_nr(tt) : 0.0;
             const double bv = sh.Xs[(lane & 15) * FV_LD + sl];
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-            if (fb) accb = __builtin_amdgcn_mfma_f64_16x16x4f64(av * av, bv, accb, 0, 0, 0);
+            if (fb) {
+                if (cur_near) {  // (zhat / t)^2: squared after the division
+                    const double qv = av * sdv.y;
+                    accb = __builtin_amdgcn_mfma_f64_16x16x4f64(qv * qv, bone, accb, 0, 0, 0);
+                } else {         // far sources: weights of zhat^2, t bounded away from 0
+                    accb = __builtin_amdgcn_mfma_f64_16x16x4f64(av * av, bv, accb, 0, 0, 0);
+                }
+            }
         }
     }
     // v_mfma_f64_16x16x4f64 returns D[4 r + lane/16][lane % 16] in accumulator r
