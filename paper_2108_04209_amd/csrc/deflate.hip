@@ -107,10 +107,17 @@ __global__ __launch_bounds__(WAVE) void k_deflate(DeflArgs a) {
     int ca = -1;
     double cd = 0.0, cz = 0.0;
     int nkept = 0;
+    // the scan walks the poles a window at a time; the next window's loads are issued before
+    // this one is worked on, so their latency is hidden behind it
+    double ndi = lane < n ? d[lane] : 0.0, nzi = lane < n ? z[lane] : 0.0;
     for (int c0 = 0; c0 < n; c0 += WAVE) {
         const int i = c0 + lane;
         const bool valid = i < n;
-        const double di = valid ? d[i] : 0.0, zi = valid ? z[i] : 0.0;
+        const double di = ndi, zi = nzi;
+        if (i + WAVE < n) {
+            ndi = d[i + WAVE];
+            nzi = z[i + WAVE];
+        }
         const bool r1 = valid && fabs(sv * zi) < tau;  // rule 1
         if (valid) {
             rright[i] = -1;
@@ -204,17 +211,24 @@ __global__ __launch_bounds__(WAVE) void k_deflate(DeflArgs a) {
     __syncthreads();  // the per-pole results are visible to the whole wavefront
     // placement: kept poles first, deflated ones after, each in pole order
     int pk = 0, pd = nkept;
+    int8_t nfl = lane < n ? flag[lane] : 0;
+    double2 nv = lane < n ? val[lane] : make_double2(0.0, 0.0);
     for (int c0 = 0; c0 < n; c0 += WAVE) {
         const int i = c0 + lane;
         const bool valid = i < n;
-        const bool k = valid && flag[i] != 0;
+        const int8_t fl = nfl;
+        const double2 v = nv;
+        if (i + WAVE < n) {  // the next window's loads in flight
+            nfl = flag[i + WAVE];
+            nv = val[i + WAVE];
+        }
+        const bool k = valid && fl != 0;
         const unsigned long long km = __ballot(k), dm = __ballot(valid && !k);
         const unsigned long long mm = k ? km : dm;
         const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(mm >> 32),
                                                    __builtin_amdgcn_mbcnt_lo((unsigned)mm, 0u));
         if (valid) {
             const int j = (k ? pk : pd) + rank;
-            const double2 v = val[i];
             a.dout[base + j] = v.x;
             a.zout[base + j] = k ? v.y : 0.0;
             a.perm[base + j] = i;
