@@ -180,7 +180,8 @@ class TraceScope {
 
 enum WsSlot {
     WS_DW = 0, WS_KE = 1, WS_DZ = 2, WS_Z2 = 3, WS_BK = 4, WS_BP = 5, WS_TMP = 6, WS_VPAIR = 7,
-    WS_VSRC = 8, WS_DEFL_VAL = 9, WS_DEFL_FLAG = 10, WS_DEFL_T = 11, kNumWs
+    WS_VSRC = 8, WS_DEFL_VAL = 9, WS_DEFL_FLAG = 10, WS_DEFL_T = 11, WS_DEFL_SEGI = 12,
+    WS_DEFL_SEGD = 13, kNumWs
 };
 
 struct superdc_ctx {
@@ -333,7 +334,9 @@ hipError_t launch_deflate(const int64_t *off, int nprob, const double *d, const 
                           const double *rho, double tau, double *dout, double *zout,
                           int32_t *perm, int32_t *rright, int32_t *rleft, double *rc, double *rs,
                           int32_t *kept, int32_t *status, double2 *val, int8_t *flag,
-                          hipStream_t s);
+                          int max_n, int4 *seg_i, double2 *seg_d, hipStream_t s);
+// segments per problem of the deflation scan (records seg_i, seg_d: nprob times this)
+int deflate_segments(int max_n);
 hipError_t launch_deflate_expand(const int64_t *off, int nprob, int64_t total, int m,
                                  const int32_t *perm, const int32_t *rright,
                                  const int32_t *rleft, const double *rc, const double *rs,

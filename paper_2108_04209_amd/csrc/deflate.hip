@@ -27,6 +27,8 @@
 
 namespace sdc {
 
+constexpr int DEFL_SEG = 2048;  // poles per segment of the parallel scan (a multiple of 64)
+
 struct DeflArgs {
     const int64_t *off;
     const double *d, *z, *rho;
@@ -37,6 +39,9 @@ struct DeflArgs {
     int32_t *kept, *status;
     double2 *val;    // workspace: final (d, z) of each pole by pole index
     int8_t *flag;    // workspace: 1 kept, 0 deflated
+    int4 *seg_i;     // workspace [nprob][maxseg]: current pole, first survivor, status, kept
+    double2 *seg_d;  // workspace [nprob][maxseg]: the current pole's (d, z)
+    int maxseg;
 };
 
 // the rule-2 test and the rotation (evaluated exactly as written)
@@ -72,49 +77,30 @@ __device__ __forceinline__ double lane_get(double v, int l) {
 }
 __device__ __forceinline__ int lane_get(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
-__global__ __launch_bounds__(WAVE) void k_deflate(DeflArgs a) {
-    __shared__ double sd[WAVE], sz[WAVE];
-    __shared__ int si[WAVE];
-    const int p = blockIdx.x;
-    const int64_t base = a.off[p];
-    const int n = (int)(a.off[p + 1] - base);
+// The scan over poles [lo, hi) of a problem, a window of 64 at a time, with the incoming
+// current pole (ca, cd, cz) (ca < 0: none yet): rule 1, the packing of the survivors into
+// lanes and the rule-2 tests, writing the outcome of every pole of the range and of the
+// incoming pole once it is decided.  On return (ca, cd, cz) is the current pole, still
+// undecided; `first` is the range's first pole that survives rule 1 (-1: none).  Returns
+// the number of poles decided kept.
+__device__ int defl_scan(const DeflArgs &a, int64_t base, int lo, int hi, double sv, int &ca,
+                         double &cd, double &cz, int &first, double *sd, double *sz, int *si) {
     const int lane = threadIdx.x;
+    const double tau = a.tau;
     const double *d = a.d + base, *z = a.z + base;
-    const double rho = a.rho[p], tau = a.tau;
-    // validation: finite, non-decreasing, rho > 0
-    int st = 0;
-    for (int i = lane; i < n; i += WAVE) {
-        const double di = d[i], zi = z[i];
-        if (!isfinite(di) || !isfinite(zi)) st |= SUPERDC_ST_NONFINITE;
-        if (i + 1 < n && d[i + 1] < di) st |= SUPERDC_ST_UNSORTED;
-    }
-    for (int o = WAVE / 2; o > 0; o >>= 1) st |= __shfl_xor(st, o);
-    if (!isfinite(rho)) st |= SUPERDC_ST_NONFINITE;
-    else if (!(rho > 0.0)) st |= SUPERDC_ST_RHO;
-    if (st) {
-        if (lane == 0) {
-            a.status[p] = st;
-            a.kept[p] = 0;
-        }
-        return;
-    }
-    const double sv = sqrt(rho);
     double2 *val = a.val + base;
     int8_t *flag = a.flag + base;
     int32_t *rright = a.rright + base, *rleft = a.rleft + base;
     double *rc = a.rc + base, *rs = a.rs + base;
-    // the current pole of the scan (wave-uniform): index ca (-1: none yet), values (cd, cz)
-    int ca = -1;
-    double cd = 0.0, cz = 0.0;
     int nkept = 0;
-    // the scan walks the poles a window at a time; the next window's loads are issued before
-    // this one is worked on, so their latency is hidden behind it
-    double ndi = lane < n ? d[lane] : 0.0, nzi = lane < n ? z[lane] : 0.0;
-    for (int c0 = 0; c0 < n; c0 += WAVE) {
+    first = -1;
+    // the next window's loads are issued before this one is worked on
+    double ndi = lo + lane < hi ? d[lo + lane] : 0.0, nzi = lo + lane < hi ? z[lo + lane] : 0.0;
+    for (int c0 = lo; c0 < hi; c0 += WAVE) {
         const int i = c0 + lane;
-        const bool valid = i < n;
+        const bool valid = i < hi;
         const double di = ndi, zi = nzi;
-        if (i + WAVE < n) {
+        if (i + WAVE < hi) {
             ndi = d[i + WAVE];
             nzi = z[i + WAVE];
         }
@@ -145,6 +131,7 @@ __global__ __launch_bounds__(WAVE) void k_deflate(DeflArgs a) {
         const int bi = live ? si[lane] : -1;
         __syncthreads();
         if (cnt == 0) continue;
+        if (first < 0) first = lane_get(bi, 0);
         // left neighbour of every lane's pair: the previous lane's pole, the current pole
         // of the scan for lane 0
         double ld = __shfl_up(bd, 1), lz = __shfl_up(bz, 1);
@@ -155,7 +142,7 @@ __global__ __launch_bounds__(WAVE) void k_deflate(DeflArgs a) {
             lz = cz;
             li = ca;
         }
-        if (ca < 0) start = 1;  // the problem's first surviving pole has no left neighbour
+        if (ca < 0) start = 1;  // the first surviving pole has no left neighbour
         int rot_lane = -1;      // lane of the last rotation in this window
         double md = 0.0, mz = 0.0;
         for (;;) {
@@ -201,24 +188,155 @@ __global__ __launch_bounds__(WAVE) void k_deflate(DeflArgs a) {
         }
         ca = lane_get(bi, cnt - 1);
     }
-    if (ca >= 0) {
-        if (lane == 0) {
-            val[ca] = make_double2(cd, cz);
-            flag[ca] = 1;
-        }
-        ++nkept;
+    return nkept;
+}
+
+// validation of poles [lo, hi) of problem p: finite, non-decreasing (across the range's
+// end as well), rho > 0
+__device__ int defl_check(const DeflArgs &a, int p, int64_t base, int lo, int hi, int n) {
+    const int lane = threadIdx.x;
+    const double *d = a.d + base, *z = a.z + base;
+    int st = 0;
+    for (int i = lo + lane; i < hi; i += WAVE) {
+        const double di = d[i], zi = z[i];
+        if (!isfinite(di) || !isfinite(zi)) st |= SUPERDC_ST_NONFINITE;
+        if (i + 1 < n && d[i + 1] < di) st |= SUPERDC_ST_UNSORTED;
     }
-    __syncthreads();  // the per-pole results are visible to the whole wavefront
-    // placement: kept poles first, deflated ones after, each in pole order
-    int pk = 0, pd = nkept;
-    int8_t nfl = lane < n ? flag[lane] : 0;
-    double2 nv = lane < n ? val[lane] : make_double2(0.0, 0.0);
-    for (int c0 = 0; c0 < n; c0 += WAVE) {
+    for (int o = WAVE / 2; o > 0; o >>= 1) st |= __shfl_xor(st, o);
+    const double rho = a.rho[p];
+    if (!isfinite(rho)) st |= SUPERDC_ST_NONFINITE;
+    else if (!(rho > 0.0)) st |= SUPERDC_ST_RHO;
+    return st;
+}
+
+// Segments of DEFL_SEG poles are scanned in parallel (blockIdx.y), each as if no pole came
+// before it; their records keep the undecided current pole at the end, the first pole that
+// survives rule 1, the status bits and the number of poles decided kept.
+__global__ __launch_bounds__(WAVE) void k_deflate(DeflArgs a) {
+    __shared__ double sd[WAVE], sz[WAVE];
+    __shared__ int si[WAVE];
+    const int p = blockIdx.x, sg = blockIdx.y;
+    const int64_t base = a.off[p];
+    const int n = (int)(a.off[p + 1] - base);
+    const int lo = sg * DEFL_SEG;
+    if (lo >= n) return;
+    const int hi = min(n, lo + DEFL_SEG);
+    const int64_t r = (int64_t)p * a.maxseg + sg;
+    const int st = defl_check(a, p, base, lo, hi, n);
+    if (st) {
+        if (threadIdx.x == 0) {
+            a.seg_i[r] = make_int4(-1, -1, st, 0);
+            a.seg_d[r] = make_double2(0.0, 0.0);
+        }
+        return;
+    }
+    int ca = -1, first = -1;
+    double cd = 0.0, cz = 0.0;
+    const int nk = defl_scan(a, base, lo, hi, sqrt(a.rho[p]), ca, cd, cz, first, sd, sz, si);
+    if (threadIdx.x == 0) {
+        a.seg_i[r] = make_int4(ca, first, 0, nk);
+        a.seg_d[r] = make_double2(cd, cz);
+    }
+}
+
+// The joins, in order, one wavefront per problem.  The scan entering segment s holds the
+// current pole of everything before it.  If that pole and the segment's first survivor do
+// not rotate, the pole is kept and the segment's own scan stands exactly (it started from
+// that survivor); if they do, the segment is scanned again from the incoming pole.
+__global__ __launch_bounds__(WAVE) void k_deflate_join(DeflArgs a) {
+    __shared__ double sd[WAVE], sz[WAVE];
+    __shared__ int si[WAVE];
+    const int p = blockIdx.x;
+    const int64_t base = a.off[p];
+    const int n = (int)(a.off[p + 1] - base);
+    const int nseg = (n + DEFL_SEG - 1) / DEFL_SEG;
+    const int64_t r0 = (int64_t)p * a.maxseg;
+    int st = 0;
+    for (int sg = 0; sg < nseg; ++sg) st |= a.seg_i[r0 + sg].z;
+    if (st) {
+        if (threadIdx.x == 0) {
+            a.status[p] = st;
+            a.kept[p] = 0;
+        }
+        return;
+    }
+    const double sv = sqrt(a.rho[p]);
+    int4 ri = a.seg_i[r0];
+    double2 rd = a.seg_d[r0];
+    int ca = ri.x, nk = ri.w;
+    double cd = rd.x, cz = rd.y;
+    for (int sg = 1; sg < nseg; ++sg) {
+        ri = a.seg_i[r0 + sg];
+        rd = a.seg_d[r0 + sg];
+        const int f = ri.y;
+        if (f < 0) continue;  // nothing survives rule 1 here: the current pole passes on
+        if (ca >= 0 && defl_test(cd, cz, a.d[base + f], a.z[base + f], a.tau)) {
+            int first;
+            const int lo = sg * DEFL_SEG;
+            nk += defl_scan(a, base, lo, min(n, lo + DEFL_SEG), sv, ca, cd, cz, first, sd, sz, si);
+            continue;
+        }
+        if (ca >= 0) {  // the incoming pole is kept; the segment's scan stands
+            if (threadIdx.x == 0) {
+                a.val[base + ca] = make_double2(cd, cz);
+                a.flag[base + ca] = 1;
+            }
+            ++nk;
+        }
+        ca = ri.x;
+        cd = rd.x;
+        cz = rd.y;
+        nk += ri.w;
+    }
+    if (ca >= 0) {
+        if (threadIdx.x == 0) {
+            a.val[base + ca] = make_double2(cd, cz);
+            a.flag[base + ca] = 1;
+        }
+        ++nk;
+    }
+    if (threadIdx.x == 0) {
+        a.kept[p] = nk;
+        a.status[p] = 0;
+    }
+}
+
+// kept poles per segment, for the placement
+__global__ __launch_bounds__(WAVE) void k_deflate_count(DeflArgs a) {
+    const int p = blockIdx.x, sg = blockIdx.y;
+    const int64_t base = a.off[p];
+    const int n = (int)(a.off[p + 1] - base);
+    const int lo = sg * DEFL_SEG;
+    if (lo >= n || a.status[p]) return;
+    const int hi = min(n, lo + DEFL_SEG);
+    int c = 0;
+    for (int i = lo + (int)threadIdx.x; i < hi; i += WAVE) c += a.flag[base + i] != 0;
+    for (int o = WAVE / 2; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if (threadIdx.x == 0) a.seg_i[(int64_t)p * a.maxseg + sg].w = c;
+}
+
+// placement: kept poles first, deflated ones after, each in pole order
+__global__ __launch_bounds__(WAVE) void k_deflate_place(DeflArgs a) {
+    const int p = blockIdx.x, sg = blockIdx.y;
+    const int64_t base = a.off[p];
+    const int n = (int)(a.off[p + 1] - base);
+    const int lo = sg * DEFL_SEG;
+    if (lo >= n || a.status[p]) return;
+    const int hi = min(n, lo + DEFL_SEG);
+    const int lane = threadIdx.x;
+    int pk = 0;  // kept poles before this segment
+    for (int u = 0; u < sg; ++u) pk += a.seg_i[(int64_t)p * a.maxseg + u].w;
+    int pd = a.kept[p] + (lo - pk);
+    const double2 *val = a.val + base;
+    const int8_t *flag = a.flag + base;
+    int8_t nfl = lo + lane < hi ? flag[lo + lane] : 0;
+    double2 nv = lo + lane < hi ? val[lo + lane] : make_double2(0.0, 0.0);
+    for (int c0 = lo; c0 < hi; c0 += WAVE) {
         const int i = c0 + lane;
-        const bool valid = i < n;
+        const bool valid = i < hi;
         const int8_t fl = nfl;
         const double2 v = nv;
-        if (i + WAVE < n) {  // the next window's loads in flight
+        if (i + WAVE < hi) {  // the next window's loads in flight
             nfl = flag[i + WAVE];
             nv = val[i + WAVE];
         }
@@ -235,10 +353,6 @@ __global__ __launch_bounds__(WAVE) void k_deflate(DeflArgs a) {
         }
         pk += __popcll(km);
         pd += __popcll(dm);
-    }
-    if (lane == 0) {
-        a.kept[p] = nkept;
-        a.status[p] = 0;
     }
 }
 
@@ -370,13 +484,23 @@ __global__ __launch_bounds__(256) void k_copy_rows(CopyRowsArgs a, int64_t dtota
 }
 
 // ---------------------------------------------------------------------------------------
+int deflate_segments(int max_n) {
+    const int s = (max_n + DEFL_SEG - 1) / DEFL_SEG;
+    return s > 1 ? s : 1;
+}
+
 hipError_t launch_deflate(const int64_t *off, int nprob, const double *d, const double *z,
                           const double *rho, double tau, double *dout, double *zout,
                           int32_t *perm, int32_t *rright, int32_t *rleft, double *rc, double *rs,
                           int32_t *kept, int32_t *status, double2 *val, int8_t *flag,
-                          hipStream_t s) {
-    DeflArgs a{off, d, z, rho, tau, dout, zout, perm, rright, rleft, rc, rs, kept, status, val, flag};
-    SDC_LAUNCH(KID_DEFLATE, k_deflate, dim3(nprob), dim3(WAVE), 0, s, a);
+                          int max_n, int4 *seg_i, double2 *seg_d, hipStream_t s) {
+    DeflArgs a{off,  d,      z,      rho,  tau,  dout,  zout,  perm,   rright,
+               rleft, rc,    rs,     kept, status, val, flag, seg_i, seg_d, deflate_segments(max_n)};
+    const dim3 g2(nprob, a.maxseg);
+    SDC_LAUNCH(KID_DEFLATE, k_deflate, g2, dim3(WAVE), 0, s, a);
+    SDC_LAUNCH(KID_DEFLATE, k_deflate_join, dim3(nprob), dim3(WAVE), 0, s, a);
+    SDC_LAUNCH(KID_DEFLATE, k_deflate_count, g2, dim3(WAVE), 0, s, a);
+    SDC_LAUNCH(KID_DEFLATE, k_deflate_place, g2, dim3(WAVE), 0, s, a);
     return hipGetLastError();
 }
 

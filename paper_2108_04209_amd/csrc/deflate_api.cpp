@@ -25,9 +25,13 @@ int superdc_deflate(superdc_ctx *ctx, const superdc_batch *b, const double *d, c
     hipStream_t s = (hipStream_t)stream;
     double2 *val = (double2 *)ws_get(ctx, WS_DEFL_VAL, sizeof(double2) * b->total);
     int8_t *flag = (int8_t *)ws_get(ctx, WS_DEFL_FLAG, sizeof(int8_t) * b->total);
-    if (!val || !flag) return SUPERDC_ENOMEM;
+    const size_t nrec = (size_t)b->nprob * deflate_segments(b->max_n);
+    int4 *seg_i = (int4 *)ws_get(ctx, WS_DEFL_SEGI, sizeof(int4) * nrec);
+    double2 *seg_d = (double2 *)ws_get(ctx, WS_DEFL_SEGD, sizeof(double2) * nrec);
+    if (!val || !flag || !seg_i || !seg_d) return SUPERDC_ENOMEM;
     hipError_t e = launch_deflate(b->off_d, b->nprob, d, z, rho, tau, d_out, z_out, perm,
-                                  rot_right, rot_left, rot_c, rot_s, kept, status, val, flag, s);
+                                  rot_right, rot_left, rot_c, rot_s, kept, status, val, flag,
+                                  b->max_n, seg_i, seg_d, s);
     return e == hipSuccess ? SUPERDC_OK : fail(e);
 }
 

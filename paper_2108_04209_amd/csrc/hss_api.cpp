@@ -57,6 +57,8 @@ struct superdc_hss {
     int32_t *xv = nullptr; // n
     double2 *xval = nullptr;
     int8_t *xflag = nullptr;
+    int4 *xsegi = nullptr;     // deflation scan records: 2^(depth-1) x segments of n
+    double2 *xsegd = nullptr;
     double *xY = nullptr, *xR0 = nullptr, *xR1 = nullptr, *xT = nullptr;  // n x 2r
     double *xa[3] = {nullptr, nullptr, nullptr};  // apply work buffers of a deflated pass
     int64_t xcap = 0;
@@ -126,6 +128,9 @@ hipError_t defl_alloc(superdc_hss *h) {
     if (e == hipSuccess) e = alloc(h, &h->xv, n);
     if (e == hipSuccess) e = alloc(h, &h->xval, n);
     if (e == hipSuccess) e = alloc(h, &h->xflag, n);
+    const size_t nrec = ((size_t)1 << (h->depth - 1)) * deflate_segments((int)n);
+    if (e == hipSuccess) e = alloc(h, &h->xsegi, nrec);
+    if (e == hipSuccess) e = alloc(h, &h->xsegd, nrec);
     for (double **p : {&h->xY, &h->xR0, &h->xR1, &h->xT})
         if (e == hipSuccess) e = alloc(h, p, n * 2 * r);
     if (e == hipSuccess) {
@@ -154,7 +159,8 @@ int defl_step(superdc_ctx *ctx, superdc_hss *h, int l, int t, int cur, int ncol,
     int32_t *kept = h->kept(l, t);
     hipError_t e = launch_deflate(b->off_d, nprob, poles, zc, h->ones, o.hss_tau, h->xd, h->xz,
                                   h->dperm + k, h->drr + k, h->drl + k, h->dc + k, h->ds + k,
-                                  kept, h->dst(l, t), h->xval, h->xflag, s);
+                                  kept, h->dst(l, t), h->xval, h->xflag, nl, h->xsegi, h->xsegd,
+                                  s);
     if (e != hipSuccess) return fail(e);
     std::vector<int32_t> kh(nprob);
     if ((e = hipMemcpyAsync(kh.data(), kept, sizeof(int32_t) * nprob, hipMemcpyDeviceToHost, s)) !=

@@ -123,3 +123,33 @@ def test_deflated_pipeline_large(orc):
     Y = res["Y0"]
     back = gp.deflated_run(batch, 1e-10, X=Y)["Y1"]
     assert np.abs(back - X).max() <= 1e-11 * np.abs(X).max()
+
+
+def test_deflate_across_scan_segments(orc):
+    """Problems longer than one segment of the parallel scan: a chain of 5000 equal poles
+    that runs through every segment end (each join must rescan the next segment from the
+    incoming pole), and long clustered problems, against the oracle's sequential scan,
+    decisions and values bit for bit."""
+    from paper_2108_04209_amd import native
+    from tests import gpu_pipeline as gp
+    g = gen.rng_for(905, 0)
+    probs = [gen.RankOne(np.full(5000, 0.5), np.abs(g.standard_normal(5000)) + 0.1, 1.0)]
+    for n in (9000, 4097, 6144):
+        probs.append(gen.deflation_problem(n, g, rho=float(g.uniform(0.2, 2.0))))
+    batch = gen.concat(probs)
+    ctx = gp.context()
+    b = native.Batch(ctx, batch.off)
+    for tau in (1e-10, 1e-6):
+        df = native.deflate(ctx, b, gp.to_dev(batch.d), gp.to_dev(batch.z), gp.to_dev(batch.rho), tau)
+        torch.cuda.synchronize()
+        res = {k: v.cpu().numpy() for k, v in df.items()}
+        assert (res["status"] == 0).all()
+        for p, pr in enumerate(probs):
+            a, e = int(batch.off[p]), int(batch.off[p + 1])
+            ref = orc.deflate(pr.d, pr.z, pr.rho, tau)
+            assert res["kept"][p] == ref["kept"], (p, tau)
+            for k, r in (("perm", "perm"), ("rot_right", "rright"), ("rot_left", "rleft")):
+                assert np.array_equal(res[k][a:e], ref[r]), (p, k, tau)
+            for k, r in (("d", "d"), ("z", "z"), ("rot_c", "c"), ("rot_s", "s")):
+                assert ulps(res[k][a:e], ref[r]).max() == 0, (p, k, tau)
+    assert res["kept"][0] == 1  # the whole chain ends in one survivor
