@@ -60,7 +60,7 @@ __device__ __forceinline__ void rr_pair(int pr, int rd, int m, int &p, int &q) {
 
 // cos and sin of the rotation with tangent t (the same operations in both kernels)
 __device__ __forceinline__ double2 rot_cs(double t) {
-    const double c = 1.0 / sqrt(t * t + 1.0);
+    const double c = rcp_nr(sqrt(t * t + 1.0));
     return make_double2(c, t * c);
 }
 
@@ -134,9 +134,11 @@ __global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
                 const double app = A[ut(p, p, m)], aqq = A[ut(q, q, m)];
                 double t = 0.0;
                 if (fabs(apq) > 2.220446049250313e-16 * sqrt(fabs(app) * fabs(aqq)) + absfloor) {
-                    const double theta = (aqq - app) / (2.0 * apq);
-                    if (fabs(theta) > 1e150) t = 0.5 / theta;
-                    else t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                    // the rotation only has to annihilate apq to rounding, so reciprocals
+                    // by Newton-refined estimates stand in for the divisions
+                    const double theta = (aqq - app) * (0.5 * rcp_nr(apq));
+                    if (fabs(theta) > 1e150) t = 0.5 * rcp_nr(theta);
+                    else t = (theta >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(theta) + sqrt(theta * theta + 1.0));
                     atomicAdd(&nrot, 1);
                 }
                 cs[tid] = t != 0.0 ? rot_cs(t) : make_double2(1.0, 0.0);
