@@ -99,12 +99,17 @@ namespace {
 // Launch shape for problems of the given sizes: the fewest wavefronts per work item
 // (split S, a power of two <= 16) and the longest chunk (<= max_chunk) whose work items
 // still give every CU 16 wavefronts, keeping >= 256 summed entries per wavefront.
+// fewest poles each wavefront of a split sums
+#ifndef SDC_MIN_SPLIT_POLES
+#define SDC_MIN_SPLIT_POLES 128
+#endif
+
 LaunchShape shape_for(const superdc_ctx *ctx, const int64_t *sizes, int count, int max_chunk) {
     const long target = (long)ctx->num_cu * 16;
     int64_t nmax = 0;
     for (int i = 0; i < count; ++i) nmax = std::max(nmax, sizes[i]);
     for (int S = 1; S <= 16; S *= 2) {
-        if (S > 1 && nmax / S < 256) break;
+        if (S > 1 && nmax / S < SDC_MIN_SPLIT_POLES) break;
         for (int C = max_chunk; C >= TILE; C /= 2) {
             long wg = 0;
             for (int i = 0; i < count; ++i) wg += (sizes[i] + C - 1) / C;
@@ -112,7 +117,7 @@ LaunchShape shape_for(const superdc_ctx *ctx, const int64_t *sizes, int count, i
         }
     }
     int S = 1;
-    while (S < 16 && nmax / (2 * S) >= 256) S *= 2;
+    while (S < 16 && nmax / (2 * S) >= SDC_MIN_SPLIT_POLES) S *= 2;
     return LaunchShape{TILE, S};
 }
 
