@@ -627,13 +627,47 @@ def bench_ex1(args):
                       "lam_err_rel_normA": float(np.abs(oo["lam"].cpu().numpy() - ex).max() / 5.0)})
         del pl, gg, dd, oo
     note("ex1 size sweep done")
+    # the paper's accuracy measures on the whole eigenmatrix (its Ex. 1 table): residual
+    # gamma = max_k ||A q_k - lambda_k q_k|| / (n ||A||), relative error
+    # delta = ||lambda - lambda*|| / (n ||lambda*||) against the closed form, and loss of
+    # orthogonality theta = max_k ||Q^T q_k - e_k|| / n; Q is formed column block by column
+    # block through the structured eigenmatrix
+    acc_table = []
+    for nn in (8192, 16384):
+        tr = gen.tridiag_hss(nn, leaf)
+        pl = native.HSSPlan(ctx, tr.leaf, tr.depth, tr.r)
+        gg = {k: torch.as_tensor(v, dtype=torch.float64, device=dev)
+              for k, v in native.pack_hss(tr).items()}
+        oo = native.hss_conquer(ctx, pl, native.hss_divide(ctx, pl, gg), opts=o)
+        lam_t = oo["lam"]
+        Q = torch.empty((nn, nn), dtype=torch.float64, device=dev)  # row c = column c of Q
+        blk = 2048
+        for c0 in range(0, nn, blk):
+            E = torch.zeros((blk, nn), dtype=torch.float64, device=dev)
+            E[torch.arange(blk, device=dev), torch.arange(c0, c0 + blk, device=dev)] = 1.0
+            Q[c0:c0 + blk] = native.hss_apply(ctx, pl, E, trans=0)
+        AQ = 3.0 * Q
+        AQ[:, :-1] -= Q[:, 1:]
+        AQ[:, 1:] -= Q[:, :-1]
+        ex = torch.as_tensor(np.sort(3.0 - 2.0 * np.cos(np.arange(1, nn + 1) * np.pi / (nn + 1))),
+                             device=dev)
+        nA = float(ex.abs().max())
+        gamma = float(torch.linalg.norm(AQ - Q * lam_t[:, None], dim=1).max()) / (nn * nA)
+        del AQ
+        G = Q @ Q.T
+        G.diagonal().sub_(1.0)
+        theta = float(torch.linalg.norm(G, dim=1).max()) / nn
+        delta = float(torch.linalg.norm(lam_t - ex) / (nn * torch.linalg.norm(ex)))
+        acc_table.append({"n": nn, "gamma": gamma, "delta": delta, "theta": theta})
+        del Q, G, pl, gg, oo
+    note("ex1 accuracy table done")
     return {"config": {"workload": "tridiagonal (3 on the diagonal, -1 beside it) as an HSS form "
                                    "of rank 2: n=65536, leaf 128, depth 9; balanced dividing "
                                    "stage + conquering pass with deflation, tau = 1e-10",
                        "n": n, "leaf": leaf,
                        "depth": tree.depth, "r": 2},
             "ms_per_step": ms, "conquer_phase_ms": phases, "divide_ms": div[0] / args.steps,
-            "size_sweep": sweep,
+            "size_sweep": sweep, "accuracy_table": acc_table,
             "divide_launches": div[1] // max(1, args.steps),
             "accuracy": {"status": int(out["status"].cpu().numpy()[0]),
                          "lam_err_rel_normA": float(np.abs(lam - exact).max() / 5.0),
