@@ -121,10 +121,10 @@ __device__ void apply_tile_mfma(const ApplyArgs &a, Tile t, double *Xs, double2 
         for (int ct = 0; ct < NCT; ++ct) acc[ct] = v4d{0.0, 0.0, 0.0, 0.0};
         // fuse_b (one pass of at most 15 columns): b = sum (zhat_s / t)^2, each term squared
         // after the division as the b kernel does (zhat^2 and 1/t^2 apart can leave the
-        // exponent range); the second product's column ncols sums them
+        // exponent range); each lane sums the terms of the entries it generates, on the
+        // VALU beside the multiply (one column does not need the MFMA)
         const bool fb = TRANS == 1 && NCT == 1 && a.fuse_b;
-        const double bone = (lane & 15) == ncols ? 1.0 : 0.0;
-        v4d accb = v4d{0.0, 0.0, 0.0, 0.0};
+        double bsum = 0.0;
         ApplyStage<NCT> st;
         apply_fetch<TRANS, NCT>(a, base, n, 0, c0, ncols, st);
         for (int s0 = 0; s0 < n; s0 += AP_K) {
@@ -146,19 +146,23 @@ __device__ void apply_tile_mfma(const ApplyArgs &a, Tile t, double *Xs, double2 
                         acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[ct], 0, 0, 0);
                         if (fb) {
                             const double qv = av * sd.y;
-                            accb = __builtin_amdgcn_mfma_f64_16x16x4f64(qv * qv, bone, accb, 0, 0, 0);
+                            bsum = fma(qv, qv, bsum);
                         }
                     }
                 }
             }
+        }
+        if (fb) {  // the four lanes of a Cauchy row (lane % 16) hold its partial sums
+            bsum += __shfl_xor(bsum, 16);
+            bsum += __shfl_xor(bsum, 32);
         }
         // v_mfma_f64_16x16x4f64 returns D[4 v + lane/16][lane % 16] in accumulator v
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int row = o0 + wv * 16 + 4 * v + (lane >> 4);
             double postb = 0.0;
-            if (fb) {  // b of this row sits in column ncols of the second product
-                postb = 1.0 / sqrt(__shfl(accb[v], (lane & ~15) | ncols));
+            if (fb) {  // b's sum of this row is held by the lanes that generated its entries
+                postb = 1.0 / sqrt(__shfl(bsum, 4 * v + (lane >> 4)));
                 if (row < n && (lane & 15) == 0) a.bout[base + row] = postb;
             }
             if (row < n) {

@@ -323,7 +323,8 @@ constexpr int FV_LD = FV_K + 1;
 constexpr int FV_MAXCH = FMM_NEAR_MAX * (1024 / FV_K) + (2 * FMM_FAR_MAX + 3) / 4;
 
 struct FvStage {
-    double2 sd;    // source position and, for near poles with fuse_b, zhat (threads < 64)
+    double2 sd;    // source position and, with fuse_b, zhat (near poles) or the weight of
+                   // zhat^2 (far equivalent sources) (threads < 64)
     double w[4];   // weights: element e = tid + 256 i -> source e % 64, column e / 64
 };
 
@@ -344,8 +345,9 @@ __device__ __forceinline__ void fv_fetch(const FmmVec &v, int64_t base, const in
     } else {
         if (tid < FV_K) {
             const int bx = tid / FMM_P, qn = tid % FMM_P;
-            st.sd = make_double2(bx < ch.z ? v.vnode[(int64_t)fbox[ch.y + bx] * FMM_P + qn] : 0.0,
-                                 0.0);
+            const int64_t sq = bx < ch.z ? (int64_t)fbox[ch.y + bx] * FMM_P + qn : -1;
+            st.sd = sq >= 0 ? make_double2(v.vnode[sq], v.fuse_b ? v.vw[sq * m + m - 1] : 0.0)
+                            : make_double2(0.0, 0.0);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -421,9 +423,10 @@ __device__ void fmmv_item_mfma(const SolveArgs &it, const FmmArgs &f, const FmmV
     const double ra = v.d[base + clamp_idx(v.origin[base + oc], n)];
     const double rb = v.eta[base + oc];
     v4d_f acc = v4d_f{0.0, 0.0, 0.0, 0.0};
-    v4d_f accb = v4d_f{0.0, 0.0, 0.0, 0.0};  // fuse_b: the same sources through 1/t^2
+    // fuse_b: this lane's share of b's sum for its Cauchy row (the sources it generates
+    // entries for), on the VALU beside the multiply: one column does not need the MFMA
+    double bsum = 0.0;
     const bool fb = v.fuse_b != 0;
-    const double bone = (lane & 15) == m - 1 ? 1.0 : 0.0;
     FvStage st;
     int4 cur = chunk(0);
     fv_fetch(v, base, sh.fbox, cur, st);
@@ -453,12 +456,16 @@ __device__ void fmmv_item_mfma(const SolveArgs &it, const FmmArgs &f, const FmmV
             if (fb) {
                 if (cur_near) {  // (zhat / t)^2: squared after the division
                     const double qv = av * sdv.y;
-                    accb = __builtin_amdgcn_mfma_f64_16x16x4f64(qv * qv, bone, accb, 0, 0, 0);
+                    bsum = fma(qv, qv, bsum);
                 } else {         // far sources: weights of zhat^2, t bounded away from 0
-                    accb = __builtin_amdgcn_mfma_f64_16x16x4f64(av * av, bv, accb, 0, 0, 0);
+                    bsum = fma(av * av, sdv.y, bsum);
                 }
             }
         }
+    }
+    if (fb) {  // the four lanes of a Cauchy row (lane % 16) hold its partial sums
+        bsum += __shfl_xor(bsum, 16);
+        bsum += __shfl_xor(bsum, 32);
     }
     // v_mfma_f64_16x16x4f64 returns D[4 r + lane/16][lane % 16] in accumulator r
 #pragma unroll
@@ -466,8 +473,8 @@ __device__ void fmmv_item_mfma(const SolveArgs &it, const FmmArgs &f, const FmmV
         const int row = o0 + wv * 16 + 4 * r + (lane >> 4);
         const int col = lane & 15;
         double post;
-        if (fb) {  // b of this row sits in column m - 1 of the second product
-            post = 1.0 / sqrt(__shfl(accb[r], (lane & ~15) | (m - 1)));
+        if (fb) {  // b's sum of this row is held by the lanes that generated its entries
+            post = 1.0 / sqrt(__shfl(bsum, 4 * r + (lane >> 4)));
             if (row < n && col == 0) v.bout[base + row] = post;
         } else {
             post = row < n ? v.post[base + row] : 0.0;
