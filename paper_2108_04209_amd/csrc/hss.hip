@@ -34,6 +34,7 @@ constexpr int LV_THREADS = 512;
 constexpr int LV_RB = 4;  // rounds of rotations staged in LDS per block of the replay
 constexpr int LV_ROWS = (LEAF_MAX / 2) / (LV_THREADS / WAVE);  // rows per wavefront (8)
 static_assert(LEAF_MAX / 2 <= WAVE, "a round's pairs must fit one wavefront");
+static_assert(LJ_PACKED < (1 << 15), "row starts of the packed triangle fit 15 bits");
 static_assert(LV_RB * (LEAF_MAX / 2) <= LV_THREADS, "one tangent per staging thread");
 
 // entry (i, j), i <= j, of the upper triangle of an m x m matrix packed by rows
@@ -73,7 +74,9 @@ __global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
     __shared__ double A[LJ_PACKED];  // upper triangle, packed by rows
     __shared__ double2 cs[LEAF_MAX / 2];
     __shared__ double tt[LEAF_MAX / 2];
-    __shared__ int4 pq[LEAF_MAX / 2];  // p, q and where rows p, q start in the packed triangle
+    // p | rowstart(p) << 16 and q | rowstart(q) << 16 (rowstart: where the row starts in
+    // the packed triangle): 8 bytes a pair for the block updates to read
+    __shared__ int2 pq[LEAF_MAX / 2];
     __shared__ double red[LJ_THREADS / WAVE];
     __shared__ int nrot;
 
@@ -139,11 +142,12 @@ __global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
                     const double theta = (aqq - app) * (0.5 * rcp_nr(apq));
                     if (fabs(theta) > 1e150) t = 0.5 * rcp_nr(theta);
                     else t = (theta >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(theta) + sqrt(theta * theta + 1.0));
-                    atomicAdd(&nrot, 1);
                 }
+                const bool anyrot = __any(t != 0.0);
+                if (tid == 0 && anyrot) nrot = 1;
                 cs[tid] = t != 0.0 ? rot_cs(t) : make_double2(1.0, 0.0);
                 tt[tid] = t;
-                pq[tid] = make_int4(p, q, ut(p, 0, m), ut(q, 0, m));
+                pq[tid] = make_int2(p | (ut(p, 0, m) << 16), q | (ut(q, 0, m) << 16));
                 log[((size_t)sweep * (m - 1) + rd) * half + tid] = t;
             }
             __syncthreads();
@@ -156,7 +160,10 @@ __global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
                 if (P1 < 0) continue;
                 const double2 r1 = cs[P1], r2 = cs[P2];
                 if (r1.y == 0.0 && r2.y == 0.0) continue;
-                const int4 ab = pq[P1], cd = pq[P2];  // (index, index, row start, row start)
+                const int2 ab2 = pq[P1], cd2 = pq[P2];
+                // (index, index, row start, row start) of each pair
+                const int4 ab = make_int4(ab2.x & 0xffff, ab2.y & 0xffff, ab2.x >> 16, ab2.y >> 16);
+                const int4 cd = make_int4(cd2.x & 0xffff, cd2.y & 0xffff, cd2.x >> 16, cd2.y >> 16);
                 if (P1 == P2) {
                     const double t = tt[P1];
                     const double apq = A[ab.z + ab.y];
