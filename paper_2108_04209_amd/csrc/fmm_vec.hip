@@ -322,10 +322,13 @@ constexpr int FV_LD = FV_K + 1;
 // a problem's last holds a multiple of 64 poles)
 constexpr int FV_MAXCH = FMM_NEAR_MAX * (1024 / FV_K) + (2 * FMM_FAR_MAX + 3) / 4;
 
+static_assert(FV_K * 16 == 4 * 256, "a chunk's 64 sources x 16 columns: four per thread");
+
 struct FvStage {
     double2 sd;    // source position and, with fuse_b, zhat (near poles) or the weight of
                    // zhat^2 (far equivalent sources) (threads < 64)
-    double w[4];   // weights: element e = tid + 256 i -> source e % 64, column e / 64
+    double w[4];   // weights: element e = tid + 256 i -> source e / 16, column e % 16 (the
+                   // weights are stored source-major, so 16 threads read a source's row)
 };
 
 __device__ __forceinline__ void fv_fetch(const FmmVec &v, int64_t base, const int *fbox, int4 ch,
@@ -339,7 +342,7 @@ __device__ __forceinline__ void fv_fetch(const FmmVec &v, int64_t base, const in
                                : make_double2(0.0, 0.0);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int e = tid + 256 * i, sl = e % FV_K, c = e / FV_K;
+            const int e = tid + 256 * i, sl = e >> 4, c = e & 15;
             st.w[i] = (sl < ch.z && c < m) ? v.src[(base + ch.y + sl) * m + c] : 0.0;
         }
     } else {
@@ -351,7 +354,7 @@ __device__ __forceinline__ void fv_fetch(const FmmVec &v, int64_t base, const in
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int e = tid + 256 * i, sl = e % FV_K, c = e / FV_K;
+            const int e = tid + 256 * i, sl = e >> 4, c = e & 15;
             const int bx = sl / FMM_P, qn = sl % FMM_P;
             st.w[i] = (bx < ch.z && c < m)
                           ? v.vw[((int64_t)fbox[ch.y + bx] * FMM_P + qn) * m + c]
@@ -436,7 +439,7 @@ __device__ void fmmv_item_mfma(const SolveArgs &it, const FmmArgs &f, const FmmV
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int e = threadIdx.x + 256 * i;
-            sh.Xs[(e / FV_K) * FV_LD + e % FV_K] = st.w[i];
+            sh.Xs[(e & 15) * FV_LD + (e >> 4)] = st.w[i];
         }
         __syncthreads();
         const int nvalid = wave_uniform(cur.x == 0 ? cur.z : cur.z * FMM_P);
