@@ -11,6 +11,8 @@ for the number of deflations a pass can make, not a fit to the results.
     structured eigenmatrix: orthonormal, and T q = lambda q with T applied directly;
   - the whole eigenmatrix of a small case (n = 1024): Q^T Q = I, T Q = Q Lambda, and the
     two directions of the structured product transposes of each other;
+  - the paper's residual, relative error and orthogonality measures on the whole
+    eigenmatrix at n = 8192;
   - random tridiagonal matrices (localised eigenvectors) against LAPACK's tridiagonal
     solver;
   - a dense-generator HSS matrix, where almost nothing deflates, against the pass without
@@ -66,6 +68,41 @@ def test_tridiagonal_example(n, leaf, tau, bound):
     res = np.linalg.norm(tmatvec(np.full(n, 3.0), np.full(n - 1, -1.0), Qs) - Qs * lam[ks], axis=0)
     assert res.max() <= max(bound, 1e-11) * 5.0
     assert np.abs(Qs.T @ Qs - np.eye(len(ks))).max() <= 1e-11
+
+
+def test_tridiagonal_accuracy_measures():
+    """The paper's three accuracy measures for its first example (its table for Ex. 1) on the
+    whole eigenmatrix at n = 8192 with tau = 1e-10: residual gamma = max_k ||T q_k - lambda_k
+    q_k|| / (n ||T||), relative error delta = ||lambda* - lambda|| / (n ||lambda*||) against the
+    closed form, loss of orthogonality theta = max_k ||Q^T q_k - e_k|| / n.  The bounds are
+    those of the sampled test above (per-root residual and eigenvalue error at most
+    5 x 1e-9, orthogonality 1e-11) in the paper's normalisation, not a fit to the results."""
+    from paper_2108_04209_amd import native
+    from tests import gpu_pipeline as gp
+    n = 8192
+    plan, lam, st = run(gen.tridiag_hss(n, 64), 1e-10)
+    assert st == 0
+    Q = torch.empty((n, n), dtype=torch.float64, device="cuda")  # row c: column c of Q
+    for c0 in range(0, n, 2048):
+        E = torch.zeros((2048, n), dtype=torch.float64, device="cuda")
+        E[torch.arange(2048), torch.arange(c0, c0 + 2048)] = 1.0
+        Q[c0:c0 + 2048] = native.hss_apply(gp.context(), plan, E, trans=0)
+    torch.cuda.synchronize()
+    exact = np.sort(3.0 - 2.0 * np.cos(np.arange(1, n + 1) * np.pi / (n + 1)))
+    nA = exact.max()
+    TQ = 3.0 * Q
+    TQ[:, :-1] -= Q[:, 1:]
+    TQ[:, 1:] -= Q[:, :-1]
+    lam_d = torch.from_numpy(lam).to("cuda")
+    gamma = float((TQ - Q * lam_d[:, None]).norm(dim=1).max()) / (n * nA)
+    del TQ
+    G = Q @ Q.T
+    G.diagonal().sub_(1.0)
+    theta = float(G.norm(dim=1).max()) / n
+    delta = float(np.linalg.norm(lam - exact) / (n * np.linalg.norm(exact)))
+    assert gamma <= 5e-9 / (n * nA)
+    assert theta <= 1e-11 / n
+    assert delta <= 5e-9 * np.sqrt(n) / (n * np.linalg.norm(exact))
 
 
 def test_tridiagonal_eigenmatrix_small():
