@@ -103,14 +103,15 @@ __global__ __launch_bounds__(1024) void k_validate(SolveArgs a, int prob_first) 
 // step (<= 11 ulp, measured); near pairs keep the shifted form (d_j - d_K) - y (eq.
 // localshift) and a reciprocal refined twice.
 //
-// Far pairs are taken two poles at a time with one shared reciprocal (the FP64
-// reciprocal issues at a quarter of the FMA rate on gfx950):
+// Outside the window (where every pole of a range lies on one side of every root), poles
+// are taken two at a time with one shared reciprocal (the FP64 reciprocal issues at a
+// quarter of the FMA rate on gfx950), far ones in lambda-form with one Newton step, near
+// ones in the shifted form with two:
 //   w0/t0 + w1/t1       = (w0 t1 + w1 t0) / (t0 t1)
 //   w0/t0^2 + w1/t1^2   = (w0 t1 t1 + w1 t0 t0) / (t0 t1)^2
-// t0 and t1 have the same sign (both poles lie on one side of every root of the range),
-// so neither numerator cancels.  The products need every |t| of the range inside
-// [2^-300, 2^300]; a range outside that (checked once per range for the whole wavefront)
-// takes one reciprocal per pole.
+// t0 and t1 have the same sign, so neither numerator cancels.  The products need every
+// |t| of the range inside [2^-300, 2^300]; a range outside that (checked once per range
+// for the whole wavefront) takes one reciprocal per pole.
 template <int MODE, bool FAR>
 __device__ __forceinline__ void secular_range(const_double2_ptr dw, int j0, int j1,
                                               int k, double dK, double y, double x,
@@ -136,12 +137,13 @@ __device__ __forceinline__ void secular_range(const_double2_ptr dw, int j0, int 
             dphi = __builtin_fma(wg, r, dphi);                        \
         }                                                             \
     }
-// two far poles, one reciprocal (MODE 0 or 1 only)
+// two poles, one reciprocal (MODE 0 or 1 only)
 #define SDC_SEC_PAIR(PA, PB)                                          \
     {                                                                 \
         const double2 pa = (PA), pb = (PB);                           \
-        const double t0 = pa.x - x, t1 = pb.x - x;                    \
-        const double R = rcp_nr1(t0 * t1);                            \
+        const double t0 = FAR ? pa.x - x : (pa.x - dK) - y;           \
+        const double t1 = FAR ? pb.x - x : (pb.x - dK) - y;           \
+        const double R = FAR ? rcp_nr1(t0 * t1) : rcp_nr(t0 * t1);    \
         const double u0 = pa.y * t1, u1 = pb.y * t0;                  \
         const double num2 = __builtin_fma(u0, t1, u1 * t0);           \
         if (MODE == 0) {                                              \
@@ -162,10 +164,12 @@ __device__ __forceinline__ void secular_range(const_double2_ptr dw, int j0, int 
     S##3 = make_double2((Q)[6], (Q)[7]);
     int j = j0;
     const_double_ptr q = dw.p + 2 * (int64_t)j0;
-    if (FAR && MODE != 2 && j + 4 <= j1) {
+    if (MODE != 2 && j + 4 <= j1) {
         // the nearest and farthest pole of the range bound every |t|
-        const double tn = fabs((MODE == 0 ? dw[j1 - 1].x : dw[j0].x) - x);
-        const double tf = fabs((MODE == 0 ? dw[j0].x : dw[j1 - 1].x) - x);
+        const double dn = MODE == 0 ? dw[j1 - 1].x : dw[j0].x;
+        const double df = MODE == 0 ? dw[j0].x : dw[j1 - 1].x;
+        const double tn = fabs(FAR ? dn - x : (dn - dK) - y);
+        const double tf = fabs(FAR ? df - x : (df - dK) - y);
         const bool ok = tn >= 0x1p-300 && tf <= 0x1p300;
         if (__ballot(!ok) == 0ull) {
             double2 a0, a1, a2, a3, b0, b1, b2, b3;
