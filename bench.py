@@ -40,6 +40,27 @@ FLOPS_BNORM = 6          # per pair: 2 sub, 1 rcp, 1 mul, 1 fma(2)
 
 
 FMM_CROSSOVER = 1024     # the library's default direct/FMM switch (roots per problem)
+ITER_COUNT_MASK, ITER_UNMET, ITER_CAP = 0xFFFF, 1 << 16, 1 << 17  # iteration records
+
+MU_DEFINITION = ("per level, the largest share over the r rank-one steps of roots that needed "
+                 "more than 5 iterations after the midpoint pass, or whose iteration ended on "
+                 "a step below rounding or a collapsed bracket (or the cap) before the "
+                 "stopping test held")
+
+
+def mu_levels(it, count_only=False):
+    """The share mu (percent) of roots not converged within 5 iterations, per level, from
+    iteration records of shape (depth, r, n)."""
+    cnt = it & ITER_COUNT_MASK
+    bad = cnt > 5 if count_only else (cnt > 5) | ((it & (ITER_UNMET | ITER_CAP)) != 0)
+    return [float(100.0 * np.max(np.mean(bad[l], axis=1))) for l in range(it.shape[0])]
+
+
+def unmet_levels(it):
+    """Per level, the largest share (percent) over the steps of roots whose iteration ended
+    before the stopping test held."""
+    bad = (it & (ITER_UNMET | ITER_CAP)) != 0
+    return [float(100.0 * np.max(np.mean(bad[l], axis=1))) for l in range(it.shape[0])]
 MFMA_MIN_M = 4           # the library's automatic VALU/MFMA apply switch (columns)
 
 
@@ -282,7 +303,7 @@ def bench_level(args, name):
     pipe = Pipeline(batch, X, persistent=1, crossover=args.fmm_crossover, leaf=args.fmm_leaf)
     wall_ms, tot_ms, ph = time_steps(pipe, args.steps, args.warmup)
     note(f"{name} batched {float(np.mean(tot_ms)):.2f} ms/step")
-    iters = pipe.out["iters"].cpu().numpy().astype(np.float64)
+    iters = (pipe.out["iters"].cpu().numpy() & ITER_COUNT_MASK).astype(np.float64)
     status_ok = bool(np.all(pipe.out["status"].cpu().numpy() == 0))
     ms = float(np.mean(tot_ms))
     solve_ms, vec_ms, apply_ms = (float(x) for x in ph.mean(axis=0))
@@ -388,7 +409,7 @@ def bench_large(args):
     for name, method in (("fmm", 2), ("direct", 1)):
         pipe = Pipeline(batch, X, persistent=1, method=method, leaf=256)  # as specified
         wall_ms, tot_ms, ph = time_steps(pipe, args.steps, args.warmup)
-        iters = pipe.out["iters"].cpu().numpy().astype(np.float64)
+        iters = (pipe.out["iters"].cpu().numpy() & ITER_COUNT_MASK).astype(np.float64)
         solve_ms, vec_ms, apply_ms = (float(x) for x in ph.mean(axis=0))
         ms = float(np.mean(tot_ms))
         note(f"large {name} {ms:.2f} ms/step")
@@ -776,7 +797,8 @@ def bench_conquer(args):
     ms, phases, counts = timed(opts1, args.steps, args.warmup)
     note(f"conquer batched {ms:.2f} ms/step")
     status = int(out["status"].cpu().numpy()[0])
-    iters = native.hss_iterations(plan).cpu().numpy().astype(np.float64)
+    it_raw = native.hss_iterations(plan).cpu().numpy()
+    iters = (it_raw & ITER_COUNT_MASK).astype(np.float64)
     lam = out["lam"].cpu().numpy()
     sec_f, vec_f, app_f = conquer_flops(tree, iters)
     roots = tree.depth * tree.r * tree.n
@@ -792,9 +814,13 @@ def bench_conquer(args):
         torch.cuda.synchronize()
         it_un = native.hss_iterations(plan).cpu().numpy()
         lam_un = un["lam"].cpu().numpy()
-        mu = lambda it: [float(100.0 * np.max(np.mean(it[l] > 5, axis=1))) for l in range(it.shape[0])]
         abl = {"levels_n": [int(tree.leaf << (tree.depth - l)) for l in range(tree.depth)],
-               "mu_percent_shifted": mu(iters), "mu_percent_unshifted": mu(it_un),
+               "mu_definition": MU_DEFINITION,
+               "mu_percent_shifted": mu_levels(it_raw), "mu_percent_unshifted": mu_levels(it_un),
+               "mu_percent_count_only_shifted": mu_levels(it_raw, count_only=True),
+               "mu_percent_count_only_unshifted": mu_levels(it_un, count_only=True),
+               "unmet_percent_shifted": unmet_levels(it_raw),
+               "unmet_percent_unshifted": unmet_levels(it_un),
                "status_unshifted": int(un["status"].cpu().numpy()[0]),
                "nonfinite_unshifted": int(np.count_nonzero(~np.isfinite(lam_un)))}
         fin = np.isfinite(lam_un)
@@ -812,7 +838,8 @@ def bench_conquer(args):
         e1.record()
         torch.cuda.synchronize()
         it_hy = native.hss_iterations(plan).cpu().numpy()
-        abl["hybrid_li93"] = {"mu_percent": mu(it_hy), "mean_iters": float(it_hy.mean()),
+        abl["hybrid_li93"] = {"mu_percent": mu_levels(it_hy),
+                              "mean_iters": float((it_hy & ITER_COUNT_MASK).mean()),
                               "mean_iters_middle_way": float(iters.mean()),
                               "ms_per_step": e0.elapsed_time(e1),
                               "status": int(hy["status"].cpu().numpy()[0]),

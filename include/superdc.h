@@ -65,6 +65,14 @@ extern "C" {
 #define SUPERDC_ST_NOCONV 16    /* a root hit the iteration cap; it keeps its best     */
                                 /* bracketed iterate                                   */
 
+/* per-root iteration record (iters array of superdc_secular_solve): the low 16 bits count
+ * the evaluations of the secular sums after the midpoint pass; one of these bits tells how
+ * the iteration ended when it did not end on the stopping test (eq. stopcrit) */
+#define SUPERDC_ITER_COUNT_MASK 0xffff
+#define SUPERDC_ITER_UNMET (1 << 16) /* a step below 2 ulps of the iterate, or a bracket    */
+                                     /* collapsed to 2 ulps, ended it before the test held */
+#define SUPERDC_ITER_CAP (1 << 17)   /* the iteration cap ended it (status NOCONV)          */
+
 typedef struct superdc_ctx superdc_ctx;
 typedef struct superdc_batch superdc_batch;
 
@@ -85,7 +93,8 @@ typedef struct {
                             (solver, b, Qhat^T X); 0 = the context's default (1024)       */
     int32_t unshifted;   /* 1: ablation of the local shifting (Sec. 4.2.2): the iterate is
                             kept as lambda itself and every pole difference is formed as
-                            d_j - lambda, the original secular equation; default 0     */
+                            d_j - lambda (f evaluated at lambda with no shift); the
+                            reciprocals keep the default precision; default 0          */
     int32_t interp;      /* rational interpolation of the iteration (Sec. 4.1.1): 0 the middle
                             way (default); 1 the hybrid of [li93]: the middle way and the
                             fixed-weight scheme (the nearer pole keeps its true weight, the
@@ -118,8 +127,9 @@ int64_t superdc_batch_total(const superdc_batch *batch);
 /*
  * Autotune the batch's launch shapes on representative data (d, z, rho as for
  * superdc_secular_solve): the secular solver's work-item length (64..512 roots) and split
- * (wavefronts sharing one work item, 1..16), and the splits of the Loewner/b and adjoint
- * kernels, each timed on `stream`.  Synchronises the stream and allocates scratch; call it
+ * (wavefronts sharing one work item, 1..16), the split of the FMM solver's work items
+ * (1..8) when opts select the FMM for some problem, and the splits of the Loewner/b and
+ * adjoint kernels, each timed on `stream`.  Synchronises the stream and allocates scratch; call it
  * once, before capturing graphs.  With SUPERDC_TUNE_CACHE set to a file path the choice is
  * read from / appended to that file, keyed by the problem sizes and the CU count.
  * Without tuning a heuristic shape is used.  Results of the solver can differ in the last
@@ -127,16 +137,19 @@ int64_t superdc_batch_total(const superdc_batch *batch);
  */
 int superdc_autotune(superdc_ctx *ctx, superdc_batch *batch, const double *d, const double *z,
                      const double *rho, const superdc_opts *opts, void *stream);
-/* Current shapes: out[0] solver work-item length, out[1] solver split, out[2] Loewner/b
- * split, out[3] adjoint split. */
+/* Current shapes (out: int32[5]): out[0] solver work-item length, out[1] solver split,
+ * out[2] Loewner/b split, out[3] adjoint split, out[4] FMM solver split (0: the heuristic,
+ * about 16 wavefronts per CU). */
 int superdc_batch_shapes(const superdc_batch *batch, int32_t *out);
 
 /*
  * Eigenvalues of every problem (*) (Alg. 2 with local shifting, Sec. 4.2).
  *   in : d[total], z[total], rho[nprob]
- *   out: lam[total], eta[total], origin[total] (int32, local), iters[total] (int32,
- *        evaluations of the secular sums after the midpoint pass; may be NULL), status[nprob] (int32, bits
- *        above; always written).
+ *   out: lam[total], eta[total], origin[total] (int32, local), iters[total] (int32: the
+ *        evaluations of the secular sums after the midpoint pass in the bits
+ *        SUPERDC_ITER_COUNT_MASK, plus SUPERDC_ITER_UNMET or SUPERDC_ITER_CAP when the
+ *        iteration ended otherwise than on the stopping test; may be NULL), status[nprob]
+ *        (int32, bits above; always written).
  * opts may be NULL (defaults).
  */
 int superdc_secular_solve(superdc_ctx *ctx, const superdc_batch *batch, const double *d,
@@ -335,6 +348,20 @@ int superdc_hss_apply(superdc_ctx *ctx, superdc_hss *plan, int trans, int32_t m,
                       const superdc_opts *opts, void *stream);
 
 /*
+ * Autotune the launch shapes of every level's batch of the plan (superdc_autotune on each
+ * level, timed on the level's own first rank-one problems, which one conquer of these
+ * generators produces on the way).  Runs that conquer on `stream`, synchronises it and
+ * allocates scratch: call it once, before timing or capturing conquers of the plan.  The
+ * choice persists in the plan's batches (and in SUPERDC_TUNE_CACHE when set).  Undeflated
+ * passes only: opts->hss_tau must be 0 (EINVAL otherwise).
+ */
+int superdc_hss_autotune(superdc_ctx *ctx, superdc_hss *plan, const double *leaf_D,
+                         const double *leaf_U, const double *R, const double *B,
+                         const double *beta, const superdc_opts *opts, void *stream);
+/* The launch shapes of level `level`'s batch, as superdc_batch_shapes (out: int32[5]). */
+int superdc_hss_batch_shapes(const superdc_hss *plan, int32_t level, int32_t *out);
+
+/*
  * Phase timing of superdc_hss_conquer (for measurement).  With timing enabled, each
  * conquer records HIP events on its stream between phases.  superdc_hss_phase_times waits
  * for the last conquer and returns, per phase, the summed milliseconds ms[6] and the
@@ -343,8 +370,8 @@ int superdc_hss_apply(superdc_ctx *ctx, superdc_hss *plan, int trans, int32_t m,
  * 4 Cauchy applies, 5 final copies.  Returns SUPERDC_EINVAL if timing was off.
  */
 int superdc_hss_set_timing(superdc_hss *plan, int enable);
-/* Copy the per-root solver evaluation counts of the last conquer to dst (device,
- * int32[depth][r][n], level-major). */
+/* Copy the per-root solver iteration records of the last conquer to dst (device,
+ * int32[depth][r][n], level-major; encoded as the iters output of superdc_secular_solve). */
 int superdc_hss_iterations(superdc_hss *plan, int32_t *dst, void *stream);
 int superdc_hss_phase_times(superdc_hss *plan, double *ms, int32_t *launches);
 
@@ -361,10 +388,14 @@ int superdc_hss_phase_times(superdc_hss *plan, double *ms, int32_t *launches);
 int superdc_kernel_timing(int enable);
 int superdc_kernel_times(double *ms, int32_t *launches, int32_t count);
 /*
- * Pole-root pair evaluations counted while kernel timing was on, per kernel id (the
- * secular solvers count each pass of each live root times the poles or equivalent sources
- * it sums; kernels without a counter report 0).  Waits for the device, then clears the
- * counters.  Returns the number of kernel ids (negative on error).
+ * Work counted on the device while kernel timing was on, per kernel id; kernels without a
+ * counter report 0.  The secular solvers (k_secular, k_secular_fmm) count pole-root pair
+ * evaluations: each pass of each live root times the poles or equivalent sources it sums.
+ * The Cauchy apply kernels (k_apply_mfma, k_apply_valu) and the eigenvector-side FMM
+ * evaluations (k_fmmv_eval_mfma, k_fmmv_eval) count algorithmic FP64 flops: (2m + 3) per
+ * Cauchy entry (pole or equivalent source against root) for m columns (6 for the b sum
+ * alone), plus 2m per output row.  Waits for the device, then clears the counters.
+ * Returns the number of kernel ids (negative on error).
  */
 int superdc_kernel_work(double *pairs, int32_t count);
 const char *superdc_kernel_name(int32_t id);

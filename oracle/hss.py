@@ -58,10 +58,11 @@ def dense_nodes(tree):
     return A
 
 
-def level_eigenvalues(tree):
+def level_eigenvalues(tree, dense=None):
     """Eigenvalues of every node, ascending per node, concatenated per level:
-    returns array (depth+1, n); row l holds the nodes of level l left to right."""
-    A = dense_nodes(tree)
+    returns array (depth+1, n); row l holds the nodes of level l left to right.
+    dense: the output of dense_nodes(tree), if the caller has it already."""
+    A = dense_nodes(tree) if dense is None else dense
     out = np.empty((tree.depth + 1, tree.n))
     for lvl in range(tree.depth + 1):
         sz = node_size(tree, lvl)

@@ -6,6 +6,12 @@ eigenvectors q_k = b_k (z_i / (d_i - lambda_k))_i on u.  The backward pass is th
 hand-written adjoint (superdc_secular_backward): implicit differentiation of the secular
 equation f(lambda_k) = 0 through Cauchy-like sums, never a dense eigendecomposition.
 All work runs in libsuperdc.so; this module only wires tensors.
+
+Nothing here waits for the device: like the C ABI, the binding leaves data-dependent
+errors on the device.  A problem with invalid input (d not strictly increasing, z_i = 0,
+rho <= 0, non-finite values) gets NaN eigenvalues, projections and gradients; pass an
+int32 tensor `status` of shape (nprob,) to receive the per-problem status bits
+(native.ST_*) by a device-side copy and check them whenever the caller synchronises.
 """
 from __future__ import annotations
 
@@ -16,11 +22,11 @@ from . import native
 
 class _SecularEig(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, d, z, rho, u, batch, opts):
+    def forward(ctx, d, z, rho, u, batch, opts, status):
         lib_ctx = batch.ctx
         s = native.secular_solve(lib_ctx, batch, d, z, rho, opts=opts)
-        if torch.any(s["status"] & ~native.ST_NOCONV):
-            raise native.SuperdcError("secular_eig: invalid input (status bits set)")
+        if status is not None:
+            status.copy_(s["status"])  # enqueued on the stream: no host synchronisation
         outs = [s["lam"]]
         if u is not None:
             zh, bn = native.loewner(lib_ctx, batch, d, z, rho, s["eta"], s["origin"], s["status"],
@@ -47,12 +53,16 @@ class _SecularEig(torch.autograd.Function):
         gu = None
         if ctx.has_u and ctx.needs_input_grad[3]:
             raise NotImplementedError("gradient with respect to u is not provided")
-        return gd, gz, gr, gu, None, None
+        return gd, gz, gr, gu, None, None, None
 
 
-def secular_eig(batch, d, z, rho, u=None, opts=None):
+def secular_eig(batch, d, z, rho, u=None, opts=None, status=None):
     """Differentiable eigenvalues (and projections on u) of a batch of rank-one problems.
-    batch: native.Batch; d, z: (total,) float64 CUDA tensors; rho: (nprob,)."""
+    batch: native.Batch; d, z: (total,) float64 CUDA tensors; rho: (nprob,).
+    status: optional int32 CUDA tensor (nprob,) that receives the status bits."""
     o = opts if opts is not None else native.default_opts()
+    if status is not None and (status.dtype != torch.int32 or status.numel() != batch.nprob
+                               or not status.is_cuda):
+        raise ValueError("status must be an int32 CUDA tensor with one entry per problem")
     return _SecularEig.apply(d.contiguous(), z.contiguous(), rho.contiguous(),
-                             None if u is None else u.contiguous(), batch, o)
+                             None if u is None else u.contiguous(), batch, o, status)

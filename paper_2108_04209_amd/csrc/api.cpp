@@ -37,6 +37,9 @@ int hip_fail(hipError_t e) {
         if (e_ != hipSuccess) return hip_fail(e_);     \
     } while (0)
 
+}  // namespace
+
+namespace sdc {
 int opts_check(const superdc_opts *o) {
     if (!(o->stop_c > 0.0) || o->max_iter < 1 || o->max_iter > 200) return SUPERDC_EINVAL;
     if (o->method < 0 || o->method > 2) return SUPERDC_EINVAL;
@@ -51,15 +54,19 @@ int opts_check(const superdc_opts *o) {
     return SUPERDC_OK;
 }
 
+int fmm_crossover_of(const superdc_ctx *ctx, const superdc_opts &o) {
+    return o.method == 1 ? 0x7fffffff
+           : o.method == 2 ? 2 * o.fmm_leaf
+           : o.fmm_crossover > 0 ? o.fmm_crossover
+                                : ctx->fmm_crossover;
+}
+
 // persistent grid: enough single-wave workgroups to fill every CU several times
 int persistent_grid(const superdc_ctx *ctx, int ntiles, int per_cu) {
     const long g = (long)ctx->num_cu * per_cu;
     return (int)std::max(1L, std::min<long>(g, ntiles));
 }
 
-}  // namespace
-
-namespace sdc {
 const TileList *tile_list(superdc_batch *b, int chunk) {
     int slot = chunk == 64 ? 0 : chunk == 128 ? 1 : chunk == 256 ? 2 : chunk == 512 ? 3 : -1;
     if (slot < 0) return nullptr;
@@ -121,6 +128,13 @@ LaunchShape shape_for(const superdc_ctx *ctx, const int64_t *sizes, int count, i
     return LaunchShape{TILE, S};
 }
 
+}  // namespace
+
+namespace sdc {
+LaunchShape plain_shape(const superdc_ctx *ctx, int64_t n) { return shape_for(ctx, &n, 1, TILE); }
+}  // namespace sdc
+
+namespace {
 LaunchShape choose_shape(const superdc_ctx *ctx, const superdc_batch *b, int max_chunk) {
     std::vector<int64_t> sizes(b->nprob);
     for (int p = 0; p < b->nprob; ++p) sizes[p] = b->off_h[p + 1] - b->off_h[p];
@@ -321,10 +335,7 @@ FmmArgs fmm_vec_args(const FmmPlan *fp, const superdc_batch *b, const double2 *p
 // the FMM plan that applies to this call, or nullptr (rc = ENOMEM on allocation failure)
 FmmPlan *fmm_for(superdc_ctx *ctx, superdc_batch *b, const superdc_opts &o, int &rc) {
     rc = SUPERDC_OK;
-    const int crossover = o.method == 1 ? 0x7fffffff
-                          : o.method == 2 ? 2 * o.fmm_leaf
-                          : o.fmm_crossover > 0 ? o.fmm_crossover
-                                              : ctx->fmm_crossover;
+    const int crossover = fmm_crossover_of(ctx, o);
     if (b->max_n < crossover) return nullptr;
     FmmPlan *fp = fmm_plan(b, o.fmm_leaf, crossover);
     if (!fp) {
@@ -697,6 +708,12 @@ int superdc_batch_create(superdc_ctx *ctx, int32_t nprob, const int64_t *off_hos
     }
     // launch shapes for the persistent launches (the autotuner may replace them)
     b->sec = choose_shape(ctx, b, SEC_CHUNK);
+    // the solver's tile list for that shape is built now, so that a later solve (the
+    // allocation-free entry point in particular) finds it ready
+    if (!tile_list(b, b->sec.chunk)) {
+        superdc_batch_destroy(b);
+        return hip_fail(hipErrorOutOfMemory);
+    }
     b->vec = choose_shape(ctx, b, TILE);
     b->bwd = b->vec;
     b->app = LaunchShape{TILE, 1};
@@ -747,10 +764,7 @@ int superdc_secular_solve(superdc_ctx *ctx, const superdc_batch *b, const double
     superdc_batch *bm = const_cast<superdc_batch *>(b);
     // problems at or above the crossover size use the triangular FMM (method 2: every
     // problem large enough to have two leaves; method 1: none)
-    const int crossover = o.method == 1 ? 0x7fffffff
-                          : o.method == 2 ? 2 * o.fmm_leaf
-                          : o.fmm_crossover > 0 ? o.fmm_crossover
-                                              : ctx->fmm_crossover;
+    const int crossover = fmm_crossover_of(ctx, o);
     FmmPlan *fp = nullptr;
     if (b->max_n >= crossover) {
         fp = fmm_plan(bm, o.fmm_leaf, crossover);
@@ -784,9 +798,9 @@ int superdc_secular_solve(superdc_ctx *ctx, const superdc_batch *b, const double
             af.ntiles = fp->snitems;
             af.chunk = fp->ssub;
             af.work = trace_work(KID_SECULAR_FMM);
-            SDC_HIP(launch_secular_fmm(af, f, fp->ssplit, ctx->queues + Q_SECULAR_FMM,
-                                       persistent_grid(ctx, af.ntiles, std::max(1, 32 / fp->ssplit)),
-                                       s));
+            const int ss = b->fmm_ssplit > 0 ? b->fmm_ssplit : fp->ssplit;  // tuned or heuristic
+            SDC_HIP(launch_secular_fmm(af, f, ss, ctx->queues + Q_SECULAR_FMM,
+                                       persistent_grid(ctx, af.ntiles, std::max(1, 32 / ss)), s));
         }
     } else {
         // one launch per problem, cut into 64-root chunks (split if the problem is large),

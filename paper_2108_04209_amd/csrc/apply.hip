@@ -156,6 +156,11 @@ __device__ void apply_tile_mfma(const ApplyArgs &a, Tile t, double *Xs, double2 
             bsum += __shfl_xor(bsum, 16);
             bsum += __shfl_xor(bsum, 32);
         }
+        if (a.work && threadIdx.x == 0) {  // kernel timing: this pass's algorithmic flops
+            const unsigned long long rows = (unsigned long long)min(AP_ROWS, n - o0);
+            const unsigned long long me = (unsigned long long)(ncols + (fb ? 1 : 0));
+            atomicAdd(a.work, rows * (unsigned long long)n * (2 * me + 3) + 2 * rows * me);
+        }
         // v_mfma_f64_16x16x4f64 returns D[4 v + lane/16][lane % 16] in accumulator v
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -275,6 +280,11 @@ __device__ void apply_tile_valu(const ApplyArgs &a, Tile t, double *Xs, double2 
                 for (int c = 0; c < ncols; ++c)
                     a.Y[base + o + (int64_t)(c0 + c) * a.ldy] = post * acc[c];
         }
+        if (a.work && threadIdx.x == 0) {  // kernel timing: this pass's algorithmic flops
+            const unsigned long long rows = (unsigned long long)min(WAVE, n - t.row0);
+            const unsigned long long me = (unsigned long long)ncols;
+            atomicAdd(a.work, rows * (unsigned long long)n * (2 * me + 3) + 2 * rows * me);
+        }
     }
 }
 
@@ -299,8 +309,10 @@ __global__ __launch_bounds__(WAVE * AV_W) void k_apply_valu(ApplyArgs a, Queue *
     }
 }
 
-hipError_t launch_apply(const ApplyArgs &a, int use_mfma, Queue *q, int grid, hipStream_t s) {
-    if (a.ntiles <= 0) return hipSuccess;
+hipError_t launch_apply(const ApplyArgs &a0, int use_mfma, Queue *q, int grid, hipStream_t s) {
+    if (a0.ntiles <= 0) return hipSuccess;
+    ApplyArgs a = a0;
+    a.work = trace_work(use_mfma ? KID_APPLY_MFMA : KID_APPLY_VALU);
     const dim3 g(q ? grid : a.ntiles);
     if (use_mfma) {
         // the pass width: 16, 32 or 64 columns, the smallest that covers m (64 beyond)

@@ -229,6 +229,7 @@ struct superdc_batch {
     TileList lists[4];                  // cut lengths 64, 128, 256, 512
     // chosen launch shapes (heuristic, or set by the autotuner): persistent launches
     LaunchShape sec, vec, app, bwd;
+    int fmm_ssplit = 0;                 // FMM solver: wavefronts per work item (0: heuristic)
     bool tuned = false;
     // triangular-FMM layout (built on the first FMM solve; see fmm.h)
     sdc::FmmPlan *fmm = nullptr;
@@ -237,6 +238,14 @@ struct superdc_batch {
 namespace sdc {
 // the tile list of a given cut length (64, 128, 256 or 512), built on first use
 const TileList *tile_list(superdc_batch *b, int chunk);
+// SUPERDC_OK or SUPERDC_EINVAL for an options struct
+int opts_check(const superdc_opts *o);
+// grid of a persistent launch: per_cu workgroups per CU, at most one per work item
+int persistent_grid(const superdc_ctx *ctx, int ntiles, int per_cu);
+// problems of at least this many roots use the triangular FMM under these options
+int fmm_crossover_of(const superdc_ctx *ctx, const superdc_opts &o);
+// launch shape of the plain (one launch per problem) direct solve of an n-root problem
+::LaunchShape plain_shape(const superdc_ctx *ctx, int64_t n);
 }  // namespace sdc
 
 namespace sdc {
@@ -310,6 +319,8 @@ struct ApplyArgs {
     int64_t ldy;
     int fuse_b;    // trans 1, MFMA, m < 16: form b with the kernel 1/t^2 on the weights
     double *bout;  // zhat^2 beside the m columns, write it here and scale by it
+    unsigned long long *work;  // kernel timing on: algorithmic flops of the launch, (2m + 3)
+                               // per Cauchy entry plus 2m per output row (set by launch_apply)
 };
 hipError_t launch_apply(const ApplyArgs &a, int use_mfma, Queue *q, int grid, hipStream_t s);
 

@@ -106,6 +106,9 @@ struct FmmVec {
                               // the evaluation forms b from it with the kernel 1/t^2, writes
                               // it to bout and scales the other m - 1 columns by it
     const double *zh;         // fuse_b: zhat, for b's near terms (zhat / t)^2
+    unsigned long long *work; // kernel timing on: algorithmic flops of the launch (set by
+                              // launch_fmmv_eval): (2m + 3) per near pole or far source of a
+                              // root for kern 1, 6 for kern 2, plus the output scaling
 };
 constexpr int FMMV_MAX_M = 16;
 

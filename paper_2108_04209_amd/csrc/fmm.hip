@@ -317,7 +317,7 @@ __global__ __launch_bounds__(FMM_P * LOC_PARTS) void k_fmm_local(FmmArgs f) {
                 const double R = rcp_nr(t0 * t1);
                 const double u0 = a.y * t1, u1 = b.y * t0;
                 s0 = __builtin_fma(u0 + u1, R, s0);
-                s1 = __builtin_fma(__builtin_fma(u0, t1, u1 * t0), R * R, s1);
+                s1 = __builtin_fma(__builtin_fma(u0, t1, u1 * t0) * R, R, s1);
             } else {  // the product would leave the exponent range: one source at a time
                 const double r0 = rcp_nr(t0), r1 = rcp_nr(t1);
                 s0 += a.y * r0 + b.y * r1;

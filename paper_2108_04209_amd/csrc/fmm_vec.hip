@@ -219,8 +219,10 @@ __device__ void fmmv_item(const SolveArgs &it, const FmmArgs &f, const FmmVec &v
     double acc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+    int64_t ent = 0;  // pole or source entries this wavefront sums per root (kernel timing)
     // one near range [lo, hi) of poles, shifted form, two Newton steps
     auto near = [&](int lo, int hi) {
+        ent += hi > lo ? hi - lo : 0;
         for (int i = lo; i < hi; ++i) {
             const double r = rcp_nr((dd[i] - dK) - eta);
             if (KERN == 1) {
@@ -248,6 +250,7 @@ __device__ void fmmv_item(const SolveArgs &it, const FmmArgs &f, const FmmVec &v
                                               : f.far_r[(int64_t)L * FMM_FAR_MAX + e - nl]);
             const const_double_ptr nd = as_const(v.vnode + (int64_t)g * FMM_P);
             const const_double_ptr ww = as_const(v.vw + (int64_t)g * FMM_P * m);
+            ent += FMM_P;
 #pragma unroll 4
             for (int q = 0; q < FMM_P; ++q) {
                 const double r = rcp_nr1(nd[q] - x);
@@ -260,6 +263,12 @@ __device__ void fmmv_item(const SolveArgs &it, const FmmArgs &f, const FmmVec &v
                 }
             }
         }
+    }
+    if (v.work && lane == 0) {  // kernel timing: algorithmic flops of this wavefront's share
+        const unsigned long long rows = (unsigned long long)__popcll(__ballot(active));
+        const unsigned long long per = KERN == 1 ? 2 * (unsigned long long)m + 3 : 6;
+        atomicAdd(v.work, rows * (unsigned long long)ent * per +
+                              (wv == 0 && KERN == 1 ? rows * (unsigned long long)m : 0));
     }
     if (S > 1) {
         if (wv > 0)
@@ -433,6 +442,7 @@ __device__ void fmmv_item_mfma(const SolveArgs &it, const FmmArgs &f, const FmmV
     FvStage st;
     int4 cur = chunk(0);
     fv_fetch(v, base, sh.fbox, cur, st);
+    int64_t ent = 0;  // near poles and far sources summed per root (kernel timing)
     for (int ci = 0; ci < nch; ++ci) {
         __syncthreads();  // the previous chunk's reads of Xs/Sd are done
         if (threadIdx.x < FV_K) sh.Sd[threadIdx.x] = st.sd;
@@ -444,6 +454,7 @@ __device__ void fmmv_item_mfma(const SolveArgs &it, const FmmArgs &f, const FmmV
         __syncthreads();
         const int nvalid = wave_uniform(cur.x == 0 ? cur.z : cur.z * FMM_P);
         const bool cur_near = cur.x == 0;
+        ent += nvalid;
         if (ci + 1 < nch) {
             cur = chunk(ci + 1);
             fv_fetch(v, base, sh.fbox, cur, st);  // in flight during the multiply below
@@ -469,6 +480,11 @@ __device__ void fmmv_item_mfma(const SolveArgs &it, const FmmArgs &f, const FmmV
     if (fb) {  // the four lanes of a Cauchy row (lane % 16) hold its partial sums
         bsum += __shfl_xor(bsum, 16);
         bsum += __shfl_xor(bsum, 32);
+    }
+    if (v.work && threadIdx.x == 0) {  // kernel timing: the item's algorithmic flops
+        const unsigned long long rows = (unsigned long long)min(FV_K, n - o0);
+        atomicAdd(v.work, rows * (unsigned long long)ent * (2 * (unsigned long long)m + 3) +
+                              2 * rows * (unsigned long long)mo);
     }
     // v_mfma_f64_16x16x4f64 returns D[4 r + lane/16][lane % 16] in accumulator r
 #pragma unroll
@@ -631,10 +647,13 @@ hipError_t launch_fmmv_sources(const FmmArgs &f, const FmmVec &v, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_fmmv_eval(const SolveArgs &it, const FmmArgs &f, const FmmVec &v, int split,
+hipError_t launch_fmmv_eval(const SolveArgs &it, const FmmArgs &f, const FmmVec &v0, int split,
                             Queue *q, int num_cu, hipStream_t s) {
     if (it.ntiles <= 0) return hipSuccess;
-    if (v.kern == 1 && (v.m >= 4 || v.fuse_b)) {  // a dense enough block of columns for the MFMA
+    FmmVec v = v0;
+    const bool mfma = v.kern == 1 && (v.m >= 4 || v.fuse_b);
+    v.work = trace_work(mfma ? KID_FMMV_EVAL_MFMA : KID_FMMV_EVAL);
+    if (mfma) {  // a dense enough block of columns for the MFMA
         const dim3 g(q ? min(it.ntiles, num_cu * 4) : it.ntiles);
         SDC_LAUNCH(KID_FMMV_EVAL_MFMA, k_fmmv_eval_mfma, g, dim3(256), 0, s, it, f, v, q);
         return hipGetLastError();

@@ -64,6 +64,7 @@ struct superdc_hss {
     int64_t xcap = 0;
     int64_t tcap = 0;
     bool ready = false;
+    bool tune = false;  // the next conquer tunes every level's batch before its first solve
     // optional phase timing: events recorded between phases of the last conquer
     bool timing = false;
     std::vector<hipEvent_t> ev;
@@ -415,6 +416,10 @@ int superdc_hss_conquer(superdc_ctx *ctx, superdc_hss *h, const double *leaf_D,
             }
             const double *poles = h->poles(l, t);
             const double *zc = h->M[cur] + (size_t)t * n;
+            if (h->tune && t == 0) {  // launch shapes of this level, on its own first problem
+                const int rc = superdc_autotune(ctx, b, poles, zc, h->ones, &o, stream);
+                if (rc) return rc;
+            }
             double *lam_t = h->lam + h->idx(l, t);
             double *eta_t = h->eta + h->idx(l, t);
             int32_t *org_t = h->org + h->idx(l, t);
@@ -463,6 +468,35 @@ int superdc_hss_conquer(superdc_ctx *ctx, superdc_hss *h, const double *leaf_D,
     if ((e = mark(h, 5, s)) != hipSuccess) return fail(e);
     h->ready = true;
     return SUPERDC_OK;
+}
+
+int superdc_hss_autotune(superdc_ctx *ctx, superdc_hss *h, const double *leaf_D,
+                         const double *leaf_U, const double *R, const double *B,
+                         const double *beta, const superdc_opts *opts, void *stream) {
+    if (!ctx || !h || h->ctx != ctx || !leaf_D || !leaf_U || !R || !B || !beta)
+        return SUPERDC_EINVAL;
+    if (opts && opts->hss_tau != 0.0) return SUPERDC_EINVAL;  // deflated batches vary per pass
+    double *lam = nullptr;
+    int32_t *st = nullptr;
+    hipError_t e = hipMalloc(&lam, sizeof(double) * (size_t)h->n);
+    if (e == hipSuccess) e = hipMalloc(&st, sizeof(int32_t));
+    int rc = e == hipSuccess ? SUPERDC_OK : fail(e);
+    if (rc == SUPERDC_OK) {
+        h->tune = true;
+        rc = superdc_hss_conquer(ctx, h, leaf_D, leaf_U, R, B, beta, lam, nullptr, st, opts,
+                                 stream);
+        h->tune = false;
+        e = hipStreamSynchronize((hipStream_t)stream);
+        if (rc == SUPERDC_OK && e != hipSuccess) rc = fail(e);
+    }
+    if (lam) (void)hipFree(lam);
+    if (st) (void)hipFree(st);
+    return rc;
+}
+
+int superdc_hss_batch_shapes(const superdc_hss *h, int32_t level, int32_t *out) {
+    if (!h || !out || level < 0 || level >= h->depth) return SUPERDC_EINVAL;
+    return superdc_batch_shapes(h->batch[level], out);
 }
 
 int superdc_hss_iterations(superdc_hss *h, int32_t *dst, void *stream) {

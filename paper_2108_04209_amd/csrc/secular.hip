@@ -97,11 +97,14 @@ __global__ __launch_bounds__(1024) void k_validate(SolveArgs a, int prob_first) 
 // ---------------------------------------------------------------------------------------
 // the secular sums over a pole range [j0, j1): MODE 0 all psi, 1 all phi, 2 split at k
 // ---------------------------------------------------------------------------------------
-// FAR: the pole is more than one tile away from every root of the wavefront.  Following
-// the paper's local shifting (Sec. 4.2.2), such pairs use lambda directly, d_j - x with
-// x = d_K + y, which is accurate there (eq. farfield), and a reciprocal with one Newton
-// step (<= 11 ulp, measured); near pairs keep the shifted form (d_j - d_K) - y (eq.
-// localshift) and a reciprocal refined twice.
+// LF: the pole difference is formed in lambda-form, d_j - x with x = d_K + y; otherwise in
+// the shifted form (d_j - d_K) - y (eq. localshift).  P1: the reciprocal gets one Newton
+// step (<= 11 ulp, measured) instead of two.  Following the paper's local shifting (Sec.
+// 4.2.2), a pole more than one tile away from every root of the wavefront (far) takes
+// lambda-form and P1, which is accurate there (eq. farfield); near poles keep the shifted
+// form and two steps.  The ablation without local shifting takes lambda-form for the near
+// poles too but keeps their two Newton steps, so it differs from the default in the form
+// of the differences alone.
 //
 // Outside the window (where every pole of a range lies on one side of every root), poles
 // are taken two at a time with one shared reciprocal (the FP64 reciprocal issues at a
@@ -109,10 +112,12 @@ __global__ __launch_bounds__(1024) void k_validate(SolveArgs a, int prob_first) 
 // ones in the shifted form with two:
 //   w0/t0 + w1/t1       = (w0 t1 + w1 t0) / (t0 t1)
 //   w0/t0^2 + w1/t1^2   = (w0 t1 t1 + w1 t0 t0) / (t0 t1)^2
-// t0 and t1 have the same sign, so neither numerator cancels.  The products need every
-// |t| of the range inside [2^-300, 2^300]; a range outside that (checked once per range
-// for the whole wavefront) takes one reciprocal per pole.
-template <int MODE, bool FAR>
+// t0 and t1 have the same sign, so neither numerator cancels.  The square of the shared
+// reciprocal is applied as (num2 R) R, so no intermediate leaves the exponent range when
+// t0 t1 does not.  The products need every |t| of the range inside [2^-300, 2^300]; a range
+// outside that (checked once per range for the whole wavefront) takes one reciprocal per
+// pole.
+template <int MODE, bool LF, bool P1>
 __device__ __forceinline__ void secular_range(const_double2_ptr dw, int j0, int j1,
                                               int k, double dK, double y, double x,
                                               double &psi, double &dpsi, double &phi,
@@ -120,7 +125,8 @@ __device__ __forceinline__ void secular_range(const_double2_ptr dw, int j0, int 
 #define SDC_SEC_BODY(JJ, PW)                                          \
     {                                                                 \
         const double2 pw = (PW);                                      \
-        const double r = FAR ? rcp_nr1(pw.x - x) : rcp_nr((pw.x - dK) - y); \
+        const double tt = LF ? pw.x - x : (pw.x - dK) - y;            \
+        const double r = P1 ? rcp_nr1(tt) : rcp_nr(tt);               \
         const double wr = pw.y * r;                                   \
         if (MODE == 0) {                                              \
             psi += wr;                                                \
@@ -141,17 +147,17 @@ __device__ __forceinline__ void secular_range(const_double2_ptr dw, int j0, int 
 #define SDC_SEC_PAIR(PA, PB)                                          \
     {                                                                 \
         const double2 pa = (PA), pb = (PB);                           \
-        const double t0 = FAR ? pa.x - x : (pa.x - dK) - y;           \
-        const double t1 = FAR ? pb.x - x : (pb.x - dK) - y;           \
-        const double R = FAR ? rcp_nr1(t0 * t1) : rcp_nr(t0 * t1);    \
+        const double t0 = LF ? pa.x - x : (pa.x - dK) - y;            \
+        const double t1 = LF ? pb.x - x : (pb.x - dK) - y;            \
+        const double R = P1 ? rcp_nr1(t0 * t1) : rcp_nr(t0 * t1);     \
         const double u0 = pa.y * t1, u1 = pb.y * t0;                  \
         const double num2 = __builtin_fma(u0, t1, u1 * t0);           \
         if (MODE == 0) {                                              \
             psi = __builtin_fma(u0 + u1, R, psi);                     \
-            dpsi = __builtin_fma(num2, R * R, dpsi);                  \
+            dpsi = __builtin_fma(num2 * R, R, dpsi);                  \
         } else {                                                      \
             phi = __builtin_fma(u0 + u1, R, phi);                     \
-            dphi = __builtin_fma(num2, R * R, dphi);                  \
+            dphi = __builtin_fma(num2 * R, R, dphi);                  \
         }                                                             \
     }
     // Poles come in blocks of 4 (one 64-byte scalar fetch).  Two register sets A and B
@@ -168,8 +174,8 @@ __device__ __forceinline__ void secular_range(const_double2_ptr dw, int j0, int 
         // the nearest and farthest pole of the range bound every |t|
         const double dn = MODE == 0 ? dw[j1 - 1].x : dw[j0].x;
         const double df = MODE == 0 ? dw[j0].x : dw[j1 - 1].x;
-        const double tn = fabs(FAR ? dn - x : (dn - dK) - y);
-        const double tf = fabs(FAR ? df - x : (df - dK) - y);
+        const double tn = fabs(LF ? dn - x : (dn - dK) - y);
+        const double tf = fabs(LF ? df - x : (df - dK) - y);
         const bool ok = tn >= 0x1p-300 && tf <= 0x1p300;
         if (__ballot(!ok) == 0ull) {
             double2 a0, a1, a2, a3, b0, b1, b2, b3;
@@ -267,17 +273,23 @@ __device__ __forceinline__ void secular_sums(const double2 *__restrict__ dwg, in
     p1 = wave_uniform(p1);
     psi = dpsi = phi = dphi = 0.0;
     const double x = dK + y;
-    // unshifted (ablation): every pole in lambda-form, none shifted
-    const int f0 = unsh ? kmin : max(kmin - TILE, 0), f1 = unsh ? kmax + 1 : min(kmax + 1 + TILE, n);
+    const int f0 = max(kmin - TILE, 0), f1 = min(kmax + 1 + TILE, n);
 #define SDC_CLIP(A, B) max((A), p0), min((B), p1)
-    secular_range<0, true>(dw, SDC_CLIP(0, f0), k, dK, y, x, psi, dpsi, phi, dphi);
-    secular_range<0, false>(dw, SDC_CLIP(f0, kmin), k, dK, y, x, psi, dpsi, phi, dphi);
-    if (unsh)
-        secular_range<2, true>(dw, SDC_CLIP(kmin, kmax + 1), k, dK, y, x, psi, dpsi, phi, dphi);
-    else
-        secular_range<2, false>(dw, SDC_CLIP(kmin, kmax + 1), k, dK, y, x, psi, dpsi, phi, dphi);
-    secular_range<1, false>(dw, SDC_CLIP(kmax + 1, f1), k, dK, y, x, psi, dpsi, phi, dphi);
-    secular_range<1, true>(dw, SDC_CLIP(f1, n), k, dK, y, x, psi, dpsi, phi, dphi);
+    secular_range<0, true, true>(dw, SDC_CLIP(0, f0), k, dK, y, x, psi, dpsi, phi, dphi);
+    if (unsh) {  // ablation: near poles and the window in lambda-form as well
+        secular_range<0, true, false>(dw, SDC_CLIP(f0, kmin), k, dK, y, x, psi, dpsi, phi, dphi);
+        secular_range<2, true, false>(dw, SDC_CLIP(kmin, kmax + 1), k, dK, y, x, psi, dpsi, phi,
+                                      dphi);
+        secular_range<1, true, false>(dw, SDC_CLIP(kmax + 1, f1), k, dK, y, x, psi, dpsi, phi,
+                                      dphi);
+    } else {
+        secular_range<0, false, false>(dw, SDC_CLIP(f0, kmin), k, dK, y, x, psi, dpsi, phi, dphi);
+        secular_range<2, false, false>(dw, SDC_CLIP(kmin, kmax + 1), k, dK, y, x, psi, dpsi, phi,
+                                       dphi);
+        secular_range<1, false, false>(dw, SDC_CLIP(kmax + 1, f1), k, dK, y, x, psi, dpsi, phi,
+                                       dphi);
+    }
+    secular_range<1, true, true>(dw, SDC_CLIP(f1, n), k, dK, y, x, psi, dpsi, phi, dphi);
 #undef SDC_CLIP
 }
 
@@ -322,33 +334,39 @@ __device__ __forceinline__ void fmm_sums(const FmmArgs &f, int L, int nn, int nl
     const double x = dK + y;
     // near leaves: the same window split as the direct sums, so only poles within one tile
     // of the live roots take the shifted form
-    const int f0 = unsh ? kmin : kmin - TILE, f1 = unsh ? kmax + 1 : kmax + 1 + TILE;
+    const int f0 = kmin - TILE, f1 = kmax + 1 + TILE;
     for (int e = 0; e < nn; ++e) {
         const int lo0 = wave_uniform(f.near_lo[(int64_t)L * FMM_NEAR_MAX + e]);
         const int hi0 = wave_uniform(f.near_hi[(int64_t)L * FMM_NEAR_MAX + e]);
         const int lo = lo0 + (int)(((int64_t)(hi0 - lo0) * wv) / S);
         const int hi = lo0 + (int)(((int64_t)(hi0 - lo0) * (wv + 1)) / S);
-        secular_range<0, true>(dw, lo, min(hi, f0), k, dK, y, x, psi, dpsi, phi, dphi);
-        secular_range<0, false>(dw, max(lo, f0), min(hi, kmin), k, dK, y, x, psi, dpsi, phi, dphi);
-        if (unsh)
-            secular_range<2, true>(dw, max(lo, kmin), min(hi, kmax + 1), k, dK, y, x, psi, dpsi,
-                                   phi, dphi);
-        else
-            secular_range<2, false>(dw, max(lo, kmin), min(hi, kmax + 1), k, dK, y, x, psi, dpsi,
-                                    phi, dphi);
-        secular_range<1, false>(dw, max(lo, kmax + 1), min(hi, f1), k, dK, y, x, psi, dpsi, phi,
-                                dphi);
-        secular_range<1, true>(dw, max(lo, f1), hi, k, dK, y, x, psi, dpsi, phi, dphi);
+        secular_range<0, true, true>(dw, lo, min(hi, f0), k, dK, y, x, psi, dpsi, phi, dphi);
+        if (unsh) {  // ablation: near poles and the window in lambda-form as well
+            secular_range<0, true, false>(dw, max(lo, f0), min(hi, kmin), k, dK, y, x, psi, dpsi,
+                                          phi, dphi);
+            secular_range<2, true, false>(dw, max(lo, kmin), min(hi, kmax + 1), k, dK, y, x, psi,
+                                          dpsi, phi, dphi);
+            secular_range<1, true, false>(dw, max(lo, kmax + 1), min(hi, f1), k, dK, y, x, psi,
+                                          dpsi, phi, dphi);
+        } else {
+            secular_range<0, false, false>(dw, max(lo, f0), min(hi, kmin), k, dK, y, x, psi, dpsi,
+                                           phi, dphi);
+            secular_range<2, false, false>(dw, max(lo, kmin), min(hi, kmax + 1), k, dK, y, x, psi,
+                                           dpsi, phi, dphi);
+            secular_range<1, false, false>(dw, max(lo, kmax + 1), min(hi, f1), k, dK, y, x, psi,
+                                           dpsi, phi, dphi);
+        }
+        secular_range<1, true, true>(dw, max(lo, f1), hi, k, dK, y, x, psi, dpsi, phi, dphi);
     }
     // far boxes outside the leaf's local expansion, through their equivalent sources
     for (int e = wv; e < nl; e += S) {
         const int g = wave_uniform(f.far_ld[(int64_t)L * FMM_FAR_MAX + e]);
-        secular_range<0, true>(as_const(f.eq + (int64_t)g * FMM_P), 0, FMM_P, k, dK, y, x, psi,
+        secular_range<0, true, true>(as_const(f.eq + (int64_t)g * FMM_P), 0, FMM_P, k, dK, y, x, psi,
                                dpsi, phi, dphi);
     }
     for (int e = wv; e < nr; e += S) {
         const int g = wave_uniform(f.far_rd[(int64_t)L * FMM_FAR_MAX + e]);
-        secular_range<1, true>(as_const(f.eq + (int64_t)g * FMM_P), 0, FMM_P, k, dK, y, x, psi,
+        secular_range<1, true, true>(as_const(f.eq + (int64_t)g * FMM_P), 0, FMM_P, k, dK, y, x, psi,
                                dpsi, phi, dphi);
     }
     // the others through the leaf's local expansion: four Chebyshev series on the target
@@ -452,6 +470,7 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
     bool fw = false;     // hybrid: the fixed-weight scheme takes the next step
     double fprev = 0.0;  // hybrid: f at the previous iterate
     int k = c0, K = c0, nev = 0, phase = 0;
+    int why = 0;  // how the root stopped: 0 the stopping test, SUPERDC_ITER_* otherwise
     double dk = 0.0, dk1 = 0.0, dK = 0.0, y = 0.0, lo = 0.0, hi = 0.0;
     for (;;) {
         // refill idle lanes with the next roots of the chunk, in order
@@ -470,6 +489,7 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
             if (unsh) y = (dK + y) - dK;
             phase = 0;
             nev = 0;
+            why = 0;
             hi_closed = false;
             fw = false;
         }
@@ -525,6 +545,7 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
         if (!done && nev >= a.max_iter) {
             done = true;
             noconv = true;
+            why = SUPERDC_ITER_CAP;
         }
         if (a.hybrid && phase == 1 && nev > 0) {
             // hybrid [li93]: a step that kept f's sign and did not cut |f| tenfold hands the
@@ -572,8 +593,10 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
             // a step below rounding, or a collapsed bracket: accept without re-evaluation
             if (unsh) yn = (dK + yn) - dK;  // lambda = d_K + y rounded, as the iterate itself
             if (fabs(yn - y) <= 2.0 * eps * fabs(yn) ||
-                hi - lo <= 2.0 * eps * fmax(fabs(lo), fabs(hi)))
+                hi - lo <= 2.0 * eps * fmax(fabs(lo), fabs(hi))) {
                 done = true;
+                why = SUPERDC_ITER_UNMET;
+            }
             y = yn;
         }
         if (done) {
@@ -581,7 +604,7 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
                 a.eta[base + k] = y;
                 a.lam[base + k] = dK + y;
                 a.origin[base + k] = K;
-                if (a.iters) a.iters[base + k] = nev;
+                if (a.iters) a.iters[base + k] = nev | why;
                 a.ke[base + k] = make_double2(dK, y);
             }
             act = false;

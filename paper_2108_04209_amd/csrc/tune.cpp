@@ -1,7 +1,8 @@
 // tune.cpp -- autotuner for the launch shapes of a batch.
 //
 // For the secular solver the candidates are the chunk length (64..512 roots per work
-// item) times the split (1..16 wavefronts per item sharing the pole range); for the
+// item) times the split (1..16 wavefronts per item sharing the pole range), and for the
+// problems that use the triangular FMM the split of its work items (1..8); for the
 // Loewner/b and adjoint kernels the split.  Each candidate is run on the caller's data
 // and timed with HIP events on the caller's stream; the fastest is kept in the batch.
 // Results can be kept across processes in a text cache (environment variable
@@ -34,20 +35,25 @@ uint64_t signature(const superdc_batch *b, int num_cu) {
     return h;
 }
 
+// one line per batch: "<key> <chunk> <split> <loewner split> <adjoint split> <fmm split>"
+// (fmm split 0: the heuristic); lines in any other form are skipped
 bool cache_load(superdc_batch *b, uint64_t key) {
     const char *path = std::getenv("SUPERDC_TUNE_CACHE");
     if (!path) return false;
     FILE *f = std::fopen(path, "r");
     if (!f) return false;
-    unsigned long long k;
-    int sc, ss, vs, bs;
+    char line[256];
     bool found = false;
-    while (std::fscanf(f, "%llx %d %d %d %d", &k, &sc, &ss, &vs, &bs) == 5) {
+    while (std::fgets(line, sizeof line, f)) {
+        unsigned long long k;
+        int sc, ss, vs, bs, fs;
+        if (std::sscanf(line, "%llx %d %d %d %d %d", &k, &sc, &ss, &vs, &bs, &fs) != 6) continue;
         if (k == key && sc >= 64 && sc <= 512 && ss >= 1 && ss <= 16 && vs >= 1 && vs <= 16 &&
-            bs >= 1 && bs <= 16) {
+            bs >= 1 && bs <= 16 && fs >= 0 && fs <= 8) {
             b->sec = LaunchShape{sc, ss};
             b->vec = LaunchShape{TILE, vs};
             b->bwd = LaunchShape{TILE, bs};
+            b->fmm_ssplit = fs;
             found = true;
         }
     }
@@ -60,8 +66,8 @@ void cache_store(const superdc_batch *b, uint64_t key) {
     if (!path) return;
     FILE *f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%llx %d %d %d %d\n", (unsigned long long)key, b->sec.chunk, b->sec.split,
-                 b->vec.split, b->bwd.split);
+    std::fprintf(f, "%llx %d %d %d %d %d\n", (unsigned long long)key, b->sec.chunk, b->sec.split,
+                 b->vec.split, b->bwd.split, b->fmm_ssplit);
     std::fclose(f);
 }
 
@@ -145,6 +151,24 @@ int superdc_autotune(superdc_ctx *ctx, superdc_batch *b, const double *d, const 
             }
         }
         b->sec = bs;
+        // the FMM solver's split, when some problem of the batch uses the FMM
+        if (b->max_n >= fmm_crossover_of(ctx, o)) {
+            float bestf = 1e30f;
+            int bf = 0;
+            for (int S = 1; S <= 8; S *= 2) {
+                b->fmm_ssplit = S;
+                bool ok = true;
+                const float t = time_best([&] {
+                    return superdc_secular_solve(ctx, b, d, z, rho, lam, eta, org, nullptr, st,
+                                                 &o, stream);
+                }, s, reps, ok);
+                if (ok && t < bestf) {
+                    bestf = t;
+                    bf = S;
+                }
+            }
+            b->fmm_ssplit = bf;
+        }
         // the solution the other phases are tuned on
         rc = superdc_secular_solve(ctx, b, d, z, rho, lam, eta, org, nullptr, st, &o, stream);
     }
@@ -198,6 +222,7 @@ int superdc_batch_shapes(const superdc_batch *b, int32_t *out) {
     out[1] = b->sec.split;
     out[2] = b->vec.split;
     out[3] = b->bwd.split;
+    out[4] = b->fmm_ssplit;
     return SUPERDC_OK;
 }
 

@@ -10,7 +10,13 @@
 // one pole as separate running products (two interleaved chains each) and strips their
 // binary exponents every 8 factors per chain (frexp), accumulating the exponents in an
 // integer; one division and one ldexp finish the pole.  No logarithms, and the 8-factor
-// blocks cannot over- or underflow for factors between 2^-120 and 2^120.
+// blocks cannot over- or underflow for factors between 2^-120 and 2^120.  Both products are
+// homogeneous in the scale of the problem (n factors over n - 1), so a problem whose span
+// s = d_{n-1} - d_0 + eta_{n-1} lies outside [2^-32, 2^32] has every factor multiplied by
+// 2^-e (e the binary exponent of s, an exact scaling) and e added back at the end: the
+// factors are then at most 2 in magnitude, and the result is the same, bit for bit, as for
+// the problem scaled into range.  Factors below 2^-120 s (relative gaps or eta_k below
+// about 7.5e-37 of the span) can still underflow a block.
 #include "common.h"
 #include "fmm.h"
 
@@ -39,11 +45,13 @@ __device__ __forceinline__ void renorm(double &num, double &den, int &E) {
 // on each other; roots are read in pointer-stepped blocks of 4 (one scalar address add per
 // block); each chain strips its exponents after every 8 factors.  The latency of the
 // scalar loads is covered by the other wavefronts of the SIMD.
-template <bool SKIP>
+// SC: every factor is multiplied by sg (a power of two) before it enters its product.
+template <bool SKIP, bool SC>
 __device__ __forceinline__ void loewner_range(const_double2_ptr ke, const_double_ptr dd,
                                               int j0, int j1,
                                               int i, double di, double &num, double &den,
-                                              int &E) {
+                                              int &E, double sg) {
+#define SDC_SCL(F) (SC ? (F) * sg : (F))
     double na = 1.0, da = 1.0, nb = 1.0, db = 1.0;
     int j = j0;
     if (j + 4 <= j1) {
@@ -51,11 +59,12 @@ __device__ __forceinline__ void loewner_range(const_double2_ptr ke, const_double
         const_double_ptr dp = dd + j;
         int blk = 0;
         for (; j + 4 <= j1; j += 4, kp += 8, dp += 4) {
-            na *= (kp[0] - di) + kp[1];
-            nb *= (kp[2] - di) + kp[3];
-            na *= (kp[4] - di) + kp[5];
-            nb *= (kp[6] - di) + kp[7];
-            const double f0 = dp[0] - di, f1 = dp[1] - di, f2 = dp[2] - di, f3 = dp[3] - di;
+            na *= SDC_SCL((kp[0] - di) + kp[1]);
+            nb *= SDC_SCL((kp[2] - di) + kp[3]);
+            na *= SDC_SCL((kp[4] - di) + kp[5]);
+            nb *= SDC_SCL((kp[6] - di) + kp[7]);
+            const double f0 = SDC_SCL(dp[0] - di), f1 = SDC_SCL(dp[1] - di);
+            const double f2 = SDC_SCL(dp[2] - di), f3 = SDC_SCL(dp[3] - di);
             da *= (SKIP && j == i) ? 1.0 : f0;
             db *= (SKIP && j + 1 == i) ? 1.0 : f1;
             da *= (SKIP && j + 2 == i) ? 1.0 : f2;
@@ -71,12 +80,22 @@ __device__ __forceinline__ void loewner_range(const_double2_ptr ke, const_double
     renorm(nb, db, E);
     for (; j < j1; ++j) {  // at most 3 more factors per chain after the strip above
         const double2 kv = ke[j];
-        na *= (kv.x - di) + kv.y;
-        da *= (SKIP && j == i) ? 1.0 : dd[j] - di;
+        na *= SDC_SCL((kv.x - di) + kv.y);
+        da *= (SKIP && j == i) ? 1.0 : SDC_SCL(dd[j] - di);
     }
     num *= na * nb;  // mantissas in [0.5, 1) times at most 3 factors: no over- or underflow
     den *= da * db;
     renorm(num, den, E);
+#undef SDC_SCL
+}
+
+// The binary exponent e used to scale a problem's factors (0 when its span is in range):
+// the span of poles and roots, d_{n-1} - d_0 + eta_{n-1}, read from the packed pairs.
+__device__ __forceinline__ int loewner_scale(const_double2_ptr ke, const_double_ptr dd, int n) {
+    const double2 kl = ke[n - 1];
+    const double span = (kl.x - dd[0]) + kl.y;
+    const int e = __builtin_amdgcn_frexp_exp(span);
+    return (e < -32 || e > 32) ? e : 0;
 }
 
 // With S = blockDim.x / 64 > 1 wavefronts per tile, wavefront w takes the roots
@@ -111,9 +130,18 @@ __device__ void loewner_tile(const VecArgs &a, Tile t, double4 *red) {
     int p0, p1;
     split_range(n, p0, p1);
     const int t1 = wave_uniform(min(t.row0 + TILE, n));
-    loewner_range<false>(ke, dd, p0, min(t.row0, p1), ii, di, num, den, E);
-    loewner_range<true>(ke, dd, max(t.row0, p0), min(t1, p1), ii, di, num, den, E);
-    loewner_range<false>(ke, dd, max(t1, p0), p1, ii, di, num, den, E);
+    const int es = wave_uniform(loewner_scale(ke, dd, n));
+    if (es == 0) {
+        loewner_range<false, false>(ke, dd, p0, min(t.row0, p1), ii, di, num, den, E, 1.0);
+        loewner_range<true, false>(ke, dd, max(t.row0, p0), min(t1, p1), ii, di, num, den, E, 1.0);
+        loewner_range<false, false>(ke, dd, max(t1, p0), p1, ii, di, num, den, E, 1.0);
+    } else {  // every factor scaled by 2^-es; the ratio gains 2^-es, added back below
+        const double sg = __builtin_ldexp(1.0, -es);
+        loewner_range<false, true>(ke, dd, p0, min(t.row0, p1), ii, di, num, den, E, sg);
+        loewner_range<true, true>(ke, dd, max(t.row0, p0), min(t1, p1), ii, di, num, den, E, sg);
+        loewner_range<false, true>(ke, dd, max(t1, p0), p1, ii, di, num, den, E, sg);
+        if (wv == 0) E += es;
+    }
     if (S > 1) {
         red[wv * WAVE + lane_id()] = make_double4(num, den, (double)E, 0.0);
         __syncthreads();
@@ -182,11 +210,20 @@ __device__ void loewner_fmm_tile(const VecArgs &a, const FmmArgs &f, const FmmlA
     const int L = wave_uniform(f.leaf_off[qf] + t.row0 / f.leaf);
     const int nn = wave_uniform(f.cnt[3 * (int64_t)L]);
     const int t0 = t.row0, t1 = wave_uniform(min(t.row0 + TILE, n));
-    // exact products over [lo, hi), the poles of this item dropping their own factor
+    // exact products over [lo, hi), the poles of this item dropping their own factor;
+    // a problem out of range has every factor scaled by sg = 2^-es (added back below)
+    const int es = wave_uniform(loewner_scale(ke, dd, n));
+    const double sg = __builtin_ldexp(1.0, -es);
     auto exact = [&](int lo, int hi) {
-        loewner_range<false>(ke, dd, lo, min(hi, t0), ii, di, num, den, E);
-        loewner_range<true>(ke, dd, max(lo, t0), min(hi, t1), ii, di, num, den, E);
-        loewner_range<false>(ke, dd, max(lo, t1), hi, ii, di, num, den, E);
+        if (es == 0) {
+            loewner_range<false, false>(ke, dd, lo, min(hi, t0), ii, di, num, den, E, 1.0);
+            loewner_range<true, false>(ke, dd, max(lo, t0), min(hi, t1), ii, di, num, den, E, 1.0);
+            loewner_range<false, false>(ke, dd, max(lo, t1), hi, ii, di, num, den, E, 1.0);
+        } else {
+            loewner_range<false, true>(ke, dd, lo, min(hi, t0), ii, di, num, den, E, sg);
+            loewner_range<true, true>(ke, dd, max(lo, t0), min(hi, t1), ii, di, num, den, E, sg);
+            loewner_range<false, true>(ke, dd, max(lo, t1), hi, ii, di, num, den, E, sg);
+        }
     };
     if (nn < 0) {
         exact(wave_uniform((int)(((int64_t)n * wv) / S)),
@@ -218,14 +255,15 @@ __device__ void loewner_fmm_tile(const VecArgs &a, const FmmArgs &f, const FmmlA
                 const int hi = (int)min((int64_t)n, (bi + 1) * span);
                 for (int j = lo; j < hi; ++j) {  // j != i: a far box never holds pole i
                     const double2 kv = ke[j];
-                    num *= (kv.x - di) + kv.y;
-                    den *= dd[j] - di;
+                    num *= ((kv.x - di) + kv.y) * sg;  // as many factors on both sides
+                    den *= (dd[j] - di) * sg;
                     if ((j & 7) == 7) renorm(num, den, E);
                 }
                 renorm(num, den, E);
             }
         }
     }
+    if (es != 0 && wv == 0) E += es;
     if (S > 1) {
         red[wv * WAVE + lane_id()] = make_double4(num, den, (double)E, far);
         __syncthreads();
@@ -267,7 +305,8 @@ __device__ void bnorm_tile(const VecArgs &a, Tile t, double4 *red) {
     split_range(n, p0, p1);
     // two poles share one reciprocal (the FP64 reciprocal issues at a quarter of the FMA
     // rate): zhat0^2/t0^2 + zhat1^2/t1^2 = ((zhat0 t1)^2 + (zhat1 t0)^2) / (t0 t1)^2, a sum
-    // of two squares over a square.  The products need every |t| inside [2^-240, 2^240];
+    // of two squares over a square, applied as (num R) R.  The products need every |t| inside
+    // [2^-300, 2^300] (the range the solver's shared reciprocals use);
     // the smallest |t| of a root is |eta| (its origin is its nearest pole) and the largest
     // is at an end of the pole range.  A wavefront with a root outside takes one
     // reciprocal per pole.
@@ -276,7 +315,7 @@ __device__ void bnorm_tile(const VecArgs &a, Tile t, double4 *red) {
     bool paired = false;
     if (p0 < p1) {
         const double tmax = fmax(fabs((dz[p0].x - kv.x) - kv.y), fabs((dz[p1 - 1].x - kv.x) - kv.y));
-        const bool ok = fabs(kv.y) >= 0x1p-240 && tmax <= 0x1p240;
+        const bool ok = fabs(kv.y) >= 0x1p-300 && tmax <= 0x1p300;
         paired = __ballot(!ok) == 0ull;
     }
     if (paired) {

@@ -15,6 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsuperdc.so")
 
 ST_UNSORTED, ST_ZERO, ST_NONFINITE, ST_RHO, ST_NOCONV = 1, 2, 4, 8, 16
+# iteration records: count in the low 16 bits, how the iteration ended above them
+ITER_COUNT_MASK, ITER_UNMET, ITER_CAP = 0xFFFF, 1 << 16, 1 << 17
 ERRORS = {0: "success", -1: "invalid argument", -2: "device allocation failed",
           -3: "HIP runtime error", -4: "no gfx950 device"}
 
@@ -343,10 +345,11 @@ def kernel_work():
 
 
 def batch_shapes(batch):
-    """superdc_batch_shapes: dict(sec_chunk, sec_split, vec_split, bwd_split)."""
-    out = (C.c_int32 * 4)()
+    """superdc_batch_shapes: dict(sec_chunk, sec_split, vec_split, bwd_split, fmm_split)."""
+    out = (C.c_int32 * 5)()
     _check(load_library().superdc_batch_shapes(batch.handle, out), "superdc_batch_shapes")
-    return dict(sec_chunk=out[0], sec_split=out[1], vec_split=out[2], bwd_split=out[3])
+    return dict(sec_chunk=out[0], sec_split=out[1], vec_split=out[2], bwd_split=out[3],
+                fmm_split=out[4])
 
 
 # ---------------------------------------------------------------------------------------
@@ -463,6 +466,28 @@ def hss_apply(ctx, plan, X, trans=0, opts=None, stream=None, Y=None):
                                             int(ldx), _ptr(Y), int(Y.shape[1]), C.byref(o),
                                             _stream(stream)), "superdc_hss_apply")
     return Y
+
+
+def hss_autotune(ctx, plan, gens, opts=None, stream=None):
+    """superdc_hss_autotune: tune every level's launch shapes on one conquer of `gens`;
+    returns the chosen shapes per level (as batch_shapes)."""
+    lib = load_library()
+    lib.superdc_hss_autotune.argtypes = [_P, _P, _P, _P, _P, _P, _P, C.POINTER(Opts), _P]
+    lib.superdc_hss_autotune.restype = C.c_int
+    lib.superdc_hss_batch_shapes.argtypes = [_P, C.c_int32, _P]
+    lib.superdc_hss_batch_shapes.restype = C.c_int
+    o = opts if opts is not None else default_opts()
+    _check(lib.superdc_hss_autotune(ctx.handle, plan.handle, _ptr(gens["leaf_D"]),
+                                    _ptr(gens["leaf_U"]), _ptr(gens["R"]), _ptr(gens["B"]),
+                                    _ptr(gens["beta"]), C.byref(o), _stream(stream)),
+           "superdc_hss_autotune")
+    shapes = []
+    for lvl in range(plan.depth):
+        out = (C.c_int32 * 5)()
+        _check(lib.superdc_hss_batch_shapes(plan.handle, lvl, out), "superdc_hss_batch_shapes")
+        shapes.append(dict(sec_chunk=out[0], sec_split=out[1], vec_split=out[2],
+                           bwd_split=out[3], fmm_split=out[4]))
+    return shapes
 
 
 def hss_set_timing(plan, enable=True):

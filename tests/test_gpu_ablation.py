@@ -1,5 +1,5 @@
 """The ablation of local shifting (opts.unshifted = 1): the iterate is kept as lambda and
-every pole difference is formed as d_j - lambda, the original secular equation.
+every pole difference is formed as d_j - lambda (f evaluated at lambda, unshifted).
 
 What it must show (Sec. 4.2, and the comparison the paper makes with and without local
 shifting):
@@ -117,4 +117,5 @@ def test_hybrid_interpolation(orc, kind, method):
         bound = 2.0 * pr.n * eps * (1.0 + np.abs(psi) + np.abs(phi)) / fp + 4.0 * eps * np.abs(eta)
         assert np.all(np.abs(res["eta"][a:e] - eta) <= bound), p
     # the hybrid takes at most a few more steps on average than the middle way
-    assert res["iters"].mean() <= mw["iters"].mean() + 1.0
+    cnt = lambda it: (it & 0xFFFF).mean()  # evaluation count (low 16 bits)
+    assert cnt(res["iters"]) <= cnt(mw["iters"]) + 1.0

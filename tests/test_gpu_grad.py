@@ -186,3 +186,34 @@ def test_full_batch_against_oracle(orc):
         assert np.abs(gd[a:e] - od).max() <= 1e-6 * sc
         assert np.abs(gz[a:e] - oz).max() <= 1e-6 * sc
         assert abs(gr[p] - orr) <= 1e-6 * max(abs(orr), sc)
+
+
+def test_invalid_problem_status_without_sync():
+    """The differentiable path does not wait for the device: a problem with invalid input
+    (here a zero weight) comes out as NaN eigenvalues, projections and gradients, its status
+    bits reach the caller's tensor by a device-side copy, and the valid problems of the
+    same batch are unaffected (equal to a batch without the invalid one)."""
+    from paper_2108_04209_amd import native
+    from paper_2108_04209_amd.autograd import secular_eig
+    batch = gen.small_batch([40, 70, 33], seed=43)
+    bad = gen.Batch(off=batch.off, d=batch.d.copy(), z=batch.z.copy(), rho=batch.rho.copy())
+    bad.z[batch.off[1] + 5] = 0.0
+    u = np.random.default_rng(2).standard_normal(batch.total_n)
+    res = {}
+    for name, bt in (("good", batch), ("bad", bad)):
+        b, d, z, rho = setup(bt)
+        st = torch.full((bt.nprob,), -1, dtype=torch.int32, device=d.device)
+        lam, p = secular_eig(b, d, z, rho, u=torch.as_tensor(u, device=d.device), status=st)
+        (lam.sum() + (p * p * torch.arange(bt.total_n, device=d.device)).sum()).backward()
+        res[name] = {k: v.detach().cpu().numpy() for k, v in
+                     dict(lam=lam, p=p, gd=d.grad, gz=z.grad, gr=rho.grad, st=st).items()}
+    g, x = res["good"], res["bad"]
+    assert np.all(g["st"] == 0)
+    assert x["st"][1] & native.ST_ZERO and x["st"][0] == 0 and x["st"][2] == 0
+    a, e = int(batch.off[1]), int(batch.off[2])
+    assert np.all(np.isnan(x["lam"][a:e])) and np.all(np.isnan(x["p"][a:e]))
+    assert np.all(np.isnan(x["gd"][a:e])) and np.isnan(x["gr"][1])
+    keep = np.r_[np.arange(0, a), np.arange(e, batch.total_n)]
+    for k in ("lam", "p", "gd", "gz"):
+        np.testing.assert_array_equal(x[k][keep], g[k][keep])
+    np.testing.assert_array_equal(x["gr"][[0, 2]], g["gr"][[0, 2]])

@@ -271,3 +271,33 @@ def adjoint_abs_bound(d, z, rho, eta, K, gl, gpj, u):
         bz += np.abs(u) * (ar @ B)
     br = A.sum() / rho ** 2
     return bd, bz, br
+
+
+# -------------------------------------------------------------------- scale invariance
+@pytest.mark.parametrize("e", [-250, 250])
+@pytest.mark.parametrize("method", [1, 2])
+def test_power_of_two_scaling(e, method):
+    """diag(s d) + (s rho) z z^T = s A for s = 2^e: eigenvalues and gaps scale by s, the
+    origins, zhat (rho zhat^2 scales by s) and the eigenvector matrix do not change, b scales
+    by s.  Scaling by a power of two is exact, so every quantity must come out as the
+    unscaled one times its power of s to rounding -- in particular no intermediate of the
+    shared reciprocals (t0 t1, its reciprocal squared) and no block of the Loewner products
+    may leave the exponent range (s = 2^-250 puts pole gaps near 2^-270)."""
+    from paper_2108_04209_amd import native
+    from tests import gpu_pipeline as gp
+    batch, X = gen.small_batch([1024, 300, 2048], seed=61, m=8)
+    s = 2.0 ** e
+    sb = gen.Batch(off=batch.off, d=batch.d * s, z=batch.z.copy(), rho=batch.rho * s)
+    o = native.default_opts(method=method)
+    print(f"scaling 2^{e}, method {method}", flush=True)
+    r0 = gp.run(batch, X=X, trans=(1,), opts=o)
+    r1 = gp.run(sb, X=X, trans=(1,), opts=o)
+    assert np.all(r0["status"] == 0) and np.all(r1["status"] == 0)
+    np.testing.assert_array_equal(r1["origin"], r0["origin"])
+    np.testing.assert_array_equal(r1["iters"], r0["iters"])
+    rel = lambda a, b: np.abs(a - b).max() / np.abs(b).max()
+    assert rel(r1["lam"] / s, r0["lam"]) <= 4e-16
+    assert np.all(np.abs(r1["eta"] / s - r0["eta"]) <= 4e-16 * np.abs(r0["eta"]))
+    assert np.all(np.abs(r1["zhat"] - r0["zhat"]) <= 1e-15 * np.abs(r0["zhat"]))
+    assert np.all(np.abs(r1["b"] / s - r0["b"]) <= 1e-15 * np.abs(r0["b"]))
+    assert rel(r1["Y1"], r0["Y1"]) <= 1e-14
