@@ -158,6 +158,31 @@ int superdc_secular_solve(superdc_ctx *ctx, const superdc_batch *batch, const do
                           const superdc_opts *opts, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): superdc_secular_solve with the same arguments
+ * and outputs, run by the same kernels with direct sums (opts->method 0 or 1; 2 is
+ * rejected), whose per-call buffers -- (d_j, rho z_j^2) and (d_K, eta) pairs, 32 bytes per
+ * root, and one double per problem -- live in one fixed array in device memory instead of
+ * the context's workspace.  The library holds that array on every GPU it runs on until the
+ * process ends (SUPERDC_NOALLOC_MAX_TOTAL * 32 + SUPERDC_NOALLOC_MAX_PROBS * 8 bytes,
+ * about 123 MiB).  The call allocates nothing, issues no memset and does not synchronise;
+ * the batch and the context must have been created beforehand and kernel timing must be
+ * off.  Results equal superdc_secular_solve's with opts->method = 1, bit for bit.
+ * Errors: SUPERDC_EINVAL for the argument errors of superdc_secular_solve, for
+ * opts->method = 2, for total > SUPERDC_NOALLOC_MAX_TOTAL or nprob >
+ * SUPERDC_NOALLOC_MAX_PROBS, and when the current device is not the context's.
+ * Every call on one GPU uses that GPU's single array: calls that overlap in time on one
+ * GPU (other streams, threads or contexts) race and give undefined results; calls ordered
+ * on one stream are safe (each call writes every entry it reads before reading it).
+ */
+#define SUPERDC_NOALLOC_MAX_TOTAL 4000000
+#define SUPERDC_NOALLOC_MAX_PROBS 65536
+int superdc_secular_solve_noalloc(superdc_ctx *ctx, const superdc_batch *batch,
+                                  const double *d, const double *z, const double *rho,
+                                  double *lam, double *eta, int32_t *origin, int32_t *iters,
+                                  int32_t *status, const superdc_opts *opts, void *stream);
+
+/*
  * Loewner update vector and normalisation (eqs. lowner and b), from the solver's output:
  *   in : d, z (only its signs are used), rho, eta, origin, status
  *   out: zhat[total] with rho zhat_i^2 = prod_j (lambda_j - d_i) / prod_{j!=i} (d_j - d_i)

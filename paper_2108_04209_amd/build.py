@@ -14,7 +14,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libsuperdc.so")
 
 SOURCES = ["secular.hip", "vectors.hip", "apply.hip", "backward.hip", "fmm.hip", "fmm_vec.hip", "hss.hip",
-           "deflate.hip", "divide.hip", "api.cpp", "hss_api.cpp", "tune.cpp", "trace.cpp", "deflate_api.cpp"]
+           "deflate.hip", "divide.hip", "noalloc.hip", "api.cpp", "hss_api.cpp", "tune.cpp", "trace.cpp", "deflate_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

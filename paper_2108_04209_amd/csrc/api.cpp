@@ -654,6 +654,13 @@ int superdc_create(superdc_ctx **out) {
     if (!ctx) return SUPERDC_ENOMEM;
     ctx->device = dev;
     ctx->num_cu = prop.multiProcessorCount;
+    {
+        const int rc = noalloc_init(dev);
+        if (rc != SUPERDC_OK) {
+            delete ctx;
+            return rc;
+        }
+    }
     hipError_t e = hipMalloc(&ctx->queues, sizeof(Queue) * kNumQueues);
     if (e == hipSuccess) e = hipMemset(ctx->queues, 0, sizeof(Queue) * kNumQueues);
     if (e == hipSuccess) e = hipDeviceSynchronize();

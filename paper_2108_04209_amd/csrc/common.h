@@ -246,6 +246,9 @@ int persistent_grid(const superdc_ctx *ctx, int ntiles, int per_cu);
 int fmm_crossover_of(const superdc_ctx *ctx, const superdc_opts &o);
 // launch shape of the plain (one launch per problem) direct solve of an n-root problem
 ::LaunchShape plain_shape(const superdc_ctx *ctx, int64_t n);
+// the allocation-free solve's scratch array: its address on `device` is looked up once
+// (noalloc.hip); called by superdc_create with that device current
+int noalloc_init(int device);
 }  // namespace sdc
 
 namespace sdc {

@@ -64,6 +64,9 @@ def load_library(path: str = LIB_PATH):
     lib.superdc_secular_solve.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                           C.POINTER(Opts), _P]
     lib.superdc_secular_solve.restype = C.c_int
+    lib.superdc_secular_solve_noalloc.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                                  C.POINTER(Opts), _P]
+    lib.superdc_secular_solve_noalloc.restype = C.c_int
     lib.superdc_loewner.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, C.POINTER(Opts), _P]
     lib.superdc_loewner.restype = C.c_int
     lib.superdc_cauchy_apply.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P, C.c_int, i32, _P, i64,
@@ -195,6 +198,27 @@ def secular_solve(ctx, batch, d, z, rho, opts=None, stream=None, out=None):
         ctx.handle, batch.handle, _ptr(d), _ptr(z), _ptr(rho), _ptr(out["lam"]),
         _ptr(out["eta"]), _ptr(out["origin"]), _ptr(out.get("iters")), _ptr(out["status"]),
         C.byref(o), _stream(stream)), "superdc_secular_solve")
+    return out
+
+
+def secular_solve_noalloc(ctx, batch, d, z, rho, opts=None, stream=None, out=None):
+    """superdc_secular_solve_noalloc (direct sums, buffers in the library's fixed device
+    array).  `out` as for secular_solve; pass it preallocated to allocate nothing here."""
+    import torch
+    tot, P = batch.total, batch.nprob
+    _f64(d, tot, "d"), _f64(z, tot, "z"), _f64(rho, P, "rho")
+    dev = d.device
+    if out is None:
+        out = dict(lam=torch.empty(tot, dtype=torch.float64, device=dev),
+                   eta=torch.empty(tot, dtype=torch.float64, device=dev),
+                   origin=torch.empty(tot, dtype=torch.int32, device=dev),
+                   iters=torch.empty(tot, dtype=torch.int32, device=dev),
+                   status=torch.empty(P, dtype=torch.int32, device=dev))
+    o = opts if opts is not None else default_opts()
+    _check(load_library().superdc_secular_solve_noalloc(
+        ctx.handle, batch.handle, _ptr(d), _ptr(z), _ptr(rho), _ptr(out["lam"]),
+        _ptr(out["eta"]), _ptr(out["origin"]), _ptr(out.get("iters")), _ptr(out["status"]),
+        C.byref(o), _stream(stream)), "superdc_secular_solve_noalloc")
     return out
 
 
