@@ -1,7 +1,8 @@
 #!/usr/bin/env python3
 """Benchmark of the conquering-stage hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload conquer|level|large|single|deflate|ex1]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+                    [--workload conquer|level|large|single|deflate|ex1|grad]
 
 A step is one pass of the whole rank-one path over one batch already resident in HBM:
 validation and packing, the secular solve (midpoint pass plus middle-way iterations to
@@ -40,7 +41,7 @@ FLOPS_BNORM = 6          # per pair: 2 sub, 1 rcp, 1 mul, 1 fma(2)
 
 
 FMM_CROSSOVER = 1024     # the library's default direct/FMM switch (roots per problem)
-ITER_COUNT_MASK, ITER_UNMET, ITER_CAP = 0xFFFF, 1 << 16, 1 << 17  # iteration records
+ITER_COUNT_MASK, ITER_UNMET, ITER_CAP, ITER_SKIPPED = 0xFFFF, 1 << 16, 1 << 17, 1 << 18
 
 MU_DEFINITION = ("per level, the largest share over the r rank-one steps of roots that needed "
                  "more than 5 iterations after the midpoint pass, or whose iteration ended on "
@@ -48,20 +49,86 @@ MU_DEFINITION = ("per level, the largest share over the r rank-one steps of root
                  "stopping test held")
 
 
+def _per_level(bad, lam_ok):
+    """Per level, the largest share (percent) over the steps of the flagged roots among the
+    roots of problems that were solved (lam_ok: not skipped for invalid input); None for a
+    level with no solved problem."""
+    out = []
+    for l in range(bad.shape[0]):
+        v = [float(100.0 * np.mean(bad[l, t][lam_ok[l, t]])) for t in range(bad.shape[1])
+             if lam_ok[l, t].any()]
+        out.append(max(v) if v else None)
+    return out
+
+
 def mu_levels(it, count_only=False):
     """The share mu (percent) of roots not converged within 5 iterations, per level, from
-    iteration records of shape (depth, r, n)."""
+    iteration records of shape (depth, r, n), over the roots of the problems solved."""
+    lam_ok = (it & ITER_SKIPPED) == 0
     cnt = it & ITER_COUNT_MASK
     bad = cnt > 5 if count_only else (cnt > 5) | ((it & (ITER_UNMET | ITER_CAP)) != 0)
-    return [float(100.0 * np.max(np.mean(bad[l], axis=1))) for l in range(it.shape[0])]
+    return _per_level(bad, lam_ok)
 
 
 def unmet_levels(it):
     """Per level, the largest share (percent) over the steps of roots whose iteration ended
-    before the stopping test held."""
-    bad = (it & (ITER_UNMET | ITER_CAP)) != 0
-    return [float(100.0 * np.max(np.mean(bad[l], axis=1))) for l in range(it.shape[0])]
+    before the stopping test held, over the roots of the problems solved."""
+    return _per_level((it & (ITER_UNMET | ITER_CAP)) != 0, (it & ITER_SKIPPED) == 0)
 MFMA_MIN_M = 4           # the library's automatic VALU/MFMA apply switch (columns)
+
+
+MFMA_KERNELS = ("k_apply_mfma", "k_fmmv_eval_mfma")  # FP64 matrix-core kernels
+APPLY_KERNELS = ("k_apply_mfma", "k_apply_valu", "k_fmmv_eval_mfma", "k_fmmv_eval")
+SOLVER_KERNELS = ("k_secular", "k_secular_fmm")
+
+
+def kernel_peak(name):
+    return PEAK_FP64_MFMA if name in MFMA_KERNELS else PEAK_FP64_VALU
+
+
+def counted_flops(kw, steps):
+    """Algorithmic flops per step from the library's device counters: the solvers count
+    pole-root pair evaluations (7 flops each), the apply and FMM evaluation kernels count
+    their algorithmic flops directly."""
+    out = {}
+    for k, v in kw.items():
+        if k in SOLVER_KERNELS:
+            out[k] = FLOPS_PER_PAIR * v / steps
+        elif k in APPLY_KERNELS:
+            out[k] = v / steps
+    return out
+
+
+def collect_counters(native):
+    """The library's device counters since the last collection: work per kernel (for
+    counted_flops) and, per solver, the share of wavefront lanes that held a live root over
+    all of its passes."""
+    kc = native.kernel_counters()
+    kw = {k: v[0] for k, v in kc.items()}
+    lanes = {k: v[1] / v[2] for k, v in kc.items() if k in SOLVER_KERNELS and v[2] > 0}
+    return kw, lanes
+
+
+def kernel_pass(native, run, steps):
+    """Per-kernel measurement in two passes of `steps` steps each: HIP events alone (the
+    kernel times; no counter atomics in the kernels), then the device counters alone (the
+    work).  Returns ({kernel: (ms, launches)}, work, live-lane fractions)."""
+    import torch
+    native.kernel_times()  # drop anything recorded before
+    native.kernel_timing(True, mode="events")
+    try:
+        for _ in range(steps):
+            run()
+        torch.cuda.synchronize()
+        kt = native.kernel_times()
+        native.kernel_timing(True, mode="counters")
+        for _ in range(steps):
+            run()
+        torch.cuda.synchronize()
+        kw, lanes = collect_counters(native)
+    finally:
+        native.kernel_timing(False)
+    return kt, kw, lanes
 
 
 def kernel_roofline(kt, flops, steps, workload=None):
@@ -69,24 +136,28 @@ def kernel_roofline(kt, flops, steps, workload=None):
 
     kt: {kernel: (ms, launches)} from the library's per-kernel HIP-event timing over
     `steps` steps; flops: {kernel: algorithmic FP64 flops per step} for the kernels whose
-    work has an algorithmic count.  The dominant kernel is the one with the largest time
-    per step among those."""
+    work has an algorithmic count.  Every such kernel gets its achieved rate and its
+    fraction of its own peak (the FP64 matrix peak for the MFMA kernels, the FP64 vector
+    peak otherwise).  The dominant kernel is the one with the largest time per step among
+    them."""
     table = {}
     for name, (ms, nl) in sorted(kt.items(), key=lambda x: -x[1][0]):
         e = {"ms_per_step": ms / steps, "launches_per_step": nl / steps,
              "avg_launch_ms": ms / nl}
-        if name in flops and ms > 0:
-            e["algorithmic_tflops"] = flops[name] / (ms / steps * 1e-3) / 1e12
+        if name in flops and flops[name] > 0 and ms > 0:
+            a = flops[name] / (ms / steps * 1e-3) / 1e12
+            e["algorithmic_tflops"] = a
+            e["peak_tflops"] = kernel_peak(name)
+            e["frac"] = a / kernel_peak(name)
+            e["bound"] = "mfma" if name in MFMA_KERNELS else "alu"
         table[name] = e
-    cand = [k for k in table if k in flops and flops[k] > 0]
+    cand = [k for k in table if "frac" in table[k]]
     if not cand:
         return table, None
     dom = max(cand, key=lambda k: table[k]["ms_per_step"])
     e = table[dom]
-    achieved = e["algorithmic_tflops"]
-    peak = PEAK_FP64_MFMA if dom == "k_apply_mfma" else PEAK_FP64_VALU
-    roof = {"bound": "mfma" if dom == "k_apply_mfma" else "alu", "achieved": achieved,
-            "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+    roof = {"bound": e["bound"], "achieved": e["algorithmic_tflops"], "peak": e["peak_tflops"],
+            "unit": "TFLOP/s", "frac": e["frac"],
             "traffic": kernel_traffic(dom, workload) if workload else None,
             "kernel": dom, "launches_per_step": e["launches_per_step"],
             "avg_launch_ms": e["avg_launch_ms"],
@@ -95,18 +166,52 @@ def kernel_roofline(kt, flops, steps, workload=None):
     return table, roof
 
 
+def apply_summary(table):
+    """The apply half of the metric: every Cauchy-apply kernel's algorithmic rate and its
+    fraction of its peak, and the whole apply's rate (their flops over their time)."""
+    ks = {k: table[k] for k in APPLY_KERNELS if k in table and "frac" in table[k]}
+    if not ks:
+        return None
+    fl = sum(v["algorithmic_tflops"] * v["ms_per_step"] for v in ks.values())
+    ms = sum(v["ms_per_step"] for v in ks.values())
+    return {"kernels": {k: {"algorithmic_tflops": v["algorithmic_tflops"], "frac": v["frac"],
+                            "peak_tflops": v["peak_tflops"], "ms_per_step": v["ms_per_step"]}
+                        for k, v in ks.items()},
+            "algorithmic_tflops": fl / ms, "ms_per_step": ms,
+            "count": "device counters: (2m + 3) flops per Cauchy entry (pole or equivalent "
+                     "source against root, m columns including a fused b) plus the output "
+                     "scaling"}
+
+
+def counted_fp64(workload, kt_table):
+    """The rocprof-counted FP64 rate of the solvers, from the committed instruction-mix
+    summary profiles/<workload>_instruction_mix.md (per-step FP64 flops from the
+    SQ_INSTS_VALU_{FMA,ADD,MUL,TRANS}_F64 counters, 64 lanes per wave instruction, an FMA
+    as 2), over this run's measured kernel time; None if the summary is missing or the
+    kernels' sources changed since it was taken."""
+    fields = _profile_fields(os.path.join(PROFILES, f"{workload}_instruction_mix.md"))
+    if not fields:
+        return None
+    out = {}
+    for k in SOLVER_KERNELS:
+        key = f"{k}_fp64_flops_per_step"
+        if key in fields and k in kt_table:
+            f = float(fields[key])
+            out[k] = {"counted_tflops": f / (kt_table[k]["ms_per_step"] * 1e-3) / 1e12,
+                      "frac_vector_peak": f / (kt_table[k]["ms_per_step"] * 1e-3) / 1e12 / PEAK_FP64_VALU,
+                      "algorithmic_tflops": kt_table[k].get("algorithmic_tflops")}
+    return out or None
+
+
 CALIB_BYTES = 512 << 20  # the calibration copy: this many bytes read and written
 PROFILES = os.path.join(ROOT, "profiles")
 CSRC = os.path.join(ROOT, "paper_2108_04209_amd", "csrc")
 
 
-def kernel_traffic(kernel, workload):
-    """HBM bytes per launch of `kernel` in `workload` from the committed counter summary
-    profiles/<kernel>_<workload>_traffic.md (FETCH_SIZE + WRITE_SIZE, each scaled by the
-    same counter's reading for a copy of known size), or None if there is none or the
-    kernel's sources changed since it was taken (their SHA-256 is recorded in it)."""
+def _profile_fields(path):
+    """The "- key: value" lines of a committed summary, or None if it is missing or the
+    sources it names changed since it was taken (their SHA-256 is recorded in it)."""
     import hashlib
-    path = os.path.join(PROFILES, f"{kernel}_{workload}_traffic.md")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -115,14 +220,25 @@ def kernel_traffic(kernel, workload):
             k, v = line[2:].split(":", 1)
             fields[k.strip()] = v.strip().strip("`")
     try:
-        srcs = fields["sources"].split(",")
         h = hashlib.sha256()
-        for f in srcs:
+        for f in fields["sources"].split(","):
             h.update(open(os.path.join(CSRC, f.strip()), "rb").read())
         if h.hexdigest() != fields["sources_sha256"]:
             return None
-        return float(fields["hbm_bytes_per_launch"])
-    except (KeyError, OSError, ValueError):
+    except (KeyError, OSError):
+        return None
+    return fields
+
+
+def kernel_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` in `workload` from the committed counter summary
+    profiles/<kernel>_<workload>_traffic.md (FETCH_SIZE + WRITE_SIZE, each scaled by the
+    same counter's reading for a copy of known size), or None if there is none or the
+    kernel's sources changed since it was taken."""
+    fields = _profile_fields(os.path.join(PROFILES, f"{kernel}_{workload}_traffic.md"))
+    try:
+        return float(fields["hbm_bytes_per_launch"]) if fields else None
+    except (KeyError, ValueError):
         return None
 
 
@@ -137,7 +253,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="conquer",
-                    choices=["conquer", "level", "large", "single", "deflate", "ex1"])
+                    choices=["conquer", "level", "large", "single", "deflate", "ex1", "grad"])
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-level", action="store_true",
@@ -301,20 +417,17 @@ def bench_level(args, name):
     m = X.shape[1]
 
     pipe = Pipeline(batch, X, persistent=1, crossover=args.fmm_crossover, leaf=args.fmm_leaf)
+    # the heuristic launch shapes first, then the autotuner's on the same data
+    h_wall, h_tot, h_ph = time_steps(pipe, args.steps, args.warmup)
+    heur = {"ms_per_step": float(np.mean(h_tot)), "shapes": pipe.native.batch_shapes(pipe.b)}
+    tuned_shapes = pipe.native.autotune(pipe.ctx, pipe.b, pipe.d, pipe.z, pipe.rho, opts=pipe.opts)
     wall_ms, tot_ms, ph = time_steps(pipe, args.steps, args.warmup)
-    note(f"{name} batched {float(np.mean(tot_ms)):.2f} ms/step")
+    note(f"{name} batched {float(np.mean(tot_ms)):.2f} ms/step (heuristic shapes "
+         f"{heur['ms_per_step']:.2f})")
     iters = (pipe.out["iters"].cpu().numpy() & ITER_COUNT_MASK).astype(np.float64)
     status_ok = bool(np.all(pipe.out["status"].cpu().numpy() == 0))
     ms = float(np.mean(tot_ms))
     solve_ms, vec_ms, apply_ms = (float(x) for x in ph.mean(axis=0))
-
-    # algorithmic work of one step
-    n_of_root = np.repeat(sizes, batch.sizes())
-    pairs = float(np.sum(n_of_root * (1.0 + iters)))
-    sec_flops = FLOPS_PER_PAIR * pairs
-    n2 = float(np.sum(sizes ** 2))
-    vec_flops = (FLOPS_LOEWNER + FLOPS_BNORM) * n2
-    apply_flops = (2 * m + 3) * n2 + 2 * tot * m
 
     # graph replay of the same step
     graph_ms = None
@@ -352,23 +465,14 @@ def bench_level(args, name):
                                           (float(x) for x in p_ph.mean(axis=0)))),
                      "launches_per_phase": batch.nprob, "steps": args.plain_steps}
 
-    # per-kernel timing pass
-    pipe.native.kernel_timing(True)
-    for _ in range(args.steps):
-        pipe.step()
-    torch.cuda.synchronize()
-    kt = pipe.native.kernel_times()
-    kw = pipe.native.kernel_work()
-    pipe.native.kernel_timing(False)
-    # direct kernels serve the problems below the FMM crossover only
+    # per-kernel timing and work
+    kt, kw, lanes = kernel_pass(pipe.native, pipe.step, args.steps)
+    # Loewner and b by direct sums serve the problems below the FMM crossover only; the
+    # solvers and the apply kernels count their work on the device
     small = sizes[sizes < (args.fmm_crossover or FMM_CROSSOVER)]
     n2d = float(np.sum(small ** 2))
-    kflops = {"k_loewner": FLOPS_LOEWNER * n2d, "k_bnorm": FLOPS_BNORM * n2d,
-              ("k_apply_mfma" if m >= MFMA_MIN_M else "k_apply_valu"):
-                  (2 * m + 3) * n2d + 2 * float(np.sum(small)) * m}
-    for k in ("k_secular", "k_secular_fmm"):  # the solvers count their pair evaluations
-        if k in kw:
-            kflops[k] = FLOPS_PER_PAIR * kw[k] / args.steps
+    kflops = {"k_loewner": FLOPS_LOEWNER * n2d, "k_bnorm": FLOPS_BNORM * n2d}
+    kflops.update(counted_flops(kw, args.steps))
     kernels, roofline = kernel_roofline(kt, kflops, args.steps, name)
     res = {
         "metric": METRIC, "value": tot / (ms * 1e-3), "unit": "roots/s", "n_gpus": 1,
@@ -376,8 +480,11 @@ def bench_level(args, name):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (seeded generators, no dataset)", "config": cfg,
         "secular_roots_per_s": tot / (solve_ms * 1e-3),
-        "apply_gflops": apply_flops / (apply_ms * 1e-3) / 1e9,
+        "apply": apply_summary(kernels),
+        "active_lane_fraction": lanes,
         "phase_ms": {"solve": solve_ms, "loewner_b": vec_ms, "apply": apply_ms},
+        "autotune": {"tuned_shapes": tuned_shapes, "tuned_ms_per_step": ms,
+                     "heuristic": heur},
         "kernels": kernels,
         "mean_iters_after_midpoint": float(iters.mean()), "max_iters": int(iters.max()),
         "graph_ms_per_step": graph_ms, "wall_ms_per_step": wall_ms,
@@ -420,6 +527,9 @@ def bench_large(args):
                      "status": int(pipe.out["status"].cpu().numpy()[0]),
                      "_pipe": pipe}
     pf, pd = out["fmm"].pop("_pipe"), out["direct"].pop("_pipe")
+    # per-kernel timing of the FMM run, with the device-counted work
+    kt, kw, lanes = kernel_pass(pf.native, pf.step, args.steps)
+    kernels, roofline = kernel_roofline(kt, counted_flops(kw, args.steps), args.steps)
     lam_f = pf.out["lam"].cpu().numpy()
     lam_d = pd.out["lam"].cpu().numpy()
     nA = float(np.abs(lam_d).max())
@@ -438,16 +548,15 @@ def bench_large(args):
     rows = np.sort(rng.choice(n, 64, replace=False))
     Yo = oracle.cauchy_apply(pr.d, zh, bn, eta_f, org_f, X, trans=1, rows=rows)
     Yf = pf.Y.cpu().numpy().T
-    fm = out["fmm"]
     best = min(("fmm", "direct"), key=lambda k: out[k]["ms_per_step"])
     return {
         "config": {"workload": "single rank-one problem n=65536, clustered poles, "
                                "64 right-hand sides, FMM order 16 leaf 256 vs direct",
                    "n": n, "m": int(m)},
         "value": out[best]["roots_per_s"], "faster": best, "fmm": out["fmm"],
-        "direct": out["direct"],
-        "apply_gflops_fmm_run": ((2 * m + 3) * float(n) ** 2 + 2 * n * m)
-                                / (fm["phase_ms"]["apply"] * 1e-3) / 1e9,
+        "direct": out["direct"], "fmm_kernels": kernels, "fmm_roofline": roofline,
+        "fmm_active_lane_fraction": lanes,
+        "fmm_apply": apply_summary(kernels),
         "accuracy": {"fmm_vs_direct_rel_normA": float(np.abs(lam_f - lam_d).max() / nA),
                      "fmm_vs_oracle_sampled_rel_normA": float(np.abs(lam_f[roots] - lam_o).max() / nA),
                      "origins_agree": bool(np.array_equal(org_f[roots], org_o)),
@@ -513,7 +622,7 @@ def bench_deflate(args):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
     native.kernel_times()
-    native.kernel_timing(True)
+    native.kernel_timing(True, mode="events")
     try:
         for _ in range(args.steps):
             step()
@@ -602,7 +711,7 @@ def bench_ex1(args):
     phases, _ = native.hss_phase_times(plan)
     native.hss_set_timing(plan, False)
     native.kernel_times()
-    native.kernel_timing(True)
+    native.kernel_timing(True, mode="events")
     try:
         for _ in range(args.steps):
             native.hss_divide(ctx, plan, gens, out=dv)
@@ -697,6 +806,106 @@ def bench_ex1(args):
             "tau": tau}
 
 
+FLOPS_BWD_PAIR = 29  # adjoint with projections: 12 per pair in the roots pass, 17 in the poles pass
+
+
+def bench_grad(args):
+    """The differentiation workload: 1024 problems, n uniform in [256, 4096].  One step is
+    the forward pass (solve, Loewner/b, projections p = Qhat^T u) and the backward pass of
+    the loss sum_k wl_k lambda_k + sum_k wp_k p_k^2 through the hand-written adjoint
+    (superdc_secular_backward: dlambda/d(d, z, rho) and the projection terms), all through
+    the C ABI on preallocated buffers."""
+    import torch
+    import oracle
+    from paper_2108_04209_amd import gen, native
+    full = gen.cfg4()
+    dev = torch.device("cuda:0")
+    f = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    ctx = native.Context()
+    b = native.Batch(ctx, full.off)
+    d, z, rho = f(full.d), f(full.z), f(full.rho)
+    u, wl, wp = f(full.extra["u"]), f(full.extra["wl"]), f(full.extra["wp"])
+    tot, P = full.total_n, full.nprob
+    o = native.default_opts()
+    sol = dict(lam=torch.empty(tot, dtype=torch.float64, device=dev),
+               eta=torch.empty(tot, dtype=torch.float64, device=dev),
+               origin=torch.empty(tot, dtype=torch.int32, device=dev),
+               iters=torch.empty(tot, dtype=torch.int32, device=dev),
+               status=torch.empty(P, dtype=torch.int32, device=dev))
+    zb = (torch.empty(tot, dtype=torch.float64, device=dev),
+          torch.empty(tot, dtype=torch.float64, device=dev))
+    pr_ = torch.empty((1, tot), dtype=torch.float64, device=dev)
+    gp = torch.empty(tot, dtype=torch.float64, device=dev)
+    g = (torch.empty(tot, dtype=torch.float64, device=dev),
+         torch.empty(tot, dtype=torch.float64, device=dev),
+         torch.empty(P, dtype=torch.float64, device=dev))
+    u2 = u.view(1, -1)
+
+    def forward():
+        native.secular_solve(ctx, b, d, z, rho, opts=o, out=sol)
+        native.loewner(ctx, b, d, z, rho, sol["eta"], sol["origin"], sol["status"], opts=o, out=zb)
+        native.cauchy_apply(ctx, b, d, zb[0], zb[1], sol["eta"], sol["origin"], sol["status"],
+                            u2, trans=1, opts=o, Y=pr_)
+
+    def backward():
+        torch.mul(pr_.view(-1), wp, out=gp).mul_(2.0)  # dL/dp = 2 wp p
+        native.secular_backward(ctx, b, d, z, rho, sol["eta"], sol["origin"], sol["status"],
+                                g_lam=wl, g_proj=gp, u=u, opts=o, out=g)
+
+    for _ in range(args.warmup):
+        forward()
+        backward()
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    for e in ev:
+        e[0].record()
+        forward()
+        e[1].record()
+        backward()
+        e[2].record()
+    torch.cuda.synchronize()
+    fw = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    bw = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    note(f"grad forward {fw:.2f} ms, backward {bw:.2f} ms")
+    def fwd_bwd():
+        forward()
+        backward()
+
+    kt, kw, lanes = kernel_pass(native, fwd_bwd, args.steps)
+    sizes = full.sizes().astype(np.float64)
+    n2 = float(np.sum(sizes ** 2))
+    small = sizes[sizes < FMM_CROSSOVER]
+    kflops = {"k_bwd": FLOPS_BWD_PAIR * n2, "k_loewner": FLOPS_LOEWNER * float(np.sum(small ** 2)),
+              "k_bnorm": FLOPS_BNORM * float(np.sum(small ** 2))}
+    kflops.update(counted_flops(kw, args.steps))
+    kernels, roofline = kernel_roofline(kt, kflops, args.steps)
+    # gradients of a seeded sample of problems against the oracle's adjoint, fed the
+    # oracle's own forward
+    gd, gz, gr = (x.cpu().numpy() for x in g)
+    err = 0.0
+    for p in np.random.default_rng(3).choice(P, 3, replace=False):
+        a, e = int(full.off[p]), int(full.off[p + 1])
+        pr = full.problem(p)
+        lam, eta, org, its, st = oracle.secular(pr.d, pr.z, pr.rho)
+        zh = oracle.loewner(pr.d, pr.z, pr.rho, eta, org)
+        bb = oracle.bnorm(pr.d, zh, eta, org)
+        pp = oracle.cauchy_apply(pr.d, zh, bb, eta, org, full.extra["u"][a:e], trans=1)[:, 0]
+        od, oz, orr = oracle.backward(pr.d, pr.z, pr.rho, eta, org, g_lam=full.extra["wl"][a:e],
+                                      g_proj=2 * full.extra["wp"][a:e] * pp, u=full.extra["u"][a:e])
+        sc = max(np.abs(od).max(), np.abs(oz).max())
+        err = max(err, float(np.abs(gd[a:e] - od).max() / sc), float(np.abs(gz[a:e] - oz).max() / sc),
+                  float(abs(gr[p] - orr) / max(abs(orr), sc)))
+    ms = fw + bw
+    return {"config": {"workload": "differentiation batch: 1024 rank-one problems, n uniform in "
+                                   "[256, 4096], FP64, loss sum wl lambda + sum wp (q^T u)^2, "
+                                   "forward + hand-written adjoint",
+                       "nprob": P, "total_n": tot},
+            "ms_per_step": ms, "roots_per_s": tot / (ms * 1e-3),
+            "forward_ms": fw, "backward_ms": bw, "kernels": kernels, "roofline": roofline,
+            "grad_err_rel_vs_oracle_sampled": err,
+            "status_all_ok": bool(np.all(sol["status"].cpu().numpy() == 0))}
+
+
 # ---------------------------------------------------------------------------------------
 # HSS conquering pass (n = 65536, leaf 128, depth 9, r = 8)
 # ---------------------------------------------------------------------------------------
@@ -738,27 +947,100 @@ def conquer_kernel_flops(tree, iters, crossover=FMM_CROSSOVER):
     return k
 
 
-def conquer_cpu_baseline(seconds):
-    """The HSS oracle (dense assembly of every node + LAPACK eigenvalues) on the subtree
-    rooted at a level-l node of the same tree, the largest that fits the time budget; the
-    roots the GPU path solves for that subtree (depth_s * r * n_s) per second."""
-    import oracle.hss as ohss
+CPU_SAMPLE_FRAC = 0.02  # share of each stand-in problem's roots (and poles) the oracle runs
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def conquer_cpu_sample(frac=CPU_SAMPLE_FRAC):
+    """The oracle (plain FP64 C, OpenMP over roots) on the rank-one problems of the HSS
+    conquer (n = 65536, leaf 128, depth 9, r = 8): per level l, 2^l problems of n / 2^l
+    roots, each solved r times with an apply of Qhat^T to m = 2r - t - 1 columns at step t
+    (r - t - 1 at the root).  One seeded stand-in problem per level (the single-problem
+    generator at that size) is run on a seeded `frac` of its roots (at least 256, so all
+    the roots of the smallest levels): the solve on those
+    roots, Loewner's zhat on as many poles, b and the apply on as many rows.  Loewner, b
+    and the apply cost a fixed number of operations per pole-root pair, so they run with
+    interval midpoints as stand-in roots.  Every time is scaled linearly to the whole
+    level (roots are independent given the poles) and summed: seconds per conquer."""
+    import oracle
     from paper_2108_04209_amd import gen
-    best = None
-    for ds in range(2, 7):
-        sub = gen.hss_tree(n=128 << ds, leaf=128, r=8, cfg=3)
+    oracle.load()
+    n, depth, r = 65536, 9, 8
+    rng = np.random.default_rng(17)
+    levels, total = [], 0.0
+    for lvl in range(depth):
+        nl, count = n >> lvl, 1 << lvl
+        pr = gen.uniform_problem(nl, gen.rng_for(6, lvl), rho=1.0, gap=1e-6)
+        k = min(nl, max(int(round(frac * nl)), 256))  # at least 256 roots (all of small ones)
+        idx = np.sort(rng.choice(nl, k, replace=False))
+        scale = nl / k
         t0 = time.perf_counter()
-        ohss.level_eigenvalues(sub)
-        dt = time.perf_counter() - t0
-        best = (ds, sub.n, dt)
-        if dt * 8.5 > seconds:   # the next depth costs ~8x (dense O(n^3))
-            break
-    ds, ns, dt = best
+        oracle.secular(pr.d, pr.z, pr.rho, roots=idx)
+        t_solve = time.perf_counter() - t0
+        org = np.arange(nl, dtype=np.int32)
+        eta = np.empty(nl)
+        eta[:-1] = 0.5 * np.diff(pr.d)
+        eta[-1] = 0.5 * pr.rho * float(pr.z @ pr.z)
+        t0 = time.perf_counter()
+        oracle.loewner(pr.d, pr.z, pr.rho, eta, org, poles=idx)
+        oracle.bnorm(pr.d, pr.z, eta, org, roots=idx)
+        t_vec = time.perf_counter() - t0
+        ncol = 2 * r if lvl > 0 else r
+        t_app = 0.0
+        for t in range(r):
+            m = ncol - t - 1
+            if m <= 0:
+                continue
+            X = rng.standard_normal((nl, m))
+            t0 = time.perf_counter()
+            oracle.cauchy_apply(pr.d, pr.z, pr.z, eta, org, X, trans=1, rows=idx)
+            t_app += time.perf_counter() - t0
+        lvl_s = count * scale * (r * (t_solve + t_vec) + t_app)
+        levels.append({"n": nl, "problems": count, "sampled_roots": k,
+                       "sample_s": t_solve + t_vec + t_app, "extrapolated_s": lvl_s})
+        total += lvl_s
+    return {"conquer_s": total, "levels": levels}
+
+
+def conquer_cpu_baseline():
+    """conquer_cpu_sample on all host threads and on one (a child process with
+    OMP_NUM_THREADS=1), as rank-one roots per second of the whole conquer."""
+    import subprocess
+    roots = 9 * 8 * 65536
+    allc = conquer_cpu_sample()
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": ds * 8 * ns / dt, "unit": "roots/s", "cores": cores, "kind": "oracle",
-            "sample": f"HSS tree n={ns} (leaf 128, depth {ds}, r 8), same generator: dense "
-                      f"assembly of every node and LAPACK eigenvalues, {dt:.1f} s; counted as "
-                      f"the {ds * 8 * ns} roots the GPU path solves for that tree"}
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    one = None
+    try:
+        out = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-sample-conquer"],
+                             env=env, capture_output=True, text=True, timeout=600, check=True)
+        one = json.loads(out.stdout.strip().splitlines()[-1])
+    except (subprocess.SubprocessError, ValueError, IndexError) as exc:
+        one = {"error": repr(exc)}
+    res = {"value": roots / allc["conquer_s"], "unit": "roots/s", "cores": cores,
+           "kind": "oracle",
+           "sample": f"the C oracle on one seeded stand-in rank-one problem per conquer level "
+                     f"(n = 65536 ... 256), {CPU_SAMPLE_FRAC:.0%} of its roots (at least 256): solve, Loewner "
+                     f"zhat and b on as many poles and roots, Q^T applied to the level's "
+                     f"m = 2r - t - 1 columns on as many rows; extrapolated linearly to the "
+                     f"2^l problems x 8 steps of every level (EXTRAPOLATED)",
+           "extrapolated": True, "conquer_s": allc["conquer_s"], "levels": allc["levels"],
+           "cpu_model": _cpu_model(), "os_cpu_count": os.cpu_count()}
+    if "conquer_s" in one:
+        res["one_core"] = {"value": roots / one["conquer_s"], "unit": "roots/s", "cores": 1,
+                           "conquer_s": one["conquer_s"]}
+    else:
+        res["one_core"] = one
+    return res
 
 
 def bench_conquer(args):
@@ -794,8 +1076,13 @@ def bench_conquer(args):
                 phases[k] += ph[k] / steps
         return float(np.mean(tot)), phases, counts
 
+    # the heuristic launch shapes first, then every level's batch tuned on its own problems
+    h_ms, _, _ = timed(opts1, args.steps, args.warmup)
+    native.hss_set_timing(plan, False)
+    tuned_shapes = native.hss_autotune(ctx, plan, gens, opts=opts1)
+    native.hss_set_timing(plan, True)
     ms, phases, counts = timed(opts1, args.steps, args.warmup)
-    note(f"conquer batched {ms:.2f} ms/step")
+    note(f"conquer batched {ms:.2f} ms/step (heuristic shapes {h_ms:.2f})")
     status = int(out["status"].cpu().numpy()[0])
     it_raw = native.hss_iterations(plan).cpu().numpy()
     iters = (it_raw & ITER_COUNT_MASK).astype(np.float64)
@@ -821,6 +1108,8 @@ def bench_conquer(args):
                "mu_percent_count_only_unshifted": mu_levels(it_un, count_only=True),
                "unmet_percent_shifted": unmet_levels(it_raw),
                "unmet_percent_unshifted": unmet_levels(it_un),
+               "skipped_percent_unshifted": [float(100.0 * np.mean((it_un[l] & ITER_SKIPPED) != 0))
+                                             for l in range(it_un.shape[0])],
                "status_unshifted": int(un["status"].cpu().numpy()[0]),
                "nonfinite_unshifted": int(np.count_nonzero(~np.isfinite(lam_un)))}
         fin = np.isfinite(lam_un)
@@ -840,6 +1129,7 @@ def bench_conquer(args):
         it_hy = native.hss_iterations(plan).cpu().numpy()
         abl["hybrid_li93"] = {"mu_percent": mu_levels(it_hy),
                               "mean_iters": float((it_hy & ITER_COUNT_MASK).mean()),
+                              "unmet_percent": unmet_levels(it_hy),
                               "mean_iters_middle_way": float(iters.mean()),
                               "ms_per_step": e0.elapsed_time(e1),
                               "status": int(hy["status"].cpu().numpy()[0]),
@@ -873,18 +1163,11 @@ def bench_conquer(args):
                     "replay_equals_eager": bool(np.array_equal(glam, lam))}
     except Exception as exc:  # report, do not hide
         graph_ms = f"capture failed: {exc!r}"
-    # per-kernel timing pass (phase events off)
-    native.kernel_timing(True)
-    for _ in range(args.steps):
-        native.hss_conquer(ctx, plan, gens, opts=opts1, out=out)
-    torch.cuda.synchronize()
-    kt = native.kernel_times()
-    kw = native.kernel_work()
-    native.kernel_timing(False)
+    # per-kernel timing and work (phase events off)
+    kt, kw, lanes = kernel_pass(native, lambda: native.hss_conquer(ctx, plan, gens, opts=opts1,
+                                                                   out=out), args.steps)
     kflops = conquer_kernel_flops(tree, iters, args.fmm_crossover or FMM_CROSSOVER)
-    for k in ("k_secular", "k_secular_fmm"):  # the solvers count their pair evaluations
-        if k in kw:
-            kflops[k] = FLOPS_PER_PAIR * kw[k] / args.steps
+    kflops.update(counted_flops(kw, args.steps))  # solvers and apply kernels: device counts
     kernels, roofline = kernel_roofline(kt, kflops, args.steps, "conquer")
     native.hss_set_timing(plan, True)
 
@@ -919,9 +1202,11 @@ def bench_conquer(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (seeded generators, no dataset)", "config": cfg,
         "secular_roots_per_s": roots / (phases["secular"] * 1e-3),
-        # the dense (2m + 3) n_l^2 work of every apply over the apply phase's time: levels whose
-        # nodes reach the FMM crossover do far less work than counted here
-        "apply_gflops_direct_equivalent": app_f / (phases["apply"] * 1e-3) / 1e9,
+        "apply": apply_summary(kernels),
+        "counted_fp64": counted_fp64("hss_conquer_n65536", kernels),
+        "active_lane_fraction": lanes,
+        "autotune": {"tuned_ms_per_step": ms, "heuristic_ms_per_step": h_ms,
+                     "tuned_shapes_per_level": tuned_shapes},
         "phase_ms": phases, "phase_intervals": counts, "kernels": kernels,
         "mean_iters_after_midpoint": float(iters.mean()), "max_iters": int(iters.max()),
         "graph": graph_ms,
@@ -935,12 +1220,15 @@ def bench_conquer(args):
     }
     note("conquer graph/accuracy/plain done")
     if not args.no_cpu:
-        res["cpu_baseline"] = conquer_cpu_baseline(args.cpu_seconds)
+        res["cpu_baseline"] = conquer_cpu_baseline()
         note("conquer cpu baseline done")
     return res
 
 
 def main():
+    if "--cpu-sample-conquer" in sys.argv:  # child of conquer_cpu_baseline: CPU only
+        print(json.dumps(conquer_cpu_sample()), flush=True)
+        return
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); "
@@ -962,13 +1250,15 @@ def main():
         if not args.no_level:
             lv = bench_level(argparse.Namespace(**{**vars(args), "no_cpu": True}), "level")
             res["level"] = {k: lv[k] for k in ("config", "value", "ms_per_step",
-                                               "secular_roots_per_s", "apply_gflops",
+                                               "secular_roots_per_s", "apply", "autotune",
                                                "phase_ms", "kernels", "graph_ms_per_step", "plain",
+                                               "active_lane_fraction",
                                                "speedup_batched_vs_plain", "accuracy",
                                                "roofline")}
             res["large"] = bench_large(argparse.Namespace(**{**vars(args), "steps": min(args.steps, 5)}))
             res["deflate"] = bench_deflate(argparse.Namespace(**{**vars(args), "steps": min(args.steps, 5)}))
             res["ex1"] = bench_ex1(argparse.Namespace(**{**vars(args), "steps": min(args.steps, 5)}))
+            res["grad"] = bench_grad(argparse.Namespace(**{**vars(args), "steps": min(args.steps, 5)}))
     elif args.workload == "deflate":
         dfl = bench_deflate(args)
         res = {"metric": METRIC, "value": dfl["roots_per_s"], "unit": "roots/s", "n_gpus": 1,
@@ -981,6 +1271,12 @@ def main():
                "unit": "roots/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
                "ms_per_step": ex["ms_per_step"], "higher_is_better": True, "scaling": "weak",
                "vs_baseline": None, "dtype": "f64", "data": "synthetic (closed-form matrix)", **ex}
+    elif args.workload == "grad":
+        gr = bench_grad(args)
+        res = {"metric": METRIC, "value": gr["roots_per_s"], "unit": "roots/s", "n_gpus": 1,
+               "steps": args.steps, "warmup": args.warmup, "ms_per_step": gr["ms_per_step"],
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+               "dtype": "f64", "data": "synthetic (seeded generators, no dataset)", **gr}
     elif args.workload == "large":
         lg = bench_large(args)
         ms = lg[lg["faster"]]["ms_per_step"]

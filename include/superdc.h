@@ -72,6 +72,7 @@ extern "C" {
 #define SUPERDC_ITER_UNMET (1 << 16) /* a step below 2 ulps of the iterate, or a bracket    */
                                      /* collapsed to 2 ulps, ended it before the test held */
 #define SUPERDC_ITER_CAP (1 << 17)   /* the iteration cap ended it (status NOCONV)          */
+#define SUPERDC_ITER_SKIPPED (1 << 18) /* not solved: the problem's input is invalid        */
 
 typedef struct superdc_ctx superdc_ctx;
 typedef struct superdc_batch superdc_batch;
@@ -148,7 +149,8 @@ int superdc_batch_shapes(const superdc_batch *batch, int32_t *out);
  *   out: lam[total], eta[total], origin[total] (int32, local), iters[total] (int32: the
  *        evaluations of the secular sums after the midpoint pass in the bits
  *        SUPERDC_ITER_COUNT_MASK, plus SUPERDC_ITER_UNMET or SUPERDC_ITER_CAP when the
- *        iteration ended otherwise than on the stopping test; may be NULL), status[nprob]
+ *        iteration ended otherwise than on the stopping test, SUPERDC_ITER_SKIPPED for the
+ *        roots of a problem with invalid input; may be NULL), status[nprob]
  *        (int32, bits above; always written).
  * opts may be NULL (defaults).
  */
@@ -401,9 +403,12 @@ int superdc_hss_iterations(superdc_hss *plan, int32_t *dst, void *stream);
 int superdc_hss_phase_times(superdc_hss *plan, double *ms, int32_t *launches);
 
 /*
- * Per-kernel timing (for measurement; process-wide, off by default).  While enabled,
- * every kernel launch of the library is bracketed by two HIP events recorded on the
- * launch's stream.  Do not enable it while a stream is being captured into a graph.
+ * Per-kernel timing (for measurement; process-wide, off by default).  enable: 0 off;
+ * 1 HIP events around every launch and the device work counters (superdc_kernel_work,
+ * superdc_kernel_counters); 2 the events only; 3 the counters only (their atomic adds cost
+ * time, so a pass that times kernels precisely leaves them off).  With events on, every
+ * kernel launch of the library is bracketed by two HIP events recorded on the launch's
+ * stream.  Do not enable it while a stream is being captured into a graph.
  * superdc_kernel_times waits for every recorded launch, writes the summed milliseconds
  * ms[id] and launch counts launches[id] for the first `count` kernel ids, starts a new
  * collection, and returns the number of kernel ids (negative on error); count = 0 only
@@ -423,6 +428,14 @@ int superdc_kernel_times(double *ms, int32_t *launches, int32_t count);
  * Returns the number of kernel ids (negative on error).
  */
 int superdc_kernel_work(double *pairs, int32_t count);
+/*
+ * All device counters of the kernels, as superdc_kernel_work (waits, then clears them):
+ * out[4 id + 0] the work above; for the secular solvers out[4 id + 1] the live lanes
+ * (roots being iterated) summed over every pass of every wavefront and out[4 id + 2] the
+ * lanes of those passes (64 each), whose ratio is the share of lanes doing useful work;
+ * out[4 id + 3] is reserved (0).  out holds 4 count doubles.
+ */
+int superdc_kernel_counters(double *out, int32_t count);
 const char *superdc_kernel_name(int32_t id);
 
 #ifdef __cplusplus

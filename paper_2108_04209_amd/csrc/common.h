@@ -148,8 +148,11 @@ enum KernelId : int {
     KID_DEFL_PLACE, KID_DEFL_ROTATE, KID_COPY_ROWS, KID_FMM_LOCAL, KID_DIVIDE, KID_SORT, KID_COUNT
 };
 
-// device counter of the pair evaluations of kernel `kid` while kernel timing is on (the
-// current device), else nullptr
+// device counters of kernel `kid` while kernel timing is on (the current device), else
+// nullptr: TRACE_WORDS words, [0] its work (pair evaluations or flops), and for the solvers
+// [1] the live lanes summed over every pass of every wavefront, [2] the lanes those
+// passes had (64 per wavefront pass)
+constexpr int TRACE_WORDS = 4;
 unsigned long long *trace_work(int kid);
 
 class TraceScope {

@@ -264,8 +264,8 @@ __device__ void fmmv_item(const SolveArgs &it, const FmmArgs &f, const FmmVec &v
             }
         }
     }
+    const unsigned long long rows = (unsigned long long)__popcll(__ballot(active));
     if (v.work && lane == 0) {  // kernel timing: algorithmic flops of this wavefront's share
-        const unsigned long long rows = (unsigned long long)__popcll(__ballot(active));
         const unsigned long long per = KERN == 1 ? 2 * (unsigned long long)m + 3 : 6;
         atomicAdd(v.work, rows * (unsigned long long)ent * per +
                               (wv == 0 && KERN == 1 ? rows * (unsigned long long)m : 0));

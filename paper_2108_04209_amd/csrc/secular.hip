@@ -429,7 +429,7 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
             a.lam[base + k] = nan;
             a.eta[base + k] = nan;
             a.origin[base + k] = k;
-            if (a.iters) a.iters[base + k] = 0;
+            if (a.iters) a.iters[base + k] = SUPERDC_ITER_SKIPPED;
             a.ke[base + k] = make_double2(nan, nan);
         }
         return;
@@ -463,7 +463,7 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
         // the local expansion (four 16-term Clenshaw series, 128 flops) counts as 18 pairs
         if (wv == 0) pairs_per_pass += 18;
     }
-    unsigned long long work = 0;
+    unsigned long long work = 0, live = 0, slots = 0;
 
     int next = c0;  // next unassigned root (wave-uniform)
     bool act = false, last = false, hi_closed = false, noconv = false;
@@ -505,7 +505,12 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
         else
             secular_sums(dw, n, p0, p1, kmin, kmax, k, dK, y, unsh, psi, dpsi, phi, dphi);
         split_reduce4(red, S, psi, dpsi, phi, dphi);
-        if (a.work) work += (unsigned long long)pairs_per_pass * (unsigned long long)__popcll(__ballot(act));
+        if (a.work) {
+            const unsigned long long na = (unsigned long long)__popcll(__ballot(act));
+            work += (unsigned long long)pairs_per_pass * na;
+            live += na;
+            slots += WAVE;
+        }
         if (!act) continue;
         const double f = 1.0 + psi + phi;
         bool done;
@@ -611,7 +616,11 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
         }
     }
     if (writer && __ballot(noconv) != 0ull && lane == 0) atomicOr(&a.status[p], SUPERDC_ST_NOCONV);
-    if (a.work && lane == 0) atomicAdd(a.work, work);
+    if (a.work && lane == 0) {
+        atomicAdd(a.work, work);
+        atomicAdd(a.work + 1, live);
+        atomicAdd(a.work + 2, slots);
+    }
 }
 
 // blockDim.x = 64 S (S = 1, 2, 4, 8, 16); dynamic LDS: 32 S bytes per lane (S > 1)

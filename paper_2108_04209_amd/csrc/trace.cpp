@@ -2,7 +2,9 @@
 //
 // When enabled, every kernel launch of the library is bracketed by two HIP events on its
 // own stream; superdc_kernel_times() waits for the recorded events and returns the summed
-// durations and launch counts per kernel, then starts a new collection.  Off by default;
+// durations and launch counts per kernel, then starts a new collection.  The device work
+// counters of some kernels (atomic adds at the end of each wavefront) can be switched on
+// with the events or on their own, so that a timed pass need not pay for them.  Off by default;
 // not for use while a stream is being captured into a graph.
 #include <hip/hip_runtime.h>
 
@@ -21,8 +23,10 @@ struct Mark {
 
 struct Tracer {
     std::mutex mu;
-    bool on = false;
-    unsigned long long *work = nullptr;  // [KID_COUNT] device counters (device `work_dev`)
+    bool events = false;    // HIP events around every launch
+    bool counters = false;  // device work counters of the kernels that have them
+    unsigned long long *work = nullptr;  // [KID_COUNT][TRACE_WORDS] device counters
+                                         // (device `work_dev`)
     int work_dev = -1;
     std::vector<hipEvent_t> pool;  // idle events
     std::vector<Mark> marks;       // recorded, not yet collected
@@ -56,15 +60,15 @@ const char *kNames[KID_COUNT] = {
 
 unsigned long long *trace_work(int kid) {
     Tracer &t = tracer();
-    if (!t.on) return nullptr;
+    if (!t.counters) return nullptr;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev != t.work_dev || !t.work) return nullptr;
-    return t.work + kid;
+    return t.work + (size_t)kid * TRACE_WORDS;
 }
 
 TraceScope::TraceScope(int kid, hipStream_t s) : kid_(kid), s_(s) {
     Tracer &t = tracer();
-    if (!t.on) return;  // racy read is fine: enabling is not synchronised with launches
+    if (!t.events) return;  // racy read is fine: enabling is not synchronised with launches
     std::lock_guard<std::mutex> g(t.mu);
     e0_ = take(t);
     e1_ = take(t);
@@ -86,27 +90,40 @@ using namespace sdc;
 extern "C" {
 
 int superdc_kernel_timing(int enable) {
+    if (enable < 0 || enable > 3) return SUPERDC_EINVAL;
     Tracer &t = tracer();
     std::lock_guard<std::mutex> g(t.mu);
-    if (enable) {
+    if (enable == 1 || enable == 3) {
         int dev = 0;
         if (hipGetDevice(&dev) != hipSuccess) return SUPERDC_EHIP;
         if (t.work && t.work_dev != dev) {
             (void)hipFree(t.work);
             t.work = nullptr;
         }
+        const size_t bytes = sizeof(unsigned long long) * KID_COUNT * TRACE_WORDS;
         if (!t.work) {
-            if (hipMalloc(&t.work, sizeof(unsigned long long) * KID_COUNT) != hipSuccess) {
+            if (hipMalloc(&t.work, bytes) != hipSuccess) {
                 t.work = nullptr;
                 return SUPERDC_ENOMEM;
             }
             t.work_dev = dev;
         }
-        if (hipMemset(t.work, 0, sizeof(unsigned long long) * KID_COUNT) != hipSuccess ||
-            hipDeviceSynchronize() != hipSuccess)
+        if (hipMemset(t.work, 0, bytes) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
             return SUPERDC_EHIP;
     }
-    t.on = enable != 0;
+    t.events = enable == 1 || enable == 2;
+    t.counters = enable == 1 || enable == 3;
+    return SUPERDC_OK;
+}
+
+// copy the counters to the host and clear them
+static int collect(Tracer &t, unsigned long long (&h)[KID_COUNT * TRACE_WORDS]) {
+    if (t.work) {
+        if (hipDeviceSynchronize() != hipSuccess ||
+            hipMemcpy(h, t.work, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemset(t.work, 0, sizeof(h)) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+            return SUPERDC_EHIP;
+    }
     return SUPERDC_OK;
 }
 
@@ -114,14 +131,21 @@ int superdc_kernel_work(double *pairs, int32_t count) {
     if (count < 0 || (count > 0 && !pairs)) return SUPERDC_EINVAL;
     Tracer &t = tracer();
     std::lock_guard<std::mutex> g(t.mu);
-    unsigned long long h[KID_COUNT] = {0};
-    if (t.work) {
-        if (hipDeviceSynchronize() != hipSuccess ||
-            hipMemcpy(h, t.work, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess ||
-            hipMemset(t.work, 0, sizeof(h)) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
-            return SUPERDC_EHIP;
-    }
-    for (int i = 0; i < count; ++i) pairs[i] = i < KID_COUNT ? (double)h[i] : 0.0;
+    unsigned long long h[KID_COUNT * TRACE_WORDS] = {0};
+    if (collect(t, h) != SUPERDC_OK) return SUPERDC_EHIP;
+    for (int i = 0; i < count; ++i) pairs[i] = i < KID_COUNT ? (double)h[i * TRACE_WORDS] : 0.0;
+    return KID_COUNT;
+}
+
+int superdc_kernel_counters(double *out, int32_t count) {
+    if (count < 0 || (count > 0 && !out)) return SUPERDC_EINVAL;
+    Tracer &t = tracer();
+    std::lock_guard<std::mutex> g(t.mu);
+    unsigned long long h[KID_COUNT * TRACE_WORDS] = {0};
+    if (collect(t, h) != SUPERDC_OK) return SUPERDC_EHIP;
+    for (int i = 0; i < count; ++i)
+        for (int w = 0; w < TRACE_WORDS; ++w)
+            out[i * TRACE_WORDS + w] = i < KID_COUNT ? (double)h[i * TRACE_WORDS + w] : 0.0;
     return KID_COUNT;
 }
 

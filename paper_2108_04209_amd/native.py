@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libsuperdc.so")
 
 ST_UNSORTED, ST_ZERO, ST_NONFINITE, ST_RHO, ST_NOCONV = 1, 2, 4, 8, 16
 # iteration records: count in the low 16 bits, how the iteration ended above them
-ITER_COUNT_MASK, ITER_UNMET, ITER_CAP = 0xFFFF, 1 << 16, 1 << 17
+ITER_COUNT_MASK, ITER_UNMET, ITER_CAP, ITER_SKIPPED = 0xFFFF, 1 << 16, 1 << 17, 1 << 18
 ERRORS = {0: "success", -1: "invalid argument", -2: "device allocation failed",
           -3: "HIP runtime error", -4: "no gfx950 device"}
 
@@ -314,13 +314,16 @@ def batch_copy_rows(ctx, src_batch, dst_batch, src, rows=None, fill=None, stream
 
 
 def secular_backward(ctx, batch, d, z, rho, eta, origin, status, g_lam=None, g_proj=None,
-                     u=None, opts=None, stream=None):
-    """superdc_secular_backward.  Returns (g_d, g_z, g_rho)."""
+                     u=None, opts=None, stream=None, out=None):
+    """superdc_secular_backward.  Returns (g_d, g_z, g_rho) (`out`, if given, is such a
+    tuple of preallocated tensors and is written in place)."""
     import torch
     tot, P = batch.total, batch.nprob
-    g_d = torch.empty(tot, dtype=torch.float64, device=d.device)
-    g_z = torch.empty(tot, dtype=torch.float64, device=d.device)
-    g_r = torch.empty(P, dtype=torch.float64, device=d.device)
+    if out is None:
+        out = (torch.empty(tot, dtype=torch.float64, device=d.device),
+               torch.empty(tot, dtype=torch.float64, device=d.device),
+               torch.empty(P, dtype=torch.float64, device=d.device))
+    g_d, g_z, g_r = out
     o = opts if opts is not None else default_opts()
     _check(load_library().superdc_secular_backward(
         ctx.handle, batch.handle, _ptr(d), _ptr(z), _ptr(rho), _ptr(eta), _ptr(origin),
@@ -340,9 +343,12 @@ def autotune(ctx, batch, d, z, rho, opts=None, stream=None):
     return batch_shapes(batch)
 
 
-def kernel_timing(enable=True):
-    """superdc_kernel_timing: bracket every library launch with HIP events."""
-    _check(load_library().superdc_kernel_timing(int(bool(enable))), "superdc_kernel_timing")
+def kernel_timing(enable=True, mode=None):
+    """superdc_kernel_timing: bracket every library launch with HIP events and count work
+    on the device (mode None: both, or off with enable False); mode "events" or
+    "counters" turns on one of them alone."""
+    m = 0 if not enable else {None: 1, "events": 2, "counters": 3}[mode]
+    _check(load_library().superdc_kernel_timing(m), "superdc_kernel_timing")
 
 
 def kernel_times():
@@ -366,6 +372,19 @@ def kernel_work():
     w = (C.c_double * cnt)()
     _check(min(0, lib.superdc_kernel_work(w, cnt)), "superdc_kernel_work")
     return {lib.superdc_kernel_name(i).decode(): w[i] for i in range(cnt) if w[i] > 0}
+
+
+def kernel_counters():
+    """superdc_kernel_counters: {kernel name: (work, live lanes, lane slots)} counted while
+    kernel timing was on (kernels with a counter only); waits and clears them."""
+    lib = load_library()
+    lib.superdc_kernel_counters.argtypes = [_P, C.c_int32]
+    lib.superdc_kernel_counters.restype = C.c_int
+    cnt = lib.superdc_kernel_times(None, None, 0)
+    w = (C.c_double * (4 * cnt))()
+    _check(min(0, lib.superdc_kernel_counters(w, cnt)), "superdc_kernel_counters")
+    return {lib.superdc_kernel_name(i).decode(): (w[4 * i], w[4 * i + 1], w[4 * i + 2])
+            for i in range(cnt) if w[4 * i] > 0}
 
 
 def batch_shapes(batch):

@@ -68,3 +68,46 @@ def test_kernel_timing():
     native.secular_solve(ctx, b, d, z, rho)
     torch.cuda.synchronize()
     assert native.kernel_times() == {}
+
+
+def test_device_counters():
+    """The counters alone (no events): the direct Cauchy apply counts (2m + 3) flops per
+    matrix entry plus 2m per output row, exactly; the solver's live-lane count covers every
+    pass of every root and never exceeds the lanes its wavefronts had; the events alone
+    record times and no work."""
+    from paper_2108_04209_amd import native
+    from tests import gpu_pipeline as gp
+    batch, X = gen.small_batch([300, 1200, 64, 77], seed=74, m=5)
+    ctx = gp.context()
+    b = native.Batch(ctx, batch.off)
+    d, z, rho = gp.to_dev(batch.d), gp.to_dev(batch.z), gp.to_dev(batch.rho)
+    o = native.default_opts(method=1, apply_kernel=2)
+    s = native.secular_solve(ctx, b, d, z, rho, opts=o)
+    zh, bn = native.loewner(ctx, b, d, z, rho, s["eta"], s["origin"], s["status"], opts=o)
+    Xt = gp.to_dev(np.asarray(X).T)
+    torch.cuda.synchronize()
+    native.kernel_times()
+    native.kernel_timing(True, mode="counters")
+    try:
+        res = native.secular_solve(ctx, b, d, z, rho, opts=o)
+        native.cauchy_apply(ctx, b, d, zh, bn, s["eta"], s["origin"], s["status"], Xt, trans=1,
+                            opts=o)
+        kc = native.kernel_counters()
+        kt = native.kernel_times()
+    finally:
+        native.kernel_timing(False)
+    assert kt == {}  # no events were recorded
+    n = np.diff(batch.off).astype(np.int64)
+    m = X.shape[1]
+    assert kc["k_apply_mfma"][0] == float(np.sum(n * n * (2 * m + 3) + 2 * n * m))
+    its = res["iters"].cpu().numpy().astype(np.int64) & native.ITER_COUNT_MASK
+    work, live, slots = kc["k_secular"]
+    assert live >= np.sum(1 + its) and 0 < live <= slots
+    native.kernel_timing(True, mode="events")
+    try:
+        native.secular_solve(ctx, b, d, z, rho, opts=o)
+        kt = native.kernel_times()
+        kw = native.kernel_work()
+    finally:
+        native.kernel_timing(False)
+    assert kt["k_secular"][1] == 1 and kw == {}
