@@ -135,8 +135,10 @@ __device__ __forceinline__ void secular_range(const_double2_ptr dw, int j0, int 
             phi += wr;                                                \
             dphi = __builtin_fma(wr, r, dphi);                        \
         } else {                                                      \
-            const bool left = (JJ) <= k;                              \
-            const double wl = left ? wr : 0.0, wg = left ? 0.0 : wr;  \
+            /* j <= k exactly when the pole lies left of the iterate: */ \
+            /* w_j > 0, so the term's sign routes it (psi < 0 < phi)  */ \
+            const double wl = __builtin_fmin(wr, 0.0);                \
+            const double wg = __builtin_fmax(wr, 0.0);                \
             psi += wl;                                                \
             dpsi = __builtin_fma(wl, r, dpsi);                        \
             phi += wg;                                                \
@@ -330,6 +332,7 @@ __device__ __forceinline__ void fmm_sums(const FmmArgs &f, int L, int nn, int nl
     kmin = wave_uniform(kmin);
     kmax = wave_uniform(kmax);
     wv = wave_uniform(wv);
+    const int sh = __builtin_ctz((unsigned)S);  // the split is a power of two
     psi = dpsi = phi = dphi = 0.0;
     const double x = dK + y;
     // near leaves: the same window split as the direct sums, so only poles within one tile
@@ -338,8 +341,8 @@ __device__ __forceinline__ void fmm_sums(const FmmArgs &f, int L, int nn, int nl
     for (int e = 0; e < nn; ++e) {
         const int lo0 = wave_uniform(f.near_lo[(int64_t)L * FMM_NEAR_MAX + e]);
         const int hi0 = wave_uniform(f.near_hi[(int64_t)L * FMM_NEAR_MAX + e]);
-        const int lo = lo0 + (int)(((int64_t)(hi0 - lo0) * wv) / S);
-        const int hi = lo0 + (int)(((int64_t)(hi0 - lo0) * (wv + 1)) / S);
+        const int lo = lo0 + (int)(((int64_t)(hi0 - lo0) * wv) >> sh);  // S = 2^sh
+        const int hi = lo0 + (int)(((int64_t)(hi0 - lo0) * (wv + 1)) >> sh);
         secular_range<0, true, true>(dw, lo, min(hi, f0), k, dK, y, x, psi, dpsi, phi, dphi);
         if (unsh) {  // ablation: near poles and the window in lambda-form as well
             secular_range<0, true, false>(dw, max(lo, f0), min(hi, kmin), k, dK, y, x, psi, dpsi,
@@ -394,6 +397,79 @@ __device__ __forceinline__ void fmm_sums(const FmmArgs &f, int L, int nn, int nl
     }
 }
 
+// ---------------------------------------------------------------------------------------
+// Teams of lanes for the last roots of a work item.  Once every root of an item has
+// started, the lanes of roots that converged would idle until the item's slowest root is
+// done; instead, when at most 32 roots are live, the wavefront regroups them so that each
+// live root is held by a team of g lanes (the largest power of two with g * live <= 64),
+// every lane of a team carrying the root's full state.  Lane `sub` of a team sums every
+// g-th pole of each range from sub on (per-lane loads), the team adds its partial sums by
+// a butterfly over xor offsets below g, and every lane of the team then takes the same
+// step.  The teams of the S wavefronts of a workgroup are formed identically.
+// ---------------------------------------------------------------------------------------
+
+// the poles [j0, j1) that lane `sub` of a team of g takes, each with its own reciprocal
+// (two Newton steps); positive weights, so a term's sign routes it: negative terms (pole
+// left of the iterate) to psi, positive ones to phi.  LF: lambda-form differences
+template <bool LF>
+__device__ __forceinline__ void team_poles(const double2 *__restrict__ dw, int j0, int j1,
+                                           int sub, int g, double dK, double y, double x,
+                                           double &psi, double &dpsi, double &phi,
+                                           double &dphi) {
+#pragma unroll 4
+    for (int j = j0 + sub; j < j1; j += g) {
+        const double2 pw = dw[j];
+        const double r = rcp_nr(LF ? pw.x - x : (pw.x - dK) - y);
+        const double wr = pw.y * r;
+        const double wl = __builtin_fmin(wr, 0.0), wg = __builtin_fmax(wr, 0.0);
+        psi += wl;
+        dpsi = __builtin_fma(wl, r, dpsi);
+        phi += wg;
+        dphi = __builtin_fma(wg, r, dphi);
+    }
+}
+
+// equivalent sources of one far box (weights of either sign), lambda-form, one Newton
+// step, all into psi (LEFT) or all into phi
+template <bool LEFT>
+__device__ __forceinline__ void team_sources(const double2 *__restrict__ eq, int sub, int g,
+                                             double x, double &s0, double &s1) {
+    for (int q = sub; q < FMM_P; q += g) {
+        const double2 pw = eq[q];
+        const double r = rcp_nr1(pw.x - x);
+        const double wr = pw.y * r;
+        s0 += wr;
+        s1 = __builtin_fma(wr, r, s1);
+    }
+}
+
+// add a team's partial sums (teams are aligned groups of g lanes)
+__device__ __forceinline__ void team_reduce(int g, double &a, double &b, double &c, double &d) {
+    for (int o = 1; o < g; o <<= 1) {
+        a += __shfl_xor(a, o);
+        b += __shfl_xor(b, o);
+        c += __shfl_xor(c, o);
+        d += __shfl_xor(d, o);
+    }
+}
+
+// lane index of the s-th set bit (from 0) of m, s < popcount(m)
+__device__ __forceinline__ int nth_set_bit(unsigned long long m, int s) {
+    int pos = 0;
+    for (int w = 32; w >= 1; w >>= 1) {
+        const unsigned long long low = m & ((1ull << w) - 1ull);
+        const int c = __popcll(low);
+        if (s >= c) {
+            s -= c;
+            m >>= w;
+            pos += w;
+        } else {
+            m = low;
+        }
+    }
+    return pos;
+}
+
 __device__ __forceinline__ int wave_min(int v) {
     for (int o = WAVE / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
     return v;
@@ -402,6 +478,63 @@ __device__ __forceinline__ int wave_min(int v) {
 __device__ __forceinline__ int wave_max(int v) {
     for (int o = WAVE / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
     return v;
+}
+
+// The sums of secular_sums / fmm_sums for teams of g lanes (see above): lane `sub` of a
+// team takes every g-th pole of the wavefront's share of each range, every pole in the
+// shifted form (lambda-form in the unshifted ablation) with two Newton steps; far boxes
+// through their equivalent sources; the local expansion by the team's first lane.
+__device__ __forceinline__ void team_sums(const FmmArgs *fm, int L, int nn, int nl, int nr,
+                                          const double2 *__restrict__ dw, int p0, int p1,
+                                          double dK, double y, int wv, int S, int sub, int g,
+                                          bool unsh, double &psi, double &dpsi, double &phi,
+                                          double &dphi) {
+    psi = dpsi = phi = dphi = 0.0;
+    const double x = dK + y;
+    if (!fm || nn < 0) {  // direct sums over this wavefront's share of the poles
+        if (unsh) team_poles<true>(dw, p0, p1, sub, g, dK, y, x, psi, dpsi, phi, dphi);
+        else team_poles<false>(dw, p0, p1, sub, g, dK, y, x, psi, dpsi, phi, dphi);
+        return;
+    }
+    const FmmArgs &f = *fm;
+    const int sh = __builtin_ctz((unsigned)S);
+    for (int e = 0; e < nn; ++e) {
+        const int lo0 = wave_uniform(f.near_lo[(int64_t)L * FMM_NEAR_MAX + e]);
+        const int hi0 = wave_uniform(f.near_hi[(int64_t)L * FMM_NEAR_MAX + e]);
+        const int lo = lo0 + (int)(((int64_t)(hi0 - lo0) * wv) >> sh);
+        const int hi = lo0 + (int)(((int64_t)(hi0 - lo0) * (wv + 1)) >> sh);
+        if (unsh) team_poles<true>(dw, lo, hi, sub, g, dK, y, x, psi, dpsi, phi, dphi);
+        else team_poles<false>(dw, lo, hi, sub, g, dK, y, x, psi, dpsi, phi, dphi);
+    }
+    for (int e = wv; e < nl; e += S) {
+        const int gb = wave_uniform(f.far_ld[(int64_t)L * FMM_FAR_MAX + e]);
+        team_sources<true>(f.eq + (int64_t)gb * FMM_P, sub, g, x, psi, dpsi);
+    }
+    for (int e = wv; e < nr; e += S) {
+        const int gb = wave_uniform(f.far_rd[(int64_t)L * FMM_FAR_MAX + e]);
+        team_sources<false>(f.eq + (int64_t)gb * FMM_P, sub, g, x, phi, dphi);
+    }
+    if (wv == 0 && sub == 0) {  // the local expansion, as in fmm_sums
+        const double2 cw = f.loc_ab[L];
+        const double t = cw.y > 0.0 ? fmin(1.0, fmax(-1.0, (x - cw.x) / cw.y)) : 0.0;
+        const const_double_ptr c = as_const(f.loc + (int64_t)L * FMM_LOC);
+        double r[4];
+#pragma unroll
+        for (int fn = 0; fn < 4; ++fn) {
+            double b1 = 0.0, b2 = 0.0;
+#pragma unroll
+            for (int j = FMM_P - 1; j >= 1; --j) {
+                const double b0 = __builtin_fma(2.0 * t, b1, c[fn * FMM_P + j] - b2);
+                b2 = b1;
+                b1 = b0;
+            }
+            r[fn] = __builtin_fma(t, b1, c[fn * FMM_P] - b2);
+        }
+        psi += r[0];
+        dpsi += r[1];
+        phi += r[2];
+        dphi += r[3];
+    }
 }
 
 // One wavefront solves the roots [c0, c1) of one problem.  Each lane holds one live root;
@@ -472,6 +605,8 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
     int k = c0, K = c0, nev = 0, phase = 0;
     int why = 0;  // how the root stopped: 0 the stopping test, SUPERDC_ITER_* otherwise
     double dk = 0.0, dk1 = 0.0, dK = 0.0, y = 0.0, lo = 0.0, hi = 0.0;
+    int g = 1;                 // lanes per live root (a team; see above)
+    bool noconv_any = false;   // some root of the wavefront hit the cap (kept across regroups)
     for (;;) {
         // refill idle lanes with the next roots of the chunk, in order
         const unsigned long long freem = __ballot(!act);
@@ -495,20 +630,61 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
         }
         next = min(c1, next + (int)__popcll(freem));
         if (__ballot(act) == 0ull) break;
-        const int kmin = wave_min(act ? k : 0x7fffffff);
-        const int kmax = wave_max(act ? k : -1);
+        // once every root of the chunk has started, regroup the live roots into teams of
+        // lanes when at most half the lanes would otherwise be busy
+        if (next >= c1 && g < WAVE) {
+            const unsigned long long rep = __ballot(act && (lane & (g - 1)) == 0);
+            const int nlive = __popcll(rep);
+            int gn = g;
+            while (gn < WAVE && nlive * gn * 2 <= WAVE) gn *= 2;
+            if (gn > g) {
+                noconv_any = noconv_any || __ballot(noconv) != 0ull;
+                const int slot = lane / gn;
+                const bool keep = slot < nlive;
+                const int src = keep ? nth_set_bit(rep, slot) : lane;
+                int flags = (act ? 1 : 0) | (last ? 2 : 0) | (hi_closed ? 4 : 0) | (fw ? 8 : 0);
+                flags = __shfl(flags, src);
+                act = keep && (flags & 1);
+                last = (flags & 2) != 0;
+                hi_closed = (flags & 4) != 0;
+                fw = (flags & 8) != 0;
+                k = __shfl(k, src);
+                K = __shfl(K, src);
+                nev = __shfl(nev, src);
+                phase = __shfl(phase, src);
+                why = __shfl(why, src);
+                fprev = __shfl(fprev, src);
+                dk = __shfl(dk, src);
+                dk1 = __shfl(dk1, src);
+                dK = __shfl(dK, src);
+                y = __shfl(y, src);
+                lo = __shfl(lo, src);
+                hi = __shfl(hi, src);
+                noconv = false;
+                g = gn;
+            }
+        }
+        const int sub = lane & (g - 1);  // this lane's place in its team
 
         double psi, dpsi, phi, dphi;
-        if (FMM && nn >= 0)
-            fmm_sums(*fm, L, nn, nl, nr, dw, kmin, kmax, k, dK, y, wv, S, unsh, psi, dpsi, phi,
-                     dphi);
-        else
-            secular_sums(dw, n, p0, p1, kmin, kmax, k, dK, y, unsh, psi, dpsi, phi, dphi);
+        if (g > 1) {
+            team_sums(FMM ? fm : nullptr, L, nn, nl, nr, dw, p0, p1, dK, y, wv, S, sub, g, unsh,
+                      psi, dpsi, phi, dphi);
+            team_reduce(g, psi, dpsi, phi, dphi);
+        } else {
+            const int kmin = wave_min(act ? k : 0x7fffffff);
+            const int kmax = wave_max(act ? k : -1);
+            if (FMM && nn >= 0)
+                fmm_sums(*fm, L, nn, nl, nr, dw, kmin, kmax, k, dK, y, wv, S, unsh, psi, dpsi, phi,
+                         dphi);
+            else
+                secular_sums(dw, n, p0, p1, kmin, kmax, k, dK, y, unsh, psi, dpsi, phi, dphi);
+        }
         split_reduce4(red, S, psi, dpsi, phi, dphi);
         if (a.work) {
-            const unsigned long long na = (unsigned long long)__popcll(__ballot(act));
-            work += (unsigned long long)pairs_per_pass * na;
-            live += na;
+            const unsigned long long nroot = (unsigned long long)__popcll(__ballot(act && sub == 0));
+            work += (unsigned long long)pairs_per_pass * nroot;
+            live += (unsigned long long)__popcll(__ballot(act));
             slots += WAVE;
         }
         if (!act) continue;
@@ -605,7 +781,7 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
             y = yn;
         }
         if (done) {
-            if (writer) {
+            if (writer && sub == 0) {
                 a.eta[base + k] = y;
                 a.lam[base + k] = dK + y;
                 a.origin[base + k] = K;
@@ -615,7 +791,8 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
             act = false;
         }
     }
-    if (writer && __ballot(noconv) != 0ull && lane == 0) atomicOr(&a.status[p], SUPERDC_ST_NOCONV);
+    noconv_any = noconv_any || __ballot(noconv) != 0ull;
+    if (writer && noconv_any && lane == 0) atomicOr(&a.status[p], SUPERDC_ST_NOCONV);
     if (a.work && lane == 0) {
         atomicAdd(a.work, work);
         atomicAdd(a.work + 1, live);
@@ -659,6 +836,7 @@ __global__ __launch_bounds__(512) void k_secular_fmm(SolveArgs a, FmmArgs f, Que
 hipError_t launch_secular_fmm(const SolveArgs &a, const FmmArgs &f, int split, Queue *q,
                               int grid, hipStream_t s) {
     if (a.ntiles <= 0) return hipSuccess;
+    if (split < 1 || split > 8 || (split & (split - 1))) return hipErrorInvalidValue;
     const size_t lds = split > 1 ? sizeof(double4) * WAVE * split : 0;
     SDC_LAUNCH(KID_SECULAR_FMM, k_secular_fmm, dim3(q ? grid : a.ntiles), dim3(WAVE * split), lds, s, a,
                        f, q);
