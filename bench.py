@@ -266,6 +266,9 @@ def parse():
     ap.add_argument("--fmm-leaf", type=int, default=64,
                     help="poles per FMM leaf (multiple of 64, at most 1024; the library "
                          "default is 64)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="file that keeps the autotuner's choices between runs (the library's "
+                         "SUPERDC_TUNE_CACHE); a run that finds its shapes there does not tune")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 512 MiB device-to-device copy (the reference kernel "
                          "that scales the profiler's FETCH_SIZE / WRITE_SIZE counters)")
@@ -1230,6 +1233,8 @@ def main():
         print(json.dumps(conquer_cpu_sample()), flush=True)
         return
     args = parse()
+    if args.tune_cache:
+        os.environ["SUPERDC_TUNE_CACHE"] = args.tune_cache
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); "
               "the path has no multi-GPU mode", file=sys.stderr)

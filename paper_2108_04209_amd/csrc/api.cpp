@@ -261,7 +261,18 @@ FmmPlan *fmm_plan(superdc_batch *b, int leaf, int crossover) {
                          (size_t)fp->nboxes * FMM_P * FMMV_MAX_M) &&
               fmm_upload(fp, &fp->tail, std::vector<double>(), b->nprob) &&
               fmm_upload(fp, &fp->lgeo, std::vector<double2>(), fp->nboxes) &&
-              fmm_upload(fp, &fp->lmom, std::vector<double>(), (size_t)fp->nboxes * FMML_K);
+              fmm_upload(fp, &fp->lmom, std::vector<double>(), (size_t)fp->nboxes * FMML_K) &&
+              fmm_upload(fp, &fp->t_near_lo, std::vector<int32_t>(), (size_t)fp->nleaves * FMM_NEAR_MAX) &&
+              fmm_upload(fp, &fp->t_near_hi, std::vector<int32_t>(), (size_t)fp->nleaves * FMM_NEAR_MAX) &&
+              fmm_upload(fp, &fp->t_far_l, std::vector<int32_t>(), (size_t)fp->nleaves * FMM_FAR_MAX) &&
+              fmm_upload(fp, &fp->t_far_r, std::vector<int32_t>(), (size_t)fp->nleaves * FMM_FAR_MAX) &&
+              fmm_upload(fp, &fp->t_cnt, std::vector<int32_t>(), (size_t)fp->nleaves * 3) &&
+              fmm_upload(fp, &fp->t_far_ld, std::vector<int32_t>(), (size_t)fp->nleaves * FMM_FAR_MAX) &&
+              fmm_upload(fp, &fp->t_far_rd, std::vector<int32_t>(), (size_t)fp->nleaves * FMM_FAR_MAX) &&
+              fmm_upload(fp, &fp->t_cntd, std::vector<int32_t>(), (size_t)fp->nleaves * 2) &&
+              fmm_upload(fp, &fp->t_used, std::vector<int32_t>(), fp->nboxes) &&
+              fmm_upload(fp, &fp->t_box_ab, std::vector<double2>(), fp->nboxes) &&
+              fmm_upload(fp, &fp->t_loc_ab, std::vector<double2>(), (size_t)fp->nleaves);
     // direct chunks of the other problems, for each cut length
     fp->dir_lpt.assign(4, nullptr);
     fp->dir_count.assign(4, 0);
@@ -329,6 +340,26 @@ FmmArgs fmm_vec_args(const FmmPlan *fp, const superdc_batch *b, const double2 *p
     superdc_opts_default(&o);
     FmmArgs f = fmm_args(fp, b, a, o);
     f.tail = fp->tail;
+    return f;
+}
+
+// The FMM of the sums over the roots (Y = Qhat X): its own lists and use flags, the
+// sources' positions in `pairs` (the roots), the targets at the poles d.
+FmmArgs fmm_roots_args(const FmmPlan *fp, const superdc_batch *b, const double2 *pairs,
+                       const int32_t *status, const double *d) {
+    FmmArgs f = fmm_vec_args(fp, b, pairs, status);
+    f.tpos = d;
+    f.near_lo = fp->t_near_lo;
+    f.near_hi = fp->t_near_hi;
+    f.far_l = fp->t_far_l;
+    f.far_r = fp->t_far_r;
+    f.cnt = fp->t_cnt;
+    f.far_ld = fp->t_far_ld;
+    f.far_rd = fp->t_far_rd;
+    f.cntd = fp->t_cntd;
+    f.used = fp->t_used;
+    f.box_ab = fp->t_box_ab;
+    f.loc_ab = fp->t_loc_ab;
     return f;
 }
 
@@ -436,6 +467,7 @@ int loewner_run(superdc_ctx *ctx, const superdc_batch *b, const double *d, const
     if (rc) return rc;
     FmmvPackArgs pk{};
     FmmVec v{};
+    v.trans = 1;
     FmmArgs f{};
     FmmlArgs lf{};
     if (fp) {
@@ -555,11 +587,12 @@ int apply_run(superdc_ctx *ctx, const superdc_batch *b, const double *d, const d
     const TileList *L = tile_list(bm, TILE);
     if (!L) return SUPERDC_ENOMEM;
     // Y = Qhat^T X of the large problems by the eigenvector-side FMM (the sums run over the
-    // poles for every root, the layout of the solver's lists); the others, and every
-    // Qhat X, by the direct kernels
+    // poles for every root, the layout of the solver's lists), Y = Qhat X by the FMM of the
+    // sums over the roots (sources at the roots, targets at the poles, lists of their own);
+    // the other problems by the direct kernels
     int rc;
-    FmmPlan *fp = trans == 1 ? fmm_for(ctx, bm, o, rc) : nullptr;
-    if (trans == 1 && rc) return rc;
+    FmmPlan *fp = fmm_for(ctx, bm, o, rc);
+    if (rc) return rc;
     if (o.persistent) {
         a.tiles = fp ? fp->dir_lpt[0] : L->lpt;
         a.ntiles = fp ? fp->dir_count[0] : L->count;
@@ -573,7 +606,43 @@ int apply_run(superdc_ctx *ctx, const superdc_batch *b, const double *d, const d
             SDC_HIP(launch_apply(a, use_mfma, nullptr, 0, s));
         }
     }
-    if (fp) {
+    if (fp && trans == 0) {
+        const int mc = std::min(m, FMMV_MAX_M);
+        double2 *pairs = (double2 *)ws_get(ctx, WS_VPAIR, sizeof(double2) * b->total);
+        double *src = (double *)ws_get(ctx, WS_VSRC, sizeof(double) * b->total * mc);
+        if (!pairs || !src) return SUPERDC_ENOMEM;
+        FmmvPackArgs pk{};
+        pk.off = b->off_d;
+        pk.d = d;
+        pk.zhat = zhat;
+        pk.bnorm = bnorm;
+        pk.eta = eta;
+        pk.origin = origin;
+        pk.X = X;
+        pk.ldx = ldx;
+        pk.pairs = pairs;
+        pk.tail = fp->tail;
+        FmmVec v{};
+        v.trans = 0;
+        v.kern = 1;
+        v.src = src;
+        v.vnode = fp->vnode;
+        v.vw = fp->vw;
+        v.d = d;
+        v.origin = origin;
+        v.eta = eta;
+        v.post = zhat;
+        v.ldy = ldy;
+        v.zh = zhat;
+        const FmmArgs f = fmm_roots_args(fp, b, pairs, status, d);
+        for (int c0 = 0; c0 < m; c0 += FMMV_MAX_M) {
+            pk.c0 = c0;
+            v.m = std::min(FMMV_MAX_M, m - c0);
+            v.Y = Y + (int64_t)c0 * ldy;
+            // the lists depend on the roots' positions, packed with the first columns
+            SDC_HIP(fmmv_run(ctx, b, fp, f, pk, v, c0 == 0, o.persistent != 0, s));
+        }
+    } else if (fp) {
         const int mc = std::min(m + (fuse_b ? 1 : 0), FMMV_MAX_M);
         double2 *pairs = (double2 *)ws_get(ctx, WS_VPAIR, sizeof(double2) * b->total);
         double *src = (double *)ws_get(ctx, WS_VSRC, sizeof(double) * b->total * mc);
@@ -589,6 +658,7 @@ int apply_run(superdc_ctx *ctx, const superdc_batch *b, const double *d, const d
         pk.pairs = pairs;
         pk.tail = fp->tail;
         FmmVec v{};
+        v.trans = 1;
         v.kern = 1;
         v.src = src;
         v.vnode = fp->vnode;

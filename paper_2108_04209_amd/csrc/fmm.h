@@ -45,6 +45,10 @@ struct FmmArgs {
     int nboxes, nleaves;
     const int32_t *box_fmm;   // [nboxes] owning FMM problem of each box
     const int32_t *leaf_fmm;  // [nleaves] owning FMM problem of each leaf
+    // targets of the lists: nullptr, the roots of the solver (a target leaf's roots lie in
+    // [d_first, d_next]); else the positions of the target points themselves (the poles, for
+    // sums over the roots), a leaf spanning [tpos[first], tpos[last]]
+    const double *tpos;
 };
 
 // Host side: the FMM layout of one batch for one leaf size (device buffers owned here).
@@ -83,15 +87,26 @@ struct FmmPlan {
     double *tail = nullptr;            // [nprob] per-call bound of the last root
     double2 *lgeo = nullptr;           // Loewner far field: box geometry and moments
     double *lmom = nullptr;
+    // the lists of the sums over the roots (Y = Qhat X: sources at the roots, targets at the
+    // poles), kept apart from the solver's, which later calls on the same poles reuse
+    int32_t *t_near_lo = nullptr, *t_near_hi = nullptr, *t_far_l = nullptr, *t_far_r = nullptr;
+    int32_t *t_cnt = nullptr, *t_far_ld = nullptr, *t_far_rd = nullptr, *t_cntd = nullptr;
+    int32_t *t_used = nullptr;
+    double2 *t_box_ab = nullptr, *t_loc_ab = nullptr;
     std::vector<void *> allocs;
 };
 
 // Eigenvector-side FMM (Sec. 4.3-4.4 with local shifting): sums over the poles i of a
 // problem for every root j, sum_i src_i,c K(d_i - lambda_j), with K = 1/t (the apply
-// Y = Qhat^T X: src = zhat_i X_i,c, scaled by b_j) or K = 1/t^2 (b: src = zhat_i^2).
+// Y = Qhat^T X: src = zhat_i X_i,c, scaled by b_j) or K = 1/t^2 (b: src = zhat_i^2);
+// with trans = 0, sums over the roots j for every pole i, sum_j src_j,c / (d_i - lambda_j)
+// (the apply Y = Qhat X: src = b_j X_j,c, scaled by zhat_i), sources at the roots.
 struct FmmVec {
     int m;                    // columns of src (<= FMMV_MAX_M)
     int kern;                 // 1: 1/t, 2: 1/t^2
+    int trans;                // 1: sums over the poles (targets the roots); 0: over the roots
+                              // (source positions lambda_j = d_{K_j} + eta_j, in the .x of
+                              // the pairs the pack kernel writes)
     double *src;              // [total][m] pole-major source weights
     double *vnode;            // [boxes][FMM_P] equivalent source nodes
     double *vw;               // [boxes][FMM_P][m] equivalent source weights
@@ -135,11 +150,12 @@ struct FmmvPackArgs {
     const Tile *tiles;   // 64-entry tiles of the FMM problems
     int ntiles;
     const double *d, *zhat, *eta;
+    const double *bnorm; // trans 0: b_j, the sources' scale
     const int32_t *origin;
     const double *X;     // kern 1: right-hand sides (column-major, ld ldx), columns c0..c0+m-1
     int64_t ldx;
     int c0;
-    double2 *pairs;      // (d_i, zhat_i) for the list geometry
+    double2 *pairs;      // (d_i, zhat_i) for the list geometry; trans 0: (lambda_j, b_j)
     double *tail;        // [nprob] lambda_{n-1} - d_{n-1}
 };
 hipError_t launch_fmmv_pack(const FmmvPackArgs &a, const FmmVec &v, hipStream_t s);

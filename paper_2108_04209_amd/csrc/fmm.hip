@@ -161,8 +161,11 @@ __global__ __launch_bounds__(WAVE) void k_fmm_lists(FmmArgs f) {
         return;
     }
     const double2 *dw = f.dw + base;
-    const double xa = dw[i0].x;
-    const double xb = i1 < n ? dw[i1].x : dw[n - 1].x + fmax(f.tail[p], 0.0);
+    // the target leaf's span: its roots lie in [d_first, d_next] (the solver's targets), or
+    // the target points themselves (poles, for the sums over the roots)
+    const double xa = f.tpos ? f.tpos[base + i0] : dw[i0].x;
+    const double xb = f.tpos ? f.tpos[base + i1 - 1]
+                             : (i1 < n ? dw[i1].x : dw[n - 1].x + fmax(f.tail[p], 0.0));
     int32_t *far_l = f.far_l + (int64_t)L * FMM_FAR_MAX;
     int32_t *far_r = f.far_r + (int64_t)L * FMM_FAR_MAX;
     int32_t *near_lo = f.near_lo + (int64_t)L * FMM_NEAR_MAX;

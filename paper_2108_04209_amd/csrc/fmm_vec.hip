@@ -29,13 +29,22 @@ __device__ __forceinline__ double cheb_bary_v(int q) {
 
 }  // namespace
 
-// src_i,c = zhat_i X_i,c0+c (kern 1) or zhat_i^2 (kern 2); one lane per pole
+// src_i,c = zhat_i X_i,c0+c (kern 1) or zhat_i^2 (kern 2); one lane per pole.  trans 0:
+// src_j,c = b_j X_j,c0+c at the root lambda_j (positions in pairs[j].x); one lane per root
 __global__ __launch_bounds__(64) void k_fmmv_pack(FmmvPackArgs a, FmmVec v) {
     const Tile t = a.tiles[blockIdx.x];
     const int64_t base = a.off[t.prob];
     const int n = (int)(a.off[t.prob + 1] - base);
     const int i = t.row0 + lane_id();
     if (i >= n) return;
+    if (v.trans == 0) {
+        const int K = clamp_idx(a.origin[base + i], n);
+        const double bj = a.bnorm[base + i];
+        a.pairs[base + i] = make_double2(a.d[base + K] + a.eta[base + i], bj);
+        double *src = v.src + (base + i) * v.m;
+        for (int c = 0; c < v.m; ++c) src[c] = bj * a.X[base + i + (int64_t)(a.c0 + c) * a.ldx];
+        return;
+    }
     const double zh = a.zhat[base + i];
     const double di = a.d[base + i];
     a.pairs[base + i] = make_double2(di, zh);
@@ -86,16 +95,17 @@ __global__ __launch_bounds__(LEAVES ? 64 : 256) void k_fmmv_sources(FmmArgs f, F
     if (lo >= hi) return;  // empty box (never listed)
     const int tid = threadIdx.x;
     const int m = v.m;
-    const double *d = v.d + base;
+    const double2 *d2 = f.dw + base;  // the points' positions in .x (poles, or roots)
+    auto d = [&](int i) { return d2[i].x; };
     const double *src = v.src + base * m;
-    const double a = d[lo], b = d[hi - 1];
+    const double a = d(lo), b = d(hi - 1);
     const double cc = 0.5 * (a + b), hw = 0.5 * (b - a);
     double *node = v.vnode + (int64_t)g * FMM_P;
     double *w = v.vw + (int64_t)g * FMM_P * m;
     if (LEAVES && hi - lo <= FMM_P) {  // few poles: they are their own equivalent sources
         if (tid < FMM_P) {
             const bool in = lo + tid < hi;
-            node[tid] = in ? d[lo + tid] : cc;
+            node[tid] = in ? d(lo + tid) : cc;
             for (int c = 0; c < m; ++c) w[tid * m + c] = in ? src[(int64_t)(lo + tid) * m + c] : 0.0;
         }
         return;
@@ -121,7 +131,7 @@ __global__ __launch_bounds__(LEAVES ? 64 : 256) void k_fmmv_sources(FmmArgs f, F
             double x;
             const double *wk;
             if (LEAVES) {
-                x = d[lo + k];
+                x = d(lo + k);
                 wk = src + (int64_t)(lo + k) * m;
             } else {
                 const int gl = f.box_off[qf] + leaf0 + k / FMM_P;
@@ -340,15 +350,22 @@ struct FvStage {
                    // weights are stored source-major, so 16 threads read a source's row)
 };
 
-__device__ __forceinline__ void fv_fetch(const FmmVec &v, int64_t base, const int *fbox, int4 ch,
-                                         FvStage &st) {
+// TRANS 0 (sums over the roots): a near source is root j, staged as (d_{K_j}, eta_j) for
+// the shifted difference (d_i - d_{K_j}) - eta_j; a far one as (node, 0)
+template <int TRANS>
+__device__ __forceinline__ void fv_fetch(const FmmVec &v, int64_t base, int n, const int *fbox,
+                                         int4 ch, FvStage &st) {
     const int tid = threadIdx.x;
     const int m = v.m;
     if (ch.x == 0) {
-        if (tid < FV_K)
-            st.sd = tid < ch.z ? make_double2(v.d[base + ch.y + tid],
-                                              v.fuse_b ? v.zh[base + ch.y + tid] : 0.0)
-                               : make_double2(0.0, 0.0);
+        if (tid < FV_K) {
+            const int j = ch.y + tid;
+            if (tid >= ch.z) st.sd = make_double2(0.0, 0.0);
+            else if (TRANS == 0)
+                st.sd = make_double2(v.d[base + clamp_idx(v.origin[base + j], n)], v.eta[base + j]);
+            else
+                st.sd = make_double2(v.d[base + j], v.fuse_b ? v.zh[base + j] : 0.0);
+        }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int e = tid + 256 * i, sl = e >> 4, c = e & 15;
@@ -380,6 +397,7 @@ struct FvShared {
     int nch;
 };
 
+template <int TRANS>
 __device__ void fmmv_item_mfma(const SolveArgs &it, const FmmArgs &f, const FmmVec &v, Tile t,
                                FvShared &sh) {
     const int p = t.prob;
@@ -432,8 +450,9 @@ __device__ void fmmv_item_mfma(const SolveArgs &it, const FmmArgs &f, const FmmV
     const int orow = o0 + wv * 16 + (lane & 15);
     const bool ovalid = orow < n;
     const int oc = ovalid ? orow : n - 1;
-    const double ra = v.d[base + clamp_idx(v.origin[base + oc], n)];
-    const double rb = v.eta[base + oc];
+    // the target of the Cauchy row: root (d_K, eta), or (TRANS 0) pole d_i
+    const double ra = TRANS ? v.d[base + clamp_idx(v.origin[base + oc], n)] : v.d[base + oc];
+    const double rb = TRANS ? v.eta[base + oc] : 0.0;
     v4d_f acc = v4d_f{0.0, 0.0, 0.0, 0.0};
     // fuse_b: this lane's share of b's sum for its Cauchy row (the sources it generates
     // entries for), on the VALU beside the multiply: one column does not need the MFMA
@@ -441,7 +460,7 @@ __device__ void fmmv_item_mfma(const SolveArgs &it, const FmmArgs &f, const FmmV
     const bool fb = v.fuse_b != 0;
     FvStage st;
     int4 cur = chunk(0);
-    fv_fetch(v, base, sh.fbox, cur, st);
+    fv_fetch<TRANS>(v, base, n, sh.fbox, cur, st);
     int64_t ent = 0;  // near poles and far sources summed per root (kernel timing)
     for (int ci = 0; ci < nch; ++ci) {
         __syncthreads();  // the previous chunk's reads of Xs/Sd are done
@@ -457,13 +476,13 @@ __device__ void fmmv_item_mfma(const SolveArgs &it, const FmmArgs &f, const FmmV
         ent += nvalid;
         if (ci + 1 < nch) {
             cur = chunk(ci + 1);
-            fv_fetch(v, base, sh.fbox, cur, st);  // in flight during the multiply below
+            fv_fetch<TRANS>(v, base, n, sh.fbox, cur, st);  // in flight during the multiply
         }
 #pragma unroll 4
         for (int kk = 0; kk < FV_K; kk += 4) {
             const int sl = kk + (lane >> 4);
             const double2 sdv = sh.Sd[sl];
-            const double tt = (sdv.x - ra) - rb;
+            const double tt = TRANS ? (sdv.x - ra) - rb : (ra - sdv.x) - sdv.y;
             const double av = (ovalid && sl < nvalid) ? rcp_nr(tt) : 0.0;
             const double bv = sh.Xs[(lane & 15) * FV_LD + sl];
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
@@ -502,6 +521,7 @@ __device__ void fmmv_item_mfma(const SolveArgs &it, const FmmArgs &f, const FmmV
     }
 }
 
+template <int TRANS>
 __global__ __launch_bounds__(256) void k_fmmv_eval_mfma(SolveArgs it, FmmArgs f, FmmVec v,
                                                         Queue *q) {
     __shared__ FvShared sh;
@@ -510,11 +530,11 @@ __global__ __launch_bounds__(256) void k_fmmv_eval_mfma(SolveArgs it, FmmArgs f,
         for (;;) {
             const int item = queue_pull(q, it.ntiles, &slot);
             if (item < 0) break;
-            fmmv_item_mfma(it, f, v, it.tiles[item], sh);
+            fmmv_item_mfma<TRANS>(it, f, v, it.tiles[item], sh);
         }
         queue_leave(q);
     } else if ((int)blockIdx.x < it.ntiles) {
-        fmmv_item_mfma(it, f, v, it.tiles[blockIdx.x], sh);
+        fmmv_item_mfma<TRANS>(it, f, v, it.tiles[blockIdx.x], sh);
     }
 }
 
@@ -651,13 +671,18 @@ hipError_t launch_fmmv_eval(const SolveArgs &it, const FmmArgs &f, const FmmVec 
                             Queue *q, int num_cu, hipStream_t s) {
     if (it.ntiles <= 0) return hipSuccess;
     FmmVec v = v0;
-    const bool mfma = v.kern == 1 && (v.m >= 4 || v.fuse_b);
+    // the MFMA for a dense enough block of columns, and for every sum over the roots
+    const bool mfma = v.kern == 1 && (v.m >= 4 || v.fuse_b || v.trans == 0);
     v.work = trace_work(mfma ? KID_FMMV_EVAL_MFMA : KID_FMMV_EVAL);
-    if (mfma) {  // a dense enough block of columns for the MFMA
+    if (mfma) {
         const dim3 g(q ? min(it.ntiles, num_cu * 4) : it.ntiles);
-        SDC_LAUNCH(KID_FMMV_EVAL_MFMA, k_fmmv_eval_mfma, g, dim3(256), 0, s, it, f, v, q);
+        if (v.trans == 0)
+            SDC_LAUNCH(KID_FMMV_EVAL_MFMA, k_fmmv_eval_mfma<0>, g, dim3(256), 0, s, it, f, v, q);
+        else
+            SDC_LAUNCH(KID_FMMV_EVAL_MFMA, k_fmmv_eval_mfma<1>, g, dim3(256), 0, s, it, f, v, q);
         return hipGetLastError();
     }
+    if (v.trans == 0) return hipErrorInvalidValue;
     const dim3 g(q ? min(it.ntiles, num_cu * max(1, 32 / split)) : it.ntiles), blk(WAVE * split);
     if (v.kern == 2) {
         const size_t lds = sizeof(double) * WAVE * (split - 1) * 1;

@@ -98,18 +98,17 @@ __global__ __launch_bounds__(1024) void k_validate(SolveArgs a, int prob_first) 
 // the secular sums over a pole range [j0, j1): MODE 0 all psi, 1 all phi, 2 split at k
 // ---------------------------------------------------------------------------------------
 // LF: the pole difference is formed in lambda-form, d_j - x with x = d_K + y; otherwise in
-// the shifted form (d_j - d_K) - y (eq. localshift).  P1: the reciprocal gets one Newton
-// step (<= 11 ulp, measured) instead of two.  Following the paper's local shifting (Sec.
-// 4.2.2), a pole more than one tile away from every root of the wavefront (far) takes
-// lambda-form and P1, which is accurate there (eq. farfield); near poles keep the shifted
-// form and two steps.  The ablation without local shifting takes lambda-form for the near
-// poles too but keeps their two Newton steps, so it differs from the default in the form
-// of the differences alone.
+// the shifted form (d_j - d_K) - y (eq. localshift).  Following the paper's local shifting
+// (Sec. 4.2.2), a pole more than one tile away from every root of the wavefront (far) takes
+// lambda-form, which is accurate there (eq. farfield); the near poles keep the shifted form.
+// The ablation without local shifting takes lambda-form for every pole.  Every reciprocal
+// is the hardware estimate refined by one Newton step (relative error <= ~11 ulp,
+// measured), so f is evaluated to within 11 eps (|psi| + |phi|) beyond the rounding of the
+// sums, the order of the stopping test's own tolerance n eps (1 + |psi| + |phi|).
 //
 // Outside the window (where every pole of a range lies on one side of every root), poles
 // are taken two at a time with one shared reciprocal (the FP64 reciprocal issues at a
-// quarter of the FMA rate on gfx950), far ones in lambda-form with one Newton step, near
-// ones in the shifted form with two:
+// quarter of the FMA rate on gfx950):
 //   w0/t0 + w1/t1       = (w0 t1 + w1 t0) / (t0 t1)
 //   w0/t0^2 + w1/t1^2   = (w0 t1 t1 + w1 t0 t0) / (t0 t1)^2
 // t0 and t1 have the same sign, so neither numerator cancels.  The square of the shared
@@ -117,7 +116,7 @@ __global__ __launch_bounds__(1024) void k_validate(SolveArgs a, int prob_first) 
 // t0 t1 does not.  The products need every |t| of the range inside [2^-300, 2^300]; a range
 // outside that (checked once per range for the whole wavefront) takes one reciprocal per
 // pole.
-template <int MODE, bool LF, bool P1>
+template <int MODE, bool LF>
 __device__ __forceinline__ void secular_range(const_double2_ptr dw, int j0, int j1,
                                               int k, double dK, double y, double x,
                                               double &psi, double &dpsi, double &phi,
@@ -126,7 +125,7 @@ __device__ __forceinline__ void secular_range(const_double2_ptr dw, int j0, int 
     {                                                                 \
         const double2 pw = (PW);                                      \
         const double tt = LF ? pw.x - x : (pw.x - dK) - y;            \
-        const double r = P1 ? rcp_nr1(tt) : rcp_nr(tt);               \
+        const double r = rcp_nr1(tt);                                 \
         const double wr = pw.y * r;                                   \
         if (MODE == 0) {                                              \
             psi += wr;                                                \
@@ -151,7 +150,7 @@ __device__ __forceinline__ void secular_range(const_double2_ptr dw, int j0, int 
         const double2 pa = (PA), pb = (PB);                           \
         const double t0 = LF ? pa.x - x : (pa.x - dK) - y;            \
         const double t1 = LF ? pb.x - x : (pb.x - dK) - y;            \
-        const double R = P1 ? rcp_nr1(t0 * t1) : rcp_nr(t0 * t1);     \
+        const double R = rcp_nr1(t0 * t1);                            \
         const double u0 = pa.y * t1, u1 = pb.y * t0;                  \
         const double num2 = __builtin_fma(u0, t1, u1 * t0);           \
         if (MODE == 0) {                                              \
@@ -277,21 +276,21 @@ __device__ __forceinline__ void secular_sums(const double2 *__restrict__ dwg, in
     const double x = dK + y;
     const int f0 = max(kmin - TILE, 0), f1 = min(kmax + 1 + TILE, n);
 #define SDC_CLIP(A, B) max((A), p0), min((B), p1)
-    secular_range<0, true, true>(dw, SDC_CLIP(0, f0), k, dK, y, x, psi, dpsi, phi, dphi);
+    secular_range<0, true>(dw, SDC_CLIP(0, f0), k, dK, y, x, psi, dpsi, phi, dphi);
     if (unsh) {  // ablation: near poles and the window in lambda-form as well
-        secular_range<0, true, false>(dw, SDC_CLIP(f0, kmin), k, dK, y, x, psi, dpsi, phi, dphi);
-        secular_range<2, true, false>(dw, SDC_CLIP(kmin, kmax + 1), k, dK, y, x, psi, dpsi, phi,
+        secular_range<0, true>(dw, SDC_CLIP(f0, kmin), k, dK, y, x, psi, dpsi, phi, dphi);
+        secular_range<2, true>(dw, SDC_CLIP(kmin, kmax + 1), k, dK, y, x, psi, dpsi, phi,
                                       dphi);
-        secular_range<1, true, false>(dw, SDC_CLIP(kmax + 1, f1), k, dK, y, x, psi, dpsi, phi,
+        secular_range<1, true>(dw, SDC_CLIP(kmax + 1, f1), k, dK, y, x, psi, dpsi, phi,
                                       dphi);
     } else {
-        secular_range<0, false, false>(dw, SDC_CLIP(f0, kmin), k, dK, y, x, psi, dpsi, phi, dphi);
-        secular_range<2, false, false>(dw, SDC_CLIP(kmin, kmax + 1), k, dK, y, x, psi, dpsi, phi,
+        secular_range<0, false>(dw, SDC_CLIP(f0, kmin), k, dK, y, x, psi, dpsi, phi, dphi);
+        secular_range<2, false>(dw, SDC_CLIP(kmin, kmax + 1), k, dK, y, x, psi, dpsi, phi,
                                        dphi);
-        secular_range<1, false, false>(dw, SDC_CLIP(kmax + 1, f1), k, dK, y, x, psi, dpsi, phi,
+        secular_range<1, false>(dw, SDC_CLIP(kmax + 1, f1), k, dK, y, x, psi, dpsi, phi,
                                        dphi);
     }
-    secular_range<1, true, true>(dw, SDC_CLIP(f1, n), k, dK, y, x, psi, dpsi, phi, dphi);
+    secular_range<1, true>(dw, SDC_CLIP(f1, n), k, dK, y, x, psi, dpsi, phi, dphi);
 #undef SDC_CLIP
 }
 
@@ -319,6 +318,32 @@ __device__ __forceinline__ void split_reduce4(double *red, int S, double &a, dou
     d = s.w;
 }
 
+// The far field of the boxes in target leaf L's local expansion at x: four Chebyshev series
+// on the target interval (psi, psi', phi, phi'), evaluated together by Clenshaw's
+// recurrence (four independent chains; one wavefront of a work item adds them).
+__device__ __forceinline__ void local_series(const FmmArgs &f, int L, double x, double &psi,
+                                             double &dpsi, double &phi, double &dphi) {
+    const double2 cw = f.loc_ab[L];
+    const double t = cw.y > 0.0 ? fmin(1.0, fmax(-1.0, (x - cw.x) / cw.y)) : 0.0;
+    const const_double_ptr c = as_const(f.loc + (int64_t)L * FMM_LOC);
+    double r[4];
+#pragma unroll
+    for (int fn = 0; fn < 4; ++fn) {
+        double b1 = 0.0, b2 = 0.0;
+#pragma unroll
+        for (int j = FMM_P - 1; j >= 1; --j) {
+            const double b0 = __builtin_fma(2.0 * t, b1, c[fn * FMM_P + j] - b2);
+            b2 = b1;
+            b1 = b0;
+        }
+        r[fn] = __builtin_fma(t, b1, c[fn * FMM_P] - b2);
+    }
+    psi += r[0];
+    dpsi += r[1];
+    phi += r[2];
+    dphi += r[3];
+}
+
 // The same sums from the triangular FMM lists of target leaf L: near leaves directly
 // (routed by the window as above), far boxes through their equivalent
 // sources in lambda-form, left boxes into psi and right boxes into phi.  With S wavefronts
@@ -343,58 +368,37 @@ __device__ __forceinline__ void fmm_sums(const FmmArgs &f, int L, int nn, int nl
         const int hi0 = wave_uniform(f.near_hi[(int64_t)L * FMM_NEAR_MAX + e]);
         const int lo = lo0 + (int)(((int64_t)(hi0 - lo0) * wv) >> sh);  // S = 2^sh
         const int hi = lo0 + (int)(((int64_t)(hi0 - lo0) * (wv + 1)) >> sh);
-        secular_range<0, true, true>(dw, lo, min(hi, f0), k, dK, y, x, psi, dpsi, phi, dphi);
+        secular_range<0, true>(dw, lo, min(hi, f0), k, dK, y, x, psi, dpsi, phi, dphi);
         if (unsh) {  // ablation: near poles and the window in lambda-form as well
-            secular_range<0, true, false>(dw, max(lo, f0), min(hi, kmin), k, dK, y, x, psi, dpsi,
+            secular_range<0, true>(dw, max(lo, f0), min(hi, kmin), k, dK, y, x, psi, dpsi,
                                           phi, dphi);
-            secular_range<2, true, false>(dw, max(lo, kmin), min(hi, kmax + 1), k, dK, y, x, psi,
+            secular_range<2, true>(dw, max(lo, kmin), min(hi, kmax + 1), k, dK, y, x, psi,
                                           dpsi, phi, dphi);
-            secular_range<1, true, false>(dw, max(lo, kmax + 1), min(hi, f1), k, dK, y, x, psi,
+            secular_range<1, true>(dw, max(lo, kmax + 1), min(hi, f1), k, dK, y, x, psi,
                                           dpsi, phi, dphi);
         } else {
-            secular_range<0, false, false>(dw, max(lo, f0), min(hi, kmin), k, dK, y, x, psi, dpsi,
+            secular_range<0, false>(dw, max(lo, f0), min(hi, kmin), k, dK, y, x, psi, dpsi,
                                            phi, dphi);
-            secular_range<2, false, false>(dw, max(lo, kmin), min(hi, kmax + 1), k, dK, y, x, psi,
+            secular_range<2, false>(dw, max(lo, kmin), min(hi, kmax + 1), k, dK, y, x, psi,
                                            dpsi, phi, dphi);
-            secular_range<1, false, false>(dw, max(lo, kmax + 1), min(hi, f1), k, dK, y, x, psi,
+            secular_range<1, false>(dw, max(lo, kmax + 1), min(hi, f1), k, dK, y, x, psi,
                                            dpsi, phi, dphi);
         }
-        secular_range<1, true, true>(dw, max(lo, f1), hi, k, dK, y, x, psi, dpsi, phi, dphi);
+        secular_range<1, true>(dw, max(lo, f1), hi, k, dK, y, x, psi, dpsi, phi, dphi);
     }
     // far boxes outside the leaf's local expansion, through their equivalent sources
     for (int e = wv; e < nl; e += S) {
         const int g = wave_uniform(f.far_ld[(int64_t)L * FMM_FAR_MAX + e]);
-        secular_range<0, true, true>(as_const(f.eq + (int64_t)g * FMM_P), 0, FMM_P, k, dK, y, x, psi,
+        secular_range<0, true>(as_const(f.eq + (int64_t)g * FMM_P), 0, FMM_P, k, dK, y, x, psi,
                                dpsi, phi, dphi);
     }
     for (int e = wv; e < nr; e += S) {
         const int g = wave_uniform(f.far_rd[(int64_t)L * FMM_FAR_MAX + e]);
-        secular_range<1, true, true>(as_const(f.eq + (int64_t)g * FMM_P), 0, FMM_P, k, dK, y, x, psi,
+        secular_range<1, true>(as_const(f.eq + (int64_t)g * FMM_P), 0, FMM_P, k, dK, y, x, psi,
                                dpsi, phi, dphi);
     }
-    // the others through the leaf's local expansion: four Chebyshev series on the target
-    // interval (Clenshaw), added by the first wavefront only
-    if (wv == 0) {
-        const double2 cw = f.loc_ab[L];
-        const double t = cw.y > 0.0 ? fmin(1.0, fmax(-1.0, (x - cw.x) / cw.y)) : 0.0;
-        const const_double_ptr c = as_const(f.loc + (int64_t)L * FMM_LOC);
-        double r[4];
-#pragma unroll
-        for (int fn = 0; fn < 4; ++fn) {
-            double b1 = 0.0, b2 = 0.0;
-#pragma unroll
-            for (int j = FMM_P - 1; j >= 1; --j) {
-                const double b0 = __builtin_fma(2.0 * t, b1, c[fn * FMM_P + j] - b2);
-                b2 = b1;
-                b1 = b0;
-            }
-            r[fn] = __builtin_fma(t, b1, c[fn * FMM_P] - b2);
-        }
-        psi += r[0];
-        dpsi += r[1];
-        phi += r[2];
-        dphi += r[3];
-    }
+    // the others through the leaf's local expansion (the first wavefront)
+    if (wv == 0) local_series(f, L, x, psi, dpsi, phi, dphi);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -408,9 +412,9 @@ __device__ __forceinline__ void fmm_sums(const FmmArgs &f, int L, int nn, int nl
 // step.  The teams of the S wavefronts of a workgroup are formed identically.
 // ---------------------------------------------------------------------------------------
 
-// the poles [j0, j1) that lane `sub` of a team of g takes, each with its own reciprocal
-// (two Newton steps); positive weights, so a term's sign routes it: negative terms (pole
-// left of the iterate) to psi, positive ones to phi.  LF: lambda-form differences
+// the poles [j0, j1) that lane `sub` of a team of g takes, each with its own reciprocal;
+// positive weights, so a term's sign routes it: negative terms (pole left of the iterate)
+// to psi, positive ones to phi.  LF: lambda-form differences
 template <bool LF>
 __device__ __forceinline__ void team_poles(const double2 *__restrict__ dw, int j0, int j1,
                                            int sub, int g, double dK, double y, double x,
@@ -419,7 +423,7 @@ __device__ __forceinline__ void team_poles(const double2 *__restrict__ dw, int j
 #pragma unroll 4
     for (int j = j0 + sub; j < j1; j += g) {
         const double2 pw = dw[j];
-        const double r = rcp_nr(LF ? pw.x - x : (pw.x - dK) - y);
+        const double r = rcp_nr1(LF ? pw.x - x : (pw.x - dK) - y);
         const double wr = pw.y * r;
         const double wl = __builtin_fmin(wr, 0.0), wg = __builtin_fmax(wr, 0.0);
         psi += wl;
@@ -429,8 +433,8 @@ __device__ __forceinline__ void team_poles(const double2 *__restrict__ dw, int j
     }
 }
 
-// equivalent sources of one far box (weights of either sign), lambda-form, one Newton
-// step, all into psi (LEFT) or all into phi
+// equivalent sources of one far box (weights of either sign), lambda-form, all into psi
+// (LEFT) or all into phi
 template <bool LEFT>
 __device__ __forceinline__ void team_sources(const double2 *__restrict__ eq, int sub, int g,
                                              double x, double &s0, double &s1) {
@@ -482,8 +486,8 @@ __device__ __forceinline__ int wave_max(int v) {
 
 // The sums of secular_sums / fmm_sums for teams of g lanes (see above): lane `sub` of a
 // team takes every g-th pole of the wavefront's share of each range, every pole in the
-// shifted form (lambda-form in the unshifted ablation) with two Newton steps; far boxes
-// through their equivalent sources; the local expansion by the team's first lane.
+// shifted form (lambda-form in the unshifted ablation); far boxes through their equivalent
+// sources; the local expansion by the team's first lane.
 __device__ __forceinline__ void team_sums(const FmmArgs *fm, int L, int nn, int nl, int nr,
                                           const double2 *__restrict__ dw, int p0, int p1,
                                           double dK, double y, int wv, int S, int sub, int g,
@@ -514,27 +518,7 @@ __device__ __forceinline__ void team_sums(const FmmArgs *fm, int L, int nn, int 
         const int gb = wave_uniform(f.far_rd[(int64_t)L * FMM_FAR_MAX + e]);
         team_sources<false>(f.eq + (int64_t)gb * FMM_P, sub, g, x, phi, dphi);
     }
-    if (wv == 0 && sub == 0) {  // the local expansion, as in fmm_sums
-        const double2 cw = f.loc_ab[L];
-        const double t = cw.y > 0.0 ? fmin(1.0, fmax(-1.0, (x - cw.x) / cw.y)) : 0.0;
-        const const_double_ptr c = as_const(f.loc + (int64_t)L * FMM_LOC);
-        double r[4];
-#pragma unroll
-        for (int fn = 0; fn < 4; ++fn) {
-            double b1 = 0.0, b2 = 0.0;
-#pragma unroll
-            for (int j = FMM_P - 1; j >= 1; --j) {
-                const double b0 = __builtin_fma(2.0 * t, b1, c[fn * FMM_P + j] - b2);
-                b2 = b1;
-                b1 = b0;
-            }
-            r[fn] = __builtin_fma(t, b1, c[fn * FMM_P] - b2);
-        }
-        psi += r[0];
-        dpsi += r[1];
-        phi += r[2];
-        dphi += r[3];
-    }
+    if (wv == 0 && sub == 0) local_series(f, L, x, psi, dpsi, phi, dphi);  // the team's first lane
 }
 
 // One wavefront solves the roots [c0, c1) of one problem.  Each lane holds one live root;
@@ -593,8 +577,9 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
         }
         const int nfar = (nl > wv ? (nl - wv + S - 1) / S : 0) + (nr > wv ? (nr - wv + S - 1) / S : 0);
         pairs_per_pass += (int64_t)FMM_P * nfar;
-        // the local expansion (four 16-term Clenshaw series, 128 flops) counts as 18 pairs
-        if (wv == 0) pairs_per_pass += 18;
+        // the local expansion (four 16-term Clenshaw series, each 15 steps of a subtraction
+        // and an FMA and a last FMA: 192 flops) counts as 27 pairs
+        if (wv == 0) pairs_per_pass += 27;
     }
     unsigned long long work = 0, live = 0, slots = 0;
 

@@ -145,3 +145,49 @@ def test_fmm_vectors_mixed_batch(orc, persistent):
         a, e = int(batch.off[p]), int(batch.off[p + 1])
         nx = np.linalg.norm(X[a:e], axis=0).max()
         assert np.abs(Yf[a:e] - Yd[a:e]).max() <= 1e-12 * nx, p
+
+
+# ------------------------------------------------ the FMM of the sums over the roots (Qhat X)
+@pytest.mark.parametrize("kind,n,m,leaf", [("clustered", 4096, 5, 64), ("clustered", 4096, 17, 256),
+                                           ("uniform", 3000, 16, 64), ("clustered", 16384, 8, 64)])
+def test_fmm_apply_untransposed_vs_oracle(orc, kind, n, m, leaf):
+    """Y = Qhat X through the triangular FMM over the roots (method 2: near roots in the
+    shifted form (d_i - d_{K_j}) - eta_j, far root boxes through Chebyshev equivalent
+    sources at their lambda), fed the oracle's (eta, origin, zhat, b), against the oracle's
+    product: sampled rows to 1e-12 sum_j |Qhat_ij X_j| (Sec. 4.3, Alg. 4), every row
+    against the direct MFMA apply to 1e-12 ||X_c||_2, and the round trip
+    Qhat (Qhat^T X) = X.  m = 17 takes two column passes."""
+    from tests import gpu_pipeline as gp
+    batch, X = gen.small_batch([n], seed=65, kind=kind, m=m)
+    pr = batch.problem(0)
+    lam, eta, org, its, st = orc.secular(pr.d, pr.z, pr.rho)
+    zo = orc.loewner(pr.d, pr.z, pr.rho, eta, org)
+    bo = orc.bnorm(pr.d, zo, eta, org)
+    Yf = gp.apply_from(batch, zo, bo, eta, org, X, 0, opts=_opts(2, leaf=leaf))
+    Yd = gp.apply_from(batch, zo, bo, eta, org, X, 0, opts=_opts(1))
+    rng = np.random.default_rng(4)
+    rows = np.unique(np.r_[0, n - 1, rng.choice(n, 62, replace=False)])
+    Yo = orc.cauchy_apply(pr.d, zo, bo, eta, org, X, trans=0, rows=rows)
+    C = 1.0 / ((pr.d[rows][:, None] - pr.d[org][None, :]) - eta[None, :])
+    Qabs = np.abs(zo[rows][:, None] * C * bo[None, :])
+    tol = 1e-12 * (Qabs @ np.abs(X))
+    assert np.all(np.abs(Yf[rows] - Yo) <= tol), np.max(np.abs(Yf[rows] - Yo) / tol)
+    assert np.abs(Yf - Yd).max() <= 1e-12 * np.linalg.norm(X, axis=0).max()
+    Z = gp.apply_from(batch, zo, bo, eta, org, X, 1, opts=_opts(2, leaf=leaf))
+    back = gp.apply_from(batch, zo, bo, eta, org, Z, 0, opts=_opts(2, leaf=leaf))
+    assert np.abs(back - X).max() <= 1e-12 * np.linalg.norm(X, axis=0).max()
+
+
+@pytest.mark.parametrize("persistent", [1, 0])
+def test_fmm_apply_untransposed_mixed_batch(orc, persistent):
+    """FMM problems and direct ones in one Qhat X call agree with the all-direct path."""
+    from tests import gpu_pipeline as gp
+    batch, X = gen.small_batch([100, 1500, 5000, 64, 2048, 700], seed=66, kind="clustered", m=9)
+    ref = orc.solve_batch(batch)
+    args = (batch, ref["zhat"], ref["b"], ref["eta"], ref["origin"], X, 0)
+    Yf = gp.apply_from(*args, opts=_opts(2, persistent))
+    Yd = gp.apply_from(*args, opts=_opts(1, persistent))
+    for p in range(batch.nprob):
+        a, e = int(batch.off[p]), int(batch.off[p + 1])
+        nx = np.linalg.norm(X[a:e], axis=0).max()
+        assert np.abs(Yf[a:e] - Yd[a:e]).max() <= 1e-12 * nx, p
