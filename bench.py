@@ -109,23 +109,26 @@ def collect_counters(native):
     return kw, lanes
 
 
-def kernel_pass(native, run, steps):
+def kernel_pass(native, run, steps, counters=True):
     """Per-kernel measurement in two passes of `steps` steps each: HIP events alone (the
     kernel times; no counter atomics in the kernels), then the device counters alone (the
-    work).  Returns ({kernel: (ms, launches)}, work, live-lane fractions)."""
+    work; skipped with counters=False, so that every launch of a profiled run is one of the
+    timed kind).  Returns ({kernel: (ms, launches)}, work, live-lane fractions)."""
     import torch
     native.kernel_times()  # drop anything recorded before
     native.kernel_timing(True, mode="events")
+    kw, lanes = {}, {}
     try:
         for _ in range(steps):
             run()
         torch.cuda.synchronize()
         kt = native.kernel_times()
-        native.kernel_timing(True, mode="counters")
-        for _ in range(steps):
-            run()
-        torch.cuda.synchronize()
-        kw, lanes = collect_counters(native)
+        if counters:
+            native.kernel_timing(True, mode="counters")
+            for _ in range(steps):
+                run()
+            torch.cuda.synchronize()
+            kw, lanes = collect_counters(native)
     finally:
         native.kernel_timing(False)
     return kt, kw, lanes
@@ -269,6 +272,10 @@ def parse():
     ap.add_argument("--tune-cache", default=None,
                     help="file that keeps the autotuner's choices between runs (the library's "
                          "SUPERDC_TUNE_CACHE); a run that finds its shapes there does not tune")
+    ap.add_argument("--profile", action="store_true",
+                    help="the run a kernel-trace profile wraps (conquer): tuned launch shapes "
+                         "only (no heuristic-shape timing) and no device-counter pass, so the "
+                         "profiler's per-kernel averages cover the launches bench.py times")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 512 MiB device-to-device copy (the reference kernel "
                          "that scales the profiler's FETCH_SIZE / WRITE_SIZE counters)")
@@ -1080,12 +1087,12 @@ def bench_conquer(args):
         return float(np.mean(tot)), phases, counts
 
     # the heuristic launch shapes first, then every level's batch tuned on its own problems
-    h_ms, _, _ = timed(opts1, args.steps, args.warmup)
+    h_ms = None if args.profile else timed(opts1, args.steps, args.warmup)[0]
     native.hss_set_timing(plan, False)
     tuned_shapes = native.hss_autotune(ctx, plan, gens, opts=opts1)
     native.hss_set_timing(plan, True)
     ms, phases, counts = timed(opts1, args.steps, args.warmup)
-    note(f"conquer batched {ms:.2f} ms/step (heuristic shapes {h_ms:.2f})")
+    note(f"conquer batched {ms:.2f} ms/step (heuristic shapes {h_ms})")
     status = int(out["status"].cpu().numpy()[0])
     it_raw = native.hss_iterations(plan).cpu().numpy()
     iters = (it_raw & ITER_COUNT_MASK).astype(np.float64)
@@ -1168,7 +1175,8 @@ def bench_conquer(args):
         graph_ms = f"capture failed: {exc!r}"
     # per-kernel timing and work (phase events off)
     kt, kw, lanes = kernel_pass(native, lambda: native.hss_conquer(ctx, plan, gens, opts=opts1,
-                                                                   out=out), args.steps)
+                                                                   out=out), args.steps,
+                                counters=not args.profile)
     kflops = conquer_kernel_flops(tree, iters, args.fmm_crossover or FMM_CROSSOVER)
     kflops.update(counted_flops(kw, args.steps))  # solvers and apply kernels: device counts
     kernels, roofline = kernel_roofline(kt, kflops, args.steps, "conquer")
