@@ -188,16 +188,9 @@ __global__ __launch_bounds__(256) void k_apply_mfma(ApplyArgs a, Queue *q) {
     __shared__ double Xs[16 * NCT * AP_LD];
     __shared__ double2 Sd[AP_K];
     __shared__ int slot;
-    if (q) {
-        for (;;) {
-            const int item = queue_pull(q, a.ntiles, &slot);
-            if (item < 0) break;
-            apply_tile_mfma<TRANS, NCT>(a, a.tiles[item], Xs, Sd);
-        }
-        queue_leave(q);
-    } else if ((int)blockIdx.x < a.ntiles) {
-        apply_tile_mfma<TRANS, NCT>(a, a.tiles[blockIdx.x], Xs, Sd);
-    }
+    for_each_item(q, a.ntiles, &slot, [&](int item) {
+        apply_tile_mfma<TRANS, NCT>(a, a.tiles[item], Xs, Sd);
+    });
 }
 
 // ---------------------------------------------------------------------------------------
@@ -297,16 +290,9 @@ __global__ __launch_bounds__(WAVE * AV_W) void k_apply_valu(ApplyArgs a, Queue *
     __shared__ double2 Sd[AV_W * WAVE];
     __shared__ int slot;
     double *red = Xs;
-    if (q) {
-        for (;;) {
-            const int item = queue_pull(q, a.ntiles, &slot);
-            if (item < 0) break;
-            apply_tile_valu<TRANS>(a, a.tiles[item], Xs, Sd, red);
-        }
-        queue_leave(q);
-    } else if ((int)blockIdx.x < a.ntiles) {
-        apply_tile_valu<TRANS>(a, a.tiles[blockIdx.x], Xs, Sd, red);
-    }
+    for_each_item(q, a.ntiles, &slot, [&](int item) {
+        apply_tile_valu<TRANS>(a, a.tiles[item], Xs, Sd, red);
+    });
 }
 
 hipError_t launch_apply(const ApplyArgs &a0, int use_mfma, Queue *q, int grid, hipStream_t s) {

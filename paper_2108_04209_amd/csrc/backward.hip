@@ -154,18 +154,10 @@ template <bool PROJ, int PASS>
 __global__ __launch_bounds__(1024) void k_bwd(BwdArgs a, Queue *q) {
     extern __shared__ double4 red4[];
     __shared__ int slot;
-    if (q) {
-        for (;;) {
-            const int item = queue_pull(q, a.ntiles, &slot);
-            if (item < 0) break;
-            if (PASS == 1) bwd_roots_tile<PROJ>(a, a.tiles[item], red4);
-            else bwd_poles_tile<PROJ>(a, a.tiles[item], red4);
-        }
-        queue_leave(q);
-    } else if ((int)blockIdx.x < a.ntiles) {
-        if (PASS == 1) bwd_roots_tile<PROJ>(a, a.tiles[blockIdx.x], red4);
-        else bwd_poles_tile<PROJ>(a, a.tiles[blockIdx.x], red4);
-    }
+    for_each_item(q, a.ntiles, &slot, [&](int item) {
+        if (PASS == 1) bwd_roots_tile<PROJ>(a, a.tiles[item], red4);
+        else bwd_poles_tile<PROJ>(a, a.tiles[item], red4);
+    });
 }
 
 // g_rho[p] = sum_k alpha_k / rho_p^2, fixed-order block reduction

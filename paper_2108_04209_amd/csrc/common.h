@@ -136,6 +136,20 @@ __device__ __forceinline__ void queue_leave(Queue *q) {
     }
 }
 
+// The work items of a launch with one call site of the body: persistent (q != nullptr)
+// workgroups pull items until the queue runs dry and then leave it; otherwise workgroup b
+// takes item b.  One inlined copy of a large body (rather than one per branch) keeps a
+// kernel's code within the instruction cache.
+template <class Body>
+__device__ __forceinline__ void for_each_item(Queue *q, int nitems, int *slot, Body &&body) {
+    int item = q ? queue_pull(q, nitems, slot) : ((int)blockIdx.x < nitems ? (int)blockIdx.x : -1);
+    while (item >= 0) {
+        body(item);
+        item = q ? queue_pull(q, nitems, slot) : -1;
+    }
+    if (q) queue_leave(q);
+}
+
 // ----------------------------------------------------------------------------------
 // optional per-kernel timing (trace.cpp): a scope records HIP events around one launch
 // ----------------------------------------------------------------------------------

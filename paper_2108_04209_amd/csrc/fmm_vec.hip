@@ -308,16 +308,9 @@ template <int KERN, int NC>
 __global__ __launch_bounds__(512) void k_fmmv_eval(SolveArgs it, FmmArgs f, FmmVec v, Queue *q) {
     extern __shared__ double red[];
     __shared__ int slot;
-    if (q) {
-        for (;;) {
-            const int item = queue_pull(q, it.ntiles, &slot);
-            if (item < 0) break;
-            fmmv_item<KERN, NC>(it, f, v, it.tiles[item], red);
-        }
-        queue_leave(q);
-    } else if ((int)blockIdx.x < it.ntiles) {
-        fmmv_item<KERN, NC>(it, f, v, it.tiles[blockIdx.x], red);
-    }
+    for_each_item(q, it.ntiles, &slot, [&](int item) {
+        fmmv_item<KERN, NC>(it, f, v, it.tiles[item], red);
+    });
 }
 
 // ---------------------------------------------------------------------------------------
@@ -526,16 +519,9 @@ __global__ __launch_bounds__(256) void k_fmmv_eval_mfma(SolveArgs it, FmmArgs f,
                                                         Queue *q) {
     __shared__ FvShared sh;
     __shared__ int slot;
-    if (q) {
-        for (;;) {
-            const int item = queue_pull(q, it.ntiles, &slot);
-            if (item < 0) break;
-            fmmv_item_mfma<TRANS>(it, f, v, it.tiles[item], sh);
-        }
-        queue_leave(q);
-    } else if ((int)blockIdx.x < it.ntiles) {
-        fmmv_item_mfma<TRANS>(it, f, v, it.tiles[blockIdx.x], sh);
-    }
+    for_each_item(q, it.ntiles, &slot, [&](int item) {
+        fmmv_item_mfma<TRANS>(it, f, v, it.tiles[item], sh);
+    });
 }
 
 // ---------------------------------------------------------------------------------------

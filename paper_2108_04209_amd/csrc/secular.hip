@@ -294,6 +294,18 @@ __device__ __forceinline__ void secular_sums(const double2 *__restrict__ dwg, in
 #undef SDC_CLIP
 }
 
+// The same sums over the poles [p0, p1) as one sign-routed range (every pole in the shifted
+// form; lambda-form with LF): the FMM solver's fallback for a leaf whose lists overflowed,
+// kept to one loop so that the rare path adds little code to that kernel.
+template <bool LF>
+__device__ __forceinline__ void sign_routed_sums(const double2 *__restrict__ dwg, int p0, int p1,
+                                                 int k, double dK, double y, double &psi,
+                                                 double &dpsi, double &phi, double &dphi) {
+    psi = dpsi = phi = dphi = 0.0;
+    secular_range<2, LF>(as_const(dwg), wave_uniform(p0), wave_uniform(p1), k, dK, y, dK + y,
+                         psi, dpsi, phi, dphi);
+}
+
 // Combine the partial sums of the S wavefronts of a workgroup through LDS, in wavefront
 // order, so every wavefront ends with the same, reproducible totals.
 __device__ __forceinline__ void split_reduce4(double *red, int S, double &a, double &b,
@@ -530,7 +542,7 @@ __device__ __forceinline__ void team_sums(const FmmArgs *fm, int L, int nn, int 
 // With S = blockDim.x / 64 > 1 the S wavefronts of the workgroup carry identical copies of
 // the lane states, each sums 1/S of the poles, and the partial sums are combined before
 // the (identical) update; wavefront 0 writes the results.
-template <bool FMM>
+template <bool FMM, bool UNSH>
 __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const FmmArgs *fm) {
     const int p = t.prob;
     const int64_t base = a.off[p];
@@ -555,7 +567,7 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
     const double z2 = a.z2[p];
     const double eps = 2.220446049250313e-16;
     const double tol = a.stop_c * (double)n * eps;
-    const bool unsh = a.unshifted != 0;  // ablation: the iterate lives in lambda's precision
+    const bool unsh = UNSH;  // ablation: the iterate lives in lambda's precision
     // FMM: the target leaf of this chunk and its list sizes (-1: fall back to direct sums)
     int L = 0, nn = -1, nl = 0, nr = 0;
     if (FMM) {
@@ -662,6 +674,8 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
             if (FMM && nn >= 0)
                 fmm_sums(*fm, L, nn, nl, nr, dw, kmin, kmax, k, dK, y, wv, S, unsh, psi, dpsi, phi,
                          dphi);
+            else if (FMM)  // overflowed lists (rare): every pole, routed by sign, one loop
+                sign_routed_sums<UNSH>(dw, p0, p1, k, dK, y, psi, dpsi, phi, dphi);
             else
                 secular_sums(dw, n, p0, p1, kmin, kmax, k, dK, y, unsh, psi, dpsi, phi, dphi);
         }
@@ -785,37 +799,26 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
     }
 }
 
-// blockDim.x = 64 S (S = 1, 2, 4, 8, 16); dynamic LDS: 32 S bytes per lane (S > 1)
+// blockDim.x = 64 S (S = 1, 2, 4, 8, 16); dynamic LDS: 32 S bytes per lane (S > 1).
+// UNSH: the unshifted ablation, a kernel of its own so that its code stays out of the other
+template <bool UNSH>
 __global__ __launch_bounds__(1024) void k_secular(SolveArgs a, Queue *q) {
     extern __shared__ double red[];
     __shared__ int slot;
-    if (q) {
-        for (;;) {
-            const int item = queue_pull(q, a.ntiles, &slot);
-            if (item < 0) break;
-            secular_chunk<false>(a, a.tiles[item], red, nullptr);
-        }
-        queue_leave(q);
-    } else if ((int)blockIdx.x < a.ntiles) {
-        secular_chunk<false>(a, a.tiles[blockIdx.x], red, nullptr);
-    }
+    for_each_item(q, a.ntiles, &slot, [&](int item) {
+        secular_chunk<false, UNSH>(a, a.tiles[item], red, nullptr);
+    });
 }
 
 // FMM problems: one work item per 64-root piece of a target leaf; blockDim.x = 64 S with
 // the same dynamic LDS as k_secular
+template <bool UNSH>
 __global__ __launch_bounds__(512) void k_secular_fmm(SolveArgs a, FmmArgs f, Queue *q) {
     extern __shared__ double red[];
     __shared__ int slot;
-    if (q) {
-        for (;;) {
-            const int item = queue_pull(q, a.ntiles, &slot);
-            if (item < 0) break;
-            secular_chunk<true>(a, a.tiles[item], red, &f);
-        }
-        queue_leave(q);
-    } else if ((int)blockIdx.x < a.ntiles) {
-        secular_chunk<true>(a, a.tiles[blockIdx.x], red, &f);
-    }
+    for_each_item(q, a.ntiles, &slot, [&](int item) {
+        secular_chunk<true, UNSH>(a, a.tiles[item], red, &f);
+    });
 }
 
 hipError_t launch_secular_fmm(const SolveArgs &a, const FmmArgs &f, int split, Queue *q,
@@ -823,8 +826,12 @@ hipError_t launch_secular_fmm(const SolveArgs &a, const FmmArgs &f, int split, Q
     if (a.ntiles <= 0) return hipSuccess;
     if (split < 1 || split > 8 || (split & (split - 1))) return hipErrorInvalidValue;
     const size_t lds = split > 1 ? sizeof(double4) * WAVE * split : 0;
-    SDC_LAUNCH(KID_SECULAR_FMM, k_secular_fmm, dim3(q ? grid : a.ntiles), dim3(WAVE * split), lds, s, a,
-                       f, q);
+    if (a.unshifted)
+        SDC_LAUNCH(KID_SECULAR_FMM, k_secular_fmm<true>, dim3(q ? grid : a.ntiles),
+                   dim3(WAVE * split), lds, s, a, f, q);
+    else
+        SDC_LAUNCH(KID_SECULAR_FMM, k_secular_fmm<false>, dim3(q ? grid : a.ntiles),
+                   dim3(WAVE * split), lds, s, a, f, q);
     return hipGetLastError();
 }
 
@@ -838,7 +845,12 @@ hipError_t launch_validate(const SolveArgs &a, int prob_first, int nprob, int ma
 hipError_t launch_secular(const SolveArgs &a, int split, Queue *q, int grid, hipStream_t s) {
     if (a.ntiles <= 0) return hipSuccess;
     const size_t lds = split > 1 ? sizeof(double4) * WAVE * split : 0;
-    SDC_LAUNCH(KID_SECULAR, k_secular, dim3(q ? grid : a.ntiles), dim3(WAVE * split), lds, s, a, q);
+    if (a.unshifted)
+        SDC_LAUNCH(KID_SECULAR, k_secular<true>, dim3(q ? grid : a.ntiles), dim3(WAVE * split),
+                   lds, s, a, q);
+    else
+        SDC_LAUNCH(KID_SECULAR, k_secular<false>, dim3(q ? grid : a.ntiles), dim3(WAVE * split),
+                   lds, s, a, q);
     return hipGetLastError();
 }
 

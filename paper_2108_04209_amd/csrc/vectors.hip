@@ -355,46 +355,25 @@ __device__ void bnorm_tile(const VecArgs &a, Tile t, double4 *red) {
 __global__ __launch_bounds__(1024) void k_loewner(VecArgs a, Queue *q) {
     extern __shared__ double4 red4[];
     __shared__ int slot;
-    if (q) {
-        for (;;) {
-            const int item = queue_pull(q, a.ntiles, &slot);
-            if (item < 0) break;
-            loewner_tile(a, a.tiles[item], red4);
-        }
-        queue_leave(q);
-    } else if ((int)blockIdx.x < a.ntiles) {
-        loewner_tile(a, a.tiles[blockIdx.x], red4);
-    }
+    for_each_item(q, a.ntiles, &slot, [&](int item) {
+        loewner_tile(a, a.tiles[item], red4);
+    });
 }
 
 __global__ __launch_bounds__(1024) void k_bnorm(VecArgs a, Queue *q) {
     extern __shared__ double4 red4[];
     __shared__ int slot;
-    if (q) {
-        for (;;) {
-            const int item = queue_pull(q, a.ntiles, &slot);
-            if (item < 0) break;
-            bnorm_tile(a, a.tiles[item], red4);
-        }
-        queue_leave(q);
-    } else if ((int)blockIdx.x < a.ntiles) {
-        bnorm_tile(a, a.tiles[blockIdx.x], red4);
-    }
+    for_each_item(q, a.ntiles, &slot, [&](int item) {
+        bnorm_tile(a, a.tiles[item], red4);
+    });
 }
 
 __global__ __launch_bounds__(1024) void k_loewner_fmm(VecArgs a, FmmArgs f, FmmlArgs l, Queue *q) {
     extern __shared__ double4 red4[];
     __shared__ int slot;
-    if (q) {
-        for (;;) {
-            const int item = queue_pull(q, a.ntiles, &slot);
-            if (item < 0) break;
-            loewner_fmm_tile(a, f, l, a.tiles[item], red4);
-        }
-        queue_leave(q);
-    } else if ((int)blockIdx.x < a.ntiles) {
-        loewner_fmm_tile(a, f, l, a.tiles[blockIdx.x], red4);
-    }
+    for_each_item(q, a.ntiles, &slot, [&](int item) {
+        loewner_fmm_tile(a, f, l, a.tiles[item], red4);
+    });
 }
 
 hipError_t launch_pack_ke(const VecArgs &a, hipStream_t s) {
