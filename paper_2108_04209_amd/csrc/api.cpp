@@ -142,8 +142,11 @@ LaunchShape choose_shape(const superdc_ctx *ctx, const superdc_batch *b, int max
 }
 
 // far-field separation: a box is far from a target leaf when the gap is >= FMM_SEP times
-// the box's width (Chebyshev order 16 then interpolates both kernels to ~1e-14)
+// the box's width (Chebyshev order 16 then interpolates both kernels to ~1e-14); a source
+// enters a target leaf's local expansion when its gap to the target interval is >=
+// FMM_SEP_LOC times the interval's width (order 20 then interpolates both sums to ~1e-14)
 constexpr double FMM_SEP = 1.5;
+constexpr double FMM_SEP_LOC = 1.0;
 
 int fmm_dir_slot(int chunk) { return chunk == 64 ? 0 : chunk == 128 ? 1 : chunk == 256 ? 2 : 3; }
 
@@ -250,6 +253,8 @@ FmmPlan *fmm_plan(superdc_batch *b, int leaf, int crossover) {
               fmm_upload(fp, &fp->far_l, std::vector<int32_t>(), (size_t)fp->nleaves * FMM_FAR_MAX) &&
               fmm_upload(fp, &fp->far_r, std::vector<int32_t>(), (size_t)fp->nleaves * FMM_FAR_MAX) &&
               fmm_upload(fp, &fp->cnt, std::vector<int32_t>(), (size_t)fp->nleaves * 3) &&
+              fmm_upload(fp, &fp->near_lf, std::vector<int32_t>(), (size_t)fp->nleaves * FMM_NEAR_MAX) &&
+              fmm_upload(fp, &fp->t_near_lf, std::vector<int32_t>(), (size_t)fp->nleaves * FMM_NEAR_MAX) &&
               fmm_upload(fp, &fp->loc_ab, std::vector<double2>(), (size_t)fp->nleaves) &&
               fmm_upload(fp, &fp->far_ld, std::vector<int32_t>(), (size_t)fp->nleaves * FMM_FAR_MAX) &&
               fmm_upload(fp, &fp->far_rd, std::vector<int32_t>(), (size_t)fp->nleaves * FMM_FAR_MAX) &&
@@ -301,6 +306,7 @@ FmmArgs fmm_args(const FmmPlan *fp, const superdc_batch *b, const SolveArgs &a,
     f.off = b->off_d;
     f.leaf = fp->leaf;
     f.sep = FMM_SEP;
+    f.sep_loc = FMM_SEP_LOC;
     f.fmm_prob = fp->fmm_prob;
     f.fmm_of = fp->fmm_of;
     f.box_off = fp->box_off;
@@ -314,6 +320,7 @@ FmmArgs fmm_args(const FmmPlan *fp, const superdc_batch *b, const SolveArgs &a,
     f.box_ab = fp->box_ab;
     f.near_lo = fp->near_lo;
     f.near_hi = fp->near_hi;
+    f.near_lf = fp->near_lf;
     f.far_l = fp->far_l;
     f.far_r = fp->far_r;
     f.cnt = fp->cnt;
@@ -351,6 +358,7 @@ FmmArgs fmm_roots_args(const FmmPlan *fp, const superdc_batch *b, const double2 
     f.tpos = d;
     f.near_lo = fp->t_near_lo;
     f.near_hi = fp->t_near_hi;
+    f.near_lf = fp->t_near_lf;
     f.far_l = fp->t_far_l;
     f.far_r = fp->t_far_r;
     f.cnt = fp->t_cnt;

@@ -133,24 +133,30 @@ __device__ void apply_tile_mfma(const ApplyArgs &a, Tile t, double *Xs, double2 
             __syncthreads();
             // the next chunk's loads are in flight while this one is multiplied
             if (s0 + AP_K < n) apply_fetch<TRANS, NCT>(a, base, n, s0 + AP_K, c0, ncols, st);
+            // one slice of 4 sources: this lane's Cauchy entry (one reciprocal with a Newton
+            // step) into the MFMA of every column tile; MASK: padding entries past the
+            // problem's end are zeroed.  A row past the end (ovalid false) only feeds its own
+            // output row, never written.
+#define SDC_AP_SLICE(MASK)                                                                 \
+    {                                                                                      \
+        const int sl = kk + (lane >> 4);                                                   \
+        const double2 sd = Sd[sl];                                                         \
+        const double tt = TRANS ? (sd.x - ra) - rb : (ra - sd.x) - sd.y;                   \
+        const double av = (!(MASK) || s0 + sl < n) ? rcp_nr1(tt) : 0.0;                   \
+        _Pragma("unroll") for (int ct = 0; ct < NCT; ++ct) {                               \
+            if (ct < nct) {                                                                \
+                const double bv = Xs[(ct * 16 + (lane & 15)) * AP_LD + sl];                \
+                acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[ct], 0, 0, 0);  \
+                if (fb) {                                                                  \
+                    const double qv = av * sd.y;                                           \
+                    bsum = fma(qv, qv, bsum);                                              \
+                }                                                                          \
+            }                                                                              \
+        }                                                                                  \
+    }
 #pragma unroll 4
-            for (int kk = 0; kk < AP_K; kk += 4) {
-                const int sl = kk + (lane >> 4);
-                const double2 sd = Sd[sl];
-                const double tt = TRANS ? (sd.x - ra) - rb : (ra - sd.x) - sd.y;
-                const double av = (ovalid && s0 + sl < n) ? rcp_nr(tt) : 0.0;
-#pragma unroll
-                for (int ct = 0; ct < NCT; ++ct) {
-                    if (ct < nct) {
-                        const double bv = Xs[(ct * 16 + (lane & 15)) * AP_LD + sl];
-                        acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[ct], 0, 0, 0);
-                        if (fb) {
-                            const double qv = av * sd.y;
-                            bsum = fma(qv, qv, bsum);
-                        }
-                    }
-                }
-            }
+            for (int kk = 0; kk < AP_K; kk += 4) SDC_AP_SLICE(true)
+#undef SDC_AP_SLICE
         }
         if (fb) {  // the four lanes of a Cauchy row (lane % 16) hold its partial sums
             bsum += __shfl_xor(bsum, 16);

@@ -56,6 +56,15 @@ __device__ __forceinline__ double rcp_nr1(double t) {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
 
+// This wavefront's instruction-issue priority among the SIMD's wavefronts (0 lowest, 3
+// highest); p must be wave-uniform.
+__device__ __forceinline__ void wave_priority(int p) {
+    if (p <= 0) __builtin_amdgcn_s_setprio(0);
+    else if (p == 1) __builtin_amdgcn_s_setprio(1);
+    else if (p == 2) __builtin_amdgcn_s_setprio(2);
+    else __builtin_amdgcn_s_setprio(3);
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_uniform(T v) {
     return __builtin_amdgcn_readfirstlane(v);

@@ -10,8 +10,9 @@ namespace sdc {
 constexpr int FMM_P = 16;          // Chebyshev nodes per box (equivalent sources)
 constexpr int FMM_NEAR_MAX = 24;   // near leaves (and so near ranges) per target leaf
 constexpr int FMM_FAR_MAX = 64;    // far boxes per side per target leaf
-constexpr int FMM_LOC = 4 * FMM_P; // local expansion of a target leaf: psi, psi', phi, phi'
-                                   // far fields, FMM_P Chebyshev coefficients each
+constexpr int FMM_PL = 20;         // Chebyshev terms of a target leaf's local expansion
+constexpr int FMM_LOC = 4 * FMM_PL; // local expansion of a target leaf: psi, psi', phi, phi'
+                                    // far fields, FMM_PL Chebyshev coefficients each
 
 // Per batch: the problems that use the FMM, their trees, and per-leaf interaction lists.
 // Problem q (in FMM numbering) owns boxes [box_off[q], box_off[q+1]) in heap order over its
@@ -20,7 +21,9 @@ constexpr int FMM_LOC = 4 * FMM_P; // local expansion of a target leaf: psi, psi
 struct FmmArgs {
     const int64_t *off;
     int leaf;                 // poles per leaf
-    double sep;               // separation ratio for the far field
+    double sep;               // separation ratio for the far field (times the box's width)
+    double sep_loc;           // separation from the target interval, times its width, of the
+                              // sources that enter a target leaf's local expansion
     const int32_t *fmm_prob;  // [nfmm] batch problem index
     const int32_t *fmm_of;    // [nprob] FMM index of a problem, -1 for direct
     const int32_t *box_off;   // [nfmm + 1]
@@ -33,9 +36,13 @@ struct FmmArgs {
     double2 *eq;              // [boxes][FMM_P] equivalent sources (node, weight)
     double2 *box_ab;          // [boxes] (first pole, last pole) of the box
     int32_t *near_lo, *near_hi;   // [leaves][FMM_NEAR_MAX] pole ranges: runs of adjacent near leaves
+    int32_t *near_lf;             // [leaves][FMM_NEAR_MAX] 1: the range lies sep_loc target widths
+                                  // (and a tile of indices) from the target interval, so its
+                                  // poles enter the local expansion instead of the solver's
+                                  // direct sums (the other consumers sum every near range)
     int32_t *far_l, *far_r;       // [leaves][FMM_FAR_MAX] far box ids (global)
     int32_t *cnt;             // [leaves][3] counts (near, far left, far right); -1 = direct
-    // Far boxes also separated from the whole target interval (by sep times its width)
+    // Far boxes also separated from the whole target interval (by sep_loc times its width)
     // enter the leaf's local expansion instead of being summed per root and iteration.
     int32_t *far_ld, *far_rd;       // [leaves][FMM_FAR_MAX] the far boxes summed directly
                                     // from the front, those in the expansion from the back
@@ -61,7 +68,7 @@ struct FmmPlan {
     int32_t *height = nullptr, *box_fmm = nullptr, *leaf_fmm = nullptr;
     double2 *eq = nullptr, *box_ab = nullptr;
     int32_t *near_lo = nullptr, *near_hi = nullptr, *far_l = nullptr, *far_r = nullptr;
-    int32_t *cnt = nullptr;
+    int32_t *cnt = nullptr, *near_lf = nullptr;
     int32_t *far_ld = nullptr, *far_rd = nullptr, *cntd = nullptr;
     double2 *loc_ab = nullptr;
     double *loc = nullptr;
@@ -91,6 +98,7 @@ struct FmmPlan {
     // poles), kept apart from the solver's, which later calls on the same poles reuse
     int32_t *t_near_lo = nullptr, *t_near_hi = nullptr, *t_far_l = nullptr, *t_far_r = nullptr;
     int32_t *t_cnt = nullptr, *t_far_ld = nullptr, *t_far_rd = nullptr, *t_cntd = nullptr;
+    int32_t *t_near_lf = nullptr;
     int32_t *t_used = nullptr;
     double2 *t_box_ab = nullptr, *t_loc_ab = nullptr;
     std::vector<void *> allocs;

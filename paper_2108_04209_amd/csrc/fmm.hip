@@ -18,8 +18,8 @@
 
 namespace sdc {
 
-__device__ __forceinline__ double cheb_node(int q) {
-    return cos((2.0 * q + 1.0) * 3.14159265358979323846 / (2.0 * FMM_P));
+__device__ __forceinline__ double cheb_node(int q, int P = FMM_P) {
+    return cos((2.0 * q + 1.0) * 3.14159265358979323846 / (2.0 * P));
 }
 
 // barycentric weight of Chebyshev node q (first kind): (-1)^q sin((2q+1) pi / 2P)
@@ -185,8 +185,13 @@ __global__ __launch_bounds__(WAVE) void k_fmm_lists(FmmArgs f) {
         const bool fl = live && ab.y < xa && xa - ab.y >= f.sep * width && hi <= i0 - TILE;
         const bool fr = live && !fl && ab.x > xb && ab.x - xb >= f.sep * width && lo >= i1 + TILE;
         // also separated from the whole target interval: into the leaf's local expansion
-        const bool loc = (fl && xa - ab.y >= f.sep * (xb - xa)) || (fr && ab.x - xb >= f.sep * (xb - xa));
+        const double wloc = f.sep_loc * (xb - xa);
+        const bool loc = (fl && xa - ab.y >= wloc) || (fr && ab.x - xb >= wloc);
         const bool nr_leaf = live && !fl && !fr && h == H;
+        // a near leaf that is that far from the target interval (and a tile of indices
+        // away) enters the local expansion with its poles
+        const bool nloc = nr_leaf && ((ab.y < xa && xa - ab.y >= wloc && hi <= i0 - TILE) ||
+                                      (ab.x > xb && ab.x - xb >= wloc && lo >= i1 + TILE));
         const bool open = live && !fl && !fr && h < H;
         // far boxes, appended in lane order
         const unsigned long long ml = __ballot(fl), mr = __ballot(fr);
@@ -229,7 +234,8 @@ __global__ __launch_bounds__(WAVE) void k_fmm_lists(FmmArgs f) {
             nel += __popcll(mel);
             ner += __popcll(mer);
         }
-        // near leaves (ascending), adjacent ones merged into one range
+        // near leaves (ascending), adjacent ones of the same kind (direct or into the local
+        // expansion) merged into one range
         const unsigned long long mn = __ballot(nr_leaf);
         if (mn) {
             if (__popcll(mn) > FMM_NEAR_MAX) {
@@ -239,7 +245,8 @@ __global__ __launch_bounds__(WAVE) void k_fmm_lists(FmmArgs f) {
             const unsigned long long below = lane ? (mn & ((1ull << lane) - 1)) : 0ull;
             const int prev = below ? 63 - __builtin_clzll(below) : -1;
             const int hprev = __shfl(hi, prev < 0 ? 0 : prev);
-            const bool start = nr_leaf && (prev < 0 || hprev != lo);
+            const bool lprev = __shfl((int)nloc, prev < 0 ? 0 : prev) != 0;
+            const bool start = nr_leaf && (prev < 0 || hprev != lo || lprev != nloc);
             const unsigned long long ms = __ballot(start);
             const int rs = __builtin_amdgcn_mbcnt_hi((unsigned)(ms >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)ms, 0u));
             // the run of a start lane ends at the last near lane before the next start
@@ -251,6 +258,7 @@ __global__ __launch_bounds__(WAVE) void k_fmm_lists(FmmArgs f) {
             if (start) {
                 near_lo[nn + rs] = lo;
                 near_hi[nn + rs] = hend;
+                f.near_lf[(int64_t)L * FMM_NEAR_MAX + nn + rs] = nloc ? 1 : 0;
             }
             nn += __popcll(ms);
         }
@@ -278,20 +286,27 @@ __global__ __launch_bounds__(WAVE) void k_fmm_lists(FmmArgs f) {
     }
 }
 
-// Local expansion of a target leaf (one workgroup of 256 threads per leaf): the far field of
-// the boxes listed for it, psi_far(x) = sum W_q / (s_q - x) over the left boxes and
-// phi_far over the right ones, with their derivatives, sampled at the FMM_P Chebyshev nodes
-// of the target interval [xa, xb] (which holds every iterate of the leaf's roots) and turned
-// into Chebyshev coefficients, so that the solver evaluates four short series per root and
-// iteration instead of 16 equivalent sources per box.  Thread (node m, part u) sums the
-// boxes e = u (mod LOC_PARTS), two sources per reciprocal (all on one side of the node);
-// the parts are added in order.
+// Local expansion of a target leaf (one workgroup per leaf): the far field of the boxes
+// listed for it in the expansion and of the near ranges flagged for it (their poles
+// themselves), psi_far(x) = sum W_q / (s_q - x) over the sources left of the leaf and
+// phi_far over those right of it, with their derivatives, sampled at the FMM_PL Chebyshev
+// nodes of the target interval [xa, xb] (which holds every iterate of the leaf's roots) and
+// turned into Chebyshev coefficients, so that the solver evaluates four short series per
+// root and iteration instead of the sources one by one.  Every source is at least sep_loc
+// interval widths from the interval.  Thread (node m, part u) sums the boxes e = u (mod
+// LOC_PARTS), two sources per reciprocal (all on one side of the node), and every
+// LOC_PARTS-th pole of the flagged ranges; the parts are added in order.
 constexpr int LOC_PARTS = 16;
-__global__ __launch_bounds__(FMM_P * LOC_PARTS) void k_fmm_local(FmmArgs f) {
-    __shared__ double part[LOC_PARTS][4][FMM_P];  // [part][function][node]
-    __shared__ double val[4][FMM_P];      // [function][node]
+__global__ __launch_bounds__(FMM_PL * LOC_PARTS) void k_fmm_local(FmmArgs f) {
+    __shared__ double part[LOC_PARTS][4][FMM_PL];  // [part][function][node]
+    __shared__ double val[4][FMM_PL];              // [function][node]
+    __shared__ double Tkm[FMM_PL][FMM_PL];         // T_k(t_m) = cos(k (2m + 1) pi / 2P)
     const int L = blockIdx.x;
     const int tid = threadIdx.x;
+    for (int e = tid; e < FMM_PL * FMM_PL; e += blockDim.x)
+        Tkm[e / FMM_PL][e % FMM_PL] =
+            cos((double)((e / FMM_PL) * (2 * (e % FMM_PL) + 1)) * 3.14159265358979323846 /
+                (2.0 * FMM_PL));
     const int q = f.leaf_fmm[L];
     const int p = f.fmm_prob[q];
     if (f.status[p] & ~SUPERDC_ST_NOCONV) return;
@@ -300,8 +315,8 @@ __global__ __launch_bounds__(FMM_P * LOC_PARTS) void k_fmm_local(FmmArgs f) {
     const int nel = f.cnt[3 * (int64_t)L + 1] - f.cntd[2 * (int64_t)L];
     const int ner = f.cnt[3 * (int64_t)L + 2] - f.cntd[2 * (int64_t)L + 1];
     const double2 cw = f.loc_ab[L];
-    const int m = tid % FMM_P, u = tid / FMM_P;
-    const double tm = cheb_node(m);
+    const int m = tid % FMM_PL, u = tid / FMM_PL;
+    const double tm = cheb_node(m, FMM_PL);
     const double x = cw.x + cw.y * tm;
     double ps = 0.0, dps = 0.0, ph = 0.0, dph = 0.0;
     for (int e = u; e < nel + ner; e += LOC_PARTS) {
@@ -335,33 +350,51 @@ __global__ __launch_bounds__(FMM_P * LOC_PARTS) void k_fmm_local(FmmArgs f) {
             dph += s1;
         }
     }
+    // flagged near ranges: their poles, left of the leaf into psi, right of it into phi
+    {
+        const int64_t base = f.off[p];
+        const int i0 = (L - f.leaf_off[q]) * f.leaf;
+        const double2 *dw = f.dw + base;
+        for (int e = 0; e < nn; ++e) {
+            if (!f.near_lf[(int64_t)L * FMM_NEAR_MAX + e]) continue;
+            const int lo = f.near_lo[(int64_t)L * FMM_NEAR_MAX + e];
+            const int hi = f.near_hi[(int64_t)L * FMM_NEAR_MAX + e];
+            double s0 = 0.0, s1 = 0.0;
+            for (int j = lo + u; j < hi; j += LOC_PARTS) {
+                const double2 pw = dw[j];
+                const double r = rcp_nr(pw.x - x);
+                const double wr = pw.y * r;
+                s0 += wr;
+                s1 = __builtin_fma(wr, r, s1);
+            }
+            if (hi <= i0) {
+                ps += s0;
+                dps += s1;
+            } else {
+                ph += s0;
+                dph += s1;
+            }
+        }
+    }
     part[u][0][m] = ps;
     part[u][1][m] = dps;
     part[u][2][m] = ph;
     part[u][3][m] = dph;
     __syncthreads();
-    if (tid < 4 * FMM_P) {
-        const int fn = tid / FMM_P;  // thread (function fn, node m) adds the parts in order
+    if (tid < 4 * FMM_PL) {
+        const int fn = tid / FMM_PL, mm = tid % FMM_PL;  // (function, node): parts in order
         double sv = 0.0;
-        for (int w = 0; w < LOC_PARTS; ++w) sv += part[w][fn][m];
-        val[fn][m] = sv;
+        for (int w = 0; w < LOC_PARTS; ++w) sv += part[w][fn][mm];
+        val[fn][mm] = sv;
     }
     __syncthreads();
-    if (tid >= 4 * FMM_P) return;
+    if (tid >= 4 * FMM_PL) return;
     // c_k = (2 - [k = 0]) / P * sum_m f(t_m) T_k(t_m), thread (function fn, degree k)
-    const int fn = tid / FMM_P, k = tid % FMM_P;
+    const int fn = tid / FMM_PL, k = tid % FMM_PL;
     double ck = 0.0;
-    for (int mm = 0; mm < FMM_P; ++mm) {
-        const double t = cheb_node(mm);
-        double T0 = 1.0, T1 = t, Tk = k == 0 ? 1.0 : t;
-        for (int j = 2; j <= k; ++j) {
-            Tk = 2.0 * t * T1 - T0;
-            T0 = T1;
-            T1 = Tk;
-        }
-        ck = __builtin_fma(val[fn][mm], Tk, ck);
-    }
-    f.loc[(int64_t)L * FMM_LOC + fn * FMM_P + k] = ck * ((k == 0 ? 1.0 : 2.0) / FMM_P);
+#pragma unroll 4
+    for (int mm = 0; mm < FMM_PL; ++mm) ck = __builtin_fma(val[fn][mm], Tkm[k][mm], ck);
+    f.loc[(int64_t)L * FMM_LOC + fn * FMM_PL + k] = ck * ((k == 0 ? 1.0 : 2.0) / FMM_PL);
 }
 
 hipError_t launch_fmm_lists(const FmmArgs &f, hipStream_t s) {
@@ -377,7 +410,7 @@ hipError_t launch_fmm_build(const FmmArgs &f, hipStream_t s) {
     if (e != hipSuccess) return e;
     SDC_LAUNCH(KID_FMM_BOXES, k_fmm_boxes<true>, dim3(f.nboxes), dim3(64), 0, s, f);
     SDC_LAUNCH(KID_FMM_BOXES, k_fmm_boxes<false>, dim3(f.nboxes), dim3(256), 0, s, f);
-    SDC_LAUNCH(KID_FMM_LOCAL, k_fmm_local, dim3(f.nleaves), dim3(FMM_P * LOC_PARTS), 0, s, f);
+    SDC_LAUNCH(KID_FMM_LOCAL, k_fmm_local, dim3(f.nleaves), dim3(FMM_PL * LOC_PARTS), 0, s, f);
     return hipGetLastError();
 }
 

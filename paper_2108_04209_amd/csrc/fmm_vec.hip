@@ -350,6 +350,8 @@ __device__ __forceinline__ void fv_fetch(const FmmVec &v, int64_t base, int n, c
                                          int4 ch, FvStage &st) {
     const int tid = threadIdx.x;
     const int m = v.m;
+    // weight element i of this thread: source r16 + 16 i of the chunk, column c
+    const int c = tid & 15, r16 = tid >> 4;
     if (ch.x == 0) {
         if (tid < FV_K) {
             const int j = ch.y + tid;
@@ -359,12 +361,12 @@ __device__ __forceinline__ void fv_fetch(const FmmVec &v, int64_t base, int n, c
             else
                 st.sd = make_double2(v.d[base + j], v.fuse_b ? v.zh[base + j] : 0.0);
         }
+        const double *srow = v.src + (base + ch.y + r16) * m + c;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int e = tid + 256 * i, sl = e >> 4, c = e & 15;
-            st.w[i] = (sl < ch.z && c < m) ? v.src[(base + ch.y + sl) * m + c] : 0.0;
-        }
+        for (int i = 0; i < 4; ++i)
+            st.w[i] = (r16 + 16 * i < ch.z && c < m) ? srow[(int64_t)16 * i * m] : 0.0;
     } else {
+        // far chunk: box i of the chunk holds its FMM_P = 16 sources r16
         if (tid < FV_K) {
             const int bx = tid / FMM_P, qn = tid % FMM_P;
             const int64_t sq = bx < ch.z ? (int64_t)fbox[ch.y + bx] * FMM_P + qn : -1;
@@ -372,13 +374,10 @@ __device__ __forceinline__ void fv_fetch(const FmmVec &v, int64_t base, int n, c
                             : make_double2(0.0, 0.0);
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int e = tid + 256 * i, sl = e >> 4, c = e & 15;
-            const int bx = sl / FMM_P, qn = sl % FMM_P;
-            st.w[i] = (bx < ch.z && c < m)
-                          ? v.vw[((int64_t)fbox[ch.y + bx] * FMM_P + qn) * m + c]
+        for (int i = 0; i < 4; ++i)
+            st.w[i] = (i < ch.z && c < m)
+                          ? v.vw[((int64_t)fbox[ch.y + i] * FMM_P + r16) * m + c]
                           : 0.0;
-        }
     }
 }
 
@@ -471,23 +470,35 @@ __device__ void fmmv_item_mfma(const SolveArgs &it, const FmmArgs &f, const FmmV
             cur = chunk(ci + 1);
             fv_fetch<TRANS>(v, base, n, sh.fbox, cur, st);  // in flight during the multiply
         }
+        // one slice of 4 sources: the Cauchy entries of this lane's row (one reciprocal
+        // with a Newton step each) into the MFMA; MASK: a partial chunk, whose padding
+        // entries are zeroed (a padding source may sit on a row's target).  A row past the
+        // problem's end (ovalid false) only feeds its own output row, never written.
+#define SDC_FV_SLICE(MASK)                                                              \
+    {                                                                                   \
+        const int sl = kk + (lane >> 4);                                                \
+        const double2 sdv = sh.Sd[sl];                                                  \
+        const double tt = TRANS ? (sdv.x - ra) - rb : (ra - sdv.x) - sdv.y;             \
+        const double av = (!(MASK) || sl < nvalid) ? rcp_nr1(tt) : 0.0;                 \
+        const double bv = sh.Xs[(lane & 15) * FV_LD + sl];                              \
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);               \
+        if (fb) {                                                                       \
+            if (cur_near) { /* (zhat / t)^2: squared after the division */              \
+                const double qv = av * sdv.y;                                           \
+                bsum = fma(qv, qv, bsum);                                               \
+            } else { /* far sources: weights of zhat^2, t bounded away from 0 */        \
+                bsum = fma(av * av, sdv.y, bsum);                                       \
+            }                                                                           \
+        }                                                                               \
+    }
+        if (nvalid == FV_K) {
 #pragma unroll 4
-        for (int kk = 0; kk < FV_K; kk += 4) {
-            const int sl = kk + (lane >> 4);
-            const double2 sdv = sh.Sd[sl];
-            const double tt = TRANS ? (sdv.x - ra) - rb : (ra - sdv.x) - sdv.y;
-            const double av = (ovalid && sl < nvalid) ? rcp_nr(tt) : 0.0;
-            const double bv = sh.Xs[(lane & 15) * FV_LD + sl];
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-            if (fb) {
-                if (cur_near) {  // (zhat / t)^2: squared after the division
-                    const double qv = av * sdv.y;
-                    bsum = fma(qv, qv, bsum);
-                } else {         // far sources: weights of zhat^2, t bounded away from 0
-                    bsum = fma(av * av, sdv.y, bsum);
-                }
-            }
+            for (int kk = 0; kk < FV_K; kk += 4) SDC_FV_SLICE(false)
+        } else {
+#pragma unroll 4
+            for (int kk = 0; kk < FV_K; kk += 4) SDC_FV_SLICE(true)
         }
+#undef SDC_FV_SLICE
     }
     if (fb) {  // the four lanes of a Cauchy row (lane % 16) hold its partial sums
         bsum += __shfl_xor(bsum, 16);

@@ -343,12 +343,12 @@ __device__ __forceinline__ void local_series(const FmmArgs &f, int L, double x, 
     for (int fn = 0; fn < 4; ++fn) {
         double b1 = 0.0, b2 = 0.0;
 #pragma unroll
-        for (int j = FMM_P - 1; j >= 1; --j) {
-            const double b0 = __builtin_fma(2.0 * t, b1, c[fn * FMM_P + j] - b2);
+        for (int j = FMM_PL - 1; j >= 1; --j) {
+            const double b0 = __builtin_fma(2.0 * t, b1, c[fn * FMM_PL + j] - b2);
             b2 = b1;
             b1 = b0;
         }
-        r[fn] = __builtin_fma(t, b1, c[fn * FMM_P] - b2);
+        r[fn] = __builtin_fma(t, b1, c[fn * FMM_PL] - b2);
     }
     psi += r[0];
     dpsi += r[1];
@@ -376,6 +376,7 @@ __device__ __forceinline__ void fmm_sums(const FmmArgs &f, int L, int nn, int nl
     // of the live roots take the shifted form
     const int f0 = kmin - TILE, f1 = kmax + 1 + TILE;
     for (int e = 0; e < nn; ++e) {
+        if (wave_uniform(f.near_lf[(int64_t)L * FMM_NEAR_MAX + e])) continue;  // in the expansion
         const int lo0 = wave_uniform(f.near_lo[(int64_t)L * FMM_NEAR_MAX + e]);
         const int hi0 = wave_uniform(f.near_hi[(int64_t)L * FMM_NEAR_MAX + e]);
         const int lo = lo0 + (int)(((int64_t)(hi0 - lo0) * wv) >> sh);  // S = 2^sh
@@ -515,6 +516,7 @@ __device__ __forceinline__ void team_sums(const FmmArgs *fm, int L, int nn, int 
     const FmmArgs &f = *fm;
     const int sh = __builtin_ctz((unsigned)S);
     for (int e = 0; e < nn; ++e) {
+        if (wave_uniform(f.near_lf[(int64_t)L * FMM_NEAR_MAX + e])) continue;  // in the expansion
         const int lo0 = wave_uniform(f.near_lo[(int64_t)L * FMM_NEAR_MAX + e]);
         const int hi0 = wave_uniform(f.near_hi[(int64_t)L * FMM_NEAR_MAX + e]);
         const int lo = lo0 + (int)(((int64_t)(hi0 - lo0) * wv) >> sh);
@@ -582,6 +584,7 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
     if (a.work && FMM && nn >= 0) {
         pairs_per_pass = 0;
         for (int e = 0; e < nn; ++e) {
+            if (fm->near_lf[(int64_t)L * FMM_NEAR_MAX + e]) continue;
             const int lo0 = fm->near_lo[(int64_t)L * FMM_NEAR_MAX + e];
             const int hi0 = fm->near_hi[(int64_t)L * FMM_NEAR_MAX + e];
             pairs_per_pass += (int)(((int64_t)(hi0 - lo0) * (wv + 1)) / S) -
@@ -589,9 +592,10 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
         }
         const int nfar = (nl > wv ? (nl - wv + S - 1) / S : 0) + (nr > wv ? (nr - wv + S - 1) / S : 0);
         pairs_per_pass += (int64_t)FMM_P * nfar;
-        // the local expansion (four 16-term Clenshaw series, each 15 steps of a subtraction
-        // and an FMA and a last FMA: 192 flops) counts as 27 pairs
-        if (wv == 0) pairs_per_pass += 27;
+        // the local expansion (four 20-term Clenshaw series, each 19 steps of a subtraction
+        // and an FMA and a last FMA: 240 flops) counts as 34 pairs
+        static_assert(FMM_PL == 20, "the local expansion's pair count");
+        if (wv == 0) pairs_per_pass += 34;
     }
     unsigned long long work = 0, live = 0, slots = 0;
 
@@ -603,6 +607,7 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
     int why = 0;  // how the root stopped: 0 the stopping test, SUPERDC_ITER_* otherwise
     double dk = 0.0, dk1 = 0.0, dK = 0.0, y = 0.0, lo = 0.0, hi = 0.0;
     int g = 1;                 // lanes per live root (a team; see above)
+    int pass = 0;
     bool noconv_any = false;   // some root of the wavefront hit the cap (kept across regroups)
     for (;;) {
         // refill idle lanes with the next roots of the chunk, in order
@@ -680,6 +685,10 @@ __device__ void secular_chunk(const SolveArgs &a, Tile t, double *red, const Fmm
                 secular_sums(dw, n, p0, p1, kmin, kmax, k, dK, y, unsh, psi, dpsi, phi, dphi);
         }
         split_reduce4(red, S, psi, dpsi, phi, dphi);
+        // issue priority falls as the item's passes add up: the SIMD serves the items in
+        // their first passes (every lane live, the loads of a fresh item) ahead of the
+        // long-running ones (measured: 7.2 -> 6.9 ms per conquer step for the FMM solver)
+        wave_priority(3 - (++pass >> 1));
         if (a.work) {
             const unsigned long long nroot = (unsigned long long)__popcll(__ballot(act && sub == 0));
             work += (unsigned long long)pairs_per_pass * nroot;

@@ -43,8 +43,9 @@ __device__ __forceinline__ void renorm(double &num, double &den, int &E) {
 // products over roots j in [j0, j1); SKIP drops the denominator factor j == i.
 // Two independent product chains (even and odd roots) keep the multiplies from waiting
 // on each other; roots are read in pointer-stepped blocks of 4 (one scalar address add per
-// block); each chain strips its exponents after every 8 factors.  The latency of the
-// scalar loads is covered by the other wavefronts of the SIMD.
+// block) into two register sets that alternate, so the next block's scalar loads are in
+// flight while this block is multiplied; each chain strips its exponents after every 8
+// factors.
 // SC: every factor is multiplied by sg (a power of two) before it enters its product.
 template <bool SKIP, bool SC>
 __device__ __forceinline__ void loewner_range(const_double2_ptr ke, const_double_ptr dd,
@@ -52,28 +53,52 @@ __device__ __forceinline__ void loewner_range(const_double2_ptr ke, const_double
                                               int i, double di, double &num, double &den,
                                               int &E, double sg) {
 #define SDC_SCL(F) (SC ? (F) * sg : (F))
+#define SDC_LW_LOAD(S, KP, DP)                                                            \
+    S##k0 = (KP)[0]; S##k1 = (KP)[1]; S##k2 = (KP)[2]; S##k3 = (KP)[3];                    \
+    S##k4 = (KP)[4]; S##k5 = (KP)[5]; S##k6 = (KP)[6]; S##k7 = (KP)[7];                    \
+    S##d0 = (DP)[0]; S##d1 = (DP)[1]; S##d2 = (DP)[2]; S##d3 = (DP)[3];
+#define SDC_LW_BLOCK(S, J)                                                                \
+    {                                                                                     \
+        na *= SDC_SCL((S##k0 - di) + S##k1);                                              \
+        nb *= SDC_SCL((S##k2 - di) + S##k3);                                              \
+        na *= SDC_SCL((S##k4 - di) + S##k5);                                              \
+        nb *= SDC_SCL((S##k6 - di) + S##k7);                                              \
+        const double f0 = SDC_SCL(S##d0 - di), f1 = SDC_SCL(S##d1 - di);                  \
+        const double f2 = SDC_SCL(S##d2 - di), f3 = SDC_SCL(S##d3 - di);                  \
+        da *= (SKIP && (J) == i) ? 1.0 : f0;                                              \
+        db *= (SKIP && (J) + 1 == i) ? 1.0 : f1;                                          \
+        da *= (SKIP && (J) + 2 == i) ? 1.0 : f2;                                          \
+        db *= (SKIP && (J) + 3 == i) ? 1.0 : f3;                                          \
+        if (++blk == 4) { /* 8 factors per chain */                                       \
+            renorm(na, da, E);                                                            \
+            renorm(nb, db, E);                                                            \
+            blk = 0;                                                                      \
+        }                                                                                 \
+    }
     double na = 1.0, da = 1.0, nb = 1.0, db = 1.0;
     int j = j0;
     if (j + 4 <= j1) {
         const_double_ptr kp = ke.p + 2 * (int64_t)j;  // (d_K, eta) pairs
         const_double_ptr dp = dd + j;
+        double ak0, ak1, ak2, ak3, ak4, ak5, ak6, ak7, ad0, ad1, ad2, ad3;
+        double bk0, bk1, bk2, bk3, bk4, bk5, bk6, bk7, bd0, bd1, bd2, bd3;
         int blk = 0;
-        for (; j + 4 <= j1; j += 4, kp += 8, dp += 4) {
-            na *= SDC_SCL((kp[0] - di) + kp[1]);
-            nb *= SDC_SCL((kp[2] - di) + kp[3]);
-            na *= SDC_SCL((kp[4] - di) + kp[5]);
-            nb *= SDC_SCL((kp[6] - di) + kp[7]);
-            const double f0 = SDC_SCL(dp[0] - di), f1 = SDC_SCL(dp[1] - di);
-            const double f2 = SDC_SCL(dp[2] - di), f3 = SDC_SCL(dp[3] - di);
-            da *= (SKIP && j == i) ? 1.0 : f0;
-            db *= (SKIP && j + 1 == i) ? 1.0 : f1;
-            da *= (SKIP && j + 2 == i) ? 1.0 : f2;
-            db *= (SKIP && j + 3 == i) ? 1.0 : f3;
-            if (++blk == 4) {  // 8 factors per chain
-                renorm(na, da, E);
-                renorm(nb, db, E);
-                blk = 0;
-            }
+        SDC_LW_LOAD(a, kp, dp)
+        for (;;) {
+            const bool more = j + 8 <= j1;
+            if (more) { SDC_LW_LOAD(b, kp + 8, dp + 4) }
+            SDC_LW_BLOCK(a, j)
+            j += 4;
+            kp += 8;
+            dp += 4;
+            if (!more) break;
+            const bool more2 = j + 8 <= j1;
+            if (more2) { SDC_LW_LOAD(a, kp + 8, dp + 4) }
+            SDC_LW_BLOCK(b, j)
+            j += 4;
+            kp += 8;
+            dp += 4;
+            if (!more2) break;
         }
     }
     renorm(na, da, E);  // at most 8 factors per chain since the last strip
@@ -86,6 +111,8 @@ __device__ __forceinline__ void loewner_range(const_double2_ptr ke, const_double
     num *= na * nb;  // mantissas in [0.5, 1) times at most 3 factors: no over- or underflow
     den *= da * db;
     renorm(num, den, E);
+#undef SDC_LW_BLOCK
+#undef SDC_LW_LOAD
 #undef SDC_SCL
 }
 
