@@ -157,6 +157,7 @@ __device__ void apply_tile_mfma(const ApplyArgs &a, Tile t, double *Xs, double2 
 #pragma unroll 4
             for (int kk = 0; kk < AP_K; kk += 4) SDC_AP_SLICE(true)
 #undef SDC_AP_SLICE
+            mfma_drain();  // before any copy of the accumulators between chunks
         }
         if (fb) {  // the four lanes of a Cauchy row (lane % 16) hold its partial sums
             bsum += __shfl_xor(bsum, 16);
@@ -167,6 +168,7 @@ __device__ void apply_tile_mfma(const ApplyArgs &a, Tile t, double *Xs, double2 
             const unsigned long long me = (unsigned long long)(ncols + (fb ? 1 : 0));
             atomicAdd(a.work, rows * (unsigned long long)n * (2 * me + 3) + 2 * rows * me);
         }
+        mfma_drain();
         // v_mfma_f64_16x16x4f64 returns D[4 v + lane/16][lane % 16] in accumulator v
 #pragma unroll
         for (int v = 0; v < 4; ++v) {

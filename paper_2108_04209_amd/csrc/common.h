@@ -56,6 +56,16 @@ __device__ __forceinline__ double rcp_nr1(double t) {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
 
+// Let the last v_mfma_f64_16x16x4f64 of a chain finish before its accumulators are read
+// by other instructions: on gfx950 it occupies the matrix pipe for 64 cycles, longer than
+// the wait states the compiler puts between it and such a read, which shows as stale
+// accumulators when the SIMD has no other wavefront to issue meanwhile.  ~128 cycles.
+__device__ __forceinline__ void mfma_drain() {
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_sleep(2);
+    __builtin_amdgcn_sched_barrier(0);
+}
+
 // This wavefront's instruction-issue priority among the SIMD's wavefronts (0 lowest, 3
 // highest); p must be wave-uniform.
 __device__ __forceinline__ void wave_priority(int p) {

@@ -170,6 +170,7 @@ __global__ __launch_bounds__(LEAVES ? 64 : 256) void k_fmmv_sources(FmmArgs f, F
         }
         __syncthreads();
     }
+    mfma_drain();
     // the four wavefronts' partial W added in wavefront order (through the staging LDS);
     // accumulator r of lane l holds W[4 r + l / 16][l % 16]
     double *red = &Lq[0][0];
@@ -499,6 +500,7 @@ __device__ void fmmv_item_mfma(const SolveArgs &it, const FmmArgs &f, const FmmV
             for (int kk = 0; kk < FV_K; kk += 4) SDC_FV_SLICE(true)
         }
 #undef SDC_FV_SLICE
+        mfma_drain();  // before any copy of the accumulators between chunks
     }
     if (fb) {  // the four lanes of a Cauchy row (lane % 16) hold its partial sums
         bsum += __shfl_xor(bsum, 16);
@@ -509,6 +511,7 @@ __device__ void fmmv_item_mfma(const SolveArgs &it, const FmmArgs &f, const FmmV
         atomicAdd(v.work, rows * (unsigned long long)ent * (2 * (unsigned long long)m + 3) +
                               2 * rows * (unsigned long long)mo);
     }
+    mfma_drain();
     // v_mfma_f64_16x16x4f64 returns D[4 r + lane/16][lane % 16] in accumulator r
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
