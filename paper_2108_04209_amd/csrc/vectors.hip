@@ -211,12 +211,29 @@ __device__ __forceinline__ double lw_series(const double *M, double r) {
     return acc * r;
 }
 
+// The poles and far boxes of an item are staged through LDS, a round of them at a time
+// (every thread loads its share of the round, so a round costs one memory round trip
+// instead of one per pole block or per box), and the wavefronts read them from there.
+constexpr int LW_CH = 256;  // near poles per round
+constexpr int LW_FB = 16;   // far boxes per round
+struct LwShared {
+    double2 kep[LW_CH];     // (d_K, eta) of the staged poles' roots
+    double dd[LW_CH];       // the staged poles
+    int jj[LW_CH];          // their indices in the problem
+    int rs[FMM_NEAR_MAX + 1];  // start of near range e in the concatenation of the ranges
+    int rl[FMM_NEAR_MAX];      // its first pole
+    double2 geo[LW_FB];        // (centre, half-width) of the staged far boxes
+    double mom[LW_FB][FMML_K];
+    int box[LW_FB];
+};
+
 __device__ void loewner_fmm_tile(const VecArgs &a, const FmmArgs &f, const FmmlArgs &l, Tile t,
-                                 double4 *red) {
+                                 double4 *red, LwShared &sh) {
     const int p = t.prob;
     const int64_t base = a.off[p];
     const int n = (int)(a.off[p + 1] - base);
-    const int i = t.row0 + lane_id();
+    const int lane = lane_id();
+    const int i = t.row0 + lane;
     const bool active = i < n;
     const int S = blockDim.x / WAVE, wv = wave_uniform((int)(threadIdx.x / WAVE));
     if (a.status[p] & ~SUPERDC_ST_NOCONV) {
@@ -241,7 +258,9 @@ __device__ void loewner_fmm_tile(const VecArgs &a, const FmmArgs &f, const FmmlA
     // a problem out of range has every factor scaled by sg = 2^-es (added back below)
     const int es = wave_uniform(loewner_scale(ke, dd, n));
     const double sg = __builtin_ldexp(1.0, -es);
-    auto exact = [&](int lo, int hi) {
+    if (nn < 0) {  // overflowed lists (rare): every pole, from global memory
+        const int lo = wave_uniform((int)(((int64_t)n * wv) / S));
+        const int hi = wave_uniform((int)(((int64_t)n * (wv + 1)) / S));
         if (es == 0) {
             loewner_range<false, false>(ke, dd, lo, min(hi, t0), ii, di, num, den, E, 1.0);
             loewner_range<true, false>(ke, dd, max(lo, t0), min(hi, t1), ii, di, num, den, E, 1.0);
@@ -251,43 +270,113 @@ __device__ void loewner_fmm_tile(const VecArgs &a, const FmmArgs &f, const FmmlA
             loewner_range<true, true>(ke, dd, max(lo, t0), min(hi, t1), ii, di, num, den, E, sg);
             loewner_range<false, true>(ke, dd, max(lo, t1), hi, ii, di, num, den, E, sg);
         }
-    };
-    if (nn < 0) {
-        exact(wave_uniform((int)(((int64_t)n * wv) / S)),
-              wave_uniform((int)(((int64_t)n * (wv + 1)) / S)));
     } else {
-        for (int e = 0; e < nn; ++e) {
-            const int lo0 = wave_uniform(f.near_lo[(int64_t)L * FMM_NEAR_MAX + e]);
-            const int hi0 = wave_uniform(f.near_hi[(int64_t)L * FMM_NEAR_MAX + e]);
-            exact(lo0 + (int)(((int64_t)(hi0 - lo0) * wv) / S),
-                  lo0 + (int)(((int64_t)(hi0 - lo0) * (wv + 1)) / S));
+        __syncthreads();  // the previous item's reads of the staging are done
+        // the near ranges' starts in their concatenation (a scan by the first wavefront)
+        if (wv == 0) {
+            int lo = 0, len = 0;
+            if (lane < nn) {
+                lo = f.near_lo[(int64_t)L * FMM_NEAR_MAX + lane];
+                len = f.near_hi[(int64_t)L * FMM_NEAR_MAX + lane] - lo;
+            }
+            int incl = len;
+            for (int o = 1; o < WAVE; o <<= 1) {
+                const int v = __shfl_up(incl, o);
+                if (lane >= o) incl += v;
+            }
+            if (lane < nn) {
+                sh.rs[lane + 1] = incl;
+                sh.rl[lane] = lo;
+            }
+            if (lane == 0) sh.rs[0] = 0;
         }
+        __syncthreads();
+        const int T = sh.rs[nn];
+        // near poles, a round of LW_CH at a time: staged by every thread, then wavefront wv
+        // multiplies the factors of its contiguous share of the round (two chains, exponents
+        // stripped every 8 factors per chain)
+        for (int c0 = 0; c0 < T; c0 += LW_CH) {
+            const int cnt = min(LW_CH, T - c0);
+            for (int u = threadIdx.x; u < cnt; u += blockDim.x) {
+                const int pos = c0 + u;
+                int e = 0;
+                while (sh.rs[e + 1] <= pos) ++e;
+                const int j = sh.rl[e] + (pos - sh.rs[e]);
+                sh.kep[u] = ke[j];
+                sh.dd[u] = dd[j];
+                sh.jj[u] = j;
+            }
+            __syncthreads();
+            const int u0 = (int)(((int64_t)cnt * wv) / S), u1 = (int)(((int64_t)cnt * (wv + 1)) / S);
+            double na = 1.0, da = 1.0, nb = 1.0, db = 1.0;
+            int u = u0, blk = 0;
+            for (; u + 2 <= u1; u += 2) {
+                const double2 k0 = sh.kep[u], k1 = sh.kep[u + 1];
+                const double f0 = (sh.dd[u] - di) * sg, f1 = (sh.dd[u + 1] - di) * sg;
+                na *= ((k0.x - di) + k0.y) * sg;
+                nb *= ((k1.x - di) + k1.y) * sg;
+                da *= sh.jj[u] == ii ? 1.0 : f0;
+                db *= sh.jj[u + 1] == ii ? 1.0 : f1;
+                if (++blk == 8) {  // 8 factors per chain
+                    renorm(na, da, E);
+                    renorm(nb, db, E);
+                    blk = 0;
+                }
+            }
+            if (u < u1) {
+                const double2 k0 = sh.kep[u];
+                na *= ((k0.x - di) + k0.y) * sg;
+                da *= sh.jj[u] == ii ? 1.0 : (sh.dd[u] - di) * sg;
+            }
+            renorm(na, da, E);
+            renorm(nb, db, E);
+            num *= na * nb;
+            den *= da * db;
+            renorm(num, den, E);
+            __syncthreads();  // the round's reads are done before the next is staged
+        }
+        // far boxes, a round of LW_FB at a time: ids and geometry, then their moments, staged
+        // by every thread; wavefront wv takes the round's boxes wv, wv + S, ...
         const int nl = wave_uniform(f.cnt[3 * (int64_t)L + 1]);
         const int nr = wave_uniform(f.cnt[3 * (int64_t)L + 2]);
-        for (int e = wv; e < nl + nr; e += S) {
-            const int g = wave_uniform(e < nl ? f.far_l[(int64_t)L * FMM_FAR_MAX + e]
-                                              : f.far_r[(int64_t)L * FMM_FAR_MAX + e - nl]);
-            const double2 gc = l.geo[g];
-            const double r = gc.y / (gc.x - di);
-            if (fabs(r) <= 0.35) {
-                far += lw_series(l.mom + (int64_t)g * FMML_K, r);
-            } else {  // too close for the expansion: the box's exact products for this lane
-                const int hidx = g - f.box_off[qf];
-                const int H = f.height[qf];
-                int h = 0;
-                while ((2 << h) - 1 <= hidx) ++h;
-                const int bi = hidx - ((1 << h) - 1);
-                const int64_t span = (int64_t)f.leaf << (H - h);
-                const int lo = (int)min((int64_t)n, bi * span);
-                const int hi = (int)min((int64_t)n, (bi + 1) * span);
-                for (int j = lo; j < hi; ++j) {  // j != i: a far box never holds pole i
-                    const double2 kv = ke[j];
-                    num *= ((kv.x - di) + kv.y) * sg;  // as many factors on both sides
-                    den *= (dd[j] - di) * sg;
-                    if ((j & 7) == 7) renorm(num, den, E);
-                }
-                renorm(num, den, E);
+        for (int c0 = 0; c0 < nl + nr; c0 += LW_FB) {
+            const int cnt = min(LW_FB, nl + nr - c0);
+            if (threadIdx.x < cnt) {
+                const int e = c0 + threadIdx.x;
+                const int g = e < nl ? f.far_l[(int64_t)L * FMM_FAR_MAX + e]
+                                     : f.far_r[(int64_t)L * FMM_FAR_MAX + e - nl];
+                sh.box[threadIdx.x] = g;
+                sh.geo[threadIdx.x] = l.geo[g];
             }
+            __syncthreads();
+            for (int u = threadIdx.x; u < cnt * FMML_K; u += blockDim.x)
+                sh.mom[u / FMML_K][u % FMML_K] = l.mom[(int64_t)sh.box[u / FMML_K] * FMML_K + u % FMML_K];
+            __syncthreads();
+            for (int b = wv; b < cnt; b += S) {
+                const double2 gc = sh.geo[b];
+                const double r = gc.y / (gc.x - di);
+                if (fabs(r) <= 0.35) {
+                    far += lw_series(sh.mom[b], r);
+                } else {  // too close for the expansion: the box's exact products for this lane
+                    const int g = sh.box[b];
+                    const int hidx = g - f.box_off[qf];
+                    const int H = f.height[qf];
+                    int h = 0;
+                    while ((2 << h) - 1 <= hidx) ++h;
+                    const int bi = hidx - ((1 << h) - 1);
+                    const int64_t span = (int64_t)f.leaf << (H - h);
+                    const int lo = (int)min((int64_t)n, bi * span);
+                    const int hi = (int)min((int64_t)n, (bi + 1) * span);
+                    for (int j = lo; j < hi; ++j) {  // j != i: a far box never holds pole i
+                        const double2 kv = ke[j];
+                        num *= ((kv.x - di) + kv.y) * sg;  // as many factors on both sides
+                        den *= (dd[j] - di) * sg;
+                        if ((j & 7) == 7) renorm(num, den, E);
+                    }
+                    renorm(num, den, E);
+                }
+            }
+            __syncthreads();  // the round's reads are done before the next is staged
         }
     }
     if (es != 0 && wv == 0) E += es;
@@ -397,9 +486,10 @@ __global__ __launch_bounds__(1024) void k_bnorm(VecArgs a, Queue *q) {
 
 __global__ __launch_bounds__(1024) void k_loewner_fmm(VecArgs a, FmmArgs f, FmmlArgs l, Queue *q) {
     extern __shared__ double4 red4[];
+    __shared__ LwShared sh;
     __shared__ int slot;
     for_each_item(q, a.ntiles, &slot, [&](int item) {
-        loewner_fmm_tile(a, f, l, a.tiles[item], red4);
+        loewner_fmm_tile(a, f, l, a.tiles[item], red4, sh);
     });
 }
 
