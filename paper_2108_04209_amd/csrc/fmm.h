@@ -14,6 +14,14 @@ constexpr int FMM_PL = 20;         // Chebyshev terms of a target leaf's local e
 constexpr int FMM_LOC = 4 * FMM_PL; // local expansion of a target leaf: psi, psi', phi, phi'
                                     // far fields, FMM_PL Chebyshev coefficients each
 
+// Chebyshev nodes (first kind) of a P-point grid on [-1, 1], cos((2q + 1) pi / 2P), and the
+// barycentric weights of the first FMM_P of them, (-1)^q sin((2q + 1) pi / 2P)
+__device__ __forceinline__ double cheb_node(int q, int P = FMM_P) {
+    return cos((2.0 * q + 1.0) * 3.14159265358979323846 / (2.0 * P));
+}
+__device__ __forceinline__ double cheb_bary(int q) {
+    return ((q & 1) ? -1.0 : 1.0) * sin((2.0 * q + 1.0) * 3.14159265358979323846 / (2.0 * FMM_P));
+}
 // Per batch: the problems that use the FMM, their trees, and per-leaf interaction lists.
 // Problem q (in FMM numbering) owns boxes [box_off[q], box_off[q+1]) in heap order over its
 // leaves (level h has 2^h boxes; box (h, i) covers leaves [i 2^(H-h), (i+1) 2^(H-h))), and

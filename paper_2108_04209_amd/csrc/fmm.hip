@@ -18,14 +18,6 @@
 
 namespace sdc {
 
-__device__ __forceinline__ double cheb_node(int q, int P = FMM_P) {
-    return cos((2.0 * q + 1.0) * 3.14159265358979323846 / (2.0 * P));
-}
-
-// barycentric weight of Chebyshev node q (first kind): (-1)^q sin((2q+1) pi / 2P)
-__device__ __forceinline__ double cheb_bary(int q) {
-    return ((q & 1) ? -1.0 : 1.0) * sin((2.0 * q + 1.0) * 3.14159265358979323846 / (2.0 * FMM_P));
-}
 
 // pole range [lo, hi) of box g of FMM problem q, and its level h
 struct BoxRange {

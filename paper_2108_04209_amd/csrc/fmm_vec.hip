@@ -17,17 +17,6 @@ namespace sdc {
 
 typedef double v4d_f __attribute__((ext_vector_type(4)));
 
-namespace {
-
-__device__ __forceinline__ double cheb_node_v(int q) {
-    return cos((2.0 * q + 1.0) * 3.14159265358979323846 / (2.0 * FMM_P));
-}
-
-__device__ __forceinline__ double cheb_bary_v(int q) {
-    return ((q & 1) ? -1.0 : 1.0) * sin((2.0 * q + 1.0) * 3.14159265358979323846 / (2.0 * FMM_P));
-}
-
-}  // namespace
 
 // src_i,c = zhat_i X_i,c0+c (kern 1) or zhat_i^2 (kern 2); one lane per pole.  trans 0:
 // src_j,c = b_j X_j,c0+c at the root lambda_j (positions in pairs[j].x); one lane per root
@@ -118,8 +107,8 @@ __global__ __launch_bounds__(LEAVES ? 64 : 256) void k_fmmv_sources(FmmArgs f, F
     double tq[FMM_P], lam[FMM_P];
 #pragma unroll
     for (int r = 0; r < FMM_P; ++r) {
-        tq[r] = cheb_node_v(r);
-        lam[r] = cheb_bary_v(r);
+        tq[r] = cheb_node(r);
+        lam[r] = cheb_bary(r);
     }
     const double ihw = 1.0 / hw;
     v4d_f acc = v4d_f{0.0, 0.0, 0.0, 0.0};
@@ -618,7 +607,12 @@ __global__ __launch_bounds__(LEAVES ? 64 : 256) void k_fmml_moments(FmmArgs f, F
             l.mom[(int64_t)g * FMML_K + tid] = sk;
         }
     } else {
-        for (int stride = blockDim.x / 2; stride > 0; stride >>= 1) {
+        // only the first nleaf threads hold moments: the tree starts at the smallest power
+        // of two that covers them (the same fixed order for a given box)
+        const int nleaf = (int)((hi - lo + f.leaf - 1) / f.leaf);
+        int width = 1;
+        while (width < min(nleaf, (int)blockDim.x)) width <<= 1;
+        for (int stride = width / 2; stride > 0; stride >>= 1) {
             if (tid < stride)
                 for (int k = 0; k < FMML_K; ++k) part[tid][k] += part[tid + stride][k];
             __syncthreads();
