@@ -200,6 +200,30 @@ FmmPlan *fmm_plan(superdc_batch *b, int leaf, int crossover) {
     }
     fp->nboxes = fp->box_off_h.back();
     fp->nleaves = fp->leaf_off_h.back();
+    // the boxes the source kernels visit, so that their grids hold no workgroup without a
+    // box: every leaf (all hold poles), and every upper box with poles, largest first
+    std::vector<int32_t> leaf_box, upper_box;
+    {
+        std::vector<std::pair<int, int32_t>> up;  // (leaves below, global box id)
+        for (int q = 0; q < fp->nfmm; ++q) {
+            const int H = height[q];
+            const int nl = fp->leaf_off_h[q + 1] - fp->leaf_off_h[q];
+            const int32_t b0 = fp->box_off_h[q];
+            for (int l = 0; l < nl; ++l) leaf_box.push_back(b0 + (1 << H) - 1 + l);
+            for (int h = 0; h < H; ++h)
+                for (int i = 0; i < (1 << h); ++i) {
+                    const int first = i << (H - h);
+                    if (first < nl)
+                        up.emplace_back(std::min(1 << (H - h), nl - first), b0 + (1 << h) - 1 + i);
+                }
+        }
+        std::stable_sort(up.begin(), up.end(),
+                         [](const std::pair<int, int32_t> &x, const std::pair<int, int32_t> &y) {
+                             return x.first > y.first;
+                         });
+        for (const auto &e : up) upper_box.push_back(e.second);
+    }
+    fp->nupper = (int)upper_box.size();
     // work items (64-root pieces of the target leaves) in problem order and longest-first
     std::vector<Tile> lnat, llpt;
     fp->item_off_h.push_back(0);
@@ -244,6 +268,7 @@ FmmPlan *fmm_plan(superdc_batch *b, int leaf, int crossover) {
               fmm_upload(fp, &fp->box_off, fp->box_off_h) &&
               fmm_upload(fp, &fp->leaf_off, fp->leaf_off_h) && fmm_upload(fp, &fp->height, height) &&
               fmm_upload(fp, &fp->box_fmm, box_fmm) && fmm_upload(fp, &fp->leaf_fmm, leaf_fmm) &&
+              fmm_upload(fp, &fp->leaf_box, leaf_box) && fmm_upload(fp, &fp->upper_box, upper_box) &&
               fmm_upload(fp, &fp->leaf_nat, lnat) && fmm_upload(fp, &fp->leaf_lpt, llpt) &&
               fmm_upload(fp, &fp->sitem_nat, snat) && fmm_upload(fp, &fp->sitem_lpt, slpt) &&
               fmm_upload(fp, &fp->eq, std::vector<double2>(), (size_t)fp->nboxes * FMM_P) &&
@@ -333,6 +358,9 @@ FmmArgs fmm_args(const FmmPlan *fp, const superdc_batch *b, const SolveArgs &a,
     f.nleaves = fp->nleaves;
     f.box_fmm = fp->box_fmm;
     f.leaf_fmm = fp->leaf_fmm;
+    f.leaf_box = fp->leaf_box;
+    f.upper_box = fp->upper_box;
+    f.nupper = fp->nupper;
     (void)o;
     return f;
 }

@@ -107,30 +107,6 @@ __device__ __forceinline__ cquad as_const(const double4 *p) { return cquad{(cons
 typedef cpair const_double2_ptr;
 typedef cquad const_double4_ptr;
 
-// Sum K values over the workgroup (blockDim.x a multiple of 64): each wavefront adds its
-// lanes by xor shuffles, then the wavefronts' sums are added in wavefront order through
-// `lds` (K * blockDim.x / 64 doubles).  Every thread ends with the same totals.
-template <int K>
-__device__ __forceinline__ void block_sum(double (&v)[K], double *lds) {
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-        for (int o = WAVE / 2; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o);
-    const int nw = blockDim.x / WAVE;
-    if (nw == 1) return;
-    const int wv = threadIdx.x / WAVE;
-    if ((threadIdx.x & (WAVE - 1)) == 0) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) lds[wv * K + k] = v[k];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        double s = 0.0;
-        for (int w = 0; w < nw; ++w) s += lds[w * K + k];
-        v[k] = s;
-    }
-}
-
 // Pull the next work item from a persistent queue (called by whole wavefront-0 of a WG
 // and broadcast through LDS).  Returns -1 when the queue is drained.
 __device__ __forceinline__ int queue_pull(Queue *q, int nitems, int *slot) {

@@ -60,6 +60,10 @@ struct FmmArgs {
     int nboxes, nleaves;
     const int32_t *box_fmm;   // [nboxes] owning FMM problem of each box
     const int32_t *leaf_fmm;  // [nleaves] owning FMM problem of each leaf
+    const int32_t *leaf_box;  // [nleaves] global box id of each leaf
+    const int32_t *upper_box; // [nupper] global ids of the boxes above the leaves that hold
+                              // poles, the largest (most leaves below) first
+    int nupper;
     // targets of the lists: nullptr, the roots of the solver (a target leaf's roots lie in
     // [d_first, d_next]); else the positions of the target points themselves (the poles, for
     // sums over the roots), a leaf spanning [tpos[first], tpos[last]]
@@ -74,6 +78,8 @@ struct FmmPlan {
     std::vector<int32_t> fmm_prob_h, fmm_of_h, box_off_h, leaf_off_h;
     int32_t *fmm_prob = nullptr, *fmm_of = nullptr, *box_off = nullptr, *leaf_off = nullptr;
     int32_t *height = nullptr, *box_fmm = nullptr, *leaf_fmm = nullptr;
+    int32_t *leaf_box = nullptr, *upper_box = nullptr;
+    int nupper = 0;
     double2 *eq = nullptr, *box_ab = nullptr;
     int32_t *near_lo = nullptr, *near_hi = nullptr, *far_l = nullptr, *far_r = nullptr;
     int32_t *cnt = nullptr, *near_lf = nullptr;

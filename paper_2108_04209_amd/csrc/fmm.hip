@@ -61,15 +61,18 @@ __global__ __launch_bounds__(256) void k_fmm_geom(FmmArgs f) {
 // and the box's nodes interpolate it again).
 template <bool LEAVES>
 __global__ __launch_bounds__(LEAVES ? 64 : 256) void k_fmm_boxes(FmmArgs f) {
-    __shared__ double part[LEAVES ? 64 * (FMM_P + 1) : (256 / WAVE) * FMM_P];
-    const int g = blockIdx.x;
+    static_assert(FMM_P == 16, "the upper boxes' sum maps 256 threads to 16 x 16");
+    constexpr int NT = LEAVES ? 64 : 256;
+    __shared__ double part[NT * (FMM_P + 1)];
+    __shared__ double red[LEAVES ? 1 : 16 * (FMM_P + 1)];
+    // every leaf in the first launch, the upper boxes with poles in the second (used ones)
+    const int g = LEAVES ? f.leaf_box[blockIdx.x] : f.upper_box[blockIdx.x];
+    if (!LEAVES && !f.used[g]) return;
     const int qf = f.box_fmm[g];
     const int hidx = g - f.box_off[qf];
     const int H = f.height[qf];
     int h = 0;
     while ((2 << h) - 1 <= hidx) ++h;
-    // uniform for the workgroup: every leaf in the first launch, used upper boxes after
-    if (LEAVES ? (h != H) : (h == H || !f.used[g])) return;
     const BoxRange rg = box_range(f, g);
     const int lo = rg.lo, hi = rg.hi;
     if (lo >= hi || (f.status[rg.p] & ~SUPERDC_ST_NOCONV)) return;
@@ -116,17 +119,24 @@ __global__ __launch_bounds__(LEAVES ? 64 : 256) void k_fmm_boxes(FmmArgs f) {
             for (int r = 0; r < FMM_P; ++r) W[r] = __builtin_fma(s, inv[r], W[r]);
         }
     }
+    // the threads' partial weights added in a fixed order through LDS (shuffle trees cost
+    // several microseconds here): one wavefront, lane q adds column q over the 64 lanes;
+    // four, thread (s, q) adds column q over threads 16 s .. 16 s + 15, then lane q the 16
     double wq = 0.0;
-    if (LEAVES) {  // one wavefront: lane q adds column q over the 64 lanes in order
 #pragma unroll
-        for (int r = 0; r < FMM_P; ++r) part[tid * (FMM_P + 1) + r] = W[r];
-        __syncthreads();
+    for (int r = 0; r < FMM_P; ++r) part[tid * (FMM_P + 1) + r] = W[r];
+    __syncthreads();
+    if (LEAVES) {
         if (tid < FMM_P)
             for (int u = 0; u < 64; ++u) wq += part[u * (FMM_P + 1) + tid];
     } else {
-        block_sum<FMM_P>(W, part);
-#pragma unroll
-        for (int r = 0; r < FMM_P; ++r) wq = r == tid ? W[r] : wq;
+        const int q = tid & (FMM_P - 1), s0 = tid >> 4;
+        double ps = 0.0;
+        for (int u = 16 * s0; u < 16 * s0 + 16; ++u) ps += part[u * (FMM_P + 1) + q];
+        red[s0 * (FMM_P + 1) + q] = ps;
+        __syncthreads();
+        if (tid < FMM_P)
+            for (int u = 0; u < 16; ++u) wq += red[u * (FMM_P + 1) + tid];
     }
     if (tid < FMM_P) f.eq[(int64_t)g * FMM_P + tid] = make_double2(c + hw * tq[tid], wq);
 }
@@ -400,8 +410,9 @@ hipError_t launch_fmm_build(const FmmArgs &f, hipStream_t s) {
     if (f.nboxes <= 0) return hipSuccess;
     hipError_t e = launch_fmm_lists(f, s);
     if (e != hipSuccess) return e;
-    SDC_LAUNCH(KID_FMM_BOXES, k_fmm_boxes<true>, dim3(f.nboxes), dim3(64), 0, s, f);
-    SDC_LAUNCH(KID_FMM_BOXES, k_fmm_boxes<false>, dim3(f.nboxes), dim3(256), 0, s, f);
+    SDC_LAUNCH(KID_FMM_BOXES, k_fmm_boxes<true>, dim3(f.nleaves), dim3(64), 0, s, f);
+    if (f.nupper > 0)
+        SDC_LAUNCH(KID_FMM_BOXES, k_fmm_boxes<false>, dim3(f.nupper), dim3(256), 0, s, f);
     SDC_LAUNCH(KID_FMM_LOCAL, k_fmm_local, dim3(f.nleaves), dim3(FMM_PL * LOC_PARTS), 0, s, f);
     return hipGetLastError();
 }

@@ -66,7 +66,9 @@ __global__ __launch_bounds__(LEAVES ? 64 : 256) void k_fmmv_sources(FmmArgs f, F
     constexpr int FV_CHUNK = 64 * NW;
     __shared__ double Lq[FV_CHUNK][FMM_P + 1];
     __shared__ double Ss[FV_CHUNK][FMMV_MAX_M + 1];
-    const int g = blockIdx.x;
+    // leaves in the first launch, the upper boxes with poles in the second (used ones)
+    const int g = LEAVES ? f.leaf_box[blockIdx.x] : f.upper_box[blockIdx.x];
+    if (!LEAVES && !f.used[g]) return;
     const int qf = f.box_fmm[g];
     const int p = f.fmm_prob[qf];
     const int64_t base = f.off[p];
@@ -75,8 +77,6 @@ __global__ __launch_bounds__(LEAVES ? 64 : 256) void k_fmmv_sources(FmmArgs f, F
     const int H = f.height[qf];
     int h = 0;
     while ((2 << h) - 1 <= hidx) ++h;
-    // uniform for the workgroup: leaves in the first launch, used upper boxes in the second
-    if (LEAVES ? (h != H) : (h == H || !f.used[g])) return;
     if (f.status[p] & ~SUPERDC_ST_NOCONV) return;
     const int bi = hidx - ((1 << h) - 1);
     const int64_t span = (int64_t)f.leaf << (H - h);
@@ -114,9 +114,7 @@ __global__ __launch_bounds__(LEAVES ? 64 : 256) void k_fmmv_sources(FmmArgs f, F
     v4d_f acc = v4d_f{0.0, 0.0, 0.0, 0.0};
     for (int k0 = 0; k0 < npts; k0 += FV_CHUNK) {
         const int k = k0 + tid;
-        if (tid >= FV_CHUNK) {
-            // the chunk's points have their threads
-        } else if (k < npts) {
+        if (k < npts) {
             double x;
             const double *wk;
             if (LEAVES) {
@@ -533,12 +531,14 @@ __global__ __launch_bounds__(256) void k_fmmv_eval_mfma(SolveArgs it, FmmArgs f,
 // the box's centre and half-width (t_box = alpha + beta t_leaf):
 //     M_k = sum_m C(k, m) alpha^(k-m) beta^m M_m(leaf),  T_k(m) = alpha T_{k-1}(m) + beta T_{k-1}(m-1)
 // (M_0 = 0: each pole-root pair carries opposite unit charges).  One workgroup per box; the
-// per-thread partial moments are added by a fixed-order tree in LDS.
+// per-thread partial moments are added in a fixed order through LDS.
 // ---------------------------------------------------------------------------------------
 template <bool LEAVES>
 __global__ __launch_bounds__(LEAVES ? 64 : 256) void k_fmml_moments(FmmArgs f, FmmlArgs l) {
-    __shared__ double part[LEAVES ? 64 : 256][FMML_K + 1];
-    const int g = blockIdx.x;
+    __shared__ double part[64][FMML_K + 1];
+    __shared__ double part2[LEAVES ? 1 : 64][FMML_K + 1];
+    const int g = LEAVES ? f.leaf_box[blockIdx.x] : f.upper_box[blockIdx.x];
+    if (!LEAVES && !f.used[g]) return;
     const int qf = f.box_fmm[g];
     const int p = f.fmm_prob[qf];
     const int64_t base = f.off[p];
@@ -547,7 +547,6 @@ __global__ __launch_bounds__(LEAVES ? 64 : 256) void k_fmml_moments(FmmArgs f, F
     const int H = f.height[qf];
     int h = 0;
     while ((2 << h) - 1 <= hidx) ++h;
-    if (LEAVES ? (h != H) : (h == H || !f.used[g])) return;  // uniform for the workgroup
     if (f.status[p] & ~SUPERDC_ST_NOCONV) return;
     const int bi = hidx - ((1 << h) - 1);
     const int64_t span = (int64_t)f.leaf << (H - h);
@@ -597,21 +596,51 @@ __global__ __launch_bounds__(LEAVES ? 64 : 256) void k_fmml_moments(FmmArgs f, F
             }
         }
     }
-#pragma unroll
-    for (int k = 0; k < FMML_K; ++k) part[tid][k] = M[k];
-    __syncthreads();
     if (LEAVES) {  // one wavefront: lane k adds column k over the 64 lanes in order
+#pragma unroll
+        for (int k = 0; k < FMML_K; ++k) part[tid][k] = M[k];
+        __syncthreads();
         if (tid < FMML_K) {
             double sk = 0.0;
             for (int u = 0; u < 64; ++u) sk += part[u][tid];
             l.mom[(int64_t)g * FMML_K + tid] = sk;
         }
     } else {
-        // only the first nleaf threads hold moments: the tree starts at the smallest power
-        // of two that covers them (the same fixed order for a given box)
+        // only the first nleaf threads hold moments.  Beyond 64 leaves the four wavefronts
+        // are folded onto the first, (w0 + w2) + (w1 + w3), through two 64-row buffers; the
+        // tree over the first wavefront's rows starts at the smallest power of two that
+        // covers the rows in use (the same fixed order for a given box)
         const int nleaf = (int)((hi - lo + f.leaf - 1) / f.leaf);
+        const int wv = tid / WAVE, ln = tid % WAVE;
+        if (nleaf > WAVE) {
+            if (wv >= 2) {
+#pragma unroll
+                for (int k = 0; k < FMML_K; ++k) (wv == 2 ? part : part2)[ln][k] = M[k];
+            }
+            __syncthreads();
+            if (wv < 2) {
+#pragma unroll
+                for (int k = 0; k < FMML_K; ++k) M[k] += (wv == 0 ? part : part2)[ln][k];
+            }
+            __syncthreads();
+            if (wv == 1) {
+#pragma unroll
+                for (int k = 0; k < FMML_K; ++k) part[ln][k] = M[k];
+            }
+            __syncthreads();
+            if (wv == 0) {
+#pragma unroll
+                for (int k = 0; k < FMML_K; ++k) M[k] += part[ln][k];
+            }
+            __syncthreads();
+        }
+        if (wv == 0) {
+#pragma unroll
+            for (int k = 0; k < FMML_K; ++k) part[ln][k] = M[k];
+        }
+        __syncthreads();
         int width = 1;
-        while (width < min(nleaf, (int)blockDim.x)) width <<= 1;
+        while (width < min(nleaf, WAVE)) width <<= 1;
         for (int stride = width / 2; stride > 0; stride >>= 1) {
             if (tid < stride)
                 for (int k = 0; k < FMML_K; ++k) part[tid][k] += part[tid + stride][k];
@@ -624,8 +653,10 @@ __global__ __launch_bounds__(LEAVES ? 64 : 256) void k_fmml_moments(FmmArgs f, F
 
 hipError_t launch_fmml_moments(const FmmArgs &f, const FmmlArgs &l, hipStream_t s) {
     if (f.nboxes <= 0) return hipSuccess;
-    SDC_LAUNCH(KID_FMML_MOMENTS, k_fmml_moments<true>, dim3(f.nboxes), dim3(64), 0, s, f, l);
-    SDC_LAUNCH(KID_FMML_MOMENTS, k_fmml_moments<false>, dim3(f.nboxes), dim3(256), 0, s, f, l);
+    SDC_LAUNCH(KID_FMML_MOMENTS, k_fmml_moments<true>, dim3(f.nleaves), dim3(64), 0, s, f, l);
+    if (f.nupper > 0)
+        SDC_LAUNCH(KID_FMML_MOMENTS, k_fmml_moments<false>, dim3(f.nupper), dim3(256), 0, s, f,
+                   l);
     return hipGetLastError();
 }
 
@@ -656,8 +687,10 @@ hipError_t launch_fmmv_pack(const FmmvPackArgs &a, const FmmVec &v, hipStream_t 
 
 hipError_t launch_fmmv_sources(const FmmArgs &f, const FmmVec &v, hipStream_t s) {
     if (f.nboxes <= 0) return hipSuccess;
-    SDC_LAUNCH(KID_FMMV_SOURCES, k_fmmv_sources<true>, dim3(f.nboxes), dim3(64), 0, s, f, v);
-    SDC_LAUNCH(KID_FMMV_SOURCES, k_fmmv_sources<false>, dim3(f.nboxes), dim3(256), 0, s, f, v);
+    SDC_LAUNCH(KID_FMMV_SOURCES, k_fmmv_sources<true>, dim3(f.nleaves), dim3(64), 0, s, f, v);
+    if (f.nupper > 0)
+        SDC_LAUNCH(KID_FMMV_SOURCES, k_fmmv_sources<false>, dim3(f.nupper), dim3(256), 0, s, f,
+                   v);
     return hipGetLastError();
 }
 
