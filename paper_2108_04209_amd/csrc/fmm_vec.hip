@@ -57,15 +57,16 @@ __global__ __launch_bounds__(64) void k_fmmv_pack(FmmvPackArgs a, FmmVec v) {
 // n/4 poles: the far field of a leaf's sources equals that of its poles to the
 // interpolation accuracy, and the box's nodes interpolate it again).  Points are taken a
 // chunk at a time: each of the chunk's threads forms the 16 Lagrange values of one point in
-// LDS, then W_q,c += sum_k L_q(x_k) w_k,c over the chunk runs on the FP64 MFMA.
+// LDS, then W_q,c += sum_k L_q(x_k) w_k,c over the chunk runs on the FP64 MFMA, its weight
+// operands loaded straight from memory (they are point-major: the 4 points x m columns of
+// one step are consecutive) before the Lagrange values are formed.
 template <bool LEAVES>
-__global__ __launch_bounds__(LEAVES ? 64 : 256) void k_fmmv_sources(FmmArgs f, FmmVec v) {
+__global__ __launch_bounds__(LEAVES ? 64 : 256, LEAVES ? 1 : 4) void k_fmmv_sources(FmmArgs f, FmmVec v) {
     // leaves: one wavefront, 64 points per chunk; upper boxes (up to 16 sources per leaf
     // below): four wavefronts, 256 points per chunk
     constexpr int NW = LEAVES ? 1 : 4;
     constexpr int FV_CHUNK = 64 * NW;
     __shared__ double Lq[FV_CHUNK][FMM_P + 1];
-    __shared__ double Ss[FV_CHUNK][FMMV_MAX_M + 1];
     // leaves in the first launch, the upper boxes with poles in the second (used ones)
     const int g = LEAVES ? f.leaf_box[blockIdx.x] : f.upper_box[blockIdx.x];
     if (!LEAVES && !f.used[g]) return;
@@ -112,19 +113,24 @@ __global__ __launch_bounds__(LEAVES ? 64 : 256) void k_fmmv_sources(FmmArgs f, F
     }
     const double ihw = 1.0 / hw;
     v4d_f acc = v4d_f{0.0, 0.0, 0.0, 0.0};
+    // the points' weights, m per point: the leaf's poles in src, or the sources of the
+    // box's leaves
+    const double *wsrc = LEAVES ? src + (int64_t)lo * m
+                                : v.vw + (int64_t)(f.box_off[qf] + leaf0) * FMM_P * m;
     for (int k0 = 0; k0 < npts; k0 += FV_CHUNK) {
+        // W (16 nodes x 16 columns) += L (16 x chunk) S (chunk x 16) on the FP64 MFMA: each
+        // wavefront takes 64 points of the chunk, 4 per step
+        // (A lane l = L[l % 16][k + l / 16], B lane l = S[k + l / 16][l % 16])
+        double bs[16];
+#pragma unroll
+        for (int st = 0; st < 16; ++st) {
+            const int pt = k0 + wv * 64 + 4 * st + (lane >> 4), c = lane & 15;
+            bs[st] = pt < npts && c < m ? wsrc[(int64_t)pt * m + c] : 0.0;
+        }
         const int k = k0 + tid;
         if (k < npts) {
-            double x;
-            const double *wk;
-            if (LEAVES) {
-                x = d(lo + k);
-                wk = src + (int64_t)(lo + k) * m;
-            } else {
-                const int gl = f.box_off[qf] + leaf0 + k / FMM_P;
-                x = v.vnode[(int64_t)gl * FMM_P + k % FMM_P];
-                wk = v.vw + ((int64_t)gl * FMM_P + k % FMM_P) * m;
-            }
+            const double x = LEAVES ? d(lo + k)
+                                    : v.vnode[(int64_t)(f.box_off[qf] + leaf0) * FMM_P + k];
             const double t = fmin(1.0, fmax(-1.0, (x - cc) * ihw));
             int hit = -1;
             double inv[FMM_P], den = 0.0;
@@ -139,21 +145,15 @@ __global__ __launch_bounds__(LEAVES ? 64 : 256) void k_fmmv_sources(FmmArgs f, F
 #pragma unroll
             for (int r = 0; r < FMM_P; ++r)
                 Lq[tid][r] = hit >= 0 ? (r == hit ? 1.0 : 0.0) : inv[r] * iden;
-            for (int cc2 = 0; cc2 < FMMV_MAX_M; ++cc2) Ss[tid][cc2] = cc2 < m ? wk[cc2] : 0.0;
         } else {
 #pragma unroll
             for (int r = 0; r < FMM_P; ++r) Lq[tid][r] = 0.0;
-            for (int cc2 = 0; cc2 < FMMV_MAX_M; ++cc2) Ss[tid][cc2] = 0.0;
         }
         __syncthreads();
-        // W (16 nodes x 16 columns) += L (16 x chunk) S (chunk x 16) on the FP64 MFMA: each
-        // wavefront takes 64 points of the chunk, 4 per step
-        // (A lane l = L[l % 16][k + l / 16], B lane l = S[k + l / 16][l % 16])
 #pragma unroll
         for (int st = 0; st < 16; ++st) {
             const int kk = wv * 64 + 4 * st + (lane >> 4);
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Lq[kk][lane & 15], Ss[kk][lane & 15], acc,
-                                                     0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Lq[kk][lane & 15], bs[st], acc, 0, 0, 0);
         }
         __syncthreads();
     }
