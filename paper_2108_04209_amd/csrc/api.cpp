@@ -814,6 +814,12 @@ int superdc_batch_create(superdc_ctx *ctx, int32_t nprob, const int64_t *off_hos
     hipError_t e = hipMalloc(&b->off_d, sizeof(int64_t) * (nprob + 1));
     if (e == hipSuccess)
         e = hipMemcpy(b->off_d, off_host, sizeof(int64_t) * (nprob + 1), hipMemcpyHostToDevice);
+    // problems of 16384 entries and more are validated in slices of about 4096
+    b->vsplit = max_n >= 16384 ? std::min(16, max_n / 4096) : 1;
+    if (e == hipSuccess && b->vsplit > 1) {
+        e = hipMalloc(&b->vsum, sizeof(double) * nprob * b->vsplit);
+        if (e == hipSuccess) e = hipMalloc(&b->vst, sizeof(int32_t) * nprob * b->vsplit);
+    }
     if (e == hipSuccess && !tile_list(b, TILE)) e = hipErrorOutOfMemory;
     if (e != hipSuccess) {
         superdc_batch_destroy(b);
@@ -838,6 +844,8 @@ void superdc_batch_destroy(superdc_batch *b) {
     if (!b) return;
     (void)hipDeviceSynchronize();
     if (b->off_d) (void)hipFree(b->off_d);
+    if (b->vsum) (void)hipFree(b->vsum);
+    if (b->vst) (void)hipFree(b->vst);
     fmm_free(b->fmm);
     for (auto &l : b->lists) {
         if (l.nat) (void)hipFree(l.nat);
@@ -900,7 +908,7 @@ int superdc_secular_solve(superdc_ctx *ctx, const superdc_batch *b, const double
             a.tiles = fp->dir_lpt[slot];
             a.ntiles = fp->dir_count[slot];
         }
-        SDC_HIP(launch_validate(a, 0, b->nprob, b->max_n, s));
+        SDC_HIP(launch_validate(a, 0, b->nprob, b->max_n, s, b->vsplit, b->vsum, b->vst));
         if (fp) SDC_HIP(launch_fmm_build(f, s));
         a.work = trace_work(KID_SECULAR);
         SDC_HIP(launch_secular(a, sh.split, ctx->queues + Q_SECULAR,
@@ -919,7 +927,7 @@ int superdc_secular_solve(superdc_ctx *ctx, const superdc_batch *b, const double
         // one launch per problem, cut into 64-root chunks (split if the problem is large),
         // or its target leaves for an FMM problem
         if (fp) {
-            SDC_HIP(launch_validate(a, 0, b->nprob, b->max_n, s));
+            SDC_HIP(launch_validate(a, 0, b->nprob, b->max_n, s, b->vsplit, b->vsum, b->vst));
             SDC_HIP(launch_fmm_build(f, s));
         }
         for (int p = 0; p < b->nprob; ++p) {

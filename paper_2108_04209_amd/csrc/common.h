@@ -245,6 +245,10 @@ struct superdc_batch {
     bool tuned = false;
     // triangular-FMM layout (built on the first FMM solve; see fmm.h)
     sdc::FmmPlan *fmm = nullptr;
+    // validation of long problems: slices per problem and their partial sums
+    int vsplit = 1;
+    double *vsum = nullptr;     // [nprob][vsplit]
+    int32_t *vst = nullptr;     // [nprob][vsplit]
 };
 
 namespace sdc {
@@ -301,7 +305,11 @@ struct SolveArgs {
     int unshifted;   // ablation: iterate on lambda itself, every difference d_j - lambda
     int hybrid;      // interpolation: 0 middle way, 1 the middle-way / fixed-weight hybrid
 };
-hipError_t launch_validate(const SolveArgs &a, int prob_first, int nprob, int max_n, hipStream_t s);
+// validation and packing of problems [prob_first, prob_first + nprob); with vsplit > 1 each
+// problem is cut into vsplit slices, one workgroup each, whose partial sums go to vsum/vst
+// ([nprob][vsplit], indexed by problem) and are added in slice order by a second launch
+hipError_t launch_validate(const SolveArgs &a, int prob_first, int nprob, int max_n, hipStream_t s,
+                           int vsplit = 1, double *vsum = nullptr, int32_t *vst = nullptr);
 hipError_t launch_secular(const SolveArgs &a, int split, Queue *q, int grid, hipStream_t s);
 
 struct VecArgs {

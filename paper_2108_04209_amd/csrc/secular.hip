@@ -29,18 +29,31 @@ namespace sdc {
 // ---------------------------------------------------------------------------------------
 // validation and packing: dw_j = (d_j, rho z_j^2), z2 = sum_j w_j, status bits
 // ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_validate(SolveArgs a, int prob_first) {
+// status bits of a problem beyond its entries' (those of rho)
+__device__ __forceinline__ int rho_status(double rho) {
+    if (!isfinite(rho)) return SUPERDC_ST_NONFINITE;
+    return rho > 0.0 ? 0 : SUPERDC_ST_RHO;
+}
+
+// Workgroup (problem p, slice s): entries [s len, (s + 1) len) of problem p, len = ceil(n /
+// gridDim.y).  One slice writes z2 and status itself; several write their partial sum and
+// bits to vsum/vst for k_validate_sum.
+__global__ __launch_bounds__(1024) void k_validate(SolveArgs a, int prob_first, double *vsum,
+                                                   int32_t *vst) {
     const int p = prob_first + blockIdx.x;
+    const int S = gridDim.y, sl = blockIdx.y;
     const int64_t base = a.off[p];
     const int n = (int)(a.off[p + 1] - base);
+    const int len = (n + S - 1) / S;
+    const int j0 = min(n, sl * len), j1 = min(n, j0 + len);
     const double rho = a.rho[p];
     int st = 0;
     double ws = 0.0;
     const double *d = a.d + base, *z = a.z + base;
     const int nt = blockDim.x;
     // four entries per thread per step, all loads issued before any use
-    int j = threadIdx.x;
-    for (; j + 3 * nt < n; j += 4 * nt) {
+    int j = j0 + threadIdx.x;
+    for (; j + 3 * nt < j1; j += 4 * nt) {
         double dj[4], dn[4], zj[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -59,7 +72,7 @@ __global__ __launch_bounds__(1024) void k_validate(SolveArgs a, int prob_first) 
             ws += w;
         }
     }
-    for (; j < n; j += nt) {
+    for (; j < j1; j += nt) {
         const double dj = d[j], zj = z[j];
         if (!isfinite(dj) || !isfinite(zj)) st |= SUPERDC_ST_NONFINITE;
         if (zj == 0.0) st |= SUPERDC_ST_ZERO;
@@ -87,11 +100,31 @@ __global__ __launch_bounds__(1024) void k_validate(SolveArgs a, int prob_first) 
             t += sw[w];
             s |= ss[w];
         }
-        if (!isfinite(rho)) s |= SUPERDC_ST_NONFINITE;
-        else if (!(rho > 0.0)) s |= SUPERDC_ST_RHO;
-        a.z2[p] = t;
-        a.status[p] = s;
+        if (S == 1) {
+            a.z2[p] = t;
+            a.status[p] = s | rho_status(rho);
+        } else {
+            vsum[(int64_t)p * S + sl] = t;
+            vst[(int64_t)p * S + sl] = s;
+        }
     }
+}
+
+// the slices' partial sums of each problem added in slice order; one thread per problem
+__global__ __launch_bounds__(64) void k_validate_sum(SolveArgs a, int prob_first, int nprob,
+                                                     int S, const double *vsum,
+                                                     const int32_t *vst) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nprob) return;
+    const int p = prob_first + i;
+    double t = 0.0;
+    int s = 0;
+    for (int sl = 0; sl < S; ++sl) {
+        t += vsum[(int64_t)p * S + sl];
+        s |= vst[(int64_t)p * S + sl];
+    }
+    a.z2[p] = t;
+    a.status[p] = s | rho_status(a.rho[p]);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -844,10 +877,17 @@ hipError_t launch_secular_fmm(const SolveArgs &a, const FmmArgs &f, int split, Q
     return hipGetLastError();
 }
 
-hipError_t launch_validate(const SolveArgs &a, int prob_first, int nprob, int max_n, hipStream_t s) {
-    // one workgroup per problem, sized to the batch's largest problem
-    const int bs = max_n >= 8192 ? 1024 : (max_n >= 2048 ? 512 : 256);
-    SDC_LAUNCH(KID_VALIDATE, k_validate, dim3(nprob), dim3(bs), 0, s, a, prob_first);
+hipError_t launch_validate(const SolveArgs &a, int prob_first, int nprob, int max_n, hipStream_t s,
+                           int vsplit, double *vsum, int32_t *vst) {
+    if (nprob <= 0) return hipSuccess;
+    const int S = vsplit > 1 && vsum && vst ? vsplit : 1;
+    // one workgroup per slice, sized to the largest slice
+    const int per = (max_n + S - 1) / S;
+    const int bs = per >= 8192 ? 1024 : (per >= 2048 ? 512 : 256);
+    SDC_LAUNCH(KID_VALIDATE, k_validate, dim3(nprob, S), dim3(bs), 0, s, a, prob_first, vsum, vst);
+    if (S > 1)
+        SDC_LAUNCH(KID_VALIDATE, k_validate_sum, dim3((nprob + 63) / 64), dim3(64), 0, s, a,
+                   prob_first, nprob, S, (const double *)vsum, (const int32_t *)vst);
     return hipGetLastError();
 }
 
