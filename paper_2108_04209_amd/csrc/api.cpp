@@ -203,6 +203,9 @@ FmmPlan *fmm_plan(superdc_batch *b, int leaf, int crossover) {
     // the boxes the source kernels visit, so that their grids hold no workgroup without a
     // box: every leaf (all hold poles), and every upper box with poles, largest first
     std::vector<int32_t> leaf_box, upper_box;
+    std::vector<int4> upper_item;
+    std::vector<int2> split_box;
+    int nslot = 0;
     {
         std::vector<std::pair<int, int32_t>> up;  // (leaves below, global box id)
         for (int q = 0; q < fp->nfmm; ++q) {
@@ -222,8 +225,21 @@ FmmPlan *fmm_plan(superdc_batch *b, int leaf, int crossover) {
                              return x.first > y.first;
                          });
         for (const auto &e : up) upper_box.push_back(e.second);
+        for (const auto &e : up) {
+            const int parts = (e.first * FMM_P + FMMV_PART_PTS - 1) / FMMV_PART_PTS;
+            if (parts == 1) {
+                upper_item.push_back(make_int4(e.second, 0, 1, -1));
+                continue;
+            }
+            split_box.push_back(make_int2(e.second, nslot));
+            for (int u = 0; u < parts; ++u)
+                upper_item.push_back(make_int4(e.second, u, parts, nslot + u));
+            nslot += parts;
+        }
     }
     fp->nupper = (int)upper_box.size();
+    fp->nupper_item = (int)upper_item.size();
+    fp->nsplit = (int)split_box.size();
     // work items (64-root pieces of the target leaves) in problem order and longest-first
     std::vector<Tile> lnat, llpt;
     fp->item_off_h.push_back(0);
@@ -269,6 +285,9 @@ FmmPlan *fmm_plan(superdc_batch *b, int leaf, int crossover) {
               fmm_upload(fp, &fp->leaf_off, fp->leaf_off_h) && fmm_upload(fp, &fp->height, height) &&
               fmm_upload(fp, &fp->box_fmm, box_fmm) && fmm_upload(fp, &fp->leaf_fmm, leaf_fmm) &&
               fmm_upload(fp, &fp->leaf_box, leaf_box) && fmm_upload(fp, &fp->upper_box, upper_box) &&
+              fmm_upload(fp, &fp->upper_item, upper_item) && fmm_upload(fp, &fp->split_box, split_box) &&
+              fmm_upload(fp, &fp->vpart, std::vector<double>(),
+                         (size_t)nslot * FMM_P * FMMV_MAX_M) &&
               fmm_upload(fp, &fp->leaf_nat, lnat) && fmm_upload(fp, &fp->leaf_lpt, llpt) &&
               fmm_upload(fp, &fp->sitem_nat, snat) && fmm_upload(fp, &fp->sitem_lpt, slpt) &&
               fmm_upload(fp, &fp->eq, std::vector<double2>(), (size_t)fp->nboxes * FMM_P) &&
@@ -361,6 +380,11 @@ FmmArgs fmm_args(const FmmPlan *fp, const superdc_batch *b, const SolveArgs &a,
     f.leaf_box = fp->leaf_box;
     f.upper_box = fp->upper_box;
     f.nupper = fp->nupper;
+    f.upper_item = fp->upper_item;
+    f.nupper_item = fp->nupper_item;
+    f.split_box = fp->split_box;
+    f.nsplit = fp->nsplit;
+    f.vpart = fp->vpart;
     (void)o;
     return f;
 }

@@ -64,6 +64,14 @@ struct FmmArgs {
     const int32_t *upper_box; // [nupper] global ids of the boxes above the leaves that hold
                               // poles, the largest (most leaves below) first
     int nupper;
+    // the eigenvector-side sources of the upper boxes in parts of at most FMMV_PART_PTS
+    // points: items (box, part, parts, partial slot or -1), largest boxes first; the boxes
+    // cut into several parts (box, first slot) and their partial weights
+    const int4 *upper_item;   // [nupper_item]
+    int nupper_item;
+    const int2 *split_box;    // [nsplit]
+    int nsplit;
+    double *vpart;            // [slots][FMM_P][FMMV_MAX_M]
     // targets of the lists: nullptr, the roots of the solver (a target leaf's roots lie in
     // [d_first, d_next]); else the positions of the target points themselves (the poles, for
     // sums over the roots), a leaf spanning [tpos[first], tpos[last]]
@@ -80,6 +88,10 @@ struct FmmPlan {
     int32_t *height = nullptr, *box_fmm = nullptr, *leaf_fmm = nullptr;
     int32_t *leaf_box = nullptr, *upper_box = nullptr;
     int nupper = 0;
+    int4 *upper_item = nullptr;
+    int2 *split_box = nullptr;
+    int nupper_item = 0, nsplit = 0;
+    double *vpart = nullptr;
     double2 *eq = nullptr, *box_ab = nullptr;
     int32_t *near_lo = nullptr, *near_hi = nullptr, *far_l = nullptr, *far_r = nullptr;
     int32_t *cnt = nullptr, *near_lf = nullptr;
@@ -148,6 +160,7 @@ struct FmmVec {
                               // root for kern 1, 6 for kern 2, plus the output scaling
 };
 constexpr int FMMV_MAX_M = 16;
+constexpr int FMMV_PART_PTS = 1024;  // points per part of an upper box's sources (4 chunks)
 
 // Loewner far field (Sec. 4.3, eqs. lowner2 and logv with local shifting): for a far box B
 // and a pole x outside it,

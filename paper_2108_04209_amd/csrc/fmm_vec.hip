@@ -67,8 +67,10 @@ __global__ __launch_bounds__(LEAVES ? 64 : 256, LEAVES ? 1 : 4) void k_fmmv_sour
     constexpr int NW = LEAVES ? 1 : 4;
     constexpr int FV_CHUNK = 64 * NW;
     __shared__ double Lq[FV_CHUNK][FMM_P + 1];
-    // leaves in the first launch, the upper boxes with poles in the second (used ones)
-    const int g = LEAVES ? f.leaf_box[blockIdx.x] : f.upper_box[blockIdx.x];
+    // leaves in the first launch; in the second the parts of the upper boxes with poles
+    // (used ones): (box, part, parts, partial slot)
+    const int4 it = LEAVES ? make_int4(f.leaf_box[blockIdx.x], 0, 1, -1) : f.upper_item[blockIdx.x];
+    const int g = it.x;
     if (!LEAVES && !f.used[g]) return;
     const int qf = f.box_fmm[g];
     const int p = f.fmm_prob[qf];
@@ -104,6 +106,9 @@ __global__ __launch_bounds__(LEAVES ? 64 : 256, LEAVES ? 1 : 4) void k_fmmv_sour
     const int leaf0 = (1 << H) - 1 + bi * (1 << (H - h));      // heap index of the first leaf
     const int nleaf = (int)((hi - lo + f.leaf - 1) / f.leaf);  // leaves with poles
     const int npts = LEAVES ? hi - lo : nleaf * FMM_P;
+    // this part's points [pk0, pk1)
+    const int pk0 = LEAVES ? 0 : min(npts, it.y * FMMV_PART_PTS);
+    const int pk1 = LEAVES ? npts : (it.z == 1 ? npts : min(npts, pk0 + FMMV_PART_PTS));
     const int lane = tid & (WAVE - 1), wv = tid / WAVE;
     double tq[FMM_P], lam[FMM_P];
 #pragma unroll
@@ -117,7 +122,7 @@ __global__ __launch_bounds__(LEAVES ? 64 : 256, LEAVES ? 1 : 4) void k_fmmv_sour
     // box's leaves
     const double *wsrc = LEAVES ? src + (int64_t)lo * m
                                 : v.vw + (int64_t)(f.box_off[qf] + leaf0) * FMM_P * m;
-    for (int k0 = 0; k0 < npts; k0 += FV_CHUNK) {
+    for (int k0 = pk0; k0 < pk1; k0 += FV_CHUNK) {
         // W (16 nodes x 16 columns) += L (16 x chunk) S (chunk x 16) on the FP64 MFMA: each
         // wavefront takes 64 points of the chunk, 4 per step
         // (A lane l = L[l % 16][k + l / 16], B lane l = S[k + l / 16][l % 16])
@@ -125,10 +130,10 @@ __global__ __launch_bounds__(LEAVES ? 64 : 256, LEAVES ? 1 : 4) void k_fmmv_sour
 #pragma unroll
         for (int st = 0; st < 16; ++st) {
             const int pt = k0 + wv * 64 + 4 * st + (lane >> 4), c = lane & 15;
-            bs[st] = pt < npts && c < m ? wsrc[(int64_t)pt * m + c] : 0.0;
+            bs[st] = pt < pk1 && c < m ? wsrc[(int64_t)pt * m + c] : 0.0;
         }
         const int k = k0 + tid;
-        if (k < npts) {
+        if (k < pk1) {
             const double x = LEAVES ? d(lo + k)
                                     : v.vnode[(int64_t)(f.box_off[qf] + leaf0) * FMM_P + k];
             const double t = fmin(1.0, fmax(-1.0, (x - cc) * ihw));
@@ -172,10 +177,39 @@ __global__ __launch_bounds__(LEAVES ? 64 : 256, LEAVES ? 1 : 4) void k_fmmv_sour
             double s2 = acc[r];
             for (int u = 0; u < NW - 1; ++u) s2 += red[(u * 4 + r) * WAVE + lane];
             const int qn = 4 * r + (lane >> 4), cn = lane & 15;
-            if (cn < m) w[qn * m + cn] = s2;
+            if (it.w >= 0)  // one part of several: its partial weights, summed afterwards
+                f.vpart[((int64_t)it.w * FMM_P + qn) * FMMV_MAX_M + cn] = s2;
+            else if (cn < m)
+                w[qn * m + cn] = s2;
         }
     }
-    if (tid < FMM_P) node[tid] = cc + hw * tq[tid];
+    if (it.y == 0 && tid < FMM_P) node[tid] = cc + hw * tq[tid];
+}
+
+// The weights of the upper boxes computed in several parts: the parts' partial weights
+// added in part order.  One workgroup per such box, thread (node q, column c).
+__global__ __launch_bounds__(FMM_P * FMMV_MAX_M) void k_fmmv_sources_sum(FmmArgs f, FmmVec v) {
+    const int2 sb = f.split_box[blockIdx.x];
+    const int g = sb.x;
+    if (!f.used[g]) return;
+    const int qf = f.box_fmm[g];
+    const int p = f.fmm_prob[qf];
+    if (f.status[p] & ~SUPERDC_ST_NOCONV) return;
+    const int n = (int)(f.off[p + 1] - f.off[p]);
+    const int hidx = g - f.box_off[qf];
+    const int H = f.height[qf];
+    int h = 0;
+    while ((2 << h) - 1 <= hidx) ++h;
+    const int bi = hidx - ((1 << h) - 1);
+    const int64_t span = (int64_t)f.leaf << (H - h);
+    const int lo = (int)min((int64_t)n, bi * span), hi = (int)min((int64_t)n, (bi + 1) * span);
+    const int nleaf = (hi - lo + f.leaf - 1) / f.leaf;
+    const int parts = (nleaf * FMM_P + FMMV_PART_PTS - 1) / FMMV_PART_PTS;
+    const int q = threadIdx.x / FMMV_MAX_M, c = threadIdx.x % FMMV_MAX_M;
+    if (c >= v.m) return;
+    double s = 0.0;
+    for (int u = 0; u < parts; ++u) s += f.vpart[((int64_t)(sb.y + u) * FMM_P + q) * FMMV_MAX_M + c];
+    v.vw[((int64_t)g * FMM_P + q) * v.m + c] = s;
 }
 
 // Evaluation at the roots: work items are 64-root pieces of the target leaves; S
@@ -688,9 +722,12 @@ hipError_t launch_fmmv_pack(const FmmvPackArgs &a, const FmmVec &v, hipStream_t 
 hipError_t launch_fmmv_sources(const FmmArgs &f, const FmmVec &v, hipStream_t s) {
     if (f.nboxes <= 0) return hipSuccess;
     SDC_LAUNCH(KID_FMMV_SOURCES, k_fmmv_sources<true>, dim3(f.nleaves), dim3(64), 0, s, f, v);
-    if (f.nupper > 0)
-        SDC_LAUNCH(KID_FMMV_SOURCES, k_fmmv_sources<false>, dim3(f.nupper), dim3(256), 0, s, f,
-                   v);
+    if (f.nupper_item > 0)
+        SDC_LAUNCH(KID_FMMV_SOURCES, k_fmmv_sources<false>, dim3(f.nupper_item), dim3(256), 0, s,
+                   f, v);
+    if (f.nsplit > 0)
+        SDC_LAUNCH(KID_FMMV_SOURCES, k_fmmv_sources_sum, dim3(f.nsplit), dim3(FMM_P * FMMV_MAX_M),
+                   0, s, f, v);
     return hipGetLastError();
 }
 
