@@ -160,7 +160,7 @@ struct FmmVec {
                               // root for kern 1, 6 for kern 2, plus the output scaling
 };
 constexpr int FMMV_MAX_M = 16;
-constexpr int FMMV_PART_PTS = 1024;  // points per part of an upper box's sources (4 chunks)
+constexpr int FMMV_PART_PTS = 512;   // points per part of an upper box's sources (2 chunks)
 
 // Loewner far field (Sec. 4.3, eqs. lowner2 and logv with local shifting): for a far box B
 // and a pole x outside it,
