@@ -1066,14 +1066,15 @@ def bench_conquer(args):
     opts1 = native.default_opts(persistent=1, fmm_crossover=args.fmm_crossover,
                                 fmm_leaf=args.fmm_leaf)
     out = native.hss_conquer(ctx, plan, gens, opts=opts1)
-    native.hss_set_timing(plan, True)
 
     def timed(opts, steps, warm):
+        # the timed steps run without the phase events (a few hundred event records a step,
+        # about a millisecond); the phase breakdown comes from as many passes after them
+        native.hss_set_timing(plan, False)
         for _ in range(warm):
             native.hss_conquer(ctx, plan, gens, opts=opts, out=out)
         torch.cuda.synchronize()
-        tot, phases = [], {k: 0.0 for k in native.HSS_PHASES}
-        counts = None
+        tot = []
         for _ in range(steps):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
@@ -1081,16 +1082,20 @@ def bench_conquer(args):
             e1.record()
             torch.cuda.synchronize()
             tot.append(e0.elapsed_time(e1))
+        native.hss_set_timing(plan, True)
+        phases, counts = {k: 0.0 for k in native.HSS_PHASES}, None
+        for _ in range(steps):
+            native.hss_conquer(ctx, plan, gens, opts=opts, out=out)
+            torch.cuda.synchronize()
             ph, counts = native.hss_phase_times(plan)
             for k in phases:
                 phases[k] += ph[k] / steps
+        native.hss_set_timing(plan, False)
         return float(np.mean(tot)), phases, counts
 
     # the heuristic launch shapes first, then every level's batch tuned on its own problems
     h_ms = None if args.profile else timed(opts1, args.steps, args.warmup)[0]
-    native.hss_set_timing(plan, False)
     tuned_shapes = native.hss_autotune(ctx, plan, gens, opts=opts1)
-    native.hss_set_timing(plan, True)
     ms, phases, counts = timed(opts1, args.steps, args.warmup)
     note(f"conquer batched {ms:.2f} ms/step (heuristic shapes {h_ms})")
     status = int(out["status"].cpu().numpy()[0])
@@ -1180,7 +1185,6 @@ def bench_conquer(args):
     kflops = conquer_kernel_flops(tree, iters, args.fmm_crossover or FMM_CROSSOVER)
     kflops.update(counted_flops(kw, args.steps))  # solvers and apply kernels: device counts
     kernels, roofline = kernel_roofline(kt, kflops, args.steps, "conquer")
-    native.hss_set_timing(plan, True)
 
     # accuracy: trace identity and sampled eigenpair residuals with the oracle's product
     nA = float(np.abs(lam).max())
