@@ -116,6 +116,46 @@ def test_status_bits():
         assert np.all(np.isfinite(res[k][:40])), k
 
 
+def test_status_bits_sliced():
+    """Problems of 16384 entries and more are validated in slices, one workgroup each, with
+    the slices' sums and status bits combined by a second launch: a defect in a late slice,
+    an unsorted pair across a slice boundary (the last entry of a slice is compared with the
+    first of the next), and a valid problem whose eigenvalues keep the trace identity
+    sum(lambda) = sum(d) + rho |z|^2 and interlace with the poles."""
+    from paper_2108_04209_amd import native
+    from tests import gpu_pipeline as gp
+    n = 20000  # four slices of 5000
+    good = gen.small_batch([n], seed=3).problem(0)
+    probs = []
+    for kind in range(4):
+        d, z, rho = good.d.copy(), good.z.copy(), good.rho
+        if kind == 1:
+            d[4999], d[5000] = d[5000], d[4999]  # across the first slice boundary
+        elif kind == 2:
+            z[17000] = 0.0
+        elif kind == 3:
+            d[19999] = np.inf
+        probs.append(gen.RankOne(d, z, rho))
+    batch = gen.concat(probs)
+    res = gp.run(batch, vectors=False)
+    st = res["status"]
+    assert st[0] == 0, st
+    assert st[1] & native.ST_UNSORTED and not st[1] & (native.ST_ZERO | native.ST_NONFINITE)
+    assert st[2] & native.ST_ZERO and not st[2] & (native.ST_UNSORTED | native.ST_NONFINITE)
+    assert st[3] & native.ST_NONFINITE
+    lam = res["lam"][:n]
+    assert np.all(np.isnan(res["lam"][n:]))
+    # interlacing, up to the rounding of d_K + eta (eta can lie below half an ulp of d_K)
+    assert np.all(lam[:-1] >= good.d[:-1]) and np.all(lam[:-1] <= good.d[1:])
+    assert lam[-1] >= good.d[-1]
+    k = np.arange(n)
+    org, eta = res["origin"][:n], res["eta"][:n]
+    assert np.all((org == k) | (org == k + 1))
+    assert np.all(eta[org == k] > 0) and np.all(eta[org == k + 1] < 0)
+    tr = good.d.sum() + good.rho * np.dot(good.z, good.z)
+    assert abs(lam.sum() - tr) <= 1e-12 * n * np.abs(lam).max()
+
+
 # -------------------------------------------------------------------- Loewner and b
 @pytest.mark.parametrize("kind", ["cfg0", "uniform", "clustered"])
 def test_loewner_kernel(orc, kind):
