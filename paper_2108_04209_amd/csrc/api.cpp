@@ -144,9 +144,11 @@ LaunchShape choose_shape(const superdc_ctx *ctx, const superdc_batch *b, int max
 // far-field separation: a box is far from a target leaf when the gap is >= FMM_SEP times
 // the box's width (Chebyshev order 16 then interpolates both kernels to ~1e-14); a source
 // enters a target leaf's local expansion when its gap to the target interval is >=
-// FMM_SEP_LOC times the interval's width (order 20 then interpolates both sums to ~1e-14)
+// FMM_SEP_LOC times the interval's width (order 20 then interpolates a source's 1/(s - x)
+// to 5e-14 relative and its derivative, which only steers the step, to 2e-12; the stopping
+// test's tolerance is n eps (1 + |psi| + |phi|) >= 1.1e-13 relative for the FMM's n >= 1024)
 constexpr double FMM_SEP = 1.5;
-constexpr double FMM_SEP_LOC = 1.0;
+constexpr double FMM_SEP_LOC = 0.75;
 
 int fmm_dir_slot(int chunk) { return chunk == 64 ? 0 : chunk == 128 ? 1 : chunk == 256 ? 2 : 3; }
 
