@@ -545,6 +545,8 @@ int loewner_run(superdc_ctx *ctx, const superdc_batch *b, const double *d, const
         pk.origin = origin;
         pk.pairs = pairs;
         pk.tail = fp->tail;
+        // every problem uses the FMM: the Loewner packing writes ke as well
+        pk.ke = fp->nfmm == b->nprob ? a.ke : nullptr;
         v.m = 1;
         v.kern = 2;
         v.src = src;
@@ -567,7 +569,7 @@ int loewner_run(superdc_ctx *ctx, const superdc_batch *b, const double *d, const
     }
     a.tiles = L->lpt;
     a.ntiles = L->count;
-    SDC_HIP(launch_pack_ke(a, s));
+    if (!pk.ke) SDC_HIP(launch_pack_ke(a, s));
     if (o.persistent) {
         const int S = b->vec.split;
         if (fp) {

@@ -192,6 +192,8 @@ struct FmmvPackArgs {
     int c0;
     double2 *pairs;      // (d_i, zhat_i) for the list geometry; trans 0: (lambda_j, b_j)
     double *tail;        // [nprob] lambda_{n-1} - d_{n-1}
+    double2 *ke;         // Loewner packing, when every problem of the batch uses the FMM:
+                         // also (d_{K_j}, eta_j) for every root (else nullptr)
 };
 hipError_t launch_fmmv_pack(const FmmvPackArgs &a, const FmmVec &v, hipStream_t s);
 // Loewner far field: (d_j, delta_j) pairs and the last roots' offsets, then the products

@@ -702,8 +702,11 @@ __global__ __launch_bounds__(64) void k_fmml_pack(FmmvPackArgs a) {
     const int j = t.row0 + lane_id();
     if (j >= n) return;
     const double dj = a.d[base + j];
-    const double delta = (a.d[base + clamp_idx(a.origin[base + j], n)] - dj) + a.eta[base + j];
+    const double dK = a.d[base + clamp_idx(a.origin[base + j], n)];
+    const double ej = a.eta[base + j];
+    const double delta = (dK - dj) + ej;
     a.pairs[base + j] = make_double2(dj, delta);
+    if (a.ke) a.ke[base + j] = make_double2(dK, ej);
     if (j == n - 1) a.tail[t.prob] = delta;
 }
 
