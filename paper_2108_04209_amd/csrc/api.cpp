@@ -293,7 +293,6 @@ FmmPlan *fmm_plan(superdc_batch *b, int leaf, int crossover) {
               fmm_upload(fp, &fp->leaf_nat, lnat) && fmm_upload(fp, &fp->leaf_lpt, llpt) &&
               fmm_upload(fp, &fp->sitem_nat, snat) && fmm_upload(fp, &fp->sitem_lpt, slpt) &&
               fmm_upload(fp, &fp->eq, std::vector<double2>(), (size_t)fp->nboxes * FMM_P) &&
-              fmm_upload(fp, &fp->box_ab, std::vector<double2>(), fp->nboxes) &&
               fmm_upload(fp, &fp->near_lo, std::vector<int32_t>(), (size_t)fp->nleaves * FMM_NEAR_MAX) &&
               fmm_upload(fp, &fp->near_hi, std::vector<int32_t>(), (size_t)fp->nleaves * FMM_NEAR_MAX) &&
               fmm_upload(fp, &fp->far_l, std::vector<int32_t>(), (size_t)fp->nleaves * FMM_FAR_MAX) &&
@@ -322,7 +321,6 @@ FmmPlan *fmm_plan(superdc_batch *b, int leaf, int crossover) {
               fmm_upload(fp, &fp->t_far_rd, std::vector<int32_t>(), (size_t)fp->nleaves * FMM_FAR_MAX) &&
               fmm_upload(fp, &fp->t_cntd, std::vector<int32_t>(), (size_t)fp->nleaves * 2) &&
               fmm_upload(fp, &fp->t_used, std::vector<int32_t>(), fp->nboxes) &&
-              fmm_upload(fp, &fp->t_box_ab, std::vector<double2>(), fp->nboxes) &&
               fmm_upload(fp, &fp->t_loc_ab, std::vector<double2>(), (size_t)fp->nleaves);
     // direct chunks of the other problems, for each cut length
     fp->dir_lpt.assign(4, nullptr);
@@ -338,6 +336,10 @@ FmmPlan *fmm_plan(superdc_batch *b, int leaf, int crossover) {
         fp->dir_count[slot] = (int32_t)v.size();
         ok = fmm_upload(fp, &fp->dir_lpt[slot], v);
     }
+    // the use flags start below every lists number (the first build is number 1)
+    ok = ok && hipMemset(fp->used, 0, sizeof(int32_t) * std::max(1, fp->nboxes)) == hipSuccess &&
+         hipMemset(fp->t_used, 0, sizeof(int32_t) * std::max(1, fp->nboxes)) == hipSuccess &&
+         hipDeviceSynchronize() == hipSuccess;
     if (!ok) {
         fmm_free(fp);
         return nullptr;
@@ -362,8 +364,8 @@ FmmArgs fmm_args(const FmmPlan *fp, const superdc_batch *b, const SolveArgs &a,
     f.tail = a.z2;  // the last root lies below d_{n-1} + sum_j w_j
     f.status = a.status;
     f.used = fp->used;
+    f.gen = fp->gen;
     f.eq = fp->eq;
-    f.box_ab = fp->box_ab;
     f.near_lo = fp->near_lo;
     f.near_hi = fp->near_hi;
     f.near_lf = fp->near_lf;
@@ -420,7 +422,7 @@ FmmArgs fmm_roots_args(const FmmPlan *fp, const superdc_batch *b, const double2 
     f.far_rd = fp->t_far_rd;
     f.cntd = fp->t_cntd;
     f.used = fp->t_used;
-    f.box_ab = fp->t_box_ab;
+    f.gen = fp->t_gen;
     f.loc_ab = fp->t_loc_ab;
     return f;
 }
@@ -564,7 +566,10 @@ int loewner_run(superdc_ctx *ctx, const superdc_batch *b, const double *d, const
         // (d_j, delta_j) pairs, the lists of these poles (unless the solve left them), the
         // Loewner moments of every leaf and used box
         SDC_HIP(launch_fmml_pack(pk, s));
-        if (!reuse_lists) SDC_HIP(launch_fmm_lists(f, s));
+        if (!reuse_lists) {
+            f.gen = ++fp->gen;
+            SDC_HIP(launch_fmm_lists(f, s));
+        }
         SDC_HIP(launch_fmml_moments(f, lf, s));
     }
     a.tiles = L->lpt;
@@ -698,7 +703,8 @@ int apply_run(superdc_ctx *ctx, const superdc_batch *b, const double *d, const d
         v.post = zhat;
         v.ldy = ldy;
         v.zh = zhat;
-        const FmmArgs f = fmm_roots_args(fp, b, pairs, status, d);
+        FmmArgs f = fmm_roots_args(fp, b, pairs, status, d);
+        f.gen = ++fp->t_gen;  // built with the first columns below
         for (int c0 = 0; c0 < m; c0 += FMMV_MAX_M) {
             pk.c0 = c0;
             v.m = std::min(FMMV_MAX_M, m - c0);
@@ -735,7 +741,8 @@ int apply_run(superdc_ctx *ctx, const superdc_batch *b, const double *d, const d
         v.fuse_b = fuse_b ? 1 : 0;
         v.zh = zhat;
         v.bout = const_cast<double *>(bnorm);  // written only with fuse_b
-        const FmmArgs f = fmm_vec_args(fp, b, pairs, status);
+        FmmArgs f = fmm_vec_args(fp, b, pairs, status);
+        if (!reuse_lists) f.gen = ++fp->gen;  // built with the first columns below
         for (int c0 = 0; c0 < m; c0 += FMMV_MAX_M) {
             pk.c0 = c0;
             v.m = std::min(FMMV_MAX_M, m - c0) + v.fuse_b;  // one chunk when fused
@@ -921,7 +928,10 @@ int superdc_secular_solve(superdc_ctx *ctx, const superdc_batch *b, const double
         if (fp->nfmm == 0) fp = nullptr;
     }
     FmmArgs f{};
-    if (fp) f = fmm_args(fp, b, a, o);
+    if (fp) {
+        f = fmm_args(fp, b, a, o);
+        f.gen = ++fp->gen;  // the lists this solve builds
+    }
     if (o.persistent) {
         // one persistent launch over the chunks of the direct problems, longest first,
         // and one over the target leaves of the FMM problems

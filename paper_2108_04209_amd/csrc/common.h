@@ -152,7 +152,7 @@ enum KernelId : int {
     KID_VALIDATE = 0, KID_FMM_BOXES, KID_FMM_LISTS, KID_SECULAR, KID_SECULAR_FMM, KID_PACK,
     KID_LOEWNER, KID_BNORM, KID_APPLY_MFMA, KID_APPLY_VALU, KID_BWD, KID_BWD_RHO, KID_LEAF,
     KID_MERGE, KID_ASSEMBLE, KID_PERMUTE, KID_LEAF_APPLY, KID_STATUS_OR, KID_FILL,
-    KID_LEAF_VECTORS, KID_FMM_GEOM, KID_FMMV_PACK, KID_FMMV_SOURCES, KID_FMMV_EVAL,
+    KID_LEAF_VECTORS, KID_FMMV_PACK, KID_FMMV_SOURCES, KID_FMMV_EVAL,
     KID_FMMV_EVAL_MFMA, KID_FMML_PACK, KID_FMML_MOMENTS, KID_LOEWNER_FMM, KID_DEFLATE,
     KID_DEFL_PLACE, KID_DEFL_ROTATE, KID_COPY_ROWS, KID_FMM_LOCAL, KID_DIVIDE, KID_SORT, KID_COUNT
 };

@@ -40,9 +40,11 @@ struct FmmArgs {
     const double2 *dw;        // (d_j, w_j) of the batch (from validation); .x alone for geometry
     const double *tail;       // [nprob] bound of the last root above d_{n-1}
     const int32_t *status;
-    int32_t *used;            // [nboxes] 1 if some target leaf lists the box as far field
+    int32_t *used;            // [nboxes] == gen if some target leaf of the current lists lists
+                              // the box as far field
+    int gen;                  // the current lists' number: the lists kernel tags the boxes it
+                              // uses with it, so no pass clears the flags between builds
     double2 *eq;              // [boxes][FMM_P] equivalent sources (node, weight)
-    double2 *box_ab;          // [boxes] (first pole, last pole) of the box
     int32_t *near_lo, *near_hi;   // [leaves][FMM_NEAR_MAX] pole ranges: runs of adjacent near leaves
     int32_t *near_lf;             // [leaves][FMM_NEAR_MAX] 1: the range lies sep_loc target widths
                                   // (and a tile of indices) from the target interval, so its
@@ -92,7 +94,7 @@ struct FmmPlan {
     int2 *split_box = nullptr;
     int nupper_item = 0, nsplit = 0;
     double *vpart = nullptr;
-    double2 *eq = nullptr, *box_ab = nullptr;
+    double2 *eq = nullptr;
     int32_t *near_lo = nullptr, *near_hi = nullptr, *far_l = nullptr, *far_r = nullptr;
     int32_t *cnt = nullptr, *near_lf = nullptr;
     int32_t *far_ld = nullptr, *far_rd = nullptr, *cntd = nullptr;
@@ -115,7 +117,8 @@ struct FmmPlan {
     Tile *sitem_nat = nullptr;
     std::vector<Tile *> dir_lpt;       // direct chunks of the other problems, per cut length
     std::vector<int32_t> dir_count;
-    int32_t *used = nullptr;           // [nboxes]
+    int32_t *used = nullptr;           // [nboxes], zeroed at creation
+    int gen = 0, t_gen = 0;            // numbers of the last lists built (solver's, roots')
     double *vnode = nullptr, *vw = nullptr;  // eigenvector-side equivalent sources
     double *tail = nullptr;            // [nprob] per-call bound of the last root
     double2 *lgeo = nullptr;           // Loewner far field: box geometry and moments
@@ -126,7 +129,7 @@ struct FmmPlan {
     int32_t *t_cnt = nullptr, *t_far_ld = nullptr, *t_far_rd = nullptr, *t_cntd = nullptr;
     int32_t *t_near_lf = nullptr;
     int32_t *t_used = nullptr;
-    double2 *t_box_ab = nullptr, *t_loc_ab = nullptr;
+    double2 *t_loc_ab = nullptr;
     std::vector<void *> allocs;
 };
 
@@ -203,7 +206,7 @@ hipError_t launch_loewner_fmm(const VecArgs &a, const FmmArgs &f, const FmmlArgs
 
 
 hipError_t launch_fmm_build(const FmmArgs &f, hipStream_t s);
-// geometry and interaction lists only (no secular equivalent sources)
+// interaction lists only (no secular equivalent sources)
 hipError_t launch_fmm_lists(const FmmArgs &f, hipStream_t s);
 hipError_t launch_fmmv_sources(const FmmArgs &f, const FmmVec &v, hipStream_t s);
 // grid: persistent (q != nullptr) launches size themselves from num_cu

@@ -42,18 +42,6 @@ __device__ __forceinline__ BoxRange box_range(const FmmArgs &f, int g) {
     return r;
 }
 
-// box spans (first and last pole) and cleared use flags: one thread per box
-__global__ __launch_bounds__(256) void k_fmm_geom(FmmArgs f) {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= f.nboxes) return;
-    const BoxRange r = box_range(f, g);
-    f.used[g] = 0;
-    if (r.lo >= r.hi || (f.status[r.p] & ~SUPERDC_ST_NOCONV))
-        f.box_ab[g] = make_double2(__builtin_nan(""), __builtin_nan(""));
-    else
-        f.box_ab[g] = make_double2(f.dw[r.base + r.lo].x, f.dw[r.base + r.hi - 1].x);
-}
-
 // Secular equivalent sources, in two launches.  LEAVES: every leaf from its poles, one
 // wavefront per leaf.  Upper boxes: every box some target lists as far, four wavefronts,
 // from the equivalent sources of its leaves (16 per leaf instead of every pole below: the
@@ -67,7 +55,7 @@ __global__ __launch_bounds__(LEAVES ? 64 : 256) void k_fmm_boxes(FmmArgs f) {
     __shared__ double red[LEAVES ? 1 : 16 * (FMM_P + 1)];
     // every leaf in the first launch, the upper boxes with poles in the second (used ones)
     const int g = LEAVES ? f.leaf_box[blockIdx.x] : f.upper_box[blockIdx.x];
-    if (!LEAVES && !f.used[g]) return;
+    if (!LEAVES && f.used[g] != f.gen) return;
     const int qf = f.box_fmm[g];
     const int hidx = g - f.box_off[qf];
     const int H = f.height[qf];
@@ -178,11 +166,12 @@ __global__ __launch_bounds__(WAVE) void k_fmm_lists(FmmArgs f) {
     for (int h = 0; h <= H && ncand > 0 && !overflow; ++h) {
         const bool valid = lane < ncand;
         const int g = f.box_off[q] + hidx;
-        const double2 ab = valid ? f.box_ab[g] : make_double2(0.0, 0.0);
-        const bool live = valid && ab.x == ab.x;  // empty boxes are dropped
         const int i = hidx - ((1 << h) - 1);
         const int64_t span = (int64_t)f.leaf << (H - h);
         const int lo = (int)min((int64_t)n, i * span), hi = (int)min((int64_t)n, (i + 1) * span);
+        const bool live = valid && lo < hi;  // empty boxes are dropped
+        // the box's span: its first and last point
+        const double2 ab = live ? make_double2(dw[lo].x, dw[hi - 1].x) : make_double2(0.0, 0.0);
         const double width = ab.y - ab.x;
         const bool fl = live && ab.y < xa && xa - ab.y >= f.sep * width && hi <= i0 - TILE;
         const bool fr = live && !fl && ab.x > xb && ab.x - xb >= f.sep * width && lo >= i1 + TILE;
@@ -205,11 +194,11 @@ __global__ __launch_bounds__(WAVE) void k_fmm_lists(FmmArgs f) {
         }
         if (fl) {
             far_l[nl + rl] = g;
-            f.used[g] = 1;
+            f.used[g] = f.gen;
         }
         if (fr) {
             far_r[nr + rr] = g;
-            f.used[g] = 1;
+            f.used[g] = f.gen;
         }
         nl += __popcll(ml);
         nr += __popcll(mr);
@@ -401,7 +390,6 @@ __global__ __launch_bounds__(FMM_PL * LOC_PARTS) void k_fmm_local(FmmArgs f) {
 
 hipError_t launch_fmm_lists(const FmmArgs &f, hipStream_t s) {
     if (f.nboxes <= 0) return hipSuccess;
-    SDC_LAUNCH(KID_FMM_GEOM, k_fmm_geom, dim3((f.nboxes + 255) / 256), dim3(256), 0, s, f);
     SDC_LAUNCH(KID_FMM_LISTS, k_fmm_lists, dim3(f.nleaves), dim3(WAVE), 0, s, f);
     return hipGetLastError();
 }

@@ -71,7 +71,7 @@ __global__ __launch_bounds__(LEAVES ? 64 : 256, LEAVES ? 1 : 4) void k_fmmv_sour
     // (used ones): (box, part, parts, partial slot)
     const int4 it = LEAVES ? make_int4(f.leaf_box[blockIdx.x], 0, 1, -1) : f.upper_item[blockIdx.x];
     const int g = it.x;
-    if (!LEAVES && !f.used[g]) return;
+    if (!LEAVES && f.used[g] != f.gen) return;
     const int qf = f.box_fmm[g];
     const int p = f.fmm_prob[qf];
     const int64_t base = f.off[p];
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(LEAVES ? 64 : 256, LEAVES ? 1 : 4) void k_fmmv_sour
 __global__ __launch_bounds__(FMM_P * FMMV_MAX_M) void k_fmmv_sources_sum(FmmArgs f, FmmVec v) {
     const int2 sb = f.split_box[blockIdx.x];
     const int g = sb.x;
-    if (!f.used[g]) return;
+    if (f.used[g] != f.gen) return;
     const int qf = f.box_fmm[g];
     const int p = f.fmm_prob[qf];
     if (f.status[p] & ~SUPERDC_ST_NOCONV) return;
@@ -572,7 +572,7 @@ __global__ __launch_bounds__(LEAVES ? 64 : 256) void k_fmml_moments(FmmArgs f, F
     __shared__ double part[64][FMML_K + 1];
     __shared__ double part2[LEAVES ? 1 : 64][FMML_K + 1];
     const int g = LEAVES ? f.leaf_box[blockIdx.x] : f.upper_box[blockIdx.x];
-    if (!LEAVES && !f.used[g]) return;
+    if (!LEAVES && f.used[g] != f.gen) return;
     const int qf = f.box_fmm[g];
     const int p = f.fmm_prob[qf];
     const int64_t base = f.off[p];

@@ -52,7 +52,7 @@ const char *kNames[KID_COUNT] = {
     "k_validate", "k_fmm_boxes", "k_fmm_lists", "k_secular", "k_secular_fmm", "k_pack_ke",
     "k_loewner", "k_bnorm", "k_apply_mfma", "k_apply_valu", "k_bwd", "k_bwd_rho",
     "k_leaf_jacobi", "k_merge", "k_assemble", "k_permute", "k_leaf_apply", "k_status_or",
-    "k_fill", "k_leaf_vectors", "k_fmm_geom", "k_fmmv_pack", "k_fmmv_sources", "k_fmmv_eval",
+    "k_fill", "k_leaf_vectors", "k_fmmv_pack", "k_fmmv_sources", "k_fmmv_eval",
     "k_fmmv_eval_mfma", "k_fmml_pack", "k_fmml_moments", "k_loewner_fmm", "k_deflate",
     "k_defl_place", "k_defl_rotate", "k_copy_rows", "k_fmm_local", "k_divide", "k_sort_pass"};
 
