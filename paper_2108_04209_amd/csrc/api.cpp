@@ -448,9 +448,14 @@ hipError_t fmmv_run(superdc_ctx *ctx, const superdc_batch *b, const FmmPlan *fp,
                     bool persistent, hipStream_t s) {
     pk.tiles = fp->leaf_nat;
     pk.ntiles = fp->nitems;
-    hipError_t e = launch_fmmv_pack(pk, v, s);
-    if (e == hipSuccess && lists) e = launch_fmm_lists(f, s);
-    if (e == hipSuccess) e = launch_fmmv_sources(f, v, s);
+    hipError_t e = hipSuccess;
+    if (lists) {  // the lists need the packed positions first
+        e = launch_fmmv_pack(pk, v, s);
+        if (e == hipSuccess) e = launch_fmm_lists(f, s);
+        if (e == hipSuccess) e = launch_fmmv_sources(f, v, nullptr, s);
+    } else {  // the leaves' launch packs the sources itself
+        e = launch_fmmv_sources(f, v, &pk, s);
+    }
     if (e != hipSuccess) return e;
     SolveArgs it{};
     it.off = b->off_d;
@@ -564,11 +569,19 @@ int loewner_run(superdc_ctx *ctx, const superdc_batch *b, const double *d, const
         lf.geo = fp->lgeo;
         lf.mom = fp->lmom;
         // (d_j, delta_j) pairs, the lists of these poles (unless the solve left them), the
-        // Loewner moments of every leaf and used box
-        SDC_HIP(launch_fmml_pack(pk, s));
+        // Loewner moments of every leaf and used box; with the lists left by the solve the
+        // leaves' launch packs the pairs itself
         if (!reuse_lists) {
+            SDC_HIP(launch_fmml_pack(pk, s));
             f.gen = ++fp->gen;
             SDC_HIP(launch_fmm_lists(f, s));
+        } else {
+            lf.pack = 1;
+            lf.d = d;
+            lf.eta = eta;
+            lf.origin = origin;
+            lf.ke = pk.ke;
+            lf.tail = fp->tail;
         }
         SDC_HIP(launch_fmml_moments(f, lf, s));
     }

@@ -176,9 +176,17 @@ constexpr int FMMV_PART_PTS = 512;   // points per part of an upper box's source
 constexpr int FMML_K = 28;  // moments per box (|r| <= 1/4 at separation 1.5: 0.25^28 ~ 1e-17)
 
 struct FmmlArgs {
-    const double2 *pd;        // (d_j, delta_j) per entry (pole and its root's offset)
+    double2 *pd;              // (d_j, delta_j) per entry (pole and its root's offset)
     double2 *geo;             // [boxes] (c, hw)
     double *mom;              // [boxes][FMML_K] moments M_1 .. M_K
+    // pack != 0: the leaves' launch packs its poles itself (when the lists already exist, as
+    // the separate packing launch would): (d_j, delta_j) into pd, (d_{K_j}, eta_j) into ke
+    // when ke is set, and the last delta of each problem into tail
+    int pack;
+    const double *d, *eta;
+    const int32_t *origin;
+    double2 *ke;
+    double *tail;
 };
 hipError_t launch_fmml_moments(const FmmArgs &f, const FmmlArgs &l, hipStream_t s);
 
@@ -208,7 +216,10 @@ hipError_t launch_loewner_fmm(const VecArgs &a, const FmmArgs &f, const FmmlArgs
 hipError_t launch_fmm_build(const FmmArgs &f, hipStream_t s);
 // interaction lists only (no secular equivalent sources)
 hipError_t launch_fmm_lists(const FmmArgs &f, hipStream_t s);
-hipError_t launch_fmmv_sources(const FmmArgs &f, const FmmVec &v, hipStream_t s);
+// pk: when set, the leaves' launch packs the sources itself (pk.pairs non-null; the lists
+// must exist already), in place of launch_fmmv_pack
+hipError_t launch_fmmv_sources(const FmmArgs &f, const FmmVec &v, const FmmvPackArgs *pk,
+                               hipStream_t s);
 // grid: persistent (q != nullptr) launches size themselves from num_cu
 hipError_t launch_fmmv_eval(const SolveArgs &items, const FmmArgs &f, const FmmVec &v, int split,
                             Queue *q, int num_cu, hipStream_t s);

@@ -18,14 +18,10 @@ namespace sdc {
 typedef double v4d_f __attribute__((ext_vector_type(4)));
 
 
-// src_i,c = zhat_i X_i,c0+c (kern 1) or zhat_i^2 (kern 2); one lane per pole.  trans 0:
-// src_j,c = b_j X_j,c0+c at the root lambda_j (positions in pairs[j].x); one lane per root
-__global__ __launch_bounds__(64) void k_fmmv_pack(FmmvPackArgs a, FmmVec v) {
-    const Tile t = a.tiles[blockIdx.x];
-    const int64_t base = a.off[t.prob];
-    const int n = (int)(a.off[t.prob + 1] - base);
-    const int i = t.row0 + lane_id();
-    if (i >= n) return;
+// src_i,c = zhat_i X_i,c0+c (kern 1) or zhat_i^2 (kern 2) for pole i of problem p (entries
+// from base).  trans 0: src_j,c = b_j X_j,c0+c at the root lambda_j (positions in pairs[j].x)
+__device__ __forceinline__ void fmmv_pack_entry(const FmmvPackArgs &a, const FmmVec &v, int p,
+                                                int64_t base, int n, int i) {
     if (v.trans == 0) {
         const int K = clamp_idx(a.origin[base + i], n);
         const double bj = a.bnorm[base + i];
@@ -47,8 +43,17 @@ __global__ __launch_bounds__(64) void k_fmmv_pack(FmmvPackArgs a, FmmVec v) {
     }
     if (i == n - 1) {
         const int K = clamp_idx(a.origin[base + i], n);
-        a.tail[t.prob] = (a.d[base + K] + a.eta[base + i]) - di;
+        a.tail[p] = (a.d[base + K] + a.eta[base + i]) - di;
     }
+}
+
+// one lane per pole (per root for trans 0)
+__global__ __launch_bounds__(64) void k_fmmv_pack(FmmvPackArgs a, FmmVec v) {
+    const Tile t = a.tiles[blockIdx.x];
+    const int64_t base = a.off[t.prob];
+    const int n = (int)(a.off[t.prob + 1] - base);
+    const int i = t.row0 + lane_id();
+    if (i < n) fmmv_pack_entry(a, v, t.prob, base, n, i);
 }
 
 // Equivalent sources, one workgroup (256 threads) per box, in two launches: LEAVES = true
@@ -61,7 +66,8 @@ __global__ __launch_bounds__(64) void k_fmmv_pack(FmmvPackArgs a, FmmVec v) {
 // operands loaded straight from memory (they are point-major: the 4 points x m columns of
 // one step are consecutive) before the Lagrange values are formed.
 template <bool LEAVES>
-__global__ __launch_bounds__(LEAVES ? 64 : 256, LEAVES ? 1 : 4) void k_fmmv_sources(FmmArgs f, FmmVec v) {
+__global__ __launch_bounds__(LEAVES ? 64 : 256, LEAVES ? 1 : 4) void k_fmmv_sources(FmmArgs f, FmmVec v,
+                                                                              FmmvPackArgs pk) {
     // leaves: one wavefront, 64 points per chunk; upper boxes (up to 16 sources per leaf
     // below): four wavefronts, 256 points per chunk
     constexpr int NW = LEAVES ? 1 : 4;
@@ -86,6 +92,10 @@ __global__ __launch_bounds__(LEAVES ? 64 : 256, LEAVES ? 1 : 4) void k_fmmv_sour
     const int lo = (int)min((int64_t)n, bi * span), hi = (int)min((int64_t)n, (bi + 1) * span);
     if (lo >= hi) return;  // empty box (never listed)
     const int tid = threadIdx.x;
+    if (LEAVES && pk.pairs) {  // the leaf's poles packed here, as k_fmmv_pack would
+        for (int i = lo + tid; i < hi; i += blockDim.x) fmmv_pack_entry(pk, v, p, base, n, i);
+        __syncthreads();
+    }
     const int m = v.m;
     const double2 *d2 = f.dw + base;  // the points' positions in .x (poles, or roots)
     auto d = [&](int i) { return d2[i].x; };
@@ -586,6 +596,18 @@ __global__ __launch_bounds__(LEAVES ? 64 : 256) void k_fmml_moments(FmmArgs f, F
     const int64_t span = (int64_t)f.leaf << (H - h);
     const int lo = (int)min((int64_t)n, bi * span), hi = (int)min((int64_t)n, (bi + 1) * span);
     if (lo >= hi) return;
+    if (LEAVES && l.pack) {  // the leaf's poles packed here (the same arithmetic as k_fmml_pack)
+        for (int j = lo + (int)threadIdx.x; j < hi; j += blockDim.x) {
+            const double dj = l.d[base + j];
+            const double dK = l.d[base + clamp_idx(l.origin[base + j], n)];
+            const double ej = l.eta[base + j];
+            const double delta = (dK - dj) + ej;
+            l.pd[base + j] = make_double2(dj, delta);
+            if (l.ke) l.ke[base + j] = make_double2(dK, ej);
+            if (j == n - 1) l.tail[p] = delta;
+        }
+        __syncthreads();
+    }
     const double2 *pd = l.pd + base;
     const double a = pd[lo].x, b = pd[hi - 1].x + pd[hi - 1].y;  // poles and roots of the box
     const double c = 0.5 * (a + b), hw = 0.5 * (b - a), ihw = 1.0 / hw;
@@ -722,12 +744,15 @@ hipError_t launch_fmmv_pack(const FmmvPackArgs &a, const FmmVec &v, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t launch_fmmv_sources(const FmmArgs &f, const FmmVec &v, hipStream_t s) {
+hipError_t launch_fmmv_sources(const FmmArgs &f, const FmmVec &v, const FmmvPackArgs *pk,
+                               hipStream_t s) {
     if (f.nboxes <= 0) return hipSuccess;
-    SDC_LAUNCH(KID_FMMV_SOURCES, k_fmmv_sources<true>, dim3(f.nleaves), dim3(64), 0, s, f, v);
+    FmmvPackArgs none{};
+    SDC_LAUNCH(KID_FMMV_SOURCES, k_fmmv_sources<true>, dim3(f.nleaves), dim3(64), 0, s, f, v,
+               pk ? *pk : none);
     if (f.nupper_item > 0)
         SDC_LAUNCH(KID_FMMV_SOURCES, k_fmmv_sources<false>, dim3(f.nupper_item), dim3(256), 0, s,
-                   f, v);
+                   f, v, none);
     if (f.nsplit > 0)
         SDC_LAUNCH(KID_FMMV_SOURCES, k_fmmv_sources_sum, dim3(f.nsplit), dim3(FMM_P * FMMV_MAX_M),
                    0, s, f, v);
