@@ -42,20 +42,15 @@ __device__ __forceinline__ BoxRange box_range(const FmmArgs &f, int g) {
     return r;
 }
 
-// Secular equivalent sources, in two launches.  LEAVES: every leaf from its poles, one
-// wavefront per leaf.  Upper boxes: every box some target lists as far, four wavefronts,
-// from the equivalent sources of its leaves (16 per leaf instead of every pole below: the
-// far field of a leaf's sources equals that of its poles to the interpolation accuracy,
-// and the box's nodes interpolate it again).
+// Secular equivalent sources of box g.  LEAVES: a leaf from its poles, one wavefront (the
+// wavefront that built the leaf's lists).  Upper boxes: a box some target lists as far,
+// four wavefronts, from the equivalent sources of its leaves (16 per leaf instead of every
+// pole below: the far field of a leaf's sources equals that of its poles to the
+// interpolation accuracy, and the box's nodes interpolate it again).  part holds 64 or 256
+// rows of FMM_P + 1 doubles, red 16 of them (upper boxes).
 template <bool LEAVES>
-__global__ __launch_bounds__(LEAVES ? 64 : 256) void k_fmm_boxes(FmmArgs f) {
+__device__ __forceinline__ void box_sources(const FmmArgs &f, int g, double *part, double *red) {
     static_assert(FMM_P == 16, "the upper boxes' sum maps 256 threads to 16 x 16");
-    constexpr int NT = LEAVES ? 64 : 256;
-    __shared__ double part[NT * (FMM_P + 1)];
-    __shared__ double red[LEAVES ? 1 : 16 * (FMM_P + 1)];
-    // every leaf in the first launch, the upper boxes with poles in the second (used ones)
-    const int g = LEAVES ? f.leaf_box[blockIdx.x] : f.upper_box[blockIdx.x];
-    if (!LEAVES && f.used[g] != f.gen) return;
     const int qf = f.box_fmm[g];
     const int hidx = g - f.box_off[qf];
     const int H = f.height[qf];
@@ -129,13 +124,24 @@ __global__ __launch_bounds__(LEAVES ? 64 : 256) void k_fmm_boxes(FmmArgs f) {
     if (tid < FMM_P) f.eq[(int64_t)g * FMM_P + tid] = make_double2(c + hw * tq[tid], wq);
 }
 
+// the used upper boxes (the leaves are compressed by the lists launch of the solver)
+__global__ __launch_bounds__(256) void k_fmm_boxes(FmmArgs f) {
+    __shared__ double part[256 * (FMM_P + 1)];
+    __shared__ double red[16 * (FMM_P + 1)];
+    const int g = f.upper_box[blockIdx.x];
+    if (f.used[g] != f.gen) return;
+    box_sources<false>(f, g, part, red);
+}
+
 // interaction lists: one wavefront per target leaf walks its problem's tree level by level.
 // Lane i holds the i-th candidate box of the level (children of the previous level's open
 // boxes, left to right).  A candidate separated from the leaf is far (flagged as used), a
 // leaf that is not is near, any other box opens its two children for the next level.  More
 // than 64 candidates on a level, or full lists, make the leaf fall back to direct sums.
+template <bool EQ>
 __global__ __launch_bounds__(WAVE) void k_fmm_lists(FmmArgs f) {
     __shared__ int slot[WAVE];
+    __shared__ double part[EQ ? WAVE * (FMM_P + 1) : 1];
     const int L = blockIdx.x;
     const int lane = threadIdx.x;
     const int q = f.leaf_fmm[L];
@@ -275,6 +281,8 @@ __global__ __launch_bounds__(WAVE) void k_fmm_lists(FmmArgs f) {
         f.cntd[2 * (int64_t)L + 1] = ndr;
         f.loc_ab[L] = make_double2(0.5 * (xa + xb), 0.5 * (xb - xa));
     }
+    // EQ (the solver's lists): the leaf's own equivalent sources, which no list here needs
+    if (EQ) box_sources<true>(f, f.leaf_box[L], part, nullptr);
 }
 
 // Local expansion of a target leaf (one workgroup per leaf): the far field of the boxes
@@ -390,17 +398,16 @@ __global__ __launch_bounds__(FMM_PL * LOC_PARTS) void k_fmm_local(FmmArgs f) {
 
 hipError_t launch_fmm_lists(const FmmArgs &f, hipStream_t s) {
     if (f.nboxes <= 0) return hipSuccess;
-    SDC_LAUNCH(KID_FMM_LISTS, k_fmm_lists, dim3(f.nleaves), dim3(WAVE), 0, s, f);
+    SDC_LAUNCH(KID_FMM_LISTS, k_fmm_lists<false>, dim3(f.nleaves), dim3(WAVE), 0, s, f);
     return hipGetLastError();
 }
 
 hipError_t launch_fmm_build(const FmmArgs &f, hipStream_t s) {
     if (f.nboxes <= 0) return hipSuccess;
-    hipError_t e = launch_fmm_lists(f, s);
-    if (e != hipSuccess) return e;
-    SDC_LAUNCH(KID_FMM_BOXES, k_fmm_boxes<true>, dim3(f.nleaves), dim3(64), 0, s, f);
+    // the lists and every leaf's equivalent sources in one launch, then the used upper boxes
+    SDC_LAUNCH(KID_FMM_LISTS, k_fmm_lists<true>, dim3(f.nleaves), dim3(WAVE), 0, s, f);
     if (f.nupper > 0)
-        SDC_LAUNCH(KID_FMM_BOXES, k_fmm_boxes<false>, dim3(f.nupper), dim3(256), 0, s, f);
+        SDC_LAUNCH(KID_FMM_BOXES, k_fmm_boxes, dim3(f.nupper), dim3(256), 0, s, f);
     SDC_LAUNCH(KID_FMM_LOCAL, k_fmm_local, dim3(f.nleaves), dim3(FMM_PL * LOC_PARTS), 0, s, f);
     return hipGetLastError();
 }
