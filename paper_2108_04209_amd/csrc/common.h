@@ -107,6 +107,15 @@ __device__ __forceinline__ cquad as_const(const double4 *p) { return cquad{(cons
 typedef cpair const_double2_ptr;
 typedef cquad const_double4_ptr;
 
+// Orders one wavefront's LDS accesses across this point, for lanes that exchange data through
+// LDS without the rest of the workgroup (a wavefront's LDS operations complete in program
+// order; the fences keep the compiler from moving accesses across)
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Pull the next work item from a persistent queue (called by whole wavefront-0 of a WG
 // and broadcast through LDS).  Returns -1 when the queue is drained.
 __device__ __forceinline__ int queue_pull(Queue *q, int nitems, int *slot) {

@@ -42,14 +42,16 @@ __device__ __forceinline__ BoxRange box_range(const FmmArgs &f, int g) {
     return r;
 }
 
-// Secular equivalent sources of box g.  LEAVES: a leaf from its poles, one wavefront (the
-// wavefront that built the leaf's lists).  Upper boxes: a box some target lists as far,
-// four wavefronts, from the equivalent sources of its leaves (16 per leaf instead of every
-// pole below: the far field of a leaf's sources equals that of its poles to the
-// interpolation accuracy, and the box's nodes interpolate it again).  part holds 64 or 256
-// rows of FMM_P + 1 doubles, red 16 of them (upper boxes).
+// Secular equivalent sources of box g.  LEAVES: a leaf from its poles, one wavefront (beside
+// the one that builds the leaf's lists).  Upper boxes: a box some target lists as far, four
+// wavefronts, from the equivalent sources of its leaves (16 per leaf instead of every pole
+// below: the far field of a leaf's sources equals that of its poles to the interpolation
+// accuracy, and the box's nodes interpolate it again).  part holds 64 or 256 rows of
+// FMM_P + 1 doubles, red 16 of them (upper boxes); tid is the thread's index among the box's
+// nt threads (one wavefront for a leaf, which syncs only itself).
 template <bool LEAVES>
-__device__ __forceinline__ void box_sources(const FmmArgs &f, int g, double *part, double *red) {
+__device__ __forceinline__ void box_sources(const FmmArgs &f, int g, double *part, double *red,
+                                            int tid, int nt) {
     static_assert(FMM_P == 16, "the upper boxes' sum maps 256 threads to 16 x 16");
     const int qf = f.box_fmm[g];
     const int hidx = g - f.box_off[qf];
@@ -60,7 +62,6 @@ __device__ __forceinline__ void box_sources(const FmmArgs &f, int g, double *par
     const int lo = rg.lo, hi = rg.hi;
     if (lo >= hi || (f.status[rg.p] & ~SUPERDC_ST_NOCONV)) return;
     const double2 *dw = f.dw + rg.base;
-    const int tid = threadIdx.x;
     const double a = dw[lo].x, b = dw[hi - 1].x;
     const double c = 0.5 * (a + b), hw = 0.5 * (b - a);
     if (LEAVES && hi - lo <= FMM_P) {  // few poles: they are their own equivalent sources
@@ -82,7 +83,7 @@ __device__ __forceinline__ void box_sources(const FmmArgs &f, int g, double *par
     const int bi = hidx - ((1 << h) - 1);
     const int leaf0 = f.box_off[qf] + (1 << H) - 1 + bi * (1 << (H - h));
     const int npts = LEAVES ? hi - lo : ((hi - lo + f.leaf - 1) / f.leaf) * FMM_P;
-    for (int k = tid; k < npts; k += blockDim.x) {
+    for (int k = tid; k < npts; k += nt) {
         const double2 pw = LEAVES ? dw[lo + k] : f.eq[(int64_t)leaf0 * FMM_P + k];
         const double t = fmin(1.0, fmax(-1.0, (pw.x - c) * ihw));
         int hit = -1;
@@ -108,7 +109,10 @@ __device__ __forceinline__ void box_sources(const FmmArgs &f, int g, double *par
     double wq = 0.0;
 #pragma unroll
     for (int r = 0; r < FMM_P; ++r) part[tid * (FMM_P + 1) + r] = W[r];
-    __syncthreads();
+    if (LEAVES)
+        wave_sync();
+    else
+        __syncthreads();
     if (LEAVES) {
         if (tid < FMM_P)
             for (int u = 0; u < 64; ++u) wq += part[u * (FMM_P + 1) + tid];
@@ -130,7 +134,7 @@ __global__ __launch_bounds__(256) void k_fmm_boxes(FmmArgs f) {
     __shared__ double red[16 * (FMM_P + 1)];
     const int g = f.upper_box[blockIdx.x];
     if (f.used[g] != f.gen) return;
-    box_sources<false>(f, g, part, red);
+    box_sources<false>(f, g, part, red, threadIdx.x, blockDim.x);
 }
 
 // interaction lists: one wavefront per target leaf walks its problem's tree level by level.
@@ -139,10 +143,15 @@ __global__ __launch_bounds__(256) void k_fmm_boxes(FmmArgs f) {
 // leaf that is not is near, any other box opens its two children for the next level.  More
 // than 64 candidates on a level, or full lists, make the leaf fall back to direct sums.
 template <bool EQ>
-__global__ __launch_bounds__(WAVE) void k_fmm_lists(FmmArgs f) {
+__global__ __launch_bounds__(EQ ? 2 * WAVE : WAVE) void k_fmm_lists(FmmArgs f) {
     __shared__ int slot[WAVE];
     __shared__ double part[EQ ? WAVE * (FMM_P + 1) : 1];
     const int L = blockIdx.x;
+    // EQ (the solver's lists): a second wavefront compresses the leaf itself meanwhile
+    if (EQ && threadIdx.x >= WAVE) {
+        box_sources<true>(f, f.leaf_box[L], part, nullptr, threadIdx.x - WAVE, WAVE);
+        return;
+    }
     const int lane = threadIdx.x;
     const int q = f.leaf_fmm[L];
     const int p = f.fmm_prob[q];
@@ -267,9 +276,9 @@ __global__ __launch_bounds__(WAVE) void k_fmm_lists(FmmArgs f) {
             break;
         }
         const int ro = __builtin_amdgcn_mbcnt_hi((unsigned)(mo >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mo, 0u));
-        __syncthreads();
+        wave_sync();
         if (open) slot[ro] = hidx;
-        __syncthreads();
+        wave_sync();
         ncand = 2 * no;
         hidx = lane < ncand ? 2 * slot[lane >> 1] + 1 + (lane & 1) : 0;
     }
@@ -281,8 +290,6 @@ __global__ __launch_bounds__(WAVE) void k_fmm_lists(FmmArgs f) {
         f.cntd[2 * (int64_t)L + 1] = ndr;
         f.loc_ab[L] = make_double2(0.5 * (xa + xb), 0.5 * (xb - xa));
     }
-    // EQ (the solver's lists): the leaf's own equivalent sources, which no list here needs
-    if (EQ) box_sources<true>(f, f.leaf_box[L], part, nullptr);
 }
 
 // Local expansion of a target leaf (one workgroup per leaf): the far field of the boxes
@@ -405,7 +412,7 @@ hipError_t launch_fmm_lists(const FmmArgs &f, hipStream_t s) {
 hipError_t launch_fmm_build(const FmmArgs &f, hipStream_t s) {
     if (f.nboxes <= 0) return hipSuccess;
     // the lists and every leaf's equivalent sources in one launch, then the used upper boxes
-    SDC_LAUNCH(KID_FMM_LISTS, k_fmm_lists<true>, dim3(f.nleaves), dim3(WAVE), 0, s, f);
+    SDC_LAUNCH(KID_FMM_LISTS, k_fmm_lists<true>, dim3(f.nleaves), dim3(2 * WAVE), 0, s, f);
     if (f.nupper > 0)
         SDC_LAUNCH(KID_FMM_BOXES, k_fmm_boxes, dim3(f.nupper), dim3(256), 0, s, f);
     SDC_LAUNCH(KID_FMM_LOCAL, k_fmm_local, dim3(f.nleaves), dim3(FMM_PL * LOC_PARTS), 0, s, f);
