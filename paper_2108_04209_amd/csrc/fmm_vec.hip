@@ -573,12 +573,20 @@ __global__ __launch_bounds__(256) void k_fmmv_eval_mfma(SolveArgs it, FmmArgs f,
 // Loewner far field: box moments.  LEAVES = true: every leaf from its poles and roots;
 // LEAVES = false: every used box above the leaves from its leaves' moments, translated to
 // the box's centre and half-width (t_box = alpha + beta t_leaf):
-//     M_k = sum_m C(k, m) alpha^(k-m) beta^m M_m(leaf),  T_k(m) = alpha T_{k-1}(m) + beta T_{k-1}(m-1)
+//     M_k = sum_m C(k, m) alpha^(k-m) beta^m M_m(leaf)
 // (M_0 = 0: each pole-root pair carries opposite unit charges).  One workgroup per box; the
 // per-thread partial moments are added in a fixed order through LDS.
+
+// binomial coefficient C(k, m) for k <= FMML_K (integers below 2^53: exact in double); used
+// with constant arguments only, so every coefficient is a literal of the unrolled loops
+__host__ __device__ constexpr double binom(int k, int m) {
+    double c = 1.0;
+    for (int j = 1; j <= m; ++j) c = c * (k - m + j) / j;
+    return c;
+}
 // ---------------------------------------------------------------------------------------
 template <bool LEAVES>
-__global__ __launch_bounds__(LEAVES ? 64 : 256) void k_fmml_moments(FmmArgs f, FmmlArgs l) {
+__global__ __launch_bounds__(LEAVES ? 64 : 256, LEAVES ? 1 : 4) void k_fmml_moments(FmmArgs f, FmmlArgs l) {
     __shared__ double part[64][FMML_K + 1];
     __shared__ double part2[LEAVES ? 1 : 64][FMML_K + 1];
     const int g = LEAVES ? f.leaf_box[blockIdx.x] : f.upper_box[blockIdx.x];
@@ -634,21 +642,18 @@ __global__ __launch_bounds__(LEAVES ? 64 : 256) void k_fmml_moments(FmmArgs f, F
             const double2 gc = l.geo[gl];
             const double al = (gc.x - c) * ihw, be = gc.y * ihw;
             const double *Ml = l.mom + (int64_t)gl * FMML_K;
-            double T[FMML_K + 1];  // T[m] = C(k, m) alpha^(k-m) beta^m for the current k
-            T[0] = 1.0;
+            // moment m of the leaf spread over k >= m: C(k, m) alpha^(k-m) beta^m M_m, the
+            // power of alpha built up along k (no row of coefficients kept: few registers)
+            double bm = 1.0;
 #pragma unroll
-            for (int m = 1; m <= FMML_K; ++m) T[m] = 0.0;
+            for (int m = 1; m <= FMML_K; ++m) {
+                bm *= be;
+                double q = Ml[m - 1] * bm;  // alpha^(k-m) beta^m M_m
 #pragma unroll
-            for (int k = 1; k <= FMML_K; ++k) {
-#pragma unroll
-                for (int m = FMML_K; m >= 1; --m)
-                    if (m <= k) T[m] = __builtin_fma(al, T[m], be * T[m - 1]);
-                T[0] *= al;
-                double s2 = 0.0;
-#pragma unroll
-                for (int m = 1; m <= FMML_K; ++m)
-                    if (m <= k) s2 = __builtin_fma(T[m], Ml[m - 1], s2);
-                M[k - 1] += s2;
+                for (int k = m; k <= FMML_K; ++k) {
+                    M[k - 1] = __builtin_fma(binom(k, m), q, M[k - 1]);
+                    q *= al;
+                }
             }
         }
     }
