@@ -668,9 +668,9 @@ __global__ __launch_bounds__(LEAVES ? 64 : 256, LEAVES ? 1 : 4) void k_fmml_mome
         }
     } else {
         // only the first nleaf threads hold moments.  Beyond 64 leaves the four wavefronts
-        // are folded onto the first, (w0 + w2) + (w1 + w3), through two 64-row buffers; the
-        // tree over the first wavefront's rows starts at the smallest power of two that
-        // covers the rows in use (the same fixed order for a given box)
+        // are folded onto the first, (w0 + w2) + (w1 + w3), through two 64-row buffers; then
+        // lane k adds column k over the rows in use, in order (one pass, no barrier per level
+        // of a tree)
         const int nleaf = (int)((hi - lo + f.leaf - 1) / f.leaf);
         const int wv = tid / WAVE, ln = tid % WAVE;
         if (nleaf > WAVE) {
@@ -700,14 +700,11 @@ __global__ __launch_bounds__(LEAVES ? 64 : 256, LEAVES ? 1 : 4) void k_fmml_mome
             for (int k = 0; k < FMML_K; ++k) part[ln][k] = M[k];
         }
         __syncthreads();
-        int width = 1;
-        while (width < min(nleaf, WAVE)) width <<= 1;
-        for (int stride = width / 2; stride > 0; stride >>= 1) {
-            if (tid < stride)
-                for (int k = 0; k < FMML_K; ++k) part[tid][k] += part[tid + stride][k];
-            __syncthreads();
+        if (tid < FMML_K) {
+            double sk = 0.0;
+            for (int u = 0; u < min(nleaf, WAVE); ++u) sk += part[u][tid];
+            l.mom[(int64_t)g * FMML_K + tid] = sk;
         }
-        if (tid < FMML_K) l.mom[(int64_t)g * FMML_K + tid] = part[0][tid];
     }
     if (tid == 0) l.geo[g] = make_double2(c, hw);
 }
