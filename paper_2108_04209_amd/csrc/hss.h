@@ -17,7 +17,7 @@ struct LeafArgs {
     double *lam;      // nleaf * leaf eigenvalues, ascending per leaf
     double *W;        // Q^T U, column-major with leading dimension ldw
     int64_t ldw;
-    double *rot;      // nleaf x max_sweeps x (leaf-1) x leaf/2 rotation tangents (0: none)
+    double *rot;      // nleaf x max_sweeps x leaf rounds x leaf/2 (cos, signed sin) pairs
     int32_t *rank;    // nleaf x leaf ascending rank of each diagonal entry
     int32_t *sweeps;  // nleaf sweeps logged
     int32_t *status;  // nleaf: 0, or SUPERDC_ST_NOCONV if max_sweeps did not converge

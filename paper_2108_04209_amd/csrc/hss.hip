@@ -14,52 +14,45 @@
 namespace sdc {
 
 // ---------------------------------------------------------------------------------------
-// leaf eigendecomposition: cyclic Jacobi in three kernels, each sized so that two
-// workgroups share a CU (the rounds are short and end in barriers: a second leaf's waves
-// fill the first one's waits):
+// leaf eigendecomposition: cyclic Jacobi in three kernels:
 //   k_leaf_jacobi  rotates A -- its upper triangle, packed by rows (66 KB for a leaf of
-//                  128) -- in LDS and logs every round's rotation tangents t to HBM;
-//   k_leaf_vectors replays the log on V = I, half of V's rows per workgroup (rows of V J
-//                  are independent), then writes those rows of the sorted eigenvectors;
+//                  128) -- in LDS, two leaves to a CU (the rounds are short and end in
+//                  barriers: a second leaf's waves fill the first one's waits), and logs
+//                  every round's rotations to HBM as (cos, signed sin) by position;
+//   k_leaf_vectors replays the log on V = I with V in registers: a lane holds 16
+//                  consecutive positions of 4 rows, so a round is static register code;
 //   k_leaf_w       W = Q^T U from the stored eigenvectors.
-// All use the round-robin (circle) pair ordering, so a round's pairs are disjoint.
+// The pairs follow the odd-even ordering over positions: round A pairs positions
+// (2k, 2k+1), round B pairs (2k+1, 2k+2), and after every round the two indices of a pair
+// trade positions.  Over L rounds every pair of indices meets once (the network ends on
+// the reversed order, so a sweep reverses the positions), and a pair's rotation only ever
+// touches two neighbouring positions.
 // ---------------------------------------------------------------------------------------
-constexpr int LJ_LD = LEAF_MAX + 1;
 constexpr int LJ_THREADS = 1024;
 constexpr int LJ_PACKED = LEAF_MAX * (LEAF_MAX + 1) / 2;
 // blocks of the folded triangle per thread: (h/2)(h+1) blocks, h = LEAF_MAX/2 rounded up
 // to even, over LJ_THREADS threads
 constexpr int LJ_BLK = ((LEAF_MAX / 4) * (LEAF_MAX / 2 + 1) + LJ_THREADS - 1) / LJ_THREADS;
-constexpr int LV_THREADS = 512;
-constexpr int LV_RB = 4;  // rounds of rotations staged in LDS per block of the replay
-constexpr int LV_ROWS = (LEAF_MAX / 2) / (LV_THREADS / WAVE);  // rows per wavefront (8)
+constexpr int LV_SEG = 16;                          // positions a lane holds
+constexpr int LV_NSEG = LEAF_MAX / LV_SEG;          // segments of a row (8)
+constexpr int LV_RPL = 4;                           // rows a lane holds
+constexpr int LV_WROWS = WAVE / LV_NSEG * LV_RPL;   // rows per wavefront (32)
+constexpr int LV_PAIRS = LEAF_MAX / 2;              // log entries a round is staged with
+constexpr int LV_SP = LV_SEG / 2;                   // pairs of a segment in round A (8)
+constexpr int LV_CLD = LV_PAIRS + LV_NSEG;          // staged entry k sits at k + k / LV_SP,
+                                                    // so the segments' reads hit distinct banks
+constexpr int LV_RB = 4;                            // rounds per staged block
 static_assert(LEAF_MAX / 2 <= WAVE, "a round's pairs must fit one wavefront");
 static_assert(LJ_PACKED < (1 << 15), "row starts of the packed triangle fit 15 bits");
-static_assert(LV_RB * (LEAF_MAX / 2) <= LV_THREADS, "one tangent per staging thread");
+static_assert(LV_PAIRS == WAVE, "one staged log entry per lane");
+static_assert(LV_NSEG * LV_SEG == LEAF_MAX && LV_NSEG <= 16 && 16 % LV_NSEG == 0,
+              "a row's segments are neighbouring lanes of one 16-lane DPP row");
+static_assert(LV_RB % 2 == 0, "a staged block starts on a round A");
 
 // entry (i, j), i <= j, of the upper triangle of an m x m matrix packed by rows
 __device__ __forceinline__ int ut(int i, int j, int m) { return ((i * (2 * m - i - 1)) >> 1) + j; }
 
-// Round-robin (circle) ordering: in round `rd` every index takes part in exactly one of
-// m/2 disjoint pairs, and over m-1 rounds every pair meets once.
-__device__ __forceinline__ int rr_player(int pos, int rd, int m) {
-    if (pos == 0) return 0;
-    int v = pos - 1 + rd;  // < 2 (m - 1)
-    if (v >= m - 1) v -= m - 1;
-    return 1 + v;
-}
-
-__device__ __forceinline__ void rr_pair(int pr, int rd, int m, int &p, int &q) {
-    p = rr_player(pr, rd, m);
-    q = rr_player(m - 1 - pr, rd, m);
-    if (p > q) {
-        const int t = p;
-        p = q;
-        q = t;
-    }
-}
-
-// cos and sin of the rotation with tangent t (the same operations in both kernels)
+// cos and sin of the rotation with tangent t
 __device__ __forceinline__ double2 rot_cs(double t) {
     const double c = rcp_nr(sqrt(t * t + 1.0));
     return make_double2(c, t * c);
@@ -77,6 +70,7 @@ __global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
     // p | rowstart(p) << 16 and q | rowstart(q) << 16 (rowstart: where the row starts in
     // the packed triangle): 8 bytes a pair for the block updates to read
     __shared__ int2 pq[LEAF_MAX / 2];
+    __shared__ int posidx[LEAF_MAX];  // index at each position of the odd-even ordering
     __shared__ double red[LJ_THREADS / WAVE];
     __shared__ int nrot;
 
@@ -102,7 +96,7 @@ __global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
     const int half = m / 2;
     const int hh = (half + 1) & ~1;          // half rounded up to even, for the folding
     const int nfold = (hh / 2) * (hh + 1);  // blocks of the folded triangle
-    double *log = a.rot + (size_t)leafid * a.max_sweeps * (m - 1) * half;
+    double2 *log = reinterpret_cast<double2 *>(a.rot) + (size_t)leafid * a.max_sweeps * m * half;
     // this thread's blocks, the same in every round
     int bP1[LJ_BLK], bP2[LJ_BLK];  // bP1 < 0: no block
 #pragma unroll
@@ -124,19 +118,25 @@ __global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
         bP1[u] = P1;
         bP2[u] = P2;
     }
+    for (int i = tid; i < m; i += nt) posidx[i] = i;
     int sweep = 0;
     bool converged = false;
     for (; sweep < a.max_sweeps; ++sweep) {
         if (tid == 0) nrot = 0;
         __syncthreads();
-        for (int rd = 0; rd < m - 1; ++rd) {
+        for (int rd = 0; rd < m; ++rd) {
+            const int B = rd & 1;  // round A pairs positions (2k, 2k+1), round B (2k+1, 2k+2)
             if (tid < half) {
-                int p, q;
-                rr_pair(tid, rd, m, p, q);
+                // in round B, positions m-1 and 0 sit out: a pseudo pair with no rotation
+                const bool idle = B && tid == half - 1;
+                const int lp = idle ? m - 1 : 2 * tid + B, rp = idle ? 0 : lp + 1;
+                const int ia = posidx[lp], ib = posidx[rp];
+                const int p = min(ia, ib), q = max(ia, ib);
                 const double apq = A[ut(p, q, m)];
                 const double app = A[ut(p, p, m)], aqq = A[ut(q, q, m)];
                 double t = 0.0;
-                if (fabs(apq) > 2.220446049250313e-16 * sqrt(fabs(app) * fabs(aqq)) + absfloor) {
+                if (!idle &&
+                    fabs(apq) > 2.220446049250313e-16 * sqrt(fabs(app) * fabs(aqq)) + absfloor) {
                     // the rotation only has to annihilate apq to rounding, so reciprocals
                     // by Newton-refined estimates stand in for the divisions
                     const double theta = (aqq - app) * (0.5 * rcp_nr(apq));
@@ -145,10 +145,20 @@ __global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
                 }
                 const bool anyrot = __any(t != 0.0);
                 if (tid == 0 && anyrot) nrot = 1;
-                cs[tid] = t != 0.0 ? rot_cs(t) : make_double2(1.0, 0.0);
+                const double2 r = t != 0.0 ? rot_cs(t) : make_double2(1.0, 0.0);
+                cs[tid] = r;
                 tt[tid] = t;
                 pq[tid] = make_int2(p | (ut(p, 0, m) << 16), q | (ut(q, 0, m) << 16));
-                log[((size_t)sweep * (m - 1) + rd) * half + tid] = t;
+                if (!idle) {
+                    // by position: the left position's new value is c y + sigma x and the
+                    // right one's c x - sigma y, where x, y are the columns at the two
+                    // positions before the round and sigma is sin with the sign that
+                    // makes the left one p (then the two trade positions)
+                    log[((size_t)sweep * m + rd) * half + tid] =
+                        make_double2(r.x, ia < ib ? r.y : -r.y);
+                    posidx[lp] = ib;
+                    posidx[rp] = ia;
+                }
             }
             __syncthreads();
             // A is symmetric: only blocks P1 <= P2 (the upper triangle) are updated, and
@@ -213,83 +223,121 @@ __global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
     }
 }
 
-// blockIdx.x = 2 leaf + h: rows [h L/2, (h+1) L/2) of the leaf's V
-__global__ __launch_bounds__(LV_THREADS) void k_leaf_vectors(LeafArgs a) {
-    __shared__ double V[(LEAF_MAX / 2) * LJ_LD];
-    __shared__ double2 cs[2][LV_RB][LEAF_MAX / 2];
-    __shared__ int pq[2][LV_RB][LEAF_MAX / 2];  // p | q << 16
+// value of the neighbouring lane (lane + 1 for UP, lane - 1 otherwise) within a row of 16
+// lanes; the lanes at a row's end get their own value back
+template <bool UP>
+__device__ __forceinline__ double lane_shift(double x) {
+    constexpr int ctrl = UP ? 0x101 : 0x111;  // DPP row_shl:1 / row_shr:1
+    const long long b = __double_as_longlong(x);
+    const int lo = (int)(b & 0xffffffffll), hi = (int)(b >> 32);
+    const int l2 = __builtin_amdgcn_update_dpp(lo, lo, ctrl, 0xf, 0xf, false);
+    const int h2 = __builtin_amdgcn_update_dpp(hi, hi, ctrl, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)h2 << 32) | (unsigned int)l2);
+}
 
-    const int leafid = blockIdx.x >> 1;
-    const int L = a.leaf;
-    const int m = L, half = m / 2;
-    const int rows = L / 2, rbase = (blockIdx.x & 1) * rows;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int lane = tid % WAVE, row0 = (tid / WAVE) * LV_ROWS;  // replay: pair and rows
-    for (int e = tid; e < rows * L; e += nt) {
-        const int i = e / L, j = e % L;
-        V[i * LJ_LD + j] = (rbase + i == j) ? 1.0 : 0.0;
-    }
-    const double *log = a.rot + (size_t)leafid * a.max_sweeps * (m - 1) * half;
-    const int rounds = a.sweeps[leafid] * (m - 1);
-    const int per_block = LV_RB * half;  // tangents per staged block
-    const int nblk = (rounds + LV_RB - 1) / LV_RB;
-    // block b holds rounds [b RB, (b+1) RB); thread tid stages entry tid of a block
-    double tnext = 0.0;
-    if (tid < per_block && tid < rounds * half) tnext = log[tid];
-    for (int b = 0; b < nblk; ++b) {
-        if (tid < per_block) {
-            const int g = b * per_block + tid;
-            const int rr = tid / half, pr = tid % half;
-            cs[b & 1][rr][pr] =
-                (g < rounds * half && tnext != 0.0) ? rot_cs(tnext) : make_double2(1.0, 0.0);
-            int p, q;
-            rr_pair(pr, (b * LV_RB + rr) % (m - 1), m, p, q);
-            pq[b & 1][rr][pr] = p | (q << 16);
-        }
-        __syncthreads();
-        // the next block's tangents are in flight while this block is replayed
-        if (tid < per_block) {
-            const int g = (b + 1) * per_block + tid;
-            tnext = g < rounds * half ? log[g] : 0.0;
-        }
-        // columns: V <- V J, round after round.  Rows are independent: wavefront w owns
-        // rows [8w, 8w + 8) and lane pr the round's pair pr, so a round's rotation is read
-        // once per lane and applied to 8 rows, and every access to those rows comes from
-        // one wavefront, whose LDS accesses complete in program order -- consecutive rounds
-        // need no barrier.
-        if (lane < half && row0 < rows) {
-            const int rounds_here = min(LV_RB, rounds - b * LV_RB);
-            for (int rr = 0; rr < rounds_here; ++rr) {
-                const double2 r = cs[b & 1][rr][lane];
-                if (r.y == 0.0) continue;
-                const int c = pq[b & 1][rr][lane], cx = c & 0xffff, cy = c >> 16;
-                // all 16 loads of the round issued before the first store (the lanes' columns
-                // are disjoint, so nothing the stores write is read again this round)
-                double vp[LV_ROWS], vq[LV_ROWS];
+// Replay of the rotation log on V = I.  Rows of V J are independent and a round's
+// rotations touch neighbouring positions only, so V stays in registers: wavefront w of a
+// leaf owns rows [32 w, 32 w + 32); lane 8 g + s holds rows 32 w + 4 g .. + 3 at positions
+// [16 s, 16 s + 16) (positions past the leaf are zero padding).  Each round is static code:
+// pairs inside a segment from registers, the pairs across segments (round B) with the
+// neighbouring lane's value.  The log streams through LDS a block of rounds at a time, the
+// next block's loads in flight; only this wavefront touches its LDS, so no barrier is
+// needed.  A log entry (c, sigma) takes the columns x, y at the pair's positions to
+// (c y + sigma x, c x - sigma y); entries past a round's real pairs are (0, 1), which keeps
+// x in place and only negates the padding.
+__global__ __launch_bounds__(WAVE, 2) void k_leaf_vectors(LeafArgs a) {
+    __shared__ double2 cf[2][LV_RB][LV_CLD];
+    const int L = a.leaf, half = L / 2;
+    const int nwl = (L + LV_WROWS - 1) / LV_WROWS;
+    const int leafid = blockIdx.x / nwl, w = blockIdx.x - leafid * nwl;
+    const int lane = threadIdx.x;
+    const int sg = lane % LV_NSEG;
+    const int row0 = w * LV_WROWS + (lane / LV_NSEG) * LV_RPL, pos0 = sg * LV_SEG;
+    const bool has_left = sg > 0, has_right = sg < LV_NSEG - 1;
+    double v[LV_RPL][LV_SEG];
 #pragma unroll
-                for (int k = 0; k < LV_ROWS; ++k) {
-                    const int i = min(row0 + k, rows - 1);
-                    vp[k] = V[i * LJ_LD + cx];
-                    vq[k] = V[i * LJ_LD + cy];
+    for (int r = 0; r < LV_RPL; ++r)
+#pragma unroll
+        for (int j = 0; j < LV_SEG; ++j) v[r][j] = (row0 + r == pos0 + j) ? 1.0 : 0.0;
+
+    const double2 *log = reinterpret_cast<const double2 *>(a.rot) + (size_t)leafid * a.max_sweeps * L * half;
+    const int nsw = a.sweeps[leafid];
+    const int rounds = nsw * L;  // L is even: round rd is a round A when rd is even
+    const int nblk = (rounds + LV_RB - 1) / LV_RB;
+    const int slot = lane + lane / LV_SP;  // where this lane stages its entry
+    double2 nx[LV_RB];
+#pragma unroll
+    for (int u = 0; u < LV_RB; ++u)
+        nx[u] = (u < rounds && lane < half - (u & 1)) ? log[(size_t)u * half + lane] : make_double2(0.0, 1.0);
+    for (int b = 0; b < nblk; ++b) {
+        double2(*c)[LV_CLD] = cf[b & 1];
+#pragma unroll
+        for (int u = 0; u < LV_RB; ++u) c[u][slot] = nx[u];
+        wave_sync();
+#pragma unroll
+        for (int u = 0; u < LV_RB; ++u) {
+            const int rr = (b + 1) * LV_RB + u;
+            nx[u] = (rr < rounds && lane < half - (u & 1)) ? log[(size_t)rr * half + lane]
+                                                          : make_double2(0.0, 1.0);
+        }
+        const int nr = min(LV_RB, rounds - b * LV_RB);
+#pragma unroll
+        for (int u = 0; u < LV_RB; ++u) {
+            if (u >= nr) break;
+            const double2 *cu = c[u] + sg * (LV_SP + 1);  // entries 8 sg .. 8 sg + 7
+            if ((u & 1) == 0) {
+                // round A: pairs (2j, 2j+1) of the segment
+#pragma unroll
+                for (int j = 0; j < LV_SP; ++j) {
+                    const double2 e = cu[j];
+#pragma unroll
+                    for (int r = 0; r < LV_RPL; ++r) {
+                        const double x = v[r][2 * j], y = v[r][2 * j + 1];
+                        v[r][2 * j] = fma(e.x, y, e.y * x);
+                        v[r][2 * j + 1] = fma(e.x, x, -(e.y * y));
+                    }
+                }
+            } else {
+                // round B: pairs (2j+1, 2j+2) inside the segment, and the pairs across its
+                // ends: (16 sg + 15, 16 sg + 16) with entry 8 sg + 7 on the right, and
+                // (16 sg - 1, 16 sg) with entry 8 sg - 1 on the left
+                const double2 er = cu[LV_SP - 1];
+                const double2 el = cu[has_left ? -2 : 0];
+#pragma unroll
+                for (int r = 0; r < LV_RPL; ++r) {
+                    const double y = lane_shift<true>(v[r][0]);             // right neighbour's first
+                    const double x = lane_shift<false>(v[r][LV_SEG - 1]);  // left neighbour's last
+                    const double xs = v[r][LV_SEG - 1], ys = v[r][0];
+                    v[r][LV_SEG - 1] = has_right ? fma(er.x, y, er.y * xs) : xs;
+                    v[r][0] = has_left ? fma(el.x, x, -(el.y * ys)) : ys;
                 }
 #pragma unroll
-                for (int k = 0; k < LV_ROWS; ++k) {
-                    const int i = row0 + k;
-                    if (i >= rows) break;
-                    V[i * LJ_LD + cx] = r.x * vp[k] - r.y * vq[k];
-                    V[i * LJ_LD + cy] = r.y * vp[k] + r.x * vq[k];
+                for (int j = 0; j < LV_SP - 1; ++j) {
+                    const double2 e = cu[j];
+#pragma unroll
+                    for (int r = 0; r < LV_RPL; ++r) {
+                        const double x = v[r][2 * j + 1], y = v[r][2 * j + 2];
+                        v[r][2 * j + 1] = fma(e.x, y, e.y * x);
+                        v[r][2 * j + 2] = fma(e.x, x, -(e.y * y));
+                    }
                 }
             }
         }
+        wave_sync();
     }
-    __syncthreads();
-    // these rows of the sorted eigenvectors: column j of V is the eigenvector of diagonal
-    // entry j, whose ascending rank the Jacobi kernel stored
+    // every sweep reverses the positions: position pos holds column pos after an even
+    // number of sweeps and column L-1-pos after an odd one; column j of V is the
+    // eigenvector of diagonal entry j, whose ascending rank the Jacobi kernel stored
     const int32_t *rank = a.rank + (size_t)leafid * L;
     double *Q = a.Q + (size_t)leafid * L * L;  // eigenvector k contiguous
-    for (int e = tid; e < rows * L; e += nt) {
-        const int j = e / rows, i = e % rows;
-        Q[(size_t)rank[j] * L + rbase + i] = V[i * LJ_LD + j];
+#pragma unroll
+    for (int j = 0; j < LV_SEG; ++j) {
+        const int pos = pos0 + j;
+        if (pos >= L) continue;
+        const size_t k = (size_t)rank[(nsw & 1) ? L - 1 - pos : pos];
+#pragma unroll
+        for (int r = 0; r < LV_RPL; ++r)
+            if (row0 + r < L) Q[k * L + row0 + r] = v[r][j];
     }
 }
 
@@ -483,7 +531,8 @@ static inline dim3 grid_for(int64_t n, int b = 256) { return dim3((unsigned)((n 
 
 hipError_t launch_leaf_jacobi(const LeafArgs &a, hipStream_t s) {
     SDC_LAUNCH(KID_LEAF, k_leaf_jacobi, dim3(a.nleaf), dim3(LJ_THREADS), 0, s, a);
-    SDC_LAUNCH(KID_LEAF_VECTORS, k_leaf_vectors, dim3(2 * a.nleaf), dim3(LV_THREADS), 0, s, a);
+    SDC_LAUNCH(KID_LEAF_VECTORS, k_leaf_vectors, dim3(a.nleaf * ((a.leaf + LV_WROWS - 1) / LV_WROWS)),
+               dim3(WAVE), 0, s, a);
     SDC_LAUNCH(KID_LEAF_VECTORS, k_leaf_w, dim3(a.nleaf), dim3(256), 0, s, a);
     return hipGetLastError();
 }

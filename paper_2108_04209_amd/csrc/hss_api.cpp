@@ -25,7 +25,7 @@ struct superdc_hss {
     double *leafQ = nullptr;   // 2^depth x leaf x leaf
     double *leaf_lam = nullptr;
     double *Wleaf = nullptr;   // n x r
-    double *leaf_rot = nullptr;     // Jacobi rotation log: 2^depth x LEAF_SWEEPS x (leaf-1) x leaf/2
+    double *leaf_rot = nullptr;     // Jacobi rotation log: 2^depth x LEAF_SWEEPS x leaf x leaf/2 x 2
     int32_t *leaf_rank = nullptr;   // 2^depth x leaf
     int32_t *leaf_sweeps = nullptr; // 2^depth
     double *M[2] = {nullptr, nullptr};  // n x 2r update / basis columns (ping-pong)
@@ -274,7 +274,7 @@ int superdc_hss_plan_create(superdc_ctx *ctx, int32_t leaf, int32_t depth, int32
     if (e == hipSuccess) e = alloc(h, &h->leaf_lam, n);
     if (e == hipSuccess) e = alloc(h, &h->Wleaf, n * r);
     if (e == hipSuccess)
-        e = alloc(h, &h->leaf_rot, nleaf * LEAF_SWEEPS * (leaf - 1) * (leaf / 2));
+        e = alloc(h, &h->leaf_rot, nleaf * LEAF_SWEEPS * leaf * (leaf / 2) * 2);
     if (e == hipSuccess) e = alloc(h, &h->leaf_rank, n);
     if (e == hipSuccess) e = alloc(h, &h->leaf_sweeps, nleaf);
     if (e == hipSuccess) e = alloc(h, &h->M[0], n * 2 * r);
