@@ -30,9 +30,10 @@ namespace sdc {
 // ---------------------------------------------------------------------------------------
 constexpr int LJ_THREADS = 1024;
 constexpr int LJ_PACKED = LEAF_MAX * (LEAF_MAX + 1) / 2;
-// blocks of the folded triangle per thread: (h/2)(h+1) blocks, h = LEAF_MAX/2 rounded up
-// to even, over LJ_THREADS threads
-constexpr int LJ_BLK = ((LEAF_MAX / 4) * (LEAF_MAX / 2 + 1) + LJ_THREADS - 1) / LJ_THREADS;
+// slots of the folded block triangle per thread: (h/2)(h+1) blocks, h = LEAF_MAX/2 rounded
+// up to even, over the threads past the first wavefront
+constexpr int LJ_BLK =
+    ((LEAF_MAX / 4) * (LEAF_MAX / 2 + 1) + LJ_THREADS - WAVE - 1) / (LJ_THREADS - WAVE);
 constexpr int LV_SEG = 16;                          // positions a lane holds
 constexpr int LV_NSEG = LEAF_MAX / LV_SEG;          // segments of a row (8)
 constexpr int LV_RPL = 4;                           // rows a lane holds
@@ -63,16 +64,24 @@ __device__ __forceinline__ double2 rot_cs(double t) {
 // entries, so the round is a single pass over the matrix, and by symmetry a pass over the
 // blocks P1 <= P2.  Diagonal blocks use the updates app - t apq, aqq + t apq and set
 // apq = 0.
+//
+// The first wavefront owns the blocks that the next round's rotations read: the diagonal
+// blocks, the blocks (k, k+1) of neighbouring pairs and the block (0, m/2 - 1).  A pair of
+// the next round joins one index of pair k and one of pair k+1 of this round (or an index
+// that sits the round out), so its three entries all lie in those blocks.  That wavefront
+// therefore computes the next round's rotations right after its own blocks, while the
+// other wavefronts still update theirs, and a round ends in a single barrier; the rotation
+// data is double-buffered by round parity.
 __global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
     __shared__ double A[LJ_PACKED];  // upper triangle, packed by rows
-    __shared__ double2 cs[LEAF_MAX / 2];
-    __shared__ double tt[LEAF_MAX / 2];
+    __shared__ double2 cs[2][LEAF_MAX / 2];
+    __shared__ double tt[2][LEAF_MAX / 2];
     // p | rowstart(p) << 16 and q | rowstart(q) << 16 (rowstart: where the row starts in
     // the packed triangle): 8 bytes a pair for the block updates to read
-    __shared__ int2 pq[LEAF_MAX / 2];
+    __shared__ int2 pq[2][LEAF_MAX / 2];
     __shared__ int posidx[LEAF_MAX];  // index at each position of the odd-even ordering
     __shared__ double red[LJ_THREADS / WAVE];
-    __shared__ int nrot;
+    __shared__ int swept[2];          // per sweep parity: the sweep rotated something
 
     const int leafid = blockIdx.x;
     const int L = a.leaf;
@@ -88,6 +97,7 @@ __global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
     }
     for (int o = WAVE / 2; o > 0; o >>= 1) fro += __shfl_xor(fro, o);
     if (lane_id() == 0) red[tid / WAVE] = fro;
+    for (int i = tid; i < L; i += nt) posidx[i] = i;
     __syncthreads();
     double tot = 0.0;
     for (int w = 0; w < nt / WAVE; ++w) tot += red[w];
@@ -96,15 +106,18 @@ __global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
     const int half = m / 2;
     const int hh = (half + 1) & ~1;          // half rounded up to even, for the folding
     const int nfold = (hh / 2) * (hh + 1);  // blocks of the folded triangle
-    double2 *log = reinterpret_cast<double2 *>(a.rot) + (size_t)leafid * a.max_sweeps * m * half;
-    // this thread's blocks, the same in every round
+    const int total = a.max_sweeps * m;     // rounds the log has room for
+    double2 *log = reinterpret_cast<double2 *>(a.rot) + (size_t)leafid * total * half;
+    const bool first = tid < WAVE;
+    // the other wavefronts' blocks, the same in every round: the folded triangle dealt out
+    // over their threads, without the first wavefront's blocks
     int bP1[LJ_BLK], bP2[LJ_BLK];  // bP1 < 0: no block
 #pragma unroll
     for (int u = 0; u < LJ_BLK; ++u) {
         bP1[u] = -1;
         bP2[u] = 0;
-        const int blk = tid + u * nt;
-        if (blk >= nfold) continue;
+        const int blk = (tid - WAVE) + u * (nt - WAVE);
+        if (first || blk >= nfold) continue;
         const int r = blk / (hh + 1), e = blk - r * (hh + 1);
         int P1, P2;
         if (e < hh - r) {
@@ -115,95 +128,117 @@ __global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
             P2 = e - 1;
         }
         if (P2 >= half) continue;  // padding of an odd half
+        if (P2 - P1 <= 1 || (P1 == 0 && P2 == half - 1)) continue;  // the first wavefront's
         bP1[u] = P1;
         bP2[u] = P2;
     }
-    for (int i = tid; i < m; i += nt) posidx[i] = i;
+
+    // block (P1, P2) with the rotations of buffer b
+    auto update_block = [&](int P1, int P2, int b) {
+        const double2 r1 = cs[b][P1], r2 = cs[b][P2];
+        if (r1.y == 0.0 && r2.y == 0.0) return;
+        const int2 ab2 = pq[b][P1], cd2 = pq[b][P2];
+        // (index, index, row start, row start) of each pair
+        const int4 ab = make_int4(ab2.x & 0xffff, ab2.y & 0xffff, ab2.x >> 16, ab2.y >> 16);
+        const int4 cd = make_int4(cd2.x & 0xffff, cd2.y & 0xffff, cd2.x >> 16, cd2.y >> 16);
+        if (P1 == P2) {
+            const double t = tt[b][P1];
+            const double apq = A[ab.z + ab.y];
+            A[ab.z + ab.x] -= t * apq;
+            A[ab.w + ab.y] += t * apq;
+            A[ab.z + ab.y] = 0.0;
+            return;
+        }
+        // entry (i, j) of the upper triangle sits at rowstart(min) + max
+        const int iac = ab.x < cd.x ? ab.z + cd.x : cd.z + ab.x;
+        const int iad = ab.x < cd.y ? ab.z + cd.y : cd.w + ab.x;
+        const int ibc = ab.y < cd.x ? ab.w + cd.x : cd.z + ab.y;
+        const int ibd = ab.y < cd.y ? ab.w + cd.y : cd.w + ab.y;
+        const double xac = A[iac], xad = A[iad], xbc = A[ibc], xbd = A[ibd];
+        // rows: J1^T X
+        const double yac = r1.x * xac - r1.y * xbc, ybc = r1.y * xac + r1.x * xbc;
+        const double yad = r1.x * xad - r1.y * xbd, ybd = r1.y * xad + r1.x * xbd;
+        // columns: (J1^T X) J2
+        A[iac] = r2.x * yac - r2.y * yad;
+        A[iad] = r2.y * yac + r2.x * yad;
+        A[ibc] = r2.x * ybc - r2.y * ybd;
+        A[ibd] = r2.y * ybc + r2.x * ybd;
+    };
+
+    // rotations of round g (first wavefront, lane k: pair k) into buffer g & 1, with the
+    // positions' trade and the log entry; returns whether the wavefront rotated anything
+    auto rotations = [&](int g) -> bool {
+        const int k = tid;
+        const int B = g & 1;  // m is even: round A pairs positions (2k, 2k+1), B (2k+1, 2k+2)
+        double t = 0.0;
+        if (k < half) {
+            // in round B, positions m-1 and 0 sit out: a pseudo pair with no rotation
+            const bool idle = B && k == half - 1;
+            const int lp = idle ? m - 1 : 2 * k + B, rp = idle ? 0 : lp + 1;
+            const int ia = posidx[lp], ib = posidx[rp];
+            const int p = min(ia, ib), q = max(ia, ib);
+            const double apq = A[ut(p, q, m)];
+            const double app = A[ut(p, p, m)], aqq = A[ut(q, q, m)];
+            if (!idle &&
+                fabs(apq) > 2.220446049250313e-16 * sqrt(fabs(app) * fabs(aqq)) + absfloor) {
+                // the rotation only has to annihilate apq to rounding, so reciprocals by
+                // Newton-refined estimates stand in for the divisions
+                const double theta = (aqq - app) * (0.5 * rcp_nr(apq));
+                if (fabs(theta) > 1e150) t = 0.5 * rcp_nr(theta);
+                else t = (theta >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(theta) + sqrt(theta * theta + 1.0));
+            }
+            const double2 r = t != 0.0 ? rot_cs(t) : make_double2(1.0, 0.0);
+            cs[B][k] = r;
+            tt[B][k] = t;
+            pq[B][k] = make_int2(p | (ut(p, 0, m) << 16), q | (ut(q, 0, m) << 16));
+            if (!idle) {
+                // by position: the left position's new value is c y + sigma x and the right
+                // one's c x - sigma y, where x, y are the columns at the two positions
+                // before the round and sigma is sin with the sign that makes the left one p
+                // (then the two trade positions)
+                log[(size_t)g * half + k] = make_double2(r.x, ia < ib ? r.y : -r.y);
+                posidx[lp] = ib;
+                posidx[rp] = ia;
+            }
+        }
+        return __any(t != 0.0);
+    };
+
+    bool rot_acc = false;  // first wavefront: the current sweep's rotations so far
+    if (first) rot_acc = rotations(0);
+    __syncthreads();
     int sweep = 0;
     bool converged = false;
-    for (; sweep < a.max_sweeps; ++sweep) {
-        if (tid == 0) nrot = 0;
-        __syncthreads();
-        for (int rd = 0; rd < m; ++rd) {
-            const int B = rd & 1;  // round A pairs positions (2k, 2k+1), round B (2k+1, 2k+2)
-            if (tid < half) {
-                // in round B, positions m-1 and 0 sit out: a pseudo pair with no rotation
-                const bool idle = B && tid == half - 1;
-                const int lp = idle ? m - 1 : 2 * tid + B, rp = idle ? 0 : lp + 1;
-                const int ia = posidx[lp], ib = posidx[rp];
-                const int p = min(ia, ib), q = max(ia, ib);
-                const double apq = A[ut(p, q, m)];
-                const double app = A[ut(p, p, m)], aqq = A[ut(q, q, m)];
-                double t = 0.0;
-                if (!idle &&
-                    fabs(apq) > 2.220446049250313e-16 * sqrt(fabs(app) * fabs(aqq)) + absfloor) {
-                    // the rotation only has to annihilate apq to rounding, so reciprocals
-                    // by Newton-refined estimates stand in for the divisions
-                    const double theta = (aqq - app) * (0.5 * rcp_nr(apq));
-                    if (fabs(theta) > 1e150) t = 0.5 * rcp_nr(theta);
-                    else t = (theta >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(theta) + sqrt(theta * theta + 1.0));
-                }
-                const bool anyrot = __any(t != 0.0);
-                if (tid == 0 && anyrot) nrot = 1;
-                const double2 r = t != 0.0 ? rot_cs(t) : make_double2(1.0, 0.0);
-                cs[tid] = r;
-                tt[tid] = t;
-                pq[tid] = make_int2(p | (ut(p, 0, m) << 16), q | (ut(q, 0, m) << 16));
-                if (!idle) {
-                    // by position: the left position's new value is c y + sigma x and the
-                    // right one's c x - sigma y, where x, y are the columns at the two
-                    // positions before the round and sigma is sin with the sign that
-                    // makes the left one p (then the two trade positions)
-                    log[((size_t)sweep * m + rd) * half + tid] =
-                        make_double2(r.x, ia < ib ? r.y : -r.y);
-                    posidx[lp] = ib;
-                    posidx[rp] = ia;
+    for (int g = 0;; ++g) {
+        const int b = g & 1;  // rotation buffer, and round B when set
+        if (first) {
+            const int k = tid;
+            if (k < half) {
+                update_block(k, k, b);
+                if (!b && k + 1 < half) update_block(k, k + 1, b);
+                if (b && k >= 1) update_block(k - 1, k, b);
+            }
+            if (k == 0 && half >= 3) update_block(0, half - 1, b);
+            if (g + 1 < total) {
+                wave_sync();
+                rot_acc |= rotations(g + 1);
+                if ((g + 1) % m == m - 1) {  // the sweep's last round is decided
+                    if (tid == 0) swept[((g + 1) / m) & 1] = rot_acc;
+                    rot_acc = false;
                 }
             }
-            __syncthreads();
-            // A is symmetric: only blocks P1 <= P2 (the upper triangle) are updated, and
-            // entries are read and written at (min(i,j), max(i,j)).  The blocks are dealt out
-            // by folding row r of the block triangle with row hh-1-r (hh+1 blocks together).
+        } else {
 #pragma unroll
-            for (int u = 0; u < LJ_BLK; ++u) {
-                const int P1 = bP1[u], P2 = bP2[u];
-                if (P1 < 0) continue;
-                const double2 r1 = cs[P1], r2 = cs[P2];
-                if (r1.y == 0.0 && r2.y == 0.0) continue;
-                const int2 ab2 = pq[P1], cd2 = pq[P2];
-                // (index, index, row start, row start) of each pair
-                const int4 ab = make_int4(ab2.x & 0xffff, ab2.y & 0xffff, ab2.x >> 16, ab2.y >> 16);
-                const int4 cd = make_int4(cd2.x & 0xffff, cd2.y & 0xffff, cd2.x >> 16, cd2.y >> 16);
-                if (P1 == P2) {
-                    const double t = tt[P1];
-                    const double apq = A[ab.z + ab.y];
-                    A[ab.z + ab.x] -= t * apq;
-                    A[ab.w + ab.y] += t * apq;
-                    A[ab.z + ab.y] = 0.0;
-                    continue;
-                }
-                // entry (i, j) of the upper triangle sits at rowstart(min) + max
-                const int iac = ab.x < cd.x ? ab.z + cd.x : cd.z + ab.x;
-                const int iad = ab.x < cd.y ? ab.z + cd.y : cd.w + ab.x;
-                const int ibc = ab.y < cd.x ? ab.w + cd.x : cd.z + ab.y;
-                const int ibd = ab.y < cd.y ? ab.w + cd.y : cd.w + ab.y;
-                const double xac = A[iac], xad = A[iad], xbc = A[ibc], xbd = A[ibd];
-                // rows: J1^T X
-                const double yac = r1.x * xac - r1.y * xbc, ybc = r1.y * xac + r1.x * xbc;
-                const double yad = r1.x * xad - r1.y * xbd, ybd = r1.y * xad + r1.x * xbd;
-                // columns: (J1^T X) J2
-                A[iac] = r2.x * yac - r2.y * yad;
-                A[iad] = r2.y * yac + r2.x * yad;
-                A[ibc] = r2.x * ybc - r2.y * ybd;
-                A[ibd] = r2.y * ybc + r2.x * ybd;
-            }
-            __syncthreads();
+            for (int u = 0; u < LJ_BLK; ++u)
+                if (bP1[u] >= 0) update_block(bP1[u], bP2[u], b);
         }
-        const int nr = nrot;
         __syncthreads();
-        if (nr == 0) {  // a sweep without rotations: nothing of it needs replaying
-            converged = true;
-            break;
+        if (g % m == m - 1) {  // the end of sweep g / m
+            if (!swept[(g / m) & 1]) {  // a sweep without rotations: nothing of it needs replaying
+                converged = true;
+                break;
+            }
+            if (++sweep == a.max_sweeps) break;
         }
     }
     // ascending order of the eigenvalues (ties broken by index)
