@@ -44,7 +44,7 @@ constexpr int LV_CLD = LV_PAIRS + LV_NSEG;          // staged entry k sits at k 
                                                     // so the segments' reads hit distinct banks
 constexpr int LV_RB = 4;                            // rounds per staged block
 static_assert(LEAF_MAX / 2 <= WAVE, "a round's pairs must fit one wavefront");
-static_assert(LJ_PACKED < (1 << 15), "row starts of the packed triangle fit 15 bits");
+static_assert(LJ_PACKED < (1 << 15), "addresses in the packed triangle fit 15 bits");
 static_assert(LV_PAIRS == WAVE, "one staged log entry per lane");
 static_assert(LV_NSEG * LV_SEG == LEAF_MAX && LV_NSEG <= 16 && 16 % LV_NSEG == 0,
               "a row's segments are neighbouring lanes of one 16-lane DPP row");
@@ -59,29 +59,30 @@ __device__ __forceinline__ double2 rot_cs(double t) {
     return make_double2(c, t * c);
 }
 
-// One round applies A <- J^T A J for the m/2 disjoint rotations of the round at once:
-// every 2 x 2 block (rows of pair P1, columns of pair P2) depends only on its own four
-// entries, so the round is a single pass over the matrix, and by symmetry a pass over the
-// blocks P1 <= P2.  Diagonal blocks use the updates app - t apq, aqq + t apq and set
-// apq = 0.
+// The matrix is kept by position: entry (i, j) of the packed upper triangle is the entry
+// of the two indices at positions i and j.  A round's rotation of pair k then acts on the
+// positions (l, r) of the pair by the reflection [[sigma, c], [c, -sigma]] -- the rotation
+// followed by the trade of positions -- with theta = (A(r,r) - A(l,l)) / (2 A(l,r)) taken
+// at the positions (the sign of sigma then comes out right whichever of the two indices is
+// the smaller), and the round is A <- R A R with R the direct sum of the reflections (the
+// identity on the two positions that sit out round B).  Every 2 x 2 block (rows of pair P1,
+// columns of pair P2) depends only on its own four entries, so a round is a single pass over
+// the blocks P1 <= P2 at addresses fixed for each round type.  Diagonal blocks take
+// (x, w; w, y) to (y + t w, 0; 0, x - t w), or to (y, w; w, x) when there is no rotation.
 //
 // The first wavefront owns the blocks that the next round's rotations read: the diagonal
 // blocks, the blocks (k, k+1) of neighbouring pairs and the block (0, m/2 - 1).  A pair of
-// the next round joins one index of pair k and one of pair k+1 of this round (or an index
-// that sits the round out), so its three entries all lie in those blocks.  That wavefront
-// therefore computes the next round's rotations right after its own blocks, while the
-// other wavefronts still update theirs, and a round ends in a single barrier; the rotation
-// data is double-buffered by round parity.
-__global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
-    __shared__ double A[LJ_PACKED];  // upper triangle, packed by rows
-    __shared__ double2 cs[2][LEAF_MAX / 2];
-    __shared__ double tt[2][LEAF_MAX / 2];
-    // p | rowstart(p) << 16 and q | rowstart(q) << 16 (rowstart: where the row starts in
-    // the packed triangle): 8 bytes a pair for the block updates to read
-    __shared__ int2 pq[2][LEAF_MAX / 2];
-    __shared__ int posidx[LEAF_MAX];  // index at each position of the odd-even ordering
+// the next round joins one position of pair k and one of pair k+1 of this round (or a
+// position that sits the round out), so its three entries all lie in those blocks.  That
+// wavefront therefore computes the next round's rotations right after its own blocks,
+// while the other wavefronts still update theirs, and a round ends in a single barrier;
+// the rotation data is double-buffered by round parity.
+__global__ __launch_bounds__(LJ_THREADS, 2 * LJ_THREADS / WAVE / 4) void k_leaf_jacobi(LeafArgs a) {
+    __shared__ double A[LJ_PACKED];         // upper triangle by position, packed by rows
+    __shared__ double2 cs[2][LEAF_MAX / 2];  // (c, sigma) of each pair
+    __shared__ double tt[2][LEAF_MAX / 2];   // tangent of each pair's rotation (0: none)
     __shared__ double red[LJ_THREADS / WAVE];
-    __shared__ int swept[2];          // per sweep parity: the sweep rotated something
+    __shared__ int swept[2];  // per sweep parity: the sweep rotated something
 
     const int leafid = blockIdx.x;
     const int L = a.leaf;
@@ -97,7 +98,6 @@ __global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
     }
     for (int o = WAVE / 2; o > 0; o >>= 1) fro += __shfl_xor(fro, o);
     if (lane_id() == 0) red[tid / WAVE] = fro;
-    for (int i = tid; i < L; i += nt) posidx[i] = i;
     __syncthreads();
     double tot = 0.0;
     for (int w = 0; w < nt / WAVE; ++w) tot += red[w];
@@ -109,13 +109,26 @@ __global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
     const int total = a.max_sweeps * m;     // rounds the log has room for
     double2 *log = reinterpret_cast<double2 *>(a.rot) + (size_t)leafid * total * half;
     const bool first = tid < WAVE;
+    // addresses of the block of row pair (r0, r1) and column pair (c0, c1), r1 < c0: a
+    // column pair (m-1, 0) is the pair that sits round B out, whose entries (r, 0) are kept
+    // at (0, r)
+    auto block_addr = [&](int r0, int r1, int c0, int c1, int4 &ad) {
+        if (c1 != 0) ad = make_int4(ut(r0, c0, m), ut(r0, c1, m), ut(r1, c0, m), ut(r1, c1, m));
+        else ad = make_int4(ut(r0, m - 1, m), ut(0, r0, m), ut(r1, m - 1, m), ut(0, r1, m));
+    };
     // the other wavefronts' blocks, the same in every round: the folded triangle dealt out
-    // over their threads, without the first wavefront's blocks
+    // over their threads, without the first wavefront's blocks; addresses for round A and B
+    // (two addresses of 16 bits to an int, so that the kernel keeps to 64 registers and two
+    // leaves share a CU)
     int bP1[LJ_BLK], bP2[LJ_BLK];  // bP1 < 0: no block
+    int2 adA[LJ_BLK], adB[LJ_BLK];
+    auto pack = [](const int4 &ad) { return make_int2(ad.x | ad.y << 16, ad.z | ad.w << 16); };
+    auto unpack = [](int2 p) { return make_int4(p.x & 0xffff, p.x >> 16, p.y & 0xffff, p.y >> 16); };
 #pragma unroll
     for (int u = 0; u < LJ_BLK; ++u) {
         bP1[u] = -1;
         bP2[u] = 0;
+        adA[u] = adB[u] = make_int2(0, 0);
         const int blk = (tid - WAVE) + u * (nt - WAVE);
         if (first || blk >= nfold) continue;
         const int r = blk / (hh + 1), e = blk - r * (hh + 1);
@@ -131,75 +144,62 @@ __global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
         if (P2 - P1 <= 1 || (P1 == 0 && P2 == half - 1)) continue;  // the first wavefront's
         bP1[u] = P1;
         bP2[u] = P2;
+        int4 ad;
+        block_addr(2 * P1, 2 * P1 + 1, 2 * P2, 2 * P2 + 1, ad);
+        adA[u] = pack(ad);
+        if (P2 < half - 1) block_addr(2 * P1 + 1, 2 * P1 + 2, 2 * P2 + 1, 2 * P2 + 2, ad);
+        else block_addr(2 * P1 + 1, 2 * P1 + 2, m - 1, 0, ad);
+        adB[u] = pack(ad);
     }
 
-    // block (P1, P2) with the rotations of buffer b
-    auto update_block = [&](int P1, int P2, int b) {
-        const double2 r1 = cs[b][P1], r2 = cs[b][P2];
-        if (r1.y == 0.0 && r2.y == 0.0) return;
-        const int2 ab2 = pq[b][P1], cd2 = pq[b][P2];
-        // (index, index, row start, row start) of each pair
-        const int4 ab = make_int4(ab2.x & 0xffff, ab2.y & 0xffff, ab2.x >> 16, ab2.y >> 16);
-        const int4 cd = make_int4(cd2.x & 0xffff, cd2.y & 0xffff, cd2.x >> 16, cd2.y >> 16);
-        if (P1 == P2) {
-            const double t = tt[b][P1];
-            const double apq = A[ab.z + ab.y];
-            A[ab.z + ab.x] -= t * apq;
-            A[ab.w + ab.y] += t * apq;
-            A[ab.z + ab.y] = 0.0;
+    // off-diagonal block of pairs P1 < P2 at addresses ad, with the reflections of buffer b
+    // (cols_idle: the column pair sits the round out)
+    auto update_block = [&](int P1, int P2, const int4 &ad, int b, bool cols_idle) {
+        const double2 r1 = cs[b][P1];
+        const double x00 = A[ad.x], x01 = A[ad.y], x10 = A[ad.z], x11 = A[ad.w];
+        // rows: R1 X
+        const double y00 = fma(r1.x, x10, r1.y * x00), y10 = fma(r1.x, x00, -(r1.y * x10));
+        const double y01 = fma(r1.x, x11, r1.y * x01), y11 = fma(r1.x, x01, -(r1.y * x11));
+        if (cols_idle) {
+            A[ad.x] = y00;
+            A[ad.y] = y01;
+            A[ad.z] = y10;
+            A[ad.w] = y11;
             return;
         }
-        // entry (i, j) of the upper triangle sits at rowstart(min) + max
-        const int iac = ab.x < cd.x ? ab.z + cd.x : cd.z + ab.x;
-        const int iad = ab.x < cd.y ? ab.z + cd.y : cd.w + ab.x;
-        const int ibc = ab.y < cd.x ? ab.w + cd.x : cd.z + ab.y;
-        const int ibd = ab.y < cd.y ? ab.w + cd.y : cd.w + ab.y;
-        const double xac = A[iac], xad = A[iad], xbc = A[ibc], xbd = A[ibd];
-        // rows: J1^T X
-        const double yac = r1.x * xac - r1.y * xbc, ybc = r1.y * xac + r1.x * xbc;
-        const double yad = r1.x * xad - r1.y * xbd, ybd = r1.y * xad + r1.x * xbd;
-        // columns: (J1^T X) J2
-        A[iac] = r2.x * yac - r2.y * yad;
-        A[iad] = r2.y * yac + r2.x * yad;
-        A[ibc] = r2.x * ybc - r2.y * ybd;
-        A[ibd] = r2.y * ybc + r2.x * ybd;
+        // columns: (R1 X) R2
+        const double2 r2 = cs[b][P2];
+        A[ad.x] = fma(r2.x, y01, r2.y * y00);
+        A[ad.y] = fma(r2.x, y00, -(r2.y * y01));
+        A[ad.z] = fma(r2.x, y11, r2.y * y10);
+        A[ad.w] = fma(r2.x, y10, -(r2.y * y11));
     };
 
     // rotations of round g (first wavefront, lane k: pair k) into buffer g & 1, with the
-    // positions' trade and the log entry; returns whether the wavefront rotated anything
+    // log entry; returns whether the wavefront rotated anything
     auto rotations = [&](int g) -> bool {
         const int k = tid;
         const int B = g & 1;  // m is even: round A pairs positions (2k, 2k+1), B (2k+1, 2k+2)
         double t = 0.0;
         if (k < half) {
-            // in round B, positions m-1 and 0 sit out: a pseudo pair with no rotation
+            // in round B, positions m-1 and 0 sit out
             const bool idle = B && k == half - 1;
-            const int lp = idle ? m - 1 : 2 * k + B, rp = idle ? 0 : lp + 1;
-            const int ia = posidx[lp], ib = posidx[rp];
-            const int p = min(ia, ib), q = max(ia, ib);
-            const double apq = A[ut(p, q, m)];
-            const double app = A[ut(p, p, m)], aqq = A[ut(q, q, m)];
-            if (!idle &&
-                fabs(apq) > 2.220446049250313e-16 * sqrt(fabs(app) * fabs(aqq)) + absfloor) {
-                // the rotation only has to annihilate apq to rounding, so reciprocals by
+            const int lp = idle ? 0 : 2 * k + B, rp = lp + 1;
+            const double w = A[ut(lp, rp, m)];
+            const double x = A[ut(lp, lp, m)], y = A[ut(rp, rp, m)];
+            if (!idle && fabs(w) > 2.220446049250313e-16 * sqrt(fabs(x) * fabs(y)) + absfloor) {
+                // the rotation only has to annihilate w to rounding, so reciprocals by
                 // Newton-refined estimates stand in for the divisions
-                const double theta = (aqq - app) * (0.5 * rcp_nr(apq));
+                const double theta = (y - x) * (0.5 * rcp_nr(w));
                 if (fabs(theta) > 1e150) t = 0.5 * rcp_nr(theta);
                 else t = (theta >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(theta) + sqrt(theta * theta + 1.0));
             }
             const double2 r = t != 0.0 ? rot_cs(t) : make_double2(1.0, 0.0);
             cs[B][k] = r;
             tt[B][k] = t;
-            pq[B][k] = make_int2(p | (ut(p, 0, m) << 16), q | (ut(q, 0, m) << 16));
-            if (!idle) {
-                // by position: the left position's new value is c y + sigma x and the right
-                // one's c x - sigma y, where x, y are the columns at the two positions
-                // before the round and sigma is sin with the sign that makes the left one p
-                // (then the two trade positions)
-                log[(size_t)g * half + k] = make_double2(r.x, ia < ib ? r.y : -r.y);
-                posidx[lp] = ib;
-                posidx[rp] = ia;
-            }
+            // the left position's new column is c y + sigma x and the right one's
+            // c x - sigma y, for the columns x, y at the two positions before the round
+            if (!idle) log[(size_t)g * half + k] = r;
         }
         return __any(t != 0.0);
     };
@@ -213,12 +213,31 @@ __global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
         const int b = g & 1;  // rotation buffer, and round B when set
         if (first) {
             const int k = tid;
-            if (k < half) {
-                update_block(k, k, b);
-                if (!b && k + 1 < half) update_block(k, k + 1, b);
-                if (b && k >= 1) update_block(k - 1, k, b);
+            if (k < half && !(b && k == half - 1)) {
+                // diagonal block of pair k at positions (l, l+1)
+                const int l = 2 * k + b;
+                const int ixx = ut(l, l, m), ixw = ixx + 1, iyy = ut(l + 1, l + 1, m);
+                const double t = tt[b][k];
+                const double x = A[ixx], w = A[ixw], y = A[iyy];
+                A[ixx] = fma(t, w, y);
+                A[iyy] = fma(-t, w, x);
+                A[ixw] = t != 0.0 ? 0.0 : w;
             }
-            if (k == 0 && half >= 3) update_block(0, half - 1, b);
+            int4 ad;
+            if (!b && k + 1 < half) {  // round A: block (k, k+1)
+                block_addr(2 * k, 2 * k + 1, 2 * k + 2, 2 * k + 3, ad);
+                update_block(k, k + 1, ad, b, false);
+            }
+            if (b && k >= 1 && k < half) {  // round B: block (k-1, k)
+                const bool idle = k == half - 1;
+                block_addr(2 * k - 1, 2 * k, idle ? m - 1 : 2 * k + 1, idle ? 0 : 2 * k + 2, ad);
+                update_block(k - 1, k, ad, b, idle);
+            }
+            if (k == 0 && half >= 3) {  // block (0, m/2 - 1)
+                if (!b) block_addr(0, 1, m - 2, m - 1, ad);
+                else block_addr(1, 2, m - 1, 0, ad);
+                update_block(0, half - 1, ad, b, b);
+            }
             if (g + 1 < total) {
                 wave_sync();
                 rot_acc |= rotations(g + 1);
@@ -230,7 +249,8 @@ __global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
         } else {
 #pragma unroll
             for (int u = 0; u < LJ_BLK; ++u)
-                if (bP1[u] >= 0) update_block(bP1[u], bP2[u], b);
+                if (bP1[u] >= 0)
+                    update_block(bP1[u], bP2[u], unpack(b ? adB[u] : adA[u]), b, b && bP2[u] == half - 1);
         }
         __syncthreads();
         if (g % m == m - 1) {  // the end of sweep g / m
@@ -241,7 +261,9 @@ __global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
             if (++sweep == a.max_sweeps) break;
         }
     }
-    // ascending order of the eigenvalues (ties broken by index)
+    // ascending order of the eigenvalues (ties broken by position).  A sweep reverses the
+    // positions, and the replay stops short of a last sweep without rotations, so position j
+    // here is position m-1-j of the replayed vectors when that sweep ran
     if (tid < L) {
         const double v = A[ut(tid, tid, L)];
         int r = 0;
@@ -249,7 +271,7 @@ __global__ __launch_bounds__(LJ_THREADS) void k_leaf_jacobi(LeafArgs a) {
             const double w = A[ut(j, j, L)];
             r += (w < v) || (w == v && j < tid);
         }
-        a.rank[(size_t)leafid * L + tid] = r;
+        a.rank[(size_t)leafid * L + (converged ? L - 1 - tid : tid)] = r;
         a.lam[(size_t)leafid * L + r] = v;
     }
     if (tid == 0) {
@@ -360,16 +382,15 @@ __global__ __launch_bounds__(WAVE, 2) void k_leaf_vectors(LeafArgs a) {
         }
         wave_sync();
     }
-    // every sweep reverses the positions: position pos holds column pos after an even
-    // number of sweeps and column L-1-pos after an odd one; column j of V is the
-    // eigenvector of diagonal entry j, whose ascending rank the Jacobi kernel stored
+    // the column at position pos is the eigenvector whose ascending rank the Jacobi kernel
+    // stored for that position
     const int32_t *rank = a.rank + (size_t)leafid * L;
     double *Q = a.Q + (size_t)leafid * L * L;  // eigenvector k contiguous
 #pragma unroll
     for (int j = 0; j < LV_SEG; ++j) {
         const int pos = pos0 + j;
         if (pos >= L) continue;
-        const size_t k = (size_t)rank[(nsw & 1) ? L - 1 - pos : pos];
+        const size_t k = (size_t)rank[pos];
 #pragma unroll
         for (int r = 0; r < LV_RPL; ++r)
             if (row0 + r < L) Q[k * L + row0 + r] = v[r][j];
