@@ -33,7 +33,10 @@ def run_conquer(tree, persistent=1, levels=True, plan=None):
     return plan, {k: (None if v is None else v.cpu().numpy()) for k, v in out.items()}
 
 
-@pytest.mark.parametrize("shape", [(16, 3, 4), (32, 4, 8), (128, 3, 8), (64, 5, 2)])
+# leaves with an odd number of pairs (6, 30, 126) and of one pair (2) exercise the Jacobi's
+# pair that sits out round B and the replay's last block of two rounds
+@pytest.mark.parametrize("shape", [(16, 3, 4), (32, 4, 8), (128, 3, 8), (64, 5, 2),
+                                   (6, 2, 2), (30, 3, 4), (126, 2, 8), (2, 3, 1)])
 def test_levels_small(shape):
     leaf, depth, r = shape
     tree = gen.hss_tree(n=leaf << depth, leaf=leaf, r=r, cfg=400 + leaf + depth)
