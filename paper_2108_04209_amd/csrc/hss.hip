@@ -50,8 +50,17 @@ static_assert(LV_NSEG * LV_SEG == LEAF_MAX && LV_NSEG <= 16 && 16 % LV_NSEG == 0
               "a row's segments are neighbouring lanes of one 16-lane DPP row");
 static_assert(LV_RB % 2 == 0, "a staged block starts on a round A");
 
-// entry (i, j), i <= j, of the upper triangle of an m x m matrix packed by rows
-__device__ __forceinline__ int ut(int i, int j, int m) { return ((i * (2 * m - i - 1)) >> 1) + j; }
+// entry (i, j), i <= j, of the upper triangle of an m x m matrix (m even) packed by rows,
+// each row holding its even columns first and then its odd ones: a round's blocks take a
+// column of one parity from every pair, so lanes with neighbouring column pairs read
+// neighbouring words of a row instead of every other one (which halved the LDS bank
+// throughput)
+__device__ __forceinline__ int ut(int i, int j, int m) {
+    const int start = (i * (2 * m - i + 1)) >> 1;  // where row i starts
+    const int odd = i & 1;
+    const int neven = (m - i - odd) >> 1;           // even columns in [i, m)
+    return start + ((j & 1) ? neven + ((j - i - 1 + odd) >> 1) : ((j - i - odd) >> 1));
+}
 
 // cos and sin of the rotation with tangent t
 __device__ __forceinline__ double2 rot_cs(double t) {
@@ -216,7 +225,7 @@ __global__ __launch_bounds__(LJ_THREADS, 2 * LJ_THREADS / WAVE / 4) void k_leaf_
             if (k < half && !(b && k == half - 1)) {
                 // diagonal block of pair k at positions (l, l+1)
                 const int l = 2 * k + b;
-                const int ixx = ut(l, l, m), ixw = ixx + 1, iyy = ut(l + 1, l + 1, m);
+                const int ixx = ut(l, l, m), ixw = ut(l, l + 1, m), iyy = ut(l + 1, l + 1, m);
                 const double t = tt[b][k];
                 const double x = A[ixx], w = A[ixw], y = A[iyy];
                 A[ixx] = fma(t, w, y);
