@@ -319,7 +319,7 @@ __global__ __launch_bounds__(WAVE, 2) void k_leaf_vectors(LeafArgs a) {
     const int lane = threadIdx.x;
     const int sg = lane % LV_NSEG;
     const int row0 = w * LV_WROWS + (lane / LV_NSEG) * LV_RPL, pos0 = sg * LV_SEG;
-    const bool has_left = sg > 0, has_right = sg < LV_NSEG - 1;
+    const bool has_left = sg > 0;
     double v[LV_RPL][LV_SEG];
 #pragma unroll
     for (int r = 0; r < LV_RPL; ++r)
@@ -367,15 +367,19 @@ __global__ __launch_bounds__(WAVE, 2) void k_leaf_vectors(LeafArgs a) {
                 // round B: pairs (2j+1, 2j+2) inside the segment, and the pairs across its
                 // ends: (16 sg + 15, 16 sg + 16) with entry 8 sg + 7 on the right, and
                 // (16 sg - 1, 16 sg) with entry 8 sg - 1 on the left
+                // the last segment's entry 8 sg + 7 is past the round's pairs, so (0, 1) keeps
+                // its last position; the first segment has no left pair, and (0, -1) keeps
+                // its first position (the neighbours' values are finite either way)
                 const double2 er = cu[LV_SP - 1];
-                const double2 el = cu[has_left ? -2 : 0];
+                double2 el = cu[has_left ? -2 : 0];
+                if (!has_left) el = make_double2(0.0, -1.0);
 #pragma unroll
                 for (int r = 0; r < LV_RPL; ++r) {
                     const double y = lane_shift<true>(v[r][0]);             // right neighbour's first
                     const double x = lane_shift<false>(v[r][LV_SEG - 1]);  // left neighbour's last
                     const double xs = v[r][LV_SEG - 1], ys = v[r][0];
-                    v[r][LV_SEG - 1] = has_right ? fma(er.x, y, er.y * xs) : xs;
-                    v[r][0] = has_left ? fma(el.x, x, -(el.y * ys)) : ys;
+                    v[r][LV_SEG - 1] = fma(er.x, y, er.y * xs);
+                    v[r][0] = fma(el.x, x, -(el.y * ys));
                 }
 #pragma unroll
                 for (int j = 0; j < LV_SP - 1; ++j) {
