@@ -91,7 +91,8 @@ __global__ __launch_bounds__(LJ_THREADS, 2 * LJ_THREADS / WAVE / 4) void k_leaf_
     __shared__ double2 cs[2][LEAF_MAX / 2];  // (c, sigma) of each pair
     __shared__ double tt[2][LEAF_MAX / 2];   // tangent of each pair's rotation (0: none)
     __shared__ double red[LJ_THREADS / WAVE];
-    __shared__ int swept[2];  // per sweep parity: the sweep rotated something
+    __shared__ int swept[2];       // per sweep parity: the sweep rotated something
+    __shared__ int swbig[2];       // per sweep parity: some tangent was at least 1e-6
 
     const int leafid = blockIdx.x;
     const int L = a.leaf;
@@ -126,18 +127,16 @@ __global__ __launch_bounds__(LJ_THREADS, 2 * LJ_THREADS / WAVE / 4) void k_leaf_
         else ad = make_int4(ut(r0, m - 1, m), ut(0, r0, m), ut(r1, m - 1, m), ut(0, r1, m));
     };
     // the other wavefronts' blocks, the same in every round: the folded triangle dealt out
-    // over their threads, without the first wavefront's blocks; addresses for round A and B
-    // (two addresses of 16 bits to an int, so that the kernel keeps to 64 registers and two
-    // leaves share a CU)
-    int bP1[LJ_BLK], bP2[LJ_BLK];  // bP1 < 0: no block
-    int2 adA[LJ_BLK], adB[LJ_BLK];
-    auto pack = [](const int4 &ad) { return make_int2(ad.x | ad.y << 16, ad.z | ad.w << 16); };
-    auto unpack = [](int2 p) { return make_int4(p.x & 0xffff, p.x >> 16, p.y & 0xffff, p.y >> 16); };
+    // over their threads, without the first wavefront's blocks.  A slot keeps P1 | P2 << 8
+    // and, per round type, the addresses of the two rows' entries in the column pair's
+    // first column (16 bits each); the second column's follow from the row's parity, so
+    // that the kernel keeps to 64 registers and two leaves share a CU
+    int bP[LJ_BLK];  // < 0: no block
+    int adA[LJ_BLK], adB[LJ_BLK];
 #pragma unroll
     for (int u = 0; u < LJ_BLK; ++u) {
-        bP1[u] = -1;
-        bP2[u] = 0;
-        adA[u] = adB[u] = make_int2(0, 0);
+        bP[u] = -1;
+        adA[u] = adB[u] = 0;
         const int blk = (tid - WAVE) + u * (nt - WAVE);
         if (first || blk >= nfold) continue;
         const int r = blk / (hh + 1), e = blk - r * (hh + 1);
@@ -151,15 +150,29 @@ __global__ __launch_bounds__(LJ_THREADS, 2 * LJ_THREADS / WAVE / 4) void k_leaf_
         }
         if (P2 >= half) continue;  // padding of an odd half
         if (P2 - P1 <= 1 || (P1 == 0 && P2 == half - 1)) continue;  // the first wavefront's
-        bP1[u] = P1;
-        bP2[u] = P2;
+        bP[u] = P1 | P2 << 8;
         int4 ad;
         block_addr(2 * P1, 2 * P1 + 1, 2 * P2, 2 * P2 + 1, ad);
-        adA[u] = pack(ad);
+        adA[u] = ad.x | ad.z << 16;
         if (P2 < half - 1) block_addr(2 * P1 + 1, 2 * P1 + 2, 2 * P2 + 1, 2 * P2 + 2, ad);
         else block_addr(2 * P1 + 1, 2 * P1 + 2, m - 1, 0, ad);
-        adB[u] = pack(ad);
+        adB[u] = ad.x | ad.z << 16;
     }
+    // the four addresses of slot block (P1, P2) in a round of type b from the packed pair:
+    // in row r the column pair's second column lies neven(r) + odd(r) words after its first
+    // in round A (even, odd), and 1 - odd(r) - neven(r) words in round B (odd, even); when
+    // the column pair (m-1, 0) sits out, rows r0 = 2 P1 + 1 and r1 = r0 + 1 keep column 0
+    // at (0, r), which is m/2 + P1 and P1 + 1
+    auto slot_addr = [&](int pk, int P1, int b, bool cols_idle) {
+        const int ax = pk & 0xffff, az = pk >> 16;
+        if (cols_idle) return make_int4(ax, half + P1, az, P1 + 1);
+        auto step = [&](int r) {
+            const int odd = r & 1, neven = (m - r - odd) >> 1;
+            return b ? 1 - odd - neven : neven + odd;
+        };
+        const int r0 = 2 * P1 + b;
+        return make_int4(ax, ax + step(r0), az, az + step(r0 + 1));
+    };
 
     // off-diagonal block of pairs P1 < P2 at addresses ad, with the reflections of buffer b
     // (cols_idle: the column pair sits the round out)
@@ -185,8 +198,8 @@ __global__ __launch_bounds__(LJ_THREADS, 2 * LJ_THREADS / WAVE / 4) void k_leaf_
     };
 
     // rotations of round g (first wavefront, lane k: pair k) into buffer g & 1, with the
-    // log entry; returns whether the wavefront rotated anything
-    auto rotations = [&](int g) -> bool {
+    // log entry; returns the lane's tangent (0: no rotation)
+    auto rotations = [&](int g) -> double {
         const int k = tid;
         const int B = g & 1;  // m is even: round A pairs positions (2k, 2k+1), B (2k+1, 2k+2)
         double t = 0.0;
@@ -208,16 +221,46 @@ __global__ __launch_bounds__(LJ_THREADS, 2 * LJ_THREADS / WAVE / 4) void k_leaf_
             tt[B][k] = t;
             // the left position's new column is c y + sigma x and the right one's
             // c x - sigma y, for the columns x, y at the two positions before the round
-            if (!idle) log[(size_t)g * half + k] = r;
+            if (!idle) {
+                // the lane's offset through an empty asm, so that the per-lane log address is
+                // formed here rather than held in registers through the rounds
+                int kk = k;
+                asm volatile("" : "+v"(kk));
+                log[(size_t)g * half + kk] = r;
+            }
         }
-        return __any(t != 0.0);
+        return t;
+    };
+    // whether some pair (i, j) of the matrix as it stands would pass the rotation test, over
+    // all threads (ends in a barrier).  A sweep that rotates nothing leaves the matrix as it
+    // is, so when no pair passes, the next sweep would be empty.  It runs about once per
+    // leaf: the thread index goes through an empty asm so that none of its index
+    // arithmetic is hoisted out of the rounds and held in registers through them.
+    auto any_pair_rotates = [&]() -> bool {
+        int t = tid;
+        asm volatile("" : "+v"(t));
+        const int tpr = nt / m;  // threads per row
+        const int i = t / tpr;
+        bool any = false;
+        if (i < m) {
+            const double x = fabs(A[ut(i, i, m)]);
+            for (int j = i + 1 + t % tpr; j < m; j += tpr)
+                any |= fabs(A[ut(i, j, m)]) > 2.220446049250313e-16 * sqrt(x * fabs(A[ut(j, j, m)])) + absfloor;
+        }
+        return __syncthreads_or(any);
     };
 
-    bool rot_acc = false;  // first wavefront: the current sweep's rotations so far
-    if (first) rot_acc = rotations(0);
+    // first wavefront: whether the current sweep has rotated anything so far, and anything
+    // by a tangent of at least 1e-6
+    bool rot_acc = false, big_acc = false;
+    if (first) {
+        const double t = rotations(0);
+        rot_acc = __any(t != 0.0);
+        big_acc = __any(fabs(t) >= 1e-6);
+    }
     __syncthreads();
     int sweep = 0;
-    bool converged = false;
+    bool converged = false, reversed = false;  // reversed: an empty sweep ran
     for (int g = 0;; ++g) {
         const int b = g & 1;  // rotation buffer, and round B when set
         if (first) {
@@ -249,25 +292,40 @@ __global__ __launch_bounds__(LJ_THREADS, 2 * LJ_THREADS / WAVE / 4) void k_leaf_
             }
             if (g + 1 < total) {
                 wave_sync();
-                rot_acc |= rotations(g + 1);
+                const double t = rotations(g + 1);
+                rot_acc |= __any(t != 0.0);
+                big_acc |= __any(fabs(t) >= 1e-6);
                 if ((g + 1) % m == m - 1) {  // the sweep's last round is decided
-                    if (tid == 0) swept[((g + 1) / m) & 1] = rot_acc;
-                    rot_acc = false;
+                    if (tid == 0) {
+                        swept[((g + 1) / m) & 1] = rot_acc;
+                        swbig[((g + 1) / m) & 1] = big_acc;
+                    }
+                    rot_acc = big_acc = false;
                 }
             }
         } else {
 #pragma unroll
-            for (int u = 0; u < LJ_BLK; ++u)
-                if (bP1[u] >= 0)
-                    update_block(bP1[u], bP2[u], unpack(b ? adB[u] : adA[u]), b, b && bP2[u] == half - 1);
+            for (int u = 0; u < LJ_BLK; ++u) {
+                if (bP[u] < 0) continue;
+                const int P1 = bP[u] & 0xff, P2 = bP[u] >> 8;
+                const bool idle = b && P2 == half - 1;
+                update_block(P1, P2, slot_addr(b ? adB[u] : adA[u], P1, b, idle), b, idle);
+            }
         }
         __syncthreads();
         if (g % m == m - 1) {  // the end of sweep g / m
             if (!swept[(g / m) & 1]) {  // a sweep without rotations: nothing of it needs replaying
+                converged = reversed = true;
+                break;
+            }
+            ++sweep;
+            // once the sweep's rotations are all tiny, the next one may well be empty: test
+            // every pair now instead of running it to find out (the same decision)
+            if (!swbig[(g / m) & 1] && !any_pair_rotates()) {
                 converged = true;
                 break;
             }
-            if (++sweep == a.max_sweeps) break;
+            if (sweep == a.max_sweeps) break;
         }
     }
     // ascending order of the eigenvalues (ties broken by position).  A sweep reverses the
@@ -280,7 +338,7 @@ __global__ __launch_bounds__(LJ_THREADS, 2 * LJ_THREADS / WAVE / 4) void k_leaf_
             const double w = A[ut(j, j, L)];
             r += (w < v) || (w == v && j < tid);
         }
-        a.rank[(size_t)leafid * L + (converged ? L - 1 - tid : tid)] = r;
+        a.rank[(size_t)leafid * L + (reversed ? L - 1 - tid : tid)] = r;
         a.lam[(size_t)leafid * L + r] = v;
     }
     if (tid == 0) {
