@@ -15,10 +15,11 @@ namespace sdc {
 
 // ---------------------------------------------------------------------------------------
 // leaf eigendecomposition: cyclic Jacobi in three kernels:
-//   k_leaf_jacobi  rotates A -- its upper triangle, packed by rows (66 KB for a leaf of
-//                  128) -- in LDS, two leaves to a CU (the rounds are short and end in
-//                  barriers: a second leaf's waves fill the first one's waits), and logs
-//                  every round's rotations to HBM as (cos, signed sin) by position;
+//   k_leaf_jacobi  rotates A -- kept by position, its upper triangle packed by rows
+//                  (66 KB for a leaf of 128) -- in LDS, two leaves to a CU (the rounds are
+//                  short and end in a barrier: a second leaf's waves fill the first one's
+//                  waits), and logs every round's rotations to HBM as (cos, signed sin) by
+//                  position;
 //   k_leaf_vectors replays the log on V = I with V in registers: a lane holds 16
 //                  consecutive positions of 4 rows, so a round is static register code;
 //   k_leaf_w       W = Q^T U from the stored eigenvectors.
