@@ -49,7 +49,8 @@ static_assert(LJ_PACKED < (1 << 15), "addresses in the packed triangle fit 15 bi
 static_assert(LV_PAIRS == WAVE, "one staged log entry per lane");
 static_assert(LV_NSEG * LV_SEG == LEAF_MAX && LV_NSEG <= 16 && 16 % LV_NSEG == 0,
               "a row's segments are neighbouring lanes of one 16-lane DPP row");
-static_assert(LV_RB % 2 == 0, "a staged block starts on a round A");
+static_assert(LV_RB == 4, "a staged block starts on a round A, and two padding rounds negate\n"
+              "every position but the first");
 
 // entry (i, j), i <= j, of the upper triangle of an m x m matrix (m even) packed by rows,
 // each row holding its even columns first and then its odd ones: a round's blocks take a
@@ -360,6 +361,57 @@ __device__ __forceinline__ double lane_shift(double x) {
     return __longlong_as_double(((long long)h2 << 32) | (unsigned int)l2);
 }
 
+// the LV_RB rounds of a staged block, whose first round is a round A (static code with no
+// exit between the rounds, so V keeps its registers through the block)
+__device__ __forceinline__ void replay_block(double (&v)[LV_RPL][LV_SEG], const double2 (*c)[LV_CLD],
+                                             int sg, bool has_left) {
+#pragma unroll
+    for (int u = 0; u < LV_RB; ++u) {
+        const double2 *cu = c[u] + sg * (LV_SP + 1);  // entries 8 sg .. 8 sg + 7
+        if ((u & 1) == 0) {
+            // round A: pairs (2j, 2j+1) of the segment
+#pragma unroll
+            for (int j = 0; j < LV_SP; ++j) {
+                const double2 e = cu[j];
+#pragma unroll
+                for (int r = 0; r < LV_RPL; ++r) {
+                    const double x = v[r][2 * j], y = v[r][2 * j + 1];
+                    v[r][2 * j] = fma(e.x, y, e.y * x);
+                    v[r][2 * j + 1] = fma(e.x, x, -(e.y * y));
+                }
+            }
+        } else {
+            // round B: pairs (2j+1, 2j+2) inside the segment, and the pairs across its
+            // ends: (16 sg + 15, 16 sg + 16) with entry 8 sg + 7 on the right, and
+            // (16 sg - 1, 16 sg) with entry 8 sg - 1 on the left
+            // the last segment's entry 8 sg + 7 is past the round's pairs, so (0, 1) keeps
+            // its last position; the first segment has no left pair, and (0, -1) keeps
+            // its first position (the neighbours' values are finite either way)
+            const double2 er = cu[LV_SP - 1];
+            double2 el = cu[has_left ? -2 : 0];
+            if (!has_left) el = make_double2(0.0, -1.0);
+#pragma unroll
+            for (int r = 0; r < LV_RPL; ++r) {
+                const double y = lane_shift<true>(v[r][0]);             // right neighbour's first
+                const double x = lane_shift<false>(v[r][LV_SEG - 1]);  // left neighbour's last
+                const double xs = v[r][LV_SEG - 1], ys = v[r][0];
+                v[r][LV_SEG - 1] = fma(er.x, y, er.y * xs);
+                v[r][0] = fma(el.x, x, -(el.y * ys));
+            }
+#pragma unroll
+            for (int j = 0; j < LV_SP - 1; ++j) {
+                const double2 e = cu[j];
+#pragma unroll
+                for (int r = 0; r < LV_RPL; ++r) {
+                    const double x = v[r][2 * j + 1], y = v[r][2 * j + 2];
+                    v[r][2 * j + 1] = fma(e.x, y, e.y * x);
+                    v[r][2 * j + 2] = fma(e.x, x, -(e.y * y));
+                }
+            }
+        }
+    }
+}
+
 // Replay of the rotation log on V = I.  Rows of V J are independent and a round's
 // rotations touch neighbouring positions only, so V stays in registers: wavefront w of a
 // leaf owns rows [32 w, 32 w + 32); lane 8 g + s holds rows 32 w + 4 g .. + 3 at positions
@@ -388,7 +440,11 @@ __global__ __launch_bounds__(WAVE, 2) void k_leaf_vectors(LeafArgs a) {
     const double2 *log = reinterpret_cast<const double2 *>(a.rot) + (size_t)leafid * a.max_sweeps * L * half;
     const int nsw = a.sweeps[leafid];
     const int rounds = nsw * L;  // L is even: round rd is a round A when rd is even
+    // whole blocks only: when the rounds end half-way through a block, its last two rounds
+    // run on (0, 1) entries, which keep x and negate y -- over a round A and a round B that
+    // negates every position but 0, undone when the vectors are written
     const int nblk = (rounds + LV_RB - 1) / LV_RB;
+    const bool padded = rounds % LV_RB != 0;
     const int slot = lane + lane / LV_SP;  // where this lane stages its entry
     double2 nx[LV_RB];
 #pragma unroll
@@ -405,53 +461,7 @@ __global__ __launch_bounds__(WAVE, 2) void k_leaf_vectors(LeafArgs a) {
             nx[u] = (rr < rounds && lane < half - (u & 1)) ? log[(size_t)rr * half + lane]
                                                           : make_double2(0.0, 1.0);
         }
-        const int nr = min(LV_RB, rounds - b * LV_RB);
-#pragma unroll
-        for (int u = 0; u < LV_RB; ++u) {
-            if (u >= nr) break;
-            const double2 *cu = c[u] + sg * (LV_SP + 1);  // entries 8 sg .. 8 sg + 7
-            if ((u & 1) == 0) {
-                // round A: pairs (2j, 2j+1) of the segment
-#pragma unroll
-                for (int j = 0; j < LV_SP; ++j) {
-                    const double2 e = cu[j];
-#pragma unroll
-                    for (int r = 0; r < LV_RPL; ++r) {
-                        const double x = v[r][2 * j], y = v[r][2 * j + 1];
-                        v[r][2 * j] = fma(e.x, y, e.y * x);
-                        v[r][2 * j + 1] = fma(e.x, x, -(e.y * y));
-                    }
-                }
-            } else {
-                // round B: pairs (2j+1, 2j+2) inside the segment, and the pairs across its
-                // ends: (16 sg + 15, 16 sg + 16) with entry 8 sg + 7 on the right, and
-                // (16 sg - 1, 16 sg) with entry 8 sg - 1 on the left
-                // the last segment's entry 8 sg + 7 is past the round's pairs, so (0, 1) keeps
-                // its last position; the first segment has no left pair, and (0, -1) keeps
-                // its first position (the neighbours' values are finite either way)
-                const double2 er = cu[LV_SP - 1];
-                double2 el = cu[has_left ? -2 : 0];
-                if (!has_left) el = make_double2(0.0, -1.0);
-#pragma unroll
-                for (int r = 0; r < LV_RPL; ++r) {
-                    const double y = lane_shift<true>(v[r][0]);             // right neighbour's first
-                    const double x = lane_shift<false>(v[r][LV_SEG - 1]);  // left neighbour's last
-                    const double xs = v[r][LV_SEG - 1], ys = v[r][0];
-                    v[r][LV_SEG - 1] = fma(er.x, y, er.y * xs);
-                    v[r][0] = fma(el.x, x, -(el.y * ys));
-                }
-#pragma unroll
-                for (int j = 0; j < LV_SP - 1; ++j) {
-                    const double2 e = cu[j];
-#pragma unroll
-                    for (int r = 0; r < LV_RPL; ++r) {
-                        const double x = v[r][2 * j + 1], y = v[r][2 * j + 2];
-                        v[r][2 * j + 1] = fma(e.x, y, e.y * x);
-                        v[r][2 * j + 2] = fma(e.x, x, -(e.y * y));
-                    }
-                }
-            }
-        }
+        replay_block(v, c, sg, has_left);
         wave_sync();
     }
     // the column at position pos is the eigenvector whose ascending rank the Jacobi kernel
@@ -463,9 +473,10 @@ __global__ __launch_bounds__(WAVE, 2) void k_leaf_vectors(LeafArgs a) {
         const int pos = pos0 + j;
         if (pos >= L) continue;
         const size_t k = (size_t)rank[pos];
+        const bool flip = padded && pos != 0;
 #pragma unroll
         for (int r = 0; r < LV_RPL; ++r)
-            if (row0 + r < L) Q[k * L + row0 + r] = v[r][j];
+            if (row0 + r < L) Q[k * L + row0 + r] = flip ? -v[r][j] : v[r][j];
     }
 }
 
