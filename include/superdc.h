@@ -319,7 +319,9 @@ int superdc_batch_copy_rows(superdc_ctx *ctx, const superdc_batch *src_batch,
 typedef struct superdc_hss superdc_hss;
 
 /* Plan a tree: leaf in [2, 128] even, depth in [1, 20], r in [1, 8].  Allocates the
- * level batches, the factor storage and work buffers (O(r n depth) doubles). */
+ * level batches, the factor storage and work buffers (O(r n depth) doubles), and the leaf
+ * eigensolver's rotation log: room for 16 Jacobi sweeps of (cos, sin) pairs, 16 leaf n
+ * doubles (1.07 GB for n = 65536 and leaf 128). */
 int superdc_hss_plan_create(superdc_ctx *ctx, int32_t leaf, int32_t depth, int32_t r,
                             superdc_hss **plan);
 void superdc_hss_plan_destroy(superdc_hss *plan);
