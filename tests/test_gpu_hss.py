@@ -50,6 +50,27 @@ def test_levels_small(shape):
     np.testing.assert_array_equal(out["lam"], out["lam_levels"][0])
 
 
+@pytest.mark.parametrize("leaf,depth,scale", [(128, 2, 0.0), (128, 2, 1e-9), (30, 3, 0.0), (30, 3, 1e-9)])
+def test_levels_nearly_diagonal_leaves(leaf, depth, scale):
+    """Leaf blocks that are diagonal (the leaf Jacobi's first sweep rotates nothing, so no
+    rotation is replayed) or nearly so (every rotation tiny, so the test of every pair ends
+    the sweeps without an empty one): the eigenvalues of every level against the oracle."""
+    tree = gen.hss_tree(n=leaf << depth, leaf=leaf, r=4, cfg=500 + leaf + depth)
+    D = tree.leaf_D.copy()
+    for b in range(D.shape[0]):
+        dg = np.diag(np.diag(D[b]))
+        D[b] = dg + scale * (D[b] - dg)
+    tree.leaf_D = D
+    print(f"nearly diagonal leaves: leaf {leaf} depth {depth} scale {scale}", flush=True)
+    plan, out = run_conquer(tree)
+    assert out["status"][0] == 0
+    ref = ohss.level_eigenvalues(tree)
+    for lvl in range(depth + 1):
+        sc = np.abs(ref[lvl]).max()
+        err = np.abs(out["lam_levels"][lvl] - ref[lvl]).max()
+        assert err <= 1e-12 * sc, (lvl, err / sc)
+
+
 def test_eigenmatrix_small():
     from paper_2108_04209_amd import native
     from tests import gpu_pipeline as gp
